@@ -1,0 +1,223 @@
+"""The slimLS iteration in float64 (test infrastructure only).
+
+Paper: eq. (ram)   x_k = x_{k-1} - B_k A_k^T (A_k x_{k-1} - b_k)
+       eq. (B_k)   B_k = (alpha_k^{-1} C_k + M_k^T M_k)^{-1},  M_k = [A_{k-r}; ...; A_k]
+with C_k = I and a constant alpha_k = 1/lam (sec. 1: C_k = I and r = 0 give
+damped block Kaczmarz, eq. (dbK)).  Blocks with negative index are empty,
+so M_k grows over the first r steps (sec. 1).
+
+Three algebraically equal ways to form the step s_k = x_{k-1} - x_k:
+
+* ``step_primal``   -- eq. (B_k) literally: solve (lam I + M^T M) s = A_k^T res
+                       (dense n x n; tiny problems only);
+* ``step_dual``     -- the Gram (push-through) form used for parity:
+                       (lam I + M^T M)^{-1} M^T = M^T (lam I + M M^T)^{-1} and
+                       A_k^T res = M^T [0; ...; 0; res], so
+                       s = M^T z with (M M^T + lam I) z = [0; ...; 0; res];
+                       the p x p system is solved by dense Cholesky (LAPACK)
+                       for p <= chol_max_p, else by plain CG to a relative
+                       residual of cg_tol;
+* ``step_woodbury`` -- Sherman-Morrison-Woodbury (sec. 2 remark on exact
+                       solves): s = (g - M^T (lam I + M M^T)^{-1} M g) / lam,
+                       g = A_k^T res.
+
+Pins (tests/test_oracle_*.py): the three forms agree; r = 0 is damped block
+Kaczmarz (eq. dbK); lam -> 0 with one row per block is Kaczmarz (eq. Kacz);
+full memory over one epoch gives the Tikhonov solution at every k (the
+induction of App. A with the damped Hessian); the residual identity after a
+step; consistent data is a fixed point; Theorem 3.1(i) in expectation.
+Full reconstructions at the workload sizes have no printed values: parity
+beyond these pins is unpinned.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+import scipy.linalg as sla
+import scipy.sparse as sp
+
+
+def _stack(mats):
+    if any(sp.issparse(m) for m in mats):
+        return sp.vstack([sp.csr_matrix(m) for m in mats], format="csr")
+    return np.vstack(mats)
+
+
+def _dense(a):
+    return a.toarray() if sp.issparse(a) else np.asarray(a)
+
+
+def cg(apply, rhs: np.ndarray, tol: float, max_iter: int = 100000):
+    """Plain conjugate gradients (Hestenes-Stiefel) for an SPD operator.
+
+    Stops when ||rhs - A z|| <= tol * ||rhs||.  Returns (z, iterations, relres)."""
+    z = np.zeros_like(rhs)
+    r = rhs.copy()
+    p = r.copy()
+    rr = r @ r
+    nb = np.sqrt(rhs @ rhs)
+    if nb == 0.0:
+        return z, 0, 0.0
+    it = 0
+    while np.sqrt(rr) > tol * nb and it < max_iter:
+        q = apply(p)
+        a = rr / (p @ q)
+        z += a * p
+        r -= a * q
+        rr_new = r @ r
+        p = r + (rr_new / rr) * p
+        rr = rr_new
+        it += 1
+    return z, it, float(np.sqrt(rr) / nb)
+
+
+def gram(window, lam: float) -> np.ndarray:
+    """G = M M^T + lam I for M = vstack(window), dense float64."""
+    M = _stack(window)
+    G = _dense(M @ M.T).astype(np.float64)
+    G[np.diag_indices_from(G)] += lam
+    return G
+
+
+def step_dual(window, res, lam, chol_max_p=8000, cg_tol=1e-12):
+    """Returns (s, z, info).  ``window`` lists the blocks A_{k-r}..A_k, oldest first."""
+    M = _stack(window)
+    p = M.shape[0]
+    e = np.zeros(p)
+    e[p - res.size:] = res
+    if p <= chol_max_p:
+        G = _dense(M @ M.T).astype(np.float64)
+        G[np.diag_indices_from(G)] += lam
+        z = sla.cho_solve(sla.cho_factor(G, lower=True), e)
+        info = {"mode": "chol", "iters": 0, "relres": 0.0}
+    else:
+        z, it, rel = cg(lambda v: M @ (M.T @ v) + lam * v, e, cg_tol)
+        info = {"mode": "cg", "iters": it, "relres": rel}
+    s = M.T @ z
+    return np.asarray(s).reshape(-1), z, info
+
+
+def step_primal(window, res, lam):
+    """s = (lam I + M^T M)^{-1} A_k^T res, eq. (B_k) with C_k = I, alpha = 1/lam."""
+    M = _dense(_stack(window))
+    Ak = _dense(window[-1])
+    H = M.T @ M
+    H[np.diag_indices_from(H)] += lam
+    return np.linalg.solve(H, Ak.T @ res)
+
+
+def step_woodbury(window, res, lam):
+    """s = (g - M^T (lam I + M M^T)^{-1} M g) / lam with g = A_k^T res."""
+    M = _dense(_stack(window))
+    g = _dense(window[-1]).T @ res
+    G = M @ M.T
+    G[np.diag_indices_from(G)] += lam
+    return (g - M.T @ np.linalg.solve(G, M @ g)) / lam
+
+
+@dataclass
+class StepRecord:
+    k: int
+    block: int
+    step_norm: float
+    x_norm: float
+    err_norm: float
+    mode: str = "chol"
+    cg_iters: int = 0
+
+
+@dataclass
+class SlimLS:
+    """Iterates of slimLS for a problem given block-wise.
+
+    block_rows(beta) -> rows A_beta (sparse or dense), block_data(beta) -> b_beta.
+    """
+    block_rows: callable
+    block_data: callable
+    r: int
+    lam: float
+    x: np.ndarray
+    x_true: np.ndarray | None = None
+    form: str = "dual"
+    chol_max_p: int = 8000
+    cg_tol: float = 1e-12
+    window: list = field(default_factory=list)     # block ids, oldest first
+    k: int = 0
+    history: list = field(default_factory=list)
+
+    def step(self, beta: int) -> StepRecord:
+        self.window.append(int(beta))
+        if len(self.window) > self.r + 1:
+            self.window.pop(0)
+        mats = [self.block_rows(b) for b in self.window]
+        Ak = mats[-1]
+        res = np.asarray(Ak @ self.x).reshape(-1) - self.block_data(beta)
+        info = {"mode": self.form, "iters": 0}
+        if self.form == "dual":
+            s, _, info = step_dual(mats, res, self.lam, self.chol_max_p, self.cg_tol)
+        elif self.form == "primal":
+            s = step_primal(mats, res, self.lam)
+        elif self.form == "woodbury":
+            s = step_woodbury(mats, res, self.lam)
+        else:
+            raise ValueError(self.form)
+        self.x = self.x - s
+        self.k += 1
+        err = float(np.linalg.norm(self.x - self.x_true)) if self.x_true is not None else float("nan")
+        rec = StepRecord(self.k, int(beta), float(np.linalg.norm(s)), float(np.linalg.norm(self.x)),
+                         err, info["mode"], info.get("iters", 0))
+        self.history.append(rec)
+        return rec
+
+
+def stop_index(history, r: int, tol: float):
+    """First step k >= r+1 with ||s_k|| / ||x_k|| <= tol (1-based), or None."""
+    for rec in history:
+        if rec.k >= r + 1 and rec.x_norm > 0 and rec.step_norm / rec.x_norm <= tol:
+            return rec.k
+    return None
+
+
+class Tomo:
+    """slimLS on a 2D parallel-beam problem: block beta = angles g*beta .. g*beta+g-1."""
+
+    def __init__(self, projector, b: np.ndarray, g: int, r: int, lam: float,
+                 x0: np.ndarray | None = None, x_true: np.ndarray | None = None,
+                 chol_max_p: int = 8000, cg_tol: float = 1e-12, form: str = "dual"):
+        self.P = projector
+        self.g = g
+        self.n_blocks = projector.n_angles // g
+        self.b = np.asarray(b, np.float64).reshape(projector.n_angles, projector.R)
+        x0 = np.zeros(projector.n) if x0 is None else np.asarray(x0, np.float64).reshape(-1)
+        xt = None if x_true is None else np.asarray(x_true, np.float64).reshape(-1)
+        self.it = SlimLS(self.rows, self.data, r, lam, x0.copy(), xt, form, chol_max_p, cg_tol)
+
+    def angles_of(self, beta: int):
+        return list(range(beta * self.g, beta * self.g + self.g))
+
+    def rows(self, beta: int):
+        return self.P.rows(self.angles_of(beta))
+
+    def data(self, beta: int):
+        return self.b[self.angles_of(beta)].reshape(-1)
+
+    @property
+    def x(self):
+        return self.it.x
+
+    def step(self, beta: int) -> StepRecord:
+        return self.it.step(beta)
+
+    def run(self, sched, tol: float | None = None, epoch_len: int | None = None):
+        """Run the schedule; stop at the first k >= r+1 with rho_k <= tol if tol
+        is given.  Returns (x at the end, list of x at epoch ends, stop step)."""
+        epoch_len = self.n_blocks if epoch_len is None else epoch_len
+        snaps = []
+        for beta in sched:
+            rec = self.step(int(beta))
+            if rec.k % epoch_len == 0:
+                snaps.append(self.x.copy())
+            if tol is not None and rec.k >= self.it.r + 1 and rec.step_norm <= tol * rec.x_norm:
+                return self.x.copy(), snaps, rec.k
+        return self.x.copy(), snaps, None
