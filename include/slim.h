@@ -1,0 +1,187 @@
+/*
+ * slim.h -- C ABI of the MI355X (gfx950) slimLS library.
+ *
+ * slimLS (Chung, Chung, Slagel, Tenorio, arXiv 1912.07962, sec. 1,
+ * eq. (ram) and eq. (B_k)) iterates
+ *
+ *     x_k = x_{k-1} - (lambda I + M_k^T M_k)^{-1} A_k^T (A_k x_{k-1} - b_k),
+ *     M_k = [A_{k-r}; ...; A_k]        (C_k = I, alpha_k = 1/lambda),
+ *
+ * where A_k is a sampled block of rows of A.  Here A is the 2D parallel-beam
+ * projector of an N x N image (sec. 4.3 experiments) and a block is a set of
+ * projection angles.  The library evaluates A matrix-free with Joseph
+ * weights
+ *     a[(theta,s),(i,j)] = (h/d) max(0, 1 - |s - x_j cos - y_i sin| / (h d)),
+ *     d = max(|cos|, |sin|), h = 2/N,
+ * pixel centres x_j = (j-(N-1)/2) h, y_i = (i-(N-1)/2) h (row i, column j,
+ * row-major), ray offsets s_t = (t-(R-1)/2) h.  The step is computed in the
+ * Gram (push-through) form s = M^T z, (M M^T + lambda I) z = [0;...;0;res],
+ * by FP64 Cholesky of the explicit Gram, or by preconditioned CG on the same
+ * system when p = rows(M) is large.
+ *
+ * Conventions for every entry point:
+ *  - Array arguments marked "device" are device pointers (e.g. from torch
+ *    tensors); "host" arrays are ordinary host memory.  The caller owns all
+ *    arrays; the library only borrows them for the duration of a call (and,
+ *    for slim_set_data, until the next slim_set_data or slim_destroy).
+ *  - Layouts: image [n_slices][N][N] float32, row-major; sinogram
+ *    [n_slices][n_angles][n_rays] float32 (bf16 when precision is
+ *    SLIM_PREC_BF16, see slim_opts), angle-major.
+ *  - Work is enqueued on opts.stream (a hipStream_t; NULL is the default
+ *    stream).  Calls that return host-visible numbers (step info, solve info)
+ *    synchronise that stream.
+ *  - No entry point throws; every error is a slim_status.  Argument checks
+ *    happen before any device work.  A context is bound to one device and
+ *    one stream and is not thread-safe.
+ */
+#ifndef SLIM_H
+#define SLIM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SLIM_OK = 0,
+  SLIM_EINVAL = 1,   /* invalid argument (message via slim_last_error)        */
+  SLIM_ENOMEM = 2,   /* device workspace does not fit                         */
+  SLIM_EDEVICE = 3,  /* a HIP call failed                                     */
+  SLIM_ENUMERIC = 4, /* non-finite norm or non-positive Cholesky pivot        */
+  SLIM_ENOTCONV = 5, /* CG reached its iteration cap (the step is still taken) */
+  SLIM_ESTATE = 6    /* step/solve before slim_set_data, or bad state blob    */
+} slim_status;
+
+typedef struct slim_ctx slim_ctx;
+
+typedef struct {
+  int N;        /* pixels per side, >= 2                                  */
+  int n_slices; /* independent slices sharing A (1 for a single image)    */
+} slim_grid;
+
+enum { SLIM_PREC_FP32 = 0, SLIM_PREC_BF16 = 1 };
+enum { SLIM_GRAM_AUTO = 0, SLIM_GRAM_CHOL = 1, SLIM_GRAM_PCG = 2 };
+
+typedef struct {
+  int angles_per_block; /* g: angles in one sampled block; divides n_angles */
+  int precision;        /* SLIM_PREC_FP32 or SLIM_PREC_BF16 (bf16 sinogram
+                           input and bf16 image shadow read by the forward
+                           projector; fp32 master image and accumulation)  */
+  int gram_mode;        /* SLIM_GRAM_AUTO / CHOL / PCG                      */
+  int chol_max_p;       /* AUTO uses Cholesky while p <= chol_max_p         */
+  int pcg_max_iter;     /* CG iteration cap per step                        */
+  double pcg_tol;       /* CG stop: ||res|| <= pcg_tol * ||rhs||            */
+  int check_every;      /* slim_solve: read the step norms every q steps    */
+  uint64_t seed;        /* slim_solve: SplitMix64 seed of the block order   */
+  void* stream;         /* hipStream_t work queue (NULL = default stream)   */
+} slim_opts;
+
+typedef struct {
+  double step_norm; /* ||s_k||_2 (max over slices when n_slices > 1)        */
+  double x_norm;    /* ||x_k||_2 (of the slice attaining step_norm)         */
+  double err_norm;  /* ||x_k - x_true||_2, or -1 without x_true             */
+  int k;            /* iteration count after this step                      */
+  int pcg_iters;    /* CG iterations of this step (0 in Cholesky mode)      */
+  double pcg_relres;/* final CG relative residual (0 in Cholesky mode)      */
+} slim_step_info;
+
+typedef struct {
+  int steps;        /* steps taken                                          */
+  int epochs;       /* epochs started                                       */
+  int converged;    /* 1 if the stop rule fired                             */
+  double rho_last;  /* last ||s_k|| / ||x_k|| read                          */
+  double err_last;  /* last ||x_k - x_true|| / ||x_true|| (-1 if unknown)   */
+  int pcg_iters;    /* total CG iterations                                  */
+} slim_solve_info;
+
+/* Fill *opts with defaults: g = 1, FP32, AUTO, chol_max_p = 8192,
+ * pcg_max_iter = 1000, pcg_tol = 1e-6, check_every = 1, seed = 0, NULL stream. */
+slim_status slim_default_opts(slim_opts* opts);
+
+/* Create a context (paper sec. 1 setup, sec. 4.3 geometry).
+ *  grid      host; N >= 2, n_slices >= 1
+ *  n_angles  number of projection angles (>= 1)
+ *  angles    host [n_angles] radians in [0, pi), or NULL for a*pi/n_angles
+ *  n_rays    rays per angle R >= 1 (spacing h, centred on the axis)
+ *  r         memory level r >= 0 (sec. 1, eq. (B_k))
+ *  lambda    damping 1/alpha > 0, finite
+ *  opts      host, or NULL for defaults
+ * Allocates the geometry table and all step workspace on the current device.
+ * Errors: SLIM_EINVAL (checked before any device call), SLIM_ENOMEM, SLIM_EDEVICE. */
+slim_status slim_init(slim_ctx** out, const slim_grid* grid, int n_angles, const double* angles,
+                      int n_rays, int r, double lambda, const slim_opts* opts);
+
+/* Bind the data of the problem b = A x_true + eps (sec. 1, eq. (inverseproblem)).
+ *  b       device sinogram [n_slices][n_angles][n_rays] (float32, or bf16 bits
+ *          when precision is SLIM_PREC_BF16)
+ *  x       device image [n_slices][N][N] float32: the iterate, read and
+ *          overwritten in place by slim_step / slim_solve
+ *  x_true  device [n_slices][N][N] float32 or NULL; enables err_norm
+ * Resets the iteration (k = 0, empty memory window).
+ * Errors: SLIM_EINVAL on NULL b or x. */
+slim_status slim_set_data(slim_ctx* ctx, const void* b, void* x, const float* x_true);
+
+/* One slimLS iteration (eq. (ram)) with the sampled block A_k = rows of the
+ * given angles (host int32 [n_ids], n_ids == angles_per_block, each in
+ * [0, n_angles), no duplicates).  The block enters the memory window; the
+ * oldest block leaves once the window holds r+1 blocks.  info may be NULL
+ * (then nothing is read back and the stream is not synchronised).
+ * Errors: SLIM_EINVAL (bad ids), SLIM_ESTATE (no data), SLIM_ENUMERIC,
+ * SLIM_ENOTCONV (CG cap reached; the step is still applied), SLIM_EDEVICE. */
+slim_status slim_step(slim_ctx* ctx, const int32_t* angle_ids, int n_ids, slim_step_info* info);
+
+/* Run slimLS from x (in: x0, out: the result) with the data b until the stop
+ * rule or max_epochs.  Blocks are the fixed partition {g*beta, ..., g*beta+g-1}
+ * of the angles, visited random-cyclically (sec. 4.3): epoch e visits every
+ * block once in the order of a Fisher-Yates shuffle driven by SplitMix64
+ * outputs e*(M-1)+1 ... e*(M-1)+(M-1) of opts.seed.  Stop rule: the first
+ * k >= r+1 (checked every check_every steps) with ||s_k|| <= tol ||x_k||
+ * (sec. 4.3 early termination); tol <= 0 runs all epochs.
+ *  b, x, x_true as in slim_set_data (this call binds them).
+ * Errors: as slim_set_data and slim_step. */
+slim_status slim_solve(slim_ctx* ctx, const void* b, void* x, const float* x_true, double tol,
+                       int max_epochs, slim_solve_info* info);
+
+/* Forward projection of rows of A (sec. 4.2: function evaluations of A_k).
+ *  angle_ids  host int32 [n_ids] (any order, repeats allowed)
+ *  x          device [n_slices][N][N] float32
+ *  out        device [n_slices][n_ids][n_rays] float32, out = A_ids x
+ * Errors: SLIM_EINVAL, SLIM_EDEVICE. */
+slim_status slim_project(slim_ctx* ctx, const int32_t* angle_ids, int n_ids, const float* x,
+                         float* out);
+
+/* Back-projection, the exact adjoint of slim_project with the same weights.
+ *  v    device [n_slices][n_ids][n_rays] float32
+ *  out  device [n_slices][N][N] float32, out = A_ids^T v (overwritten)
+ * Errors: SLIM_EINVAL, SLIM_EDEVICE. */
+slim_status slim_backproject(slim_ctx* ctx, const int32_t* angle_ids, int n_ids, const float* v,
+                             float* out);
+
+/* Gram block A_ids_a A_ids_b^T (sec. 2 Woodbury remark; the blocks of
+ * M_k M_k^T).  out: device float64 [n_a*n_rays][n_b*n_rays], row-major.
+ * Errors: SLIM_EINVAL, SLIM_EDEVICE. */
+slim_status slim_gram(slim_ctx* ctx, const int32_t* ids_a, int n_a, const int32_t* ids_b, int n_b,
+                      double* out);
+
+/* Checkpoint state: k, epoch, position in the epoch and the window's angle
+ * ids.  The Gram is recomputed from the ids, so a restored run continues
+ * bit-identically.  size in/out: bytes available / needed.
+ * Errors: SLIM_EINVAL (buffer too small: *size is set), SLIM_ESTATE (bad blob). */
+slim_status slim_get_state(slim_ctx* ctx, void* buf, int64_t* size);
+slim_status slim_set_state(slim_ctx* ctx, const void* buf, int64_t size);
+
+/* Release every device allocation of ctx (NULL is a no-op). */
+void slim_destroy(slim_ctx* ctx);
+
+/* Static description of a status code. */
+const char* slim_strerror(slim_status s);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* slim_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SLIM_H */

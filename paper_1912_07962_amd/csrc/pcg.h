@@ -1,0 +1,41 @@
+// Preconditioned CG on the Gram system (lambda I + M M^T) z = [0; ...; 0; res]
+// with matrix-free M (forward projector) and M^T (back-projector); used when
+// p = rows(M) is too large for the explicit Gram.  Vectors in p-space are
+// float64; the image-space intermediate M^T v is float32.  Scalars stay on
+// the device; the host reads the residual norm every few iterations.
+#pragma once
+
+#include "slim_internal.h"
+
+namespace slim {
+
+struct PcgWork {
+  int pmax = 0;
+  int nparts = 0;
+  double* r = nullptr;      // residual           [pmax]
+  double* pd = nullptr;     // search direction   [pmax]
+  double* q = nullptr;      // G pd               [pmax]
+  double* y = nullptr;      // preconditioned r   [pmax]
+  double* dinv = nullptr;   // 1 / (||a_row||^2 + lambda), per (angle, ray) [n_angles][R]
+  double* parts = nullptr;  // per-workgroup partial dot products [2][nparts]
+  double* sc = nullptr;     // device scalars: rz, alpha, beta, rr, pq, bb
+  float* u = nullptr;       // M^T pd             [N][N]
+  float* uT = nullptr;      // its transpose      [N][N]
+  double* h_sc = nullptr;   // pinned copy of sc
+};
+
+hipError_t pcg_alloc(PcgWork& w, int N, int n_angles, int R, int64_t pmax);
+void pcg_free(PcgWork& w);
+// Per-ray squared norms of every angle -> dinv.
+hipError_t pcg_setup(PcgWork& w, const AngleGeom* geom, int N, int n_angles, int R, double lam,
+                     hipStream_t st);
+// Solve for one slice: rhs = [0; res] (res: last nres entries), z: [p] out.
+hipError_t pcg_solve(PcgWork& w, const AngleGeom* geom, int N, int R, const AngleList& win,
+                     double lam, const double* res, int nres, double* z, double tol, int max_iter,
+                     int* iters, double* relres, hipStream_t st);
+
+hipError_t launch_transpose(const float* src, float* dst, int N, hipStream_t st);
+hipError_t launch_ray_sqnorm(const AngleGeom* geom, int N, int R, const AngleList& ids, double* out,
+                             hipStream_t st);
+
+}  // namespace slim

@@ -1,0 +1,577 @@
+// C ABI of the slimLS library: argument checks, context and workspace, the
+// per-step schedule of kernels, the solve loop and its sampler.
+//
+// One step (paper eq. (ram), (B_k) with C_k = I, alpha = 1/lambda):
+//   1. res = A_k x - b_k                      forward projector, fp64 sums
+//   2. z = (M M^T + lambda I)^{-1} [0;..;res]  explicit Gram + FP64 Cholesky,
+//                                             or PCG with matrix-free M, M^T
+//   3. x <- x - M^T z                         back-projection fused with the
+//                                             update and fp64 norm partials
+// The memory window M_k = [A_{k-r}; ...; A_k] is a ring of r+1 block slots;
+// Gram blocks between a slot and the older slots are computed when the slot
+// is filled and reused while both stay in the window.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <deque>
+#include <string>
+#include <vector>
+
+#include "slim_internal.h"
+#include "pcg.h"
+
+using namespace slim;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+slim_status fail(slim_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+#define HIP_TRY(expr)                                                                   \
+  do {                                                                                  \
+    hipError_t _e = (expr);                                                             \
+    if (_e != hipSuccess)                                                               \
+      return fail(SLIM_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(_e));     \
+  } while (0)
+
+template <typename T>
+hipError_t dalloc(T** p, size_t count) {
+  *p = nullptr;
+  if (count == 0) return hipSuccess;
+  return hipMalloc((void**)p, count * sizeof(T));
+}
+
+// SplitMix64 (Steele, Lea, Flood 2014), k-th output for a seed.
+uint64_t splitmix64(uint64_t seed, uint64_t k) {
+  uint64_t z = seed + k * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// Fisher-Yates shuffle of 0..M-1 for epoch e, driven by outputs
+// e*(M-1)+1 ... of the seed; j = floor(u * (i+1) / 2^64).
+std::vector<int> epoch_order(int M, int e, uint64_t seed) {
+  std::vector<int> perm(M);
+  for (int i = 0; i < M; ++i) perm[i] = i;
+  uint64_t k = (uint64_t)e * (uint64_t)(M - 1);
+  for (int i = M - 1; i >= 1; --i) {
+    ++k;
+    const uint64_t u = splitmix64(seed, k);
+    const uint64_t j = (uint64_t)(((unsigned __int128)u * (unsigned __int128)(i + 1)) >> 64);
+    std::swap(perm[i], perm[(int)j]);
+  }
+  return perm;
+}
+
+}  // namespace
+
+struct slim_ctx {
+  int N = 0, B = 1, n_angles = 0, R = 0, r = 0, g = 1;
+  double lam = 0.0;
+  slim_opts o{};
+  hipStream_t st = nullptr;
+  int mode = SLIM_GRAM_CHOL;
+  int64_t ell = 0, pmax = 0;
+
+  std::vector<AngleGeom> h_geom;
+  AngleGeom* d_geom = nullptr;
+
+  const void* b = nullptr;
+  float* x = nullptr;
+  const float* x_true = nullptr;
+  bool bound = false;
+
+  // iteration state
+  int k = 0;
+  std::deque<int> window;                 // ring slots, oldest first
+  std::vector<std::vector<int>> slot_ids; // angle ids per slot
+  int epoch = 0, pos = 0;                 // solve sampler position
+
+  // workspace
+  double* d_res64 = nullptr;   // [B][ell]
+  double* d_tiles = nullptr;   // [(r+1)^2][ell][ell]
+  double* d_G = nullptr;       // [pmax][pmax]
+  double* d_z = nullptr;       // [B][pmax]
+  int* d_info = nullptr;
+  double* d_partials = nullptr;
+  double* d_norms = nullptr;   // [B][3]
+  float* d_xT = nullptr;       // [B][N][N]
+  float* d_tmp = nullptr;      // [N][N] scratch image (public projector)
+  PcgWork pcg{};
+
+  double* h_norms = nullptr;   // pinned [B][3]
+  int* h_info = nullptr;       // pinned
+
+  int last_pcg_iters = 0;
+  double last_pcg_relres = 0.0;
+  int total_pcg_iters = 0;
+
+  ~slim_ctx() {
+    (void)hipFree(d_geom);
+    (void)hipFree(d_res64);
+    (void)hipFree(d_tiles);
+    (void)hipFree(d_G);
+    (void)hipFree(d_z);
+    (void)hipFree(d_info);
+    (void)hipFree(d_partials);
+    (void)hipFree(d_norms);
+    (void)hipFree(d_xT);
+    (void)hipFree(d_tmp);
+    pcg_free(pcg);
+    if (h_norms) (void)hipHostFree(h_norms);
+    if (h_info) (void)hipHostFree(h_info);
+  }
+
+  size_t img_elems() const { return (size_t)N * N; }
+  size_t sino_elems() const { return (size_t)n_angles * R; }
+};
+
+namespace {
+
+slim_status check_ids(const slim_ctx* c, const int32_t* ids, int n, bool allow_repeat) {
+  if (!ids || n <= 0) return fail(SLIM_EINVAL, "angle id list is empty or NULL");
+  if (n > kMaxList) return fail(SLIM_EINVAL, "too many angle ids in one call");
+  for (int i = 0; i < n; ++i) {
+    if (ids[i] < 0 || ids[i] >= c->n_angles)
+      return fail(SLIM_EINVAL, "angle id " + std::to_string(ids[i]) + " out of range");
+    if (!allow_repeat)
+      for (int j = 0; j < i; ++j)
+        if (ids[j] == ids[i]) return fail(SLIM_EINVAL, "duplicate angle id in a block");
+  }
+  return SLIM_OK;
+}
+
+AngleList make_list(const int32_t* ids, int n) {
+  AngleList l;
+  l.n = n;
+  for (int i = 0; i < n; ++i) l.id[i] = ids[i];
+  for (int i = n; i < kMaxList; ++i) l.id[i] = 0;
+  return l;
+}
+
+AngleList window_list(const slim_ctx* c) {
+  AngleList l;
+  l.n = 0;
+  for (int s : c->window)
+    for (int a : c->slot_ids[s]) l.id[l.n++] = a;
+  for (int i = l.n; i < kMaxList; ++i) l.id[i] = 0;
+  return l;
+}
+
+slim_status transpose_slices(slim_ctx* c) {
+  for (int sl = 0; sl < c->B; ++sl)
+    HIP_TRY(launch_transpose(c->x + sl * c->img_elems(), c->d_xT + sl * c->img_elems(), c->N, c->st));
+  return SLIM_OK;
+}
+
+const float* sino_f32(const slim_ctx* c, int sl) {
+  return (const float*)c->b + (size_t)sl * c->sino_elems();
+}
+
+// Gram mode: z = G^{-1} [0; res] for every slice, G shared by the slices.
+slim_status gram_solve_chol(slim_ctx* c, int new_slot) {
+  const int64_t ell = c->ell;
+  const int W = (int)c->window.size();
+  const int64_t p = (int64_t)W * ell;
+  const int S = c->r + 1;
+  // new slot's row of tiles
+  AngleList na = make_list(c->slot_ids[new_slot].data(), c->g);
+  for (int q : c->window) {
+    AngleList nb = make_list(c->slot_ids[q].data(), c->g);
+    double* T = c->d_tiles + ((int64_t)new_slot * S + q) * ell * ell;
+    HIP_TRY(launch_gram(c->d_geom, c->N, c->R, na, nb, T, ell, c->st));
+  }
+  // assemble the lower triangle of G in window order (oldest first)
+  for (int P = 0; P < W; ++P)
+    for (int Q = 0; Q <= P; ++Q) {
+      const int sp = c->window[P], sq = c->window[Q];
+      const double* T = c->d_tiles + ((int64_t)sp * S + sq) * ell * ell;
+      HIP_TRY(launch_tile_copy(T, ell, c->d_G, p, (int)(P * ell), (int)(Q * ell), (int)ell,
+                               (int)ell, c->lam, P == Q, c->st));
+    }
+  HIP_TRY(hipMemsetAsync(c->d_info, 0, sizeof(int), c->st));
+  HIP_TRY(launch_cholesky(c->d_G, p, (int)p, c->d_info, c->st));
+  for (int sl = 0; sl < c->B; ++sl)
+    HIP_TRY(launch_chol_solve(c->d_G, p, (int)p, (int)ell, c->d_res64 + sl * ell,
+                              c->d_z + sl * c->pmax, c->st));
+  return SLIM_OK;
+}
+
+slim_status do_step(slim_ctx* c, const int32_t* ids, slim_step_info* info) {
+  const int S = c->r + 1;
+  const int slot = c->k % S;
+  if ((int)c->window.size() == S) c->window.pop_front();
+  c->slot_ids[slot].assign(ids, ids + c->g);
+  c->window.push_back(slot);
+  const AngleList blk = make_list(ids, c->g);
+  const AngleList win = window_list(c);
+  const int64_t ell = c->ell;
+  const int64_t p = (int64_t)c->window.size() * ell;
+
+  // 1. residual of the new block, every slice
+  for (int sl = 0; sl < c->B; ++sl) {
+    const float* xs = c->x + sl * c->img_elems();
+    const float* xTs = c->d_xT + sl * c->img_elems();
+    HIP_TRY(launch_forward(c->d_geom, c->N, c->R, blk, xs, xTs, sino_f32(c, sl), nullptr,
+                           c->d_res64 + sl * ell, c->st));
+  }
+  // 2. Gram system
+  int pcg_it = 0;
+  double pcg_rel = 0.0;
+  if (c->mode == SLIM_GRAM_CHOL) {
+    slim_status s = gram_solve_chol(c, slot);
+    if (s != SLIM_OK) return s;
+  } else {
+    for (int sl = 0; sl < c->B; ++sl) {
+      int it = 0;
+      double rel = 0.0;
+      hipError_t e = pcg_solve(c->pcg, c->d_geom, c->N, c->R, win, c->lam, c->d_res64 + sl * ell,
+                               (int)ell, c->d_z + sl * c->pmax, c->o.pcg_tol, c->o.pcg_max_iter,
+                               &it, &rel, c->st);
+      if (e != hipSuccess) return fail(SLIM_EDEVICE, std::string("pcg: ") + hipGetErrorString(e));
+      pcg_it = std::max(pcg_it, it);
+      pcg_rel = std::max(pcg_rel, rel);
+    }
+  }
+  // 3. update every slice
+  const int nwg = back_num_workgroups(c->N);
+  for (int sl = 0; sl < c->B; ++sl) {
+    float* xs = c->x + sl * c->img_elems();
+    const float* xt = c->x_true ? c->x_true + sl * c->img_elems() : nullptr;
+    HIP_TRY(launch_back(c->d_geom, c->N, c->R, win, nullptr, c->d_z + sl * c->pmax, nullptr, xs,
+                        c->d_xT + sl * c->img_elems(), xt, c->d_partials, 1, c->st));
+    HIP_TRY(launch_reduce3(c->d_partials, nwg, c->d_norms + 3 * sl, c->st));
+  }
+  (void)p;
+  c->k += 1;
+  c->last_pcg_iters = pcg_it;
+  c->last_pcg_relres = pcg_rel;
+  c->total_pcg_iters += pcg_it;
+  if (!info) return SLIM_OK;
+  HIP_TRY(hipMemcpyAsync(c->h_norms, c->d_norms, sizeof(double) * 3 * c->B, hipMemcpyDeviceToHost,
+                         c->st));
+  HIP_TRY(hipMemcpyAsync(c->h_info, c->d_info, sizeof(int), hipMemcpyDeviceToHost, c->st));
+  HIP_TRY(hipStreamSynchronize(c->st));
+  int best = 0;
+  for (int sl = 1; sl < c->B; ++sl)
+    if (c->h_norms[3 * sl] > c->h_norms[3 * best]) best = sl;
+  info->step_norm = std::sqrt(c->h_norms[3 * best + 0]);
+  info->x_norm = std::sqrt(c->h_norms[3 * best + 1]);
+  info->err_norm = c->x_true ? std::sqrt(c->h_norms[3 * best + 2]) : -1.0;
+  info->k = c->k;
+  info->pcg_iters = pcg_it;
+  info->pcg_relres = pcg_rel;
+  for (int sl = 0; sl < c->B; ++sl)
+    for (int q = 0; q < 3; ++q)
+      if (!std::isfinite(c->h_norms[3 * sl + q])) return fail(SLIM_ENUMERIC, "non-finite norm");
+  if (c->mode == SLIM_GRAM_CHOL && *c->h_info != 0)
+    return fail(SLIM_ENUMERIC, "Cholesky pivot " + std::to_string(*c->h_info - 1) + " not positive");
+  if (c->mode == SLIM_GRAM_PCG && pcg_rel > c->o.pcg_tol)
+    return fail(SLIM_ENOTCONV, "CG reached its iteration cap");
+  return SLIM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* slim_strerror(slim_status s) {
+  switch (s) {
+    case SLIM_OK: return "ok";
+    case SLIM_EINVAL: return "invalid argument";
+    case SLIM_ENOMEM: return "out of device memory";
+    case SLIM_EDEVICE: return "device error";
+    case SLIM_ENUMERIC: return "numerical failure";
+    case SLIM_ENOTCONV: return "iteration did not converge";
+    case SLIM_ESTATE: return "invalid state";
+  }
+  return "unknown status";
+}
+
+const char* slim_last_error(void) { return g_last_error.c_str(); }
+
+slim_status slim_default_opts(slim_opts* o) {
+  if (!o) return fail(SLIM_EINVAL, "opts is NULL");
+  o->angles_per_block = 1;
+  o->precision = SLIM_PREC_FP32;
+  o->gram_mode = SLIM_GRAM_AUTO;
+  o->chol_max_p = 8192;
+  o->pcg_max_iter = 1000;
+  o->pcg_tol = 1e-6;
+  o->check_every = 1;
+  o->seed = 0;
+  o->stream = nullptr;
+  return SLIM_OK;
+}
+
+slim_status slim_init(slim_ctx** out, const slim_grid* grid, int n_angles, const double* angles,
+                      int n_rays, int r, double lambda, const slim_opts* opts) {
+  g_last_error.clear();
+  if (!out) return fail(SLIM_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!grid) return fail(SLIM_EINVAL, "grid is NULL");
+  slim_opts o;
+  slim_default_opts(&o);
+  if (opts) o = *opts;
+  if (grid->N < 2 || grid->N > 16384) return fail(SLIM_EINVAL, "N must be in [2, 16384]");
+  if (grid->n_slices < 1) return fail(SLIM_EINVAL, "n_slices must be >= 1");
+  if (n_angles < 1) return fail(SLIM_EINVAL, "n_angles must be >= 1");
+  if (n_rays < 1 || n_rays > 65536) return fail(SLIM_EINVAL, "n_rays must be in [1, 65536]");
+  if (r < 0) return fail(SLIM_EINVAL, "memory level r must be >= 0");
+  if (!(lambda > 0.0) || !std::isfinite(lambda)) return fail(SLIM_EINVAL, "lambda must be positive and finite");
+  const int g = o.angles_per_block;
+  if (g < 1 || n_angles % g != 0) return fail(SLIM_EINVAL, "angles_per_block must divide n_angles");
+  if ((int64_t)(r + 1) * g > kMaxList) return fail(SLIM_EINVAL, "(r+1)*angles_per_block exceeds 256");
+  if (o.precision != SLIM_PREC_FP32 && o.precision != SLIM_PREC_BF16)
+    return fail(SLIM_EINVAL, "unknown precision");
+  if (o.gram_mode < SLIM_GRAM_AUTO || o.gram_mode > SLIM_GRAM_PCG) return fail(SLIM_EINVAL, "unknown gram_mode");
+  if (o.check_every < 1) return fail(SLIM_EINVAL, "check_every must be >= 1");
+  if (o.pcg_max_iter < 1 || !(o.pcg_tol > 0.0)) return fail(SLIM_EINVAL, "bad CG settings");
+  if (angles) {
+    for (int a = 0; a < n_angles; ++a)
+      if (!std::isfinite(angles[a])) return fail(SLIM_EINVAL, "non-finite angle");
+  }
+  const int64_t ell = (int64_t)g * n_rays;
+  const int64_t pmax = (int64_t)(r + 1) * ell;
+  int mode = o.gram_mode;
+  if (mode == SLIM_GRAM_AUTO) mode = (pmax <= o.chol_max_p && pmax <= 8192) ? SLIM_GRAM_CHOL : SLIM_GRAM_PCG;
+  if (mode == SLIM_GRAM_CHOL && pmax > 8192)
+    return fail(SLIM_EINVAL, "explicit Gram needs (r+1)*g*n_rays <= 8192; use PCG");
+  if (o.precision == SLIM_PREC_BF16) return fail(SLIM_EINVAL, "bf16 storage is not built yet");
+
+  slim_ctx* c = new slim_ctx();
+  c->N = grid->N;
+  c->B = grid->n_slices;
+  c->n_angles = n_angles;
+  c->R = n_rays;
+  c->r = r;
+  c->g = g;
+  c->lam = lambda;
+  c->o = o;
+  c->st = (hipStream_t)o.stream;
+  c->mode = mode;
+  c->ell = ell;
+  c->pmax = pmax;
+  c->slot_ids.assign(r + 1, std::vector<int>());
+
+  c->h_geom.resize(n_angles);
+  for (int a = 0; a < n_angles; ++a) {
+    const double th = angles ? angles[a] : (double)a * (M_PI / (double)n_angles);
+    const double cs = std::cos(th), sn = std::sin(th);
+    const double d = std::max(std::fabs(cs), std::fabs(sn));
+    AngleGeom& G = c->h_geom[a];
+    G.c = cs;
+    G.s = sn;
+    G.hd = (float)((2.0 / c->N) / d);
+    G.invd = (float)(1.0 / d);
+    G.colmajor = std::fabs(sn) > std::fabs(cs) ? 1 : 0;
+    G.pad = 0;
+  }
+  auto oom = [&](hipError_t e) -> slim_status {
+    delete c;
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
+      return fail(SLIM_ENOMEM, "device workspace does not fit");
+    return fail(SLIM_EDEVICE, std::string("allocation: ") + hipGetErrorString(e));
+  };
+  hipError_t e;
+  const size_t nimg = c->img_elems() * c->B;
+  if ((e = dalloc(&c->d_geom, n_angles)) != hipSuccess) return oom(e);
+  if ((e = dalloc(&c->d_res64, (size_t)c->B * ell)) != hipSuccess) return oom(e);
+  if ((e = dalloc(&c->d_z, (size_t)c->B * pmax)) != hipSuccess) return oom(e);
+  if ((e = dalloc(&c->d_info, 1)) != hipSuccess) return oom(e);
+  if ((e = dalloc(&c->d_partials, 3 * (size_t)back_num_workgroups(c->N))) != hipSuccess) return oom(e);
+  if ((e = dalloc(&c->d_norms, 3 * (size_t)c->B)) != hipSuccess) return oom(e);
+  if ((e = dalloc(&c->d_xT, nimg)) != hipSuccess) return oom(e);
+  if ((e = dalloc(&c->d_tmp, c->img_elems())) != hipSuccess) return oom(e);
+  if (mode == SLIM_GRAM_CHOL) {
+    if ((e = dalloc(&c->d_tiles, (size_t)(r + 1) * (r + 1) * ell * ell)) != hipSuccess) return oom(e);
+    if ((e = dalloc(&c->d_G, (size_t)pmax * pmax)) != hipSuccess) return oom(e);
+  } else {
+    if ((e = pcg_alloc(c->pcg, c->N, n_angles, c->R, pmax)) != hipSuccess) return oom(e);
+  }
+  if ((e = hipHostMalloc((void**)&c->h_norms, sizeof(double) * 3 * c->B, hipHostMallocDefault)) != hipSuccess) return oom(e);
+  if ((e = hipHostMalloc((void**)&c->h_info, sizeof(int), hipHostMallocDefault)) != hipSuccess) return oom(e);
+  if ((e = hipMemcpyAsync(c->d_geom, c->h_geom.data(), sizeof(AngleGeom) * n_angles,
+                          hipMemcpyHostToDevice, c->st)) != hipSuccess) return oom(e);
+  if ((e = hipMemsetAsync(c->d_info, 0, sizeof(int), c->st)) != hipSuccess) return oom(e);
+  if (mode == SLIM_GRAM_PCG) {
+    if ((e = pcg_setup(c->pcg, c->d_geom, c->N, n_angles, c->R, lambda, c->st)) != hipSuccess) return oom(e);
+  }
+  if ((e = hipStreamSynchronize(c->st)) != hipSuccess) return oom(e);
+  *out = c;
+  return SLIM_OK;
+}
+
+slim_status slim_set_data(slim_ctx* c, const void* b, void* x, const float* x_true) {
+  if (!c) return fail(SLIM_EINVAL, "ctx is NULL");
+  if (!b || !x) return fail(SLIM_EINVAL, "b and x must be non-NULL");
+  c->b = b;
+  c->x = (float*)x;
+  c->x_true = x_true;
+  c->bound = true;
+  c->k = 0;
+  c->window.clear();
+  c->epoch = 0;
+  c->pos = 0;
+  c->total_pcg_iters = 0;
+  return transpose_slices(c);
+}
+
+slim_status slim_step(slim_ctx* c, const int32_t* ids, int n_ids, slim_step_info* info) {
+  if (!c) return fail(SLIM_EINVAL, "ctx is NULL");
+  if (n_ids != c->g) return fail(SLIM_EINVAL, "n_ids must equal angles_per_block");
+  slim_status s = check_ids(c, ids, n_ids, false);
+  if (s != SLIM_OK) return s;
+  if (!c->bound) return fail(SLIM_ESTATE, "no data bound (slim_set_data)");
+  return do_step(c, ids, info);
+}
+
+slim_status slim_solve(slim_ctx* c, const void* b, void* x, const float* x_true, double tol,
+                       int max_epochs, slim_solve_info* info) {
+  if (!c) return fail(SLIM_EINVAL, "ctx is NULL");
+  if (max_epochs < 1) return fail(SLIM_EINVAL, "max_epochs must be >= 1");
+  if (!std::isfinite(tol)) return fail(SLIM_EINVAL, "tol must be finite");
+  slim_status s = slim_set_data(c, b, x, x_true);
+  if (s != SLIM_OK) return s;
+  const int M = c->n_angles / c->g;
+  slim_solve_info si{};
+  si.err_last = -1.0;
+  std::vector<int32_t> ids(c->g);
+  bool done = false;
+  for (int e = 0; e < max_epochs && !done; ++e) {
+    si.epochs = e + 1;
+    const std::vector<int> order = epoch_order(M, e, c->o.seed);
+    for (int q = 0; q < M && !done; ++q) {
+      for (int a = 0; a < c->g; ++a) ids[a] = order[q] * c->g + a;
+      c->epoch = e;
+      c->pos = q + 1;
+      const bool check = ((c->k + 1) % c->o.check_every == 0) || (e == max_epochs - 1 && q == M - 1);
+      slim_step_info st{};
+      s = do_step(c, ids.data(), check ? &st : nullptr);
+      if (s != SLIM_OK && s != SLIM_ENOTCONV) return s;
+      si.steps = c->k;
+      if (check) {
+        si.rho_last = st.x_norm > 0 ? st.step_norm / st.x_norm : INFINITY;
+        if (tol > 0 && c->k >= c->r + 1 && st.step_norm <= tol * st.x_norm) {
+          si.converged = 1;
+          done = true;
+        }
+      }
+    }
+  }
+  si.pcg_iters = c->total_pcg_iters;
+  if (info) *info = si;
+  return SLIM_OK;
+}
+
+slim_status slim_project(slim_ctx* c, const int32_t* ids, int n_ids, const float* x, float* out) {
+  if (!c) return fail(SLIM_EINVAL, "ctx is NULL");
+  slim_status s = check_ids(c, ids, n_ids, true);
+  if (s != SLIM_OK) return s;
+  if (!x || !out) return fail(SLIM_EINVAL, "x and out must be non-NULL");
+  const AngleList l = make_list(ids, n_ids);
+  for (int sl = 0; sl < c->B; ++sl) {
+    const float* xs = x + sl * c->img_elems();
+    HIP_TRY(launch_transpose(xs, c->d_tmp, c->N, c->st));
+    HIP_TRY(launch_forward(c->d_geom, c->N, c->R, l, xs, c->d_tmp, nullptr,
+                           out + (size_t)sl * n_ids * c->R, nullptr, c->st));
+  }
+  return SLIM_OK;
+}
+
+slim_status slim_backproject(slim_ctx* c, const int32_t* ids, int n_ids, const float* v, float* out) {
+  if (!c) return fail(SLIM_EINVAL, "ctx is NULL");
+  slim_status s = check_ids(c, ids, n_ids, true);
+  if (s != SLIM_OK) return s;
+  if (!v || !out) return fail(SLIM_EINVAL, "v and out must be non-NULL");
+  const AngleList l = make_list(ids, n_ids);
+  for (int sl = 0; sl < c->B; ++sl)
+    HIP_TRY(launch_back(c->d_geom, c->N, c->R, l, v + (size_t)sl * n_ids * c->R, nullptr,
+                        out + sl * c->img_elems(), nullptr, nullptr, nullptr, nullptr, 0, c->st));
+  return SLIM_OK;
+}
+
+slim_status slim_gram(slim_ctx* c, const int32_t* ida, int na, const int32_t* idb, int nb, double* out) {
+  if (!c) return fail(SLIM_EINVAL, "ctx is NULL");
+  slim_status s = check_ids(c, ida, na, true);
+  if (s != SLIM_OK) return s;
+  s = check_ids(c, idb, nb, true);
+  if (s != SLIM_OK) return s;
+  if (!out) return fail(SLIM_EINVAL, "out is NULL");
+  HIP_TRY(launch_gram(c->d_geom, c->N, c->R, make_list(ida, na), make_list(idb, nb), out,
+                      (int64_t)nb * c->R, c->st));
+  return SLIM_OK;
+}
+
+// State blob: magic, k, epoch, pos, window size, then g ids per window block.
+slim_status slim_get_state(slim_ctx* c, void* buf, int64_t* size) {
+  if (!c || !size) return fail(SLIM_EINVAL, "ctx or size is NULL");
+  const int64_t need = (int64_t)sizeof(int32_t) * (5 + c->window.size() * c->g);
+  if (!buf || *size < need) {
+    *size = need;
+    return fail(SLIM_EINVAL, "state buffer too small");
+  }
+  int32_t* w = (int32_t*)buf;
+  w[0] = 0x534c494d;
+  w[1] = c->k;
+  w[2] = c->epoch;
+  w[3] = c->pos;
+  w[4] = (int32_t)c->window.size();
+  int q = 5;
+  for (int s : c->window)
+    for (int a : c->slot_ids[s]) w[q++] = a;
+  *size = need;
+  return SLIM_OK;
+}
+
+slim_status slim_set_state(slim_ctx* c, const void* buf, int64_t size) {
+  if (!c || !buf) return fail(SLIM_EINVAL, "ctx or buf is NULL");
+  if (!c->bound) return fail(SLIM_ESTATE, "bind data before restoring state");
+  const int32_t* w = (const int32_t*)buf;
+  if (size < (int64_t)sizeof(int32_t) * 5 || w[0] != 0x534c494d) return fail(SLIM_ESTATE, "bad state blob");
+  const int W = w[4];
+  if (W < 0 || W > c->r + 1 || size < (int64_t)sizeof(int32_t) * (5 + W * c->g) || w[1] < W)
+    return fail(SLIM_ESTATE, "bad state blob");
+  for (int i = 0; i < W * c->g; ++i)
+    if (w[5 + i] < 0 || w[5 + i] >= c->n_angles) return fail(SLIM_ESTATE, "bad angle id in state");
+  c->k = w[1] - W;
+  c->window.clear();
+  c->epoch = w[2];
+  c->pos = w[3];
+  // replay the window's block entries without touching x: refill slots in
+  // the order the original run filled them, so slot numbers match
+  const int S = c->r + 1;
+  for (int i = 0; i < W; ++i) {
+    const int slot = c->k % S;
+    if ((int)c->window.size() == S) c->window.pop_front();
+    c->slot_ids[slot].assign(w + 5 + i * c->g, w + 5 + (i + 1) * c->g);
+    c->window.push_back(slot);
+    if (c->mode == SLIM_GRAM_CHOL) {
+      AngleList na = make_list(c->slot_ids[slot].data(), c->g);
+      for (int q : c->window) {
+        AngleList nb = make_list(c->slot_ids[q].data(), c->g);
+        double* T = c->d_tiles + ((int64_t)slot * S + q) * c->ell * c->ell;
+        HIP_TRY(launch_gram(c->d_geom, c->N, c->R, na, nb, T, c->ell, c->st));
+      }
+    }
+    c->k += 1;
+  }
+  HIP_TRY(transpose_slices(c) == SLIM_OK ? hipSuccess : hipErrorUnknown);
+  return SLIM_OK;
+}
+
+void slim_destroy(slim_ctx* c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->st);
+  delete c;
+}
+
+}  // extern "C"

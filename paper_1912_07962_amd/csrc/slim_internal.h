@@ -1,0 +1,110 @@
+// Internal declarations of the slimLS library: context, geometry table,
+// the shared Joseph weight evaluation, and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/slim.h"
+
+namespace slim {
+
+// Largest number of angles a single launch walks (window of r+1 blocks of g
+// angles).  Angle lists travel by value in the kernel arguments.
+constexpr int kMaxList = 256;
+
+struct AngleList {
+  int n;
+  int id[kMaxList];
+};
+
+// Per-angle geometry.  The detector coordinate of pixel (i, j) for an angle
+// is t = jj*c + ii*s + off in units of the ray spacing, with jj = j-(N-1)/2,
+// ii = i-(N-1)/2, off = (R-1)/2.  Rays of "row-major" angles (|c| >= |s|)
+// cross every image row once; the others cross every column once.
+struct AngleGeom {
+  double c, s;      // cos(theta), sin(theta)
+  float hd;         // h / d,  d = max(|c|, |s|)
+  float invd;       // 1 / d
+  int colmajor;     // 1 if |s| > |c|
+  int pad;
+};
+
+// Canonical detector coordinate; every kernel evaluates exactly this
+// expression so that all of them see bit-identical weights (the forward and
+// back projectors are then exact adjoints of one float32 matrix).
+__device__ __forceinline__ double det_coord(const AngleGeom& g, double ii, double jj, double off) {
+  return fma(jj, g.c, fma(ii, g.s, off));
+}
+
+// Joseph weight of a pixel at detector coordinate t on ray tr, 0 if tr is
+// neither floor(t) nor floor(t)+1 (those two are the only rays that can be
+// within d of t, since d <= 1).
+__device__ __forceinline__ float ray_weight(const AngleGeom& g, double t, int tr) {
+  const double fl = floor(t);
+  const int t0 = (int)fl;
+  const double f = t - fl;  // exact
+  float dist;
+  if (t0 == tr) dist = (float)f;
+  else if (t0 + 1 == tr) dist = (float)(1.0 - f);
+  else return 0.f;
+  return g.hd * fmaxf(0.f, 1.f - dist * g.invd);
+}
+
+// Both non-zero candidates of a pixel: rays t0 and t0+1 with weights w0, w1.
+__device__ __forceinline__ void pixel_weights(const AngleGeom& g, double t, int& t0, float& w0,
+                                              float& w1) {
+  const double fl = floor(t);
+  t0 = (int)fl;
+  const double f = t - fl;
+  w0 = g.hd * fmaxf(0.f, 1.f - (float)f * g.invd);
+  w1 = g.hd * fmaxf(0.f, 1.f - (float)(1.0 - f) * g.invd);
+}
+
+// ---- launchers (return hipError_t of the launch) --------------------------
+// Forward projection: out[a][t] = sum_pix A[(ids[a],t),pix] img[pix] - (sub ? sub[ids[a]][t] : 0),
+// accumulated in float64 per ray and written as float (out32) and/or double (out64).
+hipError_t launch_forward(const AngleGeom* geom, int N, int R, const AngleList& ids,
+                          const float* img, const float* imgT, const float* sub,
+                          float* out32, double* out64, hipStream_t st);
+
+// Back-projection over a list: s[pix] = sum_a sum_t A[(ids[a],t),pix] v[a][t]
+// with v float (v32) or double (v64).  mode 0: out = s.  mode 1: x -= s in
+// place, optional transposed copy xT, and per-workgroup float64 partial norms
+// (||s||^2, ||x_new||^2, ||x_new - x_true||^2) into partials[3*nwg].
+hipError_t launch_back(const AngleGeom* geom, int N, int R, const AngleList& ids,
+                       const float* v32, const double* v64, float* out, float* x, float* xT,
+                       const float* x_true, double* partials, int mode, hipStream_t st);
+int back_num_workgroups(int N);
+
+// Sum 3-vectors of partials in a fixed order into out[3] (one workgroup).
+hipError_t launch_reduce3(const double* partials, int n, double* out, hipStream_t st);
+
+// Gram block: out[(a,t),(b,u)] = sum_pix A[(ida[a],t),pix] A[(idb[b],u),pix],
+// float64, row-major with leading dimension ld.
+hipError_t launch_gram(const AngleGeom* geom, int N, int R, const AngleList& ida,
+                       const AngleList& idb, double* out, int64_t ld, hipStream_t st);
+
+// Copy a tile (rows x cols, leading dimension lds) into G at (r0, c0) with
+// leading dimension ldg, adding diag to its diagonal when add_diag != 0.
+hipError_t launch_tile_copy(const double* src, int64_t lds, double* G, int64_t ldg, int r0,
+                            int c0, int rows, int cols, double diag, int add_diag,
+                            hipStream_t st);
+
+// Lower Cholesky of the p x p row-major matrix G (ld) in place.  info[0] is
+// set to 1 + index of the first non-positive pivot (0 on success).
+hipError_t launch_cholesky(double* G, int64_t ld, int p, int* info, hipStream_t st);
+
+// Solve L y = e with e = [0; rhs] (rhs: last nr entries) and L^T z = y.
+// z: [p] float64.  rhs taken from rhs64.
+hipError_t launch_chol_solve(const double* L, int64_t ld, int p, int nr, const double* rhs64,
+                             double* z, hipStream_t st);
+
+// ---- PCG helpers -----------------------------------------------------------
+hipError_t launch_dot(const double* a, const double* b, int n, double* partials, int* nparts,
+                      hipStream_t st);
+
+}  // namespace slim

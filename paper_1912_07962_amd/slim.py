@@ -1,0 +1,261 @@
+"""ctypes binding of libslim.so (argument marshalling only).
+
+Every computation runs in the HIP library; this module converts torch
+tensors to device pointers, host lists to int32 arrays, and status codes to
+exceptions.  It never falls back to a CPU implementation: if the library is
+missing it raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import torch  # loads the HIP runtime first, so libslim binds to the same one
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "libslim.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "slim.h")
+
+SLIM_OK, SLIM_EINVAL, SLIM_ENOMEM, SLIM_EDEVICE, SLIM_ENUMERIC, SLIM_ENOTCONV, SLIM_ESTATE = range(7)
+PREC = {"fp32": 0, "bf16": 1}
+GRAM = {"auto": 0, "chol": 1, "pcg": 2}
+
+
+class SlimError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"slim status {status}: {msg}")
+        self.status = status
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int), ("n_slices", ctypes.c_int)]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("angles_per_block", ctypes.c_int), ("precision", ctypes.c_int),
+                ("gram_mode", ctypes.c_int), ("chol_max_p", ctypes.c_int),
+                ("pcg_max_iter", ctypes.c_int), ("pcg_tol", ctypes.c_double),
+                ("check_every", ctypes.c_int), ("seed", ctypes.c_uint64),
+                ("stream", ctypes.c_void_p)]
+
+
+class StepInfo(ctypes.Structure):
+    _fields_ = [("step_norm", ctypes.c_double), ("x_norm", ctypes.c_double),
+                ("err_norm", ctypes.c_double), ("k", ctypes.c_int), ("pcg_iters", ctypes.c_int),
+                ("pcg_relres", ctypes.c_double)]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_int), ("epochs", ctypes.c_int), ("converged", ctypes.c_int),
+                ("rho_last", ctypes.c_double), ("err_last", ctypes.c_double),
+                ("pcg_iters", ctypes.c_int)]
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load libslim.so (built by ``build()``); raises if it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I, D = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+    i32p = ctypes.POINTER(ctypes.c_int32)
+    sig = {
+        "slim_default_opts": (I, [ctypes.POINTER(Opts)]),
+        "slim_init": (I, [ctypes.POINTER(P), ctypes.POINTER(Grid), I, ctypes.POINTER(D), I, I, D,
+                          ctypes.POINTER(Opts)]),
+        "slim_set_data": (I, [P, P, P, P]),
+        "slim_step": (I, [P, i32p, I, ctypes.POINTER(StepInfo)]),
+        "slim_solve": (I, [P, P, P, P, D, I, ctypes.POINTER(SolveInfo)]),
+        "slim_project": (I, [P, i32p, I, P, P]),
+        "slim_backproject": (I, [P, i32p, I, P, P]),
+        "slim_gram": (I, [P, i32p, I, i32p, I, P]),
+        "slim_get_state": (I, [P, P, ctypes.POINTER(ctypes.c_int64)]),
+        "slim_set_state": (I, [P, P, ctypes.c_int64]),
+        "slim_destroy": (None, [P]),
+        "slim_strerror": (ctypes.c_char_p, [I]),
+        "slim_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def header_symbols() -> list[str]:
+    """Names of the functions declared in include/slim.h."""
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(slim_[a-z_]+)\s*\(", txt)))
+
+
+def _check(st: int):
+    if st != SLIM_OK:
+        msg = load().slim_last_error().decode()
+        raise SlimError(st, msg or load().slim_strerror(st).decode())
+
+
+def _ids(ids) -> tuple:
+    a = np.ascontiguousarray(np.asarray(ids, dtype=np.int32).reshape(-1))
+    return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), int(a.size)
+
+
+def _ptr(t, dtype=None, name="tensor"):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be on the GPU")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Slim:
+    """One slimLS context bound to the current device and torch stream."""
+
+    def __init__(self, N: int, n_angles: int, n_rays: int | None = None, r: int = 0,
+                 lam: float = 1e-2, n_slices: int = 1, angles_per_block: int = 1,
+                 precision: str = "fp32", gram_mode: str = "auto", chol_max_p: int = 8192,
+                 pcg_max_iter: int = 1000, pcg_tol: float = 1e-6, check_every: int = 1,
+                 seed: int = 0, angles=None, stream=None):
+        lib = load()
+        if n_rays is None:
+            n_rays = 2 * int(np.floor(N / np.sqrt(2.0))) + 1
+        self.N, self.n_angles, self.R, self.r = int(N), int(n_angles), int(n_rays), int(r)
+        self.lam, self.B, self.g = float(lam), int(n_slices), int(angles_per_block)
+        self.precision = precision
+        o = Opts()
+        lib.slim_default_opts(ctypes.byref(o))
+        o.angles_per_block = self.g
+        o.precision = PREC[precision]
+        o.gram_mode = GRAM[gram_mode]
+        o.chol_max_p = int(chol_max_p)
+        o.pcg_max_iter = int(pcg_max_iter)
+        o.pcg_tol = float(pcg_tol)
+        o.check_every = int(check_every)
+        o.seed = int(seed) & ((1 << 64) - 1)
+        if stream is None and torch.cuda.is_available():
+            stream = torch.cuda.current_stream()
+        o.stream = ctypes.c_void_p(stream.cuda_stream if stream is not None else 0)
+        self.stream = stream
+        ang = None
+        if angles is not None:
+            self._angles = np.ascontiguousarray(np.asarray(angles, dtype=np.float64))
+            ang = self._angles.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        g = Grid(self.N, self.B)
+        h = ctypes.c_void_p()
+        _check(lib.slim_init(ctypes.byref(h), ctypes.byref(g), self.n_angles, ang, self.R, self.r,
+                             self.lam, ctypes.byref(o)))
+        self._h = h
+        self._keep = []
+
+    # --- data and iteration ------------------------------------------------
+    def _b_dtype(self):
+        return torch.bfloat16 if self.precision == "bf16" else torch.float32
+
+    def set_data(self, b, x, x_true=None):
+        self._keep = [b, x, x_true]
+        _check(load().slim_set_data(self._h, _ptr(b, self._b_dtype(), "b"),
+                                    _ptr(x, torch.float32, "x"),
+                                    _ptr(x_true, torch.float32, "x_true")))
+
+    def step(self, angle_ids, read: bool = True) -> dict | None:
+        a, p, n = _ids(angle_ids)
+        info = StepInfo()
+        _check(load().slim_step(self._h, p, n, ctypes.byref(info) if read else None))
+        if not read:
+            return None
+        return {f: getattr(info, f) for f, _ in StepInfo._fields_}
+
+    def solve(self, b, x, x_true=None, tol: float = 1e-2, max_epochs: int = 1) -> dict:
+        self._keep = [b, x, x_true]
+        info = SolveInfo()
+        _check(load().slim_solve(self._h, _ptr(b, self._b_dtype(), "b"),
+                                 _ptr(x, torch.float32, "x"),
+                                 _ptr(x_true, torch.float32, "x_true"), float(tol),
+                                 int(max_epochs), ctypes.byref(info)))
+        return {f: getattr(info, f) for f, _ in SolveInfo._fields_}
+
+    # --- operators -----------------------------------------------------------
+    def project(self, angle_ids, x, out=None):
+        a, p, n = _ids(angle_ids)
+        if out is None:
+            out = torch.empty((self.B, n, self.R) if self.B > 1 else (n, self.R),
+                              dtype=torch.float32, device=x.device)
+        _check(load().slim_project(self._h, p, n, _ptr(x, torch.float32, "x"),
+                                   _ptr(out, torch.float32, "out")))
+        return out
+
+    def backproject(self, angle_ids, v, out=None):
+        a, p, n = _ids(angle_ids)
+        if out is None:
+            shape = (self.B, self.N, self.N) if self.B > 1 else (self.N, self.N)
+            out = torch.empty(shape, dtype=torch.float32, device=v.device)
+        _check(load().slim_backproject(self._h, p, n, _ptr(v, torch.float32, "v"),
+                                       _ptr(out, torch.float32, "out")))
+        return out
+
+    def gram(self, ids_a, ids_b, out=None, device="cuda"):
+        a, pa, na = _ids(ids_a)
+        b, pb, nb = _ids(ids_b)
+        if out is None:
+            out = torch.empty((na * self.R, nb * self.R), dtype=torch.float64, device=device)
+        _check(load().slim_gram(self._h, pa, na, pb, nb, _ptr(out, torch.float64, "out")))
+        return out
+
+    # --- checkpoint ----------------------------------------------------------
+    def get_state(self) -> bytes:
+        size = ctypes.c_int64(0)
+        st = load().slim_get_state(self._h, None, ctypes.byref(size))
+        if st not in (SLIM_OK, SLIM_EINVAL):
+            _check(st)
+        buf = ctypes.create_string_buffer(size.value)
+        _check(load().slim_get_state(self._h, buf, ctypes.byref(size)))
+        return buf.raw[:size.value]
+
+    def set_state(self, blob: bytes):
+        buf = ctypes.create_string_buffer(blob, len(blob))
+        _check(load().slim_set_state(self._h, buf, len(blob)))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().slim_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def init_error(**kw) -> int:
+    """Status of slim_init for the given arguments (no context kept).
+
+    Used to exercise argument validation, which runs before any device call."""
+    lib = load()
+    N = kw.get("N", 64)
+    o = Opts()
+    lib.slim_default_opts(ctypes.byref(o))
+    o.angles_per_block = kw.get("angles_per_block", 1)
+    o.precision = kw.get("precision", 0)
+    o.gram_mode = kw.get("gram_mode", 0)
+    o.check_every = kw.get("check_every", 1)
+    g = Grid(N, kw.get("n_slices", 1))
+    h = ctypes.c_void_p()
+    st = lib.slim_init(ctypes.byref(h), ctypes.byref(g), kw.get("n_angles", 90), None,
+                       kw.get("n_rays", 91), kw.get("r", 5), kw.get("lam", 1e-2), ctypes.byref(o))
+    if st == SLIM_OK:
+        lib.slim_destroy(h)
+    return st

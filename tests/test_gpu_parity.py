@@ -1,0 +1,209 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Tolerances: the library computes weights and images in float32 (exact
+float64 sums in the forward projector, float64 Gram / Cholesky / norms), the
+oracle everything in float64.  A weight carries one float32 rounding (rel.
+6e-8), a projection sums at most 3N products, so per-kernel results agree to
+~1e-6 relative; full reconstructions to <= 1e-5 relative (the target of the
+workload statement), limited by float32 storage of x.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import sampler, slimls, system
+
+torch = pytest.importorskip("torch")
+gpu = pytest.mark.gpu
+pytestmark = pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")
+
+if torch.cuda.is_available():
+    from paper_1912_07962_amd import Slim
+
+
+def _dev(a, dtype=torch.float32):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+
+def _rel(a, b):
+    a = np.asarray(a, np.float64).reshape(-1)
+    b = np.asarray(b, np.float64).reshape(-1)
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def _phantom(N, seed=3):
+    return synth.rasterize(synth.random_ellipses(8, seed), N)
+
+
+@gpu
+@pytest.mark.parametrize("N,na,ids", [
+    (64, 90, list(range(90))),
+    (37, 16, list(range(16))),                      # odd N, ragged tiles
+    (256, 180, [0, 45, 90, 135, 17, 99, 170]),
+    (1024, 720, [0, 1, 180, 359, 360, 540, 719, 97]),
+])
+def test_forward_matches_oracle(N, na, ids):
+    P = system.Projector(N, na)
+    x = _phantom(N).astype(np.float32)
+    s = Slim(N, na, r=0, lam=1.0)
+    got = s.project(ids, _dev(x)).cpu().numpy()
+    ref = P.forward(ids, x.astype(np.float64)).reshape(len(ids), P.R)
+    assert _rel(got, ref) < 1e-6
+    np.testing.assert_allclose(got, ref, rtol=0, atol=2e-6 * np.abs(ref).max())
+
+
+@gpu
+@pytest.mark.parametrize("N,na,ids", [
+    (64, 90, list(range(0, 90, 7))),
+    (37, 16, list(range(16))),
+    (1024, 720, [0, 180, 360, 540, 13, 721 % 720]),
+])
+def test_back_matches_oracle(N, na, ids):
+    P = system.Projector(N, na)
+    rng = np.random.default_rng(5)
+    v = rng.standard_normal((len(ids), P.R)).astype(np.float32)
+    s = Slim(N, na, r=0, lam=1.0)
+    got = s.backproject(ids, _dev(v)).cpu().numpy()
+    ref = P.back(ids, v.astype(np.float64)).reshape(N, N)
+    assert _rel(got, ref) < 1e-6
+
+
+@gpu
+def test_adjoint_identity_on_gpu():
+    N, na = 512, 360
+    ids = [0, 44, 90, 181, 270, 359]
+    rng = np.random.default_rng(6)
+    x = rng.standard_normal((N, N)).astype(np.float32)
+    R = 725
+    v = rng.standard_normal((len(ids), R)).astype(np.float32)
+    s = Slim(N, na, r=0, lam=1.0)
+    Ax = s.project(ids, _dev(x)).cpu().numpy().astype(np.float64)
+    Atv = s.backproject(ids, _dev(v)).cpu().numpy().astype(np.float64)
+    lhs = float(np.sum(Ax * v))
+    rhs = float(np.sum(x * Atv))
+    assert abs(lhs - rhs) <= 1e-5 * (np.linalg.norm(Ax) * np.linalg.norm(v))
+
+
+@gpu
+@pytest.mark.parametrize("ia,ib", [([3], [3]), ([3], [4]), ([10, 11], [40, 89]), ([0], [45]),
+                                    ([22], [23])])
+def test_gram_blocks_match_oracle(ia, ib):
+    N, na = 64, 90
+    P = system.Projector(N, na)
+    s = Slim(N, na, r=0, lam=1.0)
+    got = s.gram(ia, ib).cpu().numpy()
+    ref = (P.rows(ia) @ P.rows(ib).T).toarray()
+    np.testing.assert_allclose(got, ref, rtol=0, atol=1e-6 * np.abs(ref).max())
+
+
+def _c1_problem(N=64, na=90, seed=(1001, 2001)):
+    x_true, b, _ = synth.make_slice_problem(N, na, 10, 0.01, *seed)
+    return x_true, b
+
+
+@gpu
+@pytest.mark.parametrize("g,r,lam,mode", [(1, 5, 1e-2, "chol"), (2, 3, 1e-2, "chol"),
+                                          (3, 0, 1e-1, "chol"), (2, 3, 1e-2, "pcg")])
+def test_steps_match_oracle(g, r, lam, mode):
+    N, na = 64, 90
+    x_true, b = _c1_problem(N, na)
+    M = na // g
+    sched = sampler.schedule(M, 2, 3001)
+    P = system.Projector(N, na)
+    T = slimls.Tomo(P, b, g, r, lam, x_true=x_true)
+    s = Slim(N, na, r=r, lam=lam, angles_per_block=g, gram_mode=mode, pcg_tol=1e-11,
+             pcg_max_iter=3000)
+    x = torch.zeros((N, N), dtype=torch.float32, device="cuda")
+    s.set_data(_dev(b), x, _dev(x_true))
+    for k, beta in enumerate(sched, 1):
+        ids = list(range(beta * g, beta * g + g))
+        info = s.step(ids)
+        rec = T.step(beta)
+        assert info["k"] == k
+        if k % M == 0 or k <= 3:
+            xe = x.cpu().numpy()
+            assert _rel(xe, T.x) < 1e-5, (k, _rel(xe, T.x))
+            assert abs(info["step_norm"] - rec.step_norm) <= 1e-5 * rec.step_norm
+            assert abs(info["err_norm"] - rec.err_norm) <= 1e-5 * rec.err_norm
+
+
+@gpu
+def test_solve_matches_oracle_and_stop_rule():
+    cfg = synth.get_config("c1")
+    N, na, r, lam = cfg["N"], cfg["n_angles"], cfg["r"], cfg["lam"]
+    x_true, b = _c1_problem(N, na)
+    s = Slim(N, na, r=r, lam=lam, seed=cfg["schedule_seed"])
+    x = torch.zeros((N, N), dtype=torch.float32, device="cuda")
+    info = s.solve(_dev(b), x, _dev(x_true), tol=1e-2, max_epochs=3)
+    P = system.Projector(N, na)
+    T = slimls.Tomo(P, b, 1, r, lam, x_true=x_true)
+    sched = sampler.schedule(na, 3, cfg["schedule_seed"])
+    xo, _, kstop = T.run(sched, tol=1e-2)
+    assert info["converged"] == 1 and info["steps"] == kstop
+    assert _rel(x.cpu().numpy(), xo) < 1e-5
+
+
+@gpu
+def test_config2_first_step_matches_oracle():
+    cfg = synth.get_config("c2")
+    N, na, g, r, lam = cfg["N"], cfg["n_angles"], cfg["g"], cfg["r"], cfg["lam"]
+    x_true, b, _ = synth.make_slice_problem(N, na, cfg["n_ellipses"], cfg["noise"],
+                                            cfg["phantom_seed"], cfg["noise_seed"])
+    P = system.Projector(N, na)
+    T = slimls.Tomo(P, b, g, r, lam, x_true=x_true, chol_max_p=0, cg_tol=1e-10)
+    s = Slim(N, na, r=r, lam=lam, angles_per_block=g, gram_mode="pcg", pcg_tol=1e-9)
+    x = torch.zeros((N, N), dtype=torch.float32, device="cuda")
+    s.set_data(_dev(b), x, _dev(x_true))
+    beta = 37
+    info = s.step(list(range(beta * g, beta * g + g)))
+    T.step(beta)
+    assert _rel(x.cpu().numpy(), T.x) < 1e-5
+    assert info["pcg_relres"] <= 1e-9
+
+
+@gpu
+def test_bitwise_deterministic_and_checkpoint():
+    N, na, g, r, lam = 64, 90, 1, 5, 1e-2
+    x_true, b = _c1_problem(N, na)
+    sched = sampler.schedule(na, 1, 77)
+    outs = []
+    for _ in range(2):
+        s = Slim(N, na, r=r, lam=lam)
+        x = torch.zeros((N, N), dtype=torch.float32, device="cuda")
+        s.set_data(_dev(b), x)
+        for beta in sched[:40]:
+            s.step([beta], read=False)
+        torch.cuda.synchronize()
+        outs.append(x.clone())
+    assert torch.equal(outs[0], outs[1])
+    # checkpoint after 20 steps, continue in a fresh context
+    s = Slim(N, na, r=r, lam=lam)
+    x = torch.zeros((N, N), dtype=torch.float32, device="cuda")
+    s.set_data(_dev(b), x)
+    for beta in sched[:20]:
+        s.step([beta], read=False)
+    blob = s.get_state()
+    x2 = x.clone()
+    s2 = Slim(N, na, r=r, lam=lam)
+    s2.set_data(_dev(b), x2)
+    s2.set_state(blob)
+    for beta in sched[20:40]:
+        s2.step([beta], read=False)
+    torch.cuda.synchronize()
+    assert torch.equal(x2, outs[0])
+
+
+@gpu
+def test_step_argument_errors():
+    from paper_1912_07962_amd import SlimError
+    s = Slim(32, 12, r=1, lam=1e-2, angles_per_block=2)
+    with pytest.raises(SlimError) as e:
+        s.step([0, 1])
+    assert e.value.status == 6          # no data bound
+    b = torch.zeros((12, s.R), device="cuda")
+    x = torch.zeros((32, 32), device="cuda")
+    s.set_data(b, x)
+    for bad in ([0], [0, 0], [0, 12], [-1, 2]):
+        with pytest.raises(SlimError) as e:
+            s.step(bad)
+        assert e.value.status == 1
