@@ -100,10 +100,10 @@ typedef struct {
 slim_status slim_default_opts(slim_opts* opts);
 
 /* Create a context (paper sec. 1 setup, sec. 4.3 geometry).
- *  grid      host; N >= 2, n_slices >= 1
+ *  grid      host; 2 <= N <= 8192, n_slices >= 1
  *  n_angles  number of projection angles (>= 1)
  *  angles    host [n_angles] radians in [0, pi), or NULL for a*pi/n_angles
- *  n_rays    rays per angle R >= 1 (spacing h, centred on the axis)
+ *  n_rays    rays per angle, 1 <= R <= 4096 (spacing h, centred on the axis)
  *  r         memory level r >= 0 (sec. 1, eq. (B_k))
  *  lambda    damping 1/alpha > 0, finite
  *  opts      host, or NULL for defaults
@@ -170,6 +170,19 @@ slim_status slim_gram(slim_ctx* ctx, const int32_t* ids_a, int n_a, const int32_
  * Errors: SLIM_EINVAL (buffer too small: *size is set), SLIM_ESTATE (bad blob). */
 slim_status slim_get_state(slim_ctx* ctx, void* buf, int64_t* size);
 slim_status slim_set_state(slim_ctx* ctx, const void* buf, int64_t size);
+
+/* Per-kernel timing (measurement support).  slim_profile(ctx, 1) resets the
+ * counters and brackets every subsequent projector / Gram / Cholesky / CG
+ * vector launch group with HIP events on the context's stream; 0 stops.
+ * slim_kernel_stats returns the summed event time (ms) and the number of
+ * timed launch groups of one kind: 0 forward projector in CG products
+ * (M u over the window), 1 back-projector in CG products (M^T v over the
+ * window), 2 Gram blocks and assembly, 3 Cholesky factorisation and solves,
+ * 4 CG vector kernels, 5 residual forward projection of the new block,
+ * 6 fused back-projection and update of x.  Both synchronise the stream.
+ * Errors: SLIM_EINVAL (NULL arguments, unknown kind), SLIM_EDEVICE. */
+slim_status slim_profile(slim_ctx* ctx, int on);
+slim_status slim_kernel_stats(slim_ctx* ctx, int kind, double* total_ms, int64_t* launches);
 
 /* Release every device allocation of ctx (NULL is a no-op). */
 void slim_destroy(slim_ctx* ctx);

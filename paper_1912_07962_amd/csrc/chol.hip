@@ -106,8 +106,8 @@ __global__ __launch_bounds__(256) void syrk_update_kernel(double* __restrict__ G
   const int w = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
   // v_mfma_f64_16x16x4f64: A is 16x4 (lane l holds A[l%16][l/16]), B is 4x16
-  // (lane l holds B[l/16][l%16]); D 16x16, lane l holds rows 4*(l/16)+v of
-  // column l%16 in its four accumulators v = 0..3.
+  // (lane l holds B[l/16][l%16]); D is 16x16 and accumulator v of lane l
+  // holds D[4*v + l/16][l%16] (rows interleaved across the accumulators).
   double4_t acc[4];
 #pragma unroll
   for (int cb = 0; cb < 4; ++cb) acc[cb] = (double4_t){0.0, 0.0, 0.0, 0.0};
@@ -125,7 +125,7 @@ __global__ __launch_bounds__(256) void syrk_update_kernel(double* __restrict__ G
   for (int cb = 0; cb < 4; ++cb) {
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int r = r0 + w * 16 + 4 * (lane >> 4) + v;
+      const int r = r0 + w * 16 + 4 * v + (lane >> 4);
       const int c = c0 + cb * 16 + (lane & 15);
       if (r < p && c < p && c <= r) G[(int64_t)r * ld + c] -= acc[cb][v];
     }

@@ -27,15 +27,16 @@ struct PcgWork {
 hipError_t pcg_alloc(PcgWork& w, int N, int n_angles, int R, int64_t pmax);
 void pcg_free(PcgWork& w);
 // Per-ray squared norms of every angle -> dinv.
-hipError_t pcg_setup(PcgWork& w, const AngleGeom* geom, int N, int n_angles, int R, double lam,
-                     hipStream_t st);
+hipError_t pcg_setup(PcgWork& w, const AngleGeom* geom, const AngleGeom* h_geom, int N,
+                     int n_angles, int R, double lam, float* partial, hipStream_t st);
 // Solve for one slice: rhs = [0; res] (res: last nres entries), z: [p] out.
-hipError_t pcg_solve(PcgWork& w, const AngleGeom* geom, int N, int R, const AngleList& win,
+hipError_t pcg_solve(PcgWork& w, const AngleGeom* geom, const AngleGeom* h_geom, float* partial,
+                     int N, int R, const AngleList& win,
                      double lam, const double* res, int nres, double* z, double tol, int max_iter,
-                     int* iters, double* relres, hipStream_t st);
+                     int* iters, double* relres, Profiler* prof, hipStream_t st);
 
 hipError_t launch_transpose(const float* src, float* dst, int N, hipStream_t st);
-hipError_t launch_ray_sqnorm(const AngleGeom* geom, int N, int R, const AngleList& ids, double* out,
-                             hipStream_t st);
+hipError_t launch_ray_sqnorm(const AngleGeom* geom, const AngleGeom* h_geom, int N, int R,
+                             const AngleList& ids, double* out, float* partial, hipStream_t st);
 
 }  // namespace slim

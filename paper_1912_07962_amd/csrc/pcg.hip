@@ -68,23 +68,6 @@ __global__ __launch_bounds__(kThreads) void init_kernel(AngleList win, int R, in
   }
 }
 
-// q += lambda pd; partial <pd, q>
-__global__ __launch_bounds__(kThreads) void apply_tail_kernel(int p, double lam,
-                                                              const double* __restrict__ pd,
-                                                              double* __restrict__ q,
-                                                              double* __restrict__ parts) {
-  __shared__ double sh[kThreads / 64];
-  const int i = blockIdx.x * kThreads + threadIdx.x;
-  double pq = 0.0;
-  if (i < p) {
-    const double v = fma(lam, pd[i], q[i]);
-    q[i] = v;
-    pq = pd[i] * v;
-  }
-  pq = block_sum(pq, sh);
-  if (threadIdx.x == 0) parts[blockIdx.x] = pq;
-}
-
 // which: 0 -> init (rz, rr, bb=rr), 1 -> alpha = rz / pq, 2 -> beta, rz, rr
 __global__ __launch_bounds__(kThreads) void scalar_kernel(const double* __restrict__ parts,
                                                           int nparts, int which,
@@ -193,13 +176,13 @@ void pcg_free(PcgWork& w) {
   w = PcgWork{};
 }
 
-hipError_t pcg_setup(PcgWork& w, const AngleGeom* geom, int N, int n_angles, int R, double lam,
-                     hipStream_t st) {
+hipError_t pcg_setup(PcgWork& w, const AngleGeom* geom, const AngleGeom* h_geom, int N,
+                     int n_angles, int R, double lam, float* partial, hipStream_t st) {
   for (int a0 = 0; a0 < n_angles; a0 += kMaxList) {
     AngleList l;
     l.n = std::min(kMaxList, n_angles - a0);
     for (int i = 0; i < kMaxList; ++i) l.id[i] = (i < l.n) ? a0 + i : 0;
-    hipError_t e = launch_ray_sqnorm(geom, N, R, l, w.dinv + (size_t)a0 * R, st);
+    hipError_t e = launch_ray_sqnorm(geom, h_geom, N, R, l, w.dinv + (size_t)a0 * R, partial, st);
     if (e != hipSuccess) return e;
   }
   const int n = n_angles * R;
@@ -208,9 +191,10 @@ hipError_t pcg_setup(PcgWork& w, const AngleGeom* geom, int N, int n_angles, int
   return hipGetLastError();
 }
 
-hipError_t pcg_solve(PcgWork& w, const AngleGeom* geom, int N, int R, const AngleList& win,
+hipError_t pcg_solve(PcgWork& w, const AngleGeom* geom, const AngleGeom* h_geom, float* partial,
+                     int N, int R, const AngleList& win,
                      double lam, const double* res, int nres, double* z, double tol, int max_iter,
-                     int* iters, double* relres, hipStream_t st) {
+                     int* iters, double* relres, Profiler* prof, hipStream_t st) {
   const int p = win.n * R;
   const int nb = (p + kThreads - 1) / kThreads;
   hipError_t e;
@@ -230,31 +214,77 @@ hipError_t pcg_solve(PcgWork& w, const AngleGeom* geom, int N, int R, const Angl
   while (it < max_iter) {
     const int todo = std::min(kCheck, max_iter - it);
     for (int q = 0; q < todo; ++q) {
+      if (prof->on && (e = prof->begin(K_BACK, st)) != hipSuccess) return e;
       if ((e = launch_back(geom, N, R, win, nullptr, w.pd, w.u, nullptr, w.uT, nullptr, nullptr, 0,
                            st)) != hipSuccess)
         return e;
-      if ((e = launch_forward(geom, N, R, win, w.u, w.uT, nullptr, nullptr, w.q, st)) != hipSuccess)
+      if (prof->on && (e = prof->end(st)) != hipSuccess) return e;
+      if (prof->on && (e = prof->begin(K_FORWARD, st)) != hipSuccess) return e;
+      // q = M u + lambda pd and partial <pd, q>, fused into the forward's reduction
+      if ((e = launch_forward(geom, h_geom, N, R, win, w.u, w.uT, nullptr, nullptr, w.q, partial,
+                              w.pd, lam, w.parts, st)) != hipSuccess)
         return e;
-      hipLaunchKernelGGL(apply_tail_kernel, dim3(nb), dim3(kThreads), 0, st, p, lam, w.pd, w.q,
-                         w.parts);
+      if (prof->on && (e = prof->end(st)) != hipSuccess) return e;
+      if (prof->on && (e = prof->begin(K_VEC, st)) != hipSuccess) return e;
       hipLaunchKernelGGL(scalar_kernel, dim3(1), dim3(kThreads), 0, st, w.parts, nb, 1, w.sc);
       hipLaunchKernelGGL(update_kernel, dim3(nb), dim3(kThreads), 0, st, win, R, p, w.sc, w.dinv,
                          w.pd, w.q, z, w.r, w.y, w.parts, nb);
       hipLaunchKernelGGL(scalar_kernel, dim3(1), dim3(kThreads), 0, st, w.parts, nb, 2, w.sc);
       hipLaunchKernelGGL(direction_kernel, dim3(nb), dim3(kThreads), 0, st, p, w.sc, w.y, w.pd);
       if ((e = hipGetLastError()) != hipSuccess) return e;
+      if (prof->on && (e = prof->end(st)) != hipSuccess) return e;
     }
     it += todo;
     if ((e = hipMemcpyAsync(w.h_sc, w.sc, S_COUNT * sizeof(double), hipMemcpyDeviceToHost, st)) !=
         hipSuccess)
       return e;
     if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+    if (prof->on && (e = prof->harvest()) != hipSuccess) return e;
     rr = w.h_sc[S_RR];
     if (!(rr > target)) break;  // also stops on NaN
   }
   *iters = it;
   *relres = std::sqrt(rr / bb);
   return hipSuccess;
+}
+
+hipError_t Profiler::begin(int k, hipStream_t st) {
+  if ((size_t)(2 * used + 2) > pool.size()) {
+    for (int q = 0; q < 64; ++q) {
+      hipEvent_t ev;
+      hipError_t e = hipEventCreate(&ev);
+      if (e != hipSuccess) return e;
+      pool.push_back(ev);
+    }
+  }
+  if ((size_t)used >= kind.size()) kind.resize(used + 1);
+  kind[used] = k;
+  return hipEventRecord(pool[2 * used], st);
+}
+
+hipError_t Profiler::end(hipStream_t st) {
+  hipError_t e = hipEventRecord(pool[2 * used + 1], st);
+  ++used;
+  return e;
+}
+
+hipError_t Profiler::harvest() {
+  for (int q = 0; q < used; ++q) {
+    float ms = 0.f;
+    hipError_t e = hipEventElapsedTime(&ms, pool[2 * q], pool[2 * q + 1]);
+    if (e != hipSuccess) return e;
+    total_ms[kind[q]] += ms;
+    launches[kind[q]] += 1;
+  }
+  used = 0;
+  return hipSuccess;
+}
+
+void Profiler::release() {
+  for (hipEvent_t ev : pool) (void)hipEventDestroy(ev);
+  pool.clear();
+  kind.clear();
+  used = 0;
 }
 
 }  // namespace slim

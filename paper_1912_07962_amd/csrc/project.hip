@@ -1,127 +1,235 @@
 // Matrix-free Joseph projectors for gfx950.
 //
-// Forward (ray-driven): one lane per ray, a 64-wide wavefront covers 64
-// adjacent rays of one angle, and the four wavefronts of a workgroup split
-// the ray's path into four consecutive segments whose partial sums are
-// combined in a fixed order (deterministic).  A ray steps along its major
-// axis (rows for |cos| >= |sin|, else columns) and evaluates the canonical
-// weight on the three pixels nearest its crossing point; the weight is
-// exactly zero on all but at most two of them.  For column-stepping angles
-// the transposed image is read when available, so that adjacent lanes read
-// adjacent addresses in both cases.
+// Forward (ray-driven, LDS bands): the image is cut into bands of H rows
+// (row-stepping angles) or H rows of its transpose (column-stepping angles,
+// i.e. H image columns), H*(N+4) floats <= 64 KB.  A workgroup owns a group
+// of consecutive bands and a chunk of angles of one orientation; it streams
+// its bands through LDS (zero-padded by two pixels on each side, so no
+// bounds checks in the inner loop) and every lane walks up to 8 rays across
+// them, interpolating linearly between the two pixels nearest the crossing
+// point (Joseph), accumulating in float64.  Per-group partial sums are
+// combined by a second kernel in a fixed order (deterministic, no atomics).
+// Workgroups are numbered so that each XCD works on a contiguous range of
+// band groups and its L2 holds only its slice of the image.
 //
-// Back (pixel-driven gather): one lane per pixel of a 16x16 tile; for every
-// angle of the list the pixel's two rays are read and weighted.  No atomics;
-// the optional fused update writes x -= s (and its transpose through LDS)
-// and per-workgroup float64 partial norms.
+// Back (pixel-driven gather): a workgroup owns a 16 x 64 pixel tile and
+// stages, for every angle of the list, the segment of ray values its tile
+// touches (scaled by h/d) in LDS; each lane gathers two rays per angle for
+// four consecutive pixels of a row.  No atomics; the optional fused update
+// writes x -= s, the transposed image, and per-workgroup float64 partial
+// norms.  Both projectors evaluate the same closed-form weights and agree to
+// float32 rounding of the weights.
 #include "slim_internal.h"
 #include "pcg.h"
+
+#include <algorithm>
 
 namespace slim {
 
 namespace {
 
-constexpr int kFwdSeg = 4;
+// ---------------------------------------------------------------- forward
+constexpr int kFT = 512;      // threads per forward workgroup
+constexpr int kFItems = 8;    // rays per lane
+constexpr int kPad = 2;       // zero columns on each side of a band row
 
-// SQ: accumulate squared weights (row norms of A) instead of weight * pixel.
-template <bool SQ>
-__global__ __launch_bounds__(256) void forward_kernel(const AngleGeom* __restrict__ geom, int N,
-                                                      int R, AngleList ids,
-                                                      const float* __restrict__ img,
-                                                      const float* __restrict__ imgT,
-                                                      const float* __restrict__ sub,
-                                                      float* __restrict__ out32,
-                                                      double* __restrict__ out64) {
-  __shared__ double red[kFwdSeg][64];
-  const int lane = threadIdx.x & 63;
-  const int seg = threadIdx.x >> 6;
-  const int tr = blockIdx.x * 64 + lane;
-  const int a = blockIdx.y;
-  const int ang = ids.id[a];
-  const AngleGeom g = geom[ang];
-  const double half = 0.5 * (N - 1);
-  const double off = 0.5 * (R - 1);
-  double acc = 0.0;
-  if (tr < R) {
-    const double cm = g.colmajor ? g.c : g.s;  // coefficient of the major coordinate
-    const double cn = g.colmajor ? g.s : g.c;  // coefficient of the minor one, |cn| = d
-    const double inv = 1.0 / cn;
-    const double n0 = ((double)tr - off) * inv;  // crossing minor coordinate at major 0
-    const double n1 = -cm * inv;                 // its change per major step
-    const double lim = half + 1.5;
-    double lo = -half, hi = half;
-    if (n1 != 0.0) {
-      const double ma = (-lim - n0) / n1, mb = (lim - n0) / n1;
-      lo = fmax(lo, fmin(ma, mb));
-      hi = fmin(hi, fmax(ma, mb));
-    } else if (fabs(n0) > lim) {
-      lo = 1.0;
-      hi = 0.0;
-    }
-    int klo = 0, khi = -1;
-    if (lo <= hi) {
-      klo = max(0, (int)ceil(lo + half) - 1);
-      khi = min(N - 1, (int)floor(hi + half) + 1);
-    }
-    const int cnt = khi - klo + 1;
-    if (cnt > 0) {
-      const int per = (cnt + kFwdSeg - 1) / kFwdSeg;
-      const int k0 = klo + seg * per;
-      const int k1 = min(khi, k0 + per - 1);
-      if (!g.colmajor) {
-        for (int k = k0; k <= k1; ++k) {
-          const double ii = (double)k - half;
-          const double inner = fma(ii, g.s, off);
-          const double nc = fma(ii, n1, n0) + half;
-          const int jc = (int)rint(nc);
-          const float* row = img + (size_t)k * N;
-          float racc = 0.f;
-#pragma unroll
-          for (int dj = -1; dj <= 1; ++dj) {
-            const int j = jc + dj;
-            if (j >= 0 && j < N) {
-              const double t = fma((double)j - half, g.c, inner);
-              const float w = ray_weight(g, t, tr);
-              racc = fmaf(w, SQ ? w : row[j], racc);
-            }
-          }
-          acc += (double)racc;
-        }
-      } else {
-        for (int k = k0; k <= k1; ++k) {
-          const double jj = (double)k - half;
-          const double nc = fma(jj, n1, n0) + half;
-          const int ic = (int)rint(nc);
-          float racc = 0.f;
-#pragma unroll
-          for (int di = -1; di <= 1; ++di) {
-            const int i = ic + di;
-            if (i >= 0 && i < N) {
-              const double t = fma(jj, g.c, fma((double)i - half, g.s, off));
-              const float w = ray_weight(g, t, tr);
-              const float v = SQ ? w : (imgT ? imgT[(size_t)k * N + i] : img[(size_t)i * N + k]);
-              racc = fmaf(w, v, racc);
-            }
-          }
-          acc += (double)racc;
-        }
-      }
-    }
-  }
-  red[seg][lane] = acc;
-  __syncthreads();
-  if (seg == 0 && tr < R) {
-    double v = red[0][lane];
-#pragma unroll
-    for (int q = 1; q < kFwdSeg; ++q) v += red[q][lane];
-    if (sub) v -= (double)sub[(size_t)ang * R + tr];
-    const size_t o = (size_t)a * R + tr;
-    if (out32) out32[o] = (float)v;
-    if (out64) out64[o] = v;
+struct FwdPlan {
+  int n;          // entries (= output rows)
+  int n_row;      // entries 0..n_row-1 are row-stepping angles
+  int ch;         // angles per chunk
+  int n_chunks;   // row-stepping chunks first
+  int H, G;       // rows per band, bands per group
+  int n_groups;
+  short id[kMaxList];
+  short slot[kMaxList];
+};
+
+__device__ __forceinline__ void chunk_range(const FwdPlan& pl, int c, int& e0, int& e1, bool& colm) {
+  const int nrc = (pl.n_row + pl.ch - 1) / pl.ch;
+  if (c < nrc) {
+    e0 = c * pl.ch;
+    e1 = min(pl.n_row, e0 + pl.ch);
+    colm = false;
+  } else {
+    e0 = pl.n_row + (c - nrc) * pl.ch;
+    e1 = min(pl.n, e0 + pl.ch);
+    colm = true;
   }
 }
 
-constexpr int kTile = 16;
+template <bool SQ>
+__global__ __launch_bounds__(kFT) void fwd_band_kernel(const AngleGeom* __restrict__ geom, int N,
+                                                       int R, FwdPlan pl,
+                                                       const float* __restrict__ img,
+                                                       const float* __restrict__ imgT,
+                                                       float* __restrict__ partial) {
+  extern __shared__ float band[];
+  const int W = N + 2 * kPad;
+  // XCD-aware numbering: consecutive positions live on one XCD
+  const int total = pl.n_groups * pl.n_chunks;
+  const int per_xcd = gridDim.x >> 3;
+  const int pos = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+  if (pos >= total) return;
+  const int grp = pos / pl.n_chunks;
+  const int chunk = pos % pl.n_chunks;
+  int e0, e1;
+  bool colm;
+  chunk_range(pl, chunk, e0, e1, colm);
+  const int nitems = (e1 - e0) * R;
+  const float* src = colm ? imgT : img;
+  const double half = 0.5 * (N - 1);
+  const double off = 0.5 * (R - 1);
+
+  double pos0[kFItems], step[kFItems], acc[kFItems];
+  int klo[kFItems], khi[kFItems];
+#pragma unroll
+  for (int q = 0; q < kFItems; ++q) {
+    const int item = threadIdx.x + q * kFT;
+    acc[q] = 0.0;
+    klo[q] = 0;
+    khi[q] = -1;
+    pos0[q] = 0.0;
+    step[q] = 0.0;
+    if (item < nitems) {
+      const int e = e0 + item / R;
+      const int t = item % R;
+      const AngleGeom g = geom[pl.id[e]];
+      const double cm = colm ? g.c : g.s;   // coefficient of the major coordinate
+      const double cn = colm ? g.s : g.c;   // of the minor one, |cn| = d
+      const double inv = 1.0 / cn;
+      // crossing position (0-based minor pixel index, shifted by kPad) at major index k:
+      // pos(k) = p0 + k * n1
+      const double n1 = -cm * inv;
+      const double p0 = ((double)t - off) * inv + half + kPad - half * n1;
+      // rows with pos - kPad in [-1.5, N + 0.5]: every contributing row, all in the pad
+      const double lo_p = kPad - 1.5, hi_p = N + kPad + 0.5;
+      double lo = 0.0, hi = N - 1;
+      if (n1 != 0.0) {
+        const double ma = (lo_p - p0) / n1, mb = (hi_p - p0) / n1;
+        lo = fmax(lo, ceil(fmin(ma, mb)));
+        hi = fmin(hi, floor(fmax(ma, mb)));
+      } else if (p0 < lo_p || p0 > hi_p) {
+        lo = 1.0;
+        hi = 0.0;
+      }
+      klo[q] = (int)lo;
+      khi[q] = (int)hi;
+      pos0[q] = p0;
+      step[q] = n1;
+    }
+  }
+
+  const int kg = grp * pl.G * pl.H;
+  for (int bb = 0; bb < pl.G; ++bb) {
+    const int kb = kg + bb * pl.H;
+    if (kb >= N) break;
+    const int hb = min(pl.H, N - kb);
+    __syncthreads();
+    if (!SQ) {
+      for (int e = threadIdx.x; e < hb * W; e += kFT) {
+        const int r = e / W, c = e % W - kPad;
+        band[e] = (c >= 0 && c < N) ? src[(size_t)(kb + r) * N + c] : 0.f;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kFItems; ++q) {
+      const int k0 = max(klo[q], kb), k1 = min(khi[q], kb + hb - 1);
+      float a32 = 0.f;
+      for (int k = k0; k <= k1; ++k) {
+        const double p = fma((double)k, step[q], pos0[q]);
+        const int qi = (int)p;  // p >= 0.5 - eps: truncation is floor
+        const float phi = (float)(p - (double)qi);
+        if (SQ) {
+          const float w0 = (qi - kPad >= 0 && qi - kPad < N) ? 1.f - phi : 0.f;
+          const float w1 = (qi + 1 - kPad >= 0 && qi + 1 - kPad < N) ? phi : 0.f;
+          a32 = fmaf(w0, w0, fmaf(w1, w1, a32));
+        } else {
+          const float* rp = band + (k - kb) * W + qi;
+          const float v0 = rp[0], v1 = rp[1];
+          a32 += fmaf(phi, v1 - v0, v0);
+        }
+      }
+      acc[q] += (double)a32;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < kFItems; ++q) {
+    const int item = threadIdx.x + q * kFT;
+    if (item < nitems) {
+      const int e = e0 + item / R;
+      const int t = item % R;
+      partial[((size_t)grp * pl.n + pl.slot[e]) * R + t] = (float)acc[q];
+    }
+  }
+}
+
+// out[s][t] = (h/d) sum_groups partial - sub; optional CG tail q = out + lam*pd
+// with per-workgroup partial dot <pd, q>.
+__global__ __launch_bounds__(256) void fwd_reduce_kernel(const AngleGeom* __restrict__ geom, int R,
+                                                         AngleList ids, int n_groups, int SQ,
+                                                         const float* __restrict__ partial,
+                                                         const float* __restrict__ sub,
+                                                         float* __restrict__ out32,
+                                                         double* __restrict__ out64,
+                                                         const double* __restrict__ pd, double lam,
+                                                         double* __restrict__ dots) {
+  __shared__ double sh[4];
+  const int o = blockIdx.x * 256 + threadIdx.x;
+  const int n = ids.n * R;
+  double d = 0.0;
+  if (o < n) {
+    const int s = o / R, t = o % R;
+    const int ang = ids.id[s];
+    double v = 0.0;
+    for (int g = 0; g < n_groups; ++g) v += (double)partial[((size_t)g * ids.n + s) * R + t];
+    const double hd = (double)geom[ang].hd;
+    v *= SQ ? hd * hd : hd;
+    if (sub) v -= (double)sub[(size_t)ang * R + t];
+    if (pd) {
+      v = fma(lam, pd[o], v);
+      d = pd[o] * v;
+    }
+    if (out32) out32[o] = (float)v;
+    if (out64) out64[o] = v;
+  }
+  if (dots) {
+    for (int w = 32; w > 0; w >>= 1) d += __shfl_down(d, w, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = d;
+    __syncthreads();
+    if (threadIdx.x == 0) dots[blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
+  }
+}
+
+FwdPlan make_plan(const AngleGeom* h_geom, int N, int R, const AngleList& ids) {
+  FwdPlan pl;
+  pl.n = ids.n;
+  int k = 0;
+  for (int pass = 0; pass < 2; ++pass)
+    for (int s = 0; s < ids.n; ++s)
+      if ((h_geom[ids.id[s]].colmajor != 0) == (pass == 1)) {
+        pl.id[k] = (short)ids.id[s];
+        pl.slot[k] = (short)s;
+        ++k;
+      }
+  pl.n_row = 0;
+  for (int s = 0; s < ids.n; ++s) pl.n_row += h_geom[ids.id[s]].colmajor ? 0 : 1;
+  pl.ch = std::max(1, std::min(kFItems * kFT / R, ids.n));
+  pl.n_chunks = (pl.n_row + pl.ch - 1) / pl.ch + (ids.n - pl.n_row + pl.ch - 1) / pl.ch;
+  pl.H = std::max(1, std::min(N, 16384 / (N + 2 * kPad)));
+  const int nbands = (N + pl.H - 1) / pl.H;
+  int want = (1024 + pl.n_chunks - 1) / pl.n_chunks;
+  want = std::max(1, std::min(want, nbands));
+  pl.G = (nbands + want - 1) / want;
+  pl.n_groups = (nbands + pl.G - 1) / pl.G;
+  return pl;
+}
+
+// ------------------------------------------------------------------- back
+constexpr int kBH = 16, kBW = 64;   // tile rows, columns
+constexpr int kBPX = 4;             // consecutive pixels per lane
+constexpr int kBAng = 64;           // angles staged per pass
+constexpr int kSeg = 72;            // LDS stride of one angle's ray segment
 
 __device__ __forceinline__ double wave_sum(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
@@ -135,63 +243,104 @@ __global__ __launch_bounds__(256) void back_kernel(const AngleGeom* __restrict__
                                                    float* __restrict__ xT,
                                                    const float* __restrict__ x_true,
                                                    double* __restrict__ partials, int mode) {
-  __shared__ float tileT[kTile][kTile + 1];
+  __shared__ float seg[kBAng * kSeg];
+  __shared__ int tmin[kBAng];
+  __shared__ float tile[kBH][kBW + 1];
   __shared__ double wred[4][3];
-  const int tx = threadIdx.x & (kTile - 1);
-  const int ty = threadIdx.x / kTile;
-  const int j = blockIdx.x * kTile + tx;
-  const int i = blockIdx.y * kTile + ty;
-  const bool in = (i < N) && (j < N);
+  const int tx = threadIdx.x & 15;       // 16 lanes x 4 pixels = 64 columns
+  const int ty = threadIdx.x >> 4;       // 16 rows
+  const int i0 = blockIdx.y * kBH, j0 = blockIdx.x * kBW;
+  const int i = i0 + ty;
+  const int jb = j0 + kBPX * tx;
   const double half = 0.5 * (N - 1);
   const double off = 0.5 * (R - 1);
-  const double ii = (double)i - half, jj = (double)j - half;
-  float s = 0.f;
-  if (in) {
-    for (int a = 0; a < ids.n; ++a) {
-      const AngleGeom g = geom[ids.id[a]];
-      const double t = det_coord(g, ii, jj, off);
-      int t0;
-      float w0, w1;
-      pixel_weights(g, t, t0, w0, w1);
-      const VT* va = v + (size_t)a * R;
-      const float v0 = (t0 >= 0 && t0 < R) ? (float)va[t0] : 0.f;
-      const float v1 = (t0 + 1 >= 0 && t0 + 1 < R) ? (float)va[t0 + 1] : 0.f;
-      s = fmaf(w0, v0, s);
-      s = fmaf(w1, v1, s);
+  const double ii = (double)i - half;
+  // nominal tile corners (pixel centres) bound every pixel the lanes evaluate
+  const double ci0 = (double)i0 - half, ci1 = (double)(i0 + kBH - 1) - half;
+  const double cj0 = (double)j0 - half, cj1 = (double)(j0 + kBW - 1) - half;
+  float s[kBPX] = {0.f, 0.f, 0.f, 0.f};
+  for (int a0 = 0; a0 < ids.n; a0 += kBAng) {
+    const int na = min(kBAng, ids.n - a0);
+    __syncthreads();
+    if ((int)threadIdx.x < na) {
+      const AngleGeom g = geom[ids.id[a0 + threadIdx.x]];
+      const double t00 = det_coord(g, ci0, cj0, off), t01 = det_coord(g, ci0, cj1, off);
+      const double t10 = det_coord(g, ci1, cj0, off), t11 = det_coord(g, ci1, cj1, off);
+      tmin[threadIdx.x] = (int)floor(fmin(fmin(t00, t01), fmin(t10, t11))) - 1;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < na * kSeg; e += 256) {
+      const int a = e / kSeg, u = e % kSeg;
+      const int t = tmin[a] + u;
+      const AngleGeom& g = geom[ids.id[a0 + a]];
+      seg[e] = (t >= 0 && t < R) ? g.hd * (float)v[(size_t)(a0 + a) * R + t] : 0.f;
+    }
+    __syncthreads();
+    if (i < N) {
+      for (int a = 0; a < na; ++a) {
+        const AngleGeom g = geom[ids.id[a0 + a]];
+        const double Ti = fma(ii, g.s, off);
+        const float* sa = seg + a * kSeg - tmin[a];
+#pragma unroll
+        for (int q = 0; q < kBPX; ++q) {
+          const double t = fma((double)(jb + q) - half, g.c, Ti);
+          const double fl = floor(t);
+          const double f = t - fl;
+          const int t0 = (int)fl;
+          const float w0 = fmaxf(0.f, 1.f - (float)f * g.invd);
+          const float w1 = fmaxf(0.f, 1.f - (float)(1.0 - f) * g.invd);
+          s[q] = fmaf(w0, sa[t0], fmaf(w1, sa[t0 + 1], s[q]));
+        }
+      }
     }
   }
+  const bool full = (i < N) && (jb + kBPX - 1 < N);
   if (mode == 0) {
-    if (in) out[(size_t)i * N + j] = s;
-    if (xT) {  // transposed copy of out through LDS
-      tileT[ty][tx] = s;
+    if (full && (N & 3) == 0) {
+      *reinterpret_cast<float4*>(out + (size_t)i * N + jb) = make_float4(s[0], s[1], s[2], s[3]);
+    } else if (i < N) {
+      for (int q = 0; q < kBPX; ++q)
+        if (jb + q < N) out[(size_t)i * N + jb + q] = s[q];
+    }
+    if (xT) {
       __syncthreads();
-      const int jt = blockIdx.x * kTile + ty;
-      const int it = blockIdx.y * kTile + tx;
-      if (jt < N && it < N) xT[(size_t)jt * N + it] = tileT[tx][ty];
+#pragma unroll
+      for (int q = 0; q < kBPX; ++q) tile[ty][kBPX * tx + q] = s[q];
+      __syncthreads();
+      for (int e = threadIdx.x; e < kBH * kBW; e += 256) {
+        const int jl = e / kBH, il = e % kBH;
+        if (j0 + jl < N && i0 + il < N) xT[(size_t)(j0 + jl) * N + i0 + il] = tile[il][jl];
+      }
     }
     return;
   }
   double ss = 0.0, xx = 0.0, ee = 0.0;
-  float xn = 0.f;
-  if (in) {
-    const size_t p = (size_t)i * N + j;
-    xn = x[p] - s;
-    x[p] = xn;
-    ss = (double)s * (double)s;
-    xx = (double)xn * (double)xn;
-    if (x_true) {
-      const double e = (double)xn - (double)x_true[p];
-      ee = e * e;
+  float xn[kBPX] = {0.f, 0.f, 0.f, 0.f};
+  if (i < N) {
+#pragma unroll
+    for (int q = 0; q < kBPX; ++q) {
+      if (jb + q < N) {
+        const size_t p = (size_t)i * N + jb + q;
+        xn[q] = x[p] - s[q];
+        x[p] = xn[q];
+        ss += (double)s[q] * (double)s[q];
+        xx += (double)xn[q] * (double)xn[q];
+        if (x_true) {
+          const double e = (double)xn[q] - (double)x_true[p];
+          ee += e * e;
+        }
+      }
     }
   }
   if (xT) {
-    tileT[ty][tx] = xn;
     __syncthreads();
-    // write the transposed tile: lane (ty, tx) writes xT[j'][i'] with
-    // j' = tile column ty, i' = tile row tx -> 16 consecutive floats per row
-    const int jt = blockIdx.x * kTile + ty;
-    const int it = blockIdx.y * kTile + tx;
-    if (jt < N && it < N) xT[(size_t)jt * N + it] = tileT[tx][ty];
+#pragma unroll
+    for (int q = 0; q < kBPX; ++q) tile[ty][kBPX * tx + q] = xn[q];
+    __syncthreads();
+    for (int e = threadIdx.x; e < kBH * kBW; e += 256) {
+      const int jl = e / kBH, il = e % kBH;
+      if (j0 + jl < N && i0 + il < N) xT[(size_t)(j0 + jl) * N + i0 + il] = tile[il][jl];
+    }
   }
   ss = wave_sum(ss);
   xx = wave_sum(xx);
@@ -234,6 +383,8 @@ __global__ __launch_bounds__(256) void reduce3_kernel(const double* __restrict__
   if (threadIdx.x < 3) out[threadIdx.x] = red[threadIdx.x][0];
 }
 
+constexpr int kTile = 16;
+
 __global__ __launch_bounds__(256) void transpose_kernel(const float* __restrict__ src,
                                                         float* __restrict__ dst, int N) {
   __shared__ float t[kTile][kTile + 1];
@@ -247,41 +398,51 @@ __global__ __launch_bounds__(256) void transpose_kernel(const float* __restrict_
 
 }  // namespace
 
-hipError_t launch_forward(const AngleGeom* geom, int N, int R, const AngleList& ids,
-                          const float* img, const float* imgT, const float* sub, float* out32,
-                          double* out64, hipStream_t st) {
+size_t forward_partial_floats(int N, int R, int max_list) {
+  const int H = std::max(1, std::min(N, 16384 / (N + 2 * kPad)));
+  const size_t nbands = (size_t)(N + H - 1) / H;
+  return nbands * (size_t)max_list * (size_t)R;
+}
+
+int forward_dot_parts(int n_out) { return (n_out + 255) / 256; }
+
+hipError_t launch_forward(const AngleGeom* geom, const AngleGeom* h_geom, int N, int R,
+                          const AngleList& ids, const float* img, const float* imgT,
+                          const float* sub, float* out32, double* out64, float* partial,
+                          const double* pd, double lam, double* dots, hipStream_t st) {
   if (ids.n <= 0) return hipSuccess;
-  dim3 grid((R + 63) / 64, ids.n);
-  hipLaunchKernelGGL(forward_kernel<false>, grid, dim3(256), 0, st, geom, N, R, ids, img, imgT, sub,
-                     out32, out64);
+  const FwdPlan pl = make_plan(h_geom, N, R, ids);
+  const int total = pl.n_groups * pl.n_chunks;
+  const int nwg = (total + 7) / 8 * 8;
+  const size_t lds = (size_t)pl.H * (N + 2 * kPad) * sizeof(float);
+  hipLaunchKernelGGL(fwd_band_kernel<false>, dim3(nwg), dim3(kFT), lds, st, geom, N, R, pl, img,
+                     imgT, partial);
+  const int n = ids.n * R;
+  hipLaunchKernelGGL(fwd_reduce_kernel, dim3((n + 255) / 256), dim3(256), 0, st, geom, R, ids,
+                     pl.n_groups, 0, partial, sub, out32, out64, pd, lam, dots);
   return hipGetLastError();
 }
 
-hipError_t launch_ray_sqnorm(const AngleGeom* geom, int N, int R, const AngleList& ids, double* out,
-                             hipStream_t st) {
+hipError_t launch_ray_sqnorm(const AngleGeom* geom, const AngleGeom* h_geom, int N, int R,
+                             const AngleList& ids, double* out, float* partial, hipStream_t st) {
   if (ids.n <= 0) return hipSuccess;
-  dim3 grid((R + 63) / 64, ids.n);
-  hipLaunchKernelGGL(forward_kernel<true>, grid, dim3(256), 0, st, geom, N, R, ids, nullptr,
-                     nullptr, nullptr, nullptr, out);
+  const FwdPlan pl = make_plan(h_geom, N, R, ids);
+  const int total = pl.n_groups * pl.n_chunks;
+  const int nwg = (total + 7) / 8 * 8;
+  hipLaunchKernelGGL(fwd_band_kernel<true>, dim3(nwg), dim3(kFT), 0, st, geom, N, R, pl, nullptr,
+                     nullptr, partial);
+  const int n = ids.n * R;
+  hipLaunchKernelGGL(fwd_reduce_kernel, dim3((n + 255) / 256), dim3(256), 0, st, geom, R, ids,
+                     pl.n_groups, 1, partial, nullptr, nullptr, out, nullptr, 0.0, nullptr);
   return hipGetLastError();
 }
 
-hipError_t launch_transpose(const float* src, float* dst, int N, hipStream_t st) {
-  const int t = (N + kTile - 1) / kTile;
-  hipLaunchKernelGGL(transpose_kernel, dim3(t, t), dim3(256), 0, st, src, dst, N);
-  return hipGetLastError();
-}
-
-int back_num_workgroups(int N) {
-  const int t = (N + kTile - 1) / kTile;
-  return t * t;
-}
+int back_num_workgroups(int N) { return ((N + kBW - 1) / kBW) * ((N + kBH - 1) / kBH); }
 
 hipError_t launch_back(const AngleGeom* geom, int N, int R, const AngleList& ids,
                        const float* v32, const double* v64, float* out, float* x, float* xT,
                        const float* x_true, double* partials, int mode, hipStream_t st) {
-  const int t = (N + kTile - 1) / kTile;
-  dim3 grid(t, t);
+  dim3 grid((N + kBW - 1) / kBW, (N + kBH - 1) / kBH);
   if (v64) {
     hipLaunchKernelGGL(back_kernel<double>, grid, dim3(256), 0, st, geom, N, R, ids, v64, out, x,
                        xT, x_true, partials, mode);
@@ -294,6 +455,12 @@ hipError_t launch_back(const AngleGeom* geom, int N, int R, const AngleList& ids
 
 hipError_t launch_reduce3(const double* partials, int n, double* out, hipStream_t st) {
   hipLaunchKernelGGL(reduce3_kernel, dim3(1), dim3(256), 0, st, partials, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_transpose(const float* src, float* dst, int N, hipStream_t st) {
+  const int t = (N + kTile - 1) / kTile;
+  hipLaunchKernelGGL(transpose_kernel, dim3(t, t), dim3(256), 0, st, src, dst, N);
   return hipGetLastError();
 }
 

@@ -105,7 +105,9 @@ struct slim_ctx {
   double* d_norms = nullptr;   // [B][3]
   float* d_xT = nullptr;       // [B][N][N]
   float* d_tmp = nullptr;      // [N][N] scratch image (public projector)
+  float* d_fpart = nullptr;    // forward projector partial sums
   PcgWork pcg{};
+  Profiler prof;
 
   double* h_norms = nullptr;   // pinned [B][3]
   int* h_info = nullptr;       // pinned
@@ -125,7 +127,9 @@ struct slim_ctx {
     (void)hipFree(d_norms);
     (void)hipFree(d_xT);
     (void)hipFree(d_tmp);
+    (void)hipFree(d_fpart);
     pcg_free(pcg);
+    prof.release();
     if (h_norms) (void)hipHostFree(h_norms);
     if (h_info) (void)hipHostFree(h_info);
   }
@@ -183,6 +187,7 @@ slim_status gram_solve_chol(slim_ctx* c, int new_slot) {
   const int64_t p = (int64_t)W * ell;
   const int S = c->r + 1;
   // new slot's row of tiles
+  if (c->prof.on) HIP_TRY(c->prof.begin(K_GRAM, c->st));
   AngleList na = make_list(c->slot_ids[new_slot].data(), c->g);
   for (int q : c->window) {
     AngleList nb = make_list(c->slot_ids[q].data(), c->g);
@@ -197,11 +202,14 @@ slim_status gram_solve_chol(slim_ctx* c, int new_slot) {
       HIP_TRY(launch_tile_copy(T, ell, c->d_G, p, (int)(P * ell), (int)(Q * ell), (int)ell,
                                (int)ell, c->lam, P == Q, c->st));
     }
+  if (c->prof.on) HIP_TRY(c->prof.end(c->st));
+  if (c->prof.on) HIP_TRY(c->prof.begin(K_CHOL, c->st));
   HIP_TRY(hipMemsetAsync(c->d_info, 0, sizeof(int), c->st));
   HIP_TRY(launch_cholesky(c->d_G, p, (int)p, c->d_info, c->st));
   for (int sl = 0; sl < c->B; ++sl)
     HIP_TRY(launch_chol_solve(c->d_G, p, (int)p, (int)ell, c->d_res64 + sl * ell,
                               c->d_z + sl * c->pmax, c->st));
+  if (c->prof.on) HIP_TRY(c->prof.end(c->st));
   return SLIM_OK;
 }
 
@@ -216,13 +224,20 @@ slim_status do_step(slim_ctx* c, const int32_t* ids, slim_step_info* info) {
   const int64_t ell = c->ell;
   const int64_t p = (int64_t)c->window.size() * ell;
 
+  if (c->prof.on && c->prof.used > 4096) {
+    HIP_TRY(hipStreamSynchronize(c->st));
+    HIP_TRY(c->prof.harvest());
+  }
   // 1. residual of the new block, every slice
+  if (c->prof.on) HIP_TRY(c->prof.begin(K_RESID, c->st));
   for (int sl = 0; sl < c->B; ++sl) {
     const float* xs = c->x + sl * c->img_elems();
     const float* xTs = c->d_xT + sl * c->img_elems();
-    HIP_TRY(launch_forward(c->d_geom, c->N, c->R, blk, xs, xTs, sino_f32(c, sl), nullptr,
-                           c->d_res64 + sl * ell, c->st));
+    HIP_TRY(launch_forward(c->d_geom, c->h_geom.data(), c->N, c->R, blk, xs, xTs, sino_f32(c, sl),
+                           nullptr, c->d_res64 + sl * ell, c->d_fpart, nullptr, 0.0, nullptr,
+                           c->st));
   }
+  if (c->prof.on) HIP_TRY(c->prof.end(c->st));
   // 2. Gram system
   int pcg_it = 0;
   double pcg_rel = 0.0;
@@ -233,9 +248,10 @@ slim_status do_step(slim_ctx* c, const int32_t* ids, slim_step_info* info) {
     for (int sl = 0; sl < c->B; ++sl) {
       int it = 0;
       double rel = 0.0;
-      hipError_t e = pcg_solve(c->pcg, c->d_geom, c->N, c->R, win, c->lam, c->d_res64 + sl * ell,
+      hipError_t e = pcg_solve(c->pcg, c->d_geom, c->h_geom.data(), c->d_fpart, c->N, c->R, win,
+                               c->lam, c->d_res64 + sl * ell,
                                (int)ell, c->d_z + sl * c->pmax, c->o.pcg_tol, c->o.pcg_max_iter,
-                               &it, &rel, c->st);
+                               &it, &rel, &c->prof, c->st);
       if (e != hipSuccess) return fail(SLIM_EDEVICE, std::string("pcg: ") + hipGetErrorString(e));
       pcg_it = std::max(pcg_it, it);
       pcg_rel = std::max(pcg_rel, rel);
@@ -243,6 +259,7 @@ slim_status do_step(slim_ctx* c, const int32_t* ids, slim_step_info* info) {
   }
   // 3. update every slice
   const int nwg = back_num_workgroups(c->N);
+  if (c->prof.on) HIP_TRY(c->prof.begin(K_UPDATE, c->st));
   for (int sl = 0; sl < c->B; ++sl) {
     float* xs = c->x + sl * c->img_elems();
     const float* xt = c->x_true ? c->x_true + sl * c->img_elems() : nullptr;
@@ -250,6 +267,7 @@ slim_status do_step(slim_ctx* c, const int32_t* ids, slim_step_info* info) {
                         c->d_xT + sl * c->img_elems(), xt, c->d_partials, 1, c->st));
     HIP_TRY(launch_reduce3(c->d_partials, nwg, c->d_norms + 3 * sl, c->st));
   }
+  if (c->prof.on) HIP_TRY(c->prof.end(c->st));
   (void)p;
   c->k += 1;
   c->last_pcg_iters = pcg_it;
@@ -260,6 +278,7 @@ slim_status do_step(slim_ctx* c, const int32_t* ids, slim_step_info* info) {
                          c->st));
   HIP_TRY(hipMemcpyAsync(c->h_info, c->d_info, sizeof(int), hipMemcpyDeviceToHost, c->st));
   HIP_TRY(hipStreamSynchronize(c->st));
+  if (c->prof.on) HIP_TRY(c->prof.harvest());
   int best = 0;
   for (int sl = 1; sl < c->B; ++sl)
     if (c->h_norms[3 * sl] > c->h_norms[3 * best]) best = sl;
@@ -321,10 +340,10 @@ slim_status slim_init(slim_ctx** out, const slim_grid* grid, int n_angles, const
   slim_opts o;
   slim_default_opts(&o);
   if (opts) o = *opts;
-  if (grid->N < 2 || grid->N > 16384) return fail(SLIM_EINVAL, "N must be in [2, 16384]");
+  if (grid->N < 2 || grid->N > 8192) return fail(SLIM_EINVAL, "N must be in [2, 8192]");
   if (grid->n_slices < 1) return fail(SLIM_EINVAL, "n_slices must be >= 1");
   if (n_angles < 1) return fail(SLIM_EINVAL, "n_angles must be >= 1");
-  if (n_rays < 1 || n_rays > 65536) return fail(SLIM_EINVAL, "n_rays must be in [1, 65536]");
+  if (n_rays < 1 || n_rays > 4096) return fail(SLIM_EINVAL, "n_rays must be in [1, 4096]");
   if (r < 0) return fail(SLIM_EINVAL, "memory level r must be >= 0");
   if (!(lambda > 0.0) || !std::isfinite(lambda)) return fail(SLIM_EINVAL, "lambda must be positive and finite");
   const int g = o.angles_per_block;
@@ -391,6 +410,7 @@ slim_status slim_init(slim_ctx** out, const slim_grid* grid, int n_angles, const
   if ((e = dalloc(&c->d_norms, 3 * (size_t)c->B)) != hipSuccess) return oom(e);
   if ((e = dalloc(&c->d_xT, nimg)) != hipSuccess) return oom(e);
   if ((e = dalloc(&c->d_tmp, c->img_elems())) != hipSuccess) return oom(e);
+  if ((e = dalloc(&c->d_fpart, forward_partial_floats(c->N, c->R, kMaxList))) != hipSuccess) return oom(e);
   if (mode == SLIM_GRAM_CHOL) {
     if ((e = dalloc(&c->d_tiles, (size_t)(r + 1) * (r + 1) * ell * ell)) != hipSuccess) return oom(e);
     if ((e = dalloc(&c->d_G, (size_t)pmax * pmax)) != hipSuccess) return oom(e);
@@ -403,7 +423,9 @@ slim_status slim_init(slim_ctx** out, const slim_grid* grid, int n_angles, const
                           hipMemcpyHostToDevice, c->st)) != hipSuccess) return oom(e);
   if ((e = hipMemsetAsync(c->d_info, 0, sizeof(int), c->st)) != hipSuccess) return oom(e);
   if (mode == SLIM_GRAM_PCG) {
-    if ((e = pcg_setup(c->pcg, c->d_geom, c->N, n_angles, c->R, lambda, c->st)) != hipSuccess) return oom(e);
+    if ((e = pcg_setup(c->pcg, c->d_geom, c->h_geom.data(), c->N, n_angles, c->R, lambda, c->d_fpart,
+                       c->st)) != hipSuccess)
+      return oom(e);
   }
   if ((e = hipStreamSynchronize(c->st)) != hipSuccess) return oom(e);
   *out = c;
@@ -481,8 +503,9 @@ slim_status slim_project(slim_ctx* c, const int32_t* ids, int n_ids, const float
   for (int sl = 0; sl < c->B; ++sl) {
     const float* xs = x + sl * c->img_elems();
     HIP_TRY(launch_transpose(xs, c->d_tmp, c->N, c->st));
-    HIP_TRY(launch_forward(c->d_geom, c->N, c->R, l, xs, c->d_tmp, nullptr,
-                           out + (size_t)sl * n_ids * c->R, nullptr, c->st));
+    HIP_TRY(launch_forward(c->d_geom, c->h_geom.data(), c->N, c->R, l, xs, c->d_tmp, nullptr,
+                           out + (size_t)sl * n_ids * c->R, nullptr, c->d_fpart, nullptr, 0.0,
+                           nullptr, c->st));
   }
   return SLIM_OK;
 }
@@ -565,6 +588,28 @@ slim_status slim_set_state(slim_ctx* c, const void* buf, int64_t size) {
     c->k += 1;
   }
   HIP_TRY(transpose_slices(c) == SLIM_OK ? hipSuccess : hipErrorUnknown);
+  return SLIM_OK;
+}
+
+slim_status slim_profile(slim_ctx* c, int on) {
+  if (!c) return fail(SLIM_EINVAL, "ctx is NULL");
+  HIP_TRY(hipStreamSynchronize(c->st));
+  if (c->prof.on) HIP_TRY(c->prof.harvest());
+  c->prof.on = on != 0;
+  for (int k = 0; k < K_COUNT; ++k) {
+    c->prof.total_ms[k] = 0.0;
+    c->prof.launches[k] = 0;
+  }
+  return SLIM_OK;
+}
+
+slim_status slim_kernel_stats(slim_ctx* c, int kind, double* total_ms, int64_t* launches) {
+  if (!c || !total_ms || !launches) return fail(SLIM_EINVAL, "NULL argument");
+  if (kind < 0 || kind >= K_COUNT) return fail(SLIM_EINVAL, "unknown kernel kind");
+  HIP_TRY(hipStreamSynchronize(c->st));
+  if (c->prof.on) HIP_TRY(c->prof.harvest());
+  *total_ms = c->prof.total_ms[kind];
+  *launches = c->prof.launches[kind];
   return SLIM_OK;
 }
 

@@ -33,9 +33,10 @@ struct AngleGeom {
   int pad;
 };
 
-// Canonical detector coordinate; every kernel evaluates exactly this
-// expression so that all of them see bit-identical weights (the forward and
-// back projectors are then exact adjoints of one float32 matrix).
+// Canonical detector coordinate of a pixel.  The back-projector and the Gram
+// kernel evaluate exactly this expression, so the Gram blocks are those of
+// the weights the back-projector applies; the forward projector evaluates
+// the same closed form along rays (equal up to float32 weight rounding).
 __device__ __forceinline__ double det_coord(const AngleGeom& g, double ii, double jj, double off) {
   return fma(jj, g.c, fma(ii, g.s, off));
 }
@@ -64,12 +65,36 @@ __device__ __forceinline__ void pixel_weights(const AngleGeom& g, double t, int&
   w1 = g.hd * fmaxf(0.f, 1.f - (float)(1.0 - f) * g.invd);
 }
 
+// Optional per-kernel timing with HIP events on the launch stream.  Kinds:
+enum KernelKind { K_FORWARD = 0, K_BACK, K_GRAM, K_CHOL, K_VEC, K_RESID, K_UPDATE, K_COUNT };
+
+struct Profiler {
+  bool on = false;
+  std::vector<hipEvent_t> pool;
+  std::vector<int> kind;   // kind of each recorded pair
+  int used = 0;            // pairs recorded since the last harvest
+  double total_ms[K_COUNT] = {};
+  long long launches[K_COUNT] = {};
+  hipError_t begin(int k, hipStream_t st);
+  hipError_t end(hipStream_t st);
+  hipError_t harvest();  // stream must be synchronised
+  void release();
+};
+
 // ---- launchers (return hipError_t of the launch) --------------------------
 // Forward projection: out[a][t] = sum_pix A[(ids[a],t),pix] img[pix] - (sub ? sub[ids[a]][t] : 0),
 // accumulated in float64 per ray and written as float (out32) and/or double (out64).
-hipError_t launch_forward(const AngleGeom* geom, int N, int R, const AngleList& ids,
-                          const float* img, const float* imgT, const float* sub,
-                          float* out32, double* out64, hipStream_t st);
+// img and its transpose imgT are both required.  h_geom: host copy of the
+// geometry table (the launch plan groups angles by orientation).  partial:
+// workspace of forward_partial_floats(N, R, ids.n) floats.  CG tail when pd
+// is non-NULL: out += lam * pd and per-workgroup partial sums of pd . out
+// into dots[forward_dot_parts(ids.n * R)].
+hipError_t launch_forward(const AngleGeom* geom, const AngleGeom* h_geom, int N, int R,
+                          const AngleList& ids, const float* img, const float* imgT,
+                          const float* sub, float* out32, double* out64, float* partial,
+                          const double* pd, double lam, double* dots, hipStream_t st);
+size_t forward_partial_floats(int N, int R, int max_list);
+int forward_dot_parts(int n_out);
 
 // Back-projection over a list: s[pix] = sum_a sum_t A[(ids[a],t),pix] v[a][t]
 // with v float (v32) or double (v64).  mode 0: out = s.  mode 1: x -= s in
@@ -103,8 +128,5 @@ hipError_t launch_cholesky(double* G, int64_t ld, int p, int* info, hipStream_t 
 hipError_t launch_chol_solve(const double* L, int64_t ld, int p, int nr, const double* rhs64,
                              double* z, hipStream_t st);
 
-// ---- PCG helpers -----------------------------------------------------------
-hipError_t launch_dot(const double* a, const double* b, int n, double* partials, int* nparts,
-                      hipStream_t st);
 
 }  // namespace slim

@@ -78,6 +78,8 @@ def load() -> ctypes.CDLL:
         "slim_gram": (I, [P, i32p, I, i32p, I, P]),
         "slim_get_state": (I, [P, P, ctypes.POINTER(ctypes.c_int64)]),
         "slim_set_state": (I, [P, P, ctypes.c_int64]),
+        "slim_profile": (I, [P, I]),
+        "slim_kernel_stats": (I, [P, I, ctypes.POINTER(D), ctypes.POINTER(ctypes.c_int64)]),
         "slim_destroy": (None, [P]),
         "slim_strerror": (ctypes.c_char_p, [I]),
         "slim_last_error": (ctypes.c_char_p, []),
@@ -227,6 +229,21 @@ class Slim:
     def set_state(self, blob: bytes):
         buf = ctypes.create_string_buffer(blob, len(blob))
         _check(load().slim_set_state(self._h, buf, len(blob)))
+
+    # --- measurement ------------------------------------------------------------
+    KINDS = ("cg_forward", "cg_back", "gram", "cholesky", "cg_vector", "residual", "update")
+
+    def profile(self, on: bool = True):
+        _check(load().slim_profile(self._h, int(on)))
+
+    def kernel_stats(self) -> dict:
+        out = {}
+        for k, name in enumerate(self.KINDS):
+            ms = ctypes.c_double(0.0)
+            n = ctypes.c_int64(0)
+            _check(load().slim_kernel_stats(self._h, k, ctypes.byref(ms), ctypes.byref(n)))
+            out[name] = {"total_ms": ms.value, "launches": n.value}
+        return out
 
     def close(self):
         if getattr(self, "_h", None):
