@@ -1,4 +1,4 @@
-// Preconditioned CG on the Gram system (lambda I + M M^T) z = [0; ...; 0; res]
+// CG on the Gram system (lambda I + M M^T) z = [0; ...; 0; res]
 // with matrix-free M (forward projector) and M^T (back-projector); used when
 // p = rows(M) is too large for the explicit Gram.  Vectors in p-space are
 // float64; the image-space intermediate M^T v is float32.  Scalars stay on
@@ -15,28 +15,25 @@ struct PcgWork {
   double* r = nullptr;      // residual           [pmax]
   double* pd = nullptr;     // search direction   [pmax]
   double* q = nullptr;      // G pd               [pmax]
-  double* y = nullptr;      // preconditioned r   [pmax]
-  double* dinv = nullptr;   // 1 / (||a_row||^2 + lambda), per (angle, ray) [n_angles][R]
-  double* parts = nullptr;  // per-workgroup partial dot products [2][nparts]
-  double* sc = nullptr;     // device scalars: rz, alpha, beta, rr, pq, bb
+  double* parts = nullptr;  // per-workgroup partial dots <pd,q>, <r,r> [2][nparts]
+  double* sc = nullptr;     // device scalars, two sets used alternately
+  int* ctl = nullptr;       // stop flag and iteration count
   float* u = nullptr;       // M^T pd             [N][N]
   float* uT = nullptr;      // its transpose      [N][N]
+  int* h_ctl = nullptr;     // pinned copies of ctl, one per chunk in flight
   double* h_sc = nullptr;   // pinned copy of sc
+  hipEvent_t ev[2] = {nullptr, nullptr};
 };
 
-hipError_t pcg_alloc(PcgWork& w, int N, int n_angles, int R, int64_t pmax);
+hipError_t pcg_alloc(PcgWork& w, int N, int64_t pmax);
 void pcg_free(PcgWork& w);
-// Per-ray squared norms of every angle -> dinv.
-hipError_t pcg_setup(PcgWork& w, const AngleGeom* geom, const AngleGeom* h_geom, int N,
-                     int n_angles, int R, double lam, float* partial, hipStream_t st);
 // Solve for one slice: rhs = [0; res] (res: last nres entries), z: [p] out.
+// h_geom: host geometry table; partial: forward-projector workspace.
 hipError_t pcg_solve(PcgWork& w, const AngleGeom* geom, const AngleGeom* h_geom, float* partial,
-                     int N, int R, const AngleList& win,
-                     double lam, const double* res, int nres, double* z, double tol, int max_iter,
-                     int* iters, double* relres, Profiler* prof, hipStream_t st);
+                     int N, int R, const AngleList& win, double lam, const double* res, int nres,
+                     double* z, double tol, int max_iter, int* iters, double* relres,
+                     Profiler* prof, hipStream_t st);
 
 hipError_t launch_transpose(const float* src, float* dst, int N, hipStream_t st);
-hipError_t launch_ray_sqnorm(const AngleGeom* geom, const AngleGeom* h_geom, int N, int R,
-                             const AngleList& ids, double* out, float* partial, hipStream_t st);
 
 }  // namespace slim

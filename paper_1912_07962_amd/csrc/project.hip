@@ -30,8 +30,9 @@ namespace {
 
 // ---------------------------------------------------------------- forward
 constexpr int kFT = 512;      // threads per forward workgroup
-constexpr int kFItems = 8;    // rays per lane
-constexpr int kPad = 2;       // zero columns on each side of a band row
+constexpr int kFItems = 4;    // rays per lane
+constexpr int kPad = 4;       // zero columns on each side of a band row (keeps rows 16B-aligned)
+// float4 per lane per band: H * N / 4 <= 16384 / 4 = 8 * kFT (eight prefetch registers)
 
 struct FwdPlan {
   int n;          // entries (= output rows)
@@ -40,6 +41,7 @@ struct FwdPlan {
   int n_chunks;   // row-stepping chunks first
   int H, G;       // rows per band, bands per group
   int n_groups;
+  int items;      // rays per lane (template argument of the band kernel)
   short id[kMaxList];
   short slot[kMaxList];
 };
@@ -57,12 +59,14 @@ __device__ __forceinline__ void chunk_range(const FwdPlan& pl, int c, int& e0, i
   }
 }
 
-template <bool SQ>
-__global__ __launch_bounds__(kFT) void fwd_band_kernel(const AngleGeom* __restrict__ geom, int N,
-                                                       int R, FwdPlan pl,
-                                                       const float* __restrict__ img,
-                                                       const float* __restrict__ imgT,
-                                                       float* __restrict__ partial) {
+template <int IT>
+__global__ __launch_bounds__(kFT, 2) void fwd_band_kernel(const AngleGeom* __restrict__ geom, int N,
+                                                          int R, FwdPlan pl,
+                                                          const float* __restrict__ img,
+                                                          const float* __restrict__ imgT,
+                                                          float* __restrict__ partial,
+                                                          const int* __restrict__ stop) {
+  if (stop && stop[kCtlDone]) return;
   extern __shared__ float band[];
   const int W = N + 2 * kPad;
   // XCD-aware numbering: consecutive positions live on one XCD
@@ -79,17 +83,24 @@ __global__ __launch_bounds__(kFT) void fwd_band_kernel(const AngleGeom* __restri
   const float* src = colm ? imgT : img;
   const double half = 0.5 * (N - 1);
   const double off = 0.5 * (R - 1);
+  const int kg = grp * pl.G * pl.H;
 
-  double pos0[kFItems], step[kFItems], acc[kFItems];
-  int klo[kFItems], khi[kFItems];
+  // Ray position along the minor axis in 32.32 fixed point: P = pos * 2^32
+  // at row k is P0 + k * S (pos: 0-based pixel index shifted by kPad).
+  // Rounding P0 and S costs at most (k+1) * 2^-33 < 1.2e-7 pixel at k = 1023.
+  // Each wavefront walks, per ray slot, the union of its 64 rays' row ranges
+  // (a wave-uniform loop); a lane outside its own ray's range reads the zero
+  // pads (its index is clamped into [0, W-2]) and adds nothing.
+  int64_t P0[IT], S[IT];
+  double acc[IT];
+  int wlo[IT], whi[IT];
 #pragma unroll
-  for (int q = 0; q < kFItems; ++q) {
+  for (int q = 0; q < IT; ++q) {
     const int item = threadIdx.x + q * kFT;
     acc[q] = 0.0;
-    klo[q] = 0;
-    khi[q] = -1;
-    pos0[q] = 0.0;
-    step[q] = 0.0;
+    P0[q] = 0;  // index 0: pad column
+    S[q] = 0;
+    int klo = N, khi = -1;
     if (item < nitems) {
       const int e = e0 + item / R;
       const int t = item % R;
@@ -97,11 +108,9 @@ __global__ __launch_bounds__(kFT) void fwd_band_kernel(const AngleGeom* __restri
       const double cm = colm ? g.c : g.s;   // coefficient of the major coordinate
       const double cn = colm ? g.s : g.c;   // of the minor one, |cn| = d
       const double inv = 1.0 / cn;
-      // crossing position (0-based minor pixel index, shifted by kPad) at major index k:
-      // pos(k) = p0 + k * n1
-      const double n1 = -cm * inv;
+      const double n1 = -cm * inv;          // pos(k) = p0 + k * n1
       const double p0 = ((double)t - off) * inv + half + kPad - half * n1;
-      // rows with pos - kPad in [-1.5, N + 0.5]: every contributing row, all in the pad
+      // rows with pos - kPad in [-1.5, N + 0.5] hold every contributing row
       const double lo_p = kPad - 1.5, hi_p = N + kPad + 0.5;
       double lo = 0.0, hi = N - 1;
       if (n1 != 0.0) {
@@ -112,49 +121,97 @@ __global__ __launch_bounds__(kFT) void fwd_band_kernel(const AngleGeom* __restri
         lo = 1.0;
         hi = 0.0;
       }
-      klo[q] = (int)lo;
-      khi[q] = (int)hi;
-      pos0[q] = p0;
-      step[q] = n1;
+      if (lo <= hi) {
+        klo = (int)lo;
+        khi = (int)hi;
+      }
+      P0[q] = __double2ll_rn(p0 * 4294967296.0);
+      S[q] = __double2ll_rn(n1 * 4294967296.0);
     }
+    for (int o = 32; o > 0; o >>= 1) {
+      klo = min(klo, __shfl_xor(klo, o, 64));
+      khi = max(khi, __shfl_xor(khi, o, 64));
+    }
+    wlo[q] = __builtin_amdgcn_readfirstlane(klo);
+    whi[q] = __builtin_amdgcn_readfirstlane(khi);
   }
 
-  const int kg = grp * pl.G * pl.H;
+  {  // the zero pads are written once; band loads never touch them
+    for (int e = threadIdx.x; e < pl.H * 2 * kPad; e += kFT) {
+      const int r = e / (2 * kPad), c = e % (2 * kPad);
+      band[r * W + (c < kPad ? c : N + c)] = 0.f;
+    }
+  }
+  // Bands are software-pipelined: the next band's rows are fetched into
+  // eight named registers (16-byte loads) while the current band is used.
+  const bool vec = (N & 3) == 0;
+  const int n4 = N >> 2;
+  float4 pf0, pf1, pf2, pf3, pf4, pf5, pf6, pf7;
+#define SLIM_PF_LOAD(kb_)                                                       \
+  do {                                                                          \
+    const float4* s4 = reinterpret_cast<const float4*>(src + (size_t)(kb_) * N); \
+    const int lim = min(pl.H, N - (kb_)) * n4 - 1;                               \
+    const int t0 = (int)threadIdx.x;                                            \
+    pf0 = s4[min(t0 + 0 * kFT, lim)];                                           \
+    pf1 = s4[min(t0 + 1 * kFT, lim)];                                           \
+    pf2 = s4[min(t0 + 2 * kFT, lim)];                                           \
+    pf3 = s4[min(t0 + 3 * kFT, lim)];                                           \
+    pf4 = s4[min(t0 + 4 * kFT, lim)];                                           \
+    pf5 = s4[min(t0 + 5 * kFT, lim)];                                           \
+    pf6 = s4[min(t0 + 6 * kFT, lim)];                                           \
+    pf7 = s4[min(t0 + 7 * kFT, lim)];                                           \
+  } while (0)
+#define SLIM_PF_STORE1(u, v)                                                    \
+  do {                                                                          \
+    const int e = (int)threadIdx.x + (u) * kFT;                                 \
+    const int r = e / n4, c4 = e - r * n4;                                      \
+    if (e < lim) *reinterpret_cast<float4*>(band + r * W + kPad + 4 * c4) = (v); \
+  } while (0)
+  if (vec && kg < N) SLIM_PF_LOAD(kg);
   for (int bb = 0; bb < pl.G; ++bb) {
     const int kb = kg + bb * pl.H;
     if (kb >= N) break;
     const int hb = min(pl.H, N - kb);
     __syncthreads();
-    if (!SQ) {
-      for (int e = threadIdx.x; e < hb * W; e += kFT) {
-        const int r = e / W, c = e % W - kPad;
-        band[e] = (c >= 0 && c < N) ? src[(size_t)(kb + r) * N + c] : 0.f;
-      }
+    if (vec) {
+      const int lim = hb * n4;
+      SLIM_PF_STORE1(0, pf0);
+      SLIM_PF_STORE1(1, pf1);
+      SLIM_PF_STORE1(2, pf2);
+      SLIM_PF_STORE1(3, pf3);
+      SLIM_PF_STORE1(4, pf4);
+      SLIM_PF_STORE1(5, pf5);
+      SLIM_PF_STORE1(6, pf6);
+      SLIM_PF_STORE1(7, pf7);
+    } else {
+      for (int r = 0; r < hb; ++r)
+        for (int c = threadIdx.x; c < N; c += kFT) band[r * W + kPad + c] = src[(size_t)(kb + r) * N + c];
     }
     __syncthreads();
+    const int kbn = kb + pl.H;
+    if (vec && bb + 1 < pl.G && kbn < N) SLIM_PF_LOAD(kbn);
 #pragma unroll
-    for (int q = 0; q < kFItems; ++q) {
-      const int k0 = max(klo[q], kb), k1 = min(khi[q], kb + hb - 1);
+    for (int q = 0; q < IT; ++q) {
+      const int k0 = max(wlo[q], kb), k1 = min(whi[q], kb + hb - 1);
+      if (k0 > k1) continue;  // wave-uniform
+      int64_t P = P0[q] + (int64_t)k0 * S[q];
+      const float* row = band + (k0 - kb) * W;
       float a32 = 0.f;
       for (int k = k0; k <= k1; ++k) {
-        const double p = fma((double)k, step[q], pos0[q]);
-        const int qi = (int)p;  // p >= 0.5 - eps: truncation is floor
-        const float phi = (float)(p - (double)qi);
-        if (SQ) {
-          const float w0 = (qi - kPad >= 0 && qi - kPad < N) ? 1.f - phi : 0.f;
-          const float w1 = (qi + 1 - kPad >= 0 && qi + 1 - kPad < N) ? phi : 0.f;
-          a32 = fmaf(w0, w0, fmaf(w1, w1, a32));
-        } else {
-          const float* rp = band + (k - kb) * W + qi;
-          const float v0 = rp[0], v1 = rp[1];
-          a32 += fmaf(phi, v1 - v0, v0);
-        }
+        const int qi = min(max((int)(P >> 32), 0), W - 2);
+        const float phi = (float)(uint32_t)P * 2.3283064365386963e-10f;
+        const float v0 = row[qi], v1 = row[qi + 1];
+        a32 += fmaf(phi, v1 - v0, v0);
+        P += S[q];
+        row += W;
       }
       acc[q] += (double)a32;
     }
   }
+#undef SLIM_PF_LOAD
+#undef SLIM_PF_STORE1
 #pragma unroll
-  for (int q = 0; q < kFItems; ++q) {
+  for (int q = 0; q < IT; ++q) {
     const int item = threadIdx.x + q * kFT;
     if (item < nitems) {
       const int e = e0 + item / R;
@@ -167,13 +224,15 @@ __global__ __launch_bounds__(kFT) void fwd_band_kernel(const AngleGeom* __restri
 // out[s][t] = (h/d) sum_groups partial - sub; optional CG tail q = out + lam*pd
 // with per-workgroup partial dot <pd, q>.
 __global__ __launch_bounds__(256) void fwd_reduce_kernel(const AngleGeom* __restrict__ geom, int R,
-                                                         AngleList ids, int n_groups, int SQ,
+                                                         AngleList ids, int n_groups,
                                                          const float* __restrict__ partial,
                                                          const float* __restrict__ sub,
                                                          float* __restrict__ out32,
                                                          double* __restrict__ out64,
                                                          const double* __restrict__ pd, double lam,
-                                                         double* __restrict__ dots) {
+                                                         double* __restrict__ dots,
+                                                         const int* __restrict__ stop) {
+  if (stop && stop[kCtlDone]) return;
   __shared__ double sh[4];
   const int o = blockIdx.x * 256 + threadIdx.x;
   const int n = ids.n * R;
@@ -181,10 +240,20 @@ __global__ __launch_bounds__(256) void fwd_reduce_kernel(const AngleGeom* __rest
   if (o < n) {
     const int s = o / R, t = o % R;
     const int ang = ids.id[s];
+    const float* pp = partial + (size_t)s * R + t;
+    const size_t gs = (size_t)ids.n * R;
     double v = 0.0;
-    for (int g = 0; g < n_groups; ++g) v += (double)partial[((size_t)g * ids.n + s) * R + t];
+    int g = 0;
+    for (; g + 4 <= n_groups; g += 4) {
+      const float a = pp[g * gs], b = pp[(g + 1) * gs], c = pp[(g + 2) * gs], e = pp[(g + 3) * gs];
+      v += (double)a;
+      v += (double)b;
+      v += (double)c;
+      v += (double)e;
+    }
+    for (; g < n_groups; ++g) v += (double)pp[g * gs];
     const double hd = (double)geom[ang].hd;
-    v *= SQ ? hd * hd : hd;
+    v *= hd;
     if (sub) v -= (double)sub[(size_t)ang * R + t];
     if (pd) {
       v = fma(lam, pd[o], v);
@@ -201,7 +270,10 @@ __global__ __launch_bounds__(256) void fwd_reduce_kernel(const AngleGeom* __rest
   }
 }
 
-FwdPlan make_plan(const AngleGeom* h_geom, int N, int R, const AngleList& ids) {
+// Launch plan: angles grouped by orientation into chunks, image bands into
+// groups, with n_chunks * n_groups <= 2 * (number of CUs) so that a launch is
+// a single round of resident workgroups (two per CU, bounded by LDS).
+FwdPlan make_plan(const AngleGeom* h_geom, int N, int R, const AngleList& ids, int n_cu) {
   FwdPlan pl;
   pl.n = ids.n;
   int k = 0;
@@ -215,11 +287,12 @@ FwdPlan make_plan(const AngleGeom* h_geom, int N, int R, const AngleList& ids) {
   pl.n_row = 0;
   for (int s = 0; s < ids.n; ++s) pl.n_row += h_geom[ids.id[s]].colmajor ? 0 : 1;
   pl.ch = std::max(1, std::min(kFItems * kFT / R, ids.n));
+  pl.items = (pl.ch * R + kFT - 1) / kFT;
   pl.n_chunks = (pl.n_row + pl.ch - 1) / pl.ch + (ids.n - pl.n_row + pl.ch - 1) / pl.ch;
   pl.H = std::max(1, std::min(N, 16384 / (N + 2 * kPad)));
   const int nbands = (N + pl.H - 1) / pl.H;
-  int want = (1024 + pl.n_chunks - 1) / pl.n_chunks;
-  want = std::max(1, std::min(want, nbands));
+  const int slots = 2 * std::max(1, n_cu);
+  int want = std::max(1, std::min(slots / pl.n_chunks, nbands));
   pl.G = (nbands + want - 1) / want;
   pl.n_groups = (nbands + pl.G - 1) / pl.G;
   return pl;
@@ -242,7 +315,9 @@ __global__ __launch_bounds__(256) void back_kernel(const AngleGeom* __restrict__
                                                    float* __restrict__ out, float* __restrict__ x,
                                                    float* __restrict__ xT,
                                                    const float* __restrict__ x_true,
-                                                   double* __restrict__ partials, int mode) {
+                                                   double* __restrict__ partials, int mode,
+                                                   const int* __restrict__ stop) {
+  if (stop && stop[kCtlDone]) return;
   __shared__ float seg[kBAng * kSeg];
   __shared__ int tmin[kBAng];
   __shared__ float tile[kBH][kBW + 1];
@@ -253,7 +328,10 @@ __global__ __launch_bounds__(256) void back_kernel(const AngleGeom* __restrict__
   const int i = i0 + ty;
   const int jb = j0 + kBPX * tx;
   const double half = 0.5 * (N - 1);
-  const double off = 0.5 * (R - 1);
+  // detector coordinates are shifted by kTOff (>= every |jj c + ii s|), so
+  // they are positive and float->int truncation is floor
+  const int kTOff = 2 * N + 8;
+  const double off = 0.5 * (R - 1) + kTOff;
   const double ii = (double)i - half;
   // nominal tile corners (pixel centres) bound every pixel the lanes evaluate
   const double ci0 = (double)i0 - half, ci1 = (double)(i0 + kBH - 1) - half;
@@ -271,7 +349,7 @@ __global__ __launch_bounds__(256) void back_kernel(const AngleGeom* __restrict__
     __syncthreads();
     for (int e = threadIdx.x; e < na * kSeg; e += 256) {
       const int a = e / kSeg, u = e % kSeg;
-      const int t = tmin[a] + u;
+      const int t = tmin[a] + u - kTOff;
       const AngleGeom& g = geom[ids.id[a0 + a]];
       seg[e] = (t >= 0 && t < R) ? g.hd * (float)v[(size_t)(a0 + a) * R + t] : 0.f;
     }
@@ -281,14 +359,14 @@ __global__ __launch_bounds__(256) void back_kernel(const AngleGeom* __restrict__
         const AngleGeom g = geom[ids.id[a0 + a]];
         const double Ti = fma(ii, g.s, off);
         const float* sa = seg + a * kSeg - tmin[a];
+        const float invd = g.invd, c1 = 1.f - g.invd;
 #pragma unroll
         for (int q = 0; q < kBPX; ++q) {
           const double t = fma((double)(jb + q) - half, g.c, Ti);
-          const double fl = floor(t);
-          const double f = t - fl;
-          const int t0 = (int)fl;
-          const float w0 = fmaxf(0.f, 1.f - (float)f * g.invd);
-          const float w1 = fmaxf(0.f, 1.f - (float)(1.0 - f) * g.invd);
+          const int t0 = (int)t;                       // t > 0: floor
+          const float f = (float)(t - (double)t0);     // distance to ray t0
+          const float w0 = fmaxf(0.f, fmaf(-f, invd, 1.f));   // 1 - f/d
+          const float w1 = fmaxf(0.f, fmaf(f, invd, c1));     // 1 - (1-f)/d
           s[q] = fmaf(w0, sa[t0], fmaf(w1, sa[t0 + 1], s[q]));
         }
       }
@@ -406,34 +484,51 @@ size_t forward_partial_floats(int N, int R, int max_list) {
 
 int forward_dot_parts(int n_out) { return (n_out + 255) / 256; }
 
+static int g_num_cu = 0;
+
+static int num_cu() {
+  if (g_num_cu == 0) {
+    int dev = 0, n = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0)
+      g_num_cu = n;
+    else
+      g_num_cu = 256;
+  }
+  return g_num_cu;
+}
+
 hipError_t launch_forward(const AngleGeom* geom, const AngleGeom* h_geom, int N, int R,
                           const AngleList& ids, const float* img, const float* imgT,
                           const float* sub, float* out32, double* out64, float* partial,
-                          const double* pd, double lam, double* dots, hipStream_t st) {
+                          const double* pd, double lam, double* dots, const int* stop,
+                          hipStream_t st) {
   if (ids.n <= 0) return hipSuccess;
-  const FwdPlan pl = make_plan(h_geom, N, R, ids);
+  const FwdPlan pl = make_plan(h_geom, N, R, ids, num_cu());
   const int total = pl.n_groups * pl.n_chunks;
   const int nwg = (total + 7) / 8 * 8;
   const size_t lds = (size_t)pl.H * (N + 2 * kPad) * sizeof(float);
-  hipLaunchKernelGGL(fwd_band_kernel<false>, dim3(nwg), dim3(kFT), lds, st, geom, N, R, pl, img,
-                     imgT, partial);
+  switch (pl.items) {
+    case 1:
+      hipLaunchKernelGGL(fwd_band_kernel<1>, dim3(nwg), dim3(kFT), lds, st, geom, N, R, pl, img,
+                         imgT, partial, stop);
+      break;
+    case 2:
+      hipLaunchKernelGGL(fwd_band_kernel<2>, dim3(nwg), dim3(kFT), lds, st, geom, N, R, pl, img,
+                         imgT, partial, stop);
+      break;
+    case 3:
+      hipLaunchKernelGGL(fwd_band_kernel<3>, dim3(nwg), dim3(kFT), lds, st, geom, N, R, pl, img,
+                         imgT, partial, stop);
+      break;
+    default:
+      hipLaunchKernelGGL(fwd_band_kernel<4>, dim3(nwg), dim3(kFT), lds, st, geom, N, R, pl, img,
+                         imgT, partial, stop);
+      break;
+  }
   const int n = ids.n * R;
   hipLaunchKernelGGL(fwd_reduce_kernel, dim3((n + 255) / 256), dim3(256), 0, st, geom, R, ids,
-                     pl.n_groups, 0, partial, sub, out32, out64, pd, lam, dots);
-  return hipGetLastError();
-}
-
-hipError_t launch_ray_sqnorm(const AngleGeom* geom, const AngleGeom* h_geom, int N, int R,
-                             const AngleList& ids, double* out, float* partial, hipStream_t st) {
-  if (ids.n <= 0) return hipSuccess;
-  const FwdPlan pl = make_plan(h_geom, N, R, ids);
-  const int total = pl.n_groups * pl.n_chunks;
-  const int nwg = (total + 7) / 8 * 8;
-  hipLaunchKernelGGL(fwd_band_kernel<true>, dim3(nwg), dim3(kFT), 0, st, geom, N, R, pl, nullptr,
-                     nullptr, partial);
-  const int n = ids.n * R;
-  hipLaunchKernelGGL(fwd_reduce_kernel, dim3((n + 255) / 256), dim3(256), 0, st, geom, R, ids,
-                     pl.n_groups, 1, partial, nullptr, nullptr, out, nullptr, 0.0, nullptr);
+                     pl.n_groups, partial, sub, out32, out64, pd, lam, dots, stop);
   return hipGetLastError();
 }
 
@@ -441,14 +536,15 @@ int back_num_workgroups(int N) { return ((N + kBW - 1) / kBW) * ((N + kBH - 1) /
 
 hipError_t launch_back(const AngleGeom* geom, int N, int R, const AngleList& ids,
                        const float* v32, const double* v64, float* out, float* x, float* xT,
-                       const float* x_true, double* partials, int mode, hipStream_t st) {
+                       const float* x_true, double* partials, int mode, const int* stop,
+                       hipStream_t st) {
   dim3 grid((N + kBW - 1) / kBW, (N + kBH - 1) / kBH);
   if (v64) {
     hipLaunchKernelGGL(back_kernel<double>, grid, dim3(256), 0, st, geom, N, R, ids, v64, out, x,
-                       xT, x_true, partials, mode);
+                       xT, x_true, partials, mode, stop);
   } else {
     hipLaunchKernelGGL(back_kernel<float>, grid, dim3(256), 0, st, geom, N, R, ids, v32, out, x,
-                       xT, x_true, partials, mode);
+                       xT, x_true, partials, mode, stop);
   }
   return hipGetLastError();
 }

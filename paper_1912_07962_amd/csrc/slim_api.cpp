@@ -235,7 +235,7 @@ slim_status do_step(slim_ctx* c, const int32_t* ids, slim_step_info* info) {
     const float* xTs = c->d_xT + sl * c->img_elems();
     HIP_TRY(launch_forward(c->d_geom, c->h_geom.data(), c->N, c->R, blk, xs, xTs, sino_f32(c, sl),
                            nullptr, c->d_res64 + sl * ell, c->d_fpart, nullptr, 0.0, nullptr,
-                           c->st));
+                           nullptr, c->st));
   }
   if (c->prof.on) HIP_TRY(c->prof.end(c->st));
   // 2. Gram system
@@ -264,7 +264,7 @@ slim_status do_step(slim_ctx* c, const int32_t* ids, slim_step_info* info) {
     float* xs = c->x + sl * c->img_elems();
     const float* xt = c->x_true ? c->x_true + sl * c->img_elems() : nullptr;
     HIP_TRY(launch_back(c->d_geom, c->N, c->R, win, nullptr, c->d_z + sl * c->pmax, nullptr, xs,
-                        c->d_xT + sl * c->img_elems(), xt, c->d_partials, 1, c->st));
+                        c->d_xT + sl * c->img_elems(), xt, c->d_partials, 1, nullptr, c->st));
     HIP_TRY(launch_reduce3(c->d_partials, nwg, c->d_norms + 3 * sl, c->st));
   }
   if (c->prof.on) HIP_TRY(c->prof.end(c->st));
@@ -415,18 +415,13 @@ slim_status slim_init(slim_ctx** out, const slim_grid* grid, int n_angles, const
     if ((e = dalloc(&c->d_tiles, (size_t)(r + 1) * (r + 1) * ell * ell)) != hipSuccess) return oom(e);
     if ((e = dalloc(&c->d_G, (size_t)pmax * pmax)) != hipSuccess) return oom(e);
   } else {
-    if ((e = pcg_alloc(c->pcg, c->N, n_angles, c->R, pmax)) != hipSuccess) return oom(e);
+    if ((e = pcg_alloc(c->pcg, c->N, pmax)) != hipSuccess) return oom(e);
   }
   if ((e = hipHostMalloc((void**)&c->h_norms, sizeof(double) * 3 * c->B, hipHostMallocDefault)) != hipSuccess) return oom(e);
   if ((e = hipHostMalloc((void**)&c->h_info, sizeof(int), hipHostMallocDefault)) != hipSuccess) return oom(e);
   if ((e = hipMemcpyAsync(c->d_geom, c->h_geom.data(), sizeof(AngleGeom) * n_angles,
                           hipMemcpyHostToDevice, c->st)) != hipSuccess) return oom(e);
   if ((e = hipMemsetAsync(c->d_info, 0, sizeof(int), c->st)) != hipSuccess) return oom(e);
-  if (mode == SLIM_GRAM_PCG) {
-    if ((e = pcg_setup(c->pcg, c->d_geom, c->h_geom.data(), c->N, n_angles, c->R, lambda, c->d_fpart,
-                       c->st)) != hipSuccess)
-      return oom(e);
-  }
   if ((e = hipStreamSynchronize(c->st)) != hipSuccess) return oom(e);
   *out = c;
   return SLIM_OK;
@@ -505,7 +500,7 @@ slim_status slim_project(slim_ctx* c, const int32_t* ids, int n_ids, const float
     HIP_TRY(launch_transpose(xs, c->d_tmp, c->N, c->st));
     HIP_TRY(launch_forward(c->d_geom, c->h_geom.data(), c->N, c->R, l, xs, c->d_tmp, nullptr,
                            out + (size_t)sl * n_ids * c->R, nullptr, c->d_fpart, nullptr, 0.0,
-                           nullptr, c->st));
+                           nullptr, nullptr, c->st));
   }
   return SLIM_OK;
 }
@@ -518,7 +513,8 @@ slim_status slim_backproject(slim_ctx* c, const int32_t* ids, int n_ids, const f
   const AngleList l = make_list(ids, n_ids);
   for (int sl = 0; sl < c->B; ++sl)
     HIP_TRY(launch_back(c->d_geom, c->N, c->R, l, v + (size_t)sl * n_ids * c->R, nullptr,
-                        out + sl * c->img_elems(), nullptr, nullptr, nullptr, nullptr, 0, c->st));
+                        out + sl * c->img_elems(), nullptr, nullptr, nullptr, nullptr, 0, nullptr,
+                        c->st));
   return SLIM_OK;
 }
 

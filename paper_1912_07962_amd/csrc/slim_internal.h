@@ -65,6 +65,10 @@ __device__ __forceinline__ void pixel_weights(const AngleGeom& g, double t, int&
   w1 = g.hd * fmaxf(0.f, 1.f - (float)(1.0 - f) * g.invd);
 }
 
+// Device-side CG control word: stop flag and iteration count.  Kernels that
+// take a `stop` pointer return at entry when stop[kCtlDone] is set.
+constexpr int kCtlDone = 0, kCtlIters = 1, kCtlCount = 2;
+
 // Optional per-kernel timing with HIP events on the launch stream.  Kinds:
 enum KernelKind { K_FORWARD = 0, K_BACK, K_GRAM, K_CHOL, K_VEC, K_RESID, K_UPDATE, K_COUNT };
 
@@ -92,7 +96,8 @@ struct Profiler {
 hipError_t launch_forward(const AngleGeom* geom, const AngleGeom* h_geom, int N, int R,
                           const AngleList& ids, const float* img, const float* imgT,
                           const float* sub, float* out32, double* out64, float* partial,
-                          const double* pd, double lam, double* dots, hipStream_t st);
+                          const double* pd, double lam, double* dots, const int* stop,
+                          hipStream_t st);
 size_t forward_partial_floats(int N, int R, int max_list);
 int forward_dot_parts(int n_out);
 
@@ -102,7 +107,8 @@ int forward_dot_parts(int n_out);
 // (||s||^2, ||x_new||^2, ||x_new - x_true||^2) into partials[3*nwg].
 hipError_t launch_back(const AngleGeom* geom, int N, int R, const AngleList& ids,
                        const float* v32, const double* v64, float* out, float* x, float* xT,
-                       const float* x_true, double* partials, int mode, hipStream_t st);
+                       const float* x_true, double* partials, int mode, const int* stop,
+                       hipStream_t st);
 int back_num_workgroups(int N);
 
 // Sum 3-vectors of partials in a fixed order into out[3] (one workgroup).
