@@ -145,6 +145,9 @@ class SlimLS:
     window: list = field(default_factory=list)     # block ids, oldest first
     k: int = 0
     history: list = field(default_factory=list)
+    # x_store(x): the image as stored for the residual A_k x (identity; the
+    # bf16-storage variant passes a rounding to bfloat16)
+    x_store: callable = None
 
     def step(self, beta: int) -> StepRecord:
         self.window.append(int(beta))
@@ -152,7 +155,8 @@ class SlimLS:
             self.window.pop(0)
         mats = [self.block_rows(b) for b in self.window]
         Ak = mats[-1]
-        res = np.asarray(Ak @ self.x).reshape(-1) - self.block_data(beta)
+        xs = self.x if self.x_store is None else self.x_store(self.x)
+        res = np.asarray(Ak @ xs).reshape(-1) - self.block_data(beta)
         info = {"mode": self.form, "iters": 0}
         if self.form == "dual":
             s, _, info = step_dual(mats, res, self.lam, self.chol_max_p, self.cg_tol)
@@ -171,6 +175,18 @@ class SlimLS:
         return rec
 
 
+def round_bf16(a: np.ndarray) -> np.ndarray:
+    """Round to bfloat16 (nearest, ties to even) and return as float64.
+
+    bfloat16 keeps the upper 16 bits of an IEEE float32: the float32 value is
+    rounded to 8 significand bits by adding 0x7FFF plus the lowest kept bit
+    and truncating."""
+    f = np.asarray(a, np.float64).astype(np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    u = ((u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000).astype(np.uint32)
+    return u.view(np.float32).astype(np.float64)
+
+
 def stop_index(history, r: int, tol: float):
     """First step k >= r+1 with ||s_k|| / ||x_k|| <= tol (1-based), or None."""
     for rec in history:
@@ -184,14 +200,16 @@ class Tomo:
 
     def __init__(self, projector, b: np.ndarray, g: int, r: int, lam: float,
                  x0: np.ndarray | None = None, x_true: np.ndarray | None = None,
-                 chol_max_p: int = 8000, cg_tol: float = 1e-12, form: str = "dual"):
+                 chol_max_p: int = 8000, cg_tol: float = 1e-12, form: str = "dual",
+                 x_store=None):
         self.P = projector
         self.g = g
         self.n_blocks = projector.n_angles // g
         self.b = np.asarray(b, np.float64).reshape(projector.n_angles, projector.R)
         x0 = np.zeros(projector.n) if x0 is None else np.asarray(x0, np.float64).reshape(-1)
         xt = None if x_true is None else np.asarray(x_true, np.float64).reshape(-1)
-        self.it = SlimLS(self.rows, self.data, r, lam, x0.copy(), xt, form, chol_max_p, cg_tol)
+        self.it = SlimLS(self.rows, self.data, r, lam, x0.copy(), xt, form, chol_max_p, cg_tol,
+                         x_store=x_store)
 
     def angles_of(self, beta: int):
         return list(range(beta * self.g, beta * self.g + self.g))

@@ -34,6 +34,8 @@ hipError_t pcg_solve(PcgWork& w, const AngleGeom* geom, const AngleGeom* h_geom,
                      double* z, double tol, int max_iter, int* iters, double* relres,
                      Profiler* prof, hipStream_t st);
 
-hipError_t launch_transpose(const float* src, float* dst, int N, hipStream_t st);
+// dst = src^T (if dst), bf16 copies of src (bs) and src^T (bsT) if given.
+hipError_t launch_transpose(const float* src, float* dst, int N, uint16_t* bs, uint16_t* bsT,
+                            hipStream_t st);
 
 }  // namespace slim

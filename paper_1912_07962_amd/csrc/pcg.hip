@@ -210,11 +210,11 @@ hipError_t pcg_solve(PcgWork& w, const AngleGeom* geom, const AngleGeom* h_geom,
         double* sc_nxt = w.sc + ((enq + 1) & 1) * S_COUNT;
         if (prof->on && (e = prof->begin(K_BACK, st)) != hipSuccess) return e;
         if ((e = launch_back(geom, N, R, win, nullptr, w.pd, w.u, nullptr, w.uT, nullptr, nullptr,
-                             0, w.ctl, st)) != hipSuccess)
+                             0, w.ctl, nullptr, nullptr, st)) != hipSuccess)
           return e;
         if (prof->on && (e = prof->end(st)) != hipSuccess) return e;
         if (prof->on && (e = prof->begin(K_FORWARD, st)) != hipSuccess) return e;
-        if ((e = launch_forward(geom, h_geom, N, R, win, w.u, w.uT, nullptr, nullptr, w.q,
+        if ((e = launch_forward(geom, h_geom, N, R, win, w.u, w.uT, 0, nullptr, 0, nullptr, w.q,
                                 partial, w.pd, lam, pq_parts, w.ctl, st)) != hipSuccess)
           return e;
         if (prof->on && (e = prof->end(st)) != hipSuccess) return e;

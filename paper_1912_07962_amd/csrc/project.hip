@@ -46,6 +46,26 @@ struct FwdPlan {
   short slot[kMaxList];
 };
 
+// bf16 storage (upper half of a float32, round-to-nearest-even on store)
+__device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+__device__ __forceinline__ uint16_t f2bf(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);  // quiet NaN
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float tof(float v) { return v; }
+__device__ __forceinline__ float tof(uint16_t v) { return bf2f(v); }
+// four consecutive pixels starting at element 4*i
+__device__ __forceinline__ float4 load4(const float* p, int i) {
+  return reinterpret_cast<const float4*>(p)[i];
+}
+__device__ __forceinline__ float4 load4(const uint16_t* p, int i) {
+  const uint2 u = reinterpret_cast<const uint2*>(p)[i];
+  return make_float4(__uint_as_float(u.x << 16), __uint_as_float(u.x & 0xffff0000u),
+                     __uint_as_float(u.y << 16), __uint_as_float(u.y & 0xffff0000u));
+}
+
 __device__ __forceinline__ void chunk_range(const FwdPlan& pl, int c, int& e0, int& e1, bool& colm) {
   const int nrc = (pl.n_row + pl.ch - 1) / pl.ch;
   if (c < nrc) {
@@ -59,11 +79,11 @@ __device__ __forceinline__ void chunk_range(const FwdPlan& pl, int c, int& e0, i
   }
 }
 
-template <int IT>
+template <int IT, typename IMG>
 __global__ __launch_bounds__(kFT, 2) void fwd_band_kernel(const AngleGeom* __restrict__ geom, int N,
                                                           int R, FwdPlan pl,
-                                                          const float* __restrict__ img,
-                                                          const float* __restrict__ imgT,
+                                                          const IMG* __restrict__ img,
+                                                          const IMG* __restrict__ imgT,
                                                           float* __restrict__ partial,
                                                           const int* __restrict__ stop) {
   if (stop && stop[kCtlDone]) return;
@@ -80,7 +100,7 @@ __global__ __launch_bounds__(kFT, 2) void fwd_band_kernel(const AngleGeom* __res
   bool colm;
   chunk_range(pl, chunk, e0, e1, colm);
   const int nitems = (e1 - e0) * R;
-  const float* src = colm ? imgT : img;
+  const IMG* src = colm ? imgT : img;
   const double half = 0.5 * (N - 1);
   const double off = 0.5 * (R - 1);
   const int kg = grp * pl.G * pl.H;
@@ -149,17 +169,17 @@ __global__ __launch_bounds__(kFT, 2) void fwd_band_kernel(const AngleGeom* __res
   float4 pf0, pf1, pf2, pf3, pf4, pf5, pf6, pf7;
 #define SLIM_PF_LOAD(kb_)                                                       \
   do {                                                                          \
-    const float4* s4 = reinterpret_cast<const float4*>(src + (size_t)(kb_) * N); \
+    const IMG* s4 = src + (size_t)(kb_) * N;                                    \
     const int lim = min(pl.H, N - (kb_)) * n4 - 1;                               \
     const int t0 = (int)threadIdx.x;                                            \
-    pf0 = s4[min(t0 + 0 * kFT, lim)];                                           \
-    pf1 = s4[min(t0 + 1 * kFT, lim)];                                           \
-    pf2 = s4[min(t0 + 2 * kFT, lim)];                                           \
-    pf3 = s4[min(t0 + 3 * kFT, lim)];                                           \
-    pf4 = s4[min(t0 + 4 * kFT, lim)];                                           \
-    pf5 = s4[min(t0 + 5 * kFT, lim)];                                           \
-    pf6 = s4[min(t0 + 6 * kFT, lim)];                                           \
-    pf7 = s4[min(t0 + 7 * kFT, lim)];                                           \
+    pf0 = load4(s4, min(t0 + 0 * kFT, lim));                                    \
+    pf1 = load4(s4, min(t0 + 1 * kFT, lim));                                    \
+    pf2 = load4(s4, min(t0 + 2 * kFT, lim));                                    \
+    pf3 = load4(s4, min(t0 + 3 * kFT, lim));                                    \
+    pf4 = load4(s4, min(t0 + 4 * kFT, lim));                                    \
+    pf5 = load4(s4, min(t0 + 5 * kFT, lim));                                    \
+    pf6 = load4(s4, min(t0 + 6 * kFT, lim));                                    \
+    pf7 = load4(s4, min(t0 + 7 * kFT, lim));                                    \
   } while (0)
 #define SLIM_PF_STORE1(u, v)                                                    \
   do {                                                                          \
@@ -185,7 +205,8 @@ __global__ __launch_bounds__(kFT, 2) void fwd_band_kernel(const AngleGeom* __res
       SLIM_PF_STORE1(7, pf7);
     } else {
       for (int r = 0; r < hb; ++r)
-        for (int c = threadIdx.x; c < N; c += kFT) band[r * W + kPad + c] = src[(size_t)(kb + r) * N + c];
+        for (int c = threadIdx.x; c < N; c += kFT)
+          band[r * W + kPad + c] = tof(src[(size_t)(kb + r) * N + c]);
     }
     __syncthreads();
     const int kbn = kb + pl.H;
@@ -223,10 +244,11 @@ __global__ __launch_bounds__(kFT, 2) void fwd_band_kernel(const AngleGeom* __res
 
 // out[s][t] = (h/d) sum_groups partial - sub; optional CG tail q = out + lam*pd
 // with per-workgroup partial dot <pd, q>.
+template <typename SUB>
 __global__ __launch_bounds__(256) void fwd_reduce_kernel(const AngleGeom* __restrict__ geom, int R,
                                                          AngleList ids, int n_groups,
                                                          const float* __restrict__ partial,
-                                                         const float* __restrict__ sub,
+                                                         const SUB* __restrict__ sub,
                                                          float* __restrict__ out32,
                                                          double* __restrict__ out64,
                                                          const double* __restrict__ pd, double lam,
@@ -254,7 +276,7 @@ __global__ __launch_bounds__(256) void fwd_reduce_kernel(const AngleGeom* __rest
     for (; g < n_groups; ++g) v += (double)pp[g * gs];
     const double hd = (double)geom[ang].hd;
     v *= hd;
-    if (sub) v -= (double)sub[(size_t)ang * R + t];
+    if (sub) v -= (double)tof(sub[(size_t)ang * R + t]);
     if (pd) {
       v = fma(lam, pd[o], v);
       d = pd[o] * v;
@@ -316,7 +338,9 @@ __global__ __launch_bounds__(256) void back_kernel(const AngleGeom* __restrict__
                                                    float* __restrict__ xT,
                                                    const float* __restrict__ x_true,
                                                    double* __restrict__ partials, int mode,
-                                                   const int* __restrict__ stop) {
+                                                   const int* __restrict__ stop,
+                                                   uint16_t* __restrict__ xs,
+                                                   uint16_t* __restrict__ xsT) {
   if (stop && stop[kCtlDone]) return;
   __shared__ float seg[kBAng * kSeg];
   __shared__ int tmin[kBAng];
@@ -401,6 +425,7 @@ __global__ __launch_bounds__(256) void back_kernel(const AngleGeom* __restrict__
         const size_t p = (size_t)i * N + jb + q;
         xn[q] = x[p] - s[q];
         x[p] = xn[q];
+        if (xs) xs[p] = f2bf(xn[q]);
         ss += (double)s[q] * (double)s[q];
         xx += (double)xn[q] * (double)xn[q];
         if (x_true) {
@@ -410,14 +435,18 @@ __global__ __launch_bounds__(256) void back_kernel(const AngleGeom* __restrict__
       }
     }
   }
-  if (xT) {
+  if (xT || xsT) {
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < kBPX; ++q) tile[ty][kBPX * tx + q] = xn[q];
     __syncthreads();
     for (int e = threadIdx.x; e < kBH * kBW; e += 256) {
       const int jl = e / kBH, il = e % kBH;
-      if (j0 + jl < N && i0 + il < N) xT[(size_t)(j0 + jl) * N + i0 + il] = tile[il][jl];
+      if (j0 + jl < N && i0 + il < N) {
+        const size_t o = (size_t)(j0 + jl) * N + i0 + il;
+        if (xT) xT[o] = tile[il][jl];
+        if (xsT) xsT[o] = f2bf(tile[il][jl]);
+      }
     }
   }
   ss = wave_sum(ss);
@@ -463,15 +492,25 @@ __global__ __launch_bounds__(256) void reduce3_kernel(const double* __restrict__
 
 constexpr int kTile = 16;
 
+// dst = src^T (float32, optional); bf16 copies of src and of src^T (optional)
 __global__ __launch_bounds__(256) void transpose_kernel(const float* __restrict__ src,
-                                                        float* __restrict__ dst, int N) {
+                                                        float* __restrict__ dst, int N,
+                                                        uint16_t* __restrict__ bs,
+                                                        uint16_t* __restrict__ bsT) {
   __shared__ float t[kTile][kTile + 1];
   const int tx = threadIdx.x & (kTile - 1), ty = threadIdx.x / kTile;
   const int i = blockIdx.y * kTile + ty, j = blockIdx.x * kTile + tx;
-  if (i < N && j < N) t[ty][tx] = src[(size_t)i * N + j];
+  if (i < N && j < N) {
+    const float v = src[(size_t)i * N + j];
+    t[ty][tx] = v;
+    if (bs) bs[(size_t)i * N + j] = f2bf(v);
+  }
   __syncthreads();
   const int jt = blockIdx.x * kTile + ty, it = blockIdx.y * kTile + tx;
-  if (jt < N && it < N) dst[(size_t)jt * N + it] = t[tx][ty];
+  if (jt < N && it < N) {
+    if (dst) dst[(size_t)jt * N + it] = t[tx][ty];
+    if (bsT) bsT[(size_t)jt * N + it] = f2bf(t[tx][ty]);
+  }
 }
 
 }  // namespace
@@ -498,37 +537,54 @@ static int num_cu() {
   return g_num_cu;
 }
 
+template <typename IMG>
+static void launch_band(int items, dim3 grid, size_t lds, hipStream_t st, const AngleGeom* geom,
+                        int N, int R, const FwdPlan& pl, const IMG* img, const IMG* imgT,
+                        float* partial, const int* stop) {
+  switch (items) {
+    case 1:
+      hipLaunchKernelGGL((fwd_band_kernel<1, IMG>), grid, dim3(kFT), lds, st, geom, N, R, pl, img,
+                         imgT, partial, stop);
+      break;
+    case 2:
+      hipLaunchKernelGGL((fwd_band_kernel<2, IMG>), grid, dim3(kFT), lds, st, geom, N, R, pl, img,
+                         imgT, partial, stop);
+      break;
+    case 3:
+      hipLaunchKernelGGL((fwd_band_kernel<3, IMG>), grid, dim3(kFT), lds, st, geom, N, R, pl, img,
+                         imgT, partial, stop);
+      break;
+    default:
+      hipLaunchKernelGGL((fwd_band_kernel<4, IMG>), grid, dim3(kFT), lds, st, geom, N, R, pl, img,
+                         imgT, partial, stop);
+      break;
+  }
+}
+
 hipError_t launch_forward(const AngleGeom* geom, const AngleGeom* h_geom, int N, int R,
-                          const AngleList& ids, const float* img, const float* imgT,
-                          const float* sub, float* out32, double* out64, float* partial,
-                          const double* pd, double lam, double* dots, const int* stop,
-                          hipStream_t st) {
+                          const AngleList& ids, const void* img, const void* imgT, int img_bf16,
+                          const void* sub, int sub_bf16, float* out32, double* out64,
+                          float* partial, const double* pd, double lam, double* dots,
+                          const int* stop, hipStream_t st) {
   if (ids.n <= 0) return hipSuccess;
   const FwdPlan pl = make_plan(h_geom, N, R, ids, num_cu());
   const int total = pl.n_groups * pl.n_chunks;
   const int nwg = (total + 7) / 8 * 8;
   const size_t lds = (size_t)pl.H * (N + 2 * kPad) * sizeof(float);
-  switch (pl.items) {
-    case 1:
-      hipLaunchKernelGGL(fwd_band_kernel<1>, dim3(nwg), dim3(kFT), lds, st, geom, N, R, pl, img,
-                         imgT, partial, stop);
-      break;
-    case 2:
-      hipLaunchKernelGGL(fwd_band_kernel<2>, dim3(nwg), dim3(kFT), lds, st, geom, N, R, pl, img,
-                         imgT, partial, stop);
-      break;
-    case 3:
-      hipLaunchKernelGGL(fwd_band_kernel<3>, dim3(nwg), dim3(kFT), lds, st, geom, N, R, pl, img,
-                         imgT, partial, stop);
-      break;
-    default:
-      hipLaunchKernelGGL(fwd_band_kernel<4>, dim3(nwg), dim3(kFT), lds, st, geom, N, R, pl, img,
-                         imgT, partial, stop);
-      break;
-  }
+  if (img_bf16)
+    launch_band(pl.items, dim3(nwg), lds, st, geom, N, R, pl, (const uint16_t*)img,
+                (const uint16_t*)imgT, partial, stop);
+  else
+    launch_band(pl.items, dim3(nwg), lds, st, geom, N, R, pl, (const float*)img,
+                (const float*)imgT, partial, stop);
   const int n = ids.n * R;
-  hipLaunchKernelGGL(fwd_reduce_kernel, dim3((n + 255) / 256), dim3(256), 0, st, geom, R, ids,
-                     pl.n_groups, partial, sub, out32, out64, pd, lam, dots, stop);
+  const dim3 rg((n + 255) / 256);
+  if (sub_bf16)
+    hipLaunchKernelGGL(fwd_reduce_kernel<uint16_t>, rg, dim3(256), 0, st, geom, R, ids, pl.n_groups,
+                       partial, (const uint16_t*)sub, out32, out64, pd, lam, dots, stop);
+  else
+    hipLaunchKernelGGL(fwd_reduce_kernel<float>, rg, dim3(256), 0, st, geom, R, ids, pl.n_groups,
+                       partial, (const float*)sub, out32, out64, pd, lam, dots, stop);
   return hipGetLastError();
 }
 
@@ -537,14 +593,14 @@ int back_num_workgroups(int N) { return ((N + kBW - 1) / kBW) * ((N + kBH - 1) /
 hipError_t launch_back(const AngleGeom* geom, int N, int R, const AngleList& ids,
                        const float* v32, const double* v64, float* out, float* x, float* xT,
                        const float* x_true, double* partials, int mode, const int* stop,
-                       hipStream_t st) {
+                       uint16_t* xs, uint16_t* xsT, hipStream_t st) {
   dim3 grid((N + kBW - 1) / kBW, (N + kBH - 1) / kBH);
   if (v64) {
     hipLaunchKernelGGL(back_kernel<double>, grid, dim3(256), 0, st, geom, N, R, ids, v64, out, x,
-                       xT, x_true, partials, mode, stop);
+                       xT, x_true, partials, mode, stop, xs, xsT);
   } else {
     hipLaunchKernelGGL(back_kernel<float>, grid, dim3(256), 0, st, geom, N, R, ids, v32, out, x,
-                       xT, x_true, partials, mode, stop);
+                       xT, x_true, partials, mode, stop, xs, xsT);
   }
   return hipGetLastError();
 }
@@ -554,9 +610,10 @@ hipError_t launch_reduce3(const double* partials, int n, double* out, hipStream_
   return hipGetLastError();
 }
 
-hipError_t launch_transpose(const float* src, float* dst, int N, hipStream_t st) {
+hipError_t launch_transpose(const float* src, float* dst, int N, uint16_t* bs, uint16_t* bsT,
+                            hipStream_t st) {
   const int t = (N + kTile - 1) / kTile;
-  hipLaunchKernelGGL(transpose_kernel, dim3(t, t), dim3(256), 0, st, src, dst, N);
+  hipLaunchKernelGGL(transpose_kernel, dim3(t, t), dim3(256), 0, st, src, dst, N, bs, bsT);
   return hipGetLastError();
 }
 

@@ -106,6 +106,8 @@ struct slim_ctx {
   float* d_xT = nullptr;       // [B][N][N]
   float* d_tmp = nullptr;      // [N][N] scratch image (public projector)
   float* d_fpart = nullptr;    // forward projector partial sums
+  uint16_t* d_xs = nullptr;    // bf16 shadow of x        [B][N][N] (precision BF16)
+  uint16_t* d_xsT = nullptr;   // bf16 shadow of x^T      [B][N][N] (precision BF16)
   PcgWork pcg{};
   Profiler prof;
 
@@ -128,6 +130,8 @@ struct slim_ctx {
     (void)hipFree(d_xT);
     (void)hipFree(d_tmp);
     (void)hipFree(d_fpart);
+    (void)hipFree(d_xs);
+    (void)hipFree(d_xsT);
     pcg_free(pcg);
     prof.release();
     if (h_norms) (void)hipHostFree(h_norms);
@@ -135,6 +139,7 @@ struct slim_ctx {
   }
 
   size_t img_elems() const { return (size_t)N * N; }
+  bool bf16() const { return o.precision == SLIM_PREC_BF16; }
   size_t sino_elems() const { return (size_t)n_angles * R; }
 };
 
@@ -170,14 +175,23 @@ AngleList window_list(const slim_ctx* c) {
   return l;
 }
 
+// Refresh the copies of x that the forward projector reads: x^T (float32),
+// or the bf16 shadows of x and x^T in the bf16-storage variant.
 slim_status transpose_slices(slim_ctx* c) {
-  for (int sl = 0; sl < c->B; ++sl)
-    HIP_TRY(launch_transpose(c->x + sl * c->img_elems(), c->d_xT + sl * c->img_elems(), c->N, c->st));
+  for (int sl = 0; sl < c->B; ++sl) {
+    const size_t o = sl * c->img_elems();
+    if (c->bf16())
+      HIP_TRY(launch_transpose(c->x + o, nullptr, c->N, c->d_xs + o, c->d_xsT + o, c->st));
+    else
+      HIP_TRY(launch_transpose(c->x + o, c->d_xT + o, c->N, nullptr, nullptr, c->st));
+  }
   return SLIM_OK;
 }
 
-const float* sino_f32(const slim_ctx* c, int sl) {
-  return (const float*)c->b + (size_t)sl * c->sino_elems();
+// sinogram of slice sl (float32 or bf16 elements)
+const void* sino_slice(const slim_ctx* c, int sl) {
+  const size_t esz = c->bf16() ? sizeof(uint16_t) : sizeof(float);
+  return (const char*)c->b + (size_t)sl * c->sino_elems() * esz;
 }
 
 // Gram mode: z = G^{-1} [0; res] for every slice, G shared by the slices.
@@ -231,11 +245,12 @@ slim_status do_step(slim_ctx* c, const int32_t* ids, slim_step_info* info) {
   // 1. residual of the new block, every slice
   if (c->prof.on) HIP_TRY(c->prof.begin(K_RESID, c->st));
   for (int sl = 0; sl < c->B; ++sl) {
-    const float* xs = c->x + sl * c->img_elems();
-    const float* xTs = c->d_xT + sl * c->img_elems();
-    HIP_TRY(launch_forward(c->d_geom, c->h_geom.data(), c->N, c->R, blk, xs, xTs, sino_f32(c, sl),
-                           nullptr, c->d_res64 + sl * ell, c->d_fpart, nullptr, 0.0, nullptr,
-                           nullptr, c->st));
+    const size_t o = sl * c->img_elems();
+    const void* xs = c->bf16() ? (const void*)(c->d_xs + o) : (const void*)(c->x + o);
+    const void* xTs = c->bf16() ? (const void*)(c->d_xsT + o) : (const void*)(c->d_xT + o);
+    HIP_TRY(launch_forward(c->d_geom, c->h_geom.data(), c->N, c->R, blk, xs, xTs, c->bf16(),
+                           sino_slice(c, sl), c->bf16(), nullptr, c->d_res64 + sl * ell,
+                           c->d_fpart, nullptr, 0.0, nullptr, nullptr, c->st));
   }
   if (c->prof.on) HIP_TRY(c->prof.end(c->st));
   // 2. Gram system
@@ -263,8 +278,11 @@ slim_status do_step(slim_ctx* c, const int32_t* ids, slim_step_info* info) {
   for (int sl = 0; sl < c->B; ++sl) {
     float* xs = c->x + sl * c->img_elems();
     const float* xt = c->x_true ? c->x_true + sl * c->img_elems() : nullptr;
+    const size_t o = sl * c->img_elems();
     HIP_TRY(launch_back(c->d_geom, c->N, c->R, win, nullptr, c->d_z + sl * c->pmax, nullptr, xs,
-                        c->d_xT + sl * c->img_elems(), xt, c->d_partials, 1, nullptr, c->st));
+                        c->bf16() ? nullptr : c->d_xT + o, xt, c->d_partials, 1, nullptr,
+                        c->bf16() ? c->d_xs + o : nullptr, c->bf16() ? c->d_xsT + o : nullptr,
+                        c->st));
     HIP_TRY(launch_reduce3(c->d_partials, nwg, c->d_norms + 3 * sl, c->st));
   }
   if (c->prof.on) HIP_TRY(c->prof.end(c->st));
@@ -364,7 +382,6 @@ slim_status slim_init(slim_ctx** out, const slim_grid* grid, int n_angles, const
   if (mode == SLIM_GRAM_AUTO) mode = (pmax <= o.chol_max_p && pmax <= 8192) ? SLIM_GRAM_CHOL : SLIM_GRAM_PCG;
   if (mode == SLIM_GRAM_CHOL && pmax > 8192)
     return fail(SLIM_EINVAL, "explicit Gram needs (r+1)*g*n_rays <= 8192; use PCG");
-  if (o.precision == SLIM_PREC_BF16) return fail(SLIM_EINVAL, "bf16 storage is not built yet");
 
   slim_ctx* c = new slim_ctx();
   c->N = grid->N;
@@ -408,7 +425,12 @@ slim_status slim_init(slim_ctx** out, const slim_grid* grid, int n_angles, const
   if ((e = dalloc(&c->d_info, 1)) != hipSuccess) return oom(e);
   if ((e = dalloc(&c->d_partials, 3 * (size_t)back_num_workgroups(c->N))) != hipSuccess) return oom(e);
   if ((e = dalloc(&c->d_norms, 3 * (size_t)c->B)) != hipSuccess) return oom(e);
-  if ((e = dalloc(&c->d_xT, nimg)) != hipSuccess) return oom(e);
+  if (o.precision == SLIM_PREC_BF16) {
+    if ((e = dalloc(&c->d_xs, nimg)) != hipSuccess) return oom(e);
+    if ((e = dalloc(&c->d_xsT, nimg)) != hipSuccess) return oom(e);
+  } else {
+    if ((e = dalloc(&c->d_xT, nimg)) != hipSuccess) return oom(e);
+  }
   if ((e = dalloc(&c->d_tmp, c->img_elems())) != hipSuccess) return oom(e);
   if ((e = dalloc(&c->d_fpart, forward_partial_floats(c->N, c->R, kMaxList))) != hipSuccess) return oom(e);
   if (mode == SLIM_GRAM_CHOL) {
@@ -497,8 +519,8 @@ slim_status slim_project(slim_ctx* c, const int32_t* ids, int n_ids, const float
   const AngleList l = make_list(ids, n_ids);
   for (int sl = 0; sl < c->B; ++sl) {
     const float* xs = x + sl * c->img_elems();
-    HIP_TRY(launch_transpose(xs, c->d_tmp, c->N, c->st));
-    HIP_TRY(launch_forward(c->d_geom, c->h_geom.data(), c->N, c->R, l, xs, c->d_tmp, nullptr,
+    HIP_TRY(launch_transpose(xs, c->d_tmp, c->N, nullptr, nullptr, c->st));
+    HIP_TRY(launch_forward(c->d_geom, c->h_geom.data(), c->N, c->R, l, xs, c->d_tmp, 0, nullptr, 0,
                            out + (size_t)sl * n_ids * c->R, nullptr, c->d_fpart, nullptr, 0.0,
                            nullptr, nullptr, c->st));
   }
@@ -514,7 +536,7 @@ slim_status slim_backproject(slim_ctx* c, const int32_t* ids, int n_ids, const f
   for (int sl = 0; sl < c->B; ++sl)
     HIP_TRY(launch_back(c->d_geom, c->N, c->R, l, v + (size_t)sl * n_ids * c->R, nullptr,
                         out + sl * c->img_elems(), nullptr, nullptr, nullptr, nullptr, 0, nullptr,
-                        c->st));
+                        nullptr, nullptr, c->st));
   return SLIM_OK;
 }
 

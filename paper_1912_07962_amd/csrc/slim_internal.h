@@ -93,22 +93,24 @@ struct Profiler {
 // workspace of forward_partial_floats(N, R, ids.n) floats.  CG tail when pd
 // is non-NULL: out += lam * pd and per-workgroup partial sums of pd . out
 // into dots[forward_dot_parts(ids.n * R)].
+// img/imgT are float32, or bf16 bit patterns when img_bf16 != 0; sub likewise.
 hipError_t launch_forward(const AngleGeom* geom, const AngleGeom* h_geom, int N, int R,
-                          const AngleList& ids, const float* img, const float* imgT,
-                          const float* sub, float* out32, double* out64, float* partial,
-                          const double* pd, double lam, double* dots, const int* stop,
-                          hipStream_t st);
+                          const AngleList& ids, const void* img, const void* imgT, int img_bf16,
+                          const void* sub, int sub_bf16, float* out32, double* out64,
+                          float* partial, const double* pd, double lam, double* dots,
+                          const int* stop, hipStream_t st);
 size_t forward_partial_floats(int N, int R, int max_list);
 int forward_dot_parts(int n_out);
 
 // Back-projection over a list: s[pix] = sum_a sum_t A[(ids[a],t),pix] v[a][t]
-// with v float (v32) or double (v64).  mode 0: out = s.  mode 1: x -= s in
-// place, optional transposed copy xT, and per-workgroup float64 partial norms
+// with v float (v32) or double (v64).  mode 0: out = s (and out^T into xT).
+// mode 1: x -= s in place, optional transposed copy xT, optional bf16 copies
+// xs, xsT (round to nearest even), and per-workgroup float64 partial norms
 // (||s||^2, ||x_new||^2, ||x_new - x_true||^2) into partials[3*nwg].
 hipError_t launch_back(const AngleGeom* geom, int N, int R, const AngleList& ids,
                        const float* v32, const double* v64, float* out, float* x, float* xT,
                        const float* x_true, double* partials, int mode, const int* stop,
-                       hipStream_t st);
+                       uint16_t* xs, uint16_t* xsT, hipStream_t st);
 int back_num_workgroups(int N);
 
 // Sum 3-vectors of partials in a fixed order into out[3] (one workgroup).

@@ -276,3 +276,13 @@ def test_sparse_block_matches_dense_block():
     dense = system.dense_bruteforce(N, P.R, P.theta[ids])
     assert sp.issparse(P.rows(ids))
     np.testing.assert_allclose(P.rows(ids).toarray(), dense, rtol=1e-13, atol=1e-15)
+
+
+def test_round_bf16_published_values():
+    from oracle.slimls import round_bf16
+    # bfloat16 has an 8-bit significand: 1 + 2^-8 is a tie -> even (1.0),
+    # 1 + 3*2^-8 is a tie -> even (1 + 2^-6); pi -> 3.140625; 65504 (the
+    # largest float16) rounds up to 2^16
+    vals = np.array([1.0, 1 + 2.0 ** -8, 1 + 3 * 2.0 ** -8, np.pi, -np.pi, 65504.0])
+    got = round_bf16(vals)
+    np.testing.assert_array_equal(got, [1.0, 1.0, 1 + 2.0 ** -6, 3.140625, -3.140625, 65536.0])
