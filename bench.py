@@ -4,7 +4,7 @@
 Workload (the plain single-slice method on the GPU): a 1024 x 1024 image,
 720 angles uniform on [0, pi) x 1449 rays, 20 random ellipses, 1% noise,
 blocks of 8 angles (11,592 rays), memory r = 10, lambda = 1e-3.  The Gram
-system of the full window (p = 127,512) is solved by Jacobi-PCG with
+system of the full window (p = 127,512) is solved by conjugate gradients with
 matrix-free projectors.  Inputs are seeded synthetic data resident in HBM
 before timing.
 
@@ -19,6 +19,13 @@ time).  The line also carries:
   time_to_target  wall time and steps of the plain method to its stop rule
                 (first k >= r+1 with ||s_k|| <= 1e-2 ||x_k||) and the error
                 vs x_true there;
+  batched       the same parameters on B = 8 different 1024^2 slices in one
+                context: wall time until every slice reaches the error its
+                plain run had at its stop step, amortized over B, next to
+                the plain runs' mean time-to-target;
+  volume        512 slices of 512^2 (360 angles x 725 rays, 4 angles/block,
+                r = 8): fwd/back rays/s of one block over all slices and
+                the time of whole slimLS steps;
   cpu_baseline  the FP64 oracle's steps of the same run on the host.
 """
 from __future__ import annotations
@@ -68,6 +75,178 @@ def cpu_baseline(cfg, b, x_true, budget_s):
                       f"single-threaded sparse kernels"}
 
 
+def plain_ttr(s, bd, x, xt, sched, g, r, M, nrm):
+    """Plain run from x = 0 to the stop rule (first k >= r+1 with
+    ||s_k|| <= 1e-2 ||x_k||, at most 3 epochs).  Returns (wall s, steps,
+    rel err at the stop step, stopped by the rule)."""
+    import torch
+    x.zero_()
+    s.set_data(bd, x, xt)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    k = 0
+    while True:
+        beta = int(sched[k % len(sched)])
+        info = s.step(list(range(beta * g, beta * g + g)))
+        k += 1
+        if k >= r + 1 and info["step_norm"] <= 1e-2 * info["x_norm"]:
+            break
+        if k >= 3 * M:
+            break
+    torch.cuda.synchronize()
+    return time.perf_counter() - t1, k, info["err_norm"] / nrm, k < 3 * M
+
+
+def batched_ttr(cfg, s1, sched, dev, B):
+    """B different 1024^2 slices (phantom and noise seeds + slice index) under
+    the plain parameters.  Each slice's plain run fixes its target e*_b (its
+    error at its stop step); the batched context then steps all B slices
+    together until every slice is within its own e*_b."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_1912_07962_amd import Slim
+
+    N, na, g, r, lam = cfg["N"], cfg["n_angles"], cfg["g"], cfg["r"], cfg["lam"]
+    M = na // g
+    print(f"bench: batched time-to-target, {B} slices", file=sys.stderr, flush=True)
+    probs = [synth.make_slice_problem(N, na, cfg["n_ellipses"], cfg["noise"],
+                                      cfg["phantom_seed"] + i, cfg["noise_seed"] + i)
+             for i in range(B)]
+    nrm = np.array([np.linalg.norm(p[0]) for p in probs])
+    plain = []
+    x1 = torch.zeros((N, N), dtype=torch.float32, device=dev)
+    for i, (xt_i, b_i, _) in enumerate(probs):
+        bd = torch.as_tensor(b_i, dtype=torch.float32, device=dev)
+        xt = torch.as_tensor(xt_i, dtype=torch.float32, device=dev)
+        plain.append(plain_ttr(s1, bd, x1, xt, sched, g, r, M, nrm[i]))
+    e_star = np.array([p[2] for p in plain])
+
+    bd = torch.as_tensor(np.stack([p[1] for p in probs]), dtype=torch.float32, device=dev)
+    xt = torch.as_tensor(np.stack([p[0] for p in probs]), dtype=torch.float32, device=dev)
+    xb = torch.zeros((B, N, N), dtype=torch.float32, device=dev)
+    sb = Slim(N, na, r=r, lam=lam, n_slices=B, angles_per_block=g, gram_mode="pcg",
+              pcg_tol=1e-6)
+    sb.set_data(bd, xb, xt)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    k = 0
+    iters = 0
+    while True:
+        beta = int(sched[k % len(sched)])
+        info = sb.step(list(range(beta * g, beta * g + g)))
+        iters += info["pcg_iters"]
+        k += 1
+        rel = sb.slice_norms()[:, 2] / nrm
+        if np.all(rel <= e_star) or k >= 3 * M:
+            break
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t1
+    plain_mean = float(np.mean([p[0] for p in plain]))
+    out = {"slices": B, "plain_mean_s": plain_mean,
+           "plain_steps": [p[1] for p in plain], "e_star": e_star.tolist(),
+           "batched_wall_s": wall, "batched_amortized_s": wall / B, "batched_steps": k,
+           "batched_cg_iters_per_step": iters / k,
+           "reached": bool(np.all(rel <= e_star)),
+           "speedup_vs_plain": plain_mean / (wall / B)}
+    print(f"bench: batched {wall:.2f} s for {B} slices ({wall / B:.3f} s each) vs plain "
+          f"{plain_mean:.3f} s", file=sys.stderr, flush=True)
+    sb.close()
+    return out
+
+
+def volume_bench(dev, B, steps):
+    """512^2 slices of one ellipsoid volume sharing A (360 angles x 725 rays,
+    4 angles/block, r = 8, lambda = 1e-3): one-block projector rays/s over
+    all slices, then whole slimLS steps after the window has filled."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_1912_07962_amd import Slim
+
+    cfg = synth.get_config("c4")
+    N, na, g, r, lam = cfg["N"], cfg["n_angles"], cfg["g"], cfg["r"], cfg["lam"]
+    print(f"bench: volume {B} x {N}^2 inputs", file=sys.stderr, flush=True)
+    xs, bs = synth.make_volume_problem(N, B, na, cfg["n_ellipsoids"], cfg["noise"],
+                                       cfg["phantom_seed"], cfg["noise_seed"])
+    xt = torch.as_tensor(xs, dtype=torch.float32, device=dev)
+    bd = torch.as_tensor(bs, dtype=torch.float32, device=dev)
+    del xs, bs
+    s = Slim(N, na, r=r, lam=lam, n_slices=B, angles_per_block=g, gram_mode="pcg", pcg_tol=1e-6)
+    R = s.R
+    ell = g * R
+    theta = np.arange(na) * (np.pi / na)
+    n_img = N * N
+
+    def _time(fn, n=10):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(n):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / n * 1e-3
+
+    proj = []
+    v = torch.randn((B, g, R), device=dev)
+    out_f = torch.empty((B, g, R), device=dev)
+    out_b = torch.empty((B, N, N), device=dev)
+    # a block of row-stepping angles (theta near 0) and one of column-stepping
+    # angles (theta near pi/2; the public forward transposes x for those)
+    for blk in (list(range(0, g)), list(range(na // 2, na // 2 + g))):
+        t_f = _time(lambda: s.project(blk, xt, out_f))
+        t_b = _time(lambda: s.backproject(blk, v, out_b))
+        nnz = window_nnz(N, theta[blk])
+        byt = B * (8.0 * n_img + 8.0 * ell)     # fwd: x in, rays out; back: rays in, image out
+        proj.append({"angles": blk, "fwd_us": t_f * 1e6, "back_us": t_b * 1e6,
+                     "fwd_rays_per_s": ell * B / t_f, "back_rays_per_s": ell * B / t_b,
+                     "fwd_back_rays_per_s": ell * B / (t_f + t_b),
+                     "hbm_gbs_algorithmic": byt / (t_f + t_b) / 1e9,
+                     "hbm_frac": byt / (t_f + t_b) / 1e9 / PEAK_HBM_GBS,
+                     "alu_tflops": 2 * 2.0 * nnz * B / (t_f + t_b) / 1e12})
+    del out_f, out_b, v
+
+    x = torch.zeros((B, N, N), dtype=torch.float32, device=dev)
+    s.set_data(bd, x, xt)
+    sched = synth.schedule(na // g, 1, cfg["schedule_seed"])
+    for k in range(r + 1):
+        beta = int(sched[k])
+        s.step(list(range(beta * g, beta * g + g)))
+    torch.cuda.synchronize()
+    s.profile(True)
+    t0 = time.perf_counter()
+    iters = []
+    flops = 0.0
+    window = [int(sched[k]) for k in range(0, r + 1)]
+    for k in range(r + 1, r + 1 + steps):
+        beta = int(sched[k])
+        info = s.step(list(range(beta * g, beta * g + g)))
+        window = (window + [beta])[-(r + 1):]
+        ids = [a for bb in window for a in range(bb * g, bb * g + g)]
+        flops += info["pcg_iters"] * 2.0 * window_nnz(N, theta[ids]) * B
+        iters.append(info["pcg_iters"])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    stats = s.kernel_stats()
+    s.profile(False)
+    st = stats["cg_forward"]
+    avg_f = st["total_ms"] / max(st["launches"], 1) * 1e-3
+    st = stats["cg_back"]
+    avg_b = st["total_ms"] / max(st["launches"], 1) * 1e-3
+    fl = flops / max(sum(iters), 1)
+    s.close()
+    print(f"bench: volume step {wall / steps * 1e3:.1f} ms", file=sys.stderr, flush=True)
+    return {"slices": B, "N": N, "block_rays": ell, "projector": proj,
+            "ms_per_step": wall / steps * 1e3, "steps": steps,
+            "slice_rays_per_s": ell * B * steps / wall,
+            "cg_iters_per_step": float(np.mean(iters)),
+            "cg_forward_us": avg_f * 1e6, "cg_back_us": avg_b * 1e6,
+            "cg_forward_tflops": fl / avg_f / 1e12, "cg_back_tflops": fl / avg_b / 1e12,
+            "kernel_ms": {k: v2["total_ms"] for k, v2 in stats.items()}}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -76,6 +255,12 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ttr", action="store_true", help="skip the time-to-target run")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the batched time-to-target run")
+    ap.add_argument("--batch", type=int, default=8, help="slices of the batched run")
+    ap.add_argument("--volume-slices", type=int, default=512,
+                    help="slices of the 512^2 volume workload (0 skips it)")
+    ap.add_argument("--volume-steps", type=int, default=4, help="timed volume steps")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only; --gpus must be 1 "
@@ -163,25 +348,19 @@ def main():
 
     ttr = None
     if not args.no_ttr:
-        x.zero_()
-        s.set_data(bd, x, xt)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        k = 0
-        nrm = float(np.linalg.norm(x_true))
-        while True:
-            beta = int(sched[k % len(sched)])
-            info = s.step(list(range(beta * g, beta * g + g)))
-            k += 1
-            if k >= r + 1 and info["step_norm"] <= 1e-2 * info["x_norm"]:
-                break
-            if k >= 3 * M:
-                break
-        torch.cuda.synchronize()
-        ttr = {"plain_s": time.perf_counter() - t1, "plain_steps": k,
-               "rel_err_at_stop": info["err_norm"] / nrm, "stopped_by_rule": k < 3 * M}
-        print(f"bench: time-to-target {ttr['plain_s']:.2f} s in {k} steps", file=sys.stderr,
-              flush=True)
+        wall_t, k, e_star, by_rule = plain_ttr(s, bd, x, xt, sched, g, r, M,
+                                               float(np.linalg.norm(x_true)))
+        ttr = {"plain_s": wall_t, "plain_steps": k, "rel_err_at_stop": e_star,
+               "stopped_by_rule": by_rule}
+        print(f"bench: time-to-target {wall_t:.2f} s in {k} steps", file=sys.stderr, flush=True)
+
+    batched = None
+    if not args.no_batched:
+        batched = batched_ttr(cfg, s, sched, dev, args.batch)
+
+    volume = None
+    if args.volume_slices > 0:
+        volume = volume_bench(dev, args.volume_slices, args.volume_steps)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -203,7 +382,7 @@ def main():
         "dtype": "f32 (f64 CG scalars and norms)",
         "data": "synthetic: 20 random ellipses, exact line integrals + 1% Gaussian noise",
         "config": {"workload": "plain slimLS, 1024x1024 image, 720 angles x 1449 rays, "
-                               "8 angles/block, r=10, lambda=1e-3, Jacobi-PCG to 1e-6",
+                               "8 angles/block, r=10, lambda=1e-3, CG to 1e-6",
                    "parallelism": "single GPU"},
         "roofline": {"bound": "alu", "kernel": f"{dom} (88-angle window)",
                      "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
@@ -212,6 +391,8 @@ def main():
         "cpu_baseline": cpu,
         "projector": projector,
         "time_to_target": ttr,
+        "batched": batched,
+        "volume": volume,
         "cg_iters_per_step": float(np.mean(iters)),
         "event_ms_timed_region": ev_ms,
         "kernel_ms": {k: v2["total_ms"] for k, v2 in stats.items()},

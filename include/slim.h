@@ -131,6 +131,14 @@ slim_status slim_set_data(slim_ctx* ctx, const void* b, void* x, const float* x_
  * SLIM_ENOTCONV (CG cap reached; the step is still applied), SLIM_EDEVICE. */
 slim_status slim_step(slim_ctx* ctx, const int32_t* angle_ids, int n_ids, slim_step_info* info);
 
+/* Per-slice norms of the last step whose info was read back (slim_step
+ * with info != NULL, or slim_solve): out is host float64 [n_slices][3]
+ * holding ||s_k||, ||x_k|| and ||x_k - x_true|| (-1 without x_true) of each
+ * slice, the quantities of the stop rule (sec. 4.3) slice by slice.
+ * Errors: SLIM_EINVAL (NULL out or n != n_slices), SLIM_ESTATE (no step read
+ * back since the data were bound). */
+slim_status slim_slice_norms(slim_ctx* ctx, double* out, int n);
+
 /* Run slimLS from x (in: x0, out: the result) with the data b until the stop
  * rule or max_epochs.  Blocks are the fixed partition {g*beta, ..., g*beta+g-1}
  * of the angles, visited random-cyclically (sec. 4.3): epoch e visits every

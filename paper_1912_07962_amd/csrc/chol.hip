@@ -132,14 +132,18 @@ __global__ __launch_bounds__(256) void syrk_update_kernel(double* __restrict__ G
   }
 }
 
-// Single-workgroup triangular solves with the vector in LDS.
+// Triangular solves, one workgroup per right-hand side, vector in LDS.
 constexpr int kSolveMax = 12288;
 
 __global__ __launch_bounds__(1024) void chol_solve_kernel(const double* __restrict__ L, int64_t ld,
                                                           int p, int nr,
-                                                          const double* __restrict__ rhs,
-                                                          double* __restrict__ z) {
+                                                          const double* __restrict__ rhs_all,
+                                                          size_t rhs_stride,
+                                                          double* __restrict__ z_all,
+                                                          size_t z_stride) {
   extern __shared__ double y[];
+  const double* rhs = rhs_all + (size_t)blockIdx.x * rhs_stride;
+  double* z = z_all + (size_t)blockIdx.x * z_stride;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   for (int i = tid; i < p; i += 1024) y[i] = (i >= p - nr) ? rhs[i - (p - nr)] : 0.0;
@@ -211,10 +215,11 @@ hipError_t launch_cholesky(double* G, int64_t ld, int p, int* info, hipStream_t 
 }
 
 hipError_t launch_chol_solve(const double* L, int64_t ld, int p, int nr, const double* rhs64,
-                             double* z, hipStream_t st) {
+                             size_t rhs_stride, double* z, size_t z_stride, int B,
+                             hipStream_t st) {
   if (p > kSolveMax) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(chol_solve_kernel, dim3(1), dim3(1024), (size_t)p * sizeof(double), st, L, ld,
-                     p, nr, rhs64, z);
+  hipLaunchKernelGGL(chol_solve_kernel, dim3(B), dim3(1024), (size_t)p * sizeof(double), st, L, ld,
+                     p, nr, rhs64, rhs_stride, z, z_stride);
   return hipGetLastError();
 }
 

@@ -10,32 +10,31 @@
 namespace slim {
 
 struct PcgWork {
-  int pmax = 0;
-  int nparts = 0;
-  double* r = nullptr;      // residual           [pmax]
-  double* pd = nullptr;     // search direction   [pmax]
-  double* q = nullptr;      // G pd               [pmax]
-  double* parts = nullptr;  // per-workgroup partial dots <pd,q>, <r,r> [2][nparts]
-  double* sc = nullptr;     // device scalars, two sets used alternately
-  int* ctl = nullptr;       // stop flag and iteration count
-  float* u = nullptr;       // M^T pd             [N][N]
-  float* uT = nullptr;      // its transpose      [N][N]
+  int B = 0;                // slices
+  int pmax = 0;             // rows of the largest window
+  int nparts = 0;           // partial sums per slice
+  double* r = nullptr;      // residuals          [B][pmax]
+  double* pd = nullptr;     // search directions  [B][pmax]
+  double* q = nullptr;      // G pd               [B][pmax]
+  double* parts = nullptr;  // per-workgroup partial dots <pd,q>, <r,r>: [2][B][nparts]
+  double* sc = nullptr;     // per-slice scalars, two sets used alternately [2][B][S]
+  int* ctl = nullptr;       // per-slice stop flag and iteration count [B][kCtlCount]
+  float* u = nullptr;       // M^T pd             [B][N][N]
+  float* uT = nullptr;      // its transpose      [B][N][N]
   int* h_ctl = nullptr;     // pinned copies of ctl, one per chunk in flight
   double* h_sc = nullptr;   // pinned copy of sc
   hipEvent_t ev[2] = {nullptr, nullptr};
 };
 
-hipError_t pcg_alloc(PcgWork& w, int N, int64_t pmax);
+hipError_t pcg_alloc(PcgWork& w, int N, int B, int64_t pmax);
 void pcg_free(PcgWork& w);
-// Solve for one slice: rhs = [0; res] (res: last nres entries), z: [p] out.
+// Solve the B systems (lambda I + M M^T) z_b = [0; res_b] (res_b: nres entries
+// at res + b * res_stride), z_b at z + b * z_stride, all slices advancing
+// together.  *iters and *relres: the largest over the slices.
 // h_geom: host geometry table; partial: forward-projector workspace.
 hipError_t pcg_solve(PcgWork& w, const AngleGeom* geom, const AngleGeom* h_geom, float* partial,
-                     int N, int R, const AngleList& win, double lam, const double* res, int nres,
-                     double* z, double tol, int max_iter, int* iters, double* relres,
-                     Profiler* prof, hipStream_t st);
-
-// dst = src^T (if dst), bf16 copies of src (bs) and src^T (bsT) if given.
-hipError_t launch_transpose(const float* src, float* dst, int N, uint16_t* bs, uint16_t* bsT,
-                            hipStream_t st);
+                     int N, int R, int B, const AngleList& win, double lam, const double* res,
+                     size_t res_stride, int nres, double* z, size_t z_stride, double tol,
+                     int max_iter, int* iters, double* relres, Profiler* prof, hipStream_t st);
 
 }  // namespace slim

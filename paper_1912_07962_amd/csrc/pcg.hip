@@ -1,5 +1,7 @@
 // Conjugate gradients on the Gram system (lambda I + M M^T) z = e,
-// e = [0; ...; 0; res], for one slice, with matrix-free M and M^T.
+// e = [0; ...; 0; res], for a batch of slices that share M (each slice runs
+// its own CG; all advance together in the same launches), with matrix-free
+// M and M^T.
 // Per iteration:
 //   u = M^T pd                 back-projector (float32 image and transpose)
 //   q = M u + lambda pd        forward projector, float64 sums, with the
@@ -11,8 +13,9 @@
 // on this Gram (its conditioning comes from low-frequency modes shared by
 // all blocks), so the iteration is unpreconditioned.
 //
-// Termination is decided on the device: the direction kernel sets a flag
-// once ||r|| <= tol ||e|| and every later CG kernel returns at entry.  The
+// Termination is decided on the device: the direction kernel sets a slice's
+// flag once its ||r|| <= tol ||e|| and every later CG kernel skips that
+// slice (the projectors skip a slice tile once all its slices stopped).  The
 // host enqueues chunks of iterations ahead and reads the flag from pinned
 // memory after a chunk completes, keeping the next chunk in flight, so the
 // GPU does not idle on host round trips.  All dot products are two-stage
@@ -21,6 +24,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <vector>
 
 namespace slim {
 
@@ -50,54 +54,64 @@ __device__ __forceinline__ double sum_parts(const double* __restrict__ parts, in
   return block_sum(a, sh);
 }
 
-// r = e, z = 0, pd = e; partials of <r, r>
-__global__ __launch_bounds__(kThreads) void init_kernel(int p, int nres,
+// r = e, z = 0, pd = e; partials of <r, r>.  blockIdx.y = slice.
+__global__ __launch_bounds__(kThreads) void init_kernel(int p, int nres, int pmax, int nparts,
                                                         const double* __restrict__ res,
+                                                        size_t res_stride,
                                                         double* __restrict__ r,
-                                                        double* __restrict__ z,
+                                                        double* __restrict__ z, size_t z_stride,
                                                         double* __restrict__ pd,
                                                         double* __restrict__ rr_parts) {
   __shared__ double sh[kThreads / 64];
+  const int sl = blockIdx.y;
   const int i = blockIdx.x * kThreads + threadIdx.x;
+  const size_t vo = (size_t)sl * pmax;
   double rr = 0.0;
   if (i < p) {
-    const double e = (i >= p - nres) ? res[i - (p - nres)] : 0.0;
-    r[i] = e;
-    z[i] = 0.0;
-    pd[i] = e;
+    const double e = (i >= p - nres) ? res[(size_t)sl * res_stride + i - (p - nres)] : 0.0;
+    r[vo + i] = e;
+    z[(size_t)sl * z_stride + i] = 0.0;
+    pd[vo + i] = e;
     rr = e * e;
   }
   rr = block_sum(rr, sh);
-  if (threadIdx.x == 0) rr_parts[blockIdx.x] = rr;
+  if (threadIdx.x == 0) rr_parts[(size_t)sl * nparts + blockIdx.x] = rr;
 }
 
 __global__ __launch_bounds__(kThreads) void init_scalars_kernel(const double* __restrict__ rr_parts,
-                                                                int nparts, double* __restrict__ sc,
+                                                                int nb, int nparts,
+                                                                double* __restrict__ sc,
                                                                 int* __restrict__ ctl) {
   __shared__ double sh[kThreads / 64];
-  const double bb = sum_parts(rr_parts, nparts, sh);
+  const int sl = blockIdx.y;
+  const double bb = sum_parts(rr_parts + (size_t)sl * nparts, nb, sh);
   if (threadIdx.x == 0) {
-    sc[S_RR] = bb;
-    sc[S_BB] = bb;
-    sc[S_BETA] = 0.0;
-    ctl[kCtlDone] = (bb > 0.0) ? 0 : 1;
-    ctl[kCtlIters] = 0;
+    double* c = sc + (size_t)sl * S_COUNT;
+    c[S_RR] = bb;
+    c[S_BB] = bb;
+    c[S_BETA] = 0.0;
+    ctl[sl * kCtlCount + kCtlDone] = (bb > 0.0) ? 0 : 1;
+    ctl[sl * kCtlCount + kCtlIters] = 0;
   }
 }
 
 // alpha = rr / <pd, q>; z += alpha pd; r -= alpha q; partials of <r, r>
-__global__ __launch_bounds__(kThreads) void update_kernel(int p, double* __restrict__ sc,
+__global__ __launch_bounds__(kThreads) void update_kernel(int p, int pmax, int nb, int nparts,
+                                                          double* __restrict__ sc_all,
                                                           const double* __restrict__ pq_parts,
                                                           const double* __restrict__ pd,
                                                           const double* __restrict__ q,
-                                                          double* __restrict__ z,
+                                                          double* __restrict__ z, size_t z_stride,
                                                           double* __restrict__ r,
                                                           double* __restrict__ rr_parts,
-                                                          int nparts, const int* __restrict__ ctl) {
-  if (ctl[kCtlDone]) return;
+                                                          const int* __restrict__ ctl) {
+  const int sl = blockIdx.y;
+  if (ctl[sl * kCtlCount + kCtlDone]) return;
   __shared__ double sh[kThreads / 64];
+  double* sc = sc_all + (size_t)sl * S_COUNT;
+  const size_t vo = (size_t)sl * pmax;
   const int i = blockIdx.x * kThreads + threadIdx.x;
-  const double pq = sum_parts(pq_parts, nparts, sh);
+  const double pq = sum_parts(pq_parts + (size_t)sl * nparts, nb, sh);
   const double alpha = (pq != 0.0) ? sc[S_RR] / pq : 0.0;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     sc[S_PQ] = pq;
@@ -105,61 +119,70 @@ __global__ __launch_bounds__(kThreads) void update_kernel(int p, double* __restr
   }
   double rr = 0.0;
   if (i < p) {
-    z[i] = fma(alpha, pd[i], z[i]);
-    const double rn = fma(-alpha, q[i], r[i]);
-    r[i] = rn;
+    double* zs = z + (size_t)sl * z_stride;
+    zs[i] = fma(alpha, pd[vo + i], zs[i]);
+    const double rn = fma(-alpha, q[vo + i], r[vo + i]);
+    r[vo + i] = rn;
     rr = rn * rn;
   }
   rr = block_sum(rr, sh);
-  if (threadIdx.x == 0) rr_parts[blockIdx.x] = rr;
+  if (threadIdx.x == 0) rr_parts[(size_t)sl * nparts + blockIdx.x] = rr;
 }
 
 // beta = rr_new / rr; pd = r + beta pd.  Every workgroup reads the current
-// scalars in sc while workgroup 0 publishes the next ones in sc_next (the
-// two sets alternate), counts the iteration and raises the stop flag.
-__global__ __launch_bounds__(kThreads) void direction_kernel(int p, const double* __restrict__ sc,
-                                                             double* __restrict__ sc_next,
+// scalars in sc while workgroup 0 of the slice publishes the next ones in
+// sc_next (the two sets alternate), counts the iteration and raises the
+// slice's stop flag.
+__global__ __launch_bounds__(kThreads) void direction_kernel(int p, int pmax, int nb, int nparts,
+                                                             const double* __restrict__ sc_all,
+                                                             double* __restrict__ sc_next_all,
                                                              const double* __restrict__ rr_parts,
-                                                             int nparts, double tol2,
+                                                             double tol2,
                                                              const double* __restrict__ r,
                                                              double* __restrict__ pd,
                                                              int* __restrict__ ctl) {
-  if (ctl[kCtlDone]) return;
+  const int sl = blockIdx.y;
+  if (ctl[sl * kCtlCount + kCtlDone]) return;
   __shared__ double sh[kThreads / 64];
-  const double rr_new = sum_parts(rr_parts, nparts, sh);
+  const double* sc = sc_all + (size_t)sl * S_COUNT;
+  double* sc_next = sc_next_all + (size_t)sl * S_COUNT;
+  const size_t vo = (size_t)sl * pmax;
+  const double rr_new = sum_parts(rr_parts + (size_t)sl * nparts, nb, sh);
   const double rr = sc[S_RR];
   const double beta = (rr != 0.0) ? rr_new / rr : 0.0;
   const int i = blockIdx.x * kThreads + threadIdx.x;
-  if (i < p) pd[i] = fma(beta, pd[i], r[i]);
+  if (i < p) pd[vo + i] = fma(beta, pd[vo + i], r[vo + i]);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     sc_next[S_RR] = rr_new;
     sc_next[S_BETA] = beta;
     sc_next[S_BB] = sc[S_BB];
-    ctl[kCtlIters] += 1;
-    if (!(rr_new > tol2 * sc[S_BB])) ctl[kCtlDone] = 1;  // also stops on NaN
+    ctl[sl * kCtlCount + kCtlIters] += 1;
+    if (!(rr_new > tol2 * sc[S_BB])) ctl[sl * kCtlCount + kCtlDone] = 1;  // also stops on NaN
   }
 }
 
 }  // namespace
 
-hipError_t pcg_alloc(PcgWork& w, int N, int64_t pmax) {
+hipError_t pcg_alloc(PcgWork& w, int N, int B, int64_t pmax) {
   hipError_t e;
+  w.B = B;
   w.pmax = (int)pmax;
   w.nparts = (int)((pmax + kThreads - 1) / kThreads);
-  const size_t np = (size_t)pmax * sizeof(double);
+  const size_t np = (size_t)B * pmax * sizeof(double);
   if ((e = hipMalloc((void**)&w.r, np)) != hipSuccess) return e;
   if ((e = hipMalloc((void**)&w.pd, np)) != hipSuccess) return e;
   if ((e = hipMalloc((void**)&w.q, np)) != hipSuccess) return e;
-  if ((e = hipMalloc((void**)&w.parts, (size_t)2 * w.nparts * sizeof(double))) != hipSuccess) return e;
-  if ((e = hipMalloc((void**)&w.sc, 2 * S_COUNT * sizeof(double))) != hipSuccess) return e;
-  if ((e = hipMalloc((void**)&w.ctl, kCtlCount * sizeof(int))) != hipSuccess) return e;
-  if ((e = hipMalloc((void**)&w.u, (size_t)N * N * sizeof(float))) != hipSuccess) return e;
-  if ((e = hipMalloc((void**)&w.uT, (size_t)N * N * sizeof(float))) != hipSuccess) return e;
-  if ((e = hipHostMalloc((void**)&w.h_ctl, 2 * kCtlCount * sizeof(int), hipHostMallocDefault)) !=
-      hipSuccess)
+  if ((e = hipMalloc((void**)&w.parts, (size_t)2 * B * w.nparts * sizeof(double))) != hipSuccess)
     return e;
-  if ((e = hipHostMalloc((void**)&w.h_sc, 2 * S_COUNT * sizeof(double), hipHostMallocDefault)) !=
-      hipSuccess)
+  if ((e = hipMalloc((void**)&w.sc, (size_t)2 * B * S_COUNT * sizeof(double))) != hipSuccess) return e;
+  if ((e = hipMalloc((void**)&w.ctl, (size_t)B * kCtlCount * sizeof(int))) != hipSuccess) return e;
+  if ((e = hipMalloc((void**)&w.u, (size_t)B * N * N * sizeof(float))) != hipSuccess) return e;
+  if ((e = hipMalloc((void**)&w.uT, (size_t)B * N * N * sizeof(float))) != hipSuccess) return e;
+  if ((e = hipHostMalloc((void**)&w.h_ctl, (size_t)2 * B * kCtlCount * sizeof(int),
+                         hipHostMallocDefault)) != hipSuccess)
+    return e;
+  if ((e = hipHostMalloc((void**)&w.h_sc, (size_t)2 * B * S_COUNT * sizeof(double),
+                         hipHostMallocDefault)) != hipSuccess)
     return e;
   for (int k = 0; k < 2; ++k)
     if ((e = hipEventCreateWithFlags(&w.ev[k], hipEventDisableTiming)) != hipSuccess) return e;
@@ -183,20 +206,57 @@ void pcg_free(PcgWork& w) {
 }
 
 hipError_t pcg_solve(PcgWork& w, const AngleGeom* geom, const AngleGeom* h_geom, float* partial,
-                     int N, int R, const AngleList& win, double lam, const double* res, int nres,
-                     double* z, double tol, int max_iter, int* iters, double* relres,
-                     Profiler* prof, hipStream_t st) {
+                     int N, int R, int B, const AngleList& win, double lam, const double* res,
+                     size_t res_stride, int nres, double* z, size_t z_stride, double tol,
+                     int max_iter, int* iters, double* relres, Profiler* prof, hipStream_t st) {
   const int p = win.n * R;
   const int nb = (p + kThreads - 1) / kThreads;
-  double* pq_parts = w.parts;                      // written by the forward reduction
-  double* rr_parts = w.parts + (size_t)w.nparts;  // written by init / update
+  const int np = w.nparts;
+  double* pq_parts = w.parts;                              // written by the forward reduction
+  double* rr_parts = w.parts + (size_t)B * np;            // written by init / update
   const double tol2 = tol * tol;
+  const size_t img = (size_t)N * N;
   hipError_t e;
-  hipLaunchKernelGGL(init_kernel, dim3(nb), dim3(kThreads), 0, st, p, nres, res, w.r, z, w.pd,
-                     rr_parts);
-  hipLaunchKernelGGL(init_scalars_kernel, dim3(1), dim3(kThreads), 0, st, rr_parts, nb, w.sc,
+  hipLaunchKernelGGL(init_kernel, dim3(nb, B), dim3(kThreads), 0, st, p, nres, w.pmax, np, res,
+                     res_stride, w.r, z, z_stride, w.pd, rr_parts);
+  hipLaunchKernelGGL(init_scalars_kernel, dim3(1, B), dim3(kThreads), 0, st, rr_parts, nb, np, w.sc,
                      w.ctl);
   if ((e = hipGetLastError()) != hipSuccess) return e;
+
+  BackArgs ba;
+  ba.geom = geom;
+  ba.N = N;
+  ba.R = R;
+  ba.B = B;
+  ba.ids = &win;
+  ba.v64 = w.pd;
+  ba.v_stride = w.pmax;
+  ba.out = w.u;
+  ba.xT = w.uT;
+  ba.img_stride = img;
+  ba.mode = 0;
+  ba.stop = w.ctl;
+  ba.stop_stride = kCtlCount;
+  FwdArgs fa;
+  fa.geom = geom;
+  fa.h_geom = h_geom;
+  fa.N = N;
+  fa.R = R;
+  fa.B = B;
+  fa.ids = &win;
+  fa.img = w.u;
+  fa.imgT = w.uT;
+  fa.img_stride = img;
+  fa.out64 = w.q;
+  fa.out_stride = w.pmax;
+  fa.partial = partial;
+  fa.pd = w.pd;
+  fa.pd_stride = w.pmax;
+  fa.lam = lam;
+  fa.dots = pq_parts;
+  fa.dots_stride = np;
+  fa.stop = w.ctl;
+  fa.stop_stride = kCtlCount;
 
   int enq = 0;     // iterations enqueued
   int chunks = 0;  // chunks enqueued
@@ -206,29 +266,26 @@ hipError_t pcg_solve(PcgWork& w, const AngleGeom* geom, const AngleGeom* h_geom,
     if (enq < max_iter) {
       const int todo = std::min(kChunk, max_iter - enq);
       for (int q = 0; q < todo; ++q, ++enq) {
-        double* sc_cur = w.sc + (enq & 1) * S_COUNT;
-        double* sc_nxt = w.sc + ((enq + 1) & 1) * S_COUNT;
+        double* sc_cur = w.sc + (size_t)(enq & 1) * B * S_COUNT;
+        double* sc_nxt = w.sc + (size_t)((enq + 1) & 1) * B * S_COUNT;
         if (prof->on && (e = prof->begin(K_BACK, st)) != hipSuccess) return e;
-        if ((e = launch_back(geom, N, R, win, nullptr, w.pd, w.u, nullptr, w.uT, nullptr, nullptr,
-                             0, w.ctl, nullptr, nullptr, st)) != hipSuccess)
-          return e;
+        if ((e = launch_back(ba, st)) != hipSuccess) return e;
         if (prof->on && (e = prof->end(st)) != hipSuccess) return e;
         if (prof->on && (e = prof->begin(K_FORWARD, st)) != hipSuccess) return e;
-        if ((e = launch_forward(geom, h_geom, N, R, win, w.u, w.uT, 0, nullptr, 0, nullptr, w.q,
-                                partial, w.pd, lam, pq_parts, w.ctl, st)) != hipSuccess)
-          return e;
+        // q = M u + lambda pd and partial <pd, q>, fused into the forward's reduction
+        if ((e = launch_forward(fa, st)) != hipSuccess) return e;
         if (prof->on && (e = prof->end(st)) != hipSuccess) return e;
         if (prof->on && (e = prof->begin(K_VEC, st)) != hipSuccess) return e;
-        hipLaunchKernelGGL(update_kernel, dim3(nb), dim3(kThreads), 0, st, p, sc_cur, pq_parts,
-                           w.pd, w.q, z, w.r, rr_parts, nb, w.ctl);
-        hipLaunchKernelGGL(direction_kernel, dim3(nb), dim3(kThreads), 0, st, p, sc_cur, sc_nxt,
-                           rr_parts, nb, tol2, w.r, w.pd, w.ctl);
+        hipLaunchKernelGGL(update_kernel, dim3(nb, B), dim3(kThreads), 0, st, p, w.pmax, nb, np,
+                           sc_cur, pq_parts, w.pd, w.q, z, z_stride, w.r, rr_parts, w.ctl);
+        hipLaunchKernelGGL(direction_kernel, dim3(nb, B), dim3(kThreads), 0, st, p, w.pmax, nb, np,
+                           sc_cur, sc_nxt, rr_parts, tol2, w.r, w.pd, w.ctl);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         if (prof->on && (e = prof->end(st)) != hipSuccess) return e;
       }
-      int* slot = w.h_ctl + (chunks & 1) * kCtlCount;
-      if ((e = hipMemcpyAsync(slot, w.ctl, kCtlCount * sizeof(int), hipMemcpyDeviceToHost, st)) !=
-          hipSuccess)
+      int* slot = w.h_ctl + (size_t)(chunks & 1) * B * kCtlCount;
+      if ((e = hipMemcpyAsync(slot, w.ctl, (size_t)B * kCtlCount * sizeof(int),
+                              hipMemcpyDeviceToHost, st)) != hipSuccess)
         return e;
       if ((e = hipEventRecord(w.ev[chunks & 1], st)) != hipSuccess) return e;
       ++chunks;
@@ -236,23 +293,34 @@ hipError_t pcg_solve(PcgWork& w, const AngleGeom* geom, const AngleGeom* h_geom,
     // keep one chunk in flight while the previous one is checked
     if (chunks - seen >= 2 || enq >= max_iter) {
       if ((e = hipEventSynchronize(w.ev[seen & 1])) != hipSuccess) return e;
-      const int* slot = w.h_ctl + (seen & 1) * kCtlCount;
+      const int* slot = w.h_ctl + (size_t)(seen & 1) * B * kCtlCount;
       ++seen;
-      if (slot[kCtlDone]) done = true;
+      bool all = true;
+      for (int b = 0; b < B; ++b) all = all && slot[b * kCtlCount + kCtlDone] != 0;
+      if (all) done = true;
       if (enq >= max_iter && seen == chunks) done = true;
     }
   }
   if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
   if (prof->on && (e = prof->harvest()) != hipSuccess) return e;
-  int ctl[kCtlCount];
-  if ((e = hipMemcpy(ctl, w.ctl, sizeof(ctl), hipMemcpyDeviceToHost)) != hipSuccess) return e;
-  if ((e = hipMemcpy(w.h_sc, w.sc, 2 * S_COUNT * sizeof(double), hipMemcpyDeviceToHost)) !=
+  std::vector<int> ctl((size_t)B * kCtlCount);
+  if ((e = hipMemcpy(ctl.data(), w.ctl, ctl.size() * sizeof(int), hipMemcpyDeviceToHost)) !=
       hipSuccess)
     return e;
-  const double* sc_last = w.h_sc + (ctl[kCtlIters] & 1) * S_COUNT;
-  *iters = ctl[kCtlIters];
-  const double bb = w.h_sc[S_BB];
-  *relres = (bb > 0.0) ? std::sqrt(sc_last[S_RR] / bb) : 0.0;
+  if ((e = hipMemcpy(w.h_sc, w.sc, (size_t)2 * B * S_COUNT * sizeof(double),
+                     hipMemcpyDeviceToHost)) != hipSuccess)
+    return e;
+  int it_max = 0;
+  double rel_max = 0.0;
+  for (int b = 0; b < B; ++b) {
+    const int it = ctl[b * kCtlCount + kCtlIters];
+    const double* last = w.h_sc + ((size_t)(it & 1) * B + b) * S_COUNT;
+    const double bb = w.h_sc[(size_t)b * S_COUNT + S_BB];
+    it_max = std::max(it_max, it);
+    if (bb > 0.0) rel_max = std::max(rel_max, std::sqrt(last[S_RR] / bb));
+  }
+  *iters = it_max;
+  *relres = rel_max;
   return hipSuccess;
 }
 

@@ -1,24 +1,35 @@
-// Matrix-free Joseph projectors for gfx950.
+// Matrix-free Joseph projectors for gfx950, for one slice or a batch of
+// slices that share the geometry.
+//
+// Both kernels work on a tile of BT slices (BT = 1, 2 or 4, a template
+// constant).  Global arrays stay slice-outer ([slice][N][N], [slice][list][R]);
+// inside a workgroup the BT slices are interleaved in LDS, so the position of
+// a ray in a row (forward) or the weights of a pixel (back) are computed once
+// and applied to all BT slices with one 4/8/16-byte LDS read.
 //
 // Forward (ray-driven, LDS bands): the image is cut into bands of H rows
 // (row-stepping angles) or H rows of its transpose (column-stepping angles,
-// i.e. H image columns), H*(N+4) floats <= 64 KB.  A workgroup owns a group
-// of consecutive bands and a chunk of angles of one orientation; it streams
-// its bands through LDS (zero-padded by two pixels on each side, so no
-// bounds checks in the inner loop) and every lane walks up to 8 rays across
-// them, interpolating linearly between the two pixels nearest the crossing
-// point (Joseph), accumulating in float64.  Per-group partial sums are
-// combined by a second kernel in a fixed order (deterministic, no atomics).
-// Workgroups are numbered so that each XCD works on a contiguous range of
-// band groups and its L2 holds only its slice of the image.
+// i.e. H image columns), H*(N+8)*BT floats <= 64 KB.  A workgroup owns a
+// group of consecutive bands, a chunk of angles of one orientation and a
+// slice tile; it streams its bands through LDS (zero-padded by four pixels on
+// each side, so no bounds checks in the inner loop), prefetching the next
+// band into registers, and every lane walks up to four rays across them,
+// interpolating linearly between the two pixels nearest the crossing point
+// (Joseph).  The ray position is a 32.32 fixed-point number; each wavefront
+// walks the union of its rays' row ranges (wave-uniform loop).  Per-group
+// partial sums are combined by a second kernel in a fixed order
+// (deterministic, no atomics), which also applies h/d, subtracts the data
+// and can fuse the CG tail.  Workgroups are numbered so that each XCD works
+// on a contiguous range of (slice tile, band group) pairs, and the grid is
+// sized to one round of two resident workgroups per CU.
 //
-// Back (pixel-driven gather): a workgroup owns a 16 x 64 pixel tile and
-// stages, for every angle of the list, the segment of ray values its tile
-// touches (scaled by h/d) in LDS; each lane gathers two rays per angle for
-// four consecutive pixels of a row.  No atomics; the optional fused update
-// writes x -= s, the transposed image, and per-workgroup float64 partial
-// norms.  Both projectors evaluate the same closed-form weights and agree to
-// float32 rounding of the weights.
+// Back (pixel-driven gather): a workgroup owns a 16 x 64 pixel tile of a
+// slice tile and stages, for every angle of the list, the segment of ray
+// values its tile touches (scaled by h/d) in LDS; each lane gathers two rays
+// per angle for four consecutive pixels of a row.  No atomics; the optional
+// fused update writes x -= s, the transposed image, bf16 shadows and
+// per-workgroup float64 partial norms.  Both projectors evaluate the same
+// closed-form weights and agree to float32 rounding of the weights.
 #include "slim_internal.h"
 #include "pcg.h"
 
@@ -28,24 +39,7 @@ namespace slim {
 
 namespace {
 
-// ---------------------------------------------------------------- forward
-constexpr int kFT = 512;      // threads per forward workgroup
-constexpr int kFItems = 4;    // rays per lane
-constexpr int kPad = 4;       // zero columns on each side of a band row (keeps rows 16B-aligned)
-// float4 per lane per band: H * N / 4 <= 16384 / 4 = 8 * kFT (eight prefetch registers)
-
-struct FwdPlan {
-  int n;          // entries (= output rows)
-  int n_row;      // entries 0..n_row-1 are row-stepping angles
-  int ch;         // angles per chunk
-  int n_chunks;   // row-stepping chunks first
-  int H, G;       // rows per band, bands per group
-  int n_groups;
-  int items;      // rays per lane (template argument of the band kernel)
-  short id[kMaxList];
-  short slot[kMaxList];
-};
-
+// ---------------------------------------------------------------- helpers
 // bf16 storage (upper half of a float32, round-to-nearest-even on store)
 __device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 __device__ __forceinline__ uint16_t f2bf(float f) {
@@ -65,6 +59,43 @@ __device__ __forceinline__ float4 load4(const uint16_t* p, int i) {
   return make_float4(__uint_as_float(u.x << 16), __uint_as_float(u.x & 0xffff0000u),
                      __uint_as_float(u.y << 16), __uint_as_float(u.y & 0xffff0000u));
 }
+__device__ __forceinline__ float comp(const float4& v, int k) {
+  return k == 0 ? v.x : (k == 1 ? v.y : (k == 2 ? v.z : v.w));
+}
+
+// BT interleaved slices: one LDS element of BT floats
+template <int BT> struct Lane;
+template <> struct Lane<1> {
+  typedef float T;
+  static __device__ __forceinline__ float get(const float& v, int) { return v; }
+};
+template <> struct Lane<2> {
+  typedef float2 T;
+  static __device__ __forceinline__ float get(const float2& v, int b) { return b ? v.y : v.x; }
+};
+template <> struct Lane<4> {
+  typedef float4 T;
+  static __device__ __forceinline__ float get(const float4& v, int b) { return comp(v, b); }
+};
+
+// ---------------------------------------------------------------- forward
+constexpr int kFT = 512;      // threads per forward workgroup
+constexpr int kFItems = 4;    // rays per lane (upper bound)
+constexpr int kPad = 4;       // zero columns on each side of a band row (keeps rows 16B-aligned)
+constexpr int kPF = 8;        // float4 prefetch registers per lane: H*N*BT/4 <= 8 * kFT
+
+struct FwdPlan {
+  int n;          // entries (= output rows)
+  int n_row;      // entries 0..n_row-1 are row-stepping angles
+  int ch;         // angles per chunk
+  int n_chunks;   // row-stepping chunks first
+  int H, G;       // rows per band, bands per group
+  int n_groups;
+  int n_tiles;    // slice tiles of BT slices
+  int items;      // rays per lane (template argument of the band kernel)
+  short id[kMaxList];
+  short slot[kMaxList];
+};
 
 __device__ __forceinline__ void chunk_range(const FwdPlan& pl, int c, int& e0, int& e1, bool& colm) {
   const int nrc = (pl.n_row + pl.ch - 1) / pl.ch;
@@ -79,28 +110,42 @@ __device__ __forceinline__ void chunk_range(const FwdPlan& pl, int c, int& e0, i
   }
 }
 
-template <int IT, typename IMG>
+template <int IT, int BT, typename IMG>
 __global__ __launch_bounds__(kFT, 2) void fwd_band_kernel(const AngleGeom* __restrict__ geom, int N,
-                                                          int R, FwdPlan pl,
+                                                          int R, FwdPlan pl, int B,
                                                           const IMG* __restrict__ img,
                                                           const IMG* __restrict__ imgT,
+                                                          size_t img_stride,
                                                           float* __restrict__ partial,
-                                                          const int* __restrict__ stop) {
-  if (stop && stop[kCtlDone]) return;
+                                                          const int* __restrict__ stop,
+                                                          int stop_stride) {
+  typedef typename Lane<BT>::T LT;
   extern __shared__ float band[];
   const int W = N + 2 * kPad;
-  // XCD-aware numbering: consecutive positions live on one XCD
-  const int total = pl.n_groups * pl.n_chunks;
+  // XCD-aware numbering: consecutive positions (same slice tile and band
+  // group, different angle chunks) live on one XCD
+  const int total = pl.n_groups * pl.n_chunks * pl.n_tiles;
   const int per_xcd = gridDim.x >> 3;
   const int pos = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
   if (pos >= total) return;
-  const int grp = pos / pl.n_chunks;
   const int chunk = pos % pl.n_chunks;
+  const int tg = pos / pl.n_chunks;
+  const int grp = tg % pl.n_groups;
+  const int tile = tg / pl.n_groups;
+  const int b0 = tile * BT;
+  const int nb = min(BT, B - b0);
+  if (stop) {
+    bool all = true;
+    for (int b = 0; b < nb; ++b) all = all && stop[(size_t)(b0 + b) * stop_stride + kCtlDone] != 0;
+    if (all) return;
+  }
   int e0, e1;
   bool colm;
   chunk_range(pl, chunk, e0, e1, colm);
   const int nitems = (e1 - e0) * R;
-  const IMG* src = colm ? imgT : img;
+  const IMG* src[BT];
+#pragma unroll
+  for (int b = 0; b < BT; ++b) src[b] = (colm ? imgT : img) + (size_t)(b0 + min(b, nb - 1)) * img_stride;
   const double half = 0.5 * (N - 1);
   const double off = 0.5 * (R - 1);
   const int kg = grp * pl.G * pl.H;
@@ -112,12 +157,13 @@ __global__ __launch_bounds__(kFT, 2) void fwd_band_kernel(const AngleGeom* __res
   // (a wave-uniform loop); a lane outside its own ray's range reads the zero
   // pads (its index is clamped into [0, W-2]) and adds nothing.
   int64_t P0[IT], S[IT];
-  double acc[IT];
+  double acc[IT][BT];
   int wlo[IT], whi[IT];
 #pragma unroll
   for (int q = 0; q < IT; ++q) {
     const int item = threadIdx.x + q * kFT;
-    acc[q] = 0.0;
+#pragma unroll
+    for (int b = 0; b < BT; ++b) acc[q][b] = 0.0;
     P0[q] = 0;  // index 0: pad column
     S[q] = 0;
     int klo = N, khi = -1;
@@ -156,38 +202,26 @@ __global__ __launch_bounds__(kFT, 2) void fwd_band_kernel(const AngleGeom* __res
     whi[q] = __builtin_amdgcn_readfirstlane(khi);
   }
 
-  {  // the zero pads are written once; band loads never touch them
-    for (int e = threadIdx.x; e < pl.H * 2 * kPad; e += kFT) {
-      const int r = e / (2 * kPad), c = e % (2 * kPad);
-      band[r * W + (c < kPad ? c : N + c)] = 0.f;
-    }
+  // the zero pads are written once; band loads never touch them
+  for (int e = threadIdx.x; e < pl.H * 2 * kPad * BT; e += kFT) {
+    const int r = e / (2 * kPad * BT), c = (e / BT) % (2 * kPad), b = e % BT;
+    band[(r * W + (c < kPad ? c : N + c)) * BT + b] = 0.f;
   }
-  // Bands are software-pipelined: the next band's rows are fetched into
-  // eight named registers (16-byte loads) while the current band is used.
+  // Bands are software-pipelined: the next band's rows (BT slices, 16-byte
+  // loads) are fetched into registers while the current band is used.
   const bool vec = (N & 3) == 0;
   const int n4 = N >> 2;
-  float4 pf0, pf1, pf2, pf3, pf4, pf5, pf6, pf7;
-#define SLIM_PF_LOAD(kb_)                                                       \
-  do {                                                                          \
-    const IMG* s4 = src + (size_t)(kb_) * N;                                    \
-    const int lim = min(pl.H, N - (kb_)) * n4 - 1;                               \
-    const int t0 = (int)threadIdx.x;                                            \
-    pf0 = load4(s4, min(t0 + 0 * kFT, lim));                                    \
-    pf1 = load4(s4, min(t0 + 1 * kFT, lim));                                    \
-    pf2 = load4(s4, min(t0 + 2 * kFT, lim));                                    \
-    pf3 = load4(s4, min(t0 + 3 * kFT, lim));                                    \
-    pf4 = load4(s4, min(t0 + 4 * kFT, lim));                                    \
-    pf5 = load4(s4, min(t0 + 5 * kFT, lim));                                    \
-    pf6 = load4(s4, min(t0 + 6 * kFT, lim));                                    \
-    pf7 = load4(s4, min(t0 + 7 * kFT, lim));                                    \
-  } while (0)
-#define SLIM_PF_STORE1(u, v)                                                    \
-  do {                                                                          \
-    const int e = (int)threadIdx.x + (u) * kFT;                                 \
-    const int r = e / n4, c4 = e - r * n4;                                      \
-    if (e < lim) *reinterpret_cast<float4*>(band + r * W + kPad + 4 * c4) = (v); \
-  } while (0)
-  if (vec && kg < N) SLIM_PF_LOAD(kg);
+  constexpr int U = kPF / BT;  // 4-pixel chunks per lane per band
+  float4 pf[kPF];
+  if (vec && kg < N) {
+    const int lim = min(pl.H, N - kg) * n4 - 1;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = min((int)threadIdx.x + u * kFT, lim);
+#pragma unroll
+      for (int b = 0; b < BT; ++b) pf[u * BT + b] = load4(src[b] + (size_t)kg * N, e);
+    }
+  }
   for (int bb = 0; bb < pl.G; ++bb) {
     const int kb = kg + bb * pl.H;
     if (kb >= N) break;
@@ -195,66 +229,93 @@ __global__ __launch_bounds__(kFT, 2) void fwd_band_kernel(const AngleGeom* __res
     __syncthreads();
     if (vec) {
       const int lim = hb * n4;
-      SLIM_PF_STORE1(0, pf0);
-      SLIM_PF_STORE1(1, pf1);
-      SLIM_PF_STORE1(2, pf2);
-      SLIM_PF_STORE1(3, pf3);
-      SLIM_PF_STORE1(4, pf4);
-      SLIM_PF_STORE1(5, pf5);
-      SLIM_PF_STORE1(6, pf6);
-      SLIM_PF_STORE1(7, pf7);
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int e = (int)threadIdx.x + u * kFT;
+        const int r = e / n4, c4 = e - r * n4;
+        if (e < lim) {
+          float* dst = band + (size_t)(r * W + kPad + 4 * c4) * BT;
+          if (BT == 1) {
+            *reinterpret_cast<float4*>(dst) = pf[u];
+          } else {
+            // interleave: pixel k of the chunk holds the BT slices' values
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+#pragma unroll
+              for (int b = 0; b < BT; ++b) dst[k * BT + b] = comp(pf[u * BT + b], k);
+            }
+          }
+        }
+      }
     } else {
-      for (int r = 0; r < hb; ++r)
-        for (int c = threadIdx.x; c < N; c += kFT)
-          band[r * W + kPad + c] = tof(src[(size_t)(kb + r) * N + c]);
+      for (int e = threadIdx.x; e < hb * N * BT; e += kFT) {
+        const int r = e / (N * BT), c = (e / BT) % N, b = e % BT;
+        band[(r * W + kPad + c) * BT + b] = tof(src[b][(size_t)(kb + r) * N + c]);
+      }
     }
     __syncthreads();
     const int kbn = kb + pl.H;
-    if (vec && bb + 1 < pl.G && kbn < N) SLIM_PF_LOAD(kbn);
+    if (vec && bb + 1 < pl.G && kbn < N) {
+      const int lim = min(pl.H, N - kbn) * n4 - 1;
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int e = min((int)threadIdx.x + u * kFT, lim);
+#pragma unroll
+        for (int b = 0; b < BT; ++b) pf[u * BT + b] = load4(src[b] + (size_t)kbn * N, e);
+      }
+    }
+    const LT* bandv = reinterpret_cast<const LT*>(band);
 #pragma unroll
     for (int q = 0; q < IT; ++q) {
       const int k0 = max(wlo[q], kb), k1 = min(whi[q], kb + hb - 1);
       if (k0 > k1) continue;  // wave-uniform
       int64_t P = P0[q] + (int64_t)k0 * S[q];
-      const float* row = band + (k0 - kb) * W;
-      float a32 = 0.f;
+      const LT* row = bandv + (k0 - kb) * W;
+      float a32[BT];
+#pragma unroll
+      for (int b = 0; b < BT; ++b) a32[b] = 0.f;
       for (int k = k0; k <= k1; ++k) {
         const int qi = min(max((int)(P >> 32), 0), W - 2);
         const float phi = (float)(uint32_t)P * 2.3283064365386963e-10f;
-        const float v0 = row[qi], v1 = row[qi + 1];
-        a32 += fmaf(phi, v1 - v0, v0);
+        const LT v0 = row[qi], v1 = row[qi + 1];
+#pragma unroll
+        for (int b = 0; b < BT; ++b) {
+          const float a = Lane<BT>::get(v0, b), c = Lane<BT>::get(v1, b);
+          a32[b] += fmaf(phi, c - a, a);
+        }
         P += S[q];
         row += W;
       }
-      acc[q] += (double)a32;
+#pragma unroll
+      for (int b = 0; b < BT; ++b) acc[q][b] += (double)a32[b];
     }
   }
-#undef SLIM_PF_LOAD
-#undef SLIM_PF_STORE1
 #pragma unroll
   for (int q = 0; q < IT; ++q) {
     const int item = threadIdx.x + q * kFT;
     if (item < nitems) {
       const int e = e0 + item / R;
       const int t = item % R;
-      partial[((size_t)grp * pl.n + pl.slot[e]) * R + t] = (float)acc[q];
+#pragma unroll
+      for (int b = 0; b < BT; ++b)
+        if (b < nb)
+          partial[(((size_t)(b0 + b) * pl.n_groups + grp) * pl.n + pl.slot[e]) * R + t] =
+              (float)acc[q][b];
     }
   }
 }
 
-// out[s][t] = (h/d) sum_groups partial - sub; optional CG tail q = out + lam*pd
-// with per-workgroup partial dot <pd, q>.
+// out[s][t] = (h/d) sum_groups partial - sub for every slice (blockIdx.y);
+// optional CG tail q = out + lam*pd with per-workgroup partial dots <pd, q>.
 template <typename SUB>
-__global__ __launch_bounds__(256) void fwd_reduce_kernel(const AngleGeom* __restrict__ geom, int R,
-                                                         AngleList ids, int n_groups,
-                                                         const float* __restrict__ partial,
-                                                         const SUB* __restrict__ sub,
-                                                         float* __restrict__ out32,
-                                                         double* __restrict__ out64,
-                                                         const double* __restrict__ pd, double lam,
-                                                         double* __restrict__ dots,
-                                                         const int* __restrict__ stop) {
-  if (stop && stop[kCtlDone]) return;
+__global__ __launch_bounds__(256) void fwd_reduce_kernel(
+    const AngleGeom* __restrict__ geom, int R, AngleList ids, int n_groups,
+    const float* __restrict__ partial, const SUB* __restrict__ sub, size_t sub_stride,
+    float* __restrict__ out32, double* __restrict__ out64, size_t out_stride,
+    const double* __restrict__ pd, size_t pd_stride, double lam, double* __restrict__ dots,
+    size_t dots_stride, const int* __restrict__ stop, int stop_stride) {
+  const int sl = blockIdx.y;
+  if (stop && stop[(size_t)sl * stop_stride + kCtlDone]) return;
   __shared__ double sh[4];
   const int o = blockIdx.x * 256 + threadIdx.x;
   const int n = ids.n * R;
@@ -262,8 +323,8 @@ __global__ __launch_bounds__(256) void fwd_reduce_kernel(const AngleGeom* __rest
   if (o < n) {
     const int s = o / R, t = o % R;
     const int ang = ids.id[s];
-    const float* pp = partial + (size_t)s * R + t;
     const size_t gs = (size_t)ids.n * R;
+    const float* pp = partial + (size_t)sl * n_groups * gs + (size_t)s * R + t;
     double v = 0.0;
     int g = 0;
     for (; g + 4 <= n_groups; g += 4) {
@@ -274,78 +335,55 @@ __global__ __launch_bounds__(256) void fwd_reduce_kernel(const AngleGeom* __rest
       v += (double)e;
     }
     for (; g < n_groups; ++g) v += (double)pp[g * gs];
-    const double hd = (double)geom[ang].hd;
-    v *= hd;
-    if (sub) v -= (double)tof(sub[(size_t)ang * R + t]);
+    v *= (double)geom[ang].hd;
+    if (sub) v -= (double)tof(sub[(size_t)sl * sub_stride + (size_t)ang * R + t]);
     if (pd) {
-      v = fma(lam, pd[o], v);
-      d = pd[o] * v;
+      const double pv = pd[(size_t)sl * pd_stride + o];
+      v = fma(lam, pv, v);
+      d = pv * v;
     }
-    if (out32) out32[o] = (float)v;
-    if (out64) out64[o] = v;
+    if (out32) out32[(size_t)sl * out_stride + o] = (float)v;
+    if (out64) out64[(size_t)sl * out_stride + o] = v;
   }
   if (dots) {
     for (int w = 32; w > 0; w >>= 1) d += __shfl_down(d, w, 64);
     if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = d;
     __syncthreads();
-    if (threadIdx.x == 0) dots[blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
+    if (threadIdx.x == 0) dots[(size_t)sl * dots_stride + blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
   }
-}
-
-// Launch plan: angles grouped by orientation into chunks, image bands into
-// groups, with n_chunks * n_groups <= 2 * (number of CUs) so that a launch is
-// a single round of resident workgroups (two per CU, bounded by LDS).
-FwdPlan make_plan(const AngleGeom* h_geom, int N, int R, const AngleList& ids, int n_cu) {
-  FwdPlan pl;
-  pl.n = ids.n;
-  int k = 0;
-  for (int pass = 0; pass < 2; ++pass)
-    for (int s = 0; s < ids.n; ++s)
-      if ((h_geom[ids.id[s]].colmajor != 0) == (pass == 1)) {
-        pl.id[k] = (short)ids.id[s];
-        pl.slot[k] = (short)s;
-        ++k;
-      }
-  pl.n_row = 0;
-  for (int s = 0; s < ids.n; ++s) pl.n_row += h_geom[ids.id[s]].colmajor ? 0 : 1;
-  pl.ch = std::max(1, std::min(kFItems * kFT / R, ids.n));
-  pl.items = (pl.ch * R + kFT - 1) / kFT;
-  pl.n_chunks = (pl.n_row + pl.ch - 1) / pl.ch + (ids.n - pl.n_row + pl.ch - 1) / pl.ch;
-  pl.H = std::max(1, std::min(N, 16384 / (N + 2 * kPad)));
-  const int nbands = (N + pl.H - 1) / pl.H;
-  const int slots = 2 * std::max(1, n_cu);
-  int want = std::max(1, std::min(slots / pl.n_chunks, nbands));
-  pl.G = (nbands + want - 1) / want;
-  pl.n_groups = (nbands + pl.G - 1) / pl.G;
-  return pl;
 }
 
 // ------------------------------------------------------------------- back
 constexpr int kBH = 16, kBW = 64;   // tile rows, columns
 constexpr int kBPX = 4;             // consecutive pixels per lane
-constexpr int kBAng = 64;           // angles staged per pass
-constexpr int kSeg = 72;            // LDS stride of one angle's ray segment
+constexpr int kSegFloats = 64 * 72; // LDS floats of staged ray segments
+constexpr int kSeg = 72;            // rays of one angle's segment
 
 __device__ __forceinline__ double wave_sum(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
   return v;
 }
 
-template <typename VT>
-__global__ __launch_bounds__(256) void back_kernel(const AngleGeom* __restrict__ geom, int N, int R,
-                                                   AngleList ids, const VT* __restrict__ v,
-                                                   float* __restrict__ out, float* __restrict__ x,
-                                                   float* __restrict__ xT,
-                                                   const float* __restrict__ x_true,
-                                                   double* __restrict__ partials, int mode,
-                                                   const int* __restrict__ stop,
-                                                   uint16_t* __restrict__ xs,
-                                                   uint16_t* __restrict__ xsT) {
-  if (stop && stop[kCtlDone]) return;
-  __shared__ float seg[kBAng * kSeg];
-  __shared__ int tmin[kBAng];
+template <typename VT, int BT>
+__global__ __launch_bounds__(256) void back_kernel(
+    const AngleGeom* __restrict__ geom, int N, int R, AngleList ids, int B,
+    const VT* __restrict__ v, size_t v_stride, float* __restrict__ out, float* __restrict__ x,
+    float* __restrict__ xT, const float* __restrict__ x_true, size_t img_stride,
+    double* __restrict__ partials, int mode, const int* __restrict__ stop, int stop_stride,
+    uint16_t* __restrict__ xs, uint16_t* __restrict__ xsT) {
+  typedef typename Lane<BT>::T LT;
+  constexpr int kAng = kSegFloats / (kSeg * BT);   // angles staged per pass
+  const int b0 = blockIdx.z * BT;
+  const int nb = min(BT, B - b0);
+  if (stop) {
+    bool all = true;
+    for (int b = 0; b < nb; ++b) all = all && stop[(size_t)(b0 + b) * stop_stride + kCtlDone] != 0;
+    if (all) return;
+  }
+  __shared__ float seg[kSegFloats];
+  __shared__ int tmin[kAng];
   __shared__ float tile[kBH][kBW + 1];
-  __shared__ double wred[4][3];
+  __shared__ double wred[4][3 * BT];
   const int tx = threadIdx.x & 15;       // 16 lanes x 4 pixels = 64 columns
   const int ty = threadIdx.x >> 4;       // 16 rows
   const int i0 = blockIdx.y * kBH, j0 = blockIdx.x * kBW;
@@ -360,9 +398,13 @@ __global__ __launch_bounds__(256) void back_kernel(const AngleGeom* __restrict__
   // nominal tile corners (pixel centres) bound every pixel the lanes evaluate
   const double ci0 = (double)i0 - half, ci1 = (double)(i0 + kBH - 1) - half;
   const double cj0 = (double)j0 - half, cj1 = (double)(j0 + kBW - 1) - half;
-  float s[kBPX] = {0.f, 0.f, 0.f, 0.f};
-  for (int a0 = 0; a0 < ids.n; a0 += kBAng) {
-    const int na = min(kBAng, ids.n - a0);
+  float s[kBPX][BT];
+#pragma unroll
+  for (int q = 0; q < kBPX; ++q)
+#pragma unroll
+    for (int b = 0; b < BT; ++b) s[q][b] = 0.f;
+  for (int a0 = 0; a0 < ids.n; a0 += kAng) {
+    const int na = min(kAng, ids.n - a0);
     __syncthreads();
     if ((int)threadIdx.x < na) {
       const AngleGeom g = geom[ids.id[a0 + threadIdx.x]];
@@ -371,18 +413,20 @@ __global__ __launch_bounds__(256) void back_kernel(const AngleGeom* __restrict__
       tmin[threadIdx.x] = (int)floor(fmin(fmin(t00, t01), fmin(t10, t11))) - 1;
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < na * kSeg; e += 256) {
-      const int a = e / kSeg, u = e % kSeg;
+    for (int e = threadIdx.x; e < na * kSeg * BT; e += 256) {
+      const int a = e / (kSeg * BT), u = (e / BT) % kSeg, b = e % BT;
       const int t = tmin[a] + u - kTOff;
-      const AngleGeom& g = geom[ids.id[a0 + a]];
-      seg[e] = (t >= 0 && t < R) ? g.hd * (float)v[(size_t)(a0 + a) * R + t] : 0.f;
+      const float hd = geom[ids.id[a0 + a]].hd;
+      const VT* vb = v + (size_t)(b0 + min(b, nb - 1)) * v_stride;
+      seg[e] = (t >= 0 && t < R) ? hd * (float)vb[(size_t)(a0 + a) * R + t] : 0.f;
     }
     __syncthreads();
     if (i < N) {
+      const LT* segv = reinterpret_cast<const LT*>(seg);
       for (int a = 0; a < na; ++a) {
         const AngleGeom g = geom[ids.id[a0 + a]];
         const double Ti = fma(ii, g.s, off);
-        const float* sa = seg + a * kSeg - tmin[a];
+        const LT* sa = segv + a * kSeg - tmin[a];
         const float invd = g.invd, c1 = 1.f - g.invd;
 #pragma unroll
         for (int q = 0; q < kBPX; ++q) {
@@ -391,89 +435,110 @@ __global__ __launch_bounds__(256) void back_kernel(const AngleGeom* __restrict__
           const float f = (float)(t - (double)t0);     // distance to ray t0
           const float w0 = fmaxf(0.f, fmaf(-f, invd, 1.f));   // 1 - f/d
           const float w1 = fmaxf(0.f, fmaf(f, invd, c1));     // 1 - (1-f)/d
-          s[q] = fmaf(w0, sa[t0], fmaf(w1, sa[t0 + 1], s[q]));
+          const LT v0 = sa[t0], v1 = sa[t0 + 1];
+#pragma unroll
+          for (int b = 0; b < BT; ++b)
+            s[q][b] = fmaf(w0, Lane<BT>::get(v0, b), fmaf(w1, Lane<BT>::get(v1, b), s[q][b]));
         }
       }
     }
   }
-  const bool full = (i < N) && (jb + kBPX - 1 < N);
+  const bool full = (i < N) && (jb + kBPX - 1 < N) && ((N & 3) == 0);
+  const size_t prow = (size_t)i * N + jb;
   if (mode == 0) {
-    if (full && (N & 3) == 0) {
-      *reinterpret_cast<float4*>(out + (size_t)i * N + jb) = make_float4(s[0], s[1], s[2], s[3]);
-    } else if (i < N) {
-      for (int q = 0; q < kBPX; ++q)
-        if (jb + q < N) out[(size_t)i * N + jb + q] = s[q];
-    }
-    if (xT) {
-      __syncthreads();
 #pragma unroll
-      for (int q = 0; q < kBPX; ++q) tile[ty][kBPX * tx + q] = s[q];
-      __syncthreads();
-      for (int e = threadIdx.x; e < kBH * kBW; e += 256) {
-        const int jl = e / kBH, il = e % kBH;
-        if (j0 + jl < N && i0 + il < N) xT[(size_t)(j0 + jl) * N + i0 + il] = tile[il][jl];
+    for (int b = 0; b < BT; ++b) {
+      if (b >= nb) break;
+      float* ob = out + (size_t)(b0 + b) * img_stride;
+      if (full) {
+        *reinterpret_cast<float4*>(ob + prow) = make_float4(s[0][b], s[1][b], s[2][b], s[3][b]);
+      } else if (i < N) {
+        for (int q = 0; q < kBPX; ++q)
+          if (jb + q < N) ob[prow + q] = s[q][b];
+      }
+      if (xT) {  // transposed copy of out through LDS
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < kBPX; ++q) tile[ty][kBPX * tx + q] = s[q][b];
+        __syncthreads();
+        float* tb = xT + (size_t)(b0 + b) * img_stride;
+        for (int e = threadIdx.x; e < kBH * kBW; e += 256) {
+          const int jl = e / kBH, il = e % kBH;
+          if (j0 + jl < N && i0 + il < N) tb[(size_t)(j0 + jl) * N + i0 + il] = tile[il][jl];
+        }
       }
     }
     return;
   }
-  double ss = 0.0, xx = 0.0, ee = 0.0;
-  float xn[kBPX] = {0.f, 0.f, 0.f, 0.f};
-  if (i < N) {
+  double nrm[BT][3];
 #pragma unroll
-    for (int q = 0; q < kBPX; ++q) {
-      if (jb + q < N) {
-        const size_t p = (size_t)i * N + jb + q;
-        xn[q] = x[p] - s[q];
-        x[p] = xn[q];
-        if (xs) xs[p] = f2bf(xn[q]);
-        ss += (double)s[q] * (double)s[q];
-        xx += (double)xn[q] * (double)xn[q];
-        if (x_true) {
-          const double e = (double)xn[q] - (double)x_true[p];
-          ee += e * e;
+  for (int b = 0; b < BT; ++b) {
+    nrm[b][0] = nrm[b][1] = nrm[b][2] = 0.0;
+    float xn[kBPX] = {0.f, 0.f, 0.f, 0.f};
+    if (b < nb) {
+      const size_t so = (size_t)(b0 + b) * img_stride;
+      if (i < N) {
+#pragma unroll
+        for (int q = 0; q < kBPX; ++q) {
+          if (jb + q < N) {
+            const size_t p = so + prow + q;
+            xn[q] = x[p] - s[q][b];
+            x[p] = xn[q];
+            if (xs) xs[p] = f2bf(xn[q]);
+            nrm[b][0] += (double)s[q][b] * (double)s[q][b];
+            nrm[b][1] += (double)xn[q] * (double)xn[q];
+            if (x_true) {
+              const double e = (double)xn[q] - (double)x_true[p];
+              nrm[b][2] += e * e;
+            }
+          }
+        }
+      }
+      if (xT || xsT) {
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < kBPX; ++q) tile[ty][kBPX * tx + q] = xn[q];
+        __syncthreads();
+        for (int e = threadIdx.x; e < kBH * kBW; e += 256) {
+          const int jl = e / kBH, il = e % kBH;
+          if (j0 + jl < N && i0 + il < N) {
+            const size_t o = so + (size_t)(j0 + jl) * N + i0 + il;
+            if (xT) xT[o] = tile[il][jl];
+            if (xsT) xsT[o] = f2bf(tile[il][jl]);
+          }
         }
       }
     }
   }
-  if (xT || xsT) {
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < kBPX; ++q) tile[ty][kBPX * tx + q] = xn[q];
-    __syncthreads();
-    for (int e = threadIdx.x; e < kBH * kBW; e += 256) {
-      const int jl = e / kBH, il = e % kBH;
-      if (j0 + jl < N && i0 + il < N) {
-        const size_t o = (size_t)(j0 + jl) * N + i0 + il;
-        if (xT) xT[o] = tile[il][jl];
-        if (xsT) xsT[o] = f2bf(tile[il][jl]);
-      }
-    }
-  }
-  ss = wave_sum(ss);
-  xx = wave_sum(xx);
-  ee = wave_sum(ee);
   const int w = threadIdx.x >> 6;
-  if ((threadIdx.x & 63) == 0) {
-    wred[w][0] = ss;
-    wred[w][1] = xx;
-    wred[w][2] = ee;
-  }
+#pragma unroll
+  for (int b = 0; b < BT; ++b)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const double r = wave_sum(nrm[b][k]);
+      if ((threadIdx.x & 63) == 0) wred[w][3 * b + k] = r;
+    }
   __syncthreads();
-  if (threadIdx.x < 3) {
+  const int nwg = gridDim.x * gridDim.y;
+  const int wg = blockIdx.y * gridDim.x + blockIdx.x;
+  if ((int)threadIdx.x < 3 * nb) {
+    const int b = threadIdx.x / 3, k = threadIdx.x % 3;
     const double r = wred[0][threadIdx.x] + wred[1][threadIdx.x] + wred[2][threadIdx.x] +
                      wred[3][threadIdx.x];
-    partials[(size_t)3 * (blockIdx.y * gridDim.x + blockIdx.x) + threadIdx.x] = r;
+    partials[((size_t)(b0 + b) * nwg + wg) * 3 + k] = r;
   }
 }
 
+// out[3*slice + k] = sum over n partial 3-vectors of the slice (fixed order)
 __global__ __launch_bounds__(256) void reduce3_kernel(const double* __restrict__ partials, int n,
                                                       double* __restrict__ out) {
   __shared__ double red[3][256];
+  const double* p = partials + (size_t)blockIdx.x * n * 3;
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
   for (int k = threadIdx.x; k < n; k += 256) {
-    a0 += partials[3 * (size_t)k + 0];
-    a1 += partials[3 * (size_t)k + 1];
-    a2 += partials[3 * (size_t)k + 2];
+    a0 += p[3 * (size_t)k + 0];
+    a1 += p[3 * (size_t)k + 1];
+    a2 += p[3 * (size_t)k + 2];
   }
   red[0][threadIdx.x] = a0;
   red[1][threadIdx.x] = a1;
@@ -487,42 +552,38 @@ __global__ __launch_bounds__(256) void reduce3_kernel(const double* __restrict__
     }
     __syncthreads();
   }
-  if (threadIdx.x < 3) out[threadIdx.x] = red[threadIdx.x][0];
+  if (threadIdx.x < 3) out[3 * (size_t)blockIdx.x + threadIdx.x] = red[threadIdx.x][0];
 }
 
 constexpr int kTile = 16;
 
-// dst = src^T (float32, optional); bf16 copies of src and of src^T (optional)
+// dst = src^T (float32, optional); bf16 copies of src and of src^T (optional);
+// blockIdx.z = slice
 __global__ __launch_bounds__(256) void transpose_kernel(const float* __restrict__ src,
                                                         float* __restrict__ dst, int N,
+                                                        size_t stride,
                                                         uint16_t* __restrict__ bs,
                                                         uint16_t* __restrict__ bsT) {
   __shared__ float t[kTile][kTile + 1];
+  const size_t so = (size_t)blockIdx.z * stride;
   const int tx = threadIdx.x & (kTile - 1), ty = threadIdx.x / kTile;
   const int i = blockIdx.y * kTile + ty, j = blockIdx.x * kTile + tx;
   if (i < N && j < N) {
-    const float v = src[(size_t)i * N + j];
+    const float v = src[so + (size_t)i * N + j];
     t[ty][tx] = v;
-    if (bs) bs[(size_t)i * N + j] = f2bf(v);
+    if (bs) bs[so + (size_t)i * N + j] = f2bf(v);
   }
   __syncthreads();
   const int jt = blockIdx.x * kTile + ty, it = blockIdx.y * kTile + tx;
   if (jt < N && it < N) {
-    if (dst) dst[(size_t)jt * N + it] = t[tx][ty];
-    if (bsT) bsT[(size_t)jt * N + it] = f2bf(t[tx][ty]);
+    if (dst) dst[so + (size_t)jt * N + it] = t[tx][ty];
+    if (bsT) bsT[so + (size_t)jt * N + it] = f2bf(t[tx][ty]);
   }
 }
 
 }  // namespace
 
-size_t forward_partial_floats(int N, int R, int max_list) {
-  const int H = std::max(1, std::min(N, 16384 / (N + 2 * kPad)));
-  const size_t nbands = (size_t)(N + H - 1) / H;
-  return nbands * (size_t)max_list * (size_t)R;
-}
-
-int forward_dot_parts(int n_out) { return (n_out + 255) / 256; }
-
+// ---------------------------------------------------------------- launchers
 static int g_num_cu = 0;
 
 static int num_cu() {
@@ -537,83 +598,156 @@ static int num_cu() {
   return g_num_cu;
 }
 
-template <typename IMG>
+int slice_tile(int B) { return B >= 4 ? 4 : (B >= 2 ? 2 : 1); }
+
+// Launch plan: angles grouped by orientation into chunks, slices into tiles of
+// BT, image bands into groups, with chunks * tiles * groups <= 2 * (number of
+// CUs) where possible, so that a launch is one round of resident workgroups
+// (two per CU, bounded by LDS).
+static FwdPlan make_plan(const AngleGeom* h_geom, int N, int R, const AngleList& ids, int B) {
+  FwdPlan pl;
+  pl.n = ids.n;
+  int k = 0;
+  for (int pass = 0; pass < 2; ++pass)
+    for (int s = 0; s < ids.n; ++s)
+      if ((h_geom[ids.id[s]].colmajor != 0) == (pass == 1)) {
+        pl.id[k] = (short)ids.id[s];
+        pl.slot[k] = (short)s;
+        ++k;
+      }
+  pl.n_row = 0;
+  for (int s = 0; s < ids.n; ++s) pl.n_row += h_geom[ids.id[s]].colmajor ? 0 : 1;
+  const int BT = slice_tile(B);
+  const int max_items = BT == 4 ? 3 : kFItems;  // register budget with BT accumulators
+  pl.ch = std::max(1, std::min(max_items * kFT / R, ids.n));
+  pl.items = std::min(kFItems, (pl.ch * R + kFT - 1) / kFT);
+  pl.n_chunks = (pl.n_row + pl.ch - 1) / pl.ch + (ids.n - pl.n_row + pl.ch - 1) / pl.ch;
+  pl.n_tiles = (B + BT - 1) / BT;
+  pl.H = std::max(1, std::min(N, 16384 / ((N + 2 * kPad) * BT)));
+  const int nbands = (N + pl.H - 1) / pl.H;
+  const int slots = 2 * num_cu();
+  int want = std::max(1, std::min(slots / (pl.n_chunks * pl.n_tiles), nbands));
+  pl.G = (nbands + want - 1) / want;
+  pl.n_groups = (nbands + pl.G - 1) / pl.G;
+  return pl;
+}
+
+size_t forward_partial_floats(const AngleGeom* h_geom, int N, int R, const AngleList& ids, int B) {
+  const FwdPlan pl = make_plan(h_geom, N, R, ids, B);
+  return (size_t)B * pl.n_groups * ids.n * R;
+}
+
+int forward_dot_parts(int n_out) { return (n_out + 255) / 256; }
+
+template <int BT, typename IMG>
 static void launch_band(int items, dim3 grid, size_t lds, hipStream_t st, const AngleGeom* geom,
-                        int N, int R, const FwdPlan& pl, const IMG* img, const IMG* imgT,
-                        float* partial, const int* stop) {
+                        int N, int R, const FwdPlan& pl, int B, const IMG* img, const IMG* imgT,
+                        size_t stride, float* partial, const int* stop, int stop_stride) {
   switch (items) {
     case 1:
-      hipLaunchKernelGGL((fwd_band_kernel<1, IMG>), grid, dim3(kFT), lds, st, geom, N, R, pl, img,
-                         imgT, partial, stop);
+      hipLaunchKernelGGL((fwd_band_kernel<1, BT, IMG>), grid, dim3(kFT), lds, st, geom, N, R, pl, B,
+                         img, imgT, stride, partial, stop, stop_stride);
       break;
     case 2:
-      hipLaunchKernelGGL((fwd_band_kernel<2, IMG>), grid, dim3(kFT), lds, st, geom, N, R, pl, img,
-                         imgT, partial, stop);
+      hipLaunchKernelGGL((fwd_band_kernel<2, BT, IMG>), grid, dim3(kFT), lds, st, geom, N, R, pl, B,
+                         img, imgT, stride, partial, stop, stop_stride);
       break;
     case 3:
-      hipLaunchKernelGGL((fwd_band_kernel<3, IMG>), grid, dim3(kFT), lds, st, geom, N, R, pl, img,
-                         imgT, partial, stop);
+      hipLaunchKernelGGL((fwd_band_kernel<3, BT, IMG>), grid, dim3(kFT), lds, st, geom, N, R, pl, B,
+                         img, imgT, stride, partial, stop, stop_stride);
       break;
     default:
-      hipLaunchKernelGGL((fwd_band_kernel<4, IMG>), grid, dim3(kFT), lds, st, geom, N, R, pl, img,
-                         imgT, partial, stop);
+      hipLaunchKernelGGL((fwd_band_kernel<4, BT, IMG>), grid, dim3(kFT), lds, st, geom, N, R, pl, B,
+                         img, imgT, stride, partial, stop, stop_stride);
       break;
   }
 }
 
-hipError_t launch_forward(const AngleGeom* geom, const AngleGeom* h_geom, int N, int R,
-                          const AngleList& ids, const void* img, const void* imgT, int img_bf16,
-                          const void* sub, int sub_bf16, float* out32, double* out64,
-                          float* partial, const double* pd, double lam, double* dots,
-                          const int* stop, hipStream_t st) {
-  if (ids.n <= 0) return hipSuccess;
-  const FwdPlan pl = make_plan(h_geom, N, R, ids, num_cu());
-  const int total = pl.n_groups * pl.n_chunks;
+template <typename IMG>
+static void launch_band_bt(int BT, int items, dim3 grid, size_t lds, hipStream_t st,
+                           const AngleGeom* geom, int N, int R, const FwdPlan& pl, int B,
+                           const IMG* img, const IMG* imgT, size_t stride, float* partial,
+                           const int* stop, int stop_stride) {
+  if (BT == 4)
+    launch_band<4>(items, grid, lds, st, geom, N, R, pl, B, img, imgT, stride, partial, stop,
+                   stop_stride);
+  else if (BT == 2)
+    launch_band<2>(items, grid, lds, st, geom, N, R, pl, B, img, imgT, stride, partial, stop,
+                   stop_stride);
+  else
+    launch_band<1>(items, grid, lds, st, geom, N, R, pl, B, img, imgT, stride, partial, stop,
+                   stop_stride);
+}
+
+hipError_t launch_forward(const FwdArgs& a, hipStream_t st) {
+  if (a.ids->n <= 0) return hipSuccess;
+  const FwdPlan pl = make_plan(a.h_geom, a.N, a.R, *a.ids, a.B);
+  const int BT = slice_tile(a.B);
+  const int total = pl.n_groups * pl.n_chunks * pl.n_tiles;
   const int nwg = (total + 7) / 8 * 8;
-  const size_t lds = (size_t)pl.H * (N + 2 * kPad) * sizeof(float);
-  if (img_bf16)
-    launch_band(pl.items, dim3(nwg), lds, st, geom, N, R, pl, (const uint16_t*)img,
-                (const uint16_t*)imgT, partial, stop);
+  const size_t lds = (size_t)pl.H * (a.N + 2 * kPad) * BT * sizeof(float);
+  if (a.img_bf16)
+    launch_band_bt(BT, pl.items, dim3(nwg), lds, st, a.geom, a.N, a.R, pl, a.B,
+                   (const uint16_t*)a.img, (const uint16_t*)a.imgT, a.img_stride, a.partial,
+                   a.stop, a.stop_stride);
   else
-    launch_band(pl.items, dim3(nwg), lds, st, geom, N, R, pl, (const float*)img,
-                (const float*)imgT, partial, stop);
-  const int n = ids.n * R;
-  const dim3 rg((n + 255) / 256);
-  if (sub_bf16)
-    hipLaunchKernelGGL(fwd_reduce_kernel<uint16_t>, rg, dim3(256), 0, st, geom, R, ids, pl.n_groups,
-                       partial, (const uint16_t*)sub, out32, out64, pd, lam, dots, stop);
+    launch_band_bt(BT, pl.items, dim3(nwg), lds, st, a.geom, a.N, a.R, pl, a.B,
+                   (const float*)a.img, (const float*)a.imgT, a.img_stride, a.partial, a.stop,
+                   a.stop_stride);
+  const int n = a.ids->n * a.R;
+  const dim3 rg((n + 255) / 256, a.B);
+  if (a.sub_bf16)
+    hipLaunchKernelGGL(fwd_reduce_kernel<uint16_t>, rg, dim3(256), 0, st, a.geom, a.R, *a.ids,
+                       pl.n_groups, a.partial, (const uint16_t*)a.sub, a.sub_stride, a.out32,
+                       a.out64, a.out_stride, a.pd, a.pd_stride, a.lam, a.dots, a.dots_stride,
+                       a.stop, a.stop_stride);
   else
-    hipLaunchKernelGGL(fwd_reduce_kernel<float>, rg, dim3(256), 0, st, geom, R, ids, pl.n_groups,
-                       partial, (const float*)sub, out32, out64, pd, lam, dots, stop);
+    hipLaunchKernelGGL(fwd_reduce_kernel<float>, rg, dim3(256), 0, st, a.geom, a.R, *a.ids,
+                       pl.n_groups, a.partial, (const float*)a.sub, a.sub_stride, a.out32, a.out64,
+                       a.out_stride, a.pd, a.pd_stride, a.lam, a.dots, a.dots_stride, a.stop,
+                       a.stop_stride);
   return hipGetLastError();
 }
 
 int back_num_workgroups(int N) { return ((N + kBW - 1) / kBW) * ((N + kBH - 1) / kBH); }
 
-hipError_t launch_back(const AngleGeom* geom, int N, int R, const AngleList& ids,
-                       const float* v32, const double* v64, float* out, float* x, float* xT,
-                       const float* x_true, double* partials, int mode, const int* stop,
-                       uint16_t* xs, uint16_t* xsT, hipStream_t st) {
-  dim3 grid((N + kBW - 1) / kBW, (N + kBH - 1) / kBH);
-  if (v64) {
-    hipLaunchKernelGGL(back_kernel<double>, grid, dim3(256), 0, st, geom, N, R, ids, v64, out, x,
-                       xT, x_true, partials, mode, stop, xs, xsT);
-  } else {
-    hipLaunchKernelGGL(back_kernel<float>, grid, dim3(256), 0, st, geom, N, R, ids, v32, out, x,
-                       xT, x_true, partials, mode, stop, xs, xsT);
-  }
+template <typename VT, int BT>
+static void launch_back_t(const BackArgs& a, const VT* v, dim3 grid, hipStream_t st) {
+  hipLaunchKernelGGL((back_kernel<VT, BT>), grid, dim3(256), 0, st, a.geom, a.N, a.R, *a.ids, a.B, v,
+                     a.v_stride, a.out, a.x, a.xT, a.x_true, a.img_stride, a.partials, a.mode,
+                     a.stop, a.stop_stride, a.xs, a.xsT);
+}
+
+template <typename VT>
+static void launch_back_bt(const BackArgs& a, const VT* v, hipStream_t st) {
+  const int BT = slice_tile(a.B);
+  dim3 grid((a.N + kBW - 1) / kBW, (a.N + kBH - 1) / kBH, (a.B + BT - 1) / BT);
+  if (BT == 4)
+    launch_back_t<VT, 4>(a, v, grid, st);
+  else if (BT == 2)
+    launch_back_t<VT, 2>(a, v, grid, st);
+  else
+    launch_back_t<VT, 1>(a, v, grid, st);
+}
+
+hipError_t launch_back(const BackArgs& a, hipStream_t st) {
+  if (a.v64)
+    launch_back_bt(a, a.v64, st);
+  else
+    launch_back_bt(a, a.v32, st);
   return hipGetLastError();
 }
 
-hipError_t launch_reduce3(const double* partials, int n, double* out, hipStream_t st) {
-  hipLaunchKernelGGL(reduce3_kernel, dim3(1), dim3(256), 0, st, partials, n, out);
+hipError_t launch_reduce3(const double* partials, int n, int B, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(reduce3_kernel, dim3(B), dim3(256), 0, st, partials, n, out);
   return hipGetLastError();
 }
 
-hipError_t launch_transpose(const float* src, float* dst, int N, uint16_t* bs, uint16_t* bsT,
-                            hipStream_t st) {
+hipError_t launch_transpose(const float* src, float* dst, int N, int B, size_t stride,
+                            uint16_t* bs, uint16_t* bsT, hipStream_t st) {
   const int t = (N + kTile - 1) / kTile;
-  hipLaunchKernelGGL(transpose_kernel, dim3(t, t), dim3(256), 0, st, src, dst, N, bs, bsT);
+  hipLaunchKernelGGL(transpose_kernel, dim3(t, t, B), dim3(256), 0, st, src, dst, N, stride, bs,
+                     bsT);
   return hipGetLastError();
 }
 

@@ -104,14 +104,16 @@ struct slim_ctx {
   double* d_partials = nullptr;
   double* d_norms = nullptr;   // [B][3]
   float* d_xT = nullptr;       // [B][N][N]
-  float* d_tmp = nullptr;      // [N][N] scratch image (public projector)
+  float* d_tmp = nullptr;      // [B][N][N] scratch image (public projector)
   float* d_fpart = nullptr;    // forward projector partial sums
+  size_t fpart_cap = 0;        // floats allocated in d_fpart
   uint16_t* d_xs = nullptr;    // bf16 shadow of x        [B][N][N] (precision BF16)
   uint16_t* d_xsT = nullptr;   // bf16 shadow of x^T      [B][N][N] (precision BF16)
   PcgWork pcg{};
   Profiler prof;
 
   double* h_norms = nullptr;   // pinned [B][3]
+  bool norms_valid = false;    // h_norms holds the last step read back
   int* h_info = nullptr;       // pinned
 
   int last_pcg_iters = 0;
@@ -178,20 +180,39 @@ AngleList window_list(const slim_ctx* c) {
 // Refresh the copies of x that the forward projector reads: x^T (float32),
 // or the bf16 shadows of x and x^T in the bf16-storage variant.
 slim_status transpose_slices(slim_ctx* c) {
-  for (int sl = 0; sl < c->B; ++sl) {
-    const size_t o = sl * c->img_elems();
-    if (c->bf16())
-      HIP_TRY(launch_transpose(c->x + o, nullptr, c->N, c->d_xs + o, c->d_xsT + o, c->st));
-    else
-      HIP_TRY(launch_transpose(c->x + o, c->d_xT + o, c->N, nullptr, nullptr, c->st));
-  }
+  if (c->bf16())
+    HIP_TRY(launch_transpose(c->x, nullptr, c->N, c->B, c->img_elems(), c->d_xs, c->d_xsT, c->st));
+  else
+    HIP_TRY(launch_transpose(c->x, c->d_xT, c->N, c->B, c->img_elems(), nullptr, nullptr, c->st));
   return SLIM_OK;
 }
 
-// sinogram of slice sl (float32 or bf16 elements)
-const void* sino_slice(const slim_ctx* c, int sl) {
-  const size_t esz = c->bf16() ? sizeof(uint16_t) : sizeof(float);
-  return (const char*)c->b + (size_t)sl * c->sino_elems() * esz;
+// Grow the forward projector's partial-sum workspace for a launch over the
+// list l (all slices); synchronises the stream only when it grows.
+slim_status ensure_fpart(slim_ctx* c, const AngleList& l) {
+  const size_t need = forward_partial_floats(c->h_geom.data(), c->N, c->R, l, c->B);
+  if (need <= c->fpart_cap) return SLIM_OK;
+  HIP_TRY(hipStreamSynchronize(c->st));
+  HIP_TRY(hipFree(c->d_fpart));
+  c->d_fpart = nullptr;
+  c->fpart_cap = 0;
+  hipError_t e = hipMalloc((void**)&c->d_fpart, need * sizeof(float));
+  if (e != hipSuccess) return fail(SLIM_ENOMEM, "forward workspace does not fit");
+  c->fpart_cap = need;
+  return SLIM_OK;
+}
+
+FwdArgs base_fwd(const slim_ctx* c, const AngleList* l) {
+  FwdArgs a;
+  a.geom = c->d_geom;
+  a.h_geom = c->h_geom.data();
+  a.N = c->N;
+  a.R = c->R;
+  a.B = c->B;
+  a.ids = l;
+  a.img_stride = c->img_elems();
+  a.partial = c->d_fpart;
+  return a;
 }
 
 // Gram mode: z = G^{-1} [0; res] for every slice, G shared by the slices.
@@ -220,9 +241,8 @@ slim_status gram_solve_chol(slim_ctx* c, int new_slot) {
   if (c->prof.on) HIP_TRY(c->prof.begin(K_CHOL, c->st));
   HIP_TRY(hipMemsetAsync(c->d_info, 0, sizeof(int), c->st));
   HIP_TRY(launch_cholesky(c->d_G, p, (int)p, c->d_info, c->st));
-  for (int sl = 0; sl < c->B; ++sl)
-    HIP_TRY(launch_chol_solve(c->d_G, p, (int)p, (int)ell, c->d_res64 + sl * ell,
-                              c->d_z + sl * c->pmax, c->st));
+  HIP_TRY(launch_chol_solve(c->d_G, p, (int)p, (int)ell, c->d_res64, ell, c->d_z, c->pmax, c->B,
+                            c->st));
   if (c->prof.on) HIP_TRY(c->prof.end(c->st));
   return SLIM_OK;
 }
@@ -242,15 +262,24 @@ slim_status do_step(slim_ctx* c, const int32_t* ids, slim_step_info* info) {
     HIP_TRY(hipStreamSynchronize(c->st));
     HIP_TRY(c->prof.harvest());
   }
-  // 1. residual of the new block, every slice
+  {
+    slim_status s = ensure_fpart(c, blk);
+    if (s == SLIM_OK && c->mode == SLIM_GRAM_PCG) s = ensure_fpart(c, win);
+    if (s != SLIM_OK) return s;
+  }
+  // 1. residual of the new block, all slices in one launch
   if (c->prof.on) HIP_TRY(c->prof.begin(K_RESID, c->st));
-  for (int sl = 0; sl < c->B; ++sl) {
-    const size_t o = sl * c->img_elems();
-    const void* xs = c->bf16() ? (const void*)(c->d_xs + o) : (const void*)(c->x + o);
-    const void* xTs = c->bf16() ? (const void*)(c->d_xsT + o) : (const void*)(c->d_xT + o);
-    HIP_TRY(launch_forward(c->d_geom, c->h_geom.data(), c->N, c->R, blk, xs, xTs, c->bf16(),
-                           sino_slice(c, sl), c->bf16(), nullptr, c->d_res64 + sl * ell,
-                           c->d_fpart, nullptr, 0.0, nullptr, nullptr, c->st));
+  {
+    FwdArgs fa = base_fwd(c, &blk);
+    fa.img = c->bf16() ? (const void*)c->d_xs : (const void*)c->x;
+    fa.imgT = c->bf16() ? (const void*)c->d_xsT : (const void*)c->d_xT;
+    fa.img_bf16 = c->bf16();
+    fa.sub = c->b;
+    fa.sub_stride = c->sino_elems();
+    fa.sub_bf16 = c->bf16();
+    fa.out64 = c->d_res64;
+    fa.out_stride = ell;
+    HIP_TRY(launch_forward(fa, c->st));
   }
   if (c->prof.on) HIP_TRY(c->prof.end(c->st));
   // 2. Gram system
@@ -260,30 +289,33 @@ slim_status do_step(slim_ctx* c, const int32_t* ids, slim_step_info* info) {
     slim_status s = gram_solve_chol(c, slot);
     if (s != SLIM_OK) return s;
   } else {
-    for (int sl = 0; sl < c->B; ++sl) {
-      int it = 0;
-      double rel = 0.0;
-      hipError_t e = pcg_solve(c->pcg, c->d_geom, c->h_geom.data(), c->d_fpart, c->N, c->R, win,
-                               c->lam, c->d_res64 + sl * ell,
-                               (int)ell, c->d_z + sl * c->pmax, c->o.pcg_tol, c->o.pcg_max_iter,
-                               &it, &rel, &c->prof, c->st);
-      if (e != hipSuccess) return fail(SLIM_EDEVICE, std::string("pcg: ") + hipGetErrorString(e));
-      pcg_it = std::max(pcg_it, it);
-      pcg_rel = std::max(pcg_rel, rel);
-    }
+    hipError_t e = pcg_solve(c->pcg, c->d_geom, c->h_geom.data(), c->d_fpart, c->N, c->R, c->B,
+                             win, c->lam, c->d_res64, ell, (int)ell, c->d_z, c->pmax,
+                             c->o.pcg_tol, c->o.pcg_max_iter, &pcg_it, &pcg_rel, &c->prof, c->st);
+    if (e != hipSuccess) return fail(SLIM_EDEVICE, std::string("pcg: ") + hipGetErrorString(e));
   }
   // 3. update every slice
   const int nwg = back_num_workgroups(c->N);
   if (c->prof.on) HIP_TRY(c->prof.begin(K_UPDATE, c->st));
-  for (int sl = 0; sl < c->B; ++sl) {
-    float* xs = c->x + sl * c->img_elems();
-    const float* xt = c->x_true ? c->x_true + sl * c->img_elems() : nullptr;
-    const size_t o = sl * c->img_elems();
-    HIP_TRY(launch_back(c->d_geom, c->N, c->R, win, nullptr, c->d_z + sl * c->pmax, nullptr, xs,
-                        c->bf16() ? nullptr : c->d_xT + o, xt, c->d_partials, 1, nullptr,
-                        c->bf16() ? c->d_xs + o : nullptr, c->bf16() ? c->d_xsT + o : nullptr,
-                        c->st));
-    HIP_TRY(launch_reduce3(c->d_partials, nwg, c->d_norms + 3 * sl, c->st));
+  {
+    BackArgs ba;
+    ba.geom = c->d_geom;
+    ba.N = c->N;
+    ba.R = c->R;
+    ba.B = c->B;
+    ba.ids = &win;
+    ba.v64 = c->d_z;
+    ba.v_stride = c->pmax;
+    ba.x = c->x;
+    ba.xT = c->bf16() ? nullptr : c->d_xT;
+    ba.x_true = c->x_true;
+    ba.img_stride = c->img_elems();
+    ba.partials = c->d_partials;
+    ba.mode = 1;
+    ba.xs = c->bf16() ? c->d_xs : nullptr;
+    ba.xsT = c->bf16() ? c->d_xsT : nullptr;
+    HIP_TRY(launch_back(ba, c->st));
+    HIP_TRY(launch_reduce3(c->d_partials, nwg, c->B, c->d_norms, c->st));
   }
   if (c->prof.on) HIP_TRY(c->prof.end(c->st));
   (void)p;
@@ -297,6 +329,7 @@ slim_status do_step(slim_ctx* c, const int32_t* ids, slim_step_info* info) {
   HIP_TRY(hipMemcpyAsync(c->h_info, c->d_info, sizeof(int), hipMemcpyDeviceToHost, c->st));
   HIP_TRY(hipStreamSynchronize(c->st));
   if (c->prof.on) HIP_TRY(c->prof.harvest());
+  c->norms_valid = true;
   int best = 0;
   for (int sl = 1; sl < c->B; ++sl)
     if (c->h_norms[3 * sl] > c->h_norms[3 * best]) best = sl;
@@ -423,7 +456,7 @@ slim_status slim_init(slim_ctx** out, const slim_grid* grid, int n_angles, const
   if ((e = dalloc(&c->d_res64, (size_t)c->B * ell)) != hipSuccess) return oom(e);
   if ((e = dalloc(&c->d_z, (size_t)c->B * pmax)) != hipSuccess) return oom(e);
   if ((e = dalloc(&c->d_info, 1)) != hipSuccess) return oom(e);
-  if ((e = dalloc(&c->d_partials, 3 * (size_t)back_num_workgroups(c->N))) != hipSuccess) return oom(e);
+  if ((e = dalloc(&c->d_partials, 3 * (size_t)c->B * back_num_workgroups(c->N))) != hipSuccess) return oom(e);
   if ((e = dalloc(&c->d_norms, 3 * (size_t)c->B)) != hipSuccess) return oom(e);
   if (o.precision == SLIM_PREC_BF16) {
     if ((e = dalloc(&c->d_xs, nimg)) != hipSuccess) return oom(e);
@@ -431,13 +464,12 @@ slim_status slim_init(slim_ctx** out, const slim_grid* grid, int n_angles, const
   } else {
     if ((e = dalloc(&c->d_xT, nimg)) != hipSuccess) return oom(e);
   }
-  if ((e = dalloc(&c->d_tmp, c->img_elems())) != hipSuccess) return oom(e);
-  if ((e = dalloc(&c->d_fpart, forward_partial_floats(c->N, c->R, kMaxList))) != hipSuccess) return oom(e);
+  if ((e = dalloc(&c->d_tmp, nimg)) != hipSuccess) return oom(e);
   if (mode == SLIM_GRAM_CHOL) {
     if ((e = dalloc(&c->d_tiles, (size_t)(r + 1) * (r + 1) * ell * ell)) != hipSuccess) return oom(e);
     if ((e = dalloc(&c->d_G, (size_t)pmax * pmax)) != hipSuccess) return oom(e);
   } else {
-    if ((e = pcg_alloc(c->pcg, c->N, pmax)) != hipSuccess) return oom(e);
+    if ((e = pcg_alloc(c->pcg, c->N, c->B, pmax)) != hipSuccess) return oom(e);
   }
   if ((e = hipHostMalloc((void**)&c->h_norms, sizeof(double) * 3 * c->B, hipHostMallocDefault)) != hipSuccess) return oom(e);
   if ((e = hipHostMalloc((void**)&c->h_info, sizeof(int), hipHostMallocDefault)) != hipSuccess) return oom(e);
@@ -457,6 +489,7 @@ slim_status slim_set_data(slim_ctx* c, const void* b, void* x, const float* x_tr
   c->x_true = x_true;
   c->bound = true;
   c->k = 0;
+  c->norms_valid = false;
   c->window.clear();
   c->epoch = 0;
   c->pos = 0;
@@ -517,13 +550,19 @@ slim_status slim_project(slim_ctx* c, const int32_t* ids, int n_ids, const float
   if (s != SLIM_OK) return s;
   if (!x || !out) return fail(SLIM_EINVAL, "x and out must be non-NULL");
   const AngleList l = make_list(ids, n_ids);
-  for (int sl = 0; sl < c->B; ++sl) {
-    const float* xs = x + sl * c->img_elems();
-    HIP_TRY(launch_transpose(xs, c->d_tmp, c->N, nullptr, nullptr, c->st));
-    HIP_TRY(launch_forward(c->d_geom, c->h_geom.data(), c->N, c->R, l, xs, c->d_tmp, 0, nullptr, 0,
-                           out + (size_t)sl * n_ids * c->R, nullptr, c->d_fpart, nullptr, 0.0,
-                           nullptr, nullptr, c->st));
-  }
+  s = ensure_fpart(c, l);
+  if (s != SLIM_OK) return s;
+  // column-stepping angles read the transposed image: make it only if needed
+  bool any_col = false;
+  for (int i = 0; i < n_ids; ++i) any_col = any_col || c->h_geom[ids[i]].colmajor != 0;
+  if (any_col)
+    HIP_TRY(launch_transpose(x, c->d_tmp, c->N, c->B, c->img_elems(), nullptr, nullptr, c->st));
+  FwdArgs fa = base_fwd(c, &l);
+  fa.img = x;
+  fa.imgT = any_col ? c->d_tmp : x;
+  fa.out32 = out;
+  fa.out_stride = (size_t)n_ids * c->R;
+  HIP_TRY(launch_forward(fa, c->st));
   return SLIM_OK;
 }
 
@@ -533,10 +572,18 @@ slim_status slim_backproject(slim_ctx* c, const int32_t* ids, int n_ids, const f
   if (s != SLIM_OK) return s;
   if (!v || !out) return fail(SLIM_EINVAL, "v and out must be non-NULL");
   const AngleList l = make_list(ids, n_ids);
-  for (int sl = 0; sl < c->B; ++sl)
-    HIP_TRY(launch_back(c->d_geom, c->N, c->R, l, v + (size_t)sl * n_ids * c->R, nullptr,
-                        out + sl * c->img_elems(), nullptr, nullptr, nullptr, nullptr, 0, nullptr,
-                        nullptr, nullptr, c->st));
+  BackArgs ba;
+  ba.geom = c->d_geom;
+  ba.N = c->N;
+  ba.R = c->R;
+  ba.B = c->B;
+  ba.ids = &l;
+  ba.v32 = v;
+  ba.v_stride = (size_t)n_ids * c->R;
+  ba.out = out;
+  ba.img_stride = c->img_elems();
+  ba.mode = 0;
+  HIP_TRY(launch_back(ba, c->st));
   return SLIM_OK;
 }
 
@@ -606,6 +653,18 @@ slim_status slim_set_state(slim_ctx* c, const void* buf, int64_t size) {
     c->k += 1;
   }
   HIP_TRY(transpose_slices(c) == SLIM_OK ? hipSuccess : hipErrorUnknown);
+  return SLIM_OK;
+}
+
+slim_status slim_slice_norms(slim_ctx* c, double* out, int n) {
+  if (!c || !out) return fail(SLIM_EINVAL, "ctx or out is NULL");
+  if (n != c->B) return fail(SLIM_EINVAL, "n must equal n_slices");
+  if (!c->norms_valid) return fail(SLIM_ESTATE, "no step read back since the data were bound");
+  for (int sl = 0; sl < c->B; ++sl) {
+    out[3 * sl + 0] = std::sqrt(c->h_norms[3 * sl + 0]);
+    out[3 * sl + 1] = std::sqrt(c->h_norms[3 * sl + 1]);
+    out[3 * sl + 2] = c->x_true ? std::sqrt(c->h_norms[3 * sl + 2]) : -1.0;
+  }
   return SLIM_OK;
 }
 

@@ -86,35 +86,81 @@ struct Profiler {
 };
 
 // ---- launchers (return hipError_t of the launch) --------------------------
-// Forward projection: out[a][t] = sum_pix A[(ids[a],t),pix] img[pix] - (sub ? sub[ids[a]][t] : 0),
-// accumulated in float64 per ray and written as float (out32) and/or double (out64).
-// img and its transpose imgT are both required.  h_geom: host copy of the
-// geometry table (the launch plan groups angles by orientation).  partial:
-// workspace of forward_partial_floats(N, R, ids.n) floats.  CG tail when pd
-// is non-NULL: out += lam * pd and per-workgroup partial sums of pd . out
-// into dots[forward_dot_parts(ids.n * R)].
-// img/imgT are float32, or bf16 bit patterns when img_bf16 != 0; sub likewise.
-hipError_t launch_forward(const AngleGeom* geom, const AngleGeom* h_geom, int N, int R,
-                          const AngleList& ids, const void* img, const void* imgT, int img_bf16,
-                          const void* sub, int sub_bf16, float* out32, double* out64,
-                          float* partial, const double* pd, double lam, double* dots,
-                          const int* stop, hipStream_t st);
-size_t forward_partial_floats(int N, int R, int max_list);
+// Slice tile of the batched projectors (1, 2 or 4 slices per workgroup).
+int slice_tile(int B);
+
+// Forward projection of B slices sharing the geometry:
+//   out[slice][a][t] = sum_pix A[(ids[a],t),pix] img[slice][pix] - sub[slice][ids[a]][t]
+// accumulated in float64 per ray, written as float (out32) and/or double (out64).
+// img and its transpose imgT are both required (float32, or bf16 bit patterns
+// when img_bf16); sub likewise with sub_bf16.  Strides are in elements.
+// partial: workspace of forward_partial_floats(...) floats.  CG tail when pd
+// is non-NULL: out += lam * pd and per-workgroup partial sums of pd . out into
+// dots[slice * dots_stride + forward_dot_parts(ids.n * R)].  Slices whose
+// stop[slice * stop_stride + kCtlDone] is set are skipped.
+struct FwdArgs {
+  const AngleGeom* geom = nullptr;
+  const AngleGeom* h_geom = nullptr;   // host copy (the launch plan groups angles)
+  int N = 0, R = 0, B = 1;
+  const AngleList* ids = nullptr;
+  const void* img = nullptr;
+  const void* imgT = nullptr;
+  size_t img_stride = 0;
+  int img_bf16 = 0;
+  const void* sub = nullptr;
+  size_t sub_stride = 0;
+  int sub_bf16 = 0;
+  float* out32 = nullptr;
+  double* out64 = nullptr;
+  size_t out_stride = 0;
+  float* partial = nullptr;
+  const double* pd = nullptr;
+  size_t pd_stride = 0;
+  double lam = 0.0;
+  double* dots = nullptr;
+  size_t dots_stride = 0;
+  const int* stop = nullptr;
+  int stop_stride = 0;
+};
+hipError_t launch_forward(const FwdArgs& a, hipStream_t st);
+size_t forward_partial_floats(const AngleGeom* h_geom, int N, int R, const AngleList& ids, int B);
 int forward_dot_parts(int n_out);
 
-// Back-projection over a list: s[pix] = sum_a sum_t A[(ids[a],t),pix] v[a][t]
+// Back-projection of B slices: s[slice][pix] = sum_a sum_t A[(ids[a],t),pix] v[slice][a][t]
 // with v float (v32) or double (v64).  mode 0: out = s (and out^T into xT).
 // mode 1: x -= s in place, optional transposed copy xT, optional bf16 copies
 // xs, xsT (round to nearest even), and per-workgroup float64 partial norms
-// (||s||^2, ||x_new||^2, ||x_new - x_true||^2) into partials[3*nwg].
-hipError_t launch_back(const AngleGeom* geom, int N, int R, const AngleList& ids,
-                       const float* v32, const double* v64, float* out, float* x, float* xT,
-                       const float* x_true, double* partials, int mode, const int* stop,
-                       uint16_t* xs, uint16_t* xsT, hipStream_t st);
+// (||s||^2, ||x_new||^2, ||x_new - x_true||^2) into
+// partials[(slice * back_num_workgroups(N) + wg) * 3 + k].
+struct BackArgs {
+  const AngleGeom* geom = nullptr;
+  int N = 0, R = 0, B = 1;
+  const AngleList* ids = nullptr;
+  const float* v32 = nullptr;
+  const double* v64 = nullptr;
+  size_t v_stride = 0;
+  float* out = nullptr;
+  float* x = nullptr;
+  float* xT = nullptr;
+  const float* x_true = nullptr;
+  size_t img_stride = 0;
+  double* partials = nullptr;
+  int mode = 0;
+  const int* stop = nullptr;
+  int stop_stride = 0;
+  uint16_t* xs = nullptr;
+  uint16_t* xsT = nullptr;
+};
+hipError_t launch_back(const BackArgs& a, hipStream_t st);
 int back_num_workgroups(int N);
 
-// Sum 3-vectors of partials in a fixed order into out[3] (one workgroup).
-hipError_t launch_reduce3(const double* partials, int n, double* out, hipStream_t st);
+// Per slice, sum the n partial 3-vectors in a fixed order into out[3*slice..].
+hipError_t launch_reduce3(const double* partials, int n, int B, double* out, hipStream_t st);
+
+// dst = src^T (if dst), bf16 copies of src (bs) and src^T (bsT) if given, for
+// B slices with the given element stride.
+hipError_t launch_transpose(const float* src, float* dst, int N, int B, size_t stride,
+                            uint16_t* bs, uint16_t* bsT, hipStream_t st);
 
 // Gram block: out[(a,t),(b,u)] = sum_pix A[(ida[a],t),pix] A[(idb[b],u),pix],
 // float64, row-major with leading dimension ld.
@@ -131,10 +177,12 @@ hipError_t launch_tile_copy(const double* src, int64_t lds, double* G, int64_t l
 // set to 1 + index of the first non-positive pivot (0 on success).
 hipError_t launch_cholesky(double* G, int64_t ld, int p, int* info, hipStream_t st);
 
-// Solve L y = e with e = [0; rhs] (rhs: last nr entries) and L^T z = y.
-// z: [p] float64.  rhs taken from rhs64.
+// For each of B right-hand sides: solve L y = e with e = [0; rhs] (rhs: the
+// last nr entries, rhs64 + slice * rhs_stride) and L^T z = y
+// (z + slice * z_stride, float64 [p]).
 hipError_t launch_chol_solve(const double* L, int64_t ld, int p, int nr, const double* rhs64,
-                             double* z, hipStream_t st);
+                             size_t rhs_stride, double* z, size_t z_stride, int B,
+                             hipStream_t st);
 
 
 }  // namespace slim

@@ -78,6 +78,7 @@ def load() -> ctypes.CDLL:
         "slim_gram": (I, [P, i32p, I, i32p, I, P]),
         "slim_get_state": (I, [P, P, ctypes.POINTER(ctypes.c_int64)]),
         "slim_set_state": (I, [P, P, ctypes.c_int64]),
+        "slim_slice_norms": (I, [P, ctypes.POINTER(D), I]),
         "slim_profile": (I, [P, I]),
         "slim_kernel_stats": (I, [P, I, ctypes.POINTER(D), ctypes.POINTER(ctypes.c_int64)]),
         "slim_destroy": (None, [P]),
@@ -179,6 +180,14 @@ class Slim:
         if not read:
             return None
         return {f: getattr(info, f) for f, _ in StepInfo._fields_}
+
+    def slice_norms(self) -> np.ndarray:
+        """[n_slices][3] float64: ||s_k||, ||x_k||, ||x_k - x_true|| of the last
+        step read back, slice by slice."""
+        out = np.zeros((self.B, 3), dtype=np.float64)
+        _check(load().slim_slice_norms(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                       self.B))
+        return out
 
     def solve(self, b, x, x_true=None, tol: float = 1e-2, max_epochs: int = 1) -> dict:
         self._keep = [b, x, x_true]

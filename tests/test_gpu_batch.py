@@ -1,0 +1,147 @@
+"""Batched slices sharing A (independent z-slices of a volume): the library
+runs every slice in the same launches (slice tiles of up to 4 slices share
+the weight computation).  Each slice must match the FP64 oracle run on that
+slice alone with the same block schedule, and the single-slice path."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import sampler, slimls, system
+
+torch = pytest.importorskip("torch")
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+
+def _rel(a, b):
+    a = np.asarray(a, np.float64).reshape(-1)
+    b = np.asarray(b, np.float64).reshape(-1)
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def _dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float32, device="cuda")
+
+
+@pytest.mark.parametrize("B,N,na", [(5, 64, 30), (2, 37, 16), (4, 256, 24), (3, 128, 12)])
+def test_batched_projectors_match_oracle(B, N, na):
+    from paper_1912_07962_amd import Slim
+    P = system.Projector(N, na)
+    rng = np.random.default_rng(B * 100 + N)
+    x = rng.standard_normal((B, N, N)).astype(np.float32)
+    ids = list(range(0, na, 3)) + [1]
+    v = rng.standard_normal((B, len(ids), P.R)).astype(np.float32)
+    s = Slim(N, na, r=0, lam=1.0, n_slices=B)
+    fwd = s.project(ids, _dev(x)).cpu().numpy().reshape(B, len(ids), P.R)
+    back = s.backproject(ids, _dev(v)).cpu().numpy().reshape(B, N, N)
+    for b in range(B):
+        assert _rel(fwd[b], P.forward(ids, x[b].astype(np.float64))) < 1e-6
+        assert _rel(back[b], P.back(ids, v[b].astype(np.float64))) < 1e-6
+
+
+@pytest.mark.parametrize("B,g,r,mode", [(3, 1, 3, "chol"), (6, 2, 3, "pcg"), (5, 3, 1, "chol")])
+def test_batched_steps_match_oracle_per_slice(B, g, r, mode):
+    from paper_1912_07962_amd import Slim
+    N, na, lam = 48, 36, 1e-2
+    xs, bs = synth.make_volume_problem(N, B, na, 8, 0.01, 41, 42)
+    # make every slice non-trivial: add a per-slice 2D phantom
+    extra = [synth.make_slice_problem(N, na, 3, 0.01, 500 + k, 600 + k) for k in range(B)]
+    xs = xs + np.stack([e[0] for e in extra])
+    bs = bs + np.stack([e[1] for e in extra])
+    M = na // g
+    sched = sampler.schedule(M, 2, 9)
+    P = system.Projector(N, na)
+    oracles = [slimls.Tomo(P, bs[k], g, r, lam, x_true=xs[k]) for k in range(B)]
+    s = Slim(N, na, r=r, lam=lam, n_slices=B, angles_per_block=g, gram_mode=mode,
+             pcg_tol=1e-11, pcg_max_iter=3000)
+    x = torch.zeros((B, N, N), dtype=torch.float32, device="cuda")
+    s.set_data(_dev(bs), x, _dev(xs))
+    for k, beta in enumerate(sched, 1):
+        info = s.step(list(range(beta * g, beta * g + g)))
+        recs = [o.step(int(beta)) for o in oracles]
+        if k % M == 0:
+            xe = x.cpu().numpy()
+            for b in range(B):
+                assert _rel(xe[b], oracles[b].x) < 1e-5, (k, b)
+            # info reports the slice with the largest step norm
+            big = max(recs, key=lambda rr: rr.step_norm)
+            assert abs(info["step_norm"] - big.step_norm) <= 1e-5 * big.step_norm
+            # slice by slice: ||s_k||, ||x_k||, ||x_k - x_true||
+            nr = s.slice_norms()
+            for b, rec in enumerate(recs):
+                for q, want in enumerate((rec.step_norm, rec.x_norm, rec.err_norm)):
+                    assert abs(nr[b, q] - want) <= 1e-5 * want, (k, b, q)
+
+
+def test_slice_norms_state_and_arguments():
+    from paper_1912_07962_amd import Slim, SlimError
+    N, na, B = 32, 12, 3
+    xs, bs = synth.make_volume_problem(N, B, na, 4, 0.01, 3, 4)
+    s = Slim(N, na, r=1, lam=1e-2, n_slices=B, gram_mode="chol")
+    x = torch.zeros((B, N, N), dtype=torch.float32, device="cuda")
+    s.set_data(_dev(bs), x)
+    with pytest.raises(SlimError):
+        s.slice_norms()                      # no step read back yet
+    s.step([4], read=False)
+    with pytest.raises(SlimError):
+        s.slice_norms()                      # the step was not read back
+    s.step([7])
+    nr = s.slice_norms()
+    assert nr.shape == (B, 3) and np.all(nr[:, 2] == -1.0)   # no x_true bound
+    xe = x.cpu().numpy().astype(np.float64)
+    for b in range(B):
+        assert abs(nr[b, 1] - np.linalg.norm(xe[b])) <= 1e-5 * max(nr[b, 1], 1e-30)
+
+
+def test_batched_equals_single_slice_runs():
+    from paper_1912_07962_amd import Slim
+    N, na, g, r, lam, B = 64, 40, 2, 4, 1e-2, 6
+    xs, bs = synth.make_volume_problem(N, B, na, 10, 0.01, 7, 8)
+    sched = sampler.schedule(na // g, 1, 5)
+    sb = Slim(N, na, r=r, lam=lam, n_slices=B, angles_per_block=g, gram_mode="pcg", pcg_tol=1e-10)
+    xb = torch.zeros((B, N, N), dtype=torch.float32, device="cuda")
+    sb.set_data(_dev(bs), xb)
+    singles = []
+    for b in range(B):
+        s1 = Slim(N, na, r=r, lam=lam, angles_per_block=g, gram_mode="pcg", pcg_tol=1e-10)
+        x1 = torch.zeros((N, N), dtype=torch.float32, device="cuda")
+        s1.set_data(_dev(bs[b]), x1)
+        singles.append((s1, x1))
+    for beta in sched:
+        ids = list(range(beta * g, beta * g + g))
+        sb.step(ids)
+        for s1, _ in singles:
+            s1.step(ids)
+    for b, (_, x1) in enumerate(singles):
+        got, want = xb[b].cpu().numpy(), x1.cpu().numpy()
+        if not np.any(bs[b]):
+            # an empty slice (b = 0) stays exactly zero in both paths
+            assert not np.any(got) and not np.any(want)
+        else:
+            assert _rel(got, want) < 1e-5
+    assert any(not np.any(bb) for bb in bs)   # the batch holds empty slices
+
+
+def test_volume_512_first_steps_sampled_slices():
+    """The 512^2 x 360-angle batched workload (4 angles/block, r = 8,
+    lambda = 1e-3) on 16 slices, first three steps; two slices checked
+    against the oracle (p up to 3 x 2900, dense Cholesky in the oracle)."""
+    from paper_1912_07962_amd import Slim
+    cfg = synth.get_config("c4")
+    N, na, g, r, lam, B = cfg["N"], cfg["n_angles"], cfg["g"], cfg["r"], cfg["lam"], 16
+    xs, bs = synth.make_volume_problem(N, B, na, cfg["n_ellipsoids"], cfg["noise"],
+                                       cfg["phantom_seed"], cfg["noise_seed"])
+    s = Slim(N, na, r=r, lam=lam, n_slices=B, angles_per_block=g, gram_mode="pcg", pcg_tol=1e-9)
+    x = torch.zeros((B, N, N), dtype=torch.float32, device="cuda")
+    s.set_data(_dev(bs), x)
+    sched = synth.schedule(na // g, 1, cfg["schedule_seed"])[:3]
+    P = system.Projector(N, na)
+    picks = [5, 11]
+    oracles = {b: slimls.Tomo(P, bs[b], g, r, lam) for b in picks}
+    for beta in sched:
+        s.step(list(range(int(beta) * g, int(beta) * g + g)))
+        for o in oracles.values():
+            o.step(int(beta))
+    xe = x.cpu().numpy()
+    for b, o in oracles.items():
+        assert _rel(xe[b], o.x) < 1e-5
