@@ -166,6 +166,15 @@ slim_status slim_project(slim_ctx* ctx, const int32_t* angle_ids, int n_ids, con
 slim_status slim_backproject(slim_ctx* ctx, const int32_t* angle_ids, int n_ids, const float* v,
                              float* out);
 
+/* Back-projection of the bound data for the listed angles:
+ * out = A_ids^T b_ids for every slice (sec. 1: the first iterate from x0 = 0
+ * is built from such products; the learned warm start reads it).
+ *  angle_ids  host int32 [n_ids], no duplicates
+ *  out        device [n_slices][N][N] float32 (overwritten)
+ * Errors: SLIM_EINVAL, SLIM_ESTATE (no data bound), SLIM_EDEVICE. */
+slim_status slim_data_backprojection(slim_ctx* ctx, const int32_t* angle_ids, int n_ids,
+                                     float* out);
+
 /* Gram block A_ids_a A_ids_b^T (sec. 2 Woodbury remark; the blocks of
  * M_k M_k^T).  out: device float64 [n_a*n_rays][n_b*n_rays], row-major.
  * Errors: SLIM_EINVAL, SLIM_EDEVICE. */

@@ -1,0 +1,595 @@
+// Kernels of the warm-start CNN for gfx950.
+//
+// 3x3 convolutions are implicit GEMMs on v_mfma_f32_16x16x32_bf16 (M =
+// pixels, N = output channels, K = 9 taps x input channels).  A wavefront
+// owns 64 output pixels x 32 output channels (4 x 2 MFMA tiles) and reads its
+// operands straight from L1/L2: in NHWC the 8 consecutive channels a lane
+// supplies are one 16-byte load.  MFMA operand layout (lane l = 16 q + r):
+// A holds row r, k = 8q..8q+7; B holds column r, k = 8q..8q+7; accumulator
+// e of lane l is D[4q + e][r].
+//
+// Weight gradients contract over pixels, the strided dimension of NHWC, so
+// their workgroups stage 64-pixel chunks of dz and of the shifted input
+// through LDS transposed (pixel-contiguous rows) and write split-K partials
+// that a second kernel sums in a fixed order (bitwise reproducible).
+#include <algorithm>
+
+#include "cnn_internal.h"
+
+namespace slim {
+namespace cnn {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// float -> bf16, round to nearest even (NaN stays NaN)
+__device__ __forceinline__ uint16_t f2bf(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return 0x7fc0;
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ bf16x8 ld8(const uint16_t* p) {
+  return __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(p));
+}
+
+__device__ __forceinline__ bf16x8 zero8() {
+  u32x4 z = {0u, 0u, 0u, 0u};
+  return __builtin_bit_cast(bf16x8, z);
+}
+
+// Blocks are dispatched round-robin over the 8 XCDs; this numbering gives
+// consecutive logical blocks (neighbouring pixel tiles, which share input
+// rows) to one XCD and its L2.  gridDim.x must be a multiple of 8.
+__device__ __forceinline__ int64_t xcd_block() {
+  return (int64_t)(blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3);
+}
+
+unsigned grid8(int64_t blocks) { return (unsigned)((blocks + 7) / 8 * 8); }
+
+// ------------------------------------------------------------ convolution
+constexpr int kCW = 4;  // wavefronts per conv workgroup
+
+__global__ __launch_bounds__(64 * kCW) void conv3x3_kernel(ConvArgs a, int64_t n_wave_tiles) {
+  const int lane = threadIdx.x & 63;
+  const int64_t wt = xcd_block() * kCW + (threadIdx.x >> 6);
+  if (wt >= n_wave_tiles) return;
+  const int nco = a.Cout >> 5;
+  const int cot = (int)(wt % nco);
+  const int64_t pt = wt / nco;
+  const int H = a.H, HW = H * H;
+  const int Hin = a.up ? (H >> 1) : H;
+  const int r = lane & 15, q = lane >> 4;
+
+  int py[4], px[4];
+  int64_t img[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int64_t P = pt * 64 + 16 * i + r;
+    const int64_t n = P / HW;
+    const int rem = (int)(P - n * HW);
+    py[i] = rem / H;
+    px[i] = rem - py[i] * H;
+    img[i] = n * Hin * Hin;
+  }
+  const uint16_t* wrow[2];
+#pragma unroll
+  for (int j = 0; j < 2; ++j) wrow[j] = a.w + (size_t)(cot * 32 + 16 * j + r) * 9 * a.Cin + 8 * q;
+
+  f32x4 acc[4][2];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  for (int tap = 0; tap < 9; ++tap) {
+    const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+    const uint16_t* src[4];
+    bool ok[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int yy = py[i] + dy, xx = px[i] + dx;
+      ok[i] = (unsigned)yy < (unsigned)H && (unsigned)xx < (unsigned)H;
+      const int ys = ok[i] ? (a.up ? yy >> 1 : yy) : 0;
+      const int xs = ok[i] ? (a.up ? xx >> 1 : xx) : 0;
+      src[i] = a.in.p + ((img[i] + (int64_t)ys * Hin + xs) * a.in.cs + a.in.co + 8 * q);
+    }
+    for (int c0 = 0; c0 < a.Cin; c0 += 32) {
+      bf16x8 A[4], Bv[2];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) A[i] = ok[i] ? ld8(src[i] + c0) : zero8();
+#pragma unroll
+      for (int j = 0; j < 2; ++j) Bv[j] = ld8(wrow[j] + tap * a.Cin + c0);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[i], Bv[j], acc[i][j], 0, 0, 0);
+    }
+  }
+
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int co = cot * 32 + 16 * j + r;
+    const float bias = a.bias ? a.bias[co] : 0.f;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t P = pt * 64 + 16 * i + 4 * q + e;
+        float v = acc[i][j][e] + bias;
+        if (a.relu) v = fmaxf(v, 0.f);
+        if (a.mask.p && !(bf2f(a.mask.p[P * a.mask.cs + a.mask.co + co]) > 0.f)) v = 0.f;
+        a.out.p[P * a.out.cs + a.out.co + co] = f2bf(v);
+      }
+    }
+  }
+}
+
+// -------------------------------------------------------- weight gradient
+constexpr int kLD = 64 + 8;  // LDS row stride (bf16) of the staged chunks
+
+template <int TCO, int TCI>
+__global__ __launch_bounds__(64 * (TCO / 32) * (TCI / 32)) void wgrad_kernel(WgradArgs a,
+                                                                          int n_chunks,
+                                                                          int cps, int nci_t) {
+  constexpr int NT = 64 * (TCO / 32) * (TCI / 32);
+  __shared__ __attribute__((aligned(16))) uint16_t sz[TCO * kLD];
+  __shared__ __attribute__((aligned(16))) uint16_t sx[TCI * kLD];
+  const int split = blockIdx.x, tap = blockIdx.y;
+  const int cot = blockIdx.z / nci_t, cit = blockIdx.z % nci_t;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wco = (w / (TCI / 32)) * 32, wci = (w % (TCI / 32)) * 32;
+  const int r = lane & 15, q = lane >> 4;
+  const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+  const int H = a.H, HW = H * H;
+  const int Hin = a.up ? (H >> 1) : H;
+  const bool do_bias = tap == 4 && cit == 0;
+
+  f32x4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  float bsum = 0.f;
+
+  const int c_begin = split * cps, c_end = min(n_chunks, c_begin + cps);
+  for (int ch = c_begin; ch < c_end; ++ch) {
+    const int64_t P0 = (int64_t)ch * 64;
+    for (int e = tid; e < 64 * (TCO / 8); e += NT) {
+      const int p = e / (TCO / 8), cg = e % (TCO / 8);
+      const u32x4 v = *reinterpret_cast<const u32x4*>(a.dz.p + (P0 + p) * a.dz.cs + a.dz.co +
+                                                      cot * TCO + cg * 8);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) sz[(cg * 8 + j) * kLD + p] = (uint16_t)(v[j >> 1] >> (16 * (j & 1)));
+    }
+    for (int e = tid; e < 64 * (TCI / 8); e += NT) {
+      const int p = e / (TCI / 8), cg = e % (TCI / 8);
+      const int64_t P = P0 + p;
+      const int64_t n = P / HW;
+      const int rem = (int)(P - n * HW);
+      const int yy = rem / H + dy, xx = rem % H + dx;
+      u32x4 v = {0u, 0u, 0u, 0u};
+      if ((unsigned)yy < (unsigned)H && (unsigned)xx < (unsigned)H) {
+        const int ys = a.up ? yy >> 1 : yy, xs = a.up ? xx >> 1 : xx;
+        v = *reinterpret_cast<const u32x4*>(a.in.p + ((n * Hin + ys) * Hin + xs) * a.in.cs +
+                                            a.in.co + cit * TCI + cg * 8);
+      }
+#pragma unroll
+      for (int j = 0; j < 8; ++j) sx[(cg * 8 + j) * kLD + p] = (uint16_t)(v[j >> 1] >> (16 * (j & 1)));
+    }
+    __syncthreads();
+    if (do_bias && tid < TCO)
+      for (int p = 0; p < 64; ++p) bsum += bf2f(sz[tid * kLD + p]);
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks) {
+      bf16x8 A[2], Bv[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) A[i] = ld8(sz + (wco + 16 * i + r) * kLD + 32 * ks + 8 * q);
+#pragma unroll
+      for (int j = 0; j < 2; ++j) Bv[j] = ld8(sx + (wci + 16 * j + r) * kLD + 32 * ks + 8 * q);
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[i], Bv[j], acc[i][j], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+
+  const size_t nw = (size_t)a.Cout * 9 * a.Cin;
+  float* wp = a.part + (size_t)split * nw;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int co = cot * TCO + wco + 16 * i + 4 * q + e;
+        const int ci = cit * TCI + wci + 16 * j + r;
+        wp[((size_t)co * 9 + tap) * a.Cin + ci] = acc[i][j][e];
+      }
+  if (do_bias && tid < TCO)
+    a.part[(size_t)gridDim.x * nw + (size_t)split * a.Cout + cot * TCO + tid] = bsum;
+}
+
+// dw[i] = sum_s part[s][i], db[c] = sum_s bpart[s][c], splits in order
+__global__ void wgrad_reduce_kernel(const float* part, int nsplit, int64_t nw, int Cout,
+                                    float* dw, float* db) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < nw) {
+    float s = 0.f;
+    for (int k = 0; k < nsplit; ++k) s += part[(size_t)k * nw + i];
+    dw[i] = s;
+  } else if (i < nw + Cout) {
+    const int c = (int)(i - nw);
+    const float* bp = part + (size_t)nsplit * nw;
+    float s = 0.f;
+    for (int k = 0; k < nsplit; ++k) s += bp[(size_t)k * Cout + c];
+    db[c] = s;
+  }
+}
+
+struct WgradPlan {
+  int tco, tci, nco_t, nci_t, n_chunks, cps, nsplit;
+};
+
+WgradPlan wgrad_plan(int Cout, int Cin, int B, int H) {
+  WgradPlan p;
+  p.tco = Cout >= 64 ? 64 : 32;
+  p.tci = Cin >= 64 ? 64 : 32;
+  p.nco_t = Cout / p.tco;
+  p.nci_t = Cin / p.tci;
+  p.n_chunks = (int)((int64_t)B * H * H / 64);
+  const int base = 9 * p.nco_t * p.nci_t;
+  int want = (2048 + base - 1) / base;
+  want = std::max(1, std::min(want, p.n_chunks));
+  p.cps = (p.n_chunks + want - 1) / want;
+  p.nsplit = (p.n_chunks + p.cps - 1) / p.cps;
+  return p;
+}
+
+// ------------------------------------------------------------ first layer
+__global__ void conv_in_kernel(const float* u, float in_scale, const uint16_t* w,
+                               const float* bias, Tensor out, int Cout, int B, int H) {
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t total = (int64_t)B * H * H * Cout;
+  if (idx >= total) return;
+  const int co = (int)(idx % Cout);
+  const int64_t P = idx / Cout;
+  const int64_t n = P / (H * H);
+  const int rem = (int)(P - n * H * H);
+  const int y = rem / H, x = rem % H;
+  const float* un = u + n * H * H;
+  float z = 0.f;
+  for (int tap = 0; tap < 9; ++tap) {
+    const int yy = y + tap / 3 - 1, xx = x + tap % 3 - 1;
+    if ((unsigned)yy < (unsigned)H && (unsigned)xx < (unsigned)H)
+      z += bf2f(w[co * 9 + tap]) * (in_scale * un[yy * H + xx]);
+  }
+  z = fmaxf(z + bias[co], 0.f);
+  out.p[P * out.cs + out.co + co] = f2bf(z);
+}
+
+// entry t = k * Cout + co: tap k < 9 (weight) or k = 9 (bias) of channel co,
+// summed over this workgroup's pixel range
+__global__ __launch_bounds__(256) void wgrad_in_kernel(const uint16_t* dz, int Cout,
+                                                       const float* u, float in_scale, int B,
+                                                       int H, int64_t cps, float* part) {
+  const int64_t npx = (int64_t)B * H * H;
+  const int64_t p0 = (int64_t)blockIdx.x * cps, p1 = min(npx, p0 + cps);
+  for (int t = threadIdx.x; t < 10 * Cout; t += blockDim.x) {
+    const int co = t % Cout, k = t / Cout;
+    const int dy = k / 3 - 1, dx = k % 3 - 1;
+    float acc = 0.f;
+    for (int64_t P = p0; P < p1; ++P) {
+      const float g = bf2f(dz[P * Cout + co]);
+      if (k == 9) {
+        acc += g;
+      } else {
+        const int64_t n = P / (H * H);
+        const int rem = (int)(P - n * H * H);
+        const int yy = rem / H + dy, xx = rem % H + dx;
+        if ((unsigned)yy < (unsigned)H && (unsigned)xx < (unsigned)H)
+          acc += g * (in_scale * u[n * H * H + yy * H + xx]);
+      }
+    }
+    part[(size_t)blockIdx.x * 10 * Cout + t] = acc;
+  }
+}
+
+__global__ void wgrad_in_reduce_kernel(const float* part, int nsplit, int Cout, float* dw,
+                                       float* db) {
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  if (t >= 10 * Cout) return;
+  float s = 0.f;
+  for (int k = 0; k < nsplit; ++k) s += part[(size_t)k * 10 * Cout + t];
+  const int co = t % Cout, k = t / Cout;
+  if (k < 9)
+    dw[co * 9 + k] = s;
+  else
+    db[co] = s;
+}
+
+// ------------------------------------------------------- pool / up / head
+__global__ void pool_kernel(Tensor in, Tensor out, int C, int B, int H) {
+  const int Ho = H >> 1;
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= (int64_t)B * Ho * Ho * C) return;
+  const int c = (int)(idx % C);
+  const int64_t Q = idx / C;
+  const int64_t n = Q / (Ho * Ho);
+  const int rem = (int)(Q - n * Ho * Ho);
+  const int y = 2 * (rem / Ho), x = 2 * (rem % Ho);
+  const int64_t P = (n * H + y) * H + x;
+  const uint16_t* s = in.p + in.co + c;
+  const float v = bf2f(s[P * in.cs]) + bf2f(s[(P + 1) * in.cs]) + bf2f(s[(P + H) * in.cs]) +
+                  bf2f(s[(P + H + 1) * in.cs]);
+  out.p[Q * out.cs + out.co + c] = f2bf(0.25f * v);
+}
+
+__global__ void pool_back_add_kernel(Tensor dp, Tensor e, Tensor de, int C, int B, int H) {
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= (int64_t)B * H * H * C) return;
+  const int c = (int)(idx % C);
+  const int64_t P = idx / C;
+  const int64_t n = P / (H * H);
+  const int rem = (int)(P - n * H * H);
+  const int Ho = H >> 1;
+  const int64_t Q = (n * Ho + (rem / H) / 2) * Ho + (rem % H) / 2;
+  uint16_t* d = de.p + P * de.cs + de.co + c;
+  float v = bf2f(*d) + 0.25f * bf2f(dp.p[Q * dp.cs + dp.co + c]);
+  if (!(bf2f(e.p[P * e.cs + e.co + c]) > 0.f)) v = 0.f;
+  *d = f2bf(v);
+}
+
+__global__ void up_back_kernel(Tensor du, Tensor d, Tensor dd, int C, int B, int H) {
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= (int64_t)B * H * H * C) return;
+  const int c = (int)(idx % C);
+  const int64_t Q = idx / C;
+  const int64_t n = Q / (H * H);
+  const int rem = (int)(Q - n * H * H);
+  const int H2 = 2 * H;
+  const int64_t P = (n * H2 + 2 * (rem / H)) * H2 + 2 * (rem % H);
+  const uint16_t* s = du.p + du.co + c;
+  float v = bf2f(s[P * du.cs]) + bf2f(s[(P + 1) * du.cs]) + bf2f(s[(P + H2) * du.cs]) +
+            bf2f(s[(P + H2 + 1) * du.cs]);
+  if (!(bf2f(d.p[Q * d.cs + d.co + c]) > 0.f)) v = 0.f;
+  dd.p[Q * dd.cs + dd.co + c] = f2bf(v);
+}
+
+__global__ void head_kernel(Tensor d, int C, const float* head, const float* u, float in_scale,
+                            float* x0, int64_t npx) {
+  const int64_t P = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (P >= npx) return;
+  const uint16_t* dp = d.p + P * d.cs + d.co;
+  float s = 0.f;
+  for (int c = 0; c < C; ++c) s += head[c] * bf2f(dp[c]);
+  x0[P] = s + head[C] + head[C + 1] * (in_scale * u[P]);
+}
+
+// per workgroup: sums of diff^2, dx0 * D[c] (c < C), dx0, dx0 * uh
+__global__ __launch_bounds__(256) void head_back_kernel(Tensor d, int C, const float* head,
+                                                        const float* u, float in_scale,
+                                                        const float* x0, const float* target,
+                                                        int64_t npx, Tensor dz, double* part) {
+  __shared__ double red[256];
+  const int64_t P = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const bool in = P < npx;
+  float diff = 0.f, g = 0.f, uh = 0.f;
+  if (in) {
+    diff = x0[P] - target[P];
+    g = 2.f * diff / (float)npx;
+    uh = in_scale * u[P];
+  }
+  const uint16_t* dp = d.p + (in ? P : 0) * d.cs + d.co;
+  for (int k = 0; k < C + 3; ++k) {
+    double v = 0.0;
+    if (in) {
+      if (k < C) {
+        const float dv = bf2f(dp[k]);
+        v = (double)g * dv;
+        dz.p[P * dz.cs + dz.co + k] = f2bf(dv > 0.f ? g * head[k] : 0.f);
+      } else if (k == C) {
+        v = g;
+      } else if (k == C + 1) {
+        v = (double)g * uh;
+      } else {
+        v = (double)diff * diff;
+      }
+    }
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+      if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) part[(size_t)blockIdx.x * (C + 3) + k] = red[0];
+    __syncthreads();
+  }
+}
+
+__global__ void head_reduce_kernel(const double* part, int nblk, int C, double* loss,
+                                   float* dhead, double inv_npx) {
+  const int k = threadIdx.x;
+  if (k >= C + 3) return;
+  double s = 0.0;
+  for (int b = 0; b < nblk; ++b) s += part[(size_t)b * (C + 3) + k];
+  if (k < C + 2)
+    dhead[k] = (float)s;
+  else
+    *loss = s * inv_npx;
+}
+
+__global__ void adam_kernel(float* p, const float* g, float* m, float* v, int64_t n, float b1,
+                            float b2, float lr_t, float eps_t) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.f - b1) * gi;
+  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  p[i] -= lr_t * mi / (sqrtf(vi) + eps_t);
+}
+
+__global__ void cast_weights_kernel(const float* w, uint16_t* w16, uint16_t* wt16, int Cout,
+                                    int Cin) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= (int64_t)Cout * 9 * Cin) return;
+  const int co = (int)(i / (9 * Cin));
+  const int rem = (int)(i - (int64_t)co * 9 * Cin);
+  const int tap = rem / Cin, ci = rem % Cin;
+  const uint16_t h = f2bf(w[i]);
+  w16[i] = h;
+  if (wt16) wt16[((size_t)ci * 9 + (8 - tap)) * Cout + co] = h;
+}
+
+__global__ void zero_kernel(float* x, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) x[i] = 0.f;
+}
+
+unsigned blocks256(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+}  // namespace
+
+// ----------------------------------------------------------------- launchers
+hipError_t launch_conv3x3(const ConvArgs& a, hipStream_t st) {
+  const int64_t npx = (int64_t)a.B * a.H * a.H;
+  const int64_t tiles = (npx / 64) * (a.Cout / 32);
+  const int64_t blocks = (tiles + kCW - 1) / kCW;
+  hipLaunchKernelGGL(conv3x3_kernel, dim3(grid8(blocks)), dim3(64 * kCW), 0, st, a, tiles);
+  return hipGetLastError();
+}
+
+// Upper bound over every batch size up to B: a plan never uses more splits
+// than min(ceil(2048 / base), n_chunks), and that bound grows with B.
+size_t wgrad_part_floats(int Cout, int Cin, int B, int H) {
+  const WgradPlan p = wgrad_plan(Cout, Cin, B, H);
+  const int base = 9 * p.nco_t * p.nci_t;
+  const int bound = std::max(1, std::min((2048 + base - 1) / base, p.n_chunks));
+  return (size_t)bound * ((size_t)Cout * 9 * Cin + Cout);
+}
+
+hipError_t launch_wgrad(const WgradArgs& a, hipStream_t st) {
+  const WgradPlan p = wgrad_plan(a.Cout, a.Cin, a.B, a.H);
+  const dim3 grid(p.nsplit, 9, p.nco_t * p.nci_t);
+  if (p.tco == 64 && p.tci == 64)
+    hipLaunchKernelGGL((wgrad_kernel<64, 64>), grid, dim3(256), 0, st, a, p.n_chunks, p.cps, p.nci_t);
+  else if (p.tco == 64)
+    hipLaunchKernelGGL((wgrad_kernel<64, 32>), grid, dim3(128), 0, st, a, p.n_chunks, p.cps, p.nci_t);
+  else if (p.tci == 64)
+    hipLaunchKernelGGL((wgrad_kernel<32, 64>), grid, dim3(128), 0, st, a, p.n_chunks, p.cps, p.nci_t);
+  else
+    hipLaunchKernelGGL((wgrad_kernel<32, 32>), grid, dim3(64), 0, st, a, p.n_chunks, p.cps, p.nci_t);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t nw = (int64_t)a.Cout * 9 * a.Cin;
+  hipLaunchKernelGGL(wgrad_reduce_kernel, dim3(blocks256(nw + a.Cout)), dim3(256), 0, st,
+                     (const float*)a.part, p.nsplit, nw, a.Cout, a.dw, a.db);
+  return hipGetLastError();
+}
+
+hipError_t launch_conv_in(const float* u, double in_scale, const uint16_t* w, const float* bias,
+                          Tensor out, int Cout, int B, int H, hipStream_t st) {
+  const int64_t n = (int64_t)B * H * H * Cout;
+  hipLaunchKernelGGL(conv_in_kernel, dim3(blocks256(n)), dim3(256), 0, st, u, (float)in_scale, w,
+                     bias, out, Cout, B, H);
+  return hipGetLastError();
+}
+
+static int wgrad_in_splits(int B, int H) {
+  const int64_t npx = (int64_t)B * H * H;
+  return (int)std::min<int64_t>(1024, std::max<int64_t>(1, npx / 256));
+}
+
+size_t wgrad_in_part_floats(int Cout, int B, int H) {
+  return (size_t)wgrad_in_splits(B, H) * 10 * Cout;
+}
+
+hipError_t launch_wgrad_in(const uint16_t* dz, int Cout, const float* u, double in_scale, int B,
+                           int H, float* dw, float* db, float* part, hipStream_t st) {
+  const int64_t npx = (int64_t)B * H * H;
+  const int ns = wgrad_in_splits(B, H);
+  const int64_t cps = (npx + ns - 1) / ns;
+  hipLaunchKernelGGL(wgrad_in_kernel, dim3(ns), dim3(256), 0, st, dz, Cout, u, (float)in_scale,
+                     B, H, cps, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(wgrad_in_reduce_kernel, dim3(blocks256(10 * Cout)), dim3(256), 0, st,
+                     (const float*)part, ns, Cout, dw, db);
+  return hipGetLastError();
+}
+
+hipError_t launch_pool(Tensor in, Tensor out, int C, int B, int H, hipStream_t st) {
+  const int64_t n = (int64_t)B * (H / 2) * (H / 2) * C;
+  hipLaunchKernelGGL(pool_kernel, dim3(blocks256(n)), dim3(256), 0, st, in, out, C, B, H);
+  return hipGetLastError();
+}
+
+hipError_t launch_pool_back_add(Tensor dp, Tensor e, Tensor de, int C, int B, int H,
+                                hipStream_t st) {
+  const int64_t n = (int64_t)B * H * H * C;
+  hipLaunchKernelGGL(pool_back_add_kernel, dim3(blocks256(n)), dim3(256), 0, st, dp, e, de, C, B,
+                     H);
+  return hipGetLastError();
+}
+
+hipError_t launch_up_back(Tensor du, Tensor d, Tensor dd, int C, int B, int H, hipStream_t st) {
+  const int64_t n = (int64_t)B * H * H * C;
+  hipLaunchKernelGGL(up_back_kernel, dim3(blocks256(n)), dim3(256), 0, st, du, d, dd, C, B, H);
+  return hipGetLastError();
+}
+
+hipError_t launch_head(Tensor d, int C, const float* head, const float* u, double in_scale,
+                       float* x0, int64_t npx, hipStream_t st) {
+  hipLaunchKernelGGL(head_kernel, dim3(blocks256(npx)), dim3(256), 0, st, d, C, head, u,
+                     (float)in_scale, x0, npx);
+  return hipGetLastError();
+}
+
+size_t head_part_doubles(int C, int64_t npx) { return (size_t)blocks256(npx) * (C + 3); }
+
+hipError_t launch_head_back(Tensor d, int C, const float* head, const float* u, double in_scale,
+                            const float* x0, const float* target, int64_t npx, Tensor dz,
+                            double* part, double* loss, float* dhead, hipStream_t st) {
+  const unsigned nblk = blocks256(npx);
+  hipLaunchKernelGGL(head_back_kernel, dim3(nblk), dim3(256), 0, st, d, C, head, u,
+                     (float)in_scale, x0, target, npx, dz, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(head_reduce_kernel, dim3(1), dim3(((C + 3 + 63) / 64) * 64), 0, st,
+                     (const double*)part, (int)nblk, C, loss, dhead, 1.0 / (double)npx);
+  return hipGetLastError();
+}
+
+hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float beta1,
+                       float beta2, float lr_t, float eps_t, hipStream_t st) {
+  hipLaunchKernelGGL(adam_kernel, dim3(blocks256(n)), dim3(256), 0, st, p, g, m, v, n, beta1,
+                     beta2, lr_t, eps_t);
+  return hipGetLastError();
+}
+
+hipError_t launch_cast_weights(const float* w, uint16_t* w16, uint16_t* wt16, int Cout, int Cin,
+                               hipStream_t st) {
+  const int64_t n = (int64_t)Cout * 9 * Cin;
+  hipLaunchKernelGGL(cast_weights_kernel, dim3(blocks256(n)), dim3(256), 0, st, w, w16, wt16,
+                     Cout, Cin);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero(float* x, int64_t n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(zero_kernel, dim3(blocks256(n)), dim3(256), 0, st, x, n);
+  return hipGetLastError();
+}
+
+}  // namespace cnn
+}  // namespace slim

@@ -581,6 +581,17 @@ __global__ __launch_bounds__(256) void transpose_kernel(const float* __restrict_
   }
 }
 
+// out[s][i][t] = b[s][ids[i]][t]: rows of the sinogram for a list of angles
+template <typename T>
+__global__ __launch_bounds__(256) void gather_rows_kernel(const T* __restrict__ b, int n_angles,
+                                                          int R, AngleList ids,
+                                                          float* __restrict__ out) {
+  const int i = blockIdx.y, s = blockIdx.z;
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  if (t >= R) return;
+  out[((size_t)s * ids.n + i) * R + t] = tof(b[((size_t)s * n_angles + ids.id[i]) * R + t]);
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------- launchers
@@ -748,6 +759,18 @@ hipError_t launch_transpose(const float* src, float* dst, int N, int B, size_t s
   const int t = (N + kTile - 1) / kTile;
   hipLaunchKernelGGL(transpose_kernel, dim3(t, t, B), dim3(256), 0, st, src, dst, N, stride, bs,
                      bsT);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_rows(const void* b, int b_bf16, int n_angles, int R, int B,
+                              const AngleList& ids, float* out, hipStream_t st) {
+  const dim3 grid((R + 255) / 256, ids.n, B);
+  if (b_bf16)
+    hipLaunchKernelGGL(gather_rows_kernel<uint16_t>, grid, dim3(256), 0, st, (const uint16_t*)b,
+                       n_angles, R, ids, out);
+  else
+    hipLaunchKernelGGL(gather_rows_kernel<float>, grid, dim3(256), 0, st, (const float*)b,
+                       n_angles, R, ids, out);
   return hipGetLastError();
 }
 

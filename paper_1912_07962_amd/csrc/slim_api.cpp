@@ -22,6 +22,7 @@
 
 #include "slim_internal.h"
 #include "pcg.h"
+#include "cnn_internal.h"
 
 using namespace slim;
 
@@ -73,6 +74,8 @@ std::vector<int> epoch_order(int M, int e, uint64_t seed) {
 
 }  // namespace
 
+slim_status slim::set_error(slim_status s, const std::string& msg) { return fail(s, msg); }
+
 struct slim_ctx {
   int N = 0, B = 1, n_angles = 0, R = 0, r = 0, g = 1;
   double lam = 0.0;
@@ -105,6 +108,8 @@ struct slim_ctx {
   double* d_norms = nullptr;   // [B][3]
   float* d_xT = nullptr;       // [B][N][N]
   float* d_tmp = nullptr;      // [B][N][N] scratch image (public projector)
+  float* d_gather = nullptr;   // sinogram rows of an angle list [B][n][R]
+  size_t gather_cap = 0;       // floats allocated in d_gather
   float* d_fpart = nullptr;    // forward projector partial sums
   size_t fpart_cap = 0;        // floats allocated in d_fpart
   uint16_t* d_xs = nullptr;    // bf16 shadow of x        [B][N][N] (precision BF16)
@@ -132,6 +137,7 @@ struct slim_ctx {
     (void)hipFree(d_xT);
     (void)hipFree(d_tmp);
     (void)hipFree(d_fpart);
+    (void)hipFree(d_gather);
     (void)hipFree(d_xs);
     (void)hipFree(d_xsT);
     pcg_free(pcg);
@@ -584,6 +590,67 @@ slim_status slim_backproject(slim_ctx* c, const int32_t* ids, int n_ids, const f
   ba.img_stride = c->img_elems();
   ba.mode = 0;
   HIP_TRY(launch_back(ba, c->st));
+  return SLIM_OK;
+}
+
+slim_status slim_data_backprojection(slim_ctx* c, const int32_t* ids, int n_ids, float* out) {
+  if (!c) return fail(SLIM_EINVAL, "ctx is NULL");
+  slim_status s = check_ids(c, ids, n_ids, false);
+  if (s != SLIM_OK) return s;
+  if (!out) return fail(SLIM_EINVAL, "out is NULL");
+  if (!c->bound) return fail(SLIM_ESTATE, "no data bound (slim_set_data)");
+  const AngleList l = make_list(ids, n_ids);
+  const size_t need = (size_t)c->B * n_ids * c->R;
+  if (need > c->gather_cap) {
+    HIP_TRY(hipStreamSynchronize(c->st));
+    HIP_TRY(hipFree(c->d_gather));
+    c->d_gather = nullptr;
+    c->gather_cap = 0;
+    if (hipMalloc((void**)&c->d_gather, need * sizeof(float)) != hipSuccess)
+      return fail(SLIM_ENOMEM, "gather workspace does not fit");
+    c->gather_cap = need;
+  }
+  HIP_TRY(launch_gather_rows(c->b, c->bf16() ? 1 : 0, c->n_angles, c->R, c->B, l, c->d_gather,
+                             c->st));
+  BackArgs ba;
+  ba.geom = c->d_geom;
+  ba.N = c->N;
+  ba.R = c->R;
+  ba.B = c->B;
+  ba.ids = &l;
+  ba.v32 = c->d_gather;
+  ba.v_stride = (size_t)n_ids * c->R;
+  ba.out = out;
+  ba.img_stride = c->img_elems();
+  ba.mode = 0;
+  HIP_TRY(launch_back(ba, c->st));
+  return SLIM_OK;
+}
+
+slim_status slim_warmstart(slim_ctx* c, slim_cnn* net, const int32_t* ids, int n_ids, float* x0,
+                           int* used_net) {
+  if (used_net) *used_net = 0;
+  if (!c) return fail(SLIM_EINVAL, "ctx is NULL");
+  slim_status s = check_ids(c, ids, n_ids, false);
+  if (s != SLIM_OK) return s;
+  if (!x0) return fail(SLIM_EINVAL, "x0 is NULL");
+  if (!c->bound) return fail(SLIM_ESTATE, "no data bound (slim_set_data)");
+  if (net && cnn_side(net) != c->N) return fail(SLIM_EINVAL, "network image size differs from N");
+  const size_t nimg = c->img_elems() * c->B;
+  if (!cnn_usable(net)) {
+    HIP_TRY(hipMemsetAsync(x0, 0, nimg * sizeof(float), c->st));
+    return SLIM_OK;
+  }
+  s = slim_data_backprojection(c, ids, n_ids, c->d_tmp);
+  if (s != SLIM_OK) return s;
+  const int mb = cnn_max_batch(net);
+  for (int b0 = 0; b0 < c->B; b0 += mb) {
+    const int nb = std::min(mb, c->B - b0);
+    s = cnn_forward_on(net, c->d_tmp + (size_t)b0 * c->img_elems(),
+                       x0 + (size_t)b0 * c->img_elems(), nb, c->st);
+    if (s != SLIM_OK) return s;
+  }
+  if (used_net) *used_net = 1;
   return SLIM_OK;
 }
 

@@ -184,5 +184,13 @@ hipError_t launch_chol_solve(const double* L, int64_t ld, int p, int nr, const d
                              size_t rhs_stride, double* z, size_t z_stride, int B,
                              hipStream_t st);
 
+// out[s][i][t] = b[s][ids[i]][t] as float32 for B slices (b float32 or bf16,
+// slice stride n_angles * R).
+hipError_t launch_gather_rows(const void* b, int b_bf16, int n_angles, int R, int B,
+                              const AngleList& ids, float* out, hipStream_t st);
+
+// Record msg as the library's last error message and return s.
+slim_status set_error(slim_status s, const std::string& msg);
+
 
 }  // namespace slim

@@ -17,6 +17,7 @@ import torch  # loads the HIP runtime first, so libslim binds to the same one
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "_lib", "libslim.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "slim.h")
+HEADERS = [HEADER, os.path.join(os.path.dirname(_HERE), "include", "slim_cnn.h")]
 
 SLIM_OK, SLIM_EINVAL, SLIM_ENOMEM, SLIM_EDEVICE, SLIM_ENUMERIC, SLIM_ENOTCONV, SLIM_ESTATE = range(7)
 PREC = {"fp32": 0, "bf16": 1}
@@ -53,6 +54,12 @@ class SolveInfo(ctypes.Structure):
                 ("pcg_iters", ctypes.c_int)]
 
 
+class CnnDesc(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int), ("levels", ctypes.c_int), ("channels", ctypes.c_int * 4),
+                ("max_batch", ctypes.c_int), ("in_scale", ctypes.c_double),
+                ("stream", ctypes.c_void_p)]
+
+
 _lib = None
 
 
@@ -81,6 +88,17 @@ def load() -> ctypes.CDLL:
         "slim_slice_norms": (I, [P, ctypes.POINTER(D), I]),
         "slim_profile": (I, [P, I]),
         "slim_kernel_stats": (I, [P, I, ctypes.POINTER(D), ctypes.POINTER(ctypes.c_int64)]),
+        "slim_data_backprojection": (I, [P, i32p, I, P]),
+        "slim_warmstart": (I, [P, P, i32p, I, P, ctypes.POINTER(I)]),
+        "slim_cnn_create": (I, [ctypes.POINTER(P), ctypes.POINTER(CnnDesc)]),
+        "slim_cnn_num_params": (ctypes.c_int64, [P]),
+        "slim_cnn_set_params": (I, [P, P, ctypes.c_int64]),
+        "slim_cnn_get_params": (I, [P, P, ctypes.c_int64]),
+        "slim_cnn_forward": (I, [P, P, P, I]),
+        "slim_cnn_loss_grad": (I, [P, P, P, I, ctypes.POINTER(D), P]),
+        "slim_cnn_adam": (I, [P, D, D, D, D]),
+        "slim_cnn_forward_flops": (D, [P]),
+        "slim_cnn_destroy": (None, [P]),
         "slim_destroy": (None, [P]),
         "slim_strerror": (ctypes.c_char_p, [I]),
         "slim_last_error": (ctypes.c_char_p, []),
@@ -94,8 +112,8 @@ def load() -> ctypes.CDLL:
 
 
 def header_symbols() -> list[str]:
-    """Names of the functions declared in include/slim.h."""
-    txt = open(HEADER).read()
+    """Names of the functions declared in include/slim.h and slim_cnn.h."""
+    txt = "".join(open(h).read() for h in HEADERS)
     return sorted(set(re.findall(r"\b(slim_[a-z_]+)\s*\(", txt)))
 
 
@@ -188,6 +206,27 @@ class Slim:
         _check(load().slim_slice_norms(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                        self.B))
         return out
+
+    def data_backprojection(self, angle_ids, out=None):
+        """out = A_ids^T b_ids for the bound data, every slice."""
+        a, p, n = _ids(angle_ids)
+        if out is None:
+            shape = (self.B, self.N, self.N) if self.B > 1 else (self.N, self.N)
+            out = torch.empty(shape, dtype=torch.float32, device="cuda")
+        _check(load().slim_data_backprojection(self._h, p, n, _ptr(out, torch.float32, "out")))
+        return out
+
+    def warmstart(self, angle_ids, x0=None, net: "Cnn | None" = None):
+        """x0 = net(A_ids^T b_ids) for the bound data (zeros without a usable
+        network).  Returns (x0, used_net)."""
+        a, p, n = _ids(angle_ids)
+        if x0 is None:
+            shape = (self.B, self.N, self.N) if self.B > 1 else (self.N, self.N)
+            x0 = torch.empty(shape, dtype=torch.float32, device="cuda")
+        used = ctypes.c_int(0)
+        _check(load().slim_warmstart(self._h, net._h if net is not None else None, p, n,
+                                     _ptr(x0, torch.float32, "x0"), ctypes.byref(used)))
+        return x0, bool(used.value)
 
     def solve(self, b, x, x_true=None, tol: float = 1e-2, max_epochs: int = 1) -> dict:
         self._keep = [b, x, x_true]
@@ -284,4 +323,124 @@ def init_error(**kw) -> int:
                        kw.get("n_rays", 91), kw.get("r", 5), kw.get("lam", 1e-2), ctypes.byref(o))
     if st == SLIM_OK:
         lib.slim_destroy(h)
+    return st
+
+
+def cnn_layout(channels) -> list[tuple[str, tuple]]:
+    """(name, shape) of the packed warm-start parameters, in order: per conv
+    layer (forward order) weights [Cout, 3, 3, Cin] then bias [Cout]; then
+    head.w [c_1], head.b [1], head.cu [1]."""
+    c = list(channels)
+    L = len(c)
+    layers = [("e1a", c[0], 1), ("e1b", c[0], c[0])]
+    for l in range(2, L + 1):
+        layers += [(f"e{l}a", c[l - 1], c[l - 2]), (f"e{l}b", c[l - 1], c[l - 1])]
+    for l in range(L - 1, 0, -1):
+        layers += [(f"u{l}", c[l - 1], c[l]), (f"d{l}a", c[l - 1], 2 * c[l - 1]),
+                   (f"d{l}b", c[l - 1], c[l - 1])]
+    out = []
+    for name, co, ci in layers:
+        out += [(name + ".w", (co, 3, 3, ci)), (name + ".b", (co,))]
+    return out + [("head.w", (c[0],)), ("head.b", (1,)), ("head.cu", (1,))]
+
+
+class Cnn:
+    """The warm-start U-Net (include/slim_cnn.h) on the current device and
+    torch stream."""
+
+    def __init__(self, N: int, channels=(32, 64, 128, 256), max_batch: int = 8,
+                 in_scale: float = 1.0, stream=None):
+        lib = load()
+        self.N, self.channels, self.max_batch = int(N), tuple(int(c) for c in channels), int(max_batch)
+        self.in_scale = float(in_scale)
+        d = CnnDesc()
+        d.N = self.N
+        d.levels = len(self.channels)
+        for i, c in enumerate(self.channels[:4]):
+            d.channels[i] = c
+        d.max_batch = self.max_batch
+        d.in_scale = self.in_scale
+        if stream is None and torch.cuda.is_available():
+            stream = torch.cuda.current_stream()
+        d.stream = ctypes.c_void_p(stream.cuda_stream if stream is not None else 0)
+        h = ctypes.c_void_p()
+        _check(lib.slim_cnn_create(ctypes.byref(h), ctypes.byref(d)))
+        self._h = h
+        self.n_params = int(lib.slim_cnn_num_params(h))
+        self.layout = cnn_layout(self.channels)
+
+    def pack(self, params: dict) -> np.ndarray:
+        return np.concatenate([np.asarray(params[k], np.float32).reshape(-1)
+                               for k, _ in self.layout])
+
+    def unpack(self, vec) -> dict:
+        out, o = {}, 0
+        for k, shape in self.layout:
+            n = int(np.prod(shape))
+            out[k] = np.asarray(vec[o:o + n]).reshape(shape)
+            o += n
+        return out
+
+    def set_params(self, params):
+        v = self.pack(params) if isinstance(params, dict) else np.asarray(params, np.float32)
+        v = np.ascontiguousarray(v, dtype=np.float32)
+        _check(load().slim_cnn_set_params(self._h, v.ctypes.data_as(ctypes.c_void_p), v.size))
+
+    def get_params(self) -> np.ndarray:
+        v = np.empty(self.n_params, dtype=np.float32)
+        _check(load().slim_cnn_get_params(self._h, v.ctypes.data_as(ctypes.c_void_p), v.size))
+        return v
+
+    def forward(self, u, x0=None):
+        B = u.shape[0]
+        if x0 is None:
+            x0 = torch.empty_like(u)
+        _check(load().slim_cnn_forward(self._h, _ptr(u, torch.float32, "u"),
+                                       _ptr(x0, torch.float32, "x0"), int(B)))
+        return x0
+
+    def loss_grad(self, u, target, want_grad: bool = False):
+        """(loss, gradient as a packed float32 vector or None)."""
+        loss = ctypes.c_double(0.0)
+        g = np.empty(self.n_params, dtype=np.float32) if want_grad else None
+        _check(load().slim_cnn_loss_grad(self._h, _ptr(u, torch.float32, "u"),
+                                         _ptr(target, torch.float32, "target"), int(u.shape[0]),
+                                         ctypes.byref(loss),
+                                         g.ctypes.data_as(ctypes.c_void_p) if want_grad else None))
+        return loss.value, g
+
+    def adam(self, lr: float, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8):
+        _check(load().slim_cnn_adam(self._h, float(lr), float(beta1), float(beta2), float(eps)))
+
+    def forward_flops(self) -> float:
+        return float(load().slim_cnn_forward_flops(self._h))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().slim_cnn_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def cnn_create_error(**kw) -> int:
+    """Status of slim_cnn_create for the given description (argument checks
+    run before any device call)."""
+    lib = load()
+    d = CnnDesc()
+    d.N = kw.get("N", 64)
+    ch = kw.get("channels", (32, 64))
+    d.levels = kw.get("levels", len(ch))
+    for i, c in enumerate(list(ch)[:4]):
+        d.channels[i] = c
+    d.max_batch = kw.get("max_batch", 1)
+    d.in_scale = kw.get("in_scale", 1.0)
+    h = ctypes.c_void_p()
+    st = lib.slim_cnn_create(ctypes.byref(h), ctypes.byref(d))
+    if st == SLIM_OK:
+        lib.slim_cnn_destroy(h)
     return st

@@ -2,6 +2,8 @@
 rejects invalid arguments before touching a device (no compute calls)."""
 import ctypes
 
+import numpy as np
+
 import pytest
 
 from paper_1912_07962_amd import slim
@@ -45,3 +47,39 @@ def test_null_handles_are_rejected():
     assert lib.slim_project(None, None, 0, None, None) == slim.SLIM_EINVAL
     assert lib.slim_slice_norms(None, None, 0) == slim.SLIM_EINVAL
     lib.slim_destroy(None)
+
+
+@pytest.mark.parametrize("kw", [
+    dict(N=0), dict(N=20), dict(N=24, channels=(32, 64, 128)), dict(levels=1, channels=(32,)),
+    dict(levels=5, channels=(32, 64, 128, 256)), dict(channels=(48, 64)), dict(channels=(32, 0)),
+    dict(channels=(32, 1024)), dict(max_batch=0), dict(in_scale=0.0),
+    dict(in_scale=float("nan")), dict(in_scale=float("inf")),
+])
+def test_cnn_create_rejects_bad_descriptions(kw):
+    assert slim.cnn_create_error(**kw) == slim.SLIM_EINVAL
+    assert slim.load().slim_last_error() != b""
+
+
+def test_cnn_null_handles_are_rejected():
+    lib = slim.load()
+    assert lib.slim_cnn_create(None, None) == slim.SLIM_EINVAL
+    assert lib.slim_cnn_num_params(None) == 0
+    assert lib.slim_cnn_forward(None, None, None, 1) == slim.SLIM_EINVAL
+    assert lib.slim_cnn_loss_grad(None, None, None, 1, None, None) == slim.SLIM_EINVAL
+    assert lib.slim_cnn_adam(None, 1e-3, 0.9, 0.999, 1e-8) == slim.SLIM_EINVAL
+    assert lib.slim_cnn_set_params(None, None, 0) == slim.SLIM_EINVAL
+    assert lib.slim_cnn_get_params(None, None, 0) == slim.SLIM_EINVAL
+    assert lib.slim_warmstart(None, None, None, 0, None, None) == slim.SLIM_EINVAL
+    assert lib.slim_data_backprojection(None, None, 0, None) == slim.SLIM_EINVAL
+    assert lib.slim_cnn_forward_flops(None) == 0.0
+    lib.slim_cnn_destroy(None)
+
+
+def test_cnn_layout_counts():
+    from paper_1912_07962_amd import cnn_layout
+    lay = cnn_layout((32, 64, 128, 256))
+    names = [k for k, _ in lay]
+    assert names[:4] == ["e1a.w", "e1a.b", "e1b.w", "e1b.b"]
+    assert names[-3:] == ["head.w", "head.b", "head.cu"]
+    assert len(names) == 2 * 17 + 3
+    assert sum(int(np.prod(s)) for _, s in lay) == 2140066
