@@ -27,6 +27,10 @@ time).  The line also carries:
   volume        512 slices of 512^2 (360 angles x 725 rays, 4 angles/block,
                 r = 8): fwd/back rays/s of one block over all slices and
                 the time of whole slimLS steps;
+  warm_start    the learned warm start on 256^2 (180 angles, 1 angle/block,
+                r = 5): steps to each held-out sample's e* from x0 = 0 and
+                from x0 = CNN(u), single-slice wall-clock time-to-target with
+                the warm start's cost included, CNN inference throughput;
   cpu_baseline  the FP64 oracle's steps of the same run on the host.
 """
 from __future__ import annotations
@@ -43,6 +47,7 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP32_VECTOR_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
+PEAK_BF16_TFLOPS = 2500.0
 
 
 def window_nnz(N, thetas):
@@ -257,6 +262,86 @@ def volume_bench(dev, B, steps):
             "kernel_ms": {k: v2["total_ms"] for k, v2 in stats.items()}}
 
 
+
+def warm_bench(dev, n_test, n_timed):
+    """Learned warm start on the 256^2 workload (180 angles x 363 rays, 1
+    angle/block, r = 5, lambda = 1e-2) with the trained parameters shipped
+    in the package: iterations to each test sample's e* from x0 = 0 and from
+    x0 = CNN(u) over n_test held-out seeds (batched), then wall-clock
+    time-to-target of single-slice runs for n_timed of them, the warm start's
+    back-projection and CNN inference included."""
+    import numpy as np
+    import torch
+    from paper_1912_07962_amd import Cnn, Slim
+    from paper_1912_07962_amd import warmstart as ws
+
+    cfg = ws.config()
+    path = os.path.join(ROOT, "paper_1912_07962_amd", "weights", "warmstart_256.npy")
+    net = Cnn(cfg["N"], ws.CHANNELS, max_batch=16, in_scale=ws.in_scale(cfg))
+    net.set_params(np.load(path))
+    seeds = range(cfg["test_seeds"][0], cfg["test_seeds"][0] + n_test)
+    print(f"bench: warm start, {n_test} test samples", file=sys.stderr, flush=True)
+    xte, bte = ws.make_samples(seeds, workers=min(16, os.cpu_count() or 1), cfg=cfg)
+    plain = ws.plain_data(bte, xte, cfg)
+    ev = ws.evaluate(net, bte, xte, plain, cfg)
+
+    # CNN inference throughput (batch 16)
+    u16 = plain["u"][:16].contiguous()
+    x16 = torch.empty_like(u16)
+    net.forward(u16, x16)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        net.forward(u16, x16)
+    e1.record()
+    torch.cuda.synchronize()
+    t_inf = e0.elapsed_time(e1) / 10 * 1e-3
+    inf_tflops = net.forward_flops() * 16 / t_inf / 1e12
+
+    # single-slice wall clock
+    N, g, r = cfg["N"], cfg["g"], cfg["r"]
+    sched = ws.schedule(cfg)
+    first = ws.first_angles(cfg)
+    s = Slim(N, cfg["n_angles"], r=r, lam=cfg["lam"], angles_per_block=g, gram_mode="chol")
+    x = torch.zeros((N, N), dtype=torch.float32, device=dev)
+    t_plain, t_warm, st_plain, st_warm = [], [], [], []
+    for i in range(n_timed):
+        bd = torch.as_tensor(bte[i], device=dev)
+        xt = torch.as_tensor(xte[i], device=dev)
+        nrm = float(np.linalg.norm(xte[i]))
+        e_star = float(plain["e_star"][i])
+        for warm in (False, True):
+            x.zero_()
+            s.set_data(bd, x, xt)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            k = 0
+            if warm:
+                s.warmstart(first, x0=x, net=net)  # into the bound x: restarts from x0
+            err = float(torch.linalg.vector_norm(x - xt)) / nrm if warm else 1.0
+            while err > e_star and k < len(sched):
+                beta = int(sched[k])
+                info = s.step(list(range(beta * g, beta * g + g)))
+                k += 1
+                err = info["err_norm"] / nrm
+            torch.cuda.synchronize()
+            (t_warm if warm else t_plain).append(time.perf_counter() - t0)
+            (st_warm if warm else st_plain).append(k)
+    s.close()
+    ev.update({"test_samples": n_test, "timed_samples": n_timed,
+               "plain_s_mean": float(np.mean(t_plain)), "warm_s_mean": float(np.mean(t_warm)),
+               "timed_plain_steps_mean": float(np.mean(st_plain)),
+               "timed_warm_steps_mean": float(np.mean(st_warm)),
+               "speedup_vs_plain": float(np.mean(t_plain) / np.mean(t_warm)),
+               "cnn_inference_ms_batch16": t_inf * 1e3, "cnn_inference_tflops": inf_tflops,
+               "cnn_inference_mfma_frac": inf_tflops / PEAK_BF16_TFLOPS})
+    net.close()
+    print(f"bench: warm {ev['warm_s_mean']:.3f} s vs plain {ev['plain_s_mean']:.3f} s per slice",
+          file=sys.stderr, flush=True)
+    return ev
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -271,6 +356,13 @@ def main():
     ap.add_argument("--volume-slices", type=int, default=512,
                     help="slices of the 512^2 volume workload (0 skips it)")
     ap.add_argument("--volume-steps", type=int, default=4, help="timed volume steps")
+    ap.add_argument("--calibration-copy", action="store_true",
+                    help="copy 256 MiB once before timing (a kernel of known traffic for "
+                         "scaling hardware byte counters)")
+    ap.add_argument("--warm-test", type=int, default=256,
+                    help="held-out samples of the warm-start evaluation (0 skips it)")
+    ap.add_argument("--warm-timed", type=int, default=8,
+                    help="of those, samples timed as single-slice runs")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only; --gpus must be 1 "
@@ -298,6 +390,12 @@ def main():
     sched = synth.schedule(M, 1 + (args.warmup + args.steps) // M + 1, cfg["schedule_seed"])
     theta = np.arange(na) * (np.pi / na)
 
+    if args.calibration_copy:
+        src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     s.set_data(bd, x, xt)
     print(f"bench: warmup {args.warmup} steps", file=sys.stderr, flush=True)
     for k in range(args.warmup):
@@ -369,6 +467,10 @@ def main():
     if not args.no_batched:
         batched = batched_ttr(cfg, s, sched, dev, args.batch)
 
+    warm = None
+    if args.warm_test > 0:
+        warm = warm_bench(dev, args.warm_test, min(args.warm_timed, args.warm_test))
+
     volume = None
     if args.volume_slices > 0:
         volume = volume_bench(dev, args.volume_slices, args.volume_steps)
@@ -404,6 +506,7 @@ def main():
         "time_to_target": ttr,
         "batched": batched,
         "volume": volume,
+        "warm_start": warm,
         "cg_iters_per_step": float(np.mean(iters)),
         "event_ms_timed_region": ev_ms,
         "kernel_ms": {k: v2["total_ms"] for k, v2 in stats.items()},

@@ -81,7 +81,9 @@ slim_status slim_cnn_adam(slim_cnn* net, double lr, double beta1, double beta2, 
  * listed angles (host int32, the angles of the first sampled blocks), then
  * x0 = net(u) for every slice, in chunks of max_batch.  With net == NULL or
  * invalid parameters x0 = 0 and *used_net = 0 (the fallback); otherwise
- * *used_net = 1.  x0: device [n_slices][N][N] float32.  Uses ctx's stream.
+ * *used_net = 1.  x0: device [n_slices][N][N] float32.  If x0 is the image
+ * bound by slim_set_data, the iteration restarts from it (k = 0, empty
+ * memory window, as after slim_set_data).  Uses ctx's stream.
  * Errors: SLIM_EINVAL (bad ids, NULL x0, net->N != N), SLIM_ESTATE (no data
  * bound), SLIM_EDEVICE. */
 slim_status slim_warmstart(slim_ctx* ctx, slim_cnn* net, const int32_t* angle_ids, int n_ids,

@@ -637,9 +637,21 @@ slim_status slim_warmstart(slim_ctx* c, slim_cnn* net, const int32_t* ids, int n
   if (!c->bound) return fail(SLIM_ESTATE, "no data bound (slim_set_data)");
   if (net && cnn_side(net) != c->N) return fail(SLIM_EINVAL, "network image size differs from N");
   const size_t nimg = c->img_elems() * c->B;
+  // x0 may be the bound image: then the iteration restarts from it, with the
+  // projectors' copies of x refreshed
+  auto restart = [&]() -> slim_status {
+    if (x0 != c->x) return SLIM_OK;
+    c->k = 0;
+    c->norms_valid = false;
+    c->window.clear();
+    c->epoch = 0;
+    c->pos = 0;
+    c->total_pcg_iters = 0;
+    return transpose_slices(c);
+  };
   if (!cnn_usable(net)) {
     HIP_TRY(hipMemsetAsync(x0, 0, nimg * sizeof(float), c->st));
-    return SLIM_OK;
+    return restart();
   }
   s = slim_data_backprojection(c, ids, n_ids, c->d_tmp);
   if (s != SLIM_OK) return s;
@@ -651,7 +663,7 @@ slim_status slim_warmstart(slim_ctx* c, slim_cnn* net, const int32_t* ids, int n
     if (s != SLIM_OK) return s;
   }
   if (used_net) *used_net = 1;
-  return SLIM_OK;
+  return restart();
 }
 
 slim_status slim_gram(slim_ctx* c, const int32_t* ida, int na, const int32_t* idb, int nb, double* out) {

@@ -22,4 +22,4 @@ from .phantom import (  # noqa: F401
     scan_geometry,
     n_rays_for,
 )
-from .configs import CONFIGS, get_config  # noqa: F401
+from .configs import CONFIGS, get_config, warmstart_sample  # noqa: F401

@@ -31,3 +31,13 @@ CONFIGS = {
 
 def get_config(name: str) -> dict:
     return dict(CONFIGS[name])
+
+
+def warmstart_sample(seed: int):
+    """One sample of the warm-start workload: (x_true[256,256], b[180,363])
+    float64; phantom seed ``seed``, noise seed ``seed + 1_000_000``."""
+    from .phantom import make_slice_problem
+    c = CONFIGS["c5"]
+    x, b, _ = make_slice_problem(c["N"], c["n_angles"], c["n_ellipses"], c["noise"], seed,
+                                 seed + 1_000_000)
+    return x, b

@@ -166,6 +166,15 @@ def test_data_backprojection_and_warmstart():
     assert np.array_equal(x0[:1].cpu().numpy(), direct)
     direct = net.forward(_dev(u[1:])).cpu().numpy()
     assert np.array_equal(x0[1:].cpu().numpy(), direct)
+    # into the bound x: the iteration restarts from x0 with fresh projector
+    # copies, exactly as binding x0 with set_data
+    s.warmstart(ids, x0=x, net=net)
+    s.step([5])
+    x_a = x.clone()
+    x.copy_(x0)
+    s.set_data(_dev(b), x)
+    s.step([5])
+    assert torch.equal(x, x_a)
     # size mismatch
     other = Cnn(32, (32, 64), max_batch=1)
     with pytest.raises(SlimError):
