@@ -80,7 +80,16 @@ template <> struct Lane<4> {
 
 // ---------------------------------------------------------------- forward
 constexpr int kFT = 512;      // threads per forward workgroup
-constexpr int kFItems = 4;    // rays per lane (upper bound)
+// Rays per lane, bounded by registers: every ray keeps a 32.32 position and
+// step (4 VGPRs) and one fp64 accumulator per slice of the tile, within 128
+// VGPRs (four waves per SIMD: two 512-lane workgroups per CU).  More rays per workgroup means more
+// angles per pass over the image, i.e. fewer passes.
+constexpr int max_items(int BT) { return BT == 1 ? 10 : (BT == 2 ? 8 : 5); }
+// the instantiated values: 1..6, 8, then the cap
+inline int item_count(int BT, int want) {
+  const int it = want <= 6 ? want : (want <= 8 ? 8 : 10);
+  return it < max_items(BT) ? it : max_items(BT);
+}
 constexpr int kPad = 4;       // zero columns on each side of a band row (keeps rows 16B-aligned)
 constexpr int kPF = 8;        // float4 prefetch registers per lane: H*N*BT/4 <= 8 * kFT
 
@@ -611,6 +620,16 @@ static int num_cu() {
 
 int slice_tile(int B) { return B >= 4 ? 4 : (B >= 2 ? 2 : 1); }
 
+// The forward projector's slice tile: as wide as the batch allows while a
+// band still holds at least kMinRows image rows (the band is 64 KB of LDS,
+// so wide tiles of large images would leave a few rows per barrier).
+constexpr int kMinRows = 8;
+static int fwd_slice_tile(int B, int N) {
+  int bt = slice_tile(B);
+  while (bt > 1 && 16384 / ((N + 2 * kPad) * bt) < kMinRows) bt >>= 1;
+  return bt;
+}
+
 // Launch plan: angles grouped by orientation into chunks, slices into tiles of
 // BT, image bands into groups, with chunks * tiles * groups <= 2 * (number of
 // CUs) where possible, so that a launch is one round of resident workgroups
@@ -628,10 +647,9 @@ static FwdPlan make_plan(const AngleGeom* h_geom, int N, int R, const AngleList&
       }
   pl.n_row = 0;
   for (int s = 0; s < ids.n; ++s) pl.n_row += h_geom[ids.id[s]].colmajor ? 0 : 1;
-  const int BT = slice_tile(B);
-  const int max_items = BT == 4 ? 3 : kFItems;  // register budget with BT accumulators
-  pl.ch = std::max(1, std::min(max_items * kFT / R, ids.n));
-  pl.items = std::min(kFItems, (pl.ch * R + kFT - 1) / kFT);
+  const int BT = fwd_slice_tile(B, N);
+  pl.ch = std::max(1, std::min(max_items(BT) * kFT / R, ids.n));
+  pl.items = item_count(BT, std::max(1, (pl.ch * R + kFT - 1) / kFT));
   pl.n_chunks = (pl.n_row + pl.ch - 1) / pl.ch + (ids.n - pl.n_row + pl.ch - 1) / pl.ch;
   pl.n_tiles = (B + BT - 1) / BT;
   pl.H = std::max(1, std::min(N, 16384 / ((N + 2 * kPad) * BT)));
@@ -650,28 +668,38 @@ size_t forward_partial_floats(const AngleGeom* h_geom, int N, int R, const Angle
 
 int forward_dot_parts(int n_out) { return (n_out + 255) / 256; }
 
+template <int IT, int BT, typename IMG>
+static void launch_it(dim3 grid, size_t lds, hipStream_t st, const AngleGeom* geom, int N, int R,
+                      const FwdPlan& pl, int B, const IMG* img, const IMG* imgT, size_t stride,
+                      float* partial, const int* stop, int stop_stride) {
+  hipLaunchKernelGGL((fwd_band_kernel<IT, BT, IMG>), grid, dim3(kFT), lds, st, geom, N, R, pl, B,
+                     img, imgT, stride, partial, stop, stop_stride);
+}
+
+// items is one of the values item_count() returns for this BT
 template <int BT, typename IMG>
 static void launch_band(int items, dim3 grid, size_t lds, hipStream_t st, const AngleGeom* geom,
                         int N, int R, const FwdPlan& pl, int B, const IMG* img, const IMG* imgT,
                         size_t stride, float* partial, const int* stop, int stop_stride) {
+#define SLIM_FWD_CASE(IT)                                                                 \
+  case IT:                                                                              \
+    launch_it<(IT <= max_items(BT) ? IT : max_items(BT)), BT, IMG>(                     \
+        grid, lds, st, geom, N, R, pl, B, img, imgT, stride, partial, stop, stop_stride); \
+    break;
   switch (items) {
-    case 1:
-      hipLaunchKernelGGL((fwd_band_kernel<1, BT, IMG>), grid, dim3(kFT), lds, st, geom, N, R, pl, B,
-                         img, imgT, stride, partial, stop, stop_stride);
-      break;
-    case 2:
-      hipLaunchKernelGGL((fwd_band_kernel<2, BT, IMG>), grid, dim3(kFT), lds, st, geom, N, R, pl, B,
-                         img, imgT, stride, partial, stop, stop_stride);
-      break;
-    case 3:
-      hipLaunchKernelGGL((fwd_band_kernel<3, BT, IMG>), grid, dim3(kFT), lds, st, geom, N, R, pl, B,
-                         img, imgT, stride, partial, stop, stop_stride);
-      break;
+    SLIM_FWD_CASE(1)
+    SLIM_FWD_CASE(2)
+    SLIM_FWD_CASE(3)
+    SLIM_FWD_CASE(4)
+    SLIM_FWD_CASE(5)
+    SLIM_FWD_CASE(6)
+    SLIM_FWD_CASE(8)
     default:
-      hipLaunchKernelGGL((fwd_band_kernel<4, BT, IMG>), grid, dim3(kFT), lds, st, geom, N, R, pl, B,
-                         img, imgT, stride, partial, stop, stop_stride);
+      launch_it<max_items(BT), BT, IMG>(grid, lds, st, geom, N, R, pl, B, img, imgT, stride,
+                                        partial, stop, stop_stride);
       break;
   }
+#undef SLIM_FWD_CASE
 }
 
 template <typename IMG>
@@ -693,7 +721,7 @@ static void launch_band_bt(int BT, int items, dim3 grid, size_t lds, hipStream_t
 hipError_t launch_forward(const FwdArgs& a, hipStream_t st) {
   if (a.ids->n <= 0) return hipSuccess;
   const FwdPlan pl = make_plan(a.h_geom, a.N, a.R, *a.ids, a.B);
-  const int BT = slice_tile(a.B);
+  const int BT = fwd_slice_tile(a.B, a.N);
   const int total = pl.n_groups * pl.n_chunks * pl.n_tiles;
   const int nwg = (total + 7) / 8 * 8;
   const size_t lds = (size_t)pl.H * (a.N + 2 * kPad) * BT * sizeof(float);
