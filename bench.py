@@ -111,7 +111,7 @@ def plain_ttr(s, bd, x, xt, sched, g, r, M, nrm):
             "s": trace[first][0], "steps": first + 1}
 
 
-def batched_ttr(cfg, s1, sched, dev, B):
+def batched_ttr(cfg, s1, sched, dev, B, autotune=True):
     """B different 1024^2 slices (phantom and noise seeds + slice index) under
     the plain parameters.  Each slice's plain run fixes its target e*_b (its
     error at its stop step); the batched context then steps all B slices
@@ -141,6 +141,7 @@ def batched_ttr(cfg, s1, sched, dev, B):
     xb = torch.zeros((B, N, N), dtype=torch.float32, device=dev)
     sb = Slim(N, na, r=r, lam=lam, n_slices=B, angles_per_block=g, gram_mode="pcg",
               pcg_tol=1e-6)
+    tune = sb.autotune() if autotune else None
     sb.set_data(bd, xb, xt)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -163,14 +164,14 @@ def batched_ttr(cfg, s1, sched, dev, B):
            "batched_wall_s": wall, "batched_amortized_s": wall / B, "batched_steps": k,
            "batched_cg_iters_per_step": iters / k,
            "reached": bool(np.all(rel <= e_star)),
-           "speedup_vs_plain": plain_mean / (wall / B)}
+           "speedup_vs_plain": plain_mean / (wall / B), "autotune": tune}
     print(f"bench: batched {wall:.2f} s for {B} slices ({wall / B:.3f} s each) vs plain "
           f"{plain_mean:.3f} s", file=sys.stderr, flush=True)
     sb.close()
     return out
 
 
-def volume_bench(dev, B, steps):
+def volume_bench(dev, B, steps, autotune=True):
     """512^2 slices of one ellipsoid volume sharing A (360 angles x 725 rays,
     4 angles/block, r = 8, lambda = 1e-3): one-block projector rays/s over
     all slices, then whole slimLS steps after the window has filled."""
@@ -188,6 +189,7 @@ def volume_bench(dev, B, steps):
     bd = torch.as_tensor(bs, dtype=torch.float32, device=dev)
     del xs, bs
     s = Slim(N, na, r=r, lam=lam, n_slices=B, angles_per_block=g, gram_mode="pcg", pcg_tol=1e-6)
+    tune = s.autotune() if autotune else None
     R = s.R
     ell = g * R
     theta = np.arange(na) * (np.pi / na)
@@ -253,7 +255,7 @@ def volume_bench(dev, B, steps):
     fl = flops / max(sum(iters), 1)
     s.close()
     print(f"bench: volume step {wall / steps * 1e3:.1f} ms", file=sys.stderr, flush=True)
-    return {"slices": B, "N": N, "block_rays": ell, "projector": proj,
+    return {"slices": B, "N": N, "block_rays": ell, "projector": proj, "autotune": tune,
             "ms_per_step": wall / steps * 1e3, "steps": steps,
             "slice_rays_per_s": ell * B * steps / wall,
             "cg_iters_per_step": float(np.mean(iters)),
@@ -356,6 +358,8 @@ def main():
     ap.add_argument("--volume-slices", type=int, default=512,
                     help="slices of the 512^2 volume workload (0 skips it)")
     ap.add_argument("--volume-steps", type=int, default=4, help="timed volume steps")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the built-in projector launch shapes")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="copy 256 MiB once before timing (a kernel of known traffic for "
                          "scaling hardware byte counters)")
@@ -384,6 +388,7 @@ def main():
     xt = torch.as_tensor(x_true, dtype=torch.float32, device=dev)
     x = torch.zeros((N, N), dtype=torch.float32, device=dev)
     s = Slim(N, na, r=r, lam=lam, angles_per_block=g, gram_mode="pcg", pcg_tol=1e-6)
+    tune = None if args.no_autotune else s.autotune()
     R = s.R
     ell = g * R
     M = na // g
@@ -465,7 +470,7 @@ def main():
 
     batched = None
     if not args.no_batched:
-        batched = batched_ttr(cfg, s, sched, dev, args.batch)
+        batched = batched_ttr(cfg, s, sched, dev, args.batch, not args.no_autotune)
 
     warm = None
     if args.warm_test > 0:
@@ -473,7 +478,7 @@ def main():
 
     volume = None
     if args.volume_slices > 0:
-        volume = volume_bench(dev, args.volume_slices, args.volume_steps)
+        volume = volume_bench(dev, args.volume_slices, args.volume_steps, not args.no_autotune)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -502,6 +507,7 @@ def main():
                      "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": None,
                      "avg_launch_us": avg_ms * 1e3, "flops_per_launch": flops_per_launch},
         "cpu_baseline": cpu,
+        "autotune": tune,
         "projector": projector,
         "time_to_target": ttr,
         "batched": batched,

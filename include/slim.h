@@ -188,6 +188,39 @@ slim_status slim_gram(slim_ctx* ctx, const int32_t* ids_a, int n_a, const int32_
 slim_status slim_get_state(slim_ctx* ctx, void* buf, int64_t* size);
 slim_status slim_set_state(slim_ctx* ctx, const void* buf, int64_t size);
 
+/* Launch shape of the projectors.  Zero fields take the built-in rules. */
+typedef struct {
+  int fwd_bt;       /* forward slice tile: 0, 1, 2 or 4                      */
+  int fwd_items;    /* cap on forward rays per lane: 0, 2, 4, 6, 8 or 10     */
+  int fwd_slots;    /* forward workgroups per CU the grid aims at: 0, 2 or 4 */
+  int back_bt;      /* back-projector slice tile: 0, 1, 2 or 4               */
+} slim_tune;
+
+typedef struct {
+  slim_tune chosen;         /* the fastest shape measured                    */
+  double fwd_us, back_us;   /* its forward and back times on the window      */
+  double fwd_default_us;    /* the built-in rules' times on the same window  */
+  double back_default_us;
+  int candidates;           /* shapes measured                               */
+  int cached;               /* 1: taken from this process's earlier search    */
+} slim_tune_info;
+
+/* Autotuner: time every projector launch shape on this context's CG
+ * workload -- forward and back-projection of a window of (r+1) blocks of
+ * angles_per_block angles (spread over [0, pi)) for all slices -- and keep the
+ * fastest (including the built-in rules).  Results are cached per (N,
+ * n_slices, n_rays, window size) for the process; force != 0 measures again.
+ * Uses temporary device memory of about 2 images and the window's rays per
+ * slice.  info may be NULL.
+ * Errors: SLIM_EINVAL, SLIM_ENOMEM, SLIM_EDEVICE. */
+slim_status slim_autotune(slim_ctx* ctx, int force, slim_tune_info* info);
+
+/* Set (or read back, with get) the projector launch shape.  Every shape
+ * computes the same projections (to float32 rounding order).
+ * Errors: SLIM_EINVAL (NULL, or a field outside its listed values). */
+slim_status slim_set_tune(slim_ctx* ctx, const slim_tune* tune);
+slim_status slim_get_tune(slim_ctx* ctx, slim_tune* tune);
+
 /* Per-kernel timing (measurement support).  slim_profile(ctx, 1) resets the
  * counters and brackets every subsequent projector / Gram / Cholesky / CG
  * vector launch group with HIP events on the context's stream; 0 stops.

@@ -33,7 +33,7 @@ void pcg_free(PcgWork& w);
 // together.  *iters and *relres: the largest over the slices.
 // h_geom: host geometry table; partial: forward-projector workspace.
 hipError_t pcg_solve(PcgWork& w, const AngleGeom* geom, const AngleGeom* h_geom, float* partial,
-                     int N, int R, int B, const AngleList& win, double lam, const double* res,
+                     int N, int R, int B, const AngleList& win, const ProjTune& tune, double lam, const double* res,
                      size_t res_stride, int nres, double* z, size_t z_stride, double tol,
                      int max_iter, int* iters, double* relres, Profiler* prof, hipStream_t st);
 

@@ -206,7 +206,7 @@ void pcg_free(PcgWork& w) {
 }
 
 hipError_t pcg_solve(PcgWork& w, const AngleGeom* geom, const AngleGeom* h_geom, float* partial,
-                     int N, int R, int B, const AngleList& win, double lam, const double* res,
+                     int N, int R, int B, const AngleList& win, const ProjTune& tune, double lam, const double* res,
                      size_t res_stride, int nres, double* z, size_t z_stride, double tol,
                      int max_iter, int* iters, double* relres, Profiler* prof, hipStream_t st) {
   const int p = win.n * R;
@@ -224,6 +224,7 @@ hipError_t pcg_solve(PcgWork& w, const AngleGeom* geom, const AngleGeom* h_geom,
   if ((e = hipGetLastError()) != hipSuccess) return e;
 
   BackArgs ba;
+  ba.tune = tune;
   ba.geom = geom;
   ba.N = N;
   ba.R = R;
@@ -238,6 +239,7 @@ hipError_t pcg_solve(PcgWork& w, const AngleGeom* geom, const AngleGeom* h_geom,
   ba.stop = w.ctl;
   ba.stop_stride = kCtlCount;
   FwdArgs fa;
+  fa.tune = tune;
   fa.geom = geom;
   fa.h_geom = h_geom;
   fa.N = N;

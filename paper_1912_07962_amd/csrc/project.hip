@@ -102,6 +102,7 @@ struct FwdPlan {
   int n_groups;
   int n_tiles;    // slice tiles of BT slices
   int items;      // rays per lane (template argument of the band kernel)
+  int bt;         // slice tile (template argument of the band kernel)
   short id[kMaxList];
   short slot[kMaxList];
 };
@@ -634,7 +635,8 @@ static int fwd_slice_tile(int B, int N) {
 // BT, image bands into groups, with chunks * tiles * groups <= 2 * (number of
 // CUs) where possible, so that a launch is one round of resident workgroups
 // (two per CU, bounded by LDS).
-static FwdPlan make_plan(const AngleGeom* h_geom, int N, int R, const AngleList& ids, int B) {
+static FwdPlan make_plan(const AngleGeom* h_geom, int N, int R, const AngleList& ids, int B,
+                         const ProjTune& tune) {
   FwdPlan pl;
   pl.n = ids.n;
   int k = 0;
@@ -647,22 +649,27 @@ static FwdPlan make_plan(const AngleGeom* h_geom, int N, int R, const AngleList&
       }
   pl.n_row = 0;
   for (int s = 0; s < ids.n; ++s) pl.n_row += h_geom[ids.id[s]].colmajor ? 0 : 1;
-  const int BT = fwd_slice_tile(B, N);
-  pl.ch = std::max(1, std::min(max_items(BT) * kFT / R, ids.n));
+  const int BT = tune.fwd_bt > 0 ? std::min(tune.fwd_bt, slice_tile(B)) : fwd_slice_tile(B, N);
+  pl.bt = BT;
+  const int cap = tune.fwd_items > 0 ? std::min(tune.fwd_items, max_items(BT)) : max_items(BT);
+  pl.ch = std::max(1, std::min(cap * kFT / R, ids.n));
   pl.items = item_count(BT, std::max(1, (pl.ch * R + kFT - 1) / kFT));
   pl.n_chunks = (pl.n_row + pl.ch - 1) / pl.ch + (ids.n - pl.n_row + pl.ch - 1) / pl.ch;
   pl.n_tiles = (B + BT - 1) / BT;
   pl.H = std::max(1, std::min(N, 16384 / ((N + 2 * kPad) * BT)));
   const int nbands = (N + pl.H - 1) / pl.H;
-  const int slots = 2 * num_cu();
+  const int slots = (tune.fwd_slots > 0 ? tune.fwd_slots : 2) * num_cu();
   int want = std::max(1, std::min(slots / (pl.n_chunks * pl.n_tiles), nbands));
   pl.G = (nbands + want - 1) / want;
   pl.n_groups = (nbands + pl.G - 1) / pl.G;
   return pl;
 }
 
-size_t forward_partial_floats(const AngleGeom* h_geom, int N, int R, const AngleList& ids, int B) {
-  const FwdPlan pl = make_plan(h_geom, N, R, ids, B);
+int forward_max_items(int bt) { return max_items(bt); }
+
+size_t forward_partial_floats(const AngleGeom* h_geom, int N, int R, const AngleList& ids, int B,
+                              const ProjTune& tune) {
+  const FwdPlan pl = make_plan(h_geom, N, R, ids, B, tune);
   return (size_t)B * pl.n_groups * ids.n * R;
 }
 
@@ -720,8 +727,8 @@ static void launch_band_bt(int BT, int items, dim3 grid, size_t lds, hipStream_t
 
 hipError_t launch_forward(const FwdArgs& a, hipStream_t st) {
   if (a.ids->n <= 0) return hipSuccess;
-  const FwdPlan pl = make_plan(a.h_geom, a.N, a.R, *a.ids, a.B);
-  const int BT = fwd_slice_tile(a.B, a.N);
+  const FwdPlan pl = make_plan(a.h_geom, a.N, a.R, *a.ids, a.B, a.tune);
+  const int BT = pl.bt;
   const int total = pl.n_groups * pl.n_chunks * pl.n_tiles;
   const int nwg = (total + 7) / 8 * 8;
   const size_t lds = (size_t)pl.H * (a.N + 2 * kPad) * BT * sizeof(float);
@@ -759,7 +766,7 @@ static void launch_back_t(const BackArgs& a, const VT* v, dim3 grid, hipStream_t
 
 template <typename VT>
 static void launch_back_bt(const BackArgs& a, const VT* v, hipStream_t st) {
-  const int BT = slice_tile(a.B);
+  const int BT = a.tune.back_bt > 0 ? std::min(a.tune.back_bt, slice_tile(a.B)) : slice_tile(a.B);
   dim3 grid((a.N + kBW - 1) / kBW, (a.N + kBH - 1) / kBH, (a.B + BT - 1) / BT);
   if (BT == 4)
     launch_back_t<VT, 4>(a, v, grid, st);

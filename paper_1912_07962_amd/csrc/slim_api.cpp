@@ -17,7 +17,10 @@
 #include <cstdio>
 #include <cstring>
 #include <deque>
+#include <map>
+#include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "slim_internal.h"
@@ -116,6 +119,7 @@ struct slim_ctx {
   uint16_t* d_xsT = nullptr;   // bf16 shadow of x^T      [B][N][N] (precision BF16)
   PcgWork pcg{};
   Profiler prof;
+  ProjTune tune;               // projector launch shapes (zeros: built-in rules)
 
   double* h_norms = nullptr;   // pinned [B][3]
   bool norms_valid = false;    // h_norms holds the last step read back
@@ -196,7 +200,7 @@ slim_status transpose_slices(slim_ctx* c) {
 // Grow the forward projector's partial-sum workspace for a launch over the
 // list l (all slices); synchronises the stream only when it grows.
 slim_status ensure_fpart(slim_ctx* c, const AngleList& l) {
-  const size_t need = forward_partial_floats(c->h_geom.data(), c->N, c->R, l, c->B);
+  const size_t need = forward_partial_floats(c->h_geom.data(), c->N, c->R, l, c->B, c->tune);
   if (need <= c->fpart_cap) return SLIM_OK;
   HIP_TRY(hipStreamSynchronize(c->st));
   HIP_TRY(hipFree(c->d_fpart));
@@ -210,6 +214,7 @@ slim_status ensure_fpart(slim_ctx* c, const AngleList& l) {
 
 FwdArgs base_fwd(const slim_ctx* c, const AngleList* l) {
   FwdArgs a;
+  a.tune = c->tune;
   a.geom = c->d_geom;
   a.h_geom = c->h_geom.data();
   a.N = c->N;
@@ -296,7 +301,7 @@ slim_status do_step(slim_ctx* c, const int32_t* ids, slim_step_info* info) {
     if (s != SLIM_OK) return s;
   } else {
     hipError_t e = pcg_solve(c->pcg, c->d_geom, c->h_geom.data(), c->d_fpart, c->N, c->R, c->B,
-                             win, c->lam, c->d_res64, ell, (int)ell, c->d_z, c->pmax,
+                             win, c->tune, c->lam, c->d_res64, ell, (int)ell, c->d_z, c->pmax,
                              c->o.pcg_tol, c->o.pcg_max_iter, &pcg_it, &pcg_rel, &c->prof, c->st);
     if (e != hipSuccess) return fail(SLIM_EDEVICE, std::string("pcg: ") + hipGetErrorString(e));
   }
@@ -305,6 +310,7 @@ slim_status do_step(slim_ctx* c, const int32_t* ids, slim_step_info* info) {
   if (c->prof.on) HIP_TRY(c->prof.begin(K_UPDATE, c->st));
   {
     BackArgs ba;
+    ba.tune = c->tune;
     ba.geom = c->d_geom;
     ba.N = c->N;
     ba.R = c->R;
@@ -579,6 +585,7 @@ slim_status slim_backproject(slim_ctx* c, const int32_t* ids, int n_ids, const f
   if (!v || !out) return fail(SLIM_EINVAL, "v and out must be non-NULL");
   const AngleList l = make_list(ids, n_ids);
   BackArgs ba;
+  ba.tune = c->tune;
   ba.geom = c->d_geom;
   ba.N = c->N;
   ba.R = c->R;
@@ -613,6 +620,7 @@ slim_status slim_data_backprojection(slim_ctx* c, const int32_t* ids, int n_ids,
   HIP_TRY(launch_gather_rows(c->b, c->bf16() ? 1 : 0, c->n_angles, c->R, c->B, l, c->d_gather,
                              c->st));
   BackArgs ba;
+  ba.tune = c->tune;
   ba.geom = c->d_geom;
   ba.N = c->N;
   ba.R = c->R;
@@ -744,6 +752,222 @@ slim_status slim_slice_norms(slim_ctx* c, double* out, int n) {
     out[3 * sl + 1] = std::sqrt(c->h_norms[3 * sl + 1]);
     out[3 * sl + 2] = c->x_true ? std::sqrt(c->h_norms[3 * sl + 2]) : -1.0;
   }
+  return SLIM_OK;
+}
+
+
+// ------------------------------------------------------------- autotuner
+}  // extern "C"
+
+namespace {
+
+struct TuneEntry {
+  ProjTune tune;
+  slim_tune_info info;
+};
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int, int>, TuneEntry> g_tune_cache;
+
+bool valid_tune(const slim_tune& t) {
+  auto in = [](int v, std::initializer_list<int> ok) {
+    for (int o : ok)
+      if (v == o) return true;
+    return false;
+  };
+  return in(t.fwd_bt, {0, 1, 2, 4}) && in(t.fwd_items, {0, 2, 4, 6, 8, 10}) &&
+         in(t.fwd_slots, {0, 2, 4}) && in(t.back_bt, {0, 1, 2, 4});
+}
+
+ProjTune to_proj(const slim_tune& t) {
+  ProjTune p;
+  p.fwd_bt = t.fwd_bt;
+  p.fwd_items = t.fwd_items;
+  p.fwd_slots = t.fwd_slots;
+  p.back_bt = t.back_bt;
+  return p;
+}
+
+slim_tune to_public(const ProjTune& p) {
+  slim_tune t;
+  t.fwd_bt = p.fwd_bt;
+  t.fwd_items = p.fwd_items;
+  t.fwd_slots = p.fwd_slots;
+  t.back_bt = p.back_bt;
+  return t;
+}
+
+}  // namespace
+
+extern "C" {
+
+slim_status slim_set_tune(slim_ctx* c, const slim_tune* t) {
+  if (!c || !t) return fail(SLIM_EINVAL, "ctx or tune is NULL");
+  if (!valid_tune(*t)) return fail(SLIM_EINVAL, "tune field outside its allowed values");
+  c->tune = to_proj(*t);
+  return SLIM_OK;
+}
+
+slim_status slim_get_tune(slim_ctx* c, slim_tune* t) {
+  if (!c || !t) return fail(SLIM_EINVAL, "ctx or tune is NULL");
+  *t = to_public(c->tune);
+  return SLIM_OK;
+}
+
+slim_status slim_autotune(slim_ctx* c, int force, slim_tune_info* info) {
+  if (!c) return fail(SLIM_EINVAL, "ctx is NULL");
+  const int M = c->n_angles / c->g;
+  const int nblk = std::min(c->r + 1, M);
+  AngleList win;
+  win.n = 0;
+  for (int j = 0; j < nblk; ++j) {
+    const int beta = (int)((int64_t)j * M / nblk);
+    for (int a = 0; a < c->g; ++a) win.id[win.n++] = beta * c->g + a;
+  }
+  for (int i = win.n; i < kMaxList; ++i) win.id[i] = 0;
+  const auto key = std::make_tuple(c->N, c->B, c->R, win.n);
+  if (!force) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end()) {
+      c->tune = it->second.tune;
+      if (info) {
+        *info = it->second.info;
+        info->cached = 1;
+      }
+      return SLIM_OK;
+    }
+  }
+
+  // candidate shapes; the built-in rules first
+  std::vector<ProjTune> fwd_c(1), back_c(1);
+  const int bt_max = slice_tile(c->B);
+  for (int bt : {1, 2, 4}) {
+    if (bt > bt_max) continue;
+    ProjTune b;
+    b.back_bt = bt;
+    back_c.push_back(b);
+    for (int it : {2, 4, 6, 8, 10}) {
+      if (it > forward_max_items(bt)) continue;
+      for (int sl : {2, 4}) {
+        ProjTune f;
+        f.fwd_bt = bt;
+        f.fwd_items = it;
+        f.fwd_slots = sl;
+        fwd_c.push_back(f);
+      }
+    }
+  }
+  size_t part = 0;
+  for (const ProjTune& t : fwd_c)
+    part = std::max(part, forward_partial_floats(c->h_geom.data(), c->N, c->R, win, c->B, t));
+
+  // workspace: an image and its transpose (zeros), the window's rays, partials
+  const size_t nimg = c->img_elems() * c->B;
+  const size_t nray = (size_t)c->B * win.n * c->R;
+  float *img = nullptr, *imgT = nullptr, *rays = nullptr, *fpart = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  auto release = [&]() {
+    (void)hipFree(img);
+    (void)hipFree(imgT);
+    (void)hipFree(rays);
+    (void)hipFree(fpart);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+  };
+  HIP_TRY(hipStreamSynchronize(c->st));
+  if (hipMalloc((void**)&img, nimg * sizeof(float)) != hipSuccess ||
+      hipMalloc((void**)&imgT, nimg * sizeof(float)) != hipSuccess ||
+      hipMalloc((void**)&rays, nray * sizeof(float)) != hipSuccess ||
+      hipMalloc((void**)&fpart, part * sizeof(float)) != hipSuccess) {
+    release();
+    return fail(SLIM_ENOMEM, "autotune workspace does not fit");
+  }
+  hipError_t e = hipSuccess;
+  if (e == hipSuccess) e = hipMemsetAsync(img, 0, nimg * sizeof(float), c->st);
+  if (e == hipSuccess) e = hipMemsetAsync(imgT, 0, nimg * sizeof(float), c->st);
+  if (e == hipSuccess) e = hipMemsetAsync(rays, 0, nray * sizeof(float), c->st);
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e != hipSuccess) {
+    release();
+    return fail(SLIM_EDEVICE, std::string("autotune: ") + hipGetErrorString(e));
+  }
+  // mean time of 3 launches after one warm-up launch, microseconds
+  auto timed = [&](auto&& launch, double* us) -> hipError_t {
+    hipError_t r = launch();
+    if (r != hipSuccess) return r;
+    if ((r = hipEventRecord(e0, c->st)) != hipSuccess) return r;
+    for (int k = 0; k < 3; ++k)
+      if ((r = launch()) != hipSuccess) return r;
+    if ((r = hipEventRecord(e1, c->st)) != hipSuccess) return r;
+    if ((r = hipEventSynchronize(e1)) != hipSuccess) return r;
+    float ms = 0.f;
+    if ((r = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) return r;
+    *us = ms * 1e3 / 3.0;
+    return hipSuccess;
+  };
+  slim_tune_info ti{};
+  double best_f = 1e300, best_b = 1e300;
+  ProjTune best;
+  for (size_t k = 0; k < fwd_c.size() && e == hipSuccess; ++k) {
+    FwdArgs fa;
+    fa.tune = fwd_c[k];
+    fa.geom = c->d_geom;
+    fa.h_geom = c->h_geom.data();
+    fa.N = c->N;
+    fa.R = c->R;
+    fa.B = c->B;
+    fa.ids = &win;
+    fa.img = img;
+    fa.imgT = imgT;
+    fa.img_stride = c->img_elems();
+    fa.out32 = rays;
+    fa.out_stride = (size_t)win.n * c->R;
+    fa.partial = fpart;
+    double us = 0.0;
+    e = timed([&]() { return launch_forward(fa, c->st); }, &us);
+    if (k == 0) ti.fwd_default_us = us;
+    if (us < best_f) {
+      best_f = us;
+      best.fwd_bt = fwd_c[k].fwd_bt;
+      best.fwd_items = fwd_c[k].fwd_items;
+      best.fwd_slots = fwd_c[k].fwd_slots;
+    }
+  }
+  for (size_t k = 0; k < back_c.size() && e == hipSuccess; ++k) {
+    BackArgs ba;
+    ba.tune = back_c[k];
+    ba.geom = c->d_geom;
+    ba.N = c->N;
+    ba.R = c->R;
+    ba.B = c->B;
+    ba.ids = &win;
+    ba.v32 = rays;
+    ba.v_stride = (size_t)win.n * c->R;
+    ba.out = img;
+    ba.img_stride = c->img_elems();
+    ba.mode = 0;
+    double us = 0.0;
+    e = timed([&]() { return launch_back(ba, c->st); }, &us);
+    if (k == 0) ti.back_default_us = us;
+    if (us < best_b) {
+      best_b = us;
+      best.back_bt = back_c[k].back_bt;
+    }
+  }
+  release();
+  if (e != hipSuccess) return fail(SLIM_EDEVICE, std::string("autotune: ") + hipGetErrorString(e));
+  ti.chosen = to_public(best);
+  ti.fwd_us = best_f;
+  ti.back_us = best_b;
+  ti.candidates = (int)(fwd_c.size() + back_c.size());
+  ti.cached = 0;
+  c->tune = best;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache[key] = TuneEntry{best, ti};
+  }
+  if (info) *info = ti;
   return SLIM_OK;
 }
 

@@ -98,7 +98,17 @@ int slice_tile(int B);
 // is non-NULL: out += lam * pd and per-workgroup partial sums of pd . out into
 // dots[slice * dots_stride + forward_dot_parts(ids.n * R)].  Slices whose
 // stop[slice * stop_stride + kCtlDone] is set are skipped.
+// Launch shape of the projectors; zero fields take the built-in rules (the
+// autotuner measures and fills them).
+struct ProjTune {
+  int fwd_bt = 0;     // forward slice tile: 1, 2 or 4
+  int fwd_items = 0;  // cap on rays per lane of the forward
+  int fwd_slots = 0;  // resident forward workgroups per CU the grid aims at
+  int back_bt = 0;    // back-projector slice tile: 1, 2 or 4
+};
+
 struct FwdArgs {
+  ProjTune tune;
   const AngleGeom* geom = nullptr;
   const AngleGeom* h_geom = nullptr;   // host copy (the launch plan groups angles)
   int N = 0, R = 0, B = 1;
@@ -123,7 +133,10 @@ struct FwdArgs {
   int stop_stride = 0;
 };
 hipError_t launch_forward(const FwdArgs& a, hipStream_t st);
-size_t forward_partial_floats(const AngleGeom* h_geom, int N, int R, const AngleList& ids, int B);
+// Largest rays-per-lane cap the forward supports for slice tile bt.
+int forward_max_items(int bt);
+size_t forward_partial_floats(const AngleGeom* h_geom, int N, int R, const AngleList& ids, int B,
+                              const ProjTune& tune);
 int forward_dot_parts(int n_out);
 
 // Back-projection of B slices: s[slice][pix] = sum_a sum_t A[(ids[a],t),pix] v[slice][a][t]
@@ -133,6 +146,7 @@ int forward_dot_parts(int n_out);
 // (||s||^2, ||x_new||^2, ||x_new - x_true||^2) into
 // partials[(slice * back_num_workgroups(N) + wg) * 3 + k].
 struct BackArgs {
+  ProjTune tune;
   const AngleGeom* geom = nullptr;
   int N = 0, R = 0, B = 1;
   const AngleList* ids = nullptr;

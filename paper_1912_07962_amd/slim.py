@@ -54,6 +54,17 @@ class SolveInfo(ctypes.Structure):
                 ("pcg_iters", ctypes.c_int)]
 
 
+class Tune(ctypes.Structure):
+    _fields_ = [("fwd_bt", ctypes.c_int), ("fwd_items", ctypes.c_int), ("fwd_slots", ctypes.c_int),
+                ("back_bt", ctypes.c_int)]
+
+
+class TuneInfo(ctypes.Structure):
+    _fields_ = [("chosen", Tune), ("fwd_us", ctypes.c_double), ("back_us", ctypes.c_double),
+                ("fwd_default_us", ctypes.c_double), ("back_default_us", ctypes.c_double),
+                ("candidates", ctypes.c_int), ("cached", ctypes.c_int)]
+
+
 class CnnDesc(ctypes.Structure):
     _fields_ = [("N", ctypes.c_int), ("levels", ctypes.c_int), ("channels", ctypes.c_int * 4),
                 ("max_batch", ctypes.c_int), ("in_scale", ctypes.c_double),
@@ -89,6 +100,9 @@ def load() -> ctypes.CDLL:
         "slim_profile": (I, [P, I]),
         "slim_kernel_stats": (I, [P, I, ctypes.POINTER(D), ctypes.POINTER(ctypes.c_int64)]),
         "slim_data_backprojection": (I, [P, i32p, I, P]),
+        "slim_autotune": (I, [P, I, ctypes.POINTER(TuneInfo)]),
+        "slim_set_tune": (I, [P, ctypes.POINTER(Tune)]),
+        "slim_get_tune": (I, [P, ctypes.POINTER(Tune)]),
         "slim_warmstart": (I, [P, P, i32p, I, P, ctypes.POINTER(I)]),
         "slim_cnn_create": (I, [ctypes.POINTER(P), ctypes.POINTER(CnnDesc)]),
         "slim_cnn_num_params": (ctypes.c_int64, [P]),
@@ -206,6 +220,24 @@ class Slim:
         _check(load().slim_slice_norms(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                        self.B))
         return out
+
+    def autotune(self, force: bool = False) -> dict:
+        """Measure projector launch shapes on this context's CG window and keep
+        the fastest; returns the chosen shape and the times."""
+        ti = TuneInfo()
+        _check(load().slim_autotune(self._h, int(bool(force)), ctypes.byref(ti)))
+        out = {f: getattr(ti, f) for f, _ in TuneInfo._fields_ if f != "chosen"}
+        out["chosen"] = {f: getattr(ti.chosen, f) for f, _ in Tune._fields_}
+        return out
+
+    def set_tune(self, fwd_bt=0, fwd_items=0, fwd_slots=0, back_bt=0):
+        t = Tune(fwd_bt, fwd_items, fwd_slots, back_bt)
+        _check(load().slim_set_tune(self._h, ctypes.byref(t)))
+
+    def get_tune(self) -> dict:
+        t = Tune()
+        _check(load().slim_get_tune(self._h, ctypes.byref(t)))
+        return {f: getattr(t, f) for f, _ in Tune._fields_}
 
     def data_backprojection(self, angle_ids, out=None):
         """out = A_ids^T b_ids for the bound data, every slice."""

@@ -145,3 +145,61 @@ def test_volume_512_first_steps_sampled_slices():
     xe = x.cpu().numpy()
     for b, o in oracles.items():
         assert _rel(xe[b], o.x) < 1e-5
+
+
+def test_every_launch_shape_projects_the_same():
+    """Every projector launch shape the autotuner may pick (slice tile, rays
+    per lane, grid occupancy; back slice tile) against the oracle."""
+    from paper_1912_07962_amd import Slim, SlimError
+    B, N, na = 5, 64, 30
+    P = system.Projector(N, na)
+    rng = np.random.default_rng(7)
+    x = rng.standard_normal((B, N, N)).astype(np.float32)
+    ids = list(range(1, na, 2))
+    v = rng.standard_normal((B, len(ids), P.R)).astype(np.float32)
+    ref_f = [P.forward(ids, x[b].astype(np.float64)) for b in range(B)]
+    ref_b = [P.back(ids, v[b].astype(np.float64)) for b in range(B)]
+    s = Slim(N, na, r=0, lam=1.0, n_slices=B)
+    xd, vd = _dev(x), _dev(v)
+    shapes = [dict(fwd_bt=bt, fwd_items=it, fwd_slots=sl) for bt in (1, 2, 4)
+              for it in (2, 4, 6, 8, 10) for sl in (2, 4)]
+    shapes += [dict(back_bt=bt) for bt in (1, 2, 4)]
+    for sh in shapes:
+        s.set_tune(**sh)
+        assert s.get_tune() == {**dict(fwd_bt=0, fwd_items=0, fwd_slots=0, back_bt=0), **sh}
+        fwd = s.project(ids, xd).cpu().numpy().reshape(B, len(ids), P.R)
+        back = s.backproject(ids, vd).cpu().numpy().reshape(B, N, N)
+        for b in range(B):
+            assert _rel(fwd[b], ref_f[b]) < 1e-6, sh
+            assert _rel(back[b], ref_b[b]) < 1e-6, sh
+    for bad in (dict(fwd_bt=3), dict(fwd_items=7), dict(fwd_slots=1), dict(back_bt=8)):
+        with pytest.raises(SlimError):
+            s.set_tune(**bad)
+
+
+def test_autotune_picks_a_shape_and_caches_it():
+    from paper_1912_07962_amd import Slim
+    N, na, g, r, lam, B = 48, 36, 2, 3, 1e-2, 3
+    xs, bs = synth.make_volume_problem(N, B, na, 8, 0.01, 41, 42)
+    s = Slim(N, na, r=r, lam=lam, n_slices=B, angles_per_block=g, gram_mode="pcg",
+             pcg_tol=1e-11, pcg_max_iter=3000)
+    info = s.autotune(force=True)
+    assert info["candidates"] > 4 and info["cached"] == 0
+    assert info["fwd_us"] <= info["fwd_default_us"] and info["back_us"] <= info["back_default_us"]
+    assert s.get_tune() == info["chosen"]
+    s2 = Slim(N, na, r=r, lam=lam, n_slices=B, angles_per_block=g, gram_mode="pcg")
+    info2 = s2.autotune()
+    assert info2["cached"] == 1 and info2["chosen"] == info["chosen"]
+    # the tuned context still follows the oracle
+    x = torch.zeros((B, N, N), dtype=torch.float32, device="cuda")
+    s.set_data(_dev(bs), x)
+    P = system.Projector(N, na)
+    oracles = [slimls.Tomo(P, bs[k], g, r, lam) for k in range(B)]
+    for beta in sampler.schedule(na // g, 1, 3)[:8]:
+        s.step(list(range(beta * g, beta * g + g)))
+        for o in oracles:
+            o.step(int(beta))
+    xe = x.cpu().numpy()
+    for b in range(B):
+        if np.any(bs[b]):
+            assert _rel(xe[b], oracles[b].x) < 1e-5
