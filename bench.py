@@ -27,6 +27,9 @@ time).  The line also carries:
   volume        512 slices of 512^2 (360 angles x 725 rays, 4 angles/block,
                 r = 8): fwd/back rays/s of one block over all slices and
                 the time of whole slimLS steps;
+  mixed         64 x 256^2 + 32 x 512^2 + 8 x 1024^2 slices (360 angles, 4
+                angles/block, r = 8): one context per size, stepped as one
+                group with interleaved CG, vs the contexts one after another;
   warm_start    the learned warm start on 256^2 (180 angles, 1 angle/block,
                 r = 5): steps to each held-out sample's e* from x0 = 0 and
                 from x0 = CNN(u), single-slice wall-clock time-to-target with
@@ -344,6 +347,67 @@ def warm_bench(dev, n_test, n_timed):
     return ev
 
 
+
+def mixed_bench(dev, steps, autotune=True):
+    """Mixed batch: 64 slices of 256^2, 32 of 512^2 and 8 of 1024^2 (one
+    ellipsoid volume sampled at three resolutions), 360 angles, 4 angles per
+    block, r = 8, lambda = 1e-3, CG; one context per size on its own stream,
+    stepped as one group (interleaved CG) and, for comparison, one context
+    after another."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_1912_07962_amd import Group, Slim
+
+    cfg = synth.get_config("c4m")
+    na, g, r, lam = cfg["n_angles"], cfg["g"], cfg["r"], cfg["lam"]
+    print("bench: mixed batch inputs", file=sys.stderr, flush=True)
+    ctxs, keep, rays, tunes = [], [], 0, []
+    for N, B in cfg["groups"]:
+        xs, bs = synth.make_volume_problem(N, B, na, cfg["n_ellipsoids"], cfg["noise"],
+                                           cfg["phantom_seed"], cfg["noise_seed"])
+        st = torch.cuda.Stream()
+        with torch.cuda.stream(st):
+            s = Slim(N, na, r=r, lam=lam, n_slices=B, angles_per_block=g, gram_mode="pcg",
+                     pcg_tol=1e-6, stream=st)
+            if autotune:
+                tunes.append(s.autotune()["chosen"])
+            bd = torch.as_tensor(bs, dtype=torch.float32, device=dev)
+            xt = torch.as_tensor(xs, dtype=torch.float32, device=dev)
+            x = torch.zeros((B, N, N), dtype=torch.float32, device=dev)
+        st.synchronize()
+        s.set_data(bd, x, xt)
+        ctxs.append(s)
+        keep.append((st, bd, xt, x))
+        rays += B * g * s.R
+    grp = Group(ctxs)
+    sched = synth.schedule(na // g, 1, cfg["schedule_seed"])
+    blk = lambda k: list(range(int(sched[k]) * g, int(sched[k]) * g + g))
+    for k in range(r + 1):
+        grp.step(blk(k))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(r + 1, r + 1 + steps):
+        infos = grp.step(blk(k))
+    torch.cuda.synchronize()
+    t_grp = (time.perf_counter() - t0) / steps
+    t0 = time.perf_counter()
+    for k in range(r + 1 + steps, r + 1 + 2 * steps):
+        for s in ctxs:
+            s.step(blk(k))
+    torch.cuda.synchronize()
+    t_seq = (time.perf_counter() - t0) / steps
+    grp.close()
+    for s in ctxs:
+        s.close()
+    print(f"bench: mixed batch {t_grp * 1e3:.1f} ms/step grouped, {t_seq * 1e3:.1f} sequential",
+          file=sys.stderr, flush=True)
+    return {"groups": [list(gp) for gp in cfg["groups"]], "steps": steps,
+            "group_ms_per_step": t_grp * 1e3, "sequential_ms_per_step": t_seq * 1e3,
+            "group_speedup": t_seq / t_grp, "slice_rays_per_s": rays / t_grp,
+            "cg_iters_last_step": [i["pcg_iters"] for i in infos], "autotune": tunes}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -363,6 +427,8 @@ def main():
     ap.add_argument("--calibration-copy", action="store_true",
                     help="copy 256 MiB once before timing (a kernel of known traffic for "
                          "scaling hardware byte counters)")
+    ap.add_argument("--mixed-steps", type=int, default=3,
+                    help="timed steps of the mixed batch (0 skips it)")
     ap.add_argument("--warm-test", type=int, default=256,
                     help="held-out samples of the warm-start evaluation (0 skips it)")
     ap.add_argument("--warm-timed", type=int, default=8,
@@ -476,6 +542,10 @@ def main():
     if args.warm_test > 0:
         warm = warm_bench(dev, args.warm_test, min(args.warm_timed, args.warm_test))
 
+    mixed = None
+    if args.mixed_steps > 0:
+        mixed = mixed_bench(dev, args.mixed_steps, not args.no_autotune)
+
     volume = None
     if args.volume_slices > 0:
         volume = volume_bench(dev, args.volume_slices, args.volume_steps, not args.no_autotune)
@@ -512,6 +582,7 @@ def main():
         "time_to_target": ttr,
         "batched": batched,
         "volume": volume,
+        "mixed": mixed,
         "warm_start": warm,
         "cg_iters_per_step": float(np.mean(iters)),
         "event_ms_timed_region": ev_ms,

@@ -75,6 +75,10 @@ typedef struct {
   int check_every;      /* slim_solve: read the step norms every q steps    */
   uint64_t seed;        /* slim_solve: SplitMix64 seed of the block order   */
   void* stream;         /* hipStream_t work queue (NULL = default stream)   */
+  int use_graph;        /* 1: each chunk of CG iterations of a step is
+                           captured once as a hipGraph and replayed (only on
+                           a stream other than NULL, and not while kernel
+                           timing is on); 0: launched one by one            */
 } slim_opts;
 
 typedef struct {
@@ -96,7 +100,8 @@ typedef struct {
 } slim_solve_info;
 
 /* Fill *opts with defaults: g = 1, FP32, AUTO, chol_max_p = 8192,
- * pcg_max_iter = 1000, pcg_tol = 1e-6, check_every = 1, seed = 0, NULL stream. */
+ * pcg_max_iter = 1000, pcg_tol = 1e-6, check_every = 1, seed = 0, NULL stream,
+ * use_graph = 1. */
 slim_status slim_default_opts(slim_opts* opts);
 
 /* Create a context (paper sec. 1 setup, sec. 4.3 geometry).
@@ -187,6 +192,27 @@ slim_status slim_gram(slim_ctx* ctx, const int32_t* ids_a, int n_a, const int32_
  * Errors: SLIM_EINVAL (buffer too small: *size is set), SLIM_ESTATE (bad blob). */
 slim_status slim_get_state(slim_ctx* ctx, void* buf, int64_t* size);
 slim_status slim_set_state(slim_ctx* ctx, const void* buf, int64_t size);
+
+/* A group of contexts stepped together: grids of different sizes (e.g.
+ * batches of 256^2, 512^2 and 1024^2 slices) scanned with the same angles and
+ * block size.  slim_group_step applies one sampled block to every context:
+ * the residual projections and explicit Gram solves of all contexts are
+ * enqueued first, then the contexts' CG solves advance chunk by chunk under
+ * one host loop (no context waits on another's host round trips; contexts on
+ * different streams also overlap on the GPU), then every update.  The group
+ * borrows the contexts, which must outlive it.
+ * Errors: SLIM_EINVAL (NULL, n < 1, a context listed twice, contexts with
+ * different n_angles or angles_per_block). */
+typedef struct slim_group slim_group;
+slim_status slim_group_create(slim_group** out, slim_ctx* const* ctxs, int n);
+
+/* One step of every context of the group (eq. (ram) with the same block).
+ *  infos  host [n] or NULL (then nothing is read back).
+ * Errors: as slim_step; after an error the contexts must be rebound with
+ * slim_set_data. */
+slim_status slim_group_step(slim_group* g, const int32_t* angle_ids, int n_ids,
+                            slim_step_info* infos);
+void slim_group_destroy(slim_group* g);
 
 /* Launch shape of the projectors.  Zero fields take the built-in rules. */
 typedef struct {

@@ -5,4 +5,4 @@ PCG of the Gram system and the fused update -- lives in the HIP library
 ``_lib/libslim.so`` behind the C ABI of ``include/slim.h``; ``slim`` is its
 ctypes binding.
 """
-from .slim import Cnn, Slim, SlimError, cnn_layout, load, header_symbols  # noqa: F401
+from .slim import Cnn, Group, Slim, SlimError, cnn_layout, load, header_symbols  # noqa: F401

@@ -24,6 +24,28 @@ struct PcgWork {
   int* h_ctl = nullptr;     // pinned copies of ctl, one per chunk in flight
   double* h_sc = nullptr;   // pinned copy of sc
   hipEvent_t ev[2] = {nullptr, nullptr};
+  hipGraphExec_t graph_exec = nullptr;  // one chunk of iterations (graph mode)
+};
+
+// State of one CG solve, advanced by pcg_enqueue / pcg_poll so that several
+// solves (contexts of different sizes) can be interleaved by one host loop.
+// fa and ba point at win: a run must not be copied or moved once begun.
+struct PcgRun {
+  PcgWork* w = nullptr;
+  AngleList win;
+  FwdArgs fa;
+  BackArgs ba;
+  int p = 0, B = 0, nb = 0;
+  double* z = nullptr;
+  size_t z_stride = 0;
+  double tol2 = 0.0;
+  int max_iter = 0;
+  Profiler* prof = nullptr;
+  hipStream_t st = nullptr;
+  int enq = 0;      // iterations enqueued
+  int chunks = 0;   // chunks enqueued
+  int seen = 0;     // chunks whose flag copy has been read
+  bool done = false;
 };
 
 hipError_t pcg_alloc(PcgWork& w, int N, int B, int64_t pmax);
@@ -32,9 +54,25 @@ void pcg_free(PcgWork& w);
 // at res + b * res_stride), z_b at z + b * z_stride, all slices advancing
 // together.  *iters and *relres: the largest over the slices.
 // h_geom: host geometry table; partial: forward-projector workspace.
+// use_graph: replay each chunk of iterations as one graph launch (needs a
+// stream other than the null stream; chunks run eagerly while profiling).
 hipError_t pcg_solve(PcgWork& w, const AngleGeom* geom, const AngleGeom* h_geom, float* partial,
-                     int N, int R, int B, const AngleList& win, const ProjTune& tune, double lam, const double* res,
-                     size_t res_stride, int nres, double* z, size_t z_stride, double tol,
-                     int max_iter, int* iters, double* relres, Profiler* prof, hipStream_t st);
+                     int N, int R, int B, const AngleList& win, const ProjTune& tune, double lam,
+                     const double* res, size_t res_stride, int nres, double* z, size_t z_stride,
+                     double tol, int max_iter, bool use_graph, int* iters, double* relres,
+                     Profiler* prof, hipStream_t st);
+
+// The same solve in steps: begin enqueues the initialisation; enqueue adds
+// the next chunk of iterations when fewer than two are in flight; poll reads
+// the oldest chunk's stop flags once two are in flight (or the cap is
+// reached) and sets run.done; finish waits and reports.
+hipError_t pcg_begin(PcgRun& run, PcgWork& w, const AngleGeom* geom, const AngleGeom* h_geom,
+                     float* partial, int N, int R, int B, const AngleList& win,
+                     const ProjTune& tune, double lam, const double* res, size_t res_stride,
+                     int nres, double* z, size_t z_stride, double tol, int max_iter,
+                     Profiler* prof, hipStream_t st);
+hipError_t pcg_enqueue(PcgRun& run, bool use_graph);
+hipError_t pcg_poll(PcgRun& run);
+hipError_t pcg_finish(PcgRun& run, int* iters, double* relres);
 
 }  // namespace slim

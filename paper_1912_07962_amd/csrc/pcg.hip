@@ -190,6 +190,8 @@ hipError_t pcg_alloc(PcgWork& w, int N, int B, int64_t pmax) {
 }
 
 void pcg_free(PcgWork& w) {
+  if (w.graph_exec) (void)hipGraphExecDestroy(w.graph_exec);
+  w.graph_exec = nullptr;
   (void)hipFree(w.r);
   (void)hipFree(w.pd);
   (void)hipFree(w.q);
@@ -205,31 +207,42 @@ void pcg_free(PcgWork& w) {
   w = PcgWork{};
 }
 
-hipError_t pcg_solve(PcgWork& w, const AngleGeom* geom, const AngleGeom* h_geom, float* partial,
-                     int N, int R, int B, const AngleList& win, const ProjTune& tune, double lam, const double* res,
-                     size_t res_stride, int nres, double* z, size_t z_stride, double tol,
-                     int max_iter, int* iters, double* relres, Profiler* prof, hipStream_t st) {
-  const int p = win.n * R;
-  const int nb = (p + kThreads - 1) / kThreads;
+hipError_t pcg_begin(PcgRun& run, PcgWork& w, const AngleGeom* geom, const AngleGeom* h_geom,
+                     float* partial, int N, int R, int B, const AngleList& win,
+                     const ProjTune& tune, double lam, const double* res, size_t res_stride,
+                     int nres, double* z, size_t z_stride, double tol, int max_iter,
+                     Profiler* prof, hipStream_t st) {
+  run.w = &w;
+  run.win = win;
+  run.p = win.n * R;
+  run.B = B;
+  run.nb = (run.p + kThreads - 1) / kThreads;
+  run.z = z;
+  run.z_stride = z_stride;
+  run.tol2 = tol * tol;
+  run.max_iter = max_iter;
+  run.prof = prof;
+  run.st = st;
+  run.enq = run.chunks = run.seen = 0;
+  run.done = false;
   const int np = w.nparts;
-  double* pq_parts = w.parts;                              // written by the forward reduction
-  double* rr_parts = w.parts + (size_t)B * np;            // written by init / update
-  const double tol2 = tol * tol;
+  double* rr_parts = w.parts + (size_t)B * np;  // written by init / update
   const size_t img = (size_t)N * N;
-  hipError_t e;
-  hipLaunchKernelGGL(init_kernel, dim3(nb, B), dim3(kThreads), 0, st, p, nres, w.pmax, np, res,
-                     res_stride, w.r, z, z_stride, w.pd, rr_parts);
-  hipLaunchKernelGGL(init_scalars_kernel, dim3(1, B), dim3(kThreads), 0, st, rr_parts, nb, np, w.sc,
-                     w.ctl);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(init_kernel, dim3(run.nb, B), dim3(kThreads), 0, st, run.p, nres, w.pmax,
+                     np, res, res_stride, w.r, z, z_stride, w.pd, rr_parts);
+  hipLaunchKernelGGL(init_scalars_kernel, dim3(1, B), dim3(kThreads), 0, st, rr_parts, run.nb,
+                     np, w.sc, w.ctl);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
 
-  BackArgs ba;
+  BackArgs& ba = run.ba;
+  ba = BackArgs();
   ba.tune = tune;
   ba.geom = geom;
   ba.N = N;
   ba.R = R;
   ba.B = B;
-  ba.ids = &win;
+  ba.ids = &run.win;
   ba.v64 = w.pd;
   ba.v_stride = w.pmax;
   ba.out = w.u;
@@ -238,14 +251,15 @@ hipError_t pcg_solve(PcgWork& w, const AngleGeom* geom, const AngleGeom* h_geom,
   ba.mode = 0;
   ba.stop = w.ctl;
   ba.stop_stride = kCtlCount;
-  FwdArgs fa;
+  FwdArgs& fa = run.fa;
+  fa = FwdArgs();
   fa.tune = tune;
   fa.geom = geom;
   fa.h_geom = h_geom;
   fa.N = N;
   fa.R = R;
   fa.B = B;
-  fa.ids = &win;
+  fa.ids = &run.win;
   fa.img = w.u;
   fa.imgT = w.uT;
   fa.img_stride = img;
@@ -255,56 +269,125 @@ hipError_t pcg_solve(PcgWork& w, const AngleGeom* geom, const AngleGeom* h_geom,
   fa.pd = w.pd;
   fa.pd_stride = w.pmax;
   fa.lam = lam;
-  fa.dots = pq_parts;
+  fa.dots = w.parts;  // pq partials, written by the forward reduction
   fa.dots_stride = np;
   fa.stop = w.ctl;
   fa.stop_stride = kCtlCount;
+  return hipSuccess;
+}
 
-  int enq = 0;     // iterations enqueued
-  int chunks = 0;  // chunks enqueued
-  int seen = 0;    // chunks whose flag copy has been read
-  bool done = false;
-  while (!done) {
-    if (enq < max_iter) {
-      const int todo = std::min(kChunk, max_iter - enq);
-      for (int q = 0; q < todo; ++q, ++enq) {
-        double* sc_cur = w.sc + (size_t)(enq & 1) * B * S_COUNT;
-        double* sc_nxt = w.sc + (size_t)((enq + 1) & 1) * B * S_COUNT;
-        if (prof->on && (e = prof->begin(K_BACK, st)) != hipSuccess) return e;
-        if ((e = launch_back(ba, st)) != hipSuccess) return e;
-        if (prof->on && (e = prof->end(st)) != hipSuccess) return e;
-        if (prof->on && (e = prof->begin(K_FORWARD, st)) != hipSuccess) return e;
-        // q = M u + lambda pd and partial <pd, q>, fused into the forward's reduction
-        if ((e = launch_forward(fa, st)) != hipSuccess) return e;
-        if (prof->on && (e = prof->end(st)) != hipSuccess) return e;
-        if (prof->on && (e = prof->begin(K_VEC, st)) != hipSuccess) return e;
-        hipLaunchKernelGGL(update_kernel, dim3(nb, B), dim3(kThreads), 0, st, p, w.pmax, nb, np,
-                           sc_cur, pq_parts, w.pd, w.q, z, z_stride, w.r, rr_parts, w.ctl);
-        hipLaunchKernelGGL(direction_kernel, dim3(nb, B), dim3(kThreads), 0, st, p, w.pmax, nb, np,
-                           sc_cur, sc_nxt, rr_parts, tol2, w.r, w.pd, w.ctl);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-        if (prof->on && (e = prof->end(st)) != hipSuccess) return e;
-      }
-      int* slot = w.h_ctl + (size_t)(chunks & 1) * B * kCtlCount;
-      if ((e = hipMemcpyAsync(slot, w.ctl, (size_t)B * kCtlCount * sizeof(int),
-                              hipMemcpyDeviceToHost, st)) != hipSuccess)
-        return e;
-      if ((e = hipEventRecord(w.ev[chunks & 1], st)) != hipSuccess) return e;
-      ++chunks;
-    }
-    // keep one chunk in flight while the previous one is checked
-    if (chunks - seen >= 2 || enq >= max_iter) {
-      if ((e = hipEventSynchronize(w.ev[seen & 1])) != hipSuccess) return e;
-      const int* slot = w.h_ctl + (size_t)(seen & 1) * B * kCtlCount;
-      ++seen;
-      bool all = true;
-      for (int b = 0; b < B; ++b) all = all && slot[b * kCtlCount + kCtlDone] != 0;
-      if (all) done = true;
-      if (enq >= max_iter && seen == chunks) done = true;
+namespace {
+
+// Enqueue CG iterations enq .. enq+todo-1 (kernels only).
+hipError_t enqueue_iterations(PcgRun& run, int todo, bool timed) {
+  PcgWork& w = *run.w;
+  const int B = run.B, np = w.nparts;
+  double* pq_parts = w.parts;
+  double* rr_parts = w.parts + (size_t)B * np;
+  Profiler* prof = run.prof;
+  hipStream_t st = run.st;
+  hipError_t e;
+  for (int q = 0; q < todo; ++q) {
+    const int it = run.enq + q;
+    double* sc_cur = w.sc + (size_t)(it & 1) * B * S_COUNT;
+    double* sc_nxt = w.sc + (size_t)((it + 1) & 1) * B * S_COUNT;
+    if (timed && (e = prof->begin(K_BACK, st)) != hipSuccess) return e;
+    if ((e = launch_back(run.ba, st)) != hipSuccess) return e;
+    if (timed && (e = prof->end(st)) != hipSuccess) return e;
+    if (timed && (e = prof->begin(K_FORWARD, st)) != hipSuccess) return e;
+    // q = M u + lambda pd and partial <pd, q>, fused into the forward's reduction
+    if ((e = launch_forward(run.fa, st)) != hipSuccess) return e;
+    if (timed && (e = prof->end(st)) != hipSuccess) return e;
+    if (timed && (e = prof->begin(K_VEC, st)) != hipSuccess) return e;
+    hipLaunchKernelGGL(update_kernel, dim3(run.nb, B), dim3(kThreads), 0, st, run.p, w.pmax,
+                       run.nb, np, sc_cur, pq_parts, w.pd, w.q, run.z, run.z_stride, w.r,
+                       rr_parts, w.ctl);
+    hipLaunchKernelGGL(direction_kernel, dim3(run.nb, B), dim3(kThreads), 0, st, run.p, w.pmax,
+                       run.nb, np, sc_cur, sc_nxt, rr_parts, run.tol2, w.r, w.pd, w.ctl);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (timed && (e = prof->end(st)) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// The kernels of one full chunk as a graph (same arguments for every chunk
+// of a solve: the window is fixed and the scalar sets alternate with the
+// iteration's parity, which repeats every even-sized chunk).  An existing
+// executable graph is updated in place when the kernels match, else rebuilt.
+hipError_t chunk_graph(PcgRun& run) {
+  PcgWork& w = *run.w;
+  hipError_t e = hipStreamBeginCapture(run.st, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return e;
+  hipError_t ek = enqueue_iterations(run, kChunk, false);
+  hipGraph_t g = nullptr;
+  e = hipStreamEndCapture(run.st, &g);
+  if (ek != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return ek;
+  }
+  if (e != hipSuccess) return e;
+  if (w.graph_exec) {
+    hipGraphExecUpdateResult res;
+    hipGraphNode_t bad = nullptr;
+    if (hipGraphExecUpdate(w.graph_exec, g, &bad, &res) != hipSuccess ||
+        res != hipGraphExecUpdateSuccess) {
+      (void)hipGetLastError();
+      (void)hipGraphExecDestroy(w.graph_exec);
+      w.graph_exec = nullptr;
     }
   }
-  if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
-  if (prof->on && (e = prof->harvest()) != hipSuccess) return e;
+  if (!w.graph_exec) e = hipGraphInstantiate(&w.graph_exec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  return e;
+}
+
+}  // namespace
+
+hipError_t pcg_enqueue(PcgRun& run, bool use_graph) {
+  if (run.done || run.enq >= run.max_iter || run.chunks - run.seen >= 2) return hipSuccess;
+  PcgWork& w = *run.w;
+  const int B = run.B;
+  const int todo = std::min(kChunk, run.max_iter - run.enq);
+  hipError_t e;
+  const bool timed = run.prof && run.prof->on;
+  if (use_graph && !timed && todo == kChunk) {
+    if (run.enq == 0 && (e = chunk_graph(run)) != hipSuccess) return e;
+    if ((e = hipGraphLaunch(w.graph_exec, run.st)) != hipSuccess) return e;
+  } else {
+    if ((e = enqueue_iterations(run, todo, timed)) != hipSuccess) return e;
+  }
+  run.enq += todo;
+  int* slot = w.h_ctl + (size_t)(run.chunks & 1) * B * kCtlCount;
+  if ((e = hipMemcpyAsync(slot, w.ctl, (size_t)B * kCtlCount * sizeof(int), hipMemcpyDeviceToHost,
+                          run.st)) != hipSuccess)
+    return e;
+  if ((e = hipEventRecord(w.ev[run.chunks & 1], run.st)) != hipSuccess) return e;
+  ++run.chunks;
+  return hipSuccess;
+}
+
+hipError_t pcg_poll(PcgRun& run) {
+  if (run.done) return hipSuccess;
+  // keep one chunk in flight while the previous one is checked
+  if (run.chunks - run.seen >= 2 || (run.enq >= run.max_iter && run.seen < run.chunks)) {
+    PcgWork& w = *run.w;
+    hipError_t e = hipEventSynchronize(w.ev[run.seen & 1]);
+    if (e != hipSuccess) return e;
+    const int* slot = w.h_ctl + (size_t)(run.seen & 1) * run.B * kCtlCount;
+    ++run.seen;
+    bool all = true;
+    for (int b = 0; b < run.B; ++b) all = all && slot[b * kCtlCount + kCtlDone] != 0;
+    if (all || (run.enq >= run.max_iter && run.seen == run.chunks)) run.done = true;
+  }
+  return hipSuccess;
+}
+
+hipError_t pcg_finish(PcgRun& run, int* iters, double* relres) {
+  PcgWork& w = *run.w;
+  const int B = run.B;
+  hipError_t e;
+  if ((e = hipStreamSynchronize(run.st)) != hipSuccess) return e;
+  if (run.prof && run.prof->on && (e = run.prof->harvest()) != hipSuccess) return e;
   std::vector<int> ctl((size_t)B * kCtlCount);
   if ((e = hipMemcpy(ctl.data(), w.ctl, ctl.size() * sizeof(int), hipMemcpyDeviceToHost)) !=
       hipSuccess)
@@ -324,6 +407,22 @@ hipError_t pcg_solve(PcgWork& w, const AngleGeom* geom, const AngleGeom* h_geom,
   *iters = it_max;
   *relres = rel_max;
   return hipSuccess;
+}
+
+hipError_t pcg_solve(PcgWork& w, const AngleGeom* geom, const AngleGeom* h_geom, float* partial,
+                     int N, int R, int B, const AngleList& win, const ProjTune& tune, double lam,
+                     const double* res, size_t res_stride, int nres, double* z, size_t z_stride,
+                     double tol, int max_iter, bool use_graph, int* iters, double* relres,
+                     Profiler* prof, hipStream_t st) {
+  PcgRun run;
+  hipError_t e = pcg_begin(run, w, geom, h_geom, partial, N, R, B, win, tune, lam, res,
+                           res_stride, nres, z, z_stride, tol, max_iter, prof, st);
+  if (e != hipSuccess) return e;
+  while (!run.done) {
+    if ((e = pcg_enqueue(run, use_graph)) != hipSuccess) return e;
+    if ((e = pcg_poll(run)) != hipSuccess) return e;
+  }
+  return pcg_finish(run, iters, relres);
 }
 
 }  // namespace slim

@@ -18,6 +18,7 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <tuple>
@@ -152,6 +153,7 @@ struct slim_ctx {
 
   size_t img_elems() const { return (size_t)N * N; }
   bool bf16() const { return o.precision == SLIM_PREC_BF16; }
+  bool graphs() const { return o.use_graph != 0 && st != nullptr; }
   size_t sino_elems() const { return (size_t)n_angles * R; }
 };
 
@@ -258,30 +260,39 @@ slim_status gram_solve_chol(slim_ctx* c, int new_slot) {
   return SLIM_OK;
 }
 
-slim_status do_step(slim_ctx* c, const int32_t* ids, slim_step_info* info) {
+// One step in two halves around the Gram solve, so that a group of contexts
+// can interleave their CG solves.  A StepState must not move between
+// step_begin and step_end (its CG run points into itself).
+struct StepState {
+  AngleList blk, win;
+  int slot = 0;
+  bool pcg = false;
+  PcgRun run;
+};
+
+slim_status step_begin(slim_ctx* c, const int32_t* ids, StepState& ss) {
   const int S = c->r + 1;
-  const int slot = c->k % S;
+  ss.slot = c->k % S;
   if ((int)c->window.size() == S) c->window.pop_front();
-  c->slot_ids[slot].assign(ids, ids + c->g);
-  c->window.push_back(slot);
-  const AngleList blk = make_list(ids, c->g);
-  const AngleList win = window_list(c);
+  c->slot_ids[ss.slot].assign(ids, ids + c->g);
+  c->window.push_back(ss.slot);
+  ss.blk = make_list(ids, c->g);
+  ss.win = window_list(c);
   const int64_t ell = c->ell;
-  const int64_t p = (int64_t)c->window.size() * ell;
 
   if (c->prof.on && c->prof.used > 4096) {
     HIP_TRY(hipStreamSynchronize(c->st));
     HIP_TRY(c->prof.harvest());
   }
   {
-    slim_status s = ensure_fpart(c, blk);
-    if (s == SLIM_OK && c->mode == SLIM_GRAM_PCG) s = ensure_fpart(c, win);
+    slim_status s = ensure_fpart(c, ss.blk);
+    if (s == SLIM_OK && c->mode == SLIM_GRAM_PCG) s = ensure_fpart(c, ss.win);
     if (s != SLIM_OK) return s;
   }
   // 1. residual of the new block, all slices in one launch
   if (c->prof.on) HIP_TRY(c->prof.begin(K_RESID, c->st));
   {
-    FwdArgs fa = base_fwd(c, &blk);
+    FwdArgs fa = base_fwd(c, &ss.blk);
     fa.img = c->bf16() ? (const void*)c->d_xs : (const void*)c->x;
     fa.imgT = c->bf16() ? (const void*)c->d_xsT : (const void*)c->d_xT;
     fa.img_bf16 = c->bf16();
@@ -293,16 +304,21 @@ slim_status do_step(slim_ctx* c, const int32_t* ids, slim_step_info* info) {
     HIP_TRY(launch_forward(fa, c->st));
   }
   if (c->prof.on) HIP_TRY(c->prof.end(c->st));
-  // 2. Gram system
+  // 2. Gram system: solved here (Cholesky) or started (CG)
+  ss.pcg = c->mode == SLIM_GRAM_PCG;
+  if (!ss.pcg) return gram_solve_chol(c, ss.slot);
+  hipError_t e = pcg_begin(ss.run, c->pcg, c->d_geom, c->h_geom.data(), c->d_fpart, c->N, c->R,
+                           c->B, ss.win, c->tune, c->lam, c->d_res64, ell, (int)ell, c->d_z,
+                           c->pmax, c->o.pcg_tol, c->o.pcg_max_iter, &c->prof, c->st);
+  if (e != hipSuccess) return fail(SLIM_EDEVICE, std::string("pcg: ") + hipGetErrorString(e));
+  return SLIM_OK;
+}
+
+slim_status step_end(slim_ctx* c, StepState& ss, slim_step_info* info) {
   int pcg_it = 0;
   double pcg_rel = 0.0;
-  if (c->mode == SLIM_GRAM_CHOL) {
-    slim_status s = gram_solve_chol(c, slot);
-    if (s != SLIM_OK) return s;
-  } else {
-    hipError_t e = pcg_solve(c->pcg, c->d_geom, c->h_geom.data(), c->d_fpart, c->N, c->R, c->B,
-                             win, c->tune, c->lam, c->d_res64, ell, (int)ell, c->d_z, c->pmax,
-                             c->o.pcg_tol, c->o.pcg_max_iter, &pcg_it, &pcg_rel, &c->prof, c->st);
+  if (ss.pcg) {
+    hipError_t e = pcg_finish(ss.run, &pcg_it, &pcg_rel);
     if (e != hipSuccess) return fail(SLIM_EDEVICE, std::string("pcg: ") + hipGetErrorString(e));
   }
   // 3. update every slice
@@ -315,7 +331,7 @@ slim_status do_step(slim_ctx* c, const int32_t* ids, slim_step_info* info) {
     ba.N = c->N;
     ba.R = c->R;
     ba.B = c->B;
-    ba.ids = &win;
+    ba.ids = &ss.win;
     ba.v64 = c->d_z;
     ba.v_stride = c->pmax;
     ba.x = c->x;
@@ -330,7 +346,6 @@ slim_status do_step(slim_ctx* c, const int32_t* ids, slim_step_info* info) {
     HIP_TRY(launch_reduce3(c->d_partials, nwg, c->B, c->d_norms, c->st));
   }
   if (c->prof.on) HIP_TRY(c->prof.end(c->st));
-  (void)p;
   c->k += 1;
   c->last_pcg_iters = pcg_it;
   c->last_pcg_relres = pcg_rel;
@@ -359,6 +374,18 @@ slim_status do_step(slim_ctx* c, const int32_t* ids, slim_step_info* info) {
   if (c->mode == SLIM_GRAM_PCG && pcg_rel > c->o.pcg_tol)
     return fail(SLIM_ENOTCONV, "CG reached its iteration cap");
   return SLIM_OK;
+}
+
+slim_status do_step(slim_ctx* c, const int32_t* ids, slim_step_info* info) {
+  StepState ss;
+  slim_status s = step_begin(c, ids, ss);
+  if (s != SLIM_OK) return s;
+  while (ss.pcg && !ss.run.done) {
+    hipError_t e = pcg_enqueue(ss.run, c->graphs());
+    if (e == hipSuccess) e = pcg_poll(ss.run);
+    if (e != hipSuccess) return fail(SLIM_EDEVICE, std::string("pcg: ") + hipGetErrorString(e));
+  }
+  return step_end(c, ss, info);
 }
 
 }  // namespace
@@ -391,6 +418,7 @@ slim_status slim_default_opts(slim_opts* o) {
   o->check_every = 1;
   o->seed = 0;
   o->stream = nullptr;
+  o->use_graph = 1;
   return SLIM_OK;
 }
 
@@ -998,5 +1026,68 @@ void slim_destroy(slim_ctx* c) {
   (void)hipStreamSynchronize(c->st);
   delete c;
 }
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ groups
+struct slim_group {
+  std::vector<slim_ctx*> ctx;
+};
+
+extern "C" {
+
+slim_status slim_group_create(slim_group** out, slim_ctx* const* ctxs, int n) {
+  if (!out || !ctxs || n < 1) return fail(SLIM_EINVAL, "out or ctxs is NULL, or n < 1");
+  *out = nullptr;
+  for (int i = 0; i < n; ++i) {
+    if (!ctxs[i]) return fail(SLIM_EINVAL, "a context is NULL");
+    for (int j = 0; j < i; ++j)
+      if (ctxs[j] == ctxs[i]) return fail(SLIM_EINVAL, "a context is listed twice");
+    if (ctxs[i]->n_angles != ctxs[0]->n_angles || ctxs[i]->g != ctxs[0]->g)
+      return fail(SLIM_EINVAL, "contexts differ in n_angles or angles_per_block");
+  }
+  slim_group* g = new slim_group;
+  g->ctx.assign(ctxs, ctxs + n);
+  *out = g;
+  return SLIM_OK;
+}
+
+slim_status slim_group_step(slim_group* g, const int32_t* ids, int n_ids, slim_step_info* infos) {
+  if (!g) return fail(SLIM_EINVAL, "group is NULL");
+  const int n = (int)g->ctx.size();
+  for (slim_ctx* c : g->ctx) {
+    if (n_ids != c->g) return fail(SLIM_EINVAL, "n_ids must equal angles_per_block");
+    slim_status s = check_ids(c, ids, n_ids, false);
+    if (s != SLIM_OK) return s;
+    if (!c->bound) return fail(SLIM_ESTATE, "no data bound (slim_set_data)");
+  }
+  std::unique_ptr<StepState[]> ss(new StepState[n]);  // fixed addresses (CG runs)
+  for (int i = 0; i < n; ++i) {
+    slim_status s = step_begin(g->ctx[i], ids, ss[i]);
+    if (s != SLIM_OK) return s;
+  }
+  for (bool all = false; !all;) {
+    all = true;
+    for (int i = 0; i < n; ++i)
+      if (ss[i].pcg && !ss[i].run.done) {
+        hipError_t e = pcg_enqueue(ss[i].run, g->ctx[i]->graphs());
+        if (e != hipSuccess) return fail(SLIM_EDEVICE, std::string("pcg: ") + hipGetErrorString(e));
+      }
+    for (int i = 0; i < n; ++i)
+      if (ss[i].pcg && !ss[i].run.done) {
+        hipError_t e = pcg_poll(ss[i].run);
+        if (e != hipSuccess) return fail(SLIM_EDEVICE, std::string("pcg: ") + hipGetErrorString(e));
+        all = all && ss[i].run.done;
+      }
+  }
+  slim_status first = SLIM_OK;
+  for (int i = 0; i < n; ++i) {
+    slim_status s = step_end(g->ctx[i], ss[i], infos ? infos + i : nullptr);
+    if (s != SLIM_OK && first == SLIM_OK) first = s;
+  }
+  return first;
+}
+
+void slim_group_destroy(slim_group* g) { delete g; }
 
 }  // extern "C"

@@ -39,7 +39,7 @@ class Opts(ctypes.Structure):
                 ("gram_mode", ctypes.c_int), ("chol_max_p", ctypes.c_int),
                 ("pcg_max_iter", ctypes.c_int), ("pcg_tol", ctypes.c_double),
                 ("check_every", ctypes.c_int), ("seed", ctypes.c_uint64),
-                ("stream", ctypes.c_void_p)]
+                ("stream", ctypes.c_void_p), ("use_graph", ctypes.c_int)]
 
 
 class StepInfo(ctypes.Structure):
@@ -101,6 +101,9 @@ def load() -> ctypes.CDLL:
         "slim_kernel_stats": (I, [P, I, ctypes.POINTER(D), ctypes.POINTER(ctypes.c_int64)]),
         "slim_data_backprojection": (I, [P, i32p, I, P]),
         "slim_autotune": (I, [P, I, ctypes.POINTER(TuneInfo)]),
+        "slim_group_create": (I, [ctypes.POINTER(P), ctypes.POINTER(P), I]),
+        "slim_group_step": (I, [P, i32p, I, ctypes.POINTER(StepInfo)]),
+        "slim_group_destroy": (None, [P]),
         "slim_set_tune": (I, [P, ctypes.POINTER(Tune)]),
         "slim_get_tune": (I, [P, ctypes.POINTER(Tune)]),
         "slim_warmstart": (I, [P, P, i32p, I, P, ctypes.POINTER(I)]),
@@ -163,7 +166,7 @@ class Slim:
                  lam: float = 1e-2, n_slices: int = 1, angles_per_block: int = 1,
                  precision: str = "fp32", gram_mode: str = "auto", chol_max_p: int = 8192,
                  pcg_max_iter: int = 1000, pcg_tol: float = 1e-6, check_every: int = 1,
-                 seed: int = 0, angles=None, stream=None):
+                 seed: int = 0, angles=None, stream=None, use_graph: bool = True):
         lib = load()
         if n_rays is None:
             n_rays = 2 * int(np.floor(N / np.sqrt(2.0))) + 1
@@ -180,6 +183,7 @@ class Slim:
         o.pcg_tol = float(pcg_tol)
         o.check_every = int(check_every)
         o.seed = int(seed) & ((1 << 64) - 1)
+        o.use_graph = int(bool(use_graph))
         if stream is None and torch.cuda.is_available():
             stream = torch.cuda.current_stream()
         o.stream = ctypes.c_void_p(stream.cuda_stream if stream is not None else 0)
@@ -356,6 +360,37 @@ def init_error(**kw) -> int:
     if st == SLIM_OK:
         lib.slim_destroy(h)
     return st
+
+
+class Group:
+    """Contexts of different grid sizes stepped together with the same block
+    (include/slim.h, slim_group_*): their CG solves are interleaved."""
+
+    def __init__(self, contexts):
+        self.contexts = list(contexts)
+        arr = (ctypes.c_void_p * len(self.contexts))(*[c._h.value for c in self.contexts])
+        h = ctypes.c_void_p()
+        _check(load().slim_group_create(ctypes.byref(h), arr, len(self.contexts)))
+        self._h = h
+
+    def step(self, angle_ids, read: bool = True):
+        a, p, n = _ids(angle_ids)
+        infos = (StepInfo * len(self.contexts))() if read else None
+        _check(load().slim_group_step(self._h, p, n, infos))
+        if not read:
+            return None
+        return [{f: getattr(i, f) for f, _ in StepInfo._fields_} for i in infos]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().slim_group_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def cnn_layout(channels) -> list[tuple[str, tuple]]:

@@ -1,0 +1,89 @@
+"""Mixed batches (contexts of different grid sizes stepped as one group) and
+the graph replay of CG iteration chunks, both against the plain per-context
+path they must reproduce bit for bit."""
+import numpy as np
+import pytest
+
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+NA, G = 24, 2
+
+
+def _problem(N, B, seed):
+    xs, bs = synth.make_volume_problem(N, B, NA, 8, 0.01, seed, seed + 1)
+    extra = [synth.make_slice_problem(N, NA, 3, 0.01, seed + 10 + k, seed + 20 + k)
+             for k in range(B)]
+    return xs + np.stack([e[0] for e in extra]), bs + np.stack([e[1] for e in extra])
+
+
+def _ctx(N, B, mode, b, stream=None, use_graph=True):
+    from paper_1912_07962_amd import Slim
+    s = Slim(N, NA, r=3, lam=1e-2, n_slices=B, angles_per_block=G, gram_mode=mode,
+             pcg_tol=1e-10, pcg_max_iter=2000, stream=stream, use_graph=use_graph)
+    x = torch.zeros((B, N, N), dtype=torch.float32, device="cuda")
+    bd = torch.as_tensor(b, dtype=torch.float32, device="cuda")
+    s.set_data(bd, x)
+    return s, x, bd
+
+
+SPECS = [(32, 3, "pcg"), (64, 2, "chol"), (48, 4, "pcg")]
+
+
+def test_group_step_equals_separate_steps():
+    from paper_1912_07962_amd import Group
+    probs = [_problem(N, B, 100 + i) for i, (N, B, _) in enumerate(SPECS)]
+    grp_ctx = [_ctx(N, B, m, probs[i][1]) for i, (N, B, m) in enumerate(SPECS)]
+    solo = [_ctx(N, B, m, probs[i][1]) for i, (N, B, m) in enumerate(SPECS)]
+    grp = Group([c[0] for c in grp_ctx])
+    sched = synth.schedule(NA // G, 1, 17)
+    for beta in sched:
+        ids = list(range(int(beta) * G, int(beta) * G + G))
+        infos = grp.step(ids)
+        for i, (s, x, _) in enumerate(solo):
+            inf = s.step(ids)
+            assert infos[i]["step_norm"] == inf["step_norm"]
+            assert infos[i]["pcg_iters"] == inf["pcg_iters"]
+        for (_, xg, _), (_, xs, _) in zip(grp_ctx, solo):
+            assert torch.equal(xg, xs)
+
+
+def test_graph_replay_equals_eager_launches():
+    """Chunks of CG iterations replayed as graphs on a side stream, with eager
+    work and synchronisations of the program between replays, against the
+    same contexts launching every kernel on the default stream."""
+    side = torch.cuda.Stream()
+    N, B = 48, 3
+    _, b = _problem(N, B, 7)
+    eager, xe, _ = _ctx(N, B, "pcg", b, use_graph=False)
+    with torch.cuda.stream(side):
+        graph, xg, _ = _ctx(N, B, "pcg", b, stream=side, use_graph=True)
+    side.synchronize()
+    other = torch.randn((256, 256), device="cuda")
+    sched = synth.schedule(NA // G, 1, 5)
+    for k, beta in enumerate(sched):
+        ids = list(range(int(beta) * G, int(beta) * G + G))
+        ie = eager.step(ids)
+        with torch.cuda.stream(side):
+            ig = graph.step(ids)
+        side.synchronize()
+        other = other @ other.T / 256.0       # eager work between replays
+        torch.cuda.synchronize()
+        assert ig["pcg_iters"] == ie["pcg_iters"] and ig["pcg_iters"] > 8
+        assert torch.equal(xg, xe), k
+
+
+def test_group_argument_errors():
+    from paper_1912_07962_amd import Group, Slim, SlimError
+    a = Slim(32, NA, r=1, lam=1e-2, angles_per_block=G)
+    b = Slim(32, NA + 2, r=1, lam=1e-2, angles_per_block=G)
+    with pytest.raises(SlimError):
+        Group([a, b])                 # different angle sets
+    with pytest.raises(SlimError):
+        Group([a, a])                 # listed twice
+    g = Group([a])
+    with pytest.raises(SlimError):
+        g.step([0, 1])                # no data bound
