@@ -251,11 +251,12 @@ slim_status slim_get_tune(slim_ctx* ctx, slim_tune* tune);
  * counters and brackets every subsequent projector / Gram / Cholesky / CG
  * vector launch group with HIP events on the context's stream; 0 stops.
  * slim_kernel_stats returns the summed event time (ms) and the number of
- * timed launch groups of one kind: 0 forward projector in CG products
- * (M u over the window), 1 back-projector in CG products (M^T v over the
- * window), 2 Gram blocks and assembly, 3 Cholesky factorisation and solves,
- * 4 CG vector kernels, 5 residual forward projection of the new block,
- * 6 fused back-projection and update of x.  Both synchronise the stream.
+ * timed launch groups of one kind: 0 forward projector's band kernel in CG
+ * products (M u over the window), 1 back-projector in CG products (M^T v over
+ * the window), 2 Gram blocks and assembly, 3 Cholesky factorisation and
+ * solves, 4 CG vector kernels, 5 residual forward projection of the new
+ * block, 6 fused back-projection and update of x, 7 the reduction of the CG
+ * forward products.  Both synchronise the stream.
  * Errors: SLIM_EINVAL (NULL arguments, unknown kind), SLIM_EDEVICE. */
 slim_status slim_profile(slim_ctx* ctx, int on);
 slim_status slim_kernel_stats(slim_ctx* ctx, int kind, double* total_ms, int64_t* launches);

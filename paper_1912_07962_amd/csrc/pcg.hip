@@ -294,10 +294,10 @@ hipError_t enqueue_iterations(PcgRun& run, int todo, bool timed) {
     if (timed && (e = prof->begin(K_BACK, st)) != hipSuccess) return e;
     if ((e = launch_back(run.ba, st)) != hipSuccess) return e;
     if (timed && (e = prof->end(st)) != hipSuccess) return e;
-    if (timed && (e = prof->begin(K_FORWARD, st)) != hipSuccess) return e;
-    // q = M u + lambda pd and partial <pd, q>, fused into the forward's reduction
+    // q = M u + lambda pd and partial <pd, q>, fused into the forward's
+    // reduction (timed inside: band kernel and reduction separately)
+    run.fa.prof = timed ? prof : nullptr;
     if ((e = launch_forward(run.fa, st)) != hipSuccess) return e;
-    if (timed && (e = prof->end(st)) != hipSuccess) return e;
     if (timed && (e = prof->begin(K_VEC, st)) != hipSuccess) return e;
     hipLaunchKernelGGL(update_kernel, dim3(run.nb, B), dim3(kThreads), 0, st, run.p, w.pmax,
                        run.nb, np, sc_cur, pq_parts, w.pd, w.q, run.z, run.z_stride, w.r,

@@ -729,6 +729,9 @@ hipError_t launch_forward(const FwdArgs& a, hipStream_t st) {
   if (a.ids->n <= 0) return hipSuccess;
   const FwdPlan pl = make_plan(a.h_geom, a.N, a.R, *a.ids, a.B, a.tune);
   const int BT = pl.bt;
+  const bool timed = a.prof && a.prof->on;
+  hipError_t e;
+  if (timed && (e = a.prof->begin(K_FORWARD, st)) != hipSuccess) return e;
   const int total = pl.n_groups * pl.n_chunks * pl.n_tiles;
   const int nwg = (total + 7) / 8 * 8;
   const size_t lds = (size_t)pl.H * (a.N + 2 * kPad) * BT * sizeof(float);
@@ -740,6 +743,8 @@ hipError_t launch_forward(const FwdArgs& a, hipStream_t st) {
     launch_band_bt(BT, pl.items, dim3(nwg), lds, st, a.geom, a.N, a.R, pl, a.B,
                    (const float*)a.img, (const float*)a.imgT, a.img_stride, a.partial, a.stop,
                    a.stop_stride);
+  if (timed && (e = a.prof->end(st)) != hipSuccess) return e;
+  if (timed && (e = a.prof->begin(K_FWD_REDUCE, st)) != hipSuccess) return e;
   const int n = a.ids->n * a.R;
   const dim3 rg((n + 255) / 256, a.B);
   if (a.sub_bf16)
@@ -752,7 +757,9 @@ hipError_t launch_forward(const FwdArgs& a, hipStream_t st) {
                        pl.n_groups, a.partial, (const float*)a.sub, a.sub_stride, a.out32, a.out64,
                        a.out_stride, a.pd, a.pd_stride, a.lam, a.dots, a.dots_stride, a.stop,
                        a.stop_stride);
-  return hipGetLastError();
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (timed && (e = a.prof->end(st)) != hipSuccess) return e;
+  return hipSuccess;
 }
 
 int back_num_workgroups(int N) { return ((N + kBW - 1) / kBW) * ((N + kBH - 1) / kBH); }

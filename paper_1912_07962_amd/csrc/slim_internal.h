@@ -70,7 +70,7 @@ __device__ __forceinline__ void pixel_weights(const AngleGeom& g, double t, int&
 constexpr int kCtlDone = 0, kCtlIters = 1, kCtlCount = 2;
 
 // Optional per-kernel timing with HIP events on the launch stream.  Kinds:
-enum KernelKind { K_FORWARD = 0, K_BACK, K_GRAM, K_CHOL, K_VEC, K_RESID, K_UPDATE, K_COUNT };
+enum KernelKind { K_FORWARD = 0, K_BACK, K_GRAM, K_CHOL, K_VEC, K_RESID, K_UPDATE, K_FWD_REDUCE, K_COUNT };
 
 struct Profiler {
   bool on = false;
@@ -109,6 +109,8 @@ struct ProjTune {
 
 struct FwdArgs {
   ProjTune tune;
+  Profiler* prof = nullptr;   // when set (and on): events around the band kernel (K_FORWARD)
+                              // and the reduction (K_FWD_REDUCE)
   const AngleGeom* geom = nullptr;
   const AngleGeom* h_geom = nullptr;   // host copy (the launch plan groups angles)
   int N = 0, R = 0, B = 1;

@@ -315,7 +315,8 @@ class Slim:
         _check(load().slim_set_state(self._h, buf, len(blob)))
 
     # --- measurement ------------------------------------------------------------
-    KINDS = ("cg_forward", "cg_back", "gram", "cholesky", "cg_vector", "residual", "update")
+    KINDS = ("cg_forward", "cg_back", "gram", "cholesky", "cg_vector", "residual", "update",
+             "cg_forward_reduce")
 
     def profile(self, on: bool = True):
         _check(load().slim_profile(self._h, int(on)))
