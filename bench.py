@@ -52,6 +52,33 @@ PEAK_FP32_VECTOR_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
 PEAK_BF16_TFLOPS = 2500.0
 
+# HBM bytes per launch of the CG projector kernels on this workload, from
+# rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE (KiB per dispatch, mean over the
+# timed steps; profiles/ has the summary and command), each scaled by what the
+# counter reads for a copy of 256 MiB (FETCH reads half: x2.0; WRITE x1.0).
+# Valid only for the projector source they were taken on (SHA-256 below);
+# otherwise the line reports traffic as null.
+PMC_TRAFFIC = {
+    "source": "paper_1912_07962_amd/csrc/project.hip",
+    "sha256": None,
+    "fetch_scale": 2.0,
+    "write_scale": 1.0,
+    "kib": {},          # kind -> (FETCH_SIZE, WRITE_SIZE) KiB per dispatch
+}
+
+
+def pmc_traffic(kind):
+    """Scaled HBM bytes per launch of a kernel kind, or None."""
+    import hashlib
+    t = PMC_TRAFFIC
+    if t["sha256"] is None or kind not in t["kib"]:
+        return None
+    with open(os.path.join(ROOT, t["source"]), "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != t["sha256"]:
+            return None
+    fetch, write = t["kib"][kind]
+    return (fetch * t["fetch_scale"] + write * t["write_scale"]) * 1024.0
+
 
 def window_nnz(N, thetas):
     """Non-zero Joseph weights of the listed angles: 2 d N^2 per angle."""
@@ -577,7 +604,7 @@ def main():
                    "parallelism": "single GPU"},
         "roofline": {"bound": "alu", "kernel": f"{dom} (88-angle window)",
                      "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": None,
+                     "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": pmc_traffic(dom),
                      "avg_launch_us": avg_ms * 1e3, "flops_per_launch": flops_per_launch},
         "cpu_baseline": cpu,
         "autotune": tune,

@@ -2,14 +2,16 @@
 // solves, for the explicit-Gram mode (p up to a few thousand).
 //
 // Blocked right-looking factorisation, panel width 64, row-major lower
-// triangle: per panel one workgroup factors the diagonal block in LDS,
-// a row-parallel kernel solves the panel below it against L11^T, and a
-// tiled kernel applies the symmetric rank-64 update to the trailing lower
-// triangle with float64 MFMA (v_mfma_f64_16x16x4f64).
+// triangle: per panel one workgroup factors the diagonal block in LDS and
+// inverts it, the panel below is L21 = A21 L11^{-T} as a GEMM with that
+// inverse, and a tiled kernel applies the symmetric rank-64 update to the
+// trailing lower triangle; both products run on float64 MFMA
+// (v_mfma_f64_16x16x4f64).
 //
 // The right-hand side [0; ...; 0; res] is zero outside the newest block, so
-// the forward solve only touches the trailing nr x nr triangle; the backward
-// solve covers all p rows.  Both run in one workgroup with the vector in LDS.
+// the forward solve only touches the trailing rows; the backward solve covers
+// all p rows.  Both run in one workgroup per right-hand side with the vector
+// in LDS, using the inverses of the diagonal blocks kept by the factorisation.
 #include "slim_internal.h"
 
 namespace slim {
@@ -18,75 +20,138 @@ namespace {
 
 constexpr int kNB = 64;
 
+// Factor the diagonal block and invert it.  Factorisation: thread (ti, tk)
+// of a 16 x 16 grid holds entries (ti + 16m, tk + 16n), m, n < 4, of the
+// block in registers for the whole right-looking elimination; at pivot j
+// the owners of column j publish it through a double-buffered LDS vector (one
+// barrier per pivot) and every thread updates its entries with the unscaled
+// column divided by the pivot; the square roots are applied at the end.
+// Inverse W = L11^{-1}: one wavefront, lane c substitutes column c with the
+// column held in registers and L read by LDS broadcast.  W goes to winv for
+// the panel GEMM and the triangular solves.
 __global__ __launch_bounds__(256) void potrf_diag_kernel(double* __restrict__ G, int64_t ld, int k0,
-                                                         int nb, int* __restrict__ info) {
-  __shared__ double A[kNB][kNB + 1];
-  for (int e = threadIdx.x; e < nb * nb; e += 256) {
-    const int r = e / nb, c = e % nb;
-    A[r][c] = (c <= r) ? G[(int64_t)(k0 + r) * ld + (k0 + c)] : 0.0;
+                                                         int nb, int* __restrict__ info,
+                                                         double* __restrict__ winv) {
+  __shared__ double col[2][kNB];
+  __shared__ double piv[kNB];
+  __shared__ double Ls[kNB][kNB + 1];
+  const int ti = threadIdx.x >> 4, tk = threadIdx.x & 15;
+  double a[4][4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
+#pragma unroll
+    for (int n = 0; n < 4; ++n) {
+      const int i = ti + 16 * m, k = tk + 16 * n;
+      a[m][n] = (i < nb && k <= i) ? G[(int64_t)(k0 + i) * ld + (k0 + k)] : 0.0;
+    }
+#pragma unroll
+  for (int n = 0; n < 4; ++n) {
+    for (int jj = 0; jj < 16; ++jj) {
+      const int j = 16 * n + jj;
+      if (j >= nb) break;
+      double* cb = col[j & 1];
+      if (tk == jj) {
+#pragma unroll
+        for (int m = 0; m < 4; ++m) cb[ti + 16 * m] = a[m][n];
+      }
+      __syncthreads();
+      double d = cb[j];
+      const bool bad = !(d > 0.0);  // catches NaN too
+      if (bad) d = 1.0;
+      if (threadIdx.x == 0) {
+        piv[j] = d;
+        if (bad && info) atomicCAS(info, 0, k0 + j + 1);
+      }
+      const double rd = 1.0 / d;
+      double ci[4], ck[4];
+#pragma unroll
+      for (int m = 0; m < 4; ++m) ci[m] = cb[ti + 16 * m] * rd;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) ck[q] = cb[tk + 16 * q];
+#pragma unroll
+      for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int i = ti + 16 * m, k = tk + 16 * q;
+          if (k > j && k <= i) a[m][q] -= ci[m] * ck[q];
+        }
+    }
   }
   __syncthreads();
-  for (int j = 0; j < nb; ++j) {
-    __shared__ double piv;
-    if (threadIdx.x == 0) {
-      double d = A[j][j];
-      if (!(d > 0.0)) {  // catches NaN too
-        if (info) atomicCAS(info, 0, k0 + j + 1);
-        d = 1.0;
-      }
-      piv = sqrt(d);
-      A[j][j] = piv;
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
+#pragma unroll
+    for (int n = 0; n < 4; ++n) {
+      const int i = ti + 16 * m, k = tk + 16 * n;
+      double v = 0.0;
+      if (i < nb && k < i)
+        v = a[m][n] / sqrt(piv[k]);
+      else if (i < nb && k == i)
+        v = sqrt(piv[i]);
+      Ls[i][k] = v;
+      if (i < nb && k <= i) G[(int64_t)(k0 + i) * ld + (k0 + k)] = v;
     }
-    __syncthreads();
-    for (int i = j + 1 + threadIdx.x; i < nb; i += 256) A[i][j] /= piv;
-    __syncthreads();
-    for (int e = threadIdx.x; e < (nb - j - 1) * (nb - j - 1); e += 256) {
-      const int i = j + 1 + e / (nb - j - 1);
-      const int k = j + 1 + e % (nb - j - 1);
-      if (k <= i) A[i][k] -= A[i][j] * A[k][j];
+  __syncthreads();
+  if (threadIdx.x < kNB) {
+    const int c = threadIdx.x;
+    double w[kNB];
+#pragma unroll
+    for (int i = 0; i < kNB; ++i) {
+      double s = (i == c) ? 1.0 : 0.0;
+#pragma unroll
+      for (int k = 0; k < i; ++k) s -= Ls[i][k] * w[k];
+      w[i] = (i < nb) ? s / Ls[i][i] : 0.0;
     }
-    __syncthreads();
-  }
-  for (int e = threadIdx.x; e < nb * nb; e += 256) {
-    const int r = e / nb, c = e % nb;
-    if (c <= r) G[(int64_t)(k0 + r) * ld + (k0 + c)] = A[r][c];
+#pragma unroll
+    for (int i = 0; i < kNB; ++i) winv[i * kNB + c] = (c < nb) ? w[i] : 0.0;
   }
 }
 
-// rows i in [k0+nb, p): L21[i, :] = A21[i, :] L11^{-T}
-__global__ __launch_bounds__(256) void trsm_panel_kernel(double* __restrict__ G, int64_t ld, int k0,
-                                                         int nb, int p) {
-  __shared__ double L[kNB][kNB + 1];
-  for (int e = threadIdx.x; e < nb * nb; e += 256) {
-    const int r = e / nb, c = e % nb;
-    L[r][c] = (c <= r) ? G[(int64_t)(k0 + r) * ld + (k0 + c)] : 0.0;
+typedef double double4_t __attribute__((ext_vector_type(4)));
+
+// rows [k0+nb, p), 64 per workgroup: L21 = A21 W^T with W = L11^{-1}, on
+// float64 MFMA (4 wavefronts, each a 16-row strip of four 16x16 blocks).
+__global__ __launch_bounds__(256) void trsm_gemm_kernel(double* __restrict__ G, int64_t ld, int k0,
+                                                        int nb, int p,
+                                                        const double* __restrict__ winv) {
+  __shared__ double Ai[64][kNB + 1];
+  __shared__ double Wj[kNB][kNB + 1];
+  const int r0 = k0 + nb + blockIdx.x * 64;
+  for (int e = threadIdx.x; e < 64 * kNB; e += 256) {
+    const int r = e / kNB, q = e % kNB;
+    Ai[r][q] = (q < nb && r0 + r < p) ? G[(int64_t)(r0 + r) * ld + k0 + q] : 0.0;
+    Wj[r][q] = winv[e];  // zero outside nb
   }
   __syncthreads();
-  const int i = k0 + nb + blockIdx.x * 256 + threadIdx.x;
-  if (i >= p) return;
-  double x[kNB];
-  double* row = G + (int64_t)i * ld + k0;
+  const int w = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  double4_t acc[4];
 #pragma unroll
-  for (int j = 0; j < kNB; ++j) x[j] = (j < nb) ? row[j] : 0.0;
+  for (int cb = 0; cb < 4; ++cb) acc[cb] = (double4_t){0.0, 0.0, 0.0, 0.0};
+  const int ar = w * 16 + (lane & 15);
+  const int kq = lane >> 4;
+  for (int k = 0; k < kNB; k += 4) {
+    const double av = Ai[ar][k + kq];
 #pragma unroll
-  for (int j = 0; j < kNB; ++j) {
-    if (j < nb) {
-      double v = x[j];
-#pragma unroll
-      for (int q = 0; q < kNB; ++q)
-        if (q < j) v -= x[q] * L[j][q];
-      x[j] = v / L[j][j];
+    for (int cb = 0; cb < 4; ++cb) {
+      const double bv = Wj[cb * 16 + (lane & 15)][k + kq];
+      acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[cb], 0, 0, 0);
     }
   }
 #pragma unroll
-  for (int j = 0; j < kNB; ++j)
-    if (j < nb) row[j] = x[j];
+  for (int cb = 0; cb < 4; ++cb) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = r0 + w * 16 + 4 * v + (lane >> 4);
+      const int cc = cb * 16 + (lane & 15);
+      if (r < p && cc < nb) G[(int64_t)r * ld + k0 + cc] = acc[cb][v];
+    }
+  }
 }
 
 // Trailing update A22 -= L21 L21^T on 64x64 lower tiles, K = nb <= 64.
 // 4 wavefronts; wavefront w computes the 16-row strip w of the tile as four
 // 16x16 MFMA blocks.
-typedef double double4_t __attribute__((ext_vector_type(4)));
 
 __global__ __launch_bounds__(256) void syrk_update_kernel(double* __restrict__ G, int64_t ld, int k0,
                                                           int nb, int p) {
@@ -132,37 +197,38 @@ __global__ __launch_bounds__(256) void syrk_update_kernel(double* __restrict__ G
   }
 }
 
-// Triangular solves, one workgroup per right-hand side, vector in LDS.
+// Triangular solves, one workgroup per right-hand side, vector in LDS.  The
+// factorisation kept the inverse W of every 64-row diagonal block, so a
+// block's solve is a 64 x 64 matrix-vector product (no dependent chain);
+// the updates of the remaining rows are row- (forward) or column-coalesced
+// (backward).  The forward solve starts at the block holding row p - nr (the
+// rows above it have a zero right-hand side).
 constexpr int kSolveMax = 12288;
 
 __global__ __launch_bounds__(1024) void chol_solve_kernel(const double* __restrict__ L, int64_t ld,
                                                           int p, int nr,
+                                                          const double* __restrict__ winv,
                                                           const double* __restrict__ rhs_all,
                                                           size_t rhs_stride,
                                                           double* __restrict__ z_all,
                                                           size_t z_stride) {
   extern __shared__ double y[];
+  __shared__ double Wd[kNB][kNB + 1];
   const double* rhs = rhs_all + (size_t)blockIdx.x * rhs_stride;
   double* z = z_all + (size_t)blockIdx.x * z_stride;
   const int tid = threadIdx.x;
-  const int lane = tid & 63;
   for (int i = tid; i < p; i += 1024) y[i] = (i >= p - nr) ? rhs[i - (p - nr)] : 0.0;
-  __syncthreads();
-  // forward: L y = e on rows [p-nr, p)
-  for (int r0 = p - nr; r0 < p; r0 += 64) {
-    const int nbk = min(64, p - r0);
-    if (tid < 64) {
-      double v = (lane < nbk) ? y[r0 + lane] : 0.0;
-      for (int q = 0; q < nbk; ++q) {
-        double yq = 0.0;
-        if (lane == q) {
-          v /= L[(int64_t)(r0 + q) * ld + r0 + q];
-        }
-        yq = __shfl(v, q, 64);
-        if (lane > q && lane < nbk) v -= L[(int64_t)(r0 + lane) * ld + r0 + q] * yq;
-      }
-      if (lane < nbk) y[r0 + lane] = v;
-    }
+  // forward: L y = e from the block holding row p - nr
+  for (int r0 = ((p - nr) / kNB) * kNB; r0 < p; r0 += kNB) {
+    const int nbk = min(kNB, p - r0);
+    const double* W = winv + (size_t)(r0 / kNB) * kNB * kNB;
+    for (int e = tid; e < kNB * kNB; e += 1024) Wd[e / kNB][e % kNB] = W[e];
+    __syncthreads();
+    double v = 0.0;
+    if (tid < nbk)
+      for (int q = 0; q <= tid; ++q) v += Wd[tid][q] * y[r0 + q];
+    __syncthreads();
+    if (tid < nbk) y[r0 + tid] = v;
     __syncthreads();
     for (int r = r0 + nbk + tid; r < p; r += 1024) {
       const double* Lr = L + (int64_t)r * ld + r0;
@@ -172,20 +238,19 @@ __global__ __launch_bounds__(1024) void chol_solve_kernel(const double* __restri
     }
     __syncthreads();
   }
-  // backward: L^T z = y on all rows, bottom-up chunks of 64
-  const int nchunk = (p + 63) / 64;
+  // backward: L^T z = y on all rows, bottom-up blocks
+  const int nchunk = (p + kNB - 1) / kNB;
   for (int cidx = nchunk - 1; cidx >= 0; --cidx) {
-    const int r0 = cidx * 64;
-    const int nbk = min(64, p - r0);
-    if (tid < 64) {
-      double v = (lane < nbk) ? y[r0 + lane] : 0.0;
-      for (int q = nbk - 1; q >= 0; --q) {
-        if (lane == q) v /= L[(int64_t)(r0 + q) * ld + r0 + q];
-        const double zq = __shfl(v, q, 64);
-        if (lane < q) v -= L[(int64_t)(r0 + q) * ld + r0 + lane] * zq;
-      }
-      if (lane < nbk) y[r0 + lane] = v;
-    }
+    const int r0 = cidx * kNB;
+    const int nbk = min(kNB, p - r0);
+    const double* W = winv + (size_t)cidx * kNB * kNB;
+    for (int e = tid; e < kNB * kNB; e += 1024) Wd[e / kNB][e % kNB] = W[e];
+    __syncthreads();
+    double v = 0.0;
+    if (tid < nbk)
+      for (int q = tid; q < nbk; ++q) v += Wd[q][tid] * y[r0 + q];
+    __syncthreads();
+    if (tid < nbk) y[r0 + tid] = v;
     __syncthreads();
     for (int r = tid; r < r0; r += 1024) {
       double acc = 0.0;
@@ -199,14 +264,16 @@ __global__ __launch_bounds__(1024) void chol_solve_kernel(const double* __restri
 
 }  // namespace
 
-hipError_t launch_cholesky(double* G, int64_t ld, int p, int* info, hipStream_t st) {
+hipError_t launch_cholesky(double* G, int64_t ld, int p, int* info, double* work,
+                           hipStream_t st) {
   for (int k0 = 0; k0 < p; k0 += kNB) {
     const int nb = min(kNB, p - k0);
-    hipLaunchKernelGGL(potrf_diag_kernel, dim3(1), dim3(256), 0, st, G, ld, k0, nb, info);
+    double* w = work + (size_t)(k0 / kNB) * kNB * kNB;
+    hipLaunchKernelGGL(potrf_diag_kernel, dim3(1), dim3(256), 0, st, G, ld, k0, nb, info, w);
     const int rest = p - k0 - nb;
     if (rest > 0) {
-      hipLaunchKernelGGL(trsm_panel_kernel, dim3((rest + 255) / 256), dim3(256), 0, st, G, ld, k0,
-                         nb, p);
+      hipLaunchKernelGGL(trsm_gemm_kernel, dim3((rest + 63) / 64), dim3(256), 0, st, G, ld, k0, nb,
+                         p, (const double*)w);
       const int T = (rest + 63) / 64;
       hipLaunchKernelGGL(syrk_update_kernel, dim3(T, T), dim3(256), 0, st, G, ld, k0, nb, p);
     }
@@ -214,12 +281,12 @@ hipError_t launch_cholesky(double* G, int64_t ld, int p, int* info, hipStream_t 
   return hipGetLastError();
 }
 
-hipError_t launch_chol_solve(const double* L, int64_t ld, int p, int nr, const double* rhs64,
-                             size_t rhs_stride, double* z, size_t z_stride, int B,
-                             hipStream_t st) {
+hipError_t launch_chol_solve(const double* L, int64_t ld, int p, int nr, const double* work,
+                             const double* rhs64, size_t rhs_stride, double* z, size_t z_stride,
+                             int B, hipStream_t st) {
   if (p > kSolveMax) return hipErrorInvalidValue;
   hipLaunchKernelGGL(chol_solve_kernel, dim3(B), dim3(1024), (size_t)p * sizeof(double), st, L, ld,
-                     p, nr, rhs64, rhs_stride, z, z_stride);
+                     p, nr, work, rhs64, rhs_stride, z, z_stride);
   return hipGetLastError();
 }
 

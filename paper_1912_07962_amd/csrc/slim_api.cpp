@@ -106,6 +106,7 @@ struct slim_ctx {
   double* d_res64 = nullptr;   // [B][ell]
   double* d_tiles = nullptr;   // [(r+1)^2][ell][ell]
   double* d_G = nullptr;       // [pmax][pmax]
+  double* d_cholwork = nullptr;// inverse of a diagonal block (Cholesky scratch)
   double* d_z = nullptr;       // [B][pmax]
   int* d_info = nullptr;
   double* d_partials = nullptr;
@@ -135,6 +136,7 @@ struct slim_ctx {
     (void)hipFree(d_res64);
     (void)hipFree(d_tiles);
     (void)hipFree(d_G);
+    (void)hipFree(d_cholwork);
     (void)hipFree(d_z);
     (void)hipFree(d_info);
     (void)hipFree(d_partials);
@@ -253,8 +255,8 @@ slim_status gram_solve_chol(slim_ctx* c, int new_slot) {
   if (c->prof.on) HIP_TRY(c->prof.end(c->st));
   if (c->prof.on) HIP_TRY(c->prof.begin(K_CHOL, c->st));
   HIP_TRY(hipMemsetAsync(c->d_info, 0, sizeof(int), c->st));
-  HIP_TRY(launch_cholesky(c->d_G, p, (int)p, c->d_info, c->st));
-  HIP_TRY(launch_chol_solve(c->d_G, p, (int)p, (int)ell, c->d_res64, ell, c->d_z, c->pmax, c->B,
+  HIP_TRY(launch_cholesky(c->d_G, p, (int)p, c->d_info, c->d_cholwork, c->st));
+  HIP_TRY(launch_chol_solve(c->d_G, p, (int)p, (int)ell, c->d_cholwork, c->d_res64, ell, c->d_z, c->pmax, c->B,
                             c->st));
   if (c->prof.on) HIP_TRY(c->prof.end(c->st));
   return SLIM_OK;
@@ -508,6 +510,7 @@ slim_status slim_init(slim_ctx** out, const slim_grid* grid, int n_angles, const
   if (mode == SLIM_GRAM_CHOL) {
     if ((e = dalloc(&c->d_tiles, (size_t)(r + 1) * (r + 1) * ell * ell)) != hipSuccess) return oom(e);
     if ((e = dalloc(&c->d_G, (size_t)pmax * pmax)) != hipSuccess) return oom(e);
+    if ((e = dalloc(&c->d_cholwork, chol_work_doubles(pmax))) != hipSuccess) return oom(e);
   } else {
     if ((e = pcg_alloc(c->pcg, c->N, c->B, pmax)) != hipSuccess) return oom(e);
   }

@@ -190,15 +190,19 @@ hipError_t launch_tile_copy(const double* src, int64_t lds, double* G, int64_t l
                             hipStream_t st);
 
 // Lower Cholesky of the p x p row-major matrix G (ld) in place.  info[0] is
-// set to 1 + index of the first non-positive pivot (0 on success).
-hipError_t launch_cholesky(double* G, int64_t ld, int p, int* info, hipStream_t st);
+// set to 1 + index of the first non-positive pivot (0 on success).  work
+// (chol_work_doubles(p)) receives the inverses of the 64 x 64 diagonal
+// blocks of L, which the triangular solves use.
+inline size_t chol_work_doubles(int64_t p) { return (size_t)((p + 63) / 64) * 64 * 64; }
+hipError_t launch_cholesky(double* G, int64_t ld, int p, int* info, double* work,
+                           hipStream_t st);
 
 // For each of B right-hand sides: solve L y = e with e = [0; rhs] (rhs: the
 // last nr entries, rhs64 + slice * rhs_stride) and L^T z = y
 // (z + slice * z_stride, float64 [p]).
-hipError_t launch_chol_solve(const double* L, int64_t ld, int p, int nr, const double* rhs64,
-                             size_t rhs_stride, double* z, size_t z_stride, int B,
-                             hipStream_t st);
+hipError_t launch_chol_solve(const double* L, int64_t ld, int p, int nr, const double* work,
+                             const double* rhs64, size_t rhs_stride, double* z, size_t z_stride,
+                             int B, hipStream_t st);
 
 // out[s][i][t] = b[s][ids[i]][t] as float32 for B slices (b float32 or bf16,
 // slice stride n_angles * R).
