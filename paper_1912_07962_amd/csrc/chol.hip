@@ -205,6 +205,20 @@ __global__ __launch_bounds__(256) void syrk_update_kernel(double* __restrict__ G
 // rows above it have a zero right-hand side).
 constexpr int kSolveMax = 12288;
 
+// sum_{q < n} a[q * stride] * v[q] with eight independent partial sums, so
+// eight loads are in flight per lane (the order is fixed: deterministic)
+__device__ __forceinline__ double dot_rows(const double* __restrict__ a, int64_t stride,
+                                           const double* v, int n) {
+  double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  int q = 0;
+  for (; q + 8 <= n; q += 8) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc[u] += a[(q + u) * stride] * v[q + u];
+  }
+  for (int u = 0; q < n; ++q, ++u) acc[u] += a[q * stride] * v[q];
+  return ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+}
+
 __global__ __launch_bounds__(1024) void chol_solve_kernel(const double* __restrict__ L, int64_t ld,
                                                           int p, int nr,
                                                           const double* __restrict__ winv,
@@ -232,9 +246,7 @@ __global__ __launch_bounds__(1024) void chol_solve_kernel(const double* __restri
     __syncthreads();
     for (int r = r0 + nbk + tid; r < p; r += 1024) {
       const double* Lr = L + (int64_t)r * ld + r0;
-      double acc = 0.0;
-      for (int q = 0; q < nbk; ++q) acc += Lr[q] * y[r0 + q];
-      y[r] -= acc;
+      y[r] -= dot_rows(Lr, 1, y + r0, nbk);
     }
     __syncthreads();
   }
@@ -252,11 +264,7 @@ __global__ __launch_bounds__(1024) void chol_solve_kernel(const double* __restri
     __syncthreads();
     if (tid < nbk) y[r0 + tid] = v;
     __syncthreads();
-    for (int r = tid; r < r0; r += 1024) {
-      double acc = 0.0;
-      for (int q = 0; q < nbk; ++q) acc += L[(int64_t)(r0 + q) * ld + r] * y[r0 + q];
-      y[r] -= acc;
-    }
+    for (int r = tid; r < r0; r += 1024) y[r] -= dot_rows(L + (int64_t)r0 * ld + r, ld, y + r0, nbk);
     __syncthreads();
   }
   for (int i = tid; i < p; i += 1024) z[i] = y[i];
