@@ -60,10 +60,11 @@ PEAK_BF16_TFLOPS = 2500.0
 # otherwise the line reports traffic as null.
 PMC_TRAFFIC = {
     "source": "paper_1912_07962_amd/csrc/project.hip",
-    "sha256": None,
+    "sha256": "9414a2208ddae9eb991410e2c0a8f9eaeecb4dc85e647b37f74d08544daea995",
     "fetch_scale": 2.0,
     "write_scale": 1.0,
-    "kib": {},          # kind -> (FETCH_SIZE, WRITE_SIZE) KiB per dispatch
+    # kind -> (FETCH_SIZE, WRITE_SIZE) KiB per dispatch
+    "kib": {"cg_back": (2666.4, 7209.5), "cg_forward": (4029.9, 8218.7)},
 }
 
 

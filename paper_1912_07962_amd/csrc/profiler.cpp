@@ -7,7 +7,9 @@ hipError_t Profiler::begin(int k, hipStream_t st) {
   if ((size_t)(2 * used + 2) > pool.size()) {
     for (int q = 0; q < 64; ++q) {
       hipEvent_t ev;
-      hipError_t e = hipEventCreate(&ev);
+      // no system-scope fence: the events time kernels on the device, and a
+      // fence would add cache flushes inside the timed interval
+      hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableSystemFence);
       if (e != hipSuccess) return e;
       pool.push_back(ev);
     }

@@ -392,6 +392,7 @@ __global__ __launch_bounds__(256) void back_kernel(
   }
   __shared__ float seg[kSegFloats];
   __shared__ int tmin[kAng];
+  __shared__ float hdA[kAng];
   __shared__ float tile[kBH][kBW + 1];
   __shared__ double wred[4][3 * BT];
   const int tx = threadIdx.x & 15;       // 16 lanes x 4 pixels = 64 columns
@@ -421,14 +422,17 @@ __global__ __launch_bounds__(256) void back_kernel(
       const double t00 = det_coord(g, ci0, cj0, off), t01 = det_coord(g, ci0, cj1, off);
       const double t10 = det_coord(g, ci1, cj0, off), t11 = det_coord(g, ci1, cj1, off);
       tmin[threadIdx.x] = (int)floor(fmin(fmin(t00, t01), fmin(t10, t11))) - 1;
+      hdA[threadIdx.x] = g.hd;
     }
     __syncthreads();
+    // one independent global load per staged value (unrolled so several are
+    // in flight per lane)
+#pragma unroll 6
     for (int e = threadIdx.x; e < na * kSeg * BT; e += 256) {
       const int a = e / (kSeg * BT), u = (e / BT) % kSeg, b = e % BT;
       const int t = tmin[a] + u - kTOff;
-      const float hd = geom[ids.id[a0 + a]].hd;
       const VT* vb = v + (size_t)(b0 + min(b, nb - 1)) * v_stride;
-      seg[e] = (t >= 0 && t < R) ? hd * (float)vb[(size_t)(a0 + a) * R + t] : 0.f;
+      seg[e] = (t >= 0 && t < R) ? hdA[a] * (float)vb[(size_t)(a0 + a) * R + t] : 0.f;
     }
     __syncthreads();
     if (i < N) {
