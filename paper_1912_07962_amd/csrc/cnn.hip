@@ -283,20 +283,30 @@ __global__ __launch_bounds__(256) void wgrad_in_kernel(const uint16_t* dz, int C
                                                        int H, int64_t cps, float* part) {
   const int64_t npx = (int64_t)B * H * H;
   const int64_t p0 = (int64_t)blockIdx.x * cps, p1 = min(npx, p0 + cps);
+  const int64_t n0 = p0 / (H * H);
+  const int rem0 = (int)(p0 - n0 * H * H);
   for (int t = threadIdx.x; t < 10 * Cout; t += blockDim.x) {
     const int co = t % Cout, k = t / Cout;
     const int dy = k / 3 - 1, dx = k % 3 - 1;
     float acc = 0.f;
+    // pixel coordinates stepped along the range (no division per pixel)
+    int y = rem0 / H, x = rem0 % H;
+    const float* un = u + n0 * H * H;
     for (int64_t P = p0; P < p1; ++P) {
       const float g = bf2f(dz[P * Cout + co]);
       if (k == 9) {
         acc += g;
       } else {
-        const int64_t n = P / (H * H);
-        const int rem = (int)(P - n * H * H);
-        const int yy = rem / H + dy, xx = rem % H + dx;
+        const int yy = y + dy, xx = x + dx;
         if ((unsigned)yy < (unsigned)H && (unsigned)xx < (unsigned)H)
-          acc += g * (in_scale * u[n * H * H + yy * H + xx]);
+          acc += g * (in_scale * un[yy * H + xx]);
+      }
+      if (++x == H) {
+        x = 0;
+        if (++y == H) {
+          y = 0;
+          un += H * H;
+        }
       }
     }
     part[(size_t)blockIdx.x * 10 * Cout + t] = acc;
@@ -374,14 +384,22 @@ __global__ void head_kernel(Tensor d, int C, const float* head, const float* u, 
   x0[P] = s + head[C] + head[C + 1] * (in_scale * u[P]);
 }
 
-// per workgroup: sums of diff^2, dx0 * D[c] (c < C), dx0, dx0 * uh
+// per workgroup: sums of dx0 * D[c] (c < C), dx0, dx0 * uh and diff^2 (in
+// that order), each reduced within a wavefront by shuffles and across the
+// four wavefronts in a fixed order
+__device__ __forceinline__ double wave_sum64(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  return v;
+}
+
 __global__ __launch_bounds__(256) void head_back_kernel(Tensor d, int C, const float* head,
                                                         const float* u, float in_scale,
                                                         const float* x0, const float* target,
                                                         int64_t npx, Tensor dz, double* part) {
-  __shared__ double red[256];
+  extern __shared__ double red[];  // [4][C + 3]
   const int64_t P = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const bool in = P < npx;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   float diff = 0.f, g = 0.f, uh = 0.f;
   if (in) {
     diff = x0[P] - target[P];
@@ -404,27 +422,36 @@ __global__ __launch_bounds__(256) void head_back_kernel(Tensor d, int C, const f
         v = (double)diff * diff;
       }
     }
-    red[threadIdx.x] = v;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-      if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) part[(size_t)blockIdx.x * (C + 3) + k] = red[0];
-    __syncthreads();
+    v = wave_sum64(v);
+    if (lane == 0) red[w * (C + 3) + k] = v;
   }
+  __syncthreads();
+  for (int k = threadIdx.x; k < C + 3; k += 256)
+    part[(size_t)blockIdx.x * (C + 3) + k] =
+        (red[k] + red[(C + 3) + k]) + (red[2 * (C + 3) + k] + red[3 * (C + 3) + k]);
 }
 
-__global__ void head_reduce_kernel(const double* part, int nblk, int C, double* loss,
-                                   float* dhead, double inv_npx) {
-  const int k = threadIdx.x;
-  if (k >= C + 3) return;
+// out[k] = sum over workgroups of part[wg][k]: one workgroup per quantity,
+// strided partial sums and a tree, both in a fixed order
+__global__ __launch_bounds__(256) void head_reduce_kernel(const double* part, int nblk, int C,
+                                                          double* loss, float* dhead,
+                                                          double inv_npx) {
+  __shared__ double red[256];
+  const int k = blockIdx.x;
   double s = 0.0;
-  for (int b = 0; b < nblk; ++b) s += part[(size_t)b * (C + 3) + k];
-  if (k < C + 2)
-    dhead[k] = (float)s;
-  else
-    *loss = s * inv_npx;
+  for (int b = threadIdx.x; b < nblk; b += 256) s += part[(size_t)b * (C + 3) + k];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    if (k < C + 2)
+      dhead[k] = (float)red[0];
+    else
+      *loss = red[0] * inv_npx;
+  }
 }
 
 __global__ void adam_kernel(float* p, const float* g, float* m, float* v, int64_t n, float b1,
@@ -561,12 +588,12 @@ hipError_t launch_head_back(Tensor d, int C, const float* head, const float* u, 
                             const float* x0, const float* target, int64_t npx, Tensor dz,
                             double* part, double* loss, float* dhead, hipStream_t st) {
   const unsigned nblk = blocks256(npx);
-  hipLaunchKernelGGL(head_back_kernel, dim3(nblk), dim3(256), 0, st, d, C, head, u,
-                     (float)in_scale, x0, target, npx, dz, part);
+  hipLaunchKernelGGL(head_back_kernel, dim3(nblk), dim3(256), (size_t)4 * (C + 3) * sizeof(double),
+                     st, d, C, head, u, (float)in_scale, x0, target, npx, dz, part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(head_reduce_kernel, dim3(1), dim3(((C + 3 + 63) / 64) * 64), 0, st,
-                     (const double*)part, (int)nblk, C, loss, dhead, 1.0 / (double)npx);
+  hipLaunchKernelGGL(head_reduce_kernel, dim3(C + 3), dim3(256), 0, st, (const double*)part,
+                     (int)nblk, C, loss, dhead, 1.0 / (double)npx);
   return hipGetLastError();
 }
 
