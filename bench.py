@@ -120,6 +120,7 @@ def plain_ttr(s, bd, x, xt, sched, g, r, M, nrm):
     Returns dict(stop_s, stop_steps, e_star, by_rule, s, steps)."""
     import torch
     x.zero_()
+    torch.cuda.synchronize()          # x is zeroed on torch's stream, used on the library's
     s.set_data(bd, x, xt)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -170,8 +171,9 @@ def batched_ttr(cfg, s1, sched, dev, B, autotune=True):
     bd = torch.as_tensor(np.stack([p[1] for p in probs]), dtype=torch.float32, device=dev)
     xt = torch.as_tensor(np.stack([p[0] for p in probs]), dtype=torch.float32, device=dev)
     xb = torch.zeros((B, N, N), dtype=torch.float32, device=dev)
+    torch.cuda.synchronize()
     sb = Slim(N, na, r=r, lam=lam, n_slices=B, angles_per_block=g, gram_mode="pcg",
-              pcg_tol=1e-6)
+              pcg_tol=1e-6, stream=torch.cuda.Stream())
     tune = sb.autotune() if autotune else None
     sb.set_data(bd, xb, xt)
     torch.cuda.synchronize()
@@ -219,8 +221,11 @@ def volume_bench(dev, B, steps, autotune=True):
     xt = torch.as_tensor(xs, dtype=torch.float32, device=dev)
     bd = torch.as_tensor(bs, dtype=torch.float32, device=dev)
     del xs, bs
-    s = Slim(N, na, r=r, lam=lam, n_slices=B, angles_per_block=g, gram_mode="pcg", pcg_tol=1e-6)
-    tune = s.autotune() if autotune else None
+    torch.cuda.synchronize()
+    vstream = torch.cuda.Stream()
+    s = Slim(N, na, r=r, lam=lam, n_slices=B, angles_per_block=g, gram_mode="pcg", pcg_tol=1e-6,
+             stream=vstream)
+    tune = {"window": s.autotune(), "block": s.autotune(n_ids=g)} if autotune else None
     R = s.R
     ell = g * R
     theta = np.arange(na) * (np.pi / na)
@@ -230,10 +235,10 @@ def volume_bench(dev, B, steps, autotune=True):
         fn()
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
+        e0.record(vstream)
         for _ in range(n):
             fn()
-        e1.record()
+        e1.record(vstream)
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / n * 1e-3
 
@@ -241,6 +246,7 @@ def volume_bench(dev, B, steps, autotune=True):
     v = torch.randn((B, g, R), device=dev)
     out_f = torch.empty((B, g, R), device=dev)
     out_b = torch.empty((B, N, N), device=dev)
+    torch.cuda.synchronize()
     # a block of row-stepping angles (theta near 0) and one of column-stepping
     # angles (theta near pi/2; the public forward transposes x for those)
     for blk in (list(range(0, g)), list(range(na // 2, na // 2 + g))):
@@ -257,6 +263,7 @@ def volume_bench(dev, B, steps, autotune=True):
     del out_f, out_b, v
 
     x = torch.zeros((B, N, N), dtype=torch.float32, device=dev)
+    torch.cuda.synchronize()
     s.set_data(bd, x, xt)
     sched = synth.schedule(na // g, 1, cfg["schedule_seed"])
     for k in range(r + 1):
@@ -481,12 +488,16 @@ def main():
     bd = torch.as_tensor(b, dtype=torch.float32, device=dev)
     xt = torch.as_tensor(x_true, dtype=torch.float32, device=dev)
     x = torch.zeros((N, N), dtype=torch.float32, device=dev)
-    s = Slim(N, na, r=r, lam=lam, angles_per_block=g, gram_mode="pcg", pcg_tol=1e-6)
+    torch.cuda.synchronize()
+    # the library's own stream (default priority): CG chunks replay as graphs
+    main_stream = torch.cuda.Stream()
+    s = Slim(N, na, r=r, lam=lam, angles_per_block=g, gram_mode="pcg", pcg_tol=1e-6,
+             stream=main_stream)
     tune = None if args.no_autotune else s.autotune()
     R = s.R
     ell = g * R
     M = na // g
-    sched = synth.schedule(M, 1 + (args.warmup + args.steps) // M + 1, cfg["schedule_seed"])
+    sched = synth.schedule(M, 1 + (args.warmup + 2 * args.steps) // M + 1, cfg["schedule_seed"])
     theta = np.arange(na) * (np.pi / na)
 
     if args.calibration_copy:
@@ -505,34 +516,45 @@ def main():
         s.step(list(range(beta * g, beta * g + g)))
     torch.cuda.synchronize()
 
-    s.profile(True)
+    # timed region: exactly `steps` steps, no instrumentation
     iters = []
-    flops_cg = 0.0
-    window = [int(sched[k]) for k in range(max(0, args.warmup - r), args.warmup)]
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    ev0.record()
+    ev0.record(main_stream)
     for k in range(args.warmup, args.warmup + args.steps):
+        beta = int(sched[k])
+        info = s.step(list(range(beta * g, beta * g + g)))
+        iters.append(info["pcg_iters"])
+    ev1.record(main_stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev_ms = ev0.elapsed_time(ev1)
+    print(f"bench: timed {args.steps} steps in {wall:.3f} s", file=sys.stderr, flush=True)
+
+    # the next `steps` steps with HIP events around every kernel on the
+    # library's stream (launched one by one): per-kernel times for the roofline
+    s.profile(True)
+    prof_iters = []
+    flops_cg = 0.0
+    k0 = args.warmup + args.steps
+    window = [int(sched[k]) for k in range(max(0, k0 - r), k0)]
+    for k in range(k0, k0 + args.steps):
         beta = int(sched[k])
         info = s.step(list(range(beta * g, beta * g + g)))
         window = (window + [beta])[-(r + 1):]
         ids = [a for bb in window for a in range(bb * g, bb * g + g)]
         flops_cg += info["pcg_iters"] * 2.0 * window_nnz(N, theta[ids])
-        iters.append(info["pcg_iters"])
-    ev1.record()
+        prof_iters.append(info["pcg_iters"])
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ev_ms = ev0.elapsed_time(ev1)
     stats = s.kernel_stats()
     s.profile(False)
-    print(f"bench: timed {args.steps} steps in {wall:.3f} s", file=sys.stderr, flush=True)
 
     # dominant kernel: CG forward or back over the window (same work per launch)
     dom = max(("cg_forward", "cg_back"), key=lambda k: stats[k]["total_ms"])
     st = stats[dom]
     avg_ms = st["total_ms"] / max(st["launches"], 1)
-    flops_per_launch = flops_cg / max(sum(iters), 1)
+    flops_per_launch = flops_cg / max(sum(prof_iters), 1)
     achieved = flops_per_launch / (avg_ms * 1e-3) / 1e12
 
     # projector metric: one 8-angle block, fwd / back / fwd+back
@@ -543,15 +565,18 @@ def main():
         fn()
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
+        e0.record(main_stream)
         for _ in range(n):
             fn()
-        e1.record()
+        e1.record(main_stream)
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / n * 1e-3
 
-    t_f = _time(lambda: s.project(blk, xt))
-    t_b = _time(lambda: s.backproject(blk, v))
+    with torch.cuda.stream(main_stream):
+        out_f = torch.empty((8, R), device=dev)
+        out_b = torch.empty((N, N), device=dev)
+    t_f = _time(lambda: s.project(blk, xt, out_f))
+    t_b = _time(lambda: s.backproject(blk, v, out_b))
     projector = {"block_angles": 8, "rays": 8 * R, "fwd_rays_per_s": 8 * R / t_f,
                  "back_rays_per_s": 8 * R / t_b, "fwd_back_rays_per_s": 8 * R / (t_f + t_b),
                  "fwd_us": t_f * 1e6, "back_us": t_b * 1e6}
@@ -617,6 +642,7 @@ def main():
         "warm_start": warm,
         "cg_iters_per_step": float(np.mean(iters)),
         "event_ms_timed_region": ev_ms,
+        "graphs": True,
         "kernel_ms": {k: v2["total_ms"] for k, v2 in stats.items()},
     }
     print(json.dumps(line))

@@ -231,18 +231,22 @@ typedef struct {
   int cached;               /* 1: taken from this process's earlier search    */
 } slim_tune_info;
 
-/* Autotuner: time every projector launch shape on this context's CG
- * workload -- forward and back-projection of a window of (r+1) blocks of
- * angles_per_block angles (spread over [0, pi)) for all slices -- and keep the
- * fastest (including the built-in rules).  Results are cached per (N,
- * n_slices, n_rays, window size) for the process; force != 0 measures again.
- * Uses temporary device memory of about 2 images and the window's rays per
- * slice.  info may be NULL.
+/* Autotuner: time every projector launch shape on forward and back
+ * projections of a list of angles for all slices, and keep the fastest
+ * (including the built-in rules) for lists of that size.  n_ids = 0 tunes the
+ * CG workload -- a window of (r+1) blocks of angles_per_block angles spread
+ * over [0, pi) -- and also makes its shape the default for every other size;
+ * n_ids > 0 (at most min(256, n_angles)) tunes n_ids angles spread over
+ * [0, pi), e.g. angles_per_block for the residual and single-block
+ * projections.  Results are cached per (N, n_slices, n_rays, list size) for
+ * the process; force != 0 measures again.  Uses temporary device memory of
+ * about 2 images and the list's rays per slice.  info may be NULL.
  * Errors: SLIM_EINVAL, SLIM_ENOMEM, SLIM_EDEVICE. */
-slim_status slim_autotune(slim_ctx* ctx, int force, slim_tune_info* info);
+slim_status slim_autotune(slim_ctx* ctx, int n_ids, int force, slim_tune_info* info);
 
-/* Set (or read back, with get) the projector launch shape.  Every shape
- * computes the same projections (to float32 rounding order).
+/* Set (or read back, with get) the default projector launch shape; set also
+ * drops the shapes tuned for particular list sizes.  Every shape computes the
+ * same projections (to float32 rounding order).
  * Errors: SLIM_EINVAL (NULL, or a field outside its listed values). */
 slim_status slim_set_tune(slim_ctx* ctx, const slim_tune* tune);
 slim_status slim_get_tune(slim_ctx* ctx, slim_tune* tune);

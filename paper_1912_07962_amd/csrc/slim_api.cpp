@@ -121,7 +121,13 @@ struct slim_ctx {
   uint16_t* d_xsT = nullptr;   // bf16 shadow of x^T      [B][N][N] (precision BF16)
   PcgWork pcg{};
   Profiler prof;
-  ProjTune tune;               // projector launch shapes (zeros: built-in rules)
+  ProjTune tune;               // projector launch shape (zeros: built-in rules)
+  std::map<int, ProjTune> tune_by_n;  // tuned shapes per angle-list size
+
+  const ProjTune& tune_for(int n) const {
+    auto it = tune_by_n.find(n);
+    return it != tune_by_n.end() ? it->second : tune;
+  }
 
   double* h_norms = nullptr;   // pinned [B][3]
   bool norms_valid = false;    // h_norms holds the last step read back
@@ -204,7 +210,7 @@ slim_status transpose_slices(slim_ctx* c) {
 // Grow the forward projector's partial-sum workspace for a launch over the
 // list l (all slices); synchronises the stream only when it grows.
 slim_status ensure_fpart(slim_ctx* c, const AngleList& l) {
-  const size_t need = forward_partial_floats(c->h_geom.data(), c->N, c->R, l, c->B, c->tune);
+  const size_t need = forward_partial_floats(c->h_geom.data(), c->N, c->R, l, c->B, c->tune_for(l.n));
   if (need <= c->fpart_cap) return SLIM_OK;
   HIP_TRY(hipStreamSynchronize(c->st));
   HIP_TRY(hipFree(c->d_fpart));
@@ -218,7 +224,7 @@ slim_status ensure_fpart(slim_ctx* c, const AngleList& l) {
 
 FwdArgs base_fwd(const slim_ctx* c, const AngleList* l) {
   FwdArgs a;
-  a.tune = c->tune;
+  a.tune = c->tune_for(l->n);
   a.geom = c->d_geom;
   a.h_geom = c->h_geom.data();
   a.N = c->N;
@@ -310,7 +316,7 @@ slim_status step_begin(slim_ctx* c, const int32_t* ids, StepState& ss) {
   ss.pcg = c->mode == SLIM_GRAM_PCG;
   if (!ss.pcg) return gram_solve_chol(c, ss.slot);
   hipError_t e = pcg_begin(ss.run, c->pcg, c->d_geom, c->h_geom.data(), c->d_fpart, c->N, c->R,
-                           c->B, ss.win, c->tune, c->lam, c->d_res64, ell, (int)ell, c->d_z,
+                           c->B, ss.win, c->tune_for(ss.win.n), c->lam, c->d_res64, ell, (int)ell, c->d_z,
                            c->pmax, c->o.pcg_tol, c->o.pcg_max_iter, &c->prof, c->st);
   if (e != hipSuccess) return fail(SLIM_EDEVICE, std::string("pcg: ") + hipGetErrorString(e));
   return SLIM_OK;
@@ -328,7 +334,7 @@ slim_status step_end(slim_ctx* c, StepState& ss, slim_step_info* info) {
   if (c->prof.on) HIP_TRY(c->prof.begin(K_UPDATE, c->st));
   {
     BackArgs ba;
-    ba.tune = c->tune;
+    ba.tune = c->tune_for(ss.win.n);
     ba.geom = c->d_geom;
     ba.N = c->N;
     ba.R = c->R;
@@ -616,7 +622,7 @@ slim_status slim_backproject(slim_ctx* c, const int32_t* ids, int n_ids, const f
   if (!v || !out) return fail(SLIM_EINVAL, "v and out must be non-NULL");
   const AngleList l = make_list(ids, n_ids);
   BackArgs ba;
-  ba.tune = c->tune;
+  ba.tune = c->tune_for(l.n);
   ba.geom = c->d_geom;
   ba.N = c->N;
   ba.R = c->R;
@@ -651,7 +657,7 @@ slim_status slim_data_backprojection(slim_ctx* c, const int32_t* ids, int n_ids,
   HIP_TRY(launch_gather_rows(c->b, c->bf16() ? 1 : 0, c->n_angles, c->R, c->B, l, c->d_gather,
                              c->st));
   BackArgs ba;
-  ba.tune = c->tune;
+  ba.tune = c->tune_for(l.n);
   ba.geom = c->d_geom;
   ba.N = c->N;
   ba.R = c->R;
@@ -835,6 +841,7 @@ slim_status slim_set_tune(slim_ctx* c, const slim_tune* t) {
   if (!c || !t) return fail(SLIM_EINVAL, "ctx or tune is NULL");
   if (!valid_tune(*t)) return fail(SLIM_EINVAL, "tune field outside its allowed values");
   c->tune = to_proj(*t);
+  c->tune_by_n.clear();
   return SLIM_OK;
 }
 
@@ -844,23 +851,34 @@ slim_status slim_get_tune(slim_ctx* c, slim_tune* t) {
   return SLIM_OK;
 }
 
-slim_status slim_autotune(slim_ctx* c, int force, slim_tune_info* info) {
+slim_status slim_autotune(slim_ctx* c, int n_ids, int force, slim_tune_info* info) {
   if (!c) return fail(SLIM_EINVAL, "ctx is NULL");
-  const int M = c->n_angles / c->g;
-  const int nblk = std::min(c->r + 1, M);
+  if (n_ids < 0 || n_ids > std::min(kMaxList, c->n_angles))
+    return fail(SLIM_EINVAL, "n_ids must be in [0, min(256, n_angles)]");
   AngleList win;
   win.n = 0;
-  for (int j = 0; j < nblk; ++j) {
-    const int beta = (int)((int64_t)j * M / nblk);
-    for (int a = 0; a < c->g; ++a) win.id[win.n++] = beta * c->g + a;
+  const bool window = n_ids == 0;
+  if (window) {  // the CG window: r+1 blocks spread over [0, pi)
+    const int M = c->n_angles / c->g;
+    const int nblk = std::min(c->r + 1, M);
+    for (int j = 0; j < nblk; ++j) {
+      const int beta = (int)((int64_t)j * M / nblk);
+      for (int a = 0; a < c->g; ++a) win.id[win.n++] = beta * c->g + a;
+    }
+  } else {       // n_ids angles spread over [0, pi)
+    for (int j = 0; j < n_ids; ++j) win.id[win.n++] = (int)((int64_t)j * c->n_angles / n_ids);
   }
   for (int i = win.n; i < kMaxList; ++i) win.id[i] = 0;
+  auto keep = [&](const ProjTune& t) {
+    c->tune_by_n[win.n] = t;
+    if (window) c->tune = t;
+  };
   const auto key = std::make_tuple(c->N, c->B, c->R, win.n);
   if (!force) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune_cache.find(key);
     if (it != g_tune_cache.end()) {
-      c->tune = it->second.tune;
+      keep(it->second.tune);
       if (info) {
         *info = it->second.info;
         info->cached = 1;
@@ -993,7 +1011,7 @@ slim_status slim_autotune(slim_ctx* c, int force, slim_tune_info* info) {
   ti.back_us = best_b;
   ti.candidates = (int)(fwd_c.size() + back_c.size());
   ti.cached = 0;
-  c->tune = best;
+  keep(best);
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune_cache[key] = TuneEntry{best, ti};

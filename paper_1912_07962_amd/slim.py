@@ -100,7 +100,7 @@ def load() -> ctypes.CDLL:
         "slim_profile": (I, [P, I]),
         "slim_kernel_stats": (I, [P, I, ctypes.POINTER(D), ctypes.POINTER(ctypes.c_int64)]),
         "slim_data_backprojection": (I, [P, i32p, I, P]),
-        "slim_autotune": (I, [P, I, ctypes.POINTER(TuneInfo)]),
+        "slim_autotune": (I, [P, I, I, ctypes.POINTER(TuneInfo)]),
         "slim_group_create": (I, [ctypes.POINTER(P), ctypes.POINTER(P), I]),
         "slim_group_step": (I, [P, i32p, I, ctypes.POINTER(StepInfo)]),
         "slim_group_destroy": (None, [P]),
@@ -225,11 +225,12 @@ class Slim:
                                        self.B))
         return out
 
-    def autotune(self, force: bool = False) -> dict:
-        """Measure projector launch shapes on this context's CG window and keep
-        the fastest; returns the chosen shape and the times."""
+    def autotune(self, n_ids: int = 0, force: bool = False) -> dict:
+        """Measure projector launch shapes on lists of n_ids angles (0: this
+        context's CG window, also the default shape) and keep the fastest;
+        returns the chosen shape and the times."""
         ti = TuneInfo()
-        _check(load().slim_autotune(self._h, int(bool(force)), ctypes.byref(ti)))
+        _check(load().slim_autotune(self._h, int(n_ids), int(bool(force)), ctypes.byref(ti)))
         out = {f: getattr(ti, f) for f, _ in TuneInfo._fields_ if f != "chosen"}
         out["chosen"] = {f: getattr(ti.chosen, f) for f, _ in Tune._fields_}
         return out

@@ -46,7 +46,7 @@ def test_null_handles_are_rejected():
     assert lib.slim_solve(None, None, None, None, 1e-2, 1, None) == slim.SLIM_EINVAL
     assert lib.slim_project(None, None, 0, None, None) == slim.SLIM_EINVAL
     assert lib.slim_slice_norms(None, None, 0) == slim.SLIM_EINVAL
-    assert lib.slim_autotune(None, 0, None) == slim.SLIM_EINVAL
+    assert lib.slim_autotune(None, 0, 0, None) == slim.SLIM_EINVAL
     assert lib.slim_group_create(None, None, 0) == slim.SLIM_EINVAL
     assert lib.slim_group_step(None, None, 0, None) == slim.SLIM_EINVAL
     lib.slim_group_destroy(None)

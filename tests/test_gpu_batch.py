@@ -190,6 +190,11 @@ def test_autotune_picks_a_shape_and_caches_it():
     s2 = Slim(N, na, r=r, lam=lam, n_slices=B, angles_per_block=g, gram_mode="pcg")
     info2 = s2.autotune()
     assert info2["cached"] == 1 and info2["chosen"] == info["chosen"]
+    # a second list size (the residual's block of g angles) is tuned separately
+    ib = s.autotune(n_ids=g, force=True)
+    assert ib["cached"] == 0 and ib["candidates"] > 4
+    assert s.get_tune() == info["chosen"]            # the default stays the window's
+    assert s2.autotune(n_ids=g)["chosen"] == ib["chosen"]
     # the tuned context still follows the oracle
     x = torch.zeros((B, N, N), dtype=torch.float32, device="cuda")
     s.set_data(_dev(bs), x)
