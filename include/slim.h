@@ -217,7 +217,9 @@ void slim_group_destroy(slim_group* g);
 /* Launch shape of the projectors.  Zero fields take the built-in rules. */
 typedef struct {
   int fwd_bt;       /* forward slice tile: 0, 1, 2 or 4                      */
-  int fwd_items;    /* cap on forward rays per lane: 0, 2, 4, 6, 8 or 10     */
+  int fwd_items;    /* cap on forward rays per lane: 0, 2, 3, 4, 6, 8 or 10;
+                       caps above the tile's maximum (8, 6, 3 rays for tiles
+                       of 1, 2, 4 slices) act as that maximum               */
   int fwd_slots;    /* forward workgroups per CU the grid aims at: 0, 2 or 4 */
   int back_bt;      /* back-projector slice tile: 0, 1, 2 or 4               */
 } slim_tune;

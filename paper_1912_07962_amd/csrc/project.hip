@@ -81,13 +81,14 @@ template <> struct Lane<4> {
 // ---------------------------------------------------------------- forward
 constexpr int kFT = 512;      // threads per forward workgroup
 // Rays per lane, bounded by registers: every ray keeps a 32.32 position and
-// step (4 VGPRs) and one fp64 accumulator per slice of the tile, within 128
-// VGPRs (four waves per SIMD: two 512-lane workgroups per CU).  More rays per workgroup means more
-// angles per pass over the image, i.e. fewer passes.
-constexpr int max_items(int BT) { return BT == 1 ? 10 : (BT == 2 ? 8 : 5); }
-// the instantiated values: 1..6, 8, then the cap
+// step (4 VGPRs) and one fp64 accumulator per slice of the tile, and rays are
+// walked in pairs, all within 128 VGPRs (four waves per SIMD: two 512-lane
+// workgroups per CU).  More rays per workgroup means more angles per pass
+// over the image, i.e. fewer passes.
+constexpr int max_items(int BT) { return BT == 1 ? 8 : (BT == 2 ? 6 : 3); }
+// the instantiated values: 1..6, then the cap
 inline int item_count(int BT, int want) {
-  const int it = want <= 6 ? want : (want <= 8 ? 8 : 10);
+  const int it = want <= 6 ? want : 8;
   return it < max_items(BT) ? it : max_items(BT);
 }
 constexpr int kPad = 4;       // zero columns on each side of a band row (keeps rows 16B-aligned)
@@ -275,29 +276,54 @@ __global__ __launch_bounds__(kFT, 2) void fwd_band_kernel(const AngleGeom* __res
       }
     }
     const LT* bandv = reinterpret_cast<const LT*>(band);
+    // Items walk the band in pairs over the union of their two row ranges,
+    // so each row issues two independent LDS reads.  A lane outside its own
+    // ray's range reads the zero pads (see above) and adds nothing.
 #pragma unroll
-    for (int q = 0; q < IT; ++q) {
-      const int k0 = max(wlo[q], kb), k1 = min(whi[q], kb + hb - 1);
+    for (int q = 0; q < IT; q += 2) {
+      const bool two = q + 1 < IT;   // known once unrolled
+      const int qn = two ? q + 1 : q;
+      const int k0 = max(min(wlo[q], wlo[qn]), kb), k1 = min(max(whi[q], whi[qn]), kb + hb - 1);
       if (k0 > k1) continue;  // wave-uniform
-      int64_t P = P0[q] + (int64_t)k0 * S[q];
+      int64_t Pa = P0[q] + (int64_t)k0 * S[q];
+      int64_t Pb = P0[qn] + (int64_t)k0 * S[qn];
       const LT* row = bandv + (k0 - kb) * W;
-      float a32[BT];
+      // sum over rows of a + phi (c - a), phi = lo(P) 2^-32, kept as the two
+      // sums  sum a  and  sum lo(P) (c - a)  (the 2^-32 applied once per band)
+      float aa[BT], da[BT], ab[BT], db[BT];
 #pragma unroll
-      for (int b = 0; b < BT; ++b) a32[b] = 0.f;
+      for (int b = 0; b < BT; ++b) aa[b] = da[b] = ab[b] = db[b] = 0.f;
       for (int k = k0; k <= k1; ++k) {
-        const int qi = min(max((int)(P >> 32), 0), W - 2);
-        const float phi = (float)(uint32_t)P * 2.3283064365386963e-10f;
-        const LT v0 = row[qi], v1 = row[qi + 1];
+        // an index below 0 wraps above W - 2: both ends are zero pads
+        const uint32_t ia = min((uint32_t)(Pa >> 32), (uint32_t)(W - 2));
+        const LT va0 = row[ia], va1 = row[ia + 1];
+        LT vb0 = va0, vb1 = va1;
+        if (two) {
+          const uint32_t ib = min((uint32_t)(Pb >> 32), (uint32_t)(W - 2));
+          vb0 = row[ib];
+          vb1 = row[ib + 1];
+        }
+        const float la = (float)(uint32_t)Pa, lb = (float)(uint32_t)Pb;
 #pragma unroll
         for (int b = 0; b < BT; ++b) {
-          const float a = Lane<BT>::get(v0, b), c = Lane<BT>::get(v1, b);
-          a32[b] += fmaf(phi, c - a, a);
+          const float x0 = Lane<BT>::get(va0, b), x1 = Lane<BT>::get(va1, b);
+          aa[b] += x0;
+          da[b] = fmaf(la, x1 - x0, da[b]);
+          if (two) {
+            const float y0 = Lane<BT>::get(vb0, b), y1 = Lane<BT>::get(vb1, b);
+            ab[b] += y0;
+            db[b] = fmaf(lb, y1 - y0, db[b]);
+          }
         }
-        P += S[q];
+        Pa += S[q];
+        if (two) Pb += S[qn];
         row += W;
       }
 #pragma unroll
-      for (int b = 0; b < BT; ++b) acc[q][b] += (double)a32[b];
+      for (int b = 0; b < BT; ++b) {
+        acc[q][b] += (double)fmaf(da[b], 2.3283064365386963e-10f, aa[b]);
+        if (two) acc[qn][b] += (double)fmaf(db[b], 2.3283064365386963e-10f, ab[b]);
+      }
     }
   }
 #pragma unroll
@@ -369,6 +395,21 @@ constexpr int kBPX = 4;             // consecutive pixels per lane
 constexpr int kSegFloats = 64 * 72; // LDS floats of staged ray segments
 constexpr int kSeg = 72;            // rays of one angle's segment
 
+// Per-angle constants of one staged pass.  base moves the detector coordinate
+// of the angle's rays onto its LDS segment (segment index = ray - tmin + a *
+// kSeg); step is cos(theta) in 32.32 fixed point (one image column);
+// invd32 = 2^-32 / d.
+struct BackAngle {
+  double s, c, base;
+  int64_t step;
+  float invd32, c1;
+};
+
+// min(max(x, 0), 1): the weights are at most 1 by construction, so this is
+// max(0, x); written as a median it folds into the producing instruction's
+// output clamp.
+__device__ __forceinline__ float unit_clamp(float x) { return __builtin_amdgcn_fmed3f(x, 0.f, 1.f); }
+
 __device__ __forceinline__ double wave_sum(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
   return v;
@@ -393,6 +434,7 @@ __global__ __launch_bounds__(256) void back_kernel(
   __shared__ float seg[kSegFloats];
   __shared__ int tmin[kAng];
   __shared__ float hdA[kAng];
+  __shared__ BackAngle ang[kAng];
   __shared__ float tile[kBH][kBW + 1];
   __shared__ double wred[4][3 * BT];
   const int tx = threadIdx.x & 15;       // 16 lanes x 4 pixels = 64 columns
@@ -406,6 +448,7 @@ __global__ __launch_bounds__(256) void back_kernel(
   const int kTOff = 2 * N + 8;
   const double off = 0.5 * (R - 1) + kTOff;
   const double ii = (double)i - half;
+  const double jj = (double)jb - half;
   // nominal tile corners (pixel centres) bound every pixel the lanes evaluate
   const double ci0 = (double)i0 - half, ci1 = (double)(i0 + kBH - 1) - half;
   const double cj0 = (double)j0 - half, cj1 = (double)(j0 + kBW - 1) - half;
@@ -421,8 +464,17 @@ __global__ __launch_bounds__(256) void back_kernel(
       const AngleGeom g = geom[ids.id[a0 + threadIdx.x]];
       const double t00 = det_coord(g, ci0, cj0, off), t01 = det_coord(g, ci0, cj1, off);
       const double t10 = det_coord(g, ci1, cj0, off), t11 = det_coord(g, ci1, cj1, off);
-      tmin[threadIdx.x] = (int)floor(fmin(fmin(t00, t01), fmin(t10, t11))) - 1;
+      const int tm = (int)floor(fmin(fmin(t00, t01), fmin(t10, t11))) - 1;
+      tmin[threadIdx.x] = tm;
       hdA[threadIdx.x] = g.hd;
+      BackAngle A;
+      A.s = g.s;
+      A.c = g.c;
+      A.base = (double)((int)threadIdx.x * kSeg - tm);
+      A.step = __double2ll_rn(g.c * 4294967296.0);
+      A.invd32 = g.invd * 2.3283064365386963e-10f;
+      A.c1 = 1.f - g.invd;
+      ang[threadIdx.x] = A;
     }
     __syncthreads();
     // one independent global load per staged value (unrolled so several are
@@ -438,18 +490,22 @@ __global__ __launch_bounds__(256) void back_kernel(
     if (i < N) {
       const LT* segv = reinterpret_cast<const LT*>(seg);
       for (int a = 0; a < na; ++a) {
-        const AngleGeom g = geom[ids.id[a0 + a]];
-        const double Ti = fma(ii, g.s, off);
-        const LT* sa = segv + a * kSeg - tmin[a];
-        const float invd = g.invd, c1 = 1.f - g.invd;
+        const BackAngle A = ang[a];
+        // the lane's first pixel: the canonical coordinate, moved by an
+        // integer onto the staged segment (exact), split into the 32.32
+        // position T = (segment index of ray floor(t), fraction)
+        const double t = det_coord(A.s, A.c, ii, jj, off) + A.base;
+        const int t0 = (int)t;                      // t >= 1: floor
+        const double fr = t - (double)t0;           // exact
+        uint64_t T = ((uint64_t)(uint32_t)t0 << 32) | (uint32_t)(fr * 4294967296.0);
 #pragma unroll
         for (int q = 0; q < kBPX; ++q) {
-          const double t = fma((double)(jb + q) - half, g.c, Ti);
-          const int t0 = (int)t;                       // t > 0: floor
-          const float f = (float)(t - (double)t0);     // distance to ray t0
-          const float w0 = fmaxf(0.f, fmaf(-f, invd, 1.f));   // 1 - f/d
-          const float w1 = fmaxf(0.f, fmaf(f, invd, c1));     // 1 - (1-f)/d
-          const LT v0 = sa[t0], v1 = sa[t0 + 1];
+          if (q) T += (uint64_t)A.step;             // next column: t + c
+          const uint32_t k = (uint32_t)(T >> 32);
+          const float f = (float)(uint32_t)T;       // 2^32 x distance to ray k
+          const float w0 = unit_clamp(fmaf(-f, A.invd32, 1.f));   // 1 - f/d
+          const float w1 = unit_clamp(fmaf(f, A.invd32, A.c1));   // 1 - (1-f)/d
+          const LT v0 = segv[k], v1 = segv[k + 1];
 #pragma unroll
           for (int b = 0; b < BT; ++b)
             s[q][b] = fmaf(w0, Lane<BT>::get(v0, b), fmaf(w1, Lane<BT>::get(v1, b), s[q][b]));
@@ -704,7 +760,6 @@ static void launch_band(int items, dim3 grid, size_t lds, hipStream_t st, const 
     SLIM_FWD_CASE(4)
     SLIM_FWD_CASE(5)
     SLIM_FWD_CASE(6)
-    SLIM_FWD_CASE(8)
     default:
       launch_it<max_items(BT), BT, IMG>(grid, lds, st, geom, N, R, pl, B, img, imgT, stride,
                                         partial, stop, stop_stride);

@@ -811,7 +811,7 @@ bool valid_tune(const slim_tune& t) {
       if (v == o) return true;
     return false;
   };
-  return in(t.fwd_bt, {0, 1, 2, 4}) && in(t.fwd_items, {0, 2, 4, 6, 8, 10}) &&
+  return in(t.fwd_bt, {0, 1, 2, 4}) && in(t.fwd_items, {0, 2, 3, 4, 6, 8, 10}) &&
          in(t.fwd_slots, {0, 2, 4}) && in(t.back_bt, {0, 1, 2, 4});
 }
 
@@ -895,7 +895,7 @@ slim_status slim_autotune(slim_ctx* c, int n_ids, int force, slim_tune_info* inf
     ProjTune b;
     b.back_bt = bt;
     back_c.push_back(b);
-    for (int it : {2, 4, 6, 8, 10}) {
+    for (int it : {2, 3, 4, 6, 8}) {
       if (it > forward_max_items(bt)) continue;
       for (int sl : {2, 4}) {
         ProjTune f;

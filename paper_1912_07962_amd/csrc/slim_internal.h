@@ -33,12 +33,16 @@ struct AngleGeom {
   int pad;
 };
 
-// Canonical detector coordinate of a pixel.  The back-projector and the Gram
-// kernel evaluate exactly this expression, so the Gram blocks are those of
-// the weights the back-projector applies; the forward projector evaluates
-// the same closed form along rays (equal up to float32 weight rounding).
+// Canonical detector coordinate of a pixel.  The Gram kernel evaluates
+// exactly this expression; the back-projector evaluates it at the first of
+// each lane's pixels and steps along the row in 32.32 fixed point (about
+// 2^-32 apart), and the forward projector evaluates the same closed form
+// along rays, so all three agree up to float32 weight rounding.
+__device__ __forceinline__ double det_coord(double s, double c, double ii, double jj, double off) {
+  return fma(jj, c, fma(ii, s, off));
+}
 __device__ __forceinline__ double det_coord(const AngleGeom& g, double ii, double jj, double off) {
-  return fma(jj, g.c, fma(ii, g.s, off));
+  return det_coord(g.s, g.c, ii, jj, off);
 }
 
 // Joseph weight of a pixel at detector coordinate t on ray tr, 0 if tr is

@@ -162,7 +162,7 @@ def test_every_launch_shape_projects_the_same():
     s = Slim(N, na, r=0, lam=1.0, n_slices=B)
     xd, vd = _dev(x), _dev(v)
     shapes = [dict(fwd_bt=bt, fwd_items=it, fwd_slots=sl) for bt in (1, 2, 4)
-              for it in (2, 4, 6, 8, 10) for sl in (2, 4)]
+              for it in (2, 3, 4, 6, 8, 10) for sl in (2, 4)]
     shapes += [dict(back_bt=bt) for bt in (1, 2, 4)]
     for sh in shapes:
         s.set_tune(**sh)
