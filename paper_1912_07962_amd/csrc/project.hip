@@ -97,7 +97,7 @@ constexpr int kPF = 8;        // float4 prefetch registers per lane: H*N*BT/4 <=
 struct FwdPlan {
   int n;          // entries (= output rows)
   int n_row;      // entries 0..n_row-1 are row-stepping angles
-  int ch;         // angles per chunk
+  int per;        // rays per chunk (= items * threads per workgroup)
   int n_chunks;   // row-stepping chunks first
   int H, G;       // rows per band, bands per group
   int n_groups;
@@ -108,17 +108,26 @@ struct FwdPlan {
   short slot[kMaxList];
 };
 
-__device__ __forceinline__ void chunk_range(const FwdPlan& pl, int c, int& e0, int& e1, bool& colm) {
-  const int nrc = (pl.n_row + pl.ch - 1) / pl.ch;
-  if (c < nrc) {
-    e0 = c * pl.ch;
-    e1 = min(pl.n_row, e0 + pl.ch);
-    colm = false;
-  } else {
-    e0 = pl.n_row + (c - nrc) * pl.ch;
-    e1 = min(pl.n, e0 + pl.ch);
-    colm = true;
-  }
+// Chunk c: rays [i0, i1) of one orientation group, counted from the group's
+// first entry eg (ray i is entry eg + i / R, detector bin i % R).  Chunks may
+// start and end inside an angle.
+__device__ __forceinline__ void chunk_range(const FwdPlan& pl, int R, int c, int& eg, int& i0,
+                                            int& i1, bool& colm) {
+  const int nr = pl.n_row * R;
+  const int nrc = (nr + pl.per - 1) / pl.per;
+  colm = c >= nrc;
+  eg = colm ? pl.n_row : 0;
+  i0 = (colm ? c - nrc : c) * pl.per;
+  i1 = min(colm ? (pl.n - pl.n_row) * R : nr, i0 + pl.per);
+}
+
+// Ray of slot q of a lane within its chunk: slots 2p and 2p+1 of wave w hold
+// rays 2p kFT + 128 w + [0, 64) and that + 64; an unpaired last slot (odd IT)
+// holds (IT - 1) kFT + lane.  Every ray of the chunk is held exactly once.
+template <int IT>
+__device__ __forceinline__ int slot_item(int q, int tid) {
+  if (q < IT - (IT & 1)) return (q >> 1) * 2 * kFT + (tid >> 6) * 128 + (q & 1) * 64 + (tid & 63);
+  return q * kFT + tid;
 }
 
 template <int IT, int BT, typename IMG>
@@ -150,10 +159,10 @@ __global__ __launch_bounds__(kFT, 2) void fwd_band_kernel(const AngleGeom* __res
     for (int b = 0; b < nb; ++b) all = all && stop[(size_t)(b0 + b) * stop_stride + kCtlDone] != 0;
     if (all) return;
   }
-  int e0, e1;
+  int eg, i0, i1;
   bool colm;
-  chunk_range(pl, chunk, e0, e1, colm);
-  const int nitems = (e1 - e0) * R;
+  chunk_range(pl, R, chunk, eg, i0, i1, colm);
+  const int nitems = i1 - i0;
   const IMG* src[BT];
 #pragma unroll
   for (int b = 0; b < BT; ++b) src[b] = (colm ? imgT : img) + (size_t)(b0 + min(b, nb - 1)) * img_stride;
@@ -166,21 +175,24 @@ __global__ __launch_bounds__(kFT, 2) void fwd_band_kernel(const AngleGeom* __res
   // Rounding P0 and S costs at most (k+1) * 2^-33 < 1.2e-7 pixel at k = 1023.
   // Each wavefront walks, per ray slot, the union of its 64 rays' row ranges
   // (a wave-uniform loop); a lane outside its own ray's range reads the zero
-  // pads (its index is clamped into [0, W-2]) and adds nothing.
+  // pads (its index is clamped into [0, W-2]) and adds nothing.  Slots are
+  // walked in pairs, so a wave's two slots of a pair hold neighbouring runs
+  // of 64 rays (similar row ranges); an unpaired last slot takes 64
+  // consecutive rays per wave.
   int64_t P0[IT], S[IT];
   double acc[IT][BT];
   int wlo[IT], whi[IT];
 #pragma unroll
   for (int q = 0; q < IT; ++q) {
-    const int item = threadIdx.x + q * kFT;
+    const int item = slot_item<IT>(q, threadIdx.x);
 #pragma unroll
     for (int b = 0; b < BT; ++b) acc[q][b] = 0.0;
     P0[q] = 0;  // index 0: pad column
     S[q] = 0;
     int klo = N, khi = -1;
     if (item < nitems) {
-      const int e = e0 + item / R;
-      const int t = item % R;
+      const int e = eg + (i0 + item) / R;
+      const int t = (i0 + item) % R;
       const AngleGeom g = geom[pl.id[e]];
       const double cm = colm ? g.c : g.s;   // coefficient of the major coordinate
       const double cn = colm ? g.s : g.c;   // of the minor one, |cn| = d
@@ -328,10 +340,10 @@ __global__ __launch_bounds__(kFT, 2) void fwd_band_kernel(const AngleGeom* __res
   }
 #pragma unroll
   for (int q = 0; q < IT; ++q) {
-    const int item = threadIdx.x + q * kFT;
+    const int item = slot_item<IT>(q, threadIdx.x);
     if (item < nitems) {
-      const int e = e0 + item / R;
-      const int t = item % R;
+      const int e = eg + (i0 + item) / R;
+      const int t = (i0 + item) % R;
 #pragma unroll
       for (int b = 0; b < BT; ++b)
         if (b < nb)
@@ -392,8 +404,9 @@ __global__ __launch_bounds__(256) void fwd_reduce_kernel(
 // ------------------------------------------------------------------- back
 constexpr int kBH = 16, kBW = 64;   // tile rows, columns
 constexpr int kBPX = 4;             // consecutive pixels per lane
-constexpr int kSegFloats = 64 * 72; // LDS floats of staged ray segments
-constexpr int kSeg = 72;            // rays of one angle's segment
+constexpr int kSeg = 72;                // rays of one angle's segment
+constexpr int kSegFloats = 64 * kSeg;   // LDS floats of staged segments
+constexpr int kPre = kSegFloats / 512;  // staged values per lane per pass (two buffers)
 
 // Per-angle constants of one staged pass.  base moves the detector coordinate
 // of the angle's rays onto its LDS segment (segment index = ray - tmin + a *
@@ -423,7 +436,14 @@ __global__ __launch_bounds__(256) void back_kernel(
     double* __restrict__ partials, int mode, const int* __restrict__ stop, int stop_stride,
     uint16_t* __restrict__ xs, uint16_t* __restrict__ xsT) {
   typedef typename Lane<BT>::T LT;
-  constexpr int kAng = kSegFloats / (kSeg * BT);   // angles staged per pass
+  // One slice: the LDS segments form two pass buffers, the next pass loaded
+  // into registers and stored while the current one is used.  Slice tiles:
+  // one buffer of more angles, staged between barriers (the lanes' LDS reads,
+  // not load latency, bound those).
+  constexpr bool kDB = BT == 1;
+  constexpr int kBuf = kDB ? kSegFloats / 2 : kSegFloats;  // floats of one pass buffer
+  constexpr int kPass = kBuf / (kSeg * BT);               // angles staged per pass
+  constexpr int kConst = kDB ? kMaxList : kPass;           // angles with constants held
   const int b0 = blockIdx.z * BT;
   const int nb = min(BT, B - b0);
   if (stop) {
@@ -432,11 +452,13 @@ __global__ __launch_bounds__(256) void back_kernel(
     if (all) return;
   }
   __shared__ float seg[kSegFloats];
-  __shared__ int tmin[kAng];
-  __shared__ float hdA[kAng];
-  __shared__ BackAngle ang[kAng];
-  __shared__ float tile[kBH][kBW + 1];
+  __shared__ int tmin[kConst];
+  __shared__ float hdA[kConst];
+  __shared__ BackAngle ang[kConst];
   __shared__ double wred[4][3 * BT];
+  // the transposed-copy tile reuses the segment buffers once every pass is done
+  static_assert(kSegFloats >= kBH * (kBW + 1), "tile does not fit the segment buffers");
+  float(*tile)[kBW + 1] = reinterpret_cast<float(*)[kBW + 1]>(seg);
   const int tx = threadIdx.x & 15;       // 16 lanes x 4 pixels = 64 columns
   const int ty = threadIdx.x >> 4;       // 16 rows
   const int i0 = blockIdx.y * kBH, j0 = blockIdx.x * kBW;
@@ -452,66 +474,122 @@ __global__ __launch_bounds__(256) void back_kernel(
   // nominal tile corners (pixel centres) bound every pixel the lanes evaluate
   const double ci0 = (double)i0 - half, ci1 = (double)(i0 + kBH - 1) - half;
   const double cj0 = (double)j0 - half, cj1 = (double)(j0 + kBW - 1) - half;
+  // constants of list angle a in slot c: the first ray of its segment (tmin)
+  // and the position constants (base relative to its place in the pass)
+  auto set_const = [&](int a, int c) {
+    const AngleGeom g = geom[ids.id[a]];
+    const double t00 = det_coord(g, ci0, cj0, off), t01 = det_coord(g, ci0, cj1, off);
+    const double t10 = det_coord(g, ci1, cj0, off), t11 = det_coord(g, ci1, cj1, off);
+    const int tm = (int)floor(fmin(fmin(t00, t01), fmin(t10, t11))) - 1;
+    tmin[c] = tm;
+    hdA[c] = g.hd;
+    BackAngle A;
+    A.s = g.s;
+    A.c = g.c;
+    A.base = (double)((a % kPass) * kSeg - tm);
+    A.step = __double2ll_rn(g.c * 4294967296.0);
+    A.invd32 = g.invd * 2.3283064365386963e-10f;
+    A.c1 = 1.f - g.invd;
+    ang[c] = A;
+  };
   float s[kBPX][BT];
 #pragma unroll
   for (int q = 0; q < kBPX; ++q)
 #pragma unroll
     for (int b = 0; b < BT; ++b) s[q][b] = 0.f;
-  for (int a0 = 0; a0 < ids.n; a0 += kAng) {
-    const int na = min(kAng, ids.n - a0);
-    __syncthreads();
-    if ((int)threadIdx.x < na) {
-      const AngleGeom g = geom[ids.id[a0 + threadIdx.x]];
-      const double t00 = det_coord(g, ci0, cj0, off), t01 = det_coord(g, ci0, cj1, off);
-      const double t10 = det_coord(g, ci1, cj0, off), t11 = det_coord(g, ci1, cj1, off);
-      const int tm = (int)floor(fmin(fmin(t00, t01), fmin(t10, t11))) - 1;
-      tmin[threadIdx.x] = tm;
-      hdA[threadIdx.x] = g.hd;
-      BackAngle A;
-      A.s = g.s;
-      A.c = g.c;
-      A.base = (double)((int)threadIdx.x * kSeg - tm);
-      A.step = __double2ll_rn(g.c * 4294967296.0);
-      A.invd32 = g.invd * 2.3283064365386963e-10f;
-      A.c1 = 1.f - g.invd;
-      ang[threadIdx.x] = A;
-    }
-    __syncthreads();
-    // one independent global load per staged value (unrolled so several are
-    // in flight per lane)
-#pragma unroll 6
-    for (int e = threadIdx.x; e < na * kSeg * BT; e += 256) {
-      const int a = e / (kSeg * BT), u = (e / BT) % kSeg, b = e % BT;
-      const int t = tmin[a] + u - kTOff;
-      const VT* vb = v + (size_t)(b0 + min(b, nb - 1)) * v_stride;
-      seg[e] = (t >= 0 && t < R) ? hdA[a] * (float)vb[(size_t)(a0 + a) * R + t] : 0.f;
-    }
-    __syncthreads();
-    if (i < N) {
-      const LT* segv = reinterpret_cast<const LT*>(seg);
-      for (int a = 0; a < na; ++a) {
-        const BackAngle A = ang[a];
-        // the lane's first pixel: the canonical coordinate, moved by an
-        // integer onto the staged segment (exact), split into the 32.32
-        // position T = (segment index of ray floor(t), fraction)
-        const double t = det_coord(A.s, A.c, ii, jj, off) + A.base;
-        const int t0 = (int)t;                      // t >= 1: floor
-        const double fr = t - (double)t0;           // exact
-        uint64_t T = ((uint64_t)(uint32_t)t0 << 32) | (uint32_t)(fr * 4294967296.0);
+  // na angles of a pass from LDS segments segp, constants from slot c0
+  auto accumulate = [&](const float* segp, int c0, int na) {
+    if (i >= N) return;
+    const LT* segv = reinterpret_cast<const LT*>(segp);
+    for (int a = 0; a < na; ++a) {
+      const BackAngle A = ang[c0 + a];
+      // the lane's first pixel: the canonical coordinate, moved by an
+      // integer onto the staged segment (exact), split into the 32.32
+      // position T = (segment index of ray floor(t), fraction)
+      const double t = det_coord(A.s, A.c, ii, jj, off) + A.base;
+      const int t0 = (int)t;                      // t >= 1: floor
+      const double fr = t - (double)t0;           // exact
+      uint64_t T = ((uint64_t)(uint32_t)t0 << 32) | (uint32_t)(fr * 4294967296.0);
 #pragma unroll
-        for (int q = 0; q < kBPX; ++q) {
-          if (q) T += (uint64_t)A.step;             // next column: t + c
-          const uint32_t k = (uint32_t)(T >> 32);
-          const float f = (float)(uint32_t)T;       // 2^32 x distance to ray k
-          const float w0 = unit_clamp(fmaf(-f, A.invd32, 1.f));   // 1 - f/d
-          const float w1 = unit_clamp(fmaf(f, A.invd32, A.c1));   // 1 - (1-f)/d
-          const LT v0 = segv[k], v1 = segv[k + 1];
+      for (int q = 0; q < kBPX; ++q) {
+        if (q) T += (uint64_t)A.step;             // next column: t + c
+        const uint32_t k = (uint32_t)(T >> 32);
+        const float f = (float)(uint32_t)T;       // 2^32 x distance to ray k
+        const float w0 = unit_clamp(fmaf(-f, A.invd32, 1.f));   // 1 - f/d
+        const float w1 = unit_clamp(fmaf(f, A.invd32, A.c1));   // 1 - (1-f)/d
+        const LT v0 = segv[k], v1 = segv[k + 1];
 #pragma unroll
-          for (int b = 0; b < BT; ++b)
-            s[q][b] = fmaf(w0, Lane<BT>::get(v0, b), fmaf(w1, Lane<BT>::get(v1, b), s[q][b]));
-        }
+        for (int b = 0; b < BT; ++b)
+          s[q][b] = fmaf(w0, Lane<BT>::get(v0, b), fmaf(w1, Lane<BT>::get(v1, b), s[q][b]));
       }
     }
+  };
+  // Staged value e of a pass starting at list angle a0: angle a0 + e / (kSeg
+  // BT), segment ray (e / BT) % kSeg, slice e % BT; tmin and h/d from slot
+  // cs(a) of the angle; rays outside [0, R) stage 0.
+  const int npass = (ids.n + kPass - 1) / kPass;
+  if constexpr (kDB) {
+    for (int a = threadIdx.x; a < ids.n; a += 256) set_const(a, a);
+    __syncthreads();
+    // register-held loads of a pass (ray index clamped into the row; the
+    // value is scaled, or zeroed, when stored)
+    VT pf[kPre];
+    auto fetch = [&](int p) {
+      const int a0 = p * kPass, n_e = min(kPass, ids.n - a0) * kSeg * BT;
+#pragma unroll
+      for (int u = 0; u < kPre; ++u) {
+        const int e = (int)threadIdx.x + u * 256;
+        if (e < n_e) {
+          const int a = a0 + e / (kSeg * BT), b = e % BT;
+          const int t = min(max(tmin[a] + (e / BT) % kSeg - kTOff, 0), R - 1);
+          pf[u] = v[(size_t)(b0 + min(b, nb - 1)) * v_stride + (size_t)a * R + t];
+        }
+      }
+    };
+    auto store = [&](int p) {
+      float* dst = seg + (p & 1) * kBuf;
+      const int a0 = p * kPass, n_e = min(kPass, ids.n - a0) * kSeg * BT;
+#pragma unroll
+      for (int u = 0; u < kPre; ++u) {
+        const int e = (int)threadIdx.x + u * 256;
+        if (e < n_e) {
+          const int a = a0 + e / (kSeg * BT);
+          const int t = tmin[a] + (e / BT) % kSeg - kTOff;
+          dst[e] = (t >= 0 && t < R) ? hdA[a] * (float)pf[u] : 0.f;
+        }
+      }
+    };
+    fetch(0);
+    store(0);
+    if (npass > 1) fetch(1);
+    __syncthreads();
+    for (int p = 0; p < npass; ++p) {
+      accumulate(seg + (p & 1) * kBuf, p * kPass, min(kPass, ids.n - p * kPass));
+      if (p + 1 < npass) {
+        store(p + 1);   // the other buffer: its last readers passed the previous barrier
+        if (p + 2 < npass) fetch(p + 2);
+      }
+      __syncthreads();
+    }
+  } else {
+    for (int p = 0; p < npass; ++p) {
+      const int a0 = p * kPass, na = min(kPass, ids.n - a0);
+      __syncthreads();
+      if ((int)threadIdx.x < na) set_const(a0 + threadIdx.x, threadIdx.x);
+      __syncthreads();
+      // one independent global load per staged value (unrolled so several
+      // are in flight per lane)
+#pragma unroll 6
+      for (int e = threadIdx.x; e < na * kSeg * BT; e += 256) {
+        const int a = e / (kSeg * BT), b = e % BT;
+        const int t = tmin[a] + (e / BT) % kSeg - kTOff;
+        const VT* vb = v + (size_t)(b0 + min(b, nb - 1)) * v_stride;
+        seg[e] = (t >= 0 && t < R) ? hdA[a] * (float)vb[(size_t)(a0 + a) * R + t] : 0.f;
+      }
+      __syncthreads();
+      accumulate(seg, 0, na);
+    }
+    __syncthreads();   // the segments are reused as the transposed-copy tile
   }
   const bool full = (i < N) && (jb + kBPX - 1 < N) && ((N & 3) == 0);
   const size_t prow = (size_t)i * N + jb;
@@ -691,8 +769,9 @@ static int fwd_slice_tile(int B, int N) {
   return bt;
 }
 
-// Launch plan: angles grouped by orientation into chunks, slices into tiles of
-// BT, image bands into groups, with chunks * tiles * groups <= 2 * (number of
+// Launch plan: rays grouped by orientation (row-stepping angles first) and
+// cut into chunks of items * kFT rays, slices into tiles of BT, image bands
+// into groups, with chunks * tiles * groups <= 2 * (number of
 // CUs) where possible, so that a launch is one round of resident workgroups
 // (two per CU, bounded by LDS).
 static FwdPlan make_plan(const AngleGeom* h_geom, int N, int R, const AngleList& ids, int B,
@@ -712,9 +791,10 @@ static FwdPlan make_plan(const AngleGeom* h_geom, int N, int R, const AngleList&
   const int BT = tune.fwd_bt > 0 ? std::min(tune.fwd_bt, slice_tile(B)) : fwd_slice_tile(B, N);
   pl.bt = BT;
   const int cap = tune.fwd_items > 0 ? std::min(tune.fwd_items, max_items(BT)) : max_items(BT);
-  pl.ch = std::max(1, std::min(cap * kFT / R, ids.n));
-  pl.items = item_count(BT, std::max(1, (pl.ch * R + kFT - 1) / kFT));
-  pl.n_chunks = (pl.n_row + pl.ch - 1) / pl.ch + (ids.n - pl.n_row + pl.ch - 1) / pl.ch;
+  const int most = std::max(pl.n_row, ids.n - pl.n_row) * R;   // rays of the larger group
+  pl.items = item_count(BT, std::max(1, std::min(cap, (most + kFT - 1) / kFT)));
+  pl.per = pl.items * kFT;
+  pl.n_chunks = (pl.n_row * R + pl.per - 1) / pl.per + ((ids.n - pl.n_row) * R + pl.per - 1) / pl.per;
   pl.n_tiles = (B + BT - 1) / BT;
   pl.H = std::max(1, std::min(N, 16384 / ((N + 2 * kPad) * BT)));
   const int nbands = (N + pl.H - 1) / pl.H;
