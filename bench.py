@@ -54,22 +54,36 @@ PEAK_BF16_TFLOPS = 2500.0
 
 # HBM bytes per launch of the CG projector kernels on this workload, from
 # rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE (KiB per dispatch, mean over the
-# timed steps; profiles/ has the summary and command), each scaled by what the
-# counter reads for a copy of 256 MiB (FETCH reads half: x2.0; WRITE x1.0).
-# Valid only for the projector source they were taken on (SHA-256 below);
-# otherwise the line reports traffic as null.
+# 88-angle window launches; profiles/ has the summary and commands), each
+# scaled by what the counter reads for a copy of 256 MiB (FETCH reads half:
+# x2.0; WRITE x1.0), per kernel instance: the forward for every rays-per-lane
+# count the autotuner can pick, the back-projector's one-slice tile.  Valid
+# only for the projector source they were taken on (SHA-256 below); otherwise
+# the line reports traffic as null.
 PMC_TRAFFIC = {
     "source": "paper_1912_07962_amd/csrc/project.hip",
-    "sha256": "9414a2208ddae9eb991410e2c0a8f9eaeecb4dc85e647b37f74d08544daea995",
+    "sha256": "54b2aac3144ea603b12da2e2fb399f2589022024624f9c54f9af64787eab6dc7",
     "fetch_scale": 2.0,
     "write_scale": 1.0,
-    # kind -> (FETCH_SIZE, WRITE_SIZE) KiB per dispatch
-    "kib": {"cg_back": (2666.4, 7209.5), "cg_forward": (4029.9, 8218.7)},
+    # instance -> (FETCH_SIZE, WRITE_SIZE) KiB per dispatch
+    "kib": {"cg_forward/2": (5219.6, 1673.6), "cg_forward/3": (5287.9, 2540.3),
+            "cg_forward/4": (3565.7, 3387.0), "cg_forward/6": (4807.2, 4208.9),
+            "cg_forward/8": (4342.9, 5892.5), "cg_back/1": (2633.1, 6931.2)},
 }
 
 
+def fwd_rays_per_lane(fwd_items, rays_in_group):
+    """Rays per lane (the band kernel's IT) the library's launch plan uses for
+    a one-slice forward: the tune's cap (0: the maximum, 8), limited to what
+    the larger orientation group needs, rounded up to an instantiated value."""
+    cap = min(fwd_items, 8) if fwd_items > 0 else 8
+    want = max(1, min(cap, -(-rays_in_group // 512)))
+    return want if want <= 6 else 8
+
+
 def pmc_traffic(kind):
-    """Scaled HBM bytes per launch of a kernel kind, or None."""
+    """Scaled HBM bytes per launch of a kernel instance ("cg_forward/IT",
+    "cg_back/BT"), or None."""
     import hashlib
     t = PMC_TRAFFIC
     if t["sha256"] is None or kind not in t["kib"]:
@@ -459,6 +473,10 @@ def main():
     ap.add_argument("--volume-steps", type=int, default=4, help="timed volume steps")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the built-in projector launch shapes")
+    ap.add_argument("--fix-tune", default=None, metavar="FB,FI,FS,BB",
+                    help="launch shape of the 1024^2 context (fwd_bt, fwd_items, fwd_slots, "
+                         "back_bt) instead of its autotuner search; profiling runs pin it, "
+                         "since a profiler perturbs the search's timings")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="copy 256 MiB once before timing (a kernel of known traffic for "
                          "scaling hardware byte counters)")
@@ -493,7 +511,12 @@ def main():
     main_stream = torch.cuda.Stream()
     s = Slim(N, na, r=r, lam=lam, angles_per_block=g, gram_mode="pcg", pcg_tol=1e-6,
              stream=main_stream)
-    tune = None if args.no_autotune else s.autotune()
+    if args.fix_tune:
+        fb, fi, fs, bb = (int(v) for v in args.fix_tune.split(","))
+        s.set_tune(fwd_bt=fb, fwd_items=fi, fwd_slots=fs, back_bt=bb)
+        tune = {"fixed": s.get_tune()}
+    else:
+        tune = None if args.no_autotune else s.autotune()
     R = s.R
     ell = g * R
     M = na // g
@@ -552,6 +575,12 @@ def main():
 
     # dominant kernel: CG forward or back over the window (same work per launch)
     dom = max(("cg_forward", "cg_back"), key=lambda k: stats[k]["total_ms"])
+    shape = s.get_tune()
+    n_row = sum(1 for a in ids if abs(np.cos(theta[a])) >= abs(np.sin(theta[a])))
+    inst = (f"cg_forward/{fwd_rays_per_lane(shape['fwd_items'], max(n_row, len(ids) - n_row) * R)}"
+            if dom == "cg_forward" else "cg_back/1")
+    kernel_name = (f"fwd_band_kernel<{inst.split('/')[1]}, 1, float>" if dom == "cg_forward"
+                   else "back_kernel<double, 1>")
     st = stats[dom]
     avg_ms = st["total_ms"] / max(st["launches"], 1)
     flops_per_launch = flops_cg / max(sum(prof_iters), 1)
@@ -628,9 +657,9 @@ def main():
         "config": {"workload": "plain slimLS, 1024x1024 image, 720 angles x 1449 rays, "
                                "8 angles/block, r=10, lambda=1e-3, CG to 1e-6",
                    "parallelism": "single GPU"},
-        "roofline": {"bound": "alu", "kernel": f"{dom} (88-angle window)",
+        "roofline": {"bound": "alu", "kernel": f"{dom}: {kernel_name} (88-angle window)",
                      "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": pmc_traffic(dom),
+                     "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": pmc_traffic(inst),
                      "avg_launch_us": avg_ms * 1e3, "flops_per_launch": flops_per_launch},
         "cpu_baseline": cpu,
         "autotune": tune,
