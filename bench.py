@@ -30,6 +30,8 @@ time).  The line also carries:
   mixed         64 x 256^2 + 32 x 512^2 + 8 x 1024^2 slices (360 angles, 4
                 angles/block, r = 8): one context per size, stepped as one
                 group with interleaved CG, vs the contexts one after another;
+  gram_solve    explicit Gram mode on 256^2 (p = 2178): Gram update and FP64
+                Cholesky + solves per step, the factorisation's FP64 TFLOP/s;
   warm_start    the learned warm start on 256^2 (180 angles, 1 angle/block,
                 r = 5): steps to each held-out sample's e* from x0 = 0 and
                 from x0 = CNN(u), single-slice wall-clock time-to-target with
@@ -51,6 +53,7 @@ sys.path.insert(0, ROOT)
 PEAK_FP32_VECTOR_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
 PEAK_BF16_TFLOPS = 2500.0
+PEAK_FP64_TFLOPS = 78.6
 
 # HBM bytes per launch of the CG projector kernels on this workload, from
 # rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE (KiB per dispatch, mean over the
@@ -317,6 +320,50 @@ def volume_bench(dev, B, steps, autotune=True):
 
 
 
+def gram_bench(dev, steps):
+    """Explicit Gram mode on the 256^2 workload (180 angles x 363 rays, 1
+    angle/block, r = 5, lambda = 1e-2, p = 6 x 363 = 2178): per-step times of
+    the Gram update (new block row of tiles + assembly of G) and of the FP64
+    Cholesky with its two triangular solves, after the window has filled;
+    the factorisation's p^3/3 flop against the FP64 peak."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_1912_07962_amd import Slim
+
+    cfg = synth.get_config("c5")
+    N, na, g, r, lam = cfg["N"], cfg["n_angles"], cfg["g"], cfg["r"], cfg["lam"]
+    x_true, b, _ = synth.make_slice_problem(N, na, cfg["n_ellipses"], cfg["noise"], 20000, 1020000)
+    st = torch.cuda.Stream()
+    s = Slim(N, na, r=r, lam=lam, angles_per_block=g, gram_mode="chol", stream=st)
+    x = torch.zeros((N, N), dtype=torch.float32, device=dev)
+    torch.cuda.synchronize()
+    s.set_data(torch.as_tensor(b, dtype=torch.float32, device=dev), x,
+               torch.as_tensor(x_true, dtype=torch.float32, device=dev))
+    sched = synth.schedule(na // g, 2, cfg["schedule_seed"])
+    for k in range(r + 1):
+        s.step([int(sched[k])])
+    torch.cuda.synchronize()
+    s.profile(True)
+    t0 = time.perf_counter()
+    for k in range(r + 1, r + 1 + steps):
+        s.step([int(sched[k])])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    stats = s.kernel_stats()
+    s.profile(False)
+    s.close()
+    p = (r + 1) * g * s.R
+    chol_ms = stats["cholesky"]["total_ms"] / steps
+    gram_ms = stats["gram"]["total_ms"] / steps
+    flops = p ** 3 / 3.0
+    return {"workload": "256x256 image, 180 angles x 363 rays, 1 angle/block, r=5, lambda=1e-2",
+            "p": p, "steps": steps, "ms_per_step": wall / steps * 1e3,
+            "gram_ms_per_step": gram_ms, "cholesky_and_solves_ms_per_step": chol_ms,
+            "factor_fp64_tflops": flops / (chol_ms * 1e-3) / 1e12,
+            "factor_frac_fp64_peak": flops / (chol_ms * 1e-3) / 1e12 / PEAK_FP64_TFLOPS}
+
+
 def warm_bench(dev, n_test, n_timed):
     """Learned warm start on the 256^2 workload (180 angles x 363 rays, 1
     angle/block, r = 5, lambda = 1e-2) with the trained parameters shipped
@@ -482,6 +529,8 @@ def main():
                          "scaling hardware byte counters)")
     ap.add_argument("--mixed-steps", type=int, default=3,
                     help="timed steps of the mixed batch (0 skips it)")
+    ap.add_argument("--gram-steps", type=int, default=20,
+                    help="timed steps of the explicit-Gram (FP64 Cholesky) 256^2 run (0 skips it)")
     ap.add_argument("--warm-test", type=int, default=256,
                     help="held-out samples of the warm-start evaluation (0 skips it)")
     ap.add_argument("--warm-timed", type=int, default=8,
@@ -623,6 +672,11 @@ def main():
     if not args.no_batched:
         batched = batched_ttr(cfg, s, sched, dev, args.batch, not args.no_autotune)
 
+    gram = None
+    if args.gram_steps > 0:
+        print("bench: explicit Gram mode, 256^2", file=sys.stderr, flush=True)
+        gram = gram_bench(dev, args.gram_steps)
+
     warm = None
     if args.warm_test > 0:
         warm = warm_bench(dev, args.warm_test, min(args.warm_timed, args.warm_test))
@@ -668,6 +722,7 @@ def main():
         "batched": batched,
         "volume": volume,
         "mixed": mixed,
+        "gram_solve": gram,
         "warm_start": warm,
         "cg_iters_per_step": float(np.mean(iters)),
         "event_ms_timed_region": ev_ms,

@@ -97,7 +97,39 @@ __global__ void tile_copy_kernel(const double* __restrict__ src, int64_t lds, do
   G[(int64_t)(r0 + r) * ldg + (c0 + c)] = v;
 }
 
+// All tiles of the lower triangle of G in one launch: blockIdx.z enumerates
+// the window pairs P >= Q (z = P (P + 1) / 2 + Q); window position P holds
+// ring slot (first + P) mod S; tile (sp, sq) of the ring is
+// tiles[(sp S + sq) ell^2], row-major ell x ell.  lambda goes on G's diagonal.
+__global__ void tile_assemble_kernel(const double* __restrict__ tiles, int S, int first, int ell,
+                                     double* __restrict__ G, int64_t ldg, double lam) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
+  if (c >= ell) return;
+  const int z = blockIdx.z;
+  int P = (int)((sqrt(8.0 * z + 1.0) - 1.0) * 0.5);
+  while ((P + 1) * (P + 2) / 2 <= z) ++P;   // guard the float estimate
+  while (P * (P + 1) / 2 > z) --P;
+  const int Q = z - P * (P + 1) / 2;
+  const int sp = (first + P) % S, sq = (first + Q) % S;
+  const double* T = tiles + ((int64_t)sp * S + sq) * ell * ell;
+  double v = T[(int64_t)r * ell + c];
+  if (P == Q && r == c) v += lam;
+  G[(int64_t)(P * ell + r) * ldg + (Q * ell + c)] = v;
+}
+
 }  // namespace
+
+hipError_t launch_tile_assemble(const double* tiles, int S, int first, int W, int ell, double* G,
+                                int64_t ldg, double lam, hipStream_t st) {
+  const int64_t pairs = (int64_t)W * (W + 1) / 2;
+  if (pairs == 0 || ell == 0) return hipSuccess;
+  if (pairs > 65535 || ell > 65535) return hipErrorInvalidValue;
+  dim3 grid((ell + 255) / 256, ell, (unsigned)pairs);
+  hipLaunchKernelGGL(tile_assemble_kernel, grid, dim3(256), 0, st, tiles, S, first, ell, G, ldg,
+                     lam);
+  return hipGetLastError();
+}
 
 hipError_t launch_gram(const AngleGeom* geom, int N, int R, const AngleList& ida,
                        const AngleList& idb, double* out, int64_t ld, hipStream_t st) {

@@ -107,6 +107,7 @@ struct slim_ctx {
   double* d_tiles = nullptr;   // [(r+1)^2][ell][ell]
   double* d_G = nullptr;       // [pmax][pmax]
   double* d_cholwork = nullptr;// inverse of a diagonal block (Cholesky scratch)
+  double* d_ysolve = nullptr;  // [B][pmax] triangular-solve scratch
   double* d_z = nullptr;       // [B][pmax]
   int* d_info = nullptr;
   double* d_partials = nullptr;
@@ -143,6 +144,7 @@ struct slim_ctx {
     (void)hipFree(d_tiles);
     (void)hipFree(d_G);
     (void)hipFree(d_cholwork);
+    (void)hipFree(d_ysolve);
     (void)hipFree(d_z);
     (void)hipFree(d_info);
     (void)hipFree(d_partials);
@@ -250,20 +252,28 @@ slim_status gram_solve_chol(slim_ctx* c, int new_slot) {
     double* T = c->d_tiles + ((int64_t)new_slot * S + q) * ell * ell;
     HIP_TRY(launch_gram(c->d_geom, c->N, c->R, na, nb, T, ell, c->st));
   }
-  // assemble the lower triangle of G in window order (oldest first)
-  for (int P = 0; P < W; ++P)
-    for (int Q = 0; Q <= P; ++Q) {
-      const int sp = c->window[P], sq = c->window[Q];
-      const double* T = c->d_tiles + ((int64_t)sp * S + sq) * ell * ell;
-      HIP_TRY(launch_tile_copy(T, ell, c->d_G, p, (int)(P * ell), (int)(Q * ell), (int)ell,
-                               (int)ell, c->lam, P == Q, c->st));
-    }
+  // assemble the lower triangle of G in window order (oldest first); the
+  // window is consecutive ring slots, so one launch places every tile
+  bool ring = true;
+  for (int P = 0; P < W; ++P) ring = ring && c->window[P] == (c->window[0] + P) % S;
+  if (ring && (int64_t)W * (W + 1) / 2 <= 65535 && ell <= 65535) {
+    HIP_TRY(launch_tile_assemble(c->d_tiles, S, c->window[0], W, (int)ell, c->d_G, p, c->lam,
+                                 c->st));
+  } else {
+    for (int P = 0; P < W; ++P)
+      for (int Q = 0; Q <= P; ++Q) {
+        const int sp = c->window[P], sq = c->window[Q];
+        const double* T = c->d_tiles + ((int64_t)sp * S + sq) * ell * ell;
+        HIP_TRY(launch_tile_copy(T, ell, c->d_G, p, (int)(P * ell), (int)(Q * ell), (int)ell,
+                                 (int)ell, c->lam, P == Q, c->st));
+      }
+  }
   if (c->prof.on) HIP_TRY(c->prof.end(c->st));
   if (c->prof.on) HIP_TRY(c->prof.begin(K_CHOL, c->st));
   HIP_TRY(hipMemsetAsync(c->d_info, 0, sizeof(int), c->st));
   HIP_TRY(launch_cholesky(c->d_G, p, (int)p, c->d_info, c->d_cholwork, c->st));
-  HIP_TRY(launch_chol_solve(c->d_G, p, (int)p, (int)ell, c->d_cholwork, c->d_res64, ell, c->d_z, c->pmax, c->B,
-                            c->st));
+  HIP_TRY(launch_chol_solve(c->d_G, p, (int)p, (int)ell, c->d_cholwork, c->d_res64, ell, c->d_z, c->pmax,
+                            c->d_ysolve, c->B, c->st));
   if (c->prof.on) HIP_TRY(c->prof.end(c->st));
   return SLIM_OK;
 }
@@ -517,6 +527,7 @@ slim_status slim_init(slim_ctx** out, const slim_grid* grid, int n_angles, const
     if ((e = dalloc(&c->d_tiles, (size_t)(r + 1) * (r + 1) * ell * ell)) != hipSuccess) return oom(e);
     if ((e = dalloc(&c->d_G, (size_t)pmax * pmax)) != hipSuccess) return oom(e);
     if ((e = dalloc(&c->d_cholwork, chol_work_doubles(pmax))) != hipSuccess) return oom(e);
+    if ((e = dalloc(&c->d_ysolve, (size_t)c->B * pmax)) != hipSuccess) return oom(e);
   } else {
     if ((e = pcg_alloc(c->pcg, c->N, c->B, pmax)) != hipSuccess) return oom(e);
   }

@@ -189,6 +189,12 @@ hipError_t launch_gram(const AngleGeom* geom, int N, int R, const AngleList& ida
 
 // Copy a tile (rows x cols, leading dimension lds) into G at (r0, c0) with
 // leading dimension ldg, adding diag to its diagonal when add_diag != 0.
+// The lower triangle of G (ldg) from the tiles of the W window positions in
+// one launch: position P holds ring slot (first + P) mod S, tile (sp, sq) at
+// tiles + (sp S + sq) ell^2 (row-major ell x ell), lambda added on the
+// diagonal.  hipErrorInvalidValue if W (W + 1) / 2 or ell exceed 65535.
+hipError_t launch_tile_assemble(const double* tiles, int S, int first, int W, int ell, double* G,
+                                int64_t ldg, double lam, hipStream_t st);
 hipError_t launch_tile_copy(const double* src, int64_t lds, double* G, int64_t ldg, int r0,
                             int c0, int rows, int cols, double diag, int add_diag,
                             hipStream_t st);
@@ -203,10 +209,11 @@ hipError_t launch_cholesky(double* G, int64_t ld, int p, int* info, double* work
 
 // For each of B right-hand sides: solve L y = e with e = [0; rhs] (rhs: the
 // last nr entries, rhs64 + slice * rhs_stride) and L^T z = y
-// (z + slice * z_stride, float64 [p]).
+// (z + slice * z_stride, float64 [p]).  ywork: B * z_stride doubles of
+// scratch (y per right-hand side).
 hipError_t launch_chol_solve(const double* L, int64_t ld, int p, int nr, const double* work,
                              const double* rhs64, size_t rhs_stride, double* z, size_t z_stride,
-                             int B, hipStream_t st);
+                             double* ywork, int B, hipStream_t st);
 
 // out[s][i][t] = b[s][ids[i]][t] as float32 for B slices (b float32 or bf16,
 // slice stride n_angles * R).
