@@ -15,11 +15,12 @@ struct PcgWork {
   int nparts = 0;           // partial sums per slice
   double* r = nullptr;      // residuals          [B][pmax]
   double* pd = nullptr;     // search directions  [B][pmax]
-  double* q = nullptr;      // G pd               [B][pmax]
-  double* parts = nullptr;  // per-workgroup partial dots <pd,q>, <r,r>: [2][B][nparts]
+  double* q = nullptr;      // G r                [B][pmax]
+  double* s = nullptr;      // G pd (recurrence)  [B][pmax]
+  double* parts = nullptr;  // per-workgroup partial dots <r,q>, <r,r>: [2][B][nparts]
   double* sc = nullptr;     // per-slice scalars, two sets used alternately [2][B][S]
   int* ctl = nullptr;       // per-slice stop flag and iteration count [B][kCtlCount]
-  float* u = nullptr;       // M^T pd             [B][N][N]
+  float* u = nullptr;       // M^T r              [B][N][N]
   float* uT = nullptr;      // its transpose      [B][N][N]
   int* h_ctl = nullptr;     // pinned copies of ctl, one per chunk in flight
   double* h_sc = nullptr;   // pinned copy of sc

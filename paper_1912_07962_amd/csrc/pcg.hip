@@ -2,18 +2,25 @@
 // e = [0; ...; 0; res], for a batch of slices that share M (each slice runs
 // its own CG; all advance together in the same launches), with matrix-free
 // M and M^T.
-// Per iteration:
-//   u = M^T pd                 back-projector (float32 image and transpose)
-//   q = M u + lambda pd        forward projector, float64 sums, with the
-//                              partial sums of <pd, q> fused in its reduction
-//   alpha = rr / <pd, q> ; z += alpha pd ; r -= alpha q ; partials of <r, r>
-//   beta = rr_new / rr ; pd = r + beta pd
+// The iteration is CG in the form with one reduction phase per iteration
+// (Chronopoulos and Gear, 1989): the operator is applied to the residual and
+// G pd is carried by a recurrence, so both dot products come from the same
+// vectors and are formed together.  Per iteration:
+//   u = M^T r                  back-projector (float32 image and transpose)
+//   q = M u + lambda r         forward projector, float64 sums, with the
+//                              partial sums of delta = <r, q> and
+//                              gamma = <r, r> fused in its reduction
+//   stop if gamma <= tol^2 <e, e>; else beta = gamma / gamma_old,
+//   alpha = gamma / (delta - beta gamma / alpha_old) (first: beta = 0,
+//   alpha = gamma / delta), pd = r + beta pd, s = q + beta s,
+//   z += alpha pd, r -= alpha s
+// (in exact arithmetic the iterates of standard CG).
 // Block preconditioners (Jacobi, the exact per-angle tridiagonal block, the
 // exact per-block inverse) left the iteration count unchanged or raised it
 // on this Gram (its conditioning comes from low-frequency modes shared by
 // all blocks), so the iteration is unpreconditioned.
 //
-// Termination is decided on the device: the direction kernel sets a slice's
+// Termination is decided on the device: the vector kernel sets a slice's
 // flag once its ||r|| <= tol ||e|| and every later CG kernel skips that
 // slice (the projectors skip a slice tile once all its slices stopped).  The
 // host enqueues chunks of iterations ahead and reads the flag from pinned
@@ -33,7 +40,9 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kChunk = 8;   // iterations enqueued per host check
 
-enum { S_RR = 0, S_ALPHA, S_BETA, S_PQ, S_BB, S_COUNT };
+// per-slice scalars: gamma and alpha of the last update (gamma 0 before the
+// first), beta, <e, e>, and (set 0 only) the latest gamma
+enum { S_RR = 0, S_ALPHA, S_BETA, S_BB, S_LAST, S_COUNT };
 
 __device__ __forceinline__ double block_sum(double v, double* sh) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
@@ -46,6 +55,27 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   return r;
 }
 
+// Two block sums at once (a fixed order: the same values in every lane).
+__device__ __forceinline__ void block_sum2(double& a, double& b, double* sh) {
+  for (int o = 32; o > 0; o >>= 1) {
+    a += __shfl_down(a, o, 64);
+    b += __shfl_down(b, o, 64);
+  }
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    sh[w] = a;
+    sh[kThreads / 64 + w] = b;
+  }
+  __syncthreads();
+  a = 0.0;
+  b = 0.0;
+  for (int q = 0; q < kThreads / 64; ++q) {
+    a += sh[q];
+    b += sh[kThreads / 64 + q];
+  }
+  __syncthreads();
+}
+
 // Sum of a partial-sum array, computed redundantly by every workgroup in a
 // fixed order (the same value in all of them).
 __device__ __forceinline__ double sum_parts(const double* __restrict__ parts, int n, double* sh) {
@@ -54,13 +84,14 @@ __device__ __forceinline__ double sum_parts(const double* __restrict__ parts, in
   return block_sum(a, sh);
 }
 
-// r = e, z = 0, pd = e; partials of <r, r>.  blockIdx.y = slice.
+// r = e, z = 0, pd = 0, s = 0; partials of <r, r>.  blockIdx.y = slice.
 __global__ __launch_bounds__(kThreads) void init_kernel(int p, int nres, int pmax, int nparts,
                                                         const double* __restrict__ res,
                                                         size_t res_stride,
                                                         double* __restrict__ r,
                                                         double* __restrict__ z, size_t z_stride,
                                                         double* __restrict__ pd,
+                                                        double* __restrict__ sv,
                                                         double* __restrict__ rr_parts) {
   __shared__ double sh[kThreads / 64];
   const int sl = blockIdx.y;
@@ -71,7 +102,8 @@ __global__ __launch_bounds__(kThreads) void init_kernel(int p, int nres, int pma
     const double e = (i >= p - nres) ? res[(size_t)sl * res_stride + i - (p - nres)] : 0.0;
     r[vo + i] = e;
     z[(size_t)sl * z_stride + i] = 0.0;
-    pd[vo + i] = e;
+    pd[vo + i] = 0.0;
+    sv[vo + i] = 0.0;
     rr = e * e;
   }
   rr = block_sum(rr, sh);
@@ -87,77 +119,75 @@ __global__ __launch_bounds__(kThreads) void init_scalars_kernel(const double* __
   const double bb = sum_parts(rr_parts + (size_t)sl * nparts, nb, sh);
   if (threadIdx.x == 0) {
     double* c = sc + (size_t)sl * S_COUNT;
-    c[S_RR] = bb;
+    c[S_RR] = 0.0;   // no update yet: the first one takes beta = 0
+    c[S_ALPHA] = 1.0;
     c[S_BB] = bb;
     c[S_BETA] = 0.0;
+    c[S_LAST] = bb;
     ctl[sl * kCtlCount + kCtlDone] = (bb > 0.0) ? 0 : 1;
     ctl[sl * kCtlCount + kCtlIters] = 0;
   }
 }
 
-// alpha = rr / <pd, q>; z += alpha pd; r -= alpha q; partials of <r, r>
-__global__ __launch_bounds__(kThreads) void update_kernel(int p, int pmax, int nb, int nparts,
-                                                          double* __restrict__ sc_all,
-                                                          const double* __restrict__ pq_parts,
-                                                          const double* __restrict__ pd,
-                                                          const double* __restrict__ q,
-                                                          double* __restrict__ z, size_t z_stride,
-                                                          double* __restrict__ r,
-                                                          double* __restrict__ rr_parts,
-                                                          const int* __restrict__ ctl) {
-  const int sl = blockIdx.y;
-  if (ctl[sl * kCtlCount + kCtlDone]) return;
-  __shared__ double sh[kThreads / 64];
-  double* sc = sc_all + (size_t)sl * S_COUNT;
-  const size_t vo = (size_t)sl * pmax;
-  const int i = blockIdx.x * kThreads + threadIdx.x;
-  const double pq = sum_parts(pq_parts + (size_t)sl * nparts, nb, sh);
-  const double alpha = (pq != 0.0) ? sc[S_RR] / pq : 0.0;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    sc[S_PQ] = pq;
-    sc[S_ALPHA] = alpha;
-  }
-  double rr = 0.0;
-  if (i < p) {
-    double* zs = z + (size_t)sl * z_stride;
-    zs[i] = fma(alpha, pd[vo + i], zs[i]);
-    const double rn = fma(-alpha, q[vo + i], r[vo + i]);
-    r[vo + i] = rn;
-    rr = rn * rn;
-  }
-  rr = block_sum(rr, sh);
-  if (threadIdx.x == 0) rr_parts[(size_t)sl * nparts + blockIdx.x] = rr;
-}
-
-// beta = rr_new / rr; pd = r + beta pd.  Every workgroup reads the current
-// scalars in sc while workgroup 0 of the slice publishes the next ones in
-// sc_next (the two sets alternate), counts the iteration and raises the
-// slice's stop flag.
-__global__ __launch_bounds__(kThreads) void direction_kernel(int p, int pmax, int nb, int nparts,
+// One update from the forward reduction's partials of delta = <r, q> and
+// gamma = <r, r> (q = G r), each summed in a fixed order by every workgroup.
+// Converged (gamma <= tol^2 <e, e>, NaN included): no update, workgroup 0
+// raises the stop flag.  Otherwise pd = r + beta pd, s = q + beta s,
+// z += alpha pd, r -= alpha s, and workgroup 0 publishes gamma and alpha in
+// sc_next (the two sets alternate) and counts the iteration.  last: set 0 of
+// the scalars (its S_LAST slot, read by no kernel, holds the latest gamma).
+__global__ __launch_bounds__(kThreads) void cg_vector_kernel(int p, int pmax, int nb, int nparts,
                                                              const double* __restrict__ sc_all,
                                                              double* __restrict__ sc_next_all,
+                                                             double* __restrict__ last_all,
+                                                             const double* __restrict__ dq_parts,
                                                              const double* __restrict__ rr_parts,
                                                              double tol2,
-                                                             const double* __restrict__ r,
+                                                             const double* __restrict__ q,
+                                                             double* __restrict__ r,
                                                              double* __restrict__ pd,
+                                                             double* __restrict__ sv,
+                                                             double* __restrict__ z,
+                                                             size_t z_stride,
                                                              int* __restrict__ ctl) {
   const int sl = blockIdx.y;
   if (ctl[sl * kCtlCount + kCtlDone]) return;
-  __shared__ double sh[kThreads / 64];
+  __shared__ double sh[2 * (kThreads / 64)];
   const double* sc = sc_all + (size_t)sl * S_COUNT;
-  double* sc_next = sc_next_all + (size_t)sl * S_COUNT;
-  const size_t vo = (size_t)sl * pmax;
-  const double rr_new = sum_parts(rr_parts + (size_t)sl * nparts, nb, sh);
-  const double rr = sc[S_RR];
-  const double beta = (rr != 0.0) ? rr_new / rr : 0.0;
-  const int i = blockIdx.x * kThreads + threadIdx.x;
-  if (i < p) pd[vo + i] = fma(beta, pd[vo + i], r[vo + i]);
+  double delta = 0.0, gamma = 0.0;
+  for (int k = threadIdx.x; k < nb; k += kThreads) {
+    delta += dq_parts[(size_t)sl * nparts + k];
+    gamma += rr_parts[(size_t)sl * nparts + k];
+  }
+  block_sum2(delta, gamma, sh);
+  const double bb = sc[S_BB], g_old = sc[S_RR], a_old = sc[S_ALPHA];
+  const bool conv = !(gamma > tol2 * bb);
+  const double beta = (g_old > 0.0) ? gamma / g_old : 0.0;
+  const double alpha = (g_old > 0.0) ? gamma / (delta - beta * gamma / a_old) : gamma / delta;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
-    sc_next[S_RR] = rr_new;
-    sc_next[S_BETA] = beta;
-    sc_next[S_BB] = sc[S_BB];
-    ctl[sl * kCtlCount + kCtlIters] += 1;
-    if (!(rr_new > tol2 * sc[S_BB])) ctl[sl * kCtlCount + kCtlDone] = 1;  // also stops on NaN
+    last_all[(size_t)sl * S_COUNT + S_LAST] = gamma;
+    if (conv) {
+      ctl[sl * kCtlCount + kCtlDone] = 1;
+    } else {
+      double* sn = sc_next_all + (size_t)sl * S_COUNT;
+      sn[S_RR] = gamma;
+      sn[S_ALPHA] = alpha;
+      sn[S_BETA] = beta;
+      sn[S_BB] = bb;
+      ctl[sl * kCtlCount + kCtlIters] += 1;
+    }
+  }
+  if (conv) return;
+  const int i = blockIdx.x * kThreads + threadIdx.x;
+  if (i < p) {
+    const size_t o = (size_t)sl * pmax + i;
+    const double pn = fma(beta, pd[o], r[o]);
+    const double sn = fma(beta, sv[o], q[o]);
+    pd[o] = pn;
+    sv[o] = sn;
+    double* zs = z + (size_t)sl * z_stride;
+    zs[i] = fma(alpha, pn, zs[i]);
+    r[o] = fma(-alpha, sn, r[o]);
   }
 }
 
@@ -172,6 +202,7 @@ hipError_t pcg_alloc(PcgWork& w, int N, int B, int64_t pmax) {
   if ((e = hipMalloc((void**)&w.r, np)) != hipSuccess) return e;
   if ((e = hipMalloc((void**)&w.pd, np)) != hipSuccess) return e;
   if ((e = hipMalloc((void**)&w.q, np)) != hipSuccess) return e;
+  if ((e = hipMalloc((void**)&w.s, np)) != hipSuccess) return e;
   if ((e = hipMalloc((void**)&w.parts, (size_t)2 * B * w.nparts * sizeof(double))) != hipSuccess)
     return e;
   if ((e = hipMalloc((void**)&w.sc, (size_t)2 * B * S_COUNT * sizeof(double))) != hipSuccess) return e;
@@ -195,6 +226,7 @@ void pcg_free(PcgWork& w) {
   (void)hipFree(w.r);
   (void)hipFree(w.pd);
   (void)hipFree(w.q);
+  (void)hipFree(w.s);
   (void)hipFree(w.parts);
   (void)hipFree(w.sc);
   (void)hipFree(w.ctl);
@@ -226,10 +258,10 @@ hipError_t pcg_begin(PcgRun& run, PcgWork& w, const AngleGeom* geom, const Angle
   run.enq = run.chunks = run.seen = 0;
   run.done = false;
   const int np = w.nparts;
-  double* rr_parts = w.parts + (size_t)B * np;  // written by init / update
+  double* rr_parts = w.parts + (size_t)B * np;  // written by init / the forward reduction
   const size_t img = (size_t)N * N;
   hipLaunchKernelGGL(init_kernel, dim3(run.nb, B), dim3(kThreads), 0, st, run.p, nres, w.pmax,
-                     np, res, res_stride, w.r, z, z_stride, w.pd, rr_parts);
+                     np, res, res_stride, w.r, z, z_stride, w.pd, w.s, rr_parts);
   hipLaunchKernelGGL(init_scalars_kernel, dim3(1, B), dim3(kThreads), 0, st, rr_parts, run.nb,
                      np, w.sc, w.ctl);
   hipError_t e = hipGetLastError();
@@ -243,7 +275,7 @@ hipError_t pcg_begin(PcgRun& run, PcgWork& w, const AngleGeom* geom, const Angle
   ba.R = R;
   ba.B = B;
   ba.ids = &run.win;
-  ba.v64 = w.pd;
+  ba.v64 = w.r;
   ba.v_stride = w.pmax;
   ba.out = w.u;
   ba.xT = w.uT;
@@ -266,10 +298,11 @@ hipError_t pcg_begin(PcgRun& run, PcgWork& w, const AngleGeom* geom, const Angle
   fa.out64 = w.q;
   fa.out_stride = w.pmax;
   fa.partial = partial;
-  fa.pd = w.pd;
+  fa.pd = w.r;
   fa.pd_stride = w.pmax;
   fa.lam = lam;
-  fa.dots = w.parts;  // pq partials, written by the forward reduction
+  fa.dots = w.parts;  // <r, q> partials
+  fa.dots2 = rr_parts;  // <r, r> partials
   fa.dots_stride = np;
   fa.stop = w.ctl;
   fa.stop_stride = kCtlCount;
@@ -282,7 +315,7 @@ namespace {
 hipError_t enqueue_iterations(PcgRun& run, int todo, bool timed) {
   PcgWork& w = *run.w;
   const int B = run.B, np = w.nparts;
-  double* pq_parts = w.parts;
+  double* dq_parts = w.parts;
   double* rr_parts = w.parts + (size_t)B * np;
   Profiler* prof = run.prof;
   hipStream_t st = run.st;
@@ -294,16 +327,14 @@ hipError_t enqueue_iterations(PcgRun& run, int todo, bool timed) {
     if (timed && (e = prof->begin(K_BACK, st)) != hipSuccess) return e;
     if ((e = launch_back(run.ba, st)) != hipSuccess) return e;
     if (timed && (e = prof->end(st)) != hipSuccess) return e;
-    // q = M u + lambda pd and partial <pd, q>, fused into the forward's
-    // reduction (timed inside: band kernel and reduction separately)
+    // q = M u + lambda r and partials of <r, q>, <r, r>, fused into the
+    // forward's reduction (timed inside: band kernel and reduction separately)
     run.fa.prof = timed ? prof : nullptr;
     if ((e = launch_forward(run.fa, st)) != hipSuccess) return e;
     if (timed && (e = prof->begin(K_VEC, st)) != hipSuccess) return e;
-    hipLaunchKernelGGL(update_kernel, dim3(run.nb, B), dim3(kThreads), 0, st, run.p, w.pmax,
-                       run.nb, np, sc_cur, pq_parts, w.pd, w.q, run.z, run.z_stride, w.r,
-                       rr_parts, w.ctl);
-    hipLaunchKernelGGL(direction_kernel, dim3(run.nb, B), dim3(kThreads), 0, st, run.p, w.pmax,
-                       run.nb, np, sc_cur, sc_nxt, rr_parts, run.tol2, w.r, w.pd, w.ctl);
+    hipLaunchKernelGGL(cg_vector_kernel, dim3(run.nb, B), dim3(kThreads), 0, st, run.p, w.pmax,
+                       run.nb, np, sc_cur, sc_nxt, w.sc, dq_parts, rr_parts, run.tol2, w.q, w.r,
+                       w.pd, w.s, run.z, run.z_stride, w.ctl);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (timed && (e = prof->end(st)) != hipSuccess) return e;
   }
@@ -399,10 +430,9 @@ hipError_t pcg_finish(PcgRun& run, int* iters, double* relres) {
   double rel_max = 0.0;
   for (int b = 0; b < B; ++b) {
     const int it = ctl[b * kCtlCount + kCtlIters];
-    const double* last = w.h_sc + ((size_t)(it & 1) * B + b) * S_COUNT;
-    const double bb = w.h_sc[(size_t)b * S_COUNT + S_BB];
+    const double* s0 = w.h_sc + (size_t)b * S_COUNT;   // set 0: <e, e> and the latest gamma
     it_max = std::max(it_max, it);
-    if (bb > 0.0) rel_max = std::max(rel_max, std::sqrt(last[S_RR] / bb));
+    if (s0[S_BB] > 0.0) rel_max = std::max(rel_max, std::sqrt(s0[S_LAST] / s0[S_BB]));
   }
   *iters = it_max;
   *relres = rel_max;

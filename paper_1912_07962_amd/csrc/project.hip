@@ -354,20 +354,22 @@ __global__ __launch_bounds__(kFT, 2) void fwd_band_kernel(const AngleGeom* __res
 }
 
 // out[s][t] = (h/d) sum_groups partial - sub for every slice (blockIdx.y);
-// optional CG tail q = out + lam*pd with per-workgroup partial dots <pd, q>.
+// optional CG tail q = out + lam*pd with per-workgroup partial dots <pd, q>
+// (and <pd, pd> into dots2 when it is non-NULL).
 template <typename SUB>
 __global__ __launch_bounds__(256) void fwd_reduce_kernel(
     const AngleGeom* __restrict__ geom, int R, AngleList ids, int n_groups,
     const float* __restrict__ partial, const SUB* __restrict__ sub, size_t sub_stride,
     float* __restrict__ out32, double* __restrict__ out64, size_t out_stride,
     const double* __restrict__ pd, size_t pd_stride, double lam, double* __restrict__ dots,
-    size_t dots_stride, const int* __restrict__ stop, int stop_stride) {
+    double* __restrict__ dots2, size_t dots_stride, const int* __restrict__ stop,
+    int stop_stride) {
   const int sl = blockIdx.y;
   if (stop && stop[(size_t)sl * stop_stride + kCtlDone]) return;
-  __shared__ double sh[4];
+  __shared__ double sh[8];
   const int o = blockIdx.x * 256 + threadIdx.x;
   const int n = ids.n * R;
-  double d = 0.0;
+  double d = 0.0, d2 = 0.0;
   if (o < n) {
     const int s = o / R, t = o % R;
     const int ang = ids.id[s];
@@ -389,15 +391,25 @@ __global__ __launch_bounds__(256) void fwd_reduce_kernel(
       const double pv = pd[(size_t)sl * pd_stride + o];
       v = fma(lam, pv, v);
       d = pv * v;
+      d2 = pv * pv;
     }
     if (out32) out32[(size_t)sl * out_stride + o] = (float)v;
     if (out64) out64[(size_t)sl * out_stride + o] = v;
   }
   if (dots) {
-    for (int w = 32; w > 0; w >>= 1) d += __shfl_down(d, w, 64);
-    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = d;
+    for (int w = 32; w > 0; w >>= 1) {
+      d += __shfl_down(d, w, 64);
+      d2 += __shfl_down(d2, w, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+      sh[threadIdx.x >> 6] = d;
+      sh[4 + (threadIdx.x >> 6)] = d2;
+    }
     __syncthreads();
-    if (threadIdx.x == 0) dots[(size_t)sl * dots_stride + blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
+    if (threadIdx.x == 0) {
+      dots[(size_t)sl * dots_stride + blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
+      if (dots2) dots2[(size_t)sl * dots_stride + blockIdx.x] = sh[4] + sh[5] + sh[6] + sh[7];
+    }
   }
 }
 
@@ -889,12 +901,12 @@ hipError_t launch_forward(const FwdArgs& a, hipStream_t st) {
   if (a.sub_bf16)
     hipLaunchKernelGGL(fwd_reduce_kernel<uint16_t>, rg, dim3(256), 0, st, a.geom, a.R, *a.ids,
                        pl.n_groups, a.partial, (const uint16_t*)a.sub, a.sub_stride, a.out32,
-                       a.out64, a.out_stride, a.pd, a.pd_stride, a.lam, a.dots, a.dots_stride,
+                       a.out64, a.out_stride, a.pd, a.pd_stride, a.lam, a.dots, a.dots2, a.dots_stride,
                        a.stop, a.stop_stride);
   else
     hipLaunchKernelGGL(fwd_reduce_kernel<float>, rg, dim3(256), 0, st, a.geom, a.R, *a.ids,
                        pl.n_groups, a.partial, (const float*)a.sub, a.sub_stride, a.out32, a.out64,
-                       a.out_stride, a.pd, a.pd_stride, a.lam, a.dots, a.dots_stride, a.stop,
+                       a.out_stride, a.pd, a.pd_stride, a.lam, a.dots, a.dots2, a.dots_stride, a.stop,
                        a.stop_stride);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (timed && (e = a.prof->end(st)) != hipSuccess) return e;

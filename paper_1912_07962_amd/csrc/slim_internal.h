@@ -100,7 +100,8 @@ int slice_tile(int B);
 // when img_bf16); sub likewise with sub_bf16.  Strides are in elements.
 // partial: workspace of forward_partial_floats(...) floats.  CG tail when pd
 // is non-NULL: out += lam * pd and per-workgroup partial sums of pd . out into
-// dots[slice * dots_stride + forward_dot_parts(ids.n * R)].  Slices whose
+// dots[slice * dots_stride + forward_dot_parts(ids.n * R)] (and of pd . pd
+// into dots2 likewise, when dots2 is non-NULL).  Slices whose
 // stop[slice * stop_stride + kCtlDone] is set are skipped.
 // Launch shape of the projectors; zero fields take the built-in rules (the
 // autotuner measures and fills them).
@@ -134,6 +135,7 @@ struct FwdArgs {
   size_t pd_stride = 0;
   double lam = 0.0;
   double* dots = nullptr;
+  double* dots2 = nullptr;
   size_t dots_stride = 0;
   const int* stop = nullptr;
   int stop_stride = 0;
