@@ -65,13 +65,13 @@ PEAK_FP64_TFLOPS = 78.6
 # the line reports traffic as null.
 PMC_TRAFFIC = {
     "source": "paper_1912_07962_amd/csrc/project.hip",
-    "sha256": "879aa55c8e00ef9936e719a0bd5ff291fbb00ba06bd17aae6881f993baebbea0",
+    "sha256": "e14824d5a4c0119a6304bd27b0d1935c1f987bb01a065893294291cc72ef6c9b",
     "fetch_scale": 2.0,
     "write_scale": 1.0,
     # instance -> (FETCH_SIZE, WRITE_SIZE) KiB per dispatch
-    "kib": {"cg_forward/2": (5250.6, 1683.6), "cg_forward/3": (5107.9, 2450.6),
-            "cg_forward/4": (3544.8, 3367.1), "cg_forward/6": (4835.6, 4233.8),
-            "cg_forward/8": (4341.2, 5892.5), "cg_back/1": (2620.1, 6890.2)},
+    "kib": {"cg_forward/2": (5281.6, 1693.5), "cg_forward/3": (5263.2, 2525.3),
+            "cg_forward/4": (3544.8, 3367.1), "cg_forward/6": (4807.2, 4208.9),
+            "cg_forward/8": (4341.2, 5892.5), "cg_back/1": (2633.9, 6931.2)},
 }
 
 

@@ -830,7 +830,6 @@ size_t forward_partial_floats(const AngleGeom* h_geom, int N, int R, const Angle
   return (size_t)B * pl.n_groups * ids.n * R;
 }
 
-int forward_dot_parts(int n_out) { return (n_out + 255) / 256; }
 
 template <int IT, int BT, typename IMG>
 static void launch_it(dim3 grid, size_t lds, hipStream_t st, const AngleGeom* geom, int N, int R,

@@ -100,8 +100,8 @@ int slice_tile(int B);
 // when img_bf16); sub likewise with sub_bf16.  Strides are in elements.
 // partial: workspace of forward_partial_floats(...) floats.  CG tail when pd
 // is non-NULL: out += lam * pd and per-workgroup partial sums of pd . out into
-// dots[slice * dots_stride + forward_dot_parts(ids.n * R)] (and of pd . pd
-// into dots2 likewise, when dots2 is non-NULL).  Slices whose
+// dots[slice * dots_stride + w], one per 256 outputs w (and of pd . pd into
+// dots2 likewise, when dots2 is non-NULL).  Slices whose
 // stop[slice * stop_stride + kCtlDone] is set are skipped.
 // Launch shape of the projectors; zero fields take the built-in rules (the
 // autotuner measures and fills them).
@@ -145,7 +145,6 @@ hipError_t launch_forward(const FwdArgs& a, hipStream_t st);
 int forward_max_items(int bt);
 size_t forward_partial_floats(const AngleGeom* h_geom, int N, int R, const AngleList& ids, int B,
                               const ProjTune& tune);
-int forward_dot_parts(int n_out);
 
 // Back-projection of B slices: s[slice][pix] = sum_a sum_t A[(ids[a],t),pix] v[slice][a][t]
 // with v float (v32) or double (v64).  mode 0: out = s (and out^T into xT).
