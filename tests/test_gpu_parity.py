@@ -128,6 +128,36 @@ def test_steps_match_oracle(g, r, lam, mode):
 
 
 @gpu
+@pytest.mark.parametrize("N,R,g,r,mode", [
+    (32, 15, 1, 2, "chol"),    # p = 15, 30, 45: one partial Cholesky block
+    (32, 16, 1, 3, "chol"),    # p reaches 64 exactly: one full block
+    (40, 32, 2, 1, "chol"),    # p = 64, then 128: two full blocks
+    (40, 13, 2, 4, "chol"),    # p = 26 ... 130: two full blocks and a 2-row tail
+    (40, 13, 2, 4, "pcg"),
+])
+def test_custom_ray_count_windows_match_oracle(N, R, g, r, mode):
+    """Window sizes p = (r+1) g R at and around the 64-row Cholesky blocks."""
+    na, lam = 24, 1e-2
+    theta, s_det, _ = synth.scan_geometry(N, na, R)
+    ells = synth.random_ellipses(6, 11)
+    x_true = synth.rasterize(ells, N)
+    b = synth.add_noise(synth.analytic_sinogram(ells, theta, s_det), 0.01, 12)
+    M = na // g
+    P = system.Projector(N, na, R=R)
+    T = slimls.Tomo(P, b, g, r, lam, x_true=x_true)
+    s = Slim(N, na, n_rays=R, r=r, lam=lam, angles_per_block=g, gram_mode=mode, pcg_tol=1e-11,
+             pcg_max_iter=3000)
+    x = torch.zeros((N, N), dtype=torch.float32, device="cuda")
+    s.set_data(_dev(b), x, _dev(x_true))
+    for k, beta in enumerate(sampler.schedule(M, 2, 4001), 1):
+        info = s.step(list(range(beta * g, beta * g + g)))
+        rec = T.step(beta)
+        if k <= r + 2 or k % M == 0:
+            assert _rel(x.cpu().numpy(), T.x) < 1e-5, (k, _rel(x.cpu().numpy(), T.x))
+            assert abs(info["step_norm"] - rec.step_norm) <= 1e-5 * rec.step_norm
+
+
+@gpu
 def test_solve_matches_oracle_and_stop_rule():
     cfg = synth.get_config("c1")
     N, na, r, lam = cfg["N"], cfg["n_angles"], cfg["r"], cfg["lam"]
