@@ -57,21 +57,22 @@ PEAK_FP64_TFLOPS = 78.6
 
 # HBM bytes per launch of the CG projector kernels on this workload, from
 # rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE (KiB per dispatch, mean over the
-# 88-angle window launches; profiles/ has the summary and commands), each
-# scaled by what the counter reads for a copy of 256 MiB (FETCH reads half:
-# x2.0; WRITE x1.0), per kernel instance: the forward for every rays-per-lane
-# count the autotuner can pick, the back-projector's one-slice tile.  Valid
-# only for the projector source they were taken on (SHA-256 below); otherwise
-# the line reports traffic as null.
+# 88-angle window launches that did work: launches enqueued past the CG stop
+# return at entry and are left out; profiles/ has the summary and commands),
+# each scaled by what the counter reads for a copy of 256 MiB (FETCH reads
+# half: x2.0; WRITE x1.0), per kernel instance: the forward for every
+# rays-per-lane count the autotuner can pick, the back-projector's one-slice
+# tile.  Valid only for the projector source they were taken on (SHA-256
+# below); otherwise the line reports traffic as null.
 PMC_TRAFFIC = {
     "source": "paper_1912_07962_amd/csrc/project.hip",
-    "sha256": "e14824d5a4c0119a6304bd27b0d1935c1f987bb01a065893294291cc72ef6c9b",
+    "sha256": "b6c6c51d37cb2e3f1ef2c0bcf0347e0d3f3cb5327fbc55ef37f8cf0e86d0a2d0",
     "fetch_scale": 2.0,
     "write_scale": 1.0,
     # instance -> (FETCH_SIZE, WRITE_SIZE) KiB per dispatch
-    "kib": {"cg_forward/2": (5281.6, 1693.5), "cg_forward/3": (5263.2, 2525.3),
-            "cg_forward/4": (3544.8, 3367.1), "cg_forward/6": (4807.2, 4208.9),
-            "cg_forward/8": (4341.2, 5892.5), "cg_back/1": (2633.9, 6931.2)},
+    "kib": {"cg_forward/2": (6212.2, 1992.4), "cg_forward/3": (6227.6, 2988.6),
+            "cg_forward/4": (4194.5, 3984.8), "cg_forward/6": (5689.0, 4980.9),
+            "cg_forward/8": (5142.5, 6973.3), "cg_back/1": (3100.0, 8192.8)},
 }
 
 
@@ -303,10 +304,10 @@ def volume_bench(dev, B, steps, autotune=True):
     wall = time.perf_counter() - t0
     stats = s.kernel_stats()
     s.profile(False)
-    st = stats["cg_forward"]
-    avg_f = st["total_ms"] / max(st["launches"], 1) * 1e-3
-    st = stats["cg_back"]
-    avg_b = st["total_ms"] / max(st["launches"], 1) * 1e-3
+    # per CG iteration that did work: launches enqueued past the stop return
+    # at entry, and their time is charged to the iterations that did work
+    avg_f = stats["cg_forward"]["total_ms"] / max(sum(iters), 1) * 1e-3
+    avg_b = stats["cg_back"]["total_ms"] / max(sum(iters), 1) * 1e-3
     fl = flops / max(sum(iters), 1)
     s.close()
     print(f"bench: volume step {wall / steps * 1e3:.1f} ms", file=sys.stderr, flush=True)
@@ -631,7 +632,9 @@ def main():
     kernel_name = (f"fwd_band_kernel<{inst.split('/')[1]}, 1, float>" if dom == "cg_forward"
                    else "back_kernel<double, 1>")
     st = stats[dom]
-    avg_ms = st["total_ms"] / max(st["launches"], 1)
+    # per CG iteration that did work (launches enqueued past the stop return
+    # at entry; their time is charged to the iterations that did work)
+    avg_ms = st["total_ms"] / max(sum(prof_iters), 1)
     flops_per_launch = flops_cg / max(sum(prof_iters), 1)
     achieved = flops_per_launch / (avg_ms * 1e-3) / 1e12
 

@@ -22,10 +22,11 @@ struct PcgWork {
   int* ctl = nullptr;       // per-slice stop flag and iteration count [B][kCtlCount]
   float* u = nullptr;       // M^T r              [B][N][N]
   float* uT = nullptr;      // its transpose      [B][N][N]
-  int* h_ctl = nullptr;     // pinned copies of ctl, one per chunk in flight
+  int* h_ctl = nullptr;     // pinned copies of ctl: one per chunk in flight, then the final one
   double* h_sc = nullptr;   // pinned copy of sc
   hipEvent_t ev[2] = {nullptr, nullptr};
   hipGraphExec_t graph_exec = nullptr;  // one chunk of iterations (graph mode)
+  int last_iters = 0;       // iterations of the last solve reported (sizes the chunks)
 };
 
 // State of one CG solve, advanced by pcg_enqueue / pcg_poll so that several
@@ -46,6 +47,7 @@ struct PcgRun {
   int enq = 0;      // iterations enqueued
   int chunks = 0;   // chunks enqueued
   int seen = 0;     // chunks whose flag copy has been read
+  bool graph_ready = false;  // graph_exec holds this run's chunk
   bool done = false;
 };
 
@@ -66,7 +68,9 @@ hipError_t pcg_solve(PcgWork& w, const AngleGeom* geom, const AngleGeom* h_geom,
 // The same solve in steps: begin enqueues the initialisation; enqueue adds
 // the next chunk of iterations when fewer than two are in flight; poll reads
 // the oldest chunk's stop flags once two are in flight (or the cap is
-// reached) and sets run.done; finish waits and reports.
+// reached) and sets run.done; finish_async enqueues the copies of the final
+// state to pinned memory, which report reads once the caller has
+// synchronised the stream.
 hipError_t pcg_begin(PcgRun& run, PcgWork& w, const AngleGeom* geom, const AngleGeom* h_geom,
                      float* partial, int N, int R, int B, const AngleList& win,
                      const ProjTune& tune, double lam, const double* res, size_t res_stride,
@@ -74,6 +78,7 @@ hipError_t pcg_begin(PcgRun& run, PcgWork& w, const AngleGeom* geom, const Angle
                      Profiler* prof, hipStream_t st);
 hipError_t pcg_enqueue(PcgRun& run, bool use_graph);
 hipError_t pcg_poll(PcgRun& run);
-hipError_t pcg_finish(PcgRun& run, int* iters, double* relres);
+hipError_t pcg_finish_async(PcgRun& run);
+void pcg_report(PcgRun& run, int* iters, double* relres);
 
 }  // namespace slim

@@ -25,7 +25,11 @@
 // slice (the projectors skip a slice tile once all its slices stopped).  The
 // host enqueues chunks of iterations ahead and reads the flag from pinned
 // memory after a chunk completes, keeping the next chunk in flight, so the
-// GPU does not idle on host round trips.  All dot products are two-stage
+// GPU does not idle on host round trips.  Chunks are 8 iterations (one graph
+// launch) until a few iterations before the count of the previous solve on
+// the same workspace, then 2, so that few iterations are enqueued past the
+// stop; the first chunk of a solve is launched directly and the graph for
+// the solve's window is captured while it runs.  All dot products are two-stage
 // fixed-order reductions, so runs are bitwise reproducible.
 #include "pcg.h"
 
@@ -38,7 +42,9 @@ namespace slim {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kChunk = 8;   // iterations enqueued per host check
+constexpr int kChunk = 8;     // iterations per graph launch (host check)
+constexpr int kTail = 2;      // iterations per host check near the predicted end
+constexpr int kTailLead = 3;  // short chunks start this many iterations before it
 
 // per-slice scalars: gamma and alpha of the last update (gamma 0 before the
 // first), beta, <e, e>, and (set 0 only) the latest gamma
@@ -209,7 +215,7 @@ hipError_t pcg_alloc(PcgWork& w, int N, int B, int64_t pmax) {
   if ((e = hipMalloc((void**)&w.ctl, (size_t)B * kCtlCount * sizeof(int))) != hipSuccess) return e;
   if ((e = hipMalloc((void**)&w.u, (size_t)B * N * N * sizeof(float))) != hipSuccess) return e;
   if ((e = hipMalloc((void**)&w.uT, (size_t)B * N * N * sizeof(float))) != hipSuccess) return e;
-  if ((e = hipHostMalloc((void**)&w.h_ctl, (size_t)2 * B * kCtlCount * sizeof(int),
+  if ((e = hipHostMalloc((void**)&w.h_ctl, (size_t)3 * B * kCtlCount * sizeof(int),
                          hipHostMallocDefault)) != hipSuccess)
     return e;
   if ((e = hipHostMalloc((void**)&w.h_sc, (size_t)2 * B * S_COUNT * sizeof(double),
@@ -257,6 +263,7 @@ hipError_t pcg_begin(PcgRun& run, PcgWork& w, const AngleGeom* geom, const Angle
   run.st = st;
   run.enq = run.chunks = run.seen = 0;
   run.done = false;
+  run.graph_ready = false;
   const int np = w.nparts;
   double* rr_parts = w.parts + (size_t)B * np;  // written by init / the forward reduction
   const size_t img = (size_t)N * N;
@@ -378,11 +385,18 @@ hipError_t pcg_enqueue(PcgRun& run, bool use_graph) {
   if (run.done || run.enq >= run.max_iter || run.chunks - run.seen >= 2) return hipSuccess;
   PcgWork& w = *run.w;
   const int B = run.B;
-  const int todo = std::min(kChunk, run.max_iter - run.enq);
+  const int K = w.last_iters;
+  const bool tail = K > 0 && run.enq + kChunk > K - kTailLead && run.enq < K + kChunk;
+  const int todo = std::min(tail ? kTail : kChunk, run.max_iter - run.enq);
   hipError_t e;
   const bool timed = run.prof && run.prof->on;
-  if (use_graph && !timed && todo == kChunk) {
-    if (run.enq == 0 && (e = chunk_graph(run)) != hipSuccess) return e;
+  // graph chunks start at even iterations (the scalar sets alternate with
+  // the parity); every chunk before is of even length
+  if (use_graph && !timed && todo == kChunk && run.enq > 0 && (run.enq & 1) == 0) {
+    if (!run.graph_ready) {
+      if ((e = chunk_graph(run)) != hipSuccess) return e;
+      run.graph_ready = true;
+    }
     if ((e = hipGraphLaunch(w.graph_exec, run.st)) != hipSuccess) return e;
   } else {
     if ((e = enqueue_iterations(run, todo, timed)) != hipSuccess) return e;
@@ -413,19 +427,22 @@ hipError_t pcg_poll(PcgRun& run) {
   return hipSuccess;
 }
 
-hipError_t pcg_finish(PcgRun& run, int* iters, double* relres) {
+hipError_t pcg_finish_async(PcgRun& run) {
   PcgWork& w = *run.w;
   const int B = run.B;
   hipError_t e;
-  if ((e = hipStreamSynchronize(run.st)) != hipSuccess) return e;
-  if (run.prof && run.prof->on && (e = run.prof->harvest()) != hipSuccess) return e;
-  std::vector<int> ctl((size_t)B * kCtlCount);
-  if ((e = hipMemcpy(ctl.data(), w.ctl, ctl.size() * sizeof(int), hipMemcpyDeviceToHost)) !=
+  if ((e = hipMemcpyAsync(w.h_ctl + (size_t)2 * B * kCtlCount, w.ctl,
+                          (size_t)B * kCtlCount * sizeof(int), hipMemcpyDeviceToHost, run.st)) !=
       hipSuccess)
     return e;
-  if ((e = hipMemcpy(w.h_sc, w.sc, (size_t)2 * B * S_COUNT * sizeof(double),
-                     hipMemcpyDeviceToHost)) != hipSuccess)
-    return e;
+  return hipMemcpyAsync(w.h_sc, w.sc, (size_t)2 * B * S_COUNT * sizeof(double),
+                        hipMemcpyDeviceToHost, run.st);
+}
+
+void pcg_report(PcgRun& run, int* iters, double* relres) {
+  PcgWork& w = *run.w;
+  const int B = run.B;
+  const int* ctl = w.h_ctl + (size_t)2 * B * kCtlCount;
   int it_max = 0;
   double rel_max = 0.0;
   for (int b = 0; b < B; ++b) {
@@ -434,9 +451,9 @@ hipError_t pcg_finish(PcgRun& run, int* iters, double* relres) {
     it_max = std::max(it_max, it);
     if (s0[S_BB] > 0.0) rel_max = std::max(rel_max, std::sqrt(s0[S_LAST] / s0[S_BB]));
   }
+  w.last_iters = it_max;
   *iters = it_max;
   *relres = rel_max;
-  return hipSuccess;
 }
 
 hipError_t pcg_solve(PcgWork& w, const AngleGeom* geom, const AngleGeom* h_geom, float* partial,
@@ -452,7 +469,11 @@ hipError_t pcg_solve(PcgWork& w, const AngleGeom* geom, const AngleGeom* h_geom,
     if ((e = pcg_enqueue(run, use_graph)) != hipSuccess) return e;
     if ((e = pcg_poll(run)) != hipSuccess) return e;
   }
-  return pcg_finish(run, iters, relres);
+  if ((e = pcg_finish_async(run)) != hipSuccess) return e;
+  if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+  if (prof && prof->on && (e = prof->harvest()) != hipSuccess) return e;
+  pcg_report(run, iters, relres);
+  return hipSuccess;
 }
 
 }  // namespace slim

@@ -305,32 +305,57 @@ __global__ __launch_bounds__(kFT, 2) void fwd_band_kernel(const AngleGeom* __res
       float aa[BT], da[BT], ab[BT], db[BT];
 #pragma unroll
       for (int b = 0; b < BT; ++b) aa[b] = da[b] = ab[b] = db[b] = 0.f;
-      for (int k = k0; k <= k1; ++k) {
-        // an index below 0 wraps above W - 2: both ends are zero pads
-        const uint32_t ia = min((uint32_t)(Pa >> 32), (uint32_t)(W - 2));
-        const LT va0 = row[ia], va1 = row[ia + 1];
-        LT vb0 = va0, vb1 = va1;
+      // an index below 0 wraps above W - 2: both ends are zero pads
+      auto fetch = [&](int64_t pa, int64_t pb, const LT* rw, LT& x0, LT& x1, LT& y0, LT& y1) {
+        const uint32_t ia = min((uint32_t)(pa >> 32), (uint32_t)(W - 2));
+        x0 = rw[ia];
+        x1 = rw[ia + 1];
+        y0 = x0;
+        y1 = x1;
         if (two) {
-          const uint32_t ib = min((uint32_t)(Pb >> 32), (uint32_t)(W - 2));
-          vb0 = row[ib];
-          vb1 = row[ib + 1];
+          const uint32_t ib = min((uint32_t)(pb >> 32), (uint32_t)(W - 2));
+          y0 = rw[ib];
+          y1 = rw[ib + 1];
         }
-        const float la = (float)(uint32_t)Pa, lb = (float)(uint32_t)Pb;
+      };
+      auto add_row = [&](const LT& x0v, const LT& x1v, const LT& y0v, const LT& y1v, float la,
+                         float lb) {
 #pragma unroll
         for (int b = 0; b < BT; ++b) {
-          const float x0 = Lane<BT>::get(va0, b), x1 = Lane<BT>::get(va1, b);
+          const float x0 = Lane<BT>::get(x0v, b), x1 = Lane<BT>::get(x1v, b);
           aa[b] += x0;
           da[b] = fmaf(la, x1 - x0, da[b]);
           if (two) {
-            const float y0 = Lane<BT>::get(vb0, b), y1 = Lane<BT>::get(vb1, b);
+            const float y0 = Lane<BT>::get(y0v, b), y1 = Lane<BT>::get(y1v, b);
             ab[b] += y0;
             db[b] = fmaf(lb, y1 - y0, db[b]);
           }
         }
+      };
+      // pipelined by one row: the reads of row k + 1 are issued before the
+      // sums of row k, so they are in flight while those run
+      LT va0, va1, vb0, vb1;
+      fetch(Pa, Pb, row, va0, va1, vb0, vb1);
+      float la = (float)(uint32_t)Pa, lb = (float)(uint32_t)Pb;
+      for (int k = k0; k < k1; ++k) {
         Pa += S[q];
         if (two) Pb += S[qn];
+        // one position register per ray: keeps the compiler from carrying
+        // the low word separately (extra 64-bit adds per row)
+        asm volatile("" : "+v"(Pa), "+v"(Pb));
         row += W;
+        LT na0, na1, nb0, nb1;
+        fetch(Pa, Pb, row, na0, na1, nb0, nb1);
+        const float nla = (float)(uint32_t)Pa, nlb = (float)(uint32_t)Pb;
+        add_row(va0, va1, vb0, vb1, la, lb);
+        va0 = na0;
+        va1 = na1;
+        vb0 = nb0;
+        vb1 = nb1;
+        la = nla;
+        lb = nlb;
       }
+      add_row(va0, va1, vb0, vb1, la, lb);
 #pragma unroll
       for (int b = 0; b < BT; ++b) {
         acc[q][b] += (double)fmaf(da[b], 2.3283064365386963e-10f, aa[b]);

@@ -335,8 +335,8 @@ slim_status step_begin(slim_ctx* c, const int32_t* ids, StepState& ss) {
 slim_status step_end(slim_ctx* c, StepState& ss, slim_step_info* info) {
   int pcg_it = 0;
   double pcg_rel = 0.0;
-  if (ss.pcg) {
-    hipError_t e = pcg_finish(ss.run, &pcg_it, &pcg_rel);
+  if (ss.pcg) {  // the CG's final state travels with the step's other results
+    hipError_t e = pcg_finish_async(ss.run);
     if (e != hipSuccess) return fail(SLIM_EDEVICE, std::string("pcg: ") + hipGetErrorString(e));
   }
   // 3. update every slice
@@ -365,15 +365,20 @@ slim_status step_end(slim_ctx* c, StepState& ss, slim_step_info* info) {
   }
   if (c->prof.on) HIP_TRY(c->prof.end(c->st));
   c->k += 1;
+  if (info) {
+    HIP_TRY(hipMemcpyAsync(c->h_norms, c->d_norms, sizeof(double) * 3 * c->B,
+                           hipMemcpyDeviceToHost, c->st));
+    HIP_TRY(hipMemcpyAsync(c->h_info, c->d_info, sizeof(int), hipMemcpyDeviceToHost, c->st));
+  }
+  if (info || ss.pcg) {
+    HIP_TRY(hipStreamSynchronize(c->st));
+    if (c->prof.on) HIP_TRY(c->prof.harvest());
+  }
+  if (ss.pcg) pcg_report(ss.run, &pcg_it, &pcg_rel);
   c->last_pcg_iters = pcg_it;
   c->last_pcg_relres = pcg_rel;
   c->total_pcg_iters += pcg_it;
   if (!info) return SLIM_OK;
-  HIP_TRY(hipMemcpyAsync(c->h_norms, c->d_norms, sizeof(double) * 3 * c->B, hipMemcpyDeviceToHost,
-                         c->st));
-  HIP_TRY(hipMemcpyAsync(c->h_info, c->d_info, sizeof(int), hipMemcpyDeviceToHost, c->st));
-  HIP_TRY(hipStreamSynchronize(c->st));
-  if (c->prof.on) HIP_TRY(c->prof.harvest());
   c->norms_valid = true;
   int best = 0;
   for (int sl = 1; sl < c->B; ++sl)
