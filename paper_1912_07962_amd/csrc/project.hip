@@ -8,8 +8,10 @@
 // and applied to all BT slices with one 4/8/16-byte LDS read.
 //
 // Forward (ray-driven, LDS bands): the image is cut into bands of H rows
-// (row-stepping angles) or H rows of its transpose (column-stepping angles,
-// i.e. H image columns), H*(N+8)*BT floats <= 64 KB.  A workgroup owns a
+// (row-stepping angles) or H columns (column-stepping angles: H rows of the
+// transposed image when the caller has one, else H columns of the image
+// transposed on their way into LDS), H*(N+9)*BT floats <= 66 KB.  A
+// workgroup owns a
 // group of consecutive bands, a chunk of angles of one orientation and a
 // slice tile; it streams its bands through LDS (zero-padded by four pixels on
 // each side, so no bounds checks in the inner loop), prefetching the next
@@ -163,9 +165,16 @@ __global__ __launch_bounds__(kFT, 2) void fwd_band_kernel(const AngleGeom* __res
   bool colm;
   chunk_range(pl, R, chunk, eg, i0, i1, colm);
   const int nitems = i1 - i0;
+  // Column-stepping chunks walk the transposed image: from imgT when given
+  // (bands of its rows), else from img as bands of columns, transposed on
+  // their way into LDS (rows then Ws = W + 1 floats apart, which spreads the
+  // transposed writes over the LDS banks).
+  const bool cband = colm && imgT == nullptr;
+  const int Ws = cband ? W + 1 : W;
   const IMG* src[BT];
 #pragma unroll
-  for (int b = 0; b < BT; ++b) src[b] = (colm ? imgT : img) + (size_t)(b0 + min(b, nb - 1)) * img_stride;
+  for (int b = 0; b < BT; ++b)
+    src[b] = (colm && !cband ? imgT : img) + (size_t)(b0 + min(b, nb - 1)) * img_stride;
   const double half = 0.5 * (N - 1);
   const double off = 0.5 * (R - 1);
   const int kg = grp * pl.G * pl.H;
@@ -228,29 +237,36 @@ __global__ __launch_bounds__(kFT, 2) void fwd_band_kernel(const AngleGeom* __res
   // the zero pads are written once; band loads never touch them
   for (int e = threadIdx.x; e < pl.H * 2 * kPad * BT; e += kFT) {
     const int r = e / (2 * kPad * BT), c = (e / BT) % (2 * kPad), b = e % BT;
-    band[(r * W + (c < kPad ? c : N + c)) * BT + b] = 0.f;
+    band[(r * Ws + (c < kPad ? c : N + c)) * BT + b] = 0.f;
   }
   // Bands are software-pipelined: the next band's rows (BT slices, 16-byte
-  // loads) are fetched into registers while the current band is used.
-  const bool vec = (N & 3) == 0;
+  // loads) are fetched into registers while the current band is used.  A
+  // band of rows [k, k + h) is h N / 4 four-pixel chunks: chunk e is row
+  // k + e / (N/4), columns 4 (e mod N/4) + [0, 4); for a band of columns
+  // (k and h multiples of 4, see make_plan) chunk e is image row e / (h/4),
+  // columns k + 4 (e mod h/4) + [0, 4), so a wave reads whole row segments.
+  const bool vec = (N & 3) == 0 && (!cband || (pl.H & 3) == 0);
   const int n4 = N >> 2;
   constexpr int U = kPF / BT;  // 4-pixel chunks per lane per band
   float4 pf[kPF];
-  if (vec && kg < N) {
-    const int lim = min(pl.H, N - kg) * n4 - 1;
+  auto fetch_band = [&](int k, int h) {
+    const int lim = h * n4 - 1;
+    const int h4 = h >> 2;
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int e = min((int)threadIdx.x + u * kFT, lim);
+      const int at = cband ? (e / h4) * n4 + (k >> 2) + e % h4 : k * n4 + e;
 #pragma unroll
-      for (int b = 0; b < BT; ++b) pf[u * BT + b] = load4(src[b] + (size_t)kg * N, e);
+      for (int b = 0; b < BT; ++b) pf[u * BT + b] = load4(src[b], at);
     }
-  }
+  };
+  if (vec && kg < N) fetch_band(kg, min(pl.H, N - kg));
   for (int bb = 0; bb < pl.G; ++bb) {
     const int kb = kg + bb * pl.H;
     if (kb >= N) break;
     const int hb = min(pl.H, N - kb);
     __syncthreads();
-    if (vec) {
+    if (vec && !cband) {
       const int lim = hb * n4;
 #pragma unroll
       for (int u = 0; u < U; ++u) {
@@ -270,23 +286,37 @@ __global__ __launch_bounds__(kFT, 2) void fwd_band_kernel(const AngleGeom* __res
           }
         }
       }
-    } else {
+    } else if (vec) {
+      const int lim = hb * n4, h4 = hb >> 2;
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int e = (int)threadIdx.x + u * kFT;
+        const int i = e / h4, c4 = e - i * h4;
+        if (e < lim) {
+          // image row i, columns kb + 4 c4 + k: band rows 4 c4 + k, position i
+          float* dst = band + (size_t)(4 * c4 * Ws + kPad + i) * BT;
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+#pragma unroll
+            for (int b = 0; b < BT; ++b) dst[k * Ws * BT + b] = comp(pf[u * BT + b], k);
+          }
+        }
+      }
+    } else if (!cband) {
       for (int e = threadIdx.x; e < hb * N * BT; e += kFT) {
         const int r = e / (N * BT), c = (e / BT) % N, b = e % BT;
         band[(r * W + kPad + c) * BT + b] = tof(src[b][(size_t)(kb + r) * N + c]);
       }
+    } else {
+      // element e: image row e / (hb BT), column kb + (e / BT) mod hb
+      for (int e = threadIdx.x; e < hb * N * BT; e += kFT) {
+        const int i = e / (hb * BT), r = (e / BT) % hb, b = e % BT;
+        band[(r * Ws + kPad + i) * BT + b] = tof(src[b][(size_t)i * N + kb + r]);
+      }
     }
     __syncthreads();
     const int kbn = kb + pl.H;
-    if (vec && bb + 1 < pl.G && kbn < N) {
-      const int lim = min(pl.H, N - kbn) * n4 - 1;
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int e = min((int)threadIdx.x + u * kFT, lim);
-#pragma unroll
-        for (int b = 0; b < BT; ++b) pf[u * BT + b] = load4(src[b] + (size_t)kbn * N, e);
-      }
-    }
+    if (vec && bb + 1 < pl.G && kbn < N) fetch_band(kbn, min(pl.H, N - kbn));
     const LT* bandv = reinterpret_cast<const LT*>(band);
     // Items walk the band in pairs over the union of their two row ranges,
     // so each row issues two independent LDS reads.  A lane outside its own
@@ -299,7 +329,7 @@ __global__ __launch_bounds__(kFT, 2) void fwd_band_kernel(const AngleGeom* __res
       if (k0 > k1) continue;  // wave-uniform
       int64_t Pa = P0[q] + (int64_t)k0 * S[q];
       int64_t Pb = P0[qn] + (int64_t)k0 * S[qn];
-      const LT* row = bandv + (k0 - kb) * W;
+      const LT* row = bandv + (k0 - kb) * Ws;
       // sum over rows of a + phi (c - a), phi = lo(P) 2^-32, kept as the two
       // sums  sum a  and  sum lo(P) (c - a)  (the 2^-32 applied once per band)
       float aa[BT], da[BT], ab[BT], db[BT];
@@ -343,7 +373,7 @@ __global__ __launch_bounds__(kFT, 2) void fwd_band_kernel(const AngleGeom* __res
         // one position register per ray: keeps the compiler from carrying
         // the low word separately (extra 64-bit adds per row)
         asm volatile("" : "+v"(Pa), "+v"(Pb));
-        row += W;
+        row += Ws;
         LT na0, na1, nb0, nb1;
         fetch(Pa, Pb, row, na0, na1, nb0, nb1);
         const float nla = (float)(uint32_t)Pa, nlb = (float)(uint32_t)Pb;
@@ -830,7 +860,9 @@ static FwdPlan make_plan(const AngleGeom* h_geom, int N, int R, const AngleList&
       }
   pl.n_row = 0;
   for (int s = 0; s < ids.n; ++s) pl.n_row += h_geom[ids.id[s]].colmajor ? 0 : 1;
-  const int BT = tune.fwd_bt > 0 ? std::min(tune.fwd_bt, slice_tile(B)) : fwd_slice_tile(B, N);
+  int BT = tune.fwd_bt > 0 ? std::min(tune.fwd_bt, slice_tile(B)) : fwd_slice_tile(B, N);
+  // one band row of BT slices must fit the lanes' prefetch registers
+  while (BT > 1 && (size_t)N * BT > (size_t)4 * kPF * kFT) BT >>= 1;
   pl.bt = BT;
   const int cap = tune.fwd_items > 0 ? std::min(tune.fwd_items, max_items(BT)) : max_items(BT);
   const int most = std::max(pl.n_row, ids.n - pl.n_row) * R;   // rays of the larger group
@@ -839,6 +871,18 @@ static FwdPlan make_plan(const AngleGeom* h_geom, int N, int R, const AngleList&
   pl.n_chunks = (pl.n_row * R + pl.per - 1) / pl.per + ((ids.n - pl.n_row) * R + pl.per - 1) / pl.per;
   pl.n_tiles = (B + BT - 1) / BT;
   pl.H = std::max(1, std::min(N, 16384 / ((N + 2 * kPad) * BT)));
+  // bands of columns load four columns per 16-byte read: H a multiple of 4
+  // (rounded up while the band stays within 68 KB and the lanes' prefetch
+  // registers, else down), so every band starts at a multiple of 4 (the
+  // last one may be shorter)
+  if ((N & 3) == 0 && (pl.H & 3) != 0) {
+    const int up = (pl.H + 3) & ~3;
+    if (up <= N && (size_t)up * (N + 2 * kPad + 1) * BT <= 17408 &&
+        (size_t)up * N * BT <= (size_t)4 * kPF * kFT)
+      pl.H = up;
+    else if (pl.H >= 4)
+      pl.H &= ~3;
+  }
   const int nbands = (N + pl.H - 1) / pl.H;
   const int slots = (tune.fwd_slots > 0 ? tune.fwd_slots : 2) * num_cu();
   int want = std::max(1, std::min(slots / (pl.n_chunks * pl.n_tiles), nbands));
@@ -914,7 +958,7 @@ hipError_t launch_forward(const FwdArgs& a, hipStream_t st) {
   if (timed && (e = a.prof->begin(K_FORWARD, st)) != hipSuccess) return e;
   const int total = pl.n_groups * pl.n_chunks * pl.n_tiles;
   const int nwg = (total + 7) / 8 * 8;
-  const size_t lds = (size_t)pl.H * (a.N + 2 * kPad) * BT * sizeof(float);
+  const size_t lds = (size_t)pl.H * (a.N + 2 * kPad + 1) * BT * sizeof(float);
   if (a.img_bf16)
     launch_band_bt(BT, pl.items, dim3(nwg), lds, st, a.geom, a.N, a.R, pl, a.B,
                    (const uint16_t*)a.img, (const uint16_t*)a.imgT, a.img_stride, a.partial,

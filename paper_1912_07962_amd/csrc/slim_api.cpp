@@ -617,14 +617,10 @@ slim_status slim_project(slim_ctx* c, const int32_t* ids, int n_ids, const float
   const AngleList l = make_list(ids, n_ids);
   s = ensure_fpart(c, l);
   if (s != SLIM_OK) return s;
-  // column-stepping angles read the transposed image: make it only if needed
-  bool any_col = false;
-  for (int i = 0; i < n_ids; ++i) any_col = any_col || c->h_geom[ids[i]].colmajor != 0;
-  if (any_col)
-    HIP_TRY(launch_transpose(x, c->d_tmp, c->N, c->B, c->img_elems(), nullptr, nullptr, c->st));
+  // column-stepping angles stage bands of columns of x (no transposed copy)
   FwdArgs fa = base_fwd(c, &l);
   fa.img = x;
-  fa.imgT = any_col ? c->d_tmp : x;
+  fa.imgT = nullptr;
   fa.out32 = out;
   fa.out_stride = (size_t)n_ids * c->R;
   HIP_TRY(launch_forward(fa, c->st));

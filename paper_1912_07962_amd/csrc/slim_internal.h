@@ -96,8 +96,11 @@ int slice_tile(int B);
 // Forward projection of B slices sharing the geometry:
 //   out[slice][a][t] = sum_pix A[(ids[a],t),pix] img[slice][pix] - sub[slice][ids[a]][t]
 // accumulated in float64 per ray, written as float (out32) and/or double (out64).
-// img and its transpose imgT are both required (float32, or bf16 bit patterns
-// when img_bf16); sub likewise with sub_bf16.  Strides are in elements.
+// img (float32, or bf16 bit patterns when img_bf16) is required; imgT, its
+// transpose in the same format, is optional: column-stepping angles walk
+// bands of imgT's rows when it is given, else bands of img's columns
+// (transposed while staged).  sub likewise with sub_bf16.  Strides are in
+// elements.
 // partial: workspace of forward_partial_floats(...) floats.  CG tail when pd
 // is non-NULL: out += lam * pd and per-workgroup partial sums of pd . out into
 // dots[slice * dots_stride + w], one per 256 outputs w (and of pd . pd into
