@@ -66,13 +66,13 @@ PEAK_FP64_TFLOPS = 78.6
 # below); otherwise the line reports traffic as null.
 PMC_TRAFFIC = {
     "source": "paper_1912_07962_amd/csrc/project.hip",
-    "sha256": "b6c6c51d37cb2e3f1ef2c0bcf0347e0d3f3cb5327fbc55ef37f8cf0e86d0a2d0",
+    "sha256": "2a4f9ccb65561032d3c950d5b56107c8b76a5fa974fdb01657610c34f06e0d7b",
     "fetch_scale": 2.0,
     "write_scale": 1.0,
     # instance -> (FETCH_SIZE, WRITE_SIZE) KiB per dispatch
-    "kib": {"cg_forward/2": (6212.2, 1992.4), "cg_forward/3": (6227.6, 2988.6),
-            "cg_forward/4": (4194.5, 3984.8), "cg_forward/6": (5689.0, 4980.9),
-            "cg_forward/8": (5142.5, 6973.3), "cg_back/1": (3100.0, 8192.8)},
+    "kib": {"cg_forward/2": (6225.8, 1992.4), "cg_forward/3": (6236.6, 2988.6),
+            "cg_forward/4": (4208.0, 3984.8), "cg_forward/6": (5384.0, 5479.0),
+            "cg_forward/8": (4255.0, 7969.5), "cg_back/1": (3095.5, 8192.8)},
 }
 
 

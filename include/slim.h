@@ -234,8 +234,10 @@ typedef struct {
 } slim_tune_info;
 
 /* Autotuner: time every projector launch shape on forward and back
- * projections of a list of angles for all slices, and keep the fastest
- * (including the built-in rules) for lists of that size.  n_ids = 0 tunes the
+ * projections of a list of angles for all slices (three interleaved rounds
+ * of a warm-up and three timed launches each; a shape scores its fastest
+ * round), and keep the fastest (including the built-in rules) for lists of
+ * that size.  n_ids = 0 tunes the
  * CG workload -- a window of (r+1) blocks of angles_per_block angles spread
  * over [0, pi) -- and also makes its shape the default for every other size;
  * n_ids > 0 (at most min(256, n_angles)) tunes n_ids angles spread over

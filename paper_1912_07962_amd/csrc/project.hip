@@ -10,11 +10,11 @@
 // Forward (ray-driven, LDS bands): the image is cut into bands of H rows
 // (row-stepping angles) or H columns (column-stepping angles: H rows of the
 // transposed image when the caller has one, else H columns of the image
-// transposed on their way into LDS), H*(N+9)*BT floats <= 66 KB.  A
-// workgroup owns a
-// group of consecutive bands, a chunk of angles of one orientation and a
-// slice tile; it streams its bands through LDS (zero-padded by four pixels on
-// each side, so no bounds checks in the inner loop), prefetching the next
+// transposed on their way into LDS), H*(N+8)*BT floats <= 68 KB.  A
+// workgroup owns a group of consecutive bands, a chunk of angles of one
+// orientation and a slice tile; it streams its bands through LDS
+// (zero-padded by four pixels on each side, so no bounds checks in the inner
+// loop), prefetching the next
 // band into registers, and every lane walks up to four rays across them,
 // interpolating linearly between the two pixels nearest the crossing point
 // (Joseph).  The ray position is a 32.32 fixed-point number; each wavefront
@@ -167,10 +167,8 @@ __global__ __launch_bounds__(kFT, 2) void fwd_band_kernel(const AngleGeom* __res
   const int nitems = i1 - i0;
   // Column-stepping chunks walk the transposed image: from imgT when given
   // (bands of its rows), else from img as bands of columns, transposed on
-  // their way into LDS (rows then Ws = W + 1 floats apart, which spreads the
-  // transposed writes over the LDS banks).
+  // their way into LDS.
   const bool cband = colm && imgT == nullptr;
-  const int Ws = cband ? W + 1 : W;
   const IMG* src[BT];
 #pragma unroll
   for (int b = 0; b < BT; ++b)
@@ -237,27 +235,44 @@ __global__ __launch_bounds__(kFT, 2) void fwd_band_kernel(const AngleGeom* __res
   // the zero pads are written once; band loads never touch them
   for (int e = threadIdx.x; e < pl.H * 2 * kPad * BT; e += kFT) {
     const int r = e / (2 * kPad * BT), c = (e / BT) % (2 * kPad), b = e % BT;
-    band[(r * Ws + (c < kPad ? c : N + c)) * BT + b] = 0.f;
+    band[(r * W + (c < kPad ? c : N + c)) * BT + b] = 0.f;
   }
   // Bands are software-pipelined: the next band's rows (BT slices, 16-byte
   // loads) are fetched into registers while the current band is used.  A
   // band of rows [k, k + h) is h N / 4 four-pixel chunks: chunk e is row
-  // k + e / (N/4), columns 4 (e mod N/4) + [0, 4); for a band of columns
-  // (k and h multiples of 4, see make_plan) chunk e is image row e / (h/4),
-  // columns k + 4 (e mod h/4) + [0, 4), so a wave reads whole row segments.
+  // k + e / (N/4), columns 4 (e mod N/4) + [0, 4).  A band of columns (k and
+  // h multiples of 4, see make_plan) is read in blocks of RB image rows x 4
+  // columns: block e covers rows RB (e / (h/4)) + [0, RB), columns
+  // k + 4 (e mod h/4) + [0, 4), so a wave reads whole row segments, and is
+  // transposed in registers into runs of RB consecutive positions of each
+  // column for the LDS writes.
   const bool vec = (N & 3) == 0 && (!cband || (pl.H & 3) == 0);
   const int n4 = N >> 2;
   constexpr int U = kPF / BT;  // 4-pixel chunks per lane per band
+  constexpr int RB = U < 4 ? U : 4;
+  constexpr int NBL = U / RB;  // column blocks per lane per band
   float4 pf[kPF];
   auto fetch_band = [&](int k, int h) {
-    const int lim = h * n4 - 1;
-    const int h4 = h >> 2;
+    if (!cband) {
+      const int lim = h * n4 - 1;
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int e = min((int)threadIdx.x + u * kFT, lim);
-      const int at = cband ? (e / h4) * n4 + (k >> 2) + e % h4 : k * n4 + e;
+      for (int u = 0; u < U; ++u) {
+        const int e = min((int)threadIdx.x + u * kFT, lim);
 #pragma unroll
-      for (int b = 0; b < BT; ++b) pf[u * BT + b] = load4(src[b], at);
+        for (int b = 0; b < BT; ++b) pf[u * BT + b] = load4(src[b], k * n4 + e);
+      }
+    } else {
+      const int h4 = h >> 2, lim = (N / RB) * h4 - 1;
+#pragma unroll
+      for (int sb = 0; sb < NBL; ++sb) {
+        const int e = min((int)threadIdx.x + sb * kFT, lim);
+        const int i0 = RB * (e / h4), at = (k >> 2) + e % h4;
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+#pragma unroll
+          for (int b = 0; b < BT; ++b) pf[(sb * RB + r) * BT + b] = load4(src[b], (i0 + r) * n4 + at);
+        }
+      }
     }
   };
   if (vec && kg < N) fetch_band(kg, min(pl.H, N - kg));
@@ -287,18 +302,26 @@ __global__ __launch_bounds__(kFT, 2) void fwd_band_kernel(const AngleGeom* __res
         }
       }
     } else if (vec) {
-      const int lim = hb * n4, h4 = hb >> 2;
+      const int h4 = hb >> 2, nbk = (N / RB) * h4;
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int e = (int)threadIdx.x + u * kFT;
-        const int i = e / h4, c4 = e - i * h4;
-        if (e < lim) {
-          // image row i, columns kb + 4 c4 + k: band rows 4 c4 + k, position i
-          float* dst = band + (size_t)(4 * c4 * Ws + kPad + i) * BT;
+      for (int sb = 0; sb < NBL; ++sb) {
+        const int e = (int)threadIdx.x + sb * kFT;
+        if (e < nbk) {
+          const int i0 = RB * (e / h4), c4 = e % h4;
+          // image rows i0 + r, columns kb + 4 c4 + k: band row 4 c4 + k,
+          // positions i0 + r (RB BT consecutive floats, 16-byte aligned)
 #pragma unroll
           for (int k = 0; k < 4; ++k) {
+            float run[RB * BT];
 #pragma unroll
-            for (int b = 0; b < BT; ++b) dst[k * Ws * BT + b] = comp(pf[u * BT + b], k);
+            for (int r = 0; r < RB; ++r) {
+#pragma unroll
+              for (int b = 0; b < BT; ++b) run[r * BT + b] = comp(pf[(sb * RB + r) * BT + b], k);
+            }
+            float4* dst = reinterpret_cast<float4*>(band + (size_t)((4 * c4 + k) * W + kPad + i0) * BT);
+#pragma unroll
+            for (int q = 0; q < RB * BT / 4; ++q)
+              dst[q] = make_float4(run[4 * q], run[4 * q + 1], run[4 * q + 2], run[4 * q + 3]);
           }
         }
       }
@@ -311,7 +334,7 @@ __global__ __launch_bounds__(kFT, 2) void fwd_band_kernel(const AngleGeom* __res
       // element e: image row e / (hb BT), column kb + (e / BT) mod hb
       for (int e = threadIdx.x; e < hb * N * BT; e += kFT) {
         const int i = e / (hb * BT), r = (e / BT) % hb, b = e % BT;
-        band[(r * Ws + kPad + i) * BT + b] = tof(src[b][(size_t)i * N + kb + r]);
+        band[(r * W + kPad + i) * BT + b] = tof(src[b][(size_t)i * N + kb + r]);
       }
     }
     __syncthreads();
@@ -329,7 +352,7 @@ __global__ __launch_bounds__(kFT, 2) void fwd_band_kernel(const AngleGeom* __res
       if (k0 > k1) continue;  // wave-uniform
       int64_t Pa = P0[q] + (int64_t)k0 * S[q];
       int64_t Pb = P0[qn] + (int64_t)k0 * S[qn];
-      const LT* row = bandv + (k0 - kb) * Ws;
+      const LT* row = bandv + (k0 - kb) * W;
       // sum over rows of a + phi (c - a), phi = lo(P) 2^-32, kept as the two
       // sums  sum a  and  sum lo(P) (c - a)  (the 2^-32 applied once per band)
       float aa[BT], da[BT], ab[BT], db[BT];
@@ -373,7 +396,7 @@ __global__ __launch_bounds__(kFT, 2) void fwd_band_kernel(const AngleGeom* __res
         // one position register per ray: keeps the compiler from carrying
         // the low word separately (extra 64-bit adds per row)
         asm volatile("" : "+v"(Pa), "+v"(Pb));
-        row += Ws;
+        row += W;
         LT na0, na1, nb0, nb1;
         fetch(Pa, Pb, row, na0, na1, nb0, nb1);
         const float nla = (float)(uint32_t)Pa, nlb = (float)(uint32_t)Pb;
@@ -877,7 +900,7 @@ static FwdPlan make_plan(const AngleGeom* h_geom, int N, int R, const AngleList&
   // last one may be shorter)
   if ((N & 3) == 0 && (pl.H & 3) != 0) {
     const int up = (pl.H + 3) & ~3;
-    if (up <= N && (size_t)up * (N + 2 * kPad + 1) * BT <= 17408 &&
+    if (up <= N && (size_t)up * (N + 2 * kPad) * BT <= 17408 &&
         (size_t)up * N * BT <= (size_t)4 * kPF * kFT)
       pl.H = up;
     else if (pl.H >= 4)
@@ -958,7 +981,7 @@ hipError_t launch_forward(const FwdArgs& a, hipStream_t st) {
   if (timed && (e = a.prof->begin(K_FORWARD, st)) != hipSuccess) return e;
   const int total = pl.n_groups * pl.n_chunks * pl.n_tiles;
   const int nwg = (total + 7) / 8 * 8;
-  const size_t lds = (size_t)pl.H * (a.N + 2 * kPad + 1) * BT * sizeof(float);
+  const size_t lds = (size_t)pl.H * (a.N + 2 * kPad) * BT * sizeof(float);
   if (a.img_bf16)
     launch_band_bt(BT, pl.items, dim3(nwg), lds, st, a.geom, a.N, a.R, pl, a.B,
                    (const uint16_t*)a.img, (const uint16_t*)a.imgT, a.img_stride, a.partial,

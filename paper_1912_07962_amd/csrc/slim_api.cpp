@@ -968,54 +968,64 @@ slim_status slim_autotune(slim_ctx* c, int n_ids, int force, slim_tune_info* inf
     return hipSuccess;
   };
   slim_tune_info ti{};
+  // every candidate is timed in kRounds interleaved rounds and scored by its
+  // fastest round (clock and cache drift then affect all candidates alike)
+  constexpr int kRounds = 3;
+  std::vector<double> tf(fwd_c.size(), 1e300), tb(back_c.size(), 1e300);
+  for (int round = 0; round < kRounds && e == hipSuccess; ++round) {
+    for (size_t k = 0; k < fwd_c.size() && e == hipSuccess; ++k) {
+      FwdArgs fa;
+      fa.tune = fwd_c[k];
+      fa.geom = c->d_geom;
+      fa.h_geom = c->h_geom.data();
+      fa.N = c->N;
+      fa.R = c->R;
+      fa.B = c->B;
+      fa.ids = &win;
+      fa.img = img;
+      fa.imgT = imgT;
+      fa.img_stride = c->img_elems();
+      fa.out32 = rays;
+      fa.out_stride = (size_t)win.n * c->R;
+      fa.partial = fpart;
+      double us = 0.0;
+      e = timed([&]() { return launch_forward(fa, c->st); }, &us);
+      tf[k] = std::min(tf[k], us);
+    }
+    for (size_t k = 0; k < back_c.size() && e == hipSuccess; ++k) {
+      BackArgs ba;
+      ba.tune = back_c[k];
+      ba.geom = c->d_geom;
+      ba.N = c->N;
+      ba.R = c->R;
+      ba.B = c->B;
+      ba.ids = &win;
+      ba.v32 = rays;
+      ba.v_stride = (size_t)win.n * c->R;
+      ba.out = img;
+      ba.img_stride = c->img_elems();
+      ba.mode = 0;
+      double us = 0.0;
+      e = timed([&]() { return launch_back(ba, c->st); }, &us);
+      tb[k] = std::min(tb[k], us);
+    }
+  }
   double best_f = 1e300, best_b = 1e300;
   ProjTune best;
-  for (size_t k = 0; k < fwd_c.size() && e == hipSuccess; ++k) {
-    FwdArgs fa;
-    fa.tune = fwd_c[k];
-    fa.geom = c->d_geom;
-    fa.h_geom = c->h_geom.data();
-    fa.N = c->N;
-    fa.R = c->R;
-    fa.B = c->B;
-    fa.ids = &win;
-    fa.img = img;
-    fa.imgT = imgT;
-    fa.img_stride = c->img_elems();
-    fa.out32 = rays;
-    fa.out_stride = (size_t)win.n * c->R;
-    fa.partial = fpart;
-    double us = 0.0;
-    e = timed([&]() { return launch_forward(fa, c->st); }, &us);
-    if (k == 0) ti.fwd_default_us = us;
-    if (us < best_f) {
-      best_f = us;
+  for (size_t k = 0; k < fwd_c.size(); ++k)
+    if (tf[k] < best_f) {
+      best_f = tf[k];
       best.fwd_bt = fwd_c[k].fwd_bt;
       best.fwd_items = fwd_c[k].fwd_items;
       best.fwd_slots = fwd_c[k].fwd_slots;
     }
-  }
-  for (size_t k = 0; k < back_c.size() && e == hipSuccess; ++k) {
-    BackArgs ba;
-    ba.tune = back_c[k];
-    ba.geom = c->d_geom;
-    ba.N = c->N;
-    ba.R = c->R;
-    ba.B = c->B;
-    ba.ids = &win;
-    ba.v32 = rays;
-    ba.v_stride = (size_t)win.n * c->R;
-    ba.out = img;
-    ba.img_stride = c->img_elems();
-    ba.mode = 0;
-    double us = 0.0;
-    e = timed([&]() { return launch_back(ba, c->st); }, &us);
-    if (k == 0) ti.back_default_us = us;
-    if (us < best_b) {
-      best_b = us;
+  for (size_t k = 0; k < back_c.size(); ++k)
+    if (tb[k] < best_b) {
+      best_b = tb[k];
       best.back_bt = back_c[k].back_bt;
     }
-  }
+  ti.fwd_default_us = tf[0];
+  ti.back_default_us = tb[0];
   release();
   if (e != hipSuccess) return fail(SLIM_EDEVICE, std::string("autotune: ") + hipGetErrorString(e));
   ti.chosen = to_public(best);
