@@ -62,11 +62,12 @@ PEAK_FP64_TFLOPS = 78.6
 # each scaled by what the counter reads for a copy of 256 MiB (FETCH reads
 # half: x2.0; WRITE x1.0), per kernel instance: the forward for every
 # rays-per-lane count the autotuner can pick, the back-projector's one-slice
-# tile.  Valid only for the projector source they were taken on (SHA-256
-# below); otherwise the line reports traffic as null.
+# tile.  Valid only for the projector code they were taken on (SHA-256 of
+# the source without comments and layout, code_digest below); otherwise the
+# line reports traffic as null.
 PMC_TRAFFIC = {
     "source": "paper_1912_07962_amd/csrc/project.hip",
-    "sha256": "2a4f9ccb65561032d3c950d5b56107c8b76a5fa974fdb01657610c34f06e0d7b",
+    "sha256": "40795bc026e178919ee15862fdde262574b8df6407c4ed6ab6fb52dc31ebefeb",
     "fetch_scale": 2.0,
     "write_scale": 1.0,
     # instance -> (FETCH_SIZE, WRITE_SIZE) KiB per dispatch
@@ -85,16 +86,28 @@ def fwd_rays_per_lane(fwd_items, rays_in_group):
     return want if want <= 6 else 8
 
 
+def code_digest(path):
+    """SHA-256 of a C++/HIP source with its comments and layout removed, so
+    that edits to comments leave it unchanged (the code is what the counters
+    measured)."""
+    import hashlib
+    import re
+    with open(path, encoding="utf-8") as f:
+        text = f.read()
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", "", text)
+    lines = (" ".join(line.split()) for line in text.splitlines())
+    return hashlib.sha256("\n".join(l for l in lines if l).encode()).hexdigest()
+
+
 def pmc_traffic(kind):
     """Scaled HBM bytes per launch of a kernel instance ("cg_forward/IT",
     "cg_back/BT"), or None."""
-    import hashlib
     t = PMC_TRAFFIC
     if t["sha256"] is None or kind not in t["kib"]:
         return None
-    with open(os.path.join(ROOT, t["source"]), "rb") as f:
-        if hashlib.sha256(f.read()).hexdigest() != t["sha256"]:
-            return None
+    if code_digest(os.path.join(ROOT, t["source"])) != t["sha256"]:
+        return None
     fetch, write = t["kib"][kind]
     return (fetch * t["fetch_scale"] + write * t["write_scale"]) * 1024.0
 

@@ -11,24 +11,24 @@
 // (row-stepping angles) or H columns (column-stepping angles: H rows of the
 // transposed image when the caller has one, else H columns of the image
 // transposed on their way into LDS), H*(N+8)*BT floats <= 68 KB.  A
-// workgroup owns a group of consecutive bands, a chunk of angles of one
+// workgroup owns a group of consecutive bands, a chunk of rays of one
 // orientation and a slice tile; it streams its bands through LDS
 // (zero-padded by four pixels on each side, so no bounds checks in the inner
-// loop), prefetching the next
-// band into registers, and every lane walks up to four rays across them,
-// interpolating linearly between the two pixels nearest the crossing point
-// (Joseph).  The ray position is a 32.32 fixed-point number; each wavefront
-// walks the union of its rays' row ranges (wave-uniform loop).  Per-group
-// partial sums are combined by a second kernel in a fixed order
-// (deterministic, no atomics), which also applies h/d, subtracts the data
-// and can fuse the CG tail.  Workgroups are numbered so that each XCD works
-// on a contiguous range of (slice tile, band group) pairs, and the grid is
-// sized to one round of two resident workgroups per CU.
+// loop), prefetching the next band into registers, and every lane walks up
+// to eight rays across them in pairs, interpolating linearly between the two
+// pixels nearest the crossing point (Joseph).  The ray position is a 32.32
+// fixed-point number; each wavefront walks the union of its rays' row ranges
+// (wave-uniform loop).  Per-group partial sums are combined by a second
+// kernel in a fixed order (deterministic, no atomics), which also applies
+// h/d, subtracts the data and can fuse the CG tail.  Workgroups are numbered
+// so that each XCD works on a contiguous range of (slice tile, band group)
+// pairs, and the grid is sized to one round of resident workgroups (two per
+// CU by default).
 //
 // Back (pixel-driven gather): a workgroup owns a 16 x 64 pixel tile of a
 // slice tile and stages, for every angle of the list, the segment of ray
 // values its tile touches (scaled by h/d) in LDS; each lane gathers two rays
-// per angle for four consecutive pixels of a row.  No atomics; the optional
+// per angle for four pixels of a row, 16 columns apart.  No atomics; the optional
 // fused update writes x -= s, the transposed image, bf16 shadows and
 // per-workgroup float64 partial norms.  Both projectors evaluate the same
 // closed-form weights and agree to float32 rounding of the weights.
