@@ -67,7 +67,7 @@ PEAK_FP64_TFLOPS = 78.6
 # line reports traffic as null.
 PMC_TRAFFIC = {
     "source": "paper_1912_07962_amd/csrc/project.hip",
-    "sha256": "40795bc026e178919ee15862fdde262574b8df6407c4ed6ab6fb52dc31ebefeb",
+    "sha256": "55e53df273d72aad6d6a0d77acd8371309f2fbb2af933e2337c5052932a8f786",
     "fetch_scale": 2.0,
     "write_scale": 1.0,
     # instance -> (FETCH_SIZE, WRITE_SIZE) KiB per dispatch

@@ -498,12 +498,15 @@ constexpr int kSeg = 72;                // rays of one angle's segment
 constexpr int kSegFloats = 64 * kSeg;   // LDS floats of staged segments
 constexpr int kPre = kSegFloats / 512;  // staged values per lane per pass (two buffers)
 
-// Per-angle constants of one staged pass.  base moves the detector coordinate
-// of the angle's rays onto its LDS segment (segment index = ray - tmin + a *
-// kSeg); step is q cos(theta) in 32.32 fixed point (q image columns, the
-// distance between a lane's pixels); invd32 = 2^-32 / d.
+// Per-angle constants of one staged pass, positions in 32.32 fixed point.
+// T0 is the canonical detector coordinate of the tile's first pixel moved by
+// an integer onto the angle's LDS segment (segment index = ray - tmin +
+// a * kSeg), split into (segment index of ray floor(t), fraction); Ts and Tc
+// step one row and one column; step = kQ Tc is the distance between a
+// lane's pixels; invd32 = 2^-32 / d.
 struct BackAngle {
-  double s, c, base;
+  uint64_t T0;
+  int64_t Ts, Tc;
   int64_t step;
   float invd32, c1;
 };
@@ -565,8 +568,6 @@ __global__ __launch_bounds__(256) void back_kernel(
   // they are positive and float->int truncation is floor
   const int kTOff = 2 * N + 8;
   const double off = 0.5 * (R - 1) + kTOff;
-  const double ii = (double)i - half;
-  const double jj = (double)jb - half;
   // nominal tile corners (pixel centres) bound every pixel the lanes evaluate
   const double ci0 = (double)i0 - half, ci1 = (double)(i0 + kBH - 1) - half;
   const double cj0 = (double)j0 - half, cj1 = (double)(j0 + kBW - 1) - half;
@@ -580,10 +581,14 @@ __global__ __launch_bounds__(256) void back_kernel(
     tmin[c] = tm;
     hdA[c] = g.hd;
     BackAngle A;
-    A.s = g.s;
-    A.c = g.c;
-    A.base = (double)((a % kPass) * kSeg - tm);
-    A.step = __double2ll_rn(g.c * (kQ * 4294967296.0));
+    {
+      const double t = det_coord(g, ci0, cj0, off) + (double)((a % kPass) * kSeg - tm);
+      const int t0 = (int)t;                      // t >= 1: floor
+      A.T0 = ((uint64_t)(uint32_t)t0 << 32) | (uint32_t)((t - (double)t0) * 4294967296.0);
+    }
+    A.Ts = __double2ll_rn(g.s * 4294967296.0);
+    A.Tc = __double2ll_rn(g.c * 4294967296.0);
+    A.step = kQ * A.Tc;
     A.invd32 = g.invd * 2.3283064365386963e-10f;
     A.c1 = 1.f - g.invd;
     ang[c] = A;
@@ -599,13 +604,10 @@ __global__ __launch_bounds__(256) void back_kernel(
     const LT* segv = reinterpret_cast<const LT*>(segp);
     for (int a = 0; a < na; ++a) {
       const BackAngle A = ang[c0 + a];
-      // the lane's first pixel: the canonical coordinate, moved by an
-      // integer onto the staged segment (exact), split into the 32.32
-      // position T = (segment index of ray floor(t), fraction)
-      const double t = det_coord(A.s, A.c, ii, jj, off) + A.base;
-      const int t0 = (int)t;                      // t >= 1: floor
-      const double fr = t - (double)t0;           // exact
-      uint64_t T = ((uint64_t)(uint32_t)t0 << 32) | (uint32_t)(fr * 4294967296.0);
+      // the lane's first pixel (row ty, column tx of the tile); with the
+      // steps to its other pixels every position is within 40 2^-32
+      // (< 1e-8 pixel) of the canonical coordinate
+      uint64_t T = A.T0 + (uint64_t)((int64_t)ty * A.Ts) + (uint64_t)((int64_t)tx * A.Tc);
 #pragma unroll
       for (int q = 0; q < kBPX; ++q) {
         if (q) T += (uint64_t)A.step;             // kQ columns on: t + kQ c

@@ -34,10 +34,11 @@ struct AngleGeom {
 };
 
 // Canonical detector coordinate of a pixel.  The Gram kernel evaluates
-// exactly this expression; the back-projector evaluates it at the first of
-// each lane's pixels and steps along the row in 32.32 fixed point (about
-// 2^-32 apart), and the forward projector evaluates the same closed form
-// along rays, so all three agree up to float32 weight rounding.
+// exactly this expression; the back-projector evaluates it at each tile's
+// first pixel and reaches the tile's other pixels by row and column steps in
+// 32.32 fixed point (within 1e-8 pixel), and the forward projector evaluates
+// the same closed form along rays, so all three agree up to float32 weight
+// rounding.
 __device__ __forceinline__ double det_coord(double s, double c, double ii, double jj, double off) {
   return fma(jj, c, fma(ii, s, off));
 }
