@@ -22,7 +22,8 @@ struct PcgWork {
   int* ctl = nullptr;       // per-slice stop flag and iteration count [B][kCtlCount]
   float* u = nullptr;       // M^T r              [B][N][N]
   float* uT = nullptr;      // its transpose      [B][N][N]
-  int* h_ctl = nullptr;     // pinned copies of ctl: one per chunk in flight, then the final one
+  int* h_ctl = nullptr;     // pinned host copy of ctl, written by the kernels [B][kCtlCount]
+  int* d_live = nullptr;    // h_ctl's address on the device
   double* h_sc = nullptr;   // pinned copy of sc
   hipEvent_t ev[2] = {nullptr, nullptr};
   hipGraphExec_t graph_exec = nullptr;  // one chunk of iterations (graph mode)
@@ -68,9 +69,10 @@ hipError_t pcg_solve(PcgWork& w, const AngleGeom* geom, const AngleGeom* h_geom,
 // The same solve in steps: begin enqueues the initialisation; enqueue adds
 // the next chunk of iterations when fewer than two are in flight; poll reads
 // the oldest chunk's stop flags once two are in flight (or the cap is
-// reached) and sets run.done; finish_async enqueues the copies of the final
-// state to pinned memory, which report reads once the caller has
-// synchronised the stream.
+// reached) and sets run.done; finish_async enqueues the copy of the final
+// scalars to pinned memory, which report reads (with the control words the
+// kernels keep in pinned memory) once the caller has synchronised the
+// stream.
 hipError_t pcg_begin(PcgRun& run, PcgWork& w, const AngleGeom* geom, const AngleGeom* h_geom,
                      float* partial, int N, int R, int B, const AngleList& win,
                      const ProjTune& tune, double lam, const double* res, size_t res_stride,

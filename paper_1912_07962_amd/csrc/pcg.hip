@@ -23,9 +23,11 @@
 // Termination is decided on the device: the vector kernel sets a slice's
 // flag once its ||r|| <= tol ||e|| and every later CG kernel skips that
 // slice (the projectors skip a slice tile once all its slices stopped).  The
-// host enqueues chunks of iterations ahead and reads the flag from pinned
-// memory after a chunk completes, keeping the next chunk in flight, so the
-// GPU does not idle on host round trips.  Chunks are 8 iterations (one graph
+// host enqueues chunks of iterations ahead and reads the flag after a chunk
+// completes, keeping the next chunk in flight, so the GPU does not idle on
+// host round trips.  The kernels that change the control word also write it
+// to pinned host memory (mapped into the device's address space), so a
+// chunk needs no copy: its completion event makes the words visible.  Chunks are 8 iterations (one graph
 // launch) until a few iterations before the count of the previous solve on
 // the same workspace, then 2, so that few iterations are enqueued past the
 // stop; the first chunk of a solve is launched directly and the graph for
@@ -119,7 +121,8 @@ __global__ __launch_bounds__(kThreads) void init_kernel(int p, int nres, int pma
 __global__ __launch_bounds__(kThreads) void init_scalars_kernel(const double* __restrict__ rr_parts,
                                                                 int nb, int nparts,
                                                                 double* __restrict__ sc,
-                                                                int* __restrict__ ctl) {
+                                                                int* __restrict__ ctl,
+                                                                int* __restrict__ live) {
   __shared__ double sh[kThreads / 64];
   const int sl = blockIdx.y;
   const double bb = sum_parts(rr_parts + (size_t)sl * nparts, nb, sh);
@@ -130,8 +133,11 @@ __global__ __launch_bounds__(kThreads) void init_scalars_kernel(const double* __
     c[S_BB] = bb;
     c[S_BETA] = 0.0;
     c[S_LAST] = bb;
-    ctl[sl * kCtlCount + kCtlDone] = (bb > 0.0) ? 0 : 1;
+    const int done = (bb > 0.0) ? 0 : 1;
+    ctl[sl * kCtlCount + kCtlDone] = done;
     ctl[sl * kCtlCount + kCtlIters] = 0;
+    live[sl * kCtlCount + kCtlDone] = done;
+    live[sl * kCtlCount + kCtlIters] = 0;
   }
 }
 
@@ -155,7 +161,8 @@ __global__ __launch_bounds__(kThreads) void cg_vector_kernel(int p, int pmax, in
                                                              double* __restrict__ sv,
                                                              double* __restrict__ z,
                                                              size_t z_stride,
-                                                             int* __restrict__ ctl) {
+                                                             int* __restrict__ ctl,
+                                                             int* __restrict__ live) {
   const int sl = blockIdx.y;
   if (ctl[sl * kCtlCount + kCtlDone]) return;
   __shared__ double sh[2 * (kThreads / 64)];
@@ -174,13 +181,16 @@ __global__ __launch_bounds__(kThreads) void cg_vector_kernel(int p, int pmax, in
     last_all[(size_t)sl * S_COUNT + S_LAST] = gamma;
     if (conv) {
       ctl[sl * kCtlCount + kCtlDone] = 1;
+      live[sl * kCtlCount + kCtlDone] = 1;
     } else {
       double* sn = sc_next_all + (size_t)sl * S_COUNT;
       sn[S_RR] = gamma;
       sn[S_ALPHA] = alpha;
       sn[S_BETA] = beta;
       sn[S_BB] = bb;
-      ctl[sl * kCtlCount + kCtlIters] += 1;
+      const int it = ctl[sl * kCtlCount + kCtlIters] + 1;
+      ctl[sl * kCtlCount + kCtlIters] = it;
+      live[sl * kCtlCount + kCtlIters] = it;
     }
   }
   if (conv) return;
@@ -215,9 +225,10 @@ hipError_t pcg_alloc(PcgWork& w, int N, int B, int64_t pmax) {
   if ((e = hipMalloc((void**)&w.ctl, (size_t)B * kCtlCount * sizeof(int))) != hipSuccess) return e;
   if ((e = hipMalloc((void**)&w.u, (size_t)B * N * N * sizeof(float))) != hipSuccess) return e;
   if ((e = hipMalloc((void**)&w.uT, (size_t)B * N * N * sizeof(float))) != hipSuccess) return e;
-  if ((e = hipHostMalloc((void**)&w.h_ctl, (size_t)3 * B * kCtlCount * sizeof(int),
-                         hipHostMallocDefault)) != hipSuccess)
+  if ((e = hipHostMalloc((void**)&w.h_ctl, (size_t)B * kCtlCount * sizeof(int),
+                         hipHostMallocMapped | hipHostMallocCoherent)) != hipSuccess)
     return e;
+  if ((e = hipHostGetDevicePointer((void**)&w.d_live, w.h_ctl, 0)) != hipSuccess) return e;
   if ((e = hipHostMalloc((void**)&w.h_sc, (size_t)2 * B * S_COUNT * sizeof(double),
                          hipHostMallocDefault)) != hipSuccess)
     return e;
@@ -270,7 +281,7 @@ hipError_t pcg_begin(PcgRun& run, PcgWork& w, const AngleGeom* geom, const Angle
   hipLaunchKernelGGL(init_kernel, dim3(run.nb, B), dim3(kThreads), 0, st, run.p, nres, w.pmax,
                      np, res, res_stride, w.r, z, z_stride, w.pd, w.s, rr_parts);
   hipLaunchKernelGGL(init_scalars_kernel, dim3(1, B), dim3(kThreads), 0, st, rr_parts, run.nb,
-                     np, w.sc, w.ctl);
+                     np, w.sc, w.ctl, w.d_live);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
 
@@ -341,7 +352,7 @@ hipError_t enqueue_iterations(PcgRun& run, int todo, bool timed) {
     if (timed && (e = prof->begin(K_VEC, st)) != hipSuccess) return e;
     hipLaunchKernelGGL(cg_vector_kernel, dim3(run.nb, B), dim3(kThreads), 0, st, run.p, w.pmax,
                        run.nb, np, sc_cur, sc_nxt, w.sc, dq_parts, rr_parts, run.tol2, w.q, w.r,
-                       w.pd, w.s, run.z, run.z_stride, w.ctl);
+                       w.pd, w.s, run.z, run.z_stride, w.ctl, w.d_live);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (timed && (e = prof->end(st)) != hipSuccess) return e;
   }
@@ -402,10 +413,6 @@ hipError_t pcg_enqueue(PcgRun& run, bool use_graph) {
     if ((e = enqueue_iterations(run, todo, timed)) != hipSuccess) return e;
   }
   run.enq += todo;
-  int* slot = w.h_ctl + (size_t)(run.chunks & 1) * B * kCtlCount;
-  if ((e = hipMemcpyAsync(slot, w.ctl, (size_t)B * kCtlCount * sizeof(int), hipMemcpyDeviceToHost,
-                          run.st)) != hipSuccess)
-    return e;
   if ((e = hipEventRecord(w.ev[run.chunks & 1], run.st)) != hipSuccess) return e;
   ++run.chunks;
   return hipSuccess;
@@ -418,10 +425,12 @@ hipError_t pcg_poll(PcgRun& run) {
     PcgWork& w = *run.w;
     hipError_t e = hipEventSynchronize(w.ev[run.seen & 1]);
     if (e != hipSuccess) return e;
-    const int* slot = w.h_ctl + (size_t)(run.seen & 1) * run.B * kCtlCount;
+    // the control words as of this chunk's end or later (they only advance;
+    // a later chunk may be writing them)
+    const volatile int* live = w.h_ctl;
     ++run.seen;
     bool all = true;
-    for (int b = 0; b < run.B; ++b) all = all && slot[b * kCtlCount + kCtlDone] != 0;
+    for (int b = 0; b < run.B; ++b) all = all && live[b * kCtlCount + kCtlDone] != 0;
     if (all || (run.enq >= run.max_iter && run.seen == run.chunks)) run.done = true;
   }
   return hipSuccess;
@@ -429,20 +438,14 @@ hipError_t pcg_poll(PcgRun& run) {
 
 hipError_t pcg_finish_async(PcgRun& run) {
   PcgWork& w = *run.w;
-  const int B = run.B;
-  hipError_t e;
-  if ((e = hipMemcpyAsync(w.h_ctl + (size_t)2 * B * kCtlCount, w.ctl,
-                          (size_t)B * kCtlCount * sizeof(int), hipMemcpyDeviceToHost, run.st)) !=
-      hipSuccess)
-    return e;
-  return hipMemcpyAsync(w.h_sc, w.sc, (size_t)2 * B * S_COUNT * sizeof(double),
+  return hipMemcpyAsync(w.h_sc, w.sc, (size_t)2 * run.B * S_COUNT * sizeof(double),
                         hipMemcpyDeviceToHost, run.st);
 }
 
 void pcg_report(PcgRun& run, int* iters, double* relres) {
   PcgWork& w = *run.w;
   const int B = run.B;
-  const int* ctl = w.h_ctl + (size_t)2 * B * kCtlCount;
+  const volatile int* ctl = w.h_ctl;   // final once the stream is synchronised
   int it_max = 0;
   double rel_max = 0.0;
   for (int b = 0; b < B; ++b) {
