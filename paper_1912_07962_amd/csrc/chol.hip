@@ -38,6 +38,7 @@ struct PotrfLds {
   double piv[kNB];
   double rsq[kNB];   // 1 / sqrt(pivot) = 1 / L[k][k]
   double Ls[kNB][kNB + 1];
+  double X[kNB][kNB + 1];   // L^-1 being formed
 };
 struct TileLds {
   double A[kNB][kNB + 1];
@@ -115,19 +116,58 @@ __device__ __forceinline__ void potrf_diag_body(double* __restrict__ G, int64_t 
       if (i < nb && k <= i) G[(int64_t)(k0 + i) * ld + (k0 + k)] = v;
     }
   __syncthreads();
+  // L^-1 in 2 x 2 blocks of 32: X11 = L11^-1 and X22 = L22^-1 by
+  // substitution (one lane per column, both blocks at once), then
+  // X21 = -X22 (L21 X11) by all lanes; X12 = 0.
+  constexpr int kH = kNB / 2;
   if (threadIdx.x < kNB) {
-    const int c = threadIdx.x;
-    double w[kNB];
+    const int c = threadIdx.x & (kH - 1), o = threadIdx.x & kH;
+    double w[kH];
 #pragma unroll
-    for (int i = 0; i < kNB; ++i) {
+    for (int i = 0; i < kH; ++i) {
       // four independent partial sums keep the substitution's chain short
       double s4[4] = {(i == c) ? 1.0 : 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int k = 0; k < i; ++k) s4[k & 3] -= S.Ls[i][k] * w[k];
-      w[i] = (i < nb) ? ((s4[0] + s4[1]) + (s4[2] + s4[3])) * S.rsq[i] : 0.0;
+      for (int k = 0; k < i; ++k) s4[k & 3] -= S.Ls[o + i][o + k] * w[k];
+      w[i] = ((s4[0] + s4[1]) + (s4[2] + s4[3])) * S.rsq[o + i];   // rsq = 0 past nb
     }
 #pragma unroll
-    for (int i = 0; i < kNB; ++i) winv[i * kNB + c] = (c < nb) ? w[i] : 0.0;
+    for (int i = 0; i < kH; ++i) S.X[o + i][o + c] = w[i];
+  }
+  __syncthreads();
+  // T = L21 X11 into the (zero) upper-right block of X, then
+  // X21 = -X22 T.  A lane takes column q of rows r, r + 8, r + 16, r + 24;
+  // the sums run over all 32 terms (the triangles' zeros are stored), fully
+  // unrolled with four independent accumulators.
+  static_assert(kH * kH == 4 * 256, "four entries of each 32 x 32 product per lane");
+  const int q = threadIdx.x & (kH - 1), r0 = threadIdx.x >> 5;   // r0 in [0, 8)
+  {
+    double t[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < kH; ++k) {
+      const double x = S.X[k][q];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) t[j] += S.Ls[kH + r0 + 8 * j][k] * x;
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) S.X[r0 + 8 * j][kH + q] = t[j];
+  }
+  __syncthreads();
+  {
+    double t[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < kH; ++k) {
+      const double x = S.X[k][kH + q];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) t[j] += S.X[kH + r0 + 8 * j][kH + k] * x;
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) S.X[kH + r0 + 8 * j][q] = -t[j];
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < kNB * kNB; e += 256) {
+    const int i = e / kNB, c = e % kNB;
+    winv[e] = (c <= i && c < nb && i < nb) ? S.X[i][c] : 0.0;
   }
 }
 
