@@ -75,10 +75,12 @@ typedef struct {
   int check_every;      /* slim_solve: read the step norms every q steps    */
   uint64_t seed;        /* slim_solve: SplitMix64 seed of the block order   */
   void* stream;         /* hipStream_t work queue (NULL = default stream)   */
-  int use_graph;        /* 1: each chunk of CG iterations of a step is
-                           captured once as a hipGraph and replayed (only on
-                           a stream other than NULL, and not while kernel
-                           timing is on); 0: launched one by one            */
+  int use_graph;        /* 1: the 8-iteration chunks of a step's CG after
+                           the first are replayed from one hipGraph, captured
+                           while the first chunk runs (only on a stream other
+                           than NULL, and not while kernel timing is on;
+                           short chunks near the stop are launched directly);
+                           0: launched one by one                          */
 } slim_opts;
 
 typedef struct {
