@@ -551,8 +551,8 @@ def main():
                     help="of those, samples timed as single-slice runs")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build measures one GPU only; --gpus must be 1 "
-              "(the batched-slice path shards by slices, see DESIGN.md)", file=sys.stderr)
+        print("bench.py: measures one GPU only; --gpus must be 1 (more GPUs would "
+              "each take a share of the slices)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
