@@ -52,11 +52,11 @@ def test_rays_per_lane_follows_the_launch_plan():
 def test_window_nnz_matches_the_oracle_matrix():
     # the roofline's algorithmic flops count 2 d N^2 non-zero weights per
     # angle; the oracle's CSR rows of the same angles hold that many to
-    # within the pixels whose second weight is exactly zero at the borders
+    # 0.5% (it agrees to 2e-4: only border pixels differ)
     from oracle import system
     N, na = 64, 90
     P = system.Projector(N, na)
     ids = [0, 11, 22, 45, 67]
     th = np.array(ids) * np.pi / na
     nnz = P.rows(ids).nnz
-    assert abs(bench.window_nnz(N, th) - nnz) <= 0.03 * nnz
+    assert abs(bench.window_nnz(N, th) - nnz) <= 0.005 * nnz
