@@ -857,7 +857,7 @@ static int num_cu() {
 int slice_tile(int B) { return B >= 4 ? 4 : (B >= 2 ? 2 : 1); }
 
 // The forward projector's slice tile: as wide as the batch allows while a
-// band still holds at least kMinRows image rows (the band is 64 KB of LDS,
+// band still holds at least kMinRows image rows (the band is 64-68 KB of LDS,
 // so wide tiles of large images would leave a few rows per barrier).
 constexpr int kMinRows = 8;
 static int fwd_slice_tile(int B, int N) {
