@@ -67,13 +67,13 @@ PEAK_FP64_TFLOPS = 78.6
 # line reports traffic as null.
 PMC_TRAFFIC = {
     "source": "paper_1912_07962_amd/csrc/project.hip",
-    "sha256": "55e53df273d72aad6d6a0d77acd8371309f2fbb2af933e2337c5052932a8f786",
+    "sha256": "f8ea58a12f8a2e55dae482669e1d0fea65ff61f7df858d1d7d4553d5e46339fa",
     "fetch_scale": 2.0,
     "write_scale": 1.0,
     # instance -> (FETCH_SIZE, WRITE_SIZE) KiB per dispatch
-    "kib": {"cg_forward/2": (6225.8, 1992.4), "cg_forward/3": (6236.6, 2988.6),
-            "cg_forward/4": (4208.0, 3984.8), "cg_forward/6": (5384.0, 5479.0),
-            "cg_forward/8": (4255.0, 7969.5), "cg_back/1": (3095.5, 8192.8)},
+    "kib": {"cg_forward/2": (6232.8, 1992.8), "cg_forward/3": (6250.6, 2989.1),
+            "cg_forward/4": (4211.5, 3984.8), "cg_forward/6": (5401.0, 5479.7),
+            "cg_forward/8": (4274.5, 7969.5), "cg_back/1": (3088.2, 8192.8)},
 }
 
 

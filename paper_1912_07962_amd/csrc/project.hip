@@ -106,6 +106,7 @@ struct FwdPlan {
   int n_tiles;    // slice tiles of BT slices
   int items;      // rays per lane (template argument of the band kernel)
   int bt;         // slice tile (template argument of the band kernel)
+  int il_lg;      // log2 of the number of angles whose rays interleave (ray_of)
   short id[kMaxList];
   short slot[kMaxList];
 };
@@ -121,6 +122,26 @@ __device__ __forceinline__ void chunk_range(const FwdPlan& pl, int R, int c, int
   eg = colm ? pl.n_row : 0;
   i0 = (colm ? c - nrc : c) * pl.per;
   i1 = min(colm ? (pl.n - pl.n_row) * R : nr, i0 + pl.per);
+}
+
+// Ray j of an orientation group of ng angles: the angles are taken in
+// groups of il = 2^lg (il m ... il m + il - 1) whose rays interleave,
+// j = il (m R + t) + (0 ... il - 1), so the 128 rays a wave walks together
+// (a pair of 64-ray runs) are 128 / il detector bins of il angles adjacent in
+// the list (within a block of the window: row ranges that differ little,
+// and the bins' spread shrinks by il); the last ng mod il angles interleave
+// likewise among themselves.
+__device__ __forceinline__ void ray_of(int j, int ng, int R, int lg, int& e, int& t) {
+  const int il = 1 << lg, full = (ng >> lg) << lg;
+  if (j < full * R) {
+    const int m = j / (il * R), rem = j - m * il * R;
+    e = il * m + (rem & (il - 1));
+    t = rem >> lg;
+  } else {
+    const int j2 = j - full * R, k = ng - full;
+    e = full + j2 % k;
+    t = j2 / k;
+  }
 }
 
 // Ray of slot q of a lane within its chunk: slots 2p and 2p+1 of wave w hold
@@ -165,6 +186,7 @@ __global__ __launch_bounds__(kFT, 2) void fwd_band_kernel(const AngleGeom* __res
   bool colm;
   chunk_range(pl, R, chunk, eg, i0, i1, colm);
   const int nitems = i1 - i0;
+  const int ng = colm ? pl.n - pl.n_row : pl.n_row;   // angles of the orientation group
   // Column-stepping chunks walk the transposed image: from imgT when given
   // (bands of its rows), else from img as bands of columns, transposed on
   // their way into LDS.
@@ -198,8 +220,9 @@ __global__ __launch_bounds__(kFT, 2) void fwd_band_kernel(const AngleGeom* __res
     S[q] = 0;
     int klo = N, khi = -1;
     if (item < nitems) {
-      const int e = eg + (i0 + item) / R;
-      const int t = (i0 + item) % R;
+      int e, t;
+      ray_of(i0 + item, ng, R, pl.il_lg, e, t);
+      e += eg;
       const AngleGeom g = geom[pl.id[e]];
       const double cm = colm ? g.c : g.s;   // coefficient of the major coordinate
       const double cn = colm ? g.s : g.c;   // of the minor one, |cn| = d
@@ -420,8 +443,9 @@ __global__ __launch_bounds__(kFT, 2) void fwd_band_kernel(const AngleGeom* __res
   for (int q = 0; q < IT; ++q) {
     const int item = slot_item<IT>(q, threadIdx.x);
     if (item < nitems) {
-      const int e = eg + (i0 + item) / R;
-      const int t = (i0 + item) % R;
+      int e, t;
+      ray_of(i0 + item, ng, R, pl.il_lg, e, t);
+      e += eg;
 #pragma unroll
       for (int b = 0; b < BT; ++b)
         if (b < nb)
@@ -895,6 +919,10 @@ static FwdPlan make_plan(const AngleGeom* h_geom, int N, int R, const AngleList&
   pl.per = pl.items * kFT;
   pl.n_chunks = (pl.n_row * R + pl.per - 1) / pl.per + ((ids.n - pl.n_row) * R + pl.per - 1) / pl.per;
   pl.n_tiles = (B + BT - 1) / BT;
+  // interleaving more angles shrinks each wave's union of row ranges but
+  // spreads its LDS reads over more clusters: four angles paid off for
+  // detectors of 725 bins (512^2 volume window), two for 1449 (1024^2)
+  pl.il_lg = R >= 1024 ? 1 : 2;
   pl.H = std::max(1, std::min(N, 16384 / ((N + 2 * kPad) * BT)));
   // bands of columns load four columns per 16-byte read: H a multiple of 4
   // (rounded up while the band stays within 68 KB and the lanes' prefetch
