@@ -81,6 +81,10 @@ typedef struct {
                            than NULL, and not while kernel timing is on;
                            short chunks near the stop are launched directly);
                            0: launched one by one                          */
+  int damping_ramp;     /* 1: ramped damping of sec. 4.2 (used in sec. 4.3):
+                           alpha_k = k alpha / (r+1) for the first r+1 steps,
+                           i.e. step k uses lambda (r+1) / k while k <= r and
+                           lambda after; 0: constant lambda                */
 } slim_opts;
 
 typedef struct {
@@ -103,7 +107,7 @@ typedef struct {
 
 /* Fill *opts with defaults: g = 1, FP32, AUTO, chol_max_p = 8192,
  * pcg_max_iter = 1000, pcg_tol = 1e-6, check_every = 1, seed = 0, NULL stream,
- * use_graph = 1. */
+ * use_graph = 1, damping_ramp = 0. */
 slim_status slim_default_opts(slim_opts* opts);
 
 /* Create a context (paper sec. 1 setup, sec. 4.3 geometry).
@@ -137,6 +141,16 @@ slim_status slim_set_data(slim_ctx* ctx, const void* b, void* x, const float* x_
  * Errors: SLIM_EINVAL (bad ids), SLIM_ESTATE (no data), SLIM_ENUMERIC,
  * SLIM_ENOTCONV (CG cap reached; the step is still applied), SLIM_EDEVICE. */
 slim_status slim_step(slim_ctx* ctx, const int32_t* angle_ids, int n_ids, slim_step_info* info);
+
+/* Set the damping lambda = 1/alpha used by the following steps (eq. (B_k)
+ * with C_k = I).  The end of sec. 3 suggests a constant alpha_k for fast
+ * initial progress, then a decaying alpha_k (a growing lambda) for accuracy;
+ * the paper gives no formula for the decay, so the caller drives it by
+ * calling this between steps.  With damping_ramp on, steps k <= r still use lambda (r+1) / k of
+ * the value set here.  lambda is a parameter of the context, not of the
+ * iteration state (slim_get_state does not hold it).
+ * Errors: SLIM_EINVAL (NULL ctx, lambda not positive and finite). */
+slim_status slim_set_lambda(slim_ctx* ctx, double lambda);
 
 /* Per-slice norms of the last step whose info was read back (slim_step
  * with info != NULL, or slim_solve): out is host float64 [n_slices][3]

@@ -2,8 +2,11 @@
 
 Paper: eq. (ram)   x_k = x_{k-1} - B_k A_k^T (A_k x_{k-1} - b_k)
        eq. (B_k)   B_k = (alpha_k^{-1} C_k + M_k^T M_k)^{-1},  M_k = [A_{k-r}; ...; A_k]
-with C_k = I and a constant alpha_k = 1/lam (sec. 1: C_k = I and r = 0 give
-damped block Kaczmarz, eq. (dbK)).  Blocks with negative index are empty,
+with C_k = I and alpha_k = 1/lam (sec. 1: C_k = I and r = 0 give damped block
+Kaczmarz, eq. (dbK)).  alpha_k is constant, or ramped up over the first r+1
+steps as in sec. 4.2 (alpha_k = k alpha / (r+1), used in sec. 4.3), which in
+terms of lam is lam_k = lam (r+1) / k for k <= r+1; ``lam`` may also be
+changed between steps (a caller-driven decay of alpha_k, end of sec. 3).  Blocks with negative index are empty,
 so M_k grows over the first r steps (sec. 1).
 
 Three algebraically equal ways to form the step s_k = x_{k-1} - x_k:
@@ -23,6 +26,8 @@ Three algebraically equal ways to form the step s_k = x_{k-1} - x_k:
 
 Pins (tests/test_oracle_*.py): the three forms agree; r = 0 is damped block
 Kaczmarz (eq. dbK); lam -> 0 with one row per block is Kaczmarz (eq. Kacz);
+the ramp's first steps against closed forms for one- and two-row windows
+(Sherman-Morrison, Cramer's rule);
 full memory over one epoch gives the Tikhonov solution at every k (the
 induction of App. A with the damped Hessian); the residual identity after a
 step; consistent data is a fixed point; Theorem 3.1(i) in expectation.
@@ -148,6 +153,15 @@ class SlimLS:
     # x_store(x): the image as stored for the residual A_k x (identity; the
     # bf16-storage variant passes a rounding to bfloat16)
     x_store: callable = None
+    # ramp: alpha_k = k alpha / (r+1) for k <= r+1 (sec. 4.2), else alpha
+    ramp: bool = False
+
+    def lam_at(self, k: int) -> float:
+        """Damping 1/alpha_k of the k-th step (1-based)."""
+        alpha = 1.0 / self.lam
+        if self.ramp and k <= self.r + 1:
+            alpha = k * alpha / (self.r + 1)
+        return 1.0 / alpha
 
     def step(self, beta: int) -> StepRecord:
         self.window.append(int(beta))
@@ -158,12 +172,13 @@ class SlimLS:
         xs = self.x if self.x_store is None else self.x_store(self.x)
         res = np.asarray(Ak @ xs).reshape(-1) - self.block_data(beta)
         info = {"mode": self.form, "iters": 0}
+        lam = self.lam_at(self.k + 1)
         if self.form == "dual":
-            s, _, info = step_dual(mats, res, self.lam, self.chol_max_p, self.cg_tol)
+            s, _, info = step_dual(mats, res, lam, self.chol_max_p, self.cg_tol)
         elif self.form == "primal":
-            s = step_primal(mats, res, self.lam)
+            s = step_primal(mats, res, lam)
         elif self.form == "woodbury":
-            s = step_woodbury(mats, res, self.lam)
+            s = step_woodbury(mats, res, lam)
         else:
             raise ValueError(self.form)
         self.x = self.x - s
@@ -201,7 +216,7 @@ class Tomo:
     def __init__(self, projector, b: np.ndarray, g: int, r: int, lam: float,
                  x0: np.ndarray | None = None, x_true: np.ndarray | None = None,
                  chol_max_p: int = 8000, cg_tol: float = 1e-12, form: str = "dual",
-                 x_store=None):
+                 x_store=None, ramp: bool = False):
         self.P = projector
         self.g = g
         self.n_blocks = projector.n_angles // g
@@ -209,7 +224,7 @@ class Tomo:
         x0 = np.zeros(projector.n) if x0 is None else np.asarray(x0, np.float64).reshape(-1)
         xt = None if x_true is None else np.asarray(x_true, np.float64).reshape(-1)
         self.it = SlimLS(self.rows, self.data, r, lam, x0.copy(), xt, form, chol_max_p, cg_tol,
-                         x_store=x_store)
+                         x_store=x_store, ramp=ramp)
 
     def angles_of(self, beta: int):
         return list(range(beta * self.g, beta * self.g + self.g))

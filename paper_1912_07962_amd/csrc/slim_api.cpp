@@ -169,6 +169,14 @@ struct slim_ctx {
 
 namespace {
 
+// Damping of the k-th step (1-based).  Constant lambda = 1/alpha, or with the
+// ramp of sec. 4.2 (alpha_k = k alpha / (r+1) for the first r+1 steps)
+// lambda_k = lambda (r+1) / k while k <= r.
+double lam_at(const slim_ctx* c, int k) {
+  if (c->o.damping_ramp && k >= 1 && k <= c->r) return c->lam * (double)(c->r + 1) / (double)k;
+  return c->lam;
+}
+
 slim_status check_ids(const slim_ctx* c, const int32_t* ids, int n, bool allow_repeat) {
   if (!ids || n <= 0) return fail(SLIM_EINVAL, "angle id list is empty or NULL");
   if (n > kMaxList) return fail(SLIM_EINVAL, "too many angle ids in one call");
@@ -239,7 +247,7 @@ FwdArgs base_fwd(const slim_ctx* c, const AngleList* l) {
 }
 
 // Gram mode: z = G^{-1} [0; res] for every slice, G shared by the slices.
-slim_status gram_solve_chol(slim_ctx* c, int new_slot) {
+slim_status gram_solve_chol(slim_ctx* c, int new_slot, double lam) {
   const int64_t ell = c->ell;
   const int W = (int)c->window.size();
   const int64_t p = (int64_t)W * ell;
@@ -257,7 +265,7 @@ slim_status gram_solve_chol(slim_ctx* c, int new_slot) {
   bool ring = true;
   for (int P = 0; P < W; ++P) ring = ring && c->window[P] == (c->window[0] + P) % S;
   if (ring && (int64_t)W * (W + 1) / 2 <= 65535 && ell <= 65535) {
-    HIP_TRY(launch_tile_assemble(c->d_tiles, S, c->window[0], W, (int)ell, c->d_G, p, c->lam,
+    HIP_TRY(launch_tile_assemble(c->d_tiles, S, c->window[0], W, (int)ell, c->d_G, p, lam,
                                  c->st));
   } else {
     for (int P = 0; P < W; ++P)
@@ -265,7 +273,7 @@ slim_status gram_solve_chol(slim_ctx* c, int new_slot) {
         const int sp = c->window[P], sq = c->window[Q];
         const double* T = c->d_tiles + ((int64_t)sp * S + sq) * ell * ell;
         HIP_TRY(launch_tile_copy(T, ell, c->d_G, p, (int)(P * ell), (int)(Q * ell), (int)ell,
-                                 (int)ell, c->lam, P == Q, c->st));
+                                 (int)ell, lam, P == Q, c->st));
       }
   }
   if (c->prof.on) HIP_TRY(c->prof.end(c->st));
@@ -284,6 +292,7 @@ slim_status gram_solve_chol(slim_ctx* c, int new_slot) {
 struct StepState {
   AngleList blk, win;
   int slot = 0;
+  double lam = 0.0;  // damping of this step
   bool pcg = false;
   PcgRun run;
 };
@@ -291,6 +300,7 @@ struct StepState {
 slim_status step_begin(slim_ctx* c, const int32_t* ids, StepState& ss) {
   const int S = c->r + 1;
   ss.slot = c->k % S;
+  ss.lam = lam_at(c, c->k + 1);
   if ((int)c->window.size() == S) c->window.pop_front();
   c->slot_ids[ss.slot].assign(ids, ids + c->g);
   c->window.push_back(ss.slot);
@@ -324,9 +334,9 @@ slim_status step_begin(slim_ctx* c, const int32_t* ids, StepState& ss) {
   if (c->prof.on) HIP_TRY(c->prof.end(c->st));
   // 2. Gram system: solved here (Cholesky) or started (CG)
   ss.pcg = c->mode == SLIM_GRAM_PCG;
-  if (!ss.pcg) return gram_solve_chol(c, ss.slot);
+  if (!ss.pcg) return gram_solve_chol(c, ss.slot, ss.lam);
   hipError_t e = pcg_begin(ss.run, c->pcg, c->d_geom, c->h_geom.data(), c->d_fpart, c->N, c->R,
-                           c->B, ss.win, c->tune_for(ss.win.n), c->lam, c->d_res64, ell, (int)ell, c->d_z,
+                           c->B, ss.win, c->tune_for(ss.win.n), ss.lam, c->d_res64, ell, (int)ell, c->d_z,
                            c->pmax, c->o.pcg_tol, c->o.pcg_max_iter, &c->prof, c->st);
   if (e != hipSuccess) return fail(SLIM_EDEVICE, std::string("pcg: ") + hipGetErrorString(e));
   return SLIM_OK;
@@ -442,6 +452,7 @@ slim_status slim_default_opts(slim_opts* o) {
   o->seed = 0;
   o->stream = nullptr;
   o->use_graph = 1;
+  o->damping_ramp = 0;
   return SLIM_OK;
 }
 
@@ -467,6 +478,7 @@ slim_status slim_init(slim_ctx** out, const slim_grid* grid, int n_angles, const
     return fail(SLIM_EINVAL, "unknown precision");
   if (o.gram_mode < SLIM_GRAM_AUTO || o.gram_mode > SLIM_GRAM_PCG) return fail(SLIM_EINVAL, "unknown gram_mode");
   if (o.check_every < 1) return fail(SLIM_EINVAL, "check_every must be >= 1");
+  if (o.damping_ramp != 0 && o.damping_ramp != 1) return fail(SLIM_EINVAL, "damping_ramp must be 0 or 1");
   if (o.pcg_max_iter < 1 || !(o.pcg_tol > 0.0)) return fail(SLIM_EINVAL, "bad CG settings");
   if (angles) {
     for (int a = 0; a < n_angles; ++a)
@@ -560,6 +572,13 @@ slim_status slim_set_data(slim_ctx* c, const void* b, void* x, const float* x_tr
   c->pos = 0;
   c->total_pcg_iters = 0;
   return transpose_slices(c);
+}
+
+slim_status slim_set_lambda(slim_ctx* c, double lambda) {
+  if (!c) return fail(SLIM_EINVAL, "ctx is NULL");
+  if (!(lambda > 0.0) || !std::isfinite(lambda)) return fail(SLIM_EINVAL, "lambda must be positive and finite");
+  c->lam = lambda;
+  return SLIM_OK;
 }
 
 slim_status slim_step(slim_ctx* c, const int32_t* ids, int n_ids, slim_step_info* info) {

@@ -39,7 +39,8 @@ class Opts(ctypes.Structure):
                 ("gram_mode", ctypes.c_int), ("chol_max_p", ctypes.c_int),
                 ("pcg_max_iter", ctypes.c_int), ("pcg_tol", ctypes.c_double),
                 ("check_every", ctypes.c_int), ("seed", ctypes.c_uint64),
-                ("stream", ctypes.c_void_p), ("use_graph", ctypes.c_int)]
+                ("stream", ctypes.c_void_p), ("use_graph", ctypes.c_int),
+                ("damping_ramp", ctypes.c_int)]
 
 
 class StepInfo(ctypes.Structure):
@@ -90,6 +91,7 @@ def load() -> ctypes.CDLL:
                           ctypes.POINTER(Opts)]),
         "slim_set_data": (I, [P, P, P, P]),
         "slim_step": (I, [P, i32p, I, ctypes.POINTER(StepInfo)]),
+        "slim_set_lambda": (I, [P, D]),
         "slim_solve": (I, [P, P, P, P, D, I, ctypes.POINTER(SolveInfo)]),
         "slim_project": (I, [P, i32p, I, P, P]),
         "slim_backproject": (I, [P, i32p, I, P, P]),
@@ -166,7 +168,8 @@ class Slim:
                  lam: float = 1e-2, n_slices: int = 1, angles_per_block: int = 1,
                  precision: str = "fp32", gram_mode: str = "auto", chol_max_p: int = 8192,
                  pcg_max_iter: int = 1000, pcg_tol: float = 1e-6, check_every: int = 1,
-                 seed: int = 0, angles=None, stream=None, use_graph: bool = True):
+                 seed: int = 0, angles=None, stream=None, use_graph: bool = True,
+                 damping_ramp: bool = False):
         lib = load()
         if n_rays is None:
             n_rays = 2 * int(np.floor(N / np.sqrt(2.0))) + 1
@@ -184,6 +187,7 @@ class Slim:
         o.check_every = int(check_every)
         o.seed = int(seed) & ((1 << 64) - 1)
         o.use_graph = int(bool(use_graph))
+        o.damping_ramp = int(bool(damping_ramp))
         if stream is None and torch.cuda.is_available():
             stream = torch.cuda.current_stream()
         o.stream = ctypes.c_void_p(stream.cuda_stream if stream is not None else 0)
@@ -216,6 +220,11 @@ class Slim:
         if not read:
             return None
         return {f: getattr(info, f) for f, _ in StepInfo._fields_}
+
+    def set_lambda(self, lam: float):
+        """Damping lambda = 1/alpha of the following steps."""
+        _check(load().slim_set_lambda(self._h, float(lam)))
+        self.lam = float(lam)
 
     def slice_norms(self) -> np.ndarray:
         """[n_slices][3] float64: ||s_k||, ||x_k||, ||x_k - x_true|| of the last
@@ -355,6 +364,7 @@ def init_error(**kw) -> int:
     o.precision = kw.get("precision", 0)
     o.gram_mode = kw.get("gram_mode", 0)
     o.check_every = kw.get("check_every", 1)
+    o.damping_ramp = kw.get("damping_ramp", 0)
     g = Grid(N, kw.get("n_slices", 1))
     h = ctypes.c_void_p()
     st = lib.slim_init(ctypes.byref(h), ctypes.byref(g), kw.get("n_angles", 90), None,

@@ -24,6 +24,7 @@ def test_strerror_and_default_opts():
     o = slim.Opts()
     assert lib.slim_default_opts(ctypes.byref(o)) == 0
     assert o.angles_per_block == 1 and o.chol_max_p == 8192 and o.pcg_tol == 1e-6
+    assert o.use_graph == 1 and o.damping_ramp == 0
     assert lib.slim_default_opts(None) == slim.SLIM_EINVAL
 
 
@@ -31,7 +32,8 @@ def test_strerror_and_default_opts():
     dict(N=1), dict(N=0), dict(n_slices=0), dict(n_angles=0), dict(n_rays=0), dict(r=-1),
     dict(lam=0.0), dict(lam=-1.0), dict(lam=float("nan")), dict(lam=float("inf")),
     dict(angles_per_block=7), dict(angles_per_block=0), dict(precision=5), dict(gram_mode=9),
-    dict(check_every=0), dict(r=200, angles_per_block=2),
+    dict(check_every=0), dict(r=200, angles_per_block=2), dict(damping_ramp=2),
+    dict(damping_ramp=-1),
     dict(N=512, n_rays=725, n_angles=360, angles_per_block=4, r=8, gram_mode=1),  # p > 8192
 ])
 def test_init_rejects_bad_arguments(kw):
@@ -43,6 +45,7 @@ def test_null_handles_are_rejected():
     lib = slim.load()
     assert lib.slim_set_data(None, None, None, None) == slim.SLIM_EINVAL
     assert lib.slim_step(None, None, 0, None) == slim.SLIM_EINVAL
+    assert lib.slim_set_lambda(None, 1.0) == slim.SLIM_EINVAL
     assert lib.slim_solve(None, None, None, None, 1e-2, 1, None) == slim.SLIM_EINVAL
     assert lib.slim_project(None, None, 0, None, None) == slim.SLIM_EINVAL
     assert lib.slim_slice_norms(None, None, 0) == slim.SLIM_EINVAL

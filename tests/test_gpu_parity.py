@@ -157,6 +157,35 @@ def test_custom_ray_count_windows_match_oracle(N, R, g, r, mode):
             assert abs(info["step_norm"] - rec.step_norm) <= 1e-5 * rec.step_norm
 
 
+
+@gpu
+@pytest.mark.parametrize("mode", ["chol", "pcg"])
+def test_ramped_and_changed_damping_match_oracle(mode):
+    """Ramped alpha_k = k alpha / (r+1) over the first r+1 steps (sec. 4.2),
+    then a caller-driven decay of alpha_k (lambda doubled, then set back)."""
+    N, na, g, r, lam = 64, 90, 2, 3, 1e-2
+    x_true, b = _c1_problem(N, na)
+    M = na // g
+    P = system.Projector(N, na)
+    T = slimls.Tomo(P, b, g, r, lam, x_true=x_true, ramp=True)
+    s = Slim(N, na, r=r, lam=lam, angles_per_block=g, gram_mode=mode, pcg_tol=1e-11,
+             pcg_max_iter=3000, damping_ramp=True)
+    x = torch.zeros((N, N), dtype=torch.float32, device="cuda")
+    s.set_data(_dev(b), x, _dev(x_true))
+    for k, beta in enumerate(sampler.schedule(M, 1, 5001)[:12], 1):
+        if k in (7, 10):
+            new = 2 * lam if k == 7 else lam
+            s.set_lambda(new)
+            T.it.lam = new
+        info = s.step(list(range(beta * g, beta * g + g)))
+        rec = T.step(beta)
+        assert _rel(x.cpu().numpy(), T.x) < 1e-5, (k, _rel(x.cpu().numpy(), T.x))
+        assert abs(info["step_norm"] - rec.step_norm) <= 1e-5 * rec.step_norm
+    with pytest.raises(Exception):
+        s.set_lambda(0.0)
+    with pytest.raises(Exception):
+        s.set_lambda(float("nan"))
+
 @gpu
 def test_solve_matches_oracle_and_stop_rule():
     cfg = synth.get_config("c1")

@@ -286,3 +286,73 @@ def test_round_bf16_published_values():
     vals = np.array([1.0, 1 + 2.0 ** -8, 1 + 3 * 2.0 ** -8, np.pi, -np.pi, 65504.0])
     got = round_bf16(vals)
     np.testing.assert_array_equal(got, [1.0, 1.0, 1 + 2.0 ** -6, 3.140625, -3.140625, 65536.0])
+
+
+def _cramer(G, rhs):
+    """Solve G z = rhs by Cramer's rule (determinants; tiny systems only)."""
+    d = np.linalg.det(G)
+    z = np.empty(len(rhs))
+    for i in range(len(rhs)):
+        Gi = G.copy()
+        Gi[:, i] = rhs
+        z[i] = np.linalg.det(Gi) / d
+    return z
+
+
+def test_ramped_damping_first_steps_closed_forms():
+    """Ramp of sec. 4.2: alpha_k = k alpha / (r+1) for k <= r+1, then alpha.
+
+    Single-row blocks make each step a tiny Gram system: one row is
+    Sherman-Morrison, x_1 = x_0 - a (a x_0 - b) / (1/alpha_1 + |a|^2); two to
+    three rows are solved by Cramer's rule on (M M^T + I/alpha_k) z = [0; ...; res]
+    with s = M^T z (the push-through identity of eq. (B_k)).  A wrong ramp
+    index (k vs k+1, r vs r+1) or a ramp applied to lam instead of alpha
+    moves every step below."""
+    rng = np.random.default_rng(21)
+    A = rng.standard_normal((12, 7))
+    b = rng.standard_normal(12)
+    blocks = [np.array([i]) for i in range(12)]
+    r, lam = 2, 0.4
+    alpha = 1.0 / lam
+    it = slimls.SlimLS(lambda t: A[blocks[t]], lambda t: b[blocks[t]], r, lam, np.zeros(7),
+                       ramp=True)
+    plain = _runner(A, b, blocks, r, lam)
+    x = np.zeros(7)
+    sched = [4, 9, 0, 6, 2]
+    for k, tau in enumerate(sched, 1):
+        alpha_k = k * alpha / (r + 1) if k <= r + 1 else alpha
+        win = sched[max(0, k - 1 - r):k]
+        M = A[win]
+        res = A[tau] @ x - b[tau]
+        if len(win) == 1:
+            a = A[tau]
+            s = a * res / (1.0 / alpha_k + a @ a)
+        else:
+            e = np.zeros(len(win))
+            e[-1] = res
+            s = M.T @ _cramer(M @ M.T + np.eye(len(win)) / alpha_k, e)
+        x = x - s
+        it.step(tau)
+        plain.step(tau)
+        np.testing.assert_allclose(it.x, x, rtol=1e-11, atol=1e-13)
+        if k == 1:   # the ramp changes the first step (alpha/3 instead of alpha)
+            assert np.linalg.norm(plain.x - it.x) > 1e-3 * np.linalg.norm(x)
+
+
+def test_damping_changed_between_steps():
+    """A caller-driven schedule (end of sec. 3: alpha_k constant, then
+    decaying): each r = 0 single-row step is Sherman-Morrison with the
+    lam = 1/alpha_k in force."""
+    rng = np.random.default_rng(22)
+    A = rng.standard_normal((10, 6))
+    b = rng.standard_normal(10)
+    blocks = [np.array([i]) for i in range(10)]
+    it = _runner(A, b, blocks, 0, 0.5)
+    x = np.zeros(6)
+    for k, tau in enumerate([3, 8, 1, 5, 0, 7], 1):
+        lam_k = 0.5 if k <= 2 else 0.5 * k / 2.0   # alpha_k = 2 alpha / k after two steps
+        it.lam = lam_k
+        a = A[tau]
+        x = x - a * (a @ x - b[tau]) / (lam_k + a @ a)
+        it.step(tau)
+        np.testing.assert_allclose(it.x, x, rtol=1e-11, atol=1e-13)
