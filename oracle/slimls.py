@@ -6,7 +6,9 @@ with C_k = I and alpha_k = 1/lam (sec. 1: C_k = I and r = 0 give damped block
 Kaczmarz, eq. (dbK)).  alpha_k is constant, or ramped up over the first r+1
 steps as in sec. 4.2 (alpha_k = k alpha / (r+1), used in sec. 4.3), which in
 terms of lam is lam_k = lam (r+1) / k for k <= r+1; ``lam`` may also be
-changed between steps (a caller-driven decay of alpha_k, end of sec. 3).  Blocks with negative index are empty,
+changed between steps (a caller-driven decay of alpha_k, end of sec. 3).
+slimTik (sec. 2, eq. (slimTik)) with L = I is the same iteration with a
+Tikhonov term; ``tik_mu`` states the reading of its shift.  Blocks with negative index are empty,
 so M_k grows over the first r steps (sec. 1).
 
 Three algebraically equal ways to form the step s_k = x_{k-1} - x_k:
@@ -27,7 +29,9 @@ Three algebraically equal ways to form the step s_k = x_{k-1} - x_k:
 Pins (tests/test_oracle_*.py): the three forms agree; r = 0 is damped block
 Kaczmarz (eq. dbK); lam -> 0 with one row per block is Kaczmarz (eq. Kacz);
 the ramp's first steps against closed forms for one- and two-row windows
-(Sherman-Morrison, Cramer's rule);
+(Sherman-Morrison, Cramer's rule); slimTik equals plain slimLS on the stacked
+blocks [A_k; (tik/sqrt(M)) I] and, with full memory, reaches the Tikhonov
+solution of eq. (TLS1) after one epoch;
 full memory over one epoch gives the Tikhonov solution at every k (the
 induction of App. A with the damped Hessian); the residual identity after a
 step; consistent data is a fixed point; Theorem 3.1(i) in expectation.
@@ -121,6 +125,52 @@ def step_woodbury(window, res, lam):
     return (g - M.T @ np.linalg.solve(G, M @ g)) / lam
 
 
+# slimTik (sec. 2, eq. (slimTik)) with L = I: slimLS on the stacked problem
+# [A; lam_t I] x ~ [b; 0] (eq. (TLS1)) whose block k is [A_k; (lam_t/sqrt(M)) I].
+# With C_k = I the step is
+#   s = (mu I + M^T M)^{-1} (A_k^T res + tau x_{k-1}),  tau = lam_t^2 / M,
+#   mu = 1/alpha_k + W tau,
+# W the number of blocks in the window (each stacked block adds tau I to
+# M^T M).  The printed equation has r lam_t^2 / M; counting the window's
+# blocks gives W = r + 1 once the window is full (the reading used here).
+
+def tik_mu(lam: float, tik: float, n_blocks: int, W: int) -> tuple[float, float]:
+    """(mu, tau) of the slimTik step for damping lam = 1/alpha_k and window W."""
+    tau = tik * tik / n_blocks
+    return lam + W * tau, tau
+
+
+def step_tik_primal(window, res, x, lam, tik, n_blocks):
+    """eq. (slimTik) literally (L = I): dense n x n solve."""
+    M = _dense(_stack(window))
+    mu, tau = tik_mu(lam, tik, n_blocks, len(window))
+    H = M.T @ M
+    H[np.diag_indices_from(H)] += mu
+    return np.linalg.solve(H, _dense(window[-1]).T @ res + tau * x)
+
+
+def step_tik_dual(window, res, x, lam, tik, n_blocks, chol_max_p=8000, cg_tol=1e-12):
+    """The same step through the p x p Gram system: by Woodbury
+    (mu I + M^T M)^{-1} = (I - M^T (mu I + M M^T)^{-1} M) / mu, so with
+    c = tau / mu,  s = M^T z + c x  and  (M M^T + mu I) z = [0; ...; 0; res] - c M x."""
+    M = _stack(window)
+    mu, tau = tik_mu(lam, tik, n_blocks, len(window))
+    c = tau / mu
+    p = M.shape[0]
+    e = -c * np.asarray(M @ x).reshape(-1)
+    e[p - res.size:] += res
+    if p <= chol_max_p:
+        G = _dense(M @ M.T).astype(np.float64)
+        G[np.diag_indices_from(G)] += mu
+        z = sla.cho_solve(sla.cho_factor(G, lower=True), e)
+        info = {"mode": "chol", "iters": 0, "relres": 0.0}
+    else:
+        z, it, rel = cg(lambda v: M @ (M.T @ v) + mu * v, e, cg_tol)
+        info = {"mode": "cg", "iters": it, "relres": rel}
+    s = np.asarray(M.T @ z).reshape(-1) + c * x
+    return s, z, info
+
+
 @dataclass
 class StepRecord:
     k: int
@@ -155,6 +205,10 @@ class SlimLS:
     x_store: callable = None
     # ramp: alpha_k = k alpha / (r+1) for k <= r+1 (sec. 4.2), else alpha
     ramp: bool = False
+    # slimTik with L = I (eq. (slimTik)): Tikhonov parameter of eq. (TLS1)
+    # (0: plain slimLS) and the number of blocks M
+    tik: float = 0.0
+    n_blocks: int = 0
 
     def lam_at(self, k: int) -> float:
         """Damping 1/alpha_k of the k-th step (1-based)."""
@@ -173,7 +227,14 @@ class SlimLS:
         res = np.asarray(Ak @ xs).reshape(-1) - self.block_data(beta)
         info = {"mode": self.form, "iters": 0}
         lam = self.lam_at(self.k + 1)
-        if self.form == "dual":
+        if self.tik > 0.0:
+            xt = np.asarray(xs, np.float64).reshape(-1)
+            if self.form == "dual":
+                s, _, info = step_tik_dual(mats, res, xt, lam, self.tik, self.n_blocks,
+                                           self.chol_max_p, self.cg_tol)
+            else:
+                s = step_tik_primal(mats, res, xt, lam, self.tik, self.n_blocks)
+        elif self.form == "dual":
             s, _, info = step_dual(mats, res, lam, self.chol_max_p, self.cg_tol)
         elif self.form == "primal":
             s = step_primal(mats, res, lam)
@@ -216,7 +277,7 @@ class Tomo:
     def __init__(self, projector, b: np.ndarray, g: int, r: int, lam: float,
                  x0: np.ndarray | None = None, x_true: np.ndarray | None = None,
                  chol_max_p: int = 8000, cg_tol: float = 1e-12, form: str = "dual",
-                 x_store=None, ramp: bool = False):
+                 x_store=None, ramp: bool = False, tik: float = 0.0):
         self.P = projector
         self.g = g
         self.n_blocks = projector.n_angles // g
@@ -224,7 +285,7 @@ class Tomo:
         x0 = np.zeros(projector.n) if x0 is None else np.asarray(x0, np.float64).reshape(-1)
         xt = None if x_true is None else np.asarray(x_true, np.float64).reshape(-1)
         self.it = SlimLS(self.rows, self.data, r, lam, x0.copy(), xt, form, chol_max_p, cg_tol,
-                         x_store=x_store, ramp=ramp)
+                         x_store=x_store, ramp=ramp, tik=tik, n_blocks=self.n_blocks)
 
     def angles_of(self, beta: int):
         return list(range(beta * self.g, beta * self.g + self.g))

@@ -356,3 +356,47 @@ def test_damping_changed_between_steps():
         x = x - a * (a @ x - b[tau]) / (lam_k + a @ a)
         it.step(tau)
         np.testing.assert_allclose(it.x, x, rtol=1e-11, atol=1e-13)
+
+
+def _stacked_runner(A, b, blocks, r, lam, tik):
+    """Plain slimLS (no Tikhonov term) on the stacked blocks [A_k; (tik/sqrt(M)) I]
+    with data [b_k; 0]: the construction of sec. 2 that defines slimTik."""
+    M, n = len(blocks), A.shape[1]
+    reg = tik / np.sqrt(M) * np.eye(n)
+    return slimls.SlimLS(lambda t: np.vstack([A[blocks[t]], reg]),
+                         lambda t: np.concatenate([b[blocks[t]], np.zeros(n)]),
+                         r, lam, np.zeros(n), None, "primal")
+
+
+@pytest.mark.parametrize("form", ["dual", "primal"])
+@pytest.mark.parametrize("r", [0, 2, 5])
+def test_slimtik_is_slimls_on_the_stacked_system(form, r):
+    """eq. (slimTik) with L = I equals slimLS run on eq. (TLS1)'s stacked rows,
+    window by window (including the first r steps, whose windows hold fewer
+    blocks), so the Tikhonov shift counts the blocks in the window."""
+    A, b, _, blocks = _dense_problem(m=60, n=8, ell=5, seed=31)
+    tik, lam = 0.7, 0.3
+    it = slimls.SlimLS(lambda t: A[blocks[t]], lambda t: b[blocks[t]], r, lam, np.zeros(8),
+                       form=form, tik=tik, n_blocks=len(blocks))
+    ref = _stacked_runner(A, b, blocks, r, lam, tik)
+    for tau in np.random.default_rng(32).integers(0, len(blocks), 20):
+        it.step(tau)
+        ref.step(tau)
+        np.testing.assert_allclose(it.x, ref.x, rtol=1e-10, atol=1e-12)
+
+
+def test_slimtik_full_memory_epoch_reaches_tikhonov():
+    """With the window covering every block (r = M - 1), one epoch without
+    replacement and a vanishing damping lam, the slimLS induction of App. A on
+    the stacked system gives x_M = (A^T A + tik^2 I)^{-1} A^T b, the Tikhonov
+    solution of eq. (TLS1) with L = I (textbook least squares on [A; tik I]).
+    The printed shift r tik^2 / M would stop at (M-1)/M tik^2 instead."""
+    A, b, _, blocks = _dense_problem(m=48, n=10, ell=6, seed=33)
+    M, tik = len(blocks), 0.9
+    it = slimls.SlimLS(lambda t: A[blocks[t]], lambda t: b[blocks[t]], M - 1, 1e-12,
+                       np.zeros(10), tik=tik, n_blocks=M)
+    for tau in sampler.epoch_permutation(M, 0, 34):
+        it.step(tau)
+    x_tik = np.linalg.lstsq(np.vstack([A, tik * np.eye(10)]),
+                            np.concatenate([b, np.zeros(10)]), rcond=None)[0]
+    np.testing.assert_allclose(it.x, x_tik, rtol=1e-9, atol=1e-11)
