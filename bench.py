@@ -67,13 +67,13 @@ PEAK_FP64_TFLOPS = 78.6
 # line reports traffic as null.
 PMC_TRAFFIC = {
     "source": "paper_1912_07962_amd/csrc/project.hip",
-    "sha256": "f8ea58a12f8a2e55dae482669e1d0fea65ff61f7df858d1d7d4553d5e46339fa",
+    "sha256": "e681cb313f5c9ed48a8def7615ad46ae97c08e5bc76fa1265af95ae19b21578d",
     "fetch_scale": 2.0,
     "write_scale": 1.0,
     # instance -> (FETCH_SIZE, WRITE_SIZE) KiB per dispatch
-    "kib": {"cg_forward/2": (6232.8, 1992.8), "cg_forward/3": (6250.6, 2989.1),
-            "cg_forward/4": (4211.5, 3984.8), "cg_forward/6": (5401.0, 5479.7),
-            "cg_forward/8": (4274.5, 7969.5), "cg_back/1": (3088.2, 8192.8)},
+    "kib": {"cg_forward/2": (6232.2, 1992.8), "cg_forward/3": (6247.1, 2989.1),
+            "cg_forward/4": (4217.5, 3984.8), "cg_forward/6": (5399.0, 5479.7),
+            "cg_forward/8": (4281.5, 7969.5), "cg_back/1": (3097.1, 8192.8)},
 }
 
 

@@ -85,6 +85,16 @@ typedef struct {
                            alpha_k = k alpha / (r+1) for the first r+1 steps,
                            i.e. step k uses lambda (r+1) / k while k <= r and
                            lambda after; 0: constant lambda                */
+  double tikhonov;      /* > 0: slimTik (sec. 2, eq. (slimTik)) with L = I,
+                           the Tikhonov parameter of eq. (TLS1): each step
+                           solves ((lambda_k + W t^2/M) I + M^T M) s =
+                           A_k^T res + (t^2/M) x_{k-1}, W the blocks in the
+                           window, M = n_angles / g (the printed equation
+                           has r t^2/M; W = r+1 once the window is full is
+                           what slimLS on the stacked rows [A_k; t/sqrt(M) I]
+                           gives).  Costs one more forward projection of the
+                           window per step.  FP32 precision only.
+                           0: plain slimLS                                  */
 } slim_opts;
 
 typedef struct {
@@ -107,7 +117,7 @@ typedef struct {
 
 /* Fill *opts with defaults: g = 1, FP32, AUTO, chol_max_p = 8192,
  * pcg_max_iter = 1000, pcg_tol = 1e-6, check_every = 1, seed = 0, NULL stream,
- * use_graph = 1, damping_ramp = 0. */
+ * use_graph = 1, damping_ramp = 0, tikhonov = 0. */
 slim_status slim_default_opts(slim_opts* opts);
 
 /* Create a context (paper sec. 1 setup, sec. 4.3 geometry).

@@ -551,7 +551,7 @@ __global__ __launch_bounds__(256) void back_kernel(
     const VT* __restrict__ v, size_t v_stride, float* __restrict__ out, float* __restrict__ x,
     float* __restrict__ xT, const float* __restrict__ x_true, size_t img_stride,
     double* __restrict__ partials, int mode, const int* __restrict__ stop, int stop_stride,
-    uint16_t* __restrict__ xs, uint16_t* __restrict__ xsT) {
+    uint16_t* __restrict__ xs, uint16_t* __restrict__ xsT, float shrink) {
   typedef typename Lane<BT>::T LT;
   // A lane's pixels are columns tx + 16 q: for each q the 16 lanes of a row
   // take consecutive columns, so a wave's LDS reads hit nearby rays (fewer
@@ -751,10 +751,12 @@ __global__ __launch_bounds__(256) void back_kernel(
         for (int q = 0; q < kBPX; ++q) {
           if (jb + kQ * q < N) {
             const size_t p = so + prow + kQ * q;
-            xn[q] = x[p] - s[q][b];
+            const float xo = x[p];
+            const float sq = fmaf(shrink, xo, s[q][b]);
+            xn[q] = xo - sq;
             x[p] = xn[q];
             if (xs) xs[p] = f2bf(xn[q]);
-            nrm[b][0] += (double)s[q][b] * (double)s[q][b];
+            nrm[b][0] += (double)sq * (double)sq;
             nrm[b][1] += (double)xn[q] * (double)xn[q];
             if (x_true) {
               const double e = (double)xn[q] - (double)x_true[p];
@@ -1045,7 +1047,7 @@ template <typename VT, int BT>
 static void launch_back_t(const BackArgs& a, const VT* v, dim3 grid, hipStream_t st) {
   hipLaunchKernelGGL((back_kernel<VT, BT>), grid, dim3(256), 0, st, a.geom, a.N, a.R, *a.ids, a.B, v,
                      a.v_stride, a.out, a.x, a.xT, a.x_true, a.img_stride, a.partials, a.mode,
-                     a.stop, a.stop_stride, a.xs, a.xsT);
+                     a.stop, a.stop_stride, a.xs, a.xsT, a.shrink);
 }
 
 template <typename VT>

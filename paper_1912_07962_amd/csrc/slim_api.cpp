@@ -109,6 +109,8 @@ struct slim_ctx {
   double* d_cholwork = nullptr;// inverse of a diagonal block (Cholesky scratch)
   double* d_ysolve = nullptr;  // [B][pmax] triangular-solve scratch
   double* d_z = nullptr;       // [B][pmax]
+  double* d_mx = nullptr;      // [B][pmax] M x of the window (slimTik)
+  double* d_rhs = nullptr;     // [B][pmax] Gram right-hand sides (slimTik)
   int* d_info = nullptr;
   double* d_partials = nullptr;
   double* d_norms = nullptr;   // [B][3]
@@ -146,6 +148,8 @@ struct slim_ctx {
     (void)hipFree(d_cholwork);
     (void)hipFree(d_ysolve);
     (void)hipFree(d_z);
+    (void)hipFree(d_mx);
+    (void)hipFree(d_rhs);
     (void)hipFree(d_info);
     (void)hipFree(d_partials);
     (void)hipFree(d_norms);
@@ -246,8 +250,10 @@ FwdArgs base_fwd(const slim_ctx* c, const AngleList* l) {
   return a;
 }
 
-// Gram mode: z = G^{-1} [0; res] for every slice, G shared by the slices.
-slim_status gram_solve_chol(slim_ctx* c, int new_slot, double lam) {
+// Gram mode: z = G^{-1} e for every slice, G shared by the slices, e the
+// last nres entries rhs (stride rhs_stride) after zeros.
+slim_status gram_solve_chol(slim_ctx* c, int new_slot, double lam, const double* rhs,
+                            size_t rhs_stride, int nres) {
   const int64_t ell = c->ell;
   const int W = (int)c->window.size();
   const int64_t p = (int64_t)W * ell;
@@ -280,7 +286,7 @@ slim_status gram_solve_chol(slim_ctx* c, int new_slot, double lam) {
   if (c->prof.on) HIP_TRY(c->prof.begin(K_CHOL, c->st));
   HIP_TRY(hipMemsetAsync(c->d_info, 0, sizeof(int), c->st));
   HIP_TRY(launch_cholesky(c->d_G, p, (int)p, c->d_info, c->d_cholwork, c->st));
-  HIP_TRY(launch_chol_solve(c->d_G, p, (int)p, (int)ell, c->d_cholwork, c->d_res64, ell, c->d_z, c->pmax,
+  HIP_TRY(launch_chol_solve(c->d_G, p, (int)p, nres, c->d_cholwork, rhs, rhs_stride, c->d_z, c->pmax,
                             c->d_ysolve, c->B, c->st));
   if (c->prof.on) HIP_TRY(c->prof.end(c->st));
   return SLIM_OK;
@@ -292,7 +298,8 @@ slim_status gram_solve_chol(slim_ctx* c, int new_slot, double lam) {
 struct StepState {
   AngleList blk, win;
   int slot = 0;
-  double lam = 0.0;  // damping of this step
+  double lam = 0.0;  // diagonal shift of this step's Gram system
+  float shrink = 0.f;  // slimTik: c of s = M^T z + c x
   bool pcg = false;
   PcgRun run;
 };
@@ -314,7 +321,7 @@ slim_status step_begin(slim_ctx* c, const int32_t* ids, StepState& ss) {
   }
   {
     slim_status s = ensure_fpart(c, ss.blk);
-    if (s == SLIM_OK && c->mode == SLIM_GRAM_PCG) s = ensure_fpart(c, ss.win);
+    if (s == SLIM_OK && (c->mode == SLIM_GRAM_PCG || c->o.tikhonov > 0.0)) s = ensure_fpart(c, ss.win);
     if (s != SLIM_OK) return s;
   }
   // 1. residual of the new block, all slices in one launch
@@ -332,11 +339,38 @@ slim_status step_begin(slim_ctx* c, const int32_t* ids, StepState& ss) {
     HIP_TRY(launch_forward(fa, c->st));
   }
   if (c->prof.on) HIP_TRY(c->prof.end(c->st));
+  // slimTik (eq. (slimTik), L = I): shift mu = lambda_k + W tau with
+  // tau = tik^2 / M, right-hand side [0; res] - (tau / mu) M x
+  const double* rhs = c->d_res64;
+  size_t rhs_stride = ell;
+  int nres = (int)ell;
+  if (c->o.tikhonov > 0.0) {
+    const int W = (int)c->window.size();
+    const int p = (int)(W * ell);
+    const double tau = c->o.tikhonov * c->o.tikhonov / (double)(c->n_angles / c->g);
+    const double mu = ss.lam + W * tau;
+    const double cs = tau / mu;
+    ss.lam = mu;
+    ss.shrink = (float)cs;
+    FwdArgs fa = base_fwd(c, &ss.win);
+    fa.img = c->x;
+    fa.imgT = c->d_xT;
+    fa.out64 = c->d_mx;
+    fa.out_stride = c->pmax;
+    if (c->prof.on) HIP_TRY(c->prof.begin(K_RESID, c->st));
+    HIP_TRY(launch_forward(fa, c->st));
+    HIP_TRY(launch_tik_rhs(c->d_mx, c->pmax, c->d_res64, ell, p, (int)ell, cs, c->d_rhs, c->pmax,
+                           c->B, c->st));
+    if (c->prof.on) HIP_TRY(c->prof.end(c->st));
+    rhs = c->d_rhs;
+    rhs_stride = c->pmax;
+    nres = p;
+  }
   // 2. Gram system: solved here (Cholesky) or started (CG)
   ss.pcg = c->mode == SLIM_GRAM_PCG;
-  if (!ss.pcg) return gram_solve_chol(c, ss.slot, ss.lam);
+  if (!ss.pcg) return gram_solve_chol(c, ss.slot, ss.lam, rhs, rhs_stride, nres);
   hipError_t e = pcg_begin(ss.run, c->pcg, c->d_geom, c->h_geom.data(), c->d_fpart, c->N, c->R,
-                           c->B, ss.win, c->tune_for(ss.win.n), ss.lam, c->d_res64, ell, (int)ell, c->d_z,
+                           c->B, ss.win, c->tune_for(ss.win.n), ss.lam, rhs, rhs_stride, nres, c->d_z,
                            c->pmax, c->o.pcg_tol, c->o.pcg_max_iter, &c->prof, c->st);
   if (e != hipSuccess) return fail(SLIM_EDEVICE, std::string("pcg: ") + hipGetErrorString(e));
   return SLIM_OK;
@@ -370,6 +404,7 @@ slim_status step_end(slim_ctx* c, StepState& ss, slim_step_info* info) {
     ba.mode = 1;
     ba.xs = c->bf16() ? c->d_xs : nullptr;
     ba.xsT = c->bf16() ? c->d_xsT : nullptr;
+    ba.shrink = ss.shrink;
     HIP_TRY(launch_back(ba, c->st));
     HIP_TRY(launch_reduce3(c->d_partials, nwg, c->B, c->d_norms, c->st));
   }
@@ -453,6 +488,7 @@ slim_status slim_default_opts(slim_opts* o) {
   o->stream = nullptr;
   o->use_graph = 1;
   o->damping_ramp = 0;
+  o->tikhonov = 0.0;
   return SLIM_OK;
 }
 
@@ -479,6 +515,8 @@ slim_status slim_init(slim_ctx** out, const slim_grid* grid, int n_angles, const
   if (o.gram_mode < SLIM_GRAM_AUTO || o.gram_mode > SLIM_GRAM_PCG) return fail(SLIM_EINVAL, "unknown gram_mode");
   if (o.check_every < 1) return fail(SLIM_EINVAL, "check_every must be >= 1");
   if (o.damping_ramp != 0 && o.damping_ramp != 1) return fail(SLIM_EINVAL, "damping_ramp must be 0 or 1");
+  if (!(o.tikhonov >= 0.0) || !std::isfinite(o.tikhonov)) return fail(SLIM_EINVAL, "tikhonov must be >= 0 and finite");
+  if (o.tikhonov > 0.0 && o.precision != SLIM_PREC_FP32) return fail(SLIM_EINVAL, "tikhonov needs FP32 precision");
   if (o.pcg_max_iter < 1 || !(o.pcg_tol > 0.0)) return fail(SLIM_EINVAL, "bad CG settings");
   if (angles) {
     for (int a = 0; a < n_angles; ++a)
@@ -530,6 +568,10 @@ slim_status slim_init(slim_ctx** out, const slim_grid* grid, int n_angles, const
   if ((e = dalloc(&c->d_geom, n_angles)) != hipSuccess) return oom(e);
   if ((e = dalloc(&c->d_res64, (size_t)c->B * ell)) != hipSuccess) return oom(e);
   if ((e = dalloc(&c->d_z, (size_t)c->B * pmax)) != hipSuccess) return oom(e);
+  if (o.tikhonov > 0.0) {
+    if ((e = dalloc(&c->d_mx, (size_t)c->B * pmax)) != hipSuccess) return oom(e);
+    if ((e = dalloc(&c->d_rhs, (size_t)c->B * pmax)) != hipSuccess) return oom(e);
+  }
   if ((e = dalloc(&c->d_info, 1)) != hipSuccess) return oom(e);
   if ((e = dalloc(&c->d_partials, 3 * (size_t)c->B * back_num_workgroups(c->N))) != hipSuccess) return oom(e);
   if ((e = dalloc(&c->d_norms, 3 * (size_t)c->B)) != hipSuccess) return oom(e);

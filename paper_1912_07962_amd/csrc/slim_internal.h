@@ -152,9 +152,10 @@ size_t forward_partial_floats(const AngleGeom* h_geom, int N, int R, const Angle
 
 // Back-projection of B slices: s[slice][pix] = sum_a sum_t A[(ids[a],t),pix] v[slice][a][t]
 // with v float (v32) or double (v64).  mode 0: out = s (and out^T into xT).
-// mode 1: x -= s in place, optional transposed copy xT, optional bf16 copies
-// xs, xsT (round to nearest even), and per-workgroup float64 partial norms
-// (||s||^2, ||x_new||^2, ||x_new - x_true||^2) into
+// mode 1: s += shrink * x (the Tikhonov term of eq. (slimTik) with L = I;
+// shrink = 0 otherwise), x -= s in place, optional transposed copy xT,
+// optional bf16 copies xs, xsT (round to nearest even), and per-workgroup
+// float64 partial norms (||s||^2, ||x_new||^2, ||x_new - x_true||^2) into
 // partials[(slice * back_num_workgroups(N) + wg) * 3 + k].
 struct BackArgs {
   ProjTune tune;
@@ -175,6 +176,7 @@ struct BackArgs {
   int stop_stride = 0;
   uint16_t* xs = nullptr;
   uint16_t* xsT = nullptr;
+  float shrink = 0.f;
 };
 hipError_t launch_back(const BackArgs& a, hipStream_t st);
 int back_num_workgroups(int N);
@@ -224,6 +226,12 @@ hipError_t launch_chol_solve(const double* L, int64_t ld, int p, int nr, const d
 // slice stride n_angles * R).
 hipError_t launch_gather_rows(const void* b, int b_bf16, int n_angles, int R, int B,
                               const AngleList& ids, float* out, hipStream_t st);
+
+// slimTik right-hand sides for B slices: rhs[j] = -c mx[j] for j < p, plus
+// res[j - (p - nres)] for the last nres entries (eq. (slimTik), L = I).
+hipError_t launch_tik_rhs(const double* mx, size_t mx_stride, const double* res,
+                          size_t res_stride, int p, int nres, double c, double* rhs,
+                          size_t rhs_stride, int B, hipStream_t st);
 
 // Record msg as the library's last error message and return s.
 slim_status set_error(slim_status s, const std::string& msg);

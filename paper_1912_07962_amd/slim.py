@@ -40,7 +40,7 @@ class Opts(ctypes.Structure):
                 ("pcg_max_iter", ctypes.c_int), ("pcg_tol", ctypes.c_double),
                 ("check_every", ctypes.c_int), ("seed", ctypes.c_uint64),
                 ("stream", ctypes.c_void_p), ("use_graph", ctypes.c_int),
-                ("damping_ramp", ctypes.c_int)]
+                ("damping_ramp", ctypes.c_int), ("tikhonov", ctypes.c_double)]
 
 
 class StepInfo(ctypes.Structure):
@@ -169,7 +169,7 @@ class Slim:
                  precision: str = "fp32", gram_mode: str = "auto", chol_max_p: int = 8192,
                  pcg_max_iter: int = 1000, pcg_tol: float = 1e-6, check_every: int = 1,
                  seed: int = 0, angles=None, stream=None, use_graph: bool = True,
-                 damping_ramp: bool = False):
+                 damping_ramp: bool = False, tikhonov: float = 0.0):
         lib = load()
         if n_rays is None:
             n_rays = 2 * int(np.floor(N / np.sqrt(2.0))) + 1
@@ -188,6 +188,7 @@ class Slim:
         o.seed = int(seed) & ((1 << 64) - 1)
         o.use_graph = int(bool(use_graph))
         o.damping_ramp = int(bool(damping_ramp))
+        o.tikhonov = float(tikhonov)
         if stream is None and torch.cuda.is_available():
             stream = torch.cuda.current_stream()
         o.stream = ctypes.c_void_p(stream.cuda_stream if stream is not None else 0)
@@ -208,6 +209,10 @@ class Slim:
         return torch.bfloat16 if self.precision == "bf16" else torch.float32
 
     def set_data(self, b, x, x_true=None):
+        nb, nx = self.B * self.n_angles * self.R, self.B * self.N * self.N
+        for t, n, name in ((b, nb, "b"), (x, nx, "x"), (x_true, nx, "x_true")):
+            if t is not None and isinstance(t, torch.Tensor) and t.numel() != n:
+                raise ValueError(f"{name} has {t.numel()} elements, expected {n}")
         self._keep = [b, x, x_true]
         _check(load().slim_set_data(self._h, _ptr(b, self._b_dtype(), "b"),
                                     _ptr(x, torch.float32, "x"),
@@ -365,6 +370,7 @@ def init_error(**kw) -> int:
     o.gram_mode = kw.get("gram_mode", 0)
     o.check_every = kw.get("check_every", 1)
     o.damping_ramp = kw.get("damping_ramp", 0)
+    o.tikhonov = kw.get("tikhonov", 0.0)
     g = Grid(N, kw.get("n_slices", 1))
     h = ctypes.c_void_p()
     st = lib.slim_init(ctypes.byref(h), ctypes.byref(g), kw.get("n_angles", 90), None,

@@ -24,7 +24,7 @@ def test_strerror_and_default_opts():
     o = slim.Opts()
     assert lib.slim_default_opts(ctypes.byref(o)) == 0
     assert o.angles_per_block == 1 and o.chol_max_p == 8192 and o.pcg_tol == 1e-6
-    assert o.use_graph == 1 and o.damping_ramp == 0
+    assert o.use_graph == 1 and o.damping_ramp == 0 and o.tikhonov == 0.0
     assert lib.slim_default_opts(None) == slim.SLIM_EINVAL
 
 
@@ -33,7 +33,8 @@ def test_strerror_and_default_opts():
     dict(lam=0.0), dict(lam=-1.0), dict(lam=float("nan")), dict(lam=float("inf")),
     dict(angles_per_block=7), dict(angles_per_block=0), dict(precision=5), dict(gram_mode=9),
     dict(check_every=0), dict(r=200, angles_per_block=2), dict(damping_ramp=2),
-    dict(damping_ramp=-1),
+    dict(damping_ramp=-1), dict(tikhonov=-1.0), dict(tikhonov=float("nan")),
+    dict(tikhonov=float("inf")), dict(tikhonov=0.5, precision=1),
     dict(N=512, n_rays=725, n_angles=360, angles_per_block=4, r=8, gram_mode=1),  # p > 8192
 ])
 def test_init_rejects_bad_arguments(kw):
