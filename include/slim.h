@@ -135,12 +135,15 @@ slim_status slim_init(slim_ctx** out, const slim_grid* grid, int n_angles, const
 
 /* Bind the data of the problem b = A x_true + eps (sec. 1, eq. (inverseproblem)).
  *  b       device sinogram [n_slices][n_angles][n_rays] (float32, or bf16 bits
- *          when precision is SLIM_PREC_BF16)
+ *          when precision is SLIM_PREC_BF16), or NULL for streaming data: each
+ *          block's rows then arrive with its step (slim_step_data) and are kept
+ *          in a sinogram the library allocates (rows not yet delivered are
+ *          zero, also for slim_data_backprojection and slim_warmstart)
  *  x       device image [n_slices][N][N] float32: the iterate, read and
  *          overwritten in place by slim_step / slim_solve
  *  x_true  device [n_slices][N][N] float32 or NULL; enables err_norm
  * Resets the iteration (k = 0, empty memory window).
- * Errors: SLIM_EINVAL on NULL b or x. */
+ * Errors: SLIM_EINVAL on NULL x; SLIM_ENOMEM, SLIM_EDEVICE (streaming buffers). */
 slim_status slim_set_data(slim_ctx* ctx, const void* b, void* x, const float* x_true);
 
 /* One slimLS iteration (eq. (ram)) with the sampled block A_k = rows of the
@@ -151,6 +154,24 @@ slim_status slim_set_data(slim_ctx* ctx, const void* b, void* x, const float* x_
  * Errors: SLIM_EINVAL (bad ids), SLIM_ESTATE (no data), SLIM_ENUMERIC,
  * SLIM_ENOTCONV (CG cap reached; the step is still applied), SLIM_EDEVICE. */
 slim_status slim_step(slim_ctx* ctx, const int32_t* angle_ids, int n_ids, slim_step_info* info);
+
+/* slim_step for streaming data (data bound with b = NULL).  The method needs
+ * a block's data only when the block is sampled (sec. 1, eq. (ram): only b_k
+ * enters step k), so the caller passes it with the step:
+ *  b_block  [n_slices][n_ids][n_rays] float32 (bf16 bits when SLIM_PREC_BF16),
+ *           the rows of angle_ids in that order; host or device memory.  Device
+ *           memory is read in the order of the context's stream; host memory is
+ *           copied on a stream of the library's own (default priority) into one
+ *           of two staging buffers, so the copy of step k+1 overlaps step k when
+ *           the caller does not read step k back (info == NULL); use pinned
+ *           host memory for the copy to run asynchronously, and keep b_block
+ *           unchanged until the step's results are read or the context's stream
+ *           is synchronised.
+ * Errors: as slim_step; SLIM_EINVAL on NULL b_block; SLIM_ESTATE unless the
+ * data were bound with b = NULL (and slim_step returns SLIM_ESTATE on such a
+ * context). */
+slim_status slim_step_data(slim_ctx* ctx, const int32_t* angle_ids, int n_ids,
+                           const void* b_block, slim_step_info* info);
 
 /* Set the damping lambda = 1/alpha used by the following steps (eq. (B_k)
  * with C_k = I).  The end of sec. 3 suggests a constant alpha_k for fast

@@ -132,6 +132,18 @@ struct slim_ctx {
     return it != tune_by_n.end() ? it->second : tune;
   }
 
+  // streaming data (slim_set_data with b == NULL): blocks arrive with
+  // slim_step_data, are copied on copy_st into one of two staging buffers and
+  // placed into d_bstream on the step's stream
+  bool streaming = false;
+  void* d_bstream = nullptr;              // [B][n_angles][R] sinogram
+  void* d_stage[2] = {nullptr, nullptr};  // [B][g][R] delivered blocks
+  hipStream_t copy_st = nullptr;
+  hipEvent_t ev_copied[2] = {nullptr, nullptr};
+  hipEvent_t ev_used[2] = {nullptr, nullptr};
+  bool used_pending[2] = {false, false};
+  int stage_next = 0;
+
   double* h_norms = nullptr;   // pinned [B][3]
   bool norms_valid = false;    // h_norms holds the last step read back
   int* h_info = nullptr;       // pinned
@@ -163,6 +175,15 @@ struct slim_ctx {
     prof.release();
     if (h_norms) (void)hipHostFree(h_norms);
     if (h_info) (void)hipHostFree(h_info);
+    if (copy_st) (void)hipStreamSynchronize(copy_st);
+    (void)hipFree(d_bstream);
+    (void)hipFree(d_stage[0]);
+    (void)hipFree(d_stage[1]);
+    for (int i = 0; i < 2; ++i) {
+      if (ev_copied[i]) (void)hipEventDestroy(ev_copied[i]);
+      if (ev_used[i]) (void)hipEventDestroy(ev_used[i]);
+    }
+    if (copy_st) (void)hipStreamDestroy(copy_st);
   }
 
   size_t img_elems() const { return (size_t)N * N; }
@@ -600,9 +621,51 @@ slim_status slim_init(slim_ctx** out, const slim_grid* grid, int n_angles, const
   return SLIM_OK;
 }
 
+// Buffers, stream and events of streaming mode, created on first use.
+// Device (or managed) memory: its producer may still be running on the
+// context's stream, so such a block is read in that stream's order.
+static bool on_device(const void* p) {
+  hipPointerAttribute_t a;
+  if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+    (void)hipGetLastError();  // unregistered host memory: clear the query's error
+    return false;
+  }
+  return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
+}
+
+static slim_status ensure_streaming(slim_ctx* c) {
+  if (c->d_bstream) return SLIM_OK;
+  const size_t esz = c->bf16() ? 2 : 4;
+  hipError_t e;
+  if ((e = hipMalloc(&c->d_bstream, esz * c->B * c->n_angles * c->R)) != hipSuccess ||
+      (e = hipMalloc(&c->d_stage[0], esz * c->B * c->g * c->R)) != hipSuccess ||
+      (e = hipMalloc(&c->d_stage[1], esz * c->B * c->g * c->R)) != hipSuccess) {
+    (void)hipFree(c->d_bstream);
+    (void)hipFree(c->d_stage[0]);
+    (void)hipFree(c->d_stage[1]);
+    c->d_bstream = c->d_stage[0] = c->d_stage[1] = nullptr;
+    return fail(e == hipErrorOutOfMemory ? SLIM_ENOMEM : SLIM_EDEVICE,
+                std::string("streaming buffers: ") + hipGetErrorString(e));
+  }
+  HIP_TRY(hipStreamCreateWithFlags(&c->copy_st, hipStreamNonBlocking));
+  for (int i = 0; i < 2; ++i) {
+    HIP_TRY(hipEventCreateWithFlags(&c->ev_copied[i], hipEventDisableTiming));
+    HIP_TRY(hipEventCreateWithFlags(&c->ev_used[i], hipEventDisableTiming));
+  }
+  return SLIM_OK;
+}
+
 slim_status slim_set_data(slim_ctx* c, const void* b, void* x, const float* x_true) {
   if (!c) return fail(SLIM_EINVAL, "ctx is NULL");
-  if (!b || !x) return fail(SLIM_EINVAL, "b and x must be non-NULL");
+  if (!x) return fail(SLIM_EINVAL, "x must be non-NULL");
+  c->streaming = b == nullptr;
+  if (c->streaming) {
+    slim_status s = ensure_streaming(c);
+    if (s != SLIM_OK) return s;
+    const size_t esz = c->bf16() ? 2 : 4;
+    HIP_TRY(hipMemsetAsync(c->d_bstream, 0, esz * c->B * c->n_angles * c->R, c->st));
+    b = c->d_bstream;
+  }
   c->b = b;
   c->x = (float*)x;
   c->x_true = x_true;
@@ -629,6 +692,38 @@ slim_status slim_step(slim_ctx* c, const int32_t* ids, int n_ids, slim_step_info
   slim_status s = check_ids(c, ids, n_ids, false);
   if (s != SLIM_OK) return s;
   if (!c->bound) return fail(SLIM_ESTATE, "no data bound (slim_set_data)");
+  if (c->streaming) return fail(SLIM_ESTATE, "streaming context: pass each block's data to slim_step_data");
+  return do_step(c, ids, info);
+}
+
+slim_status slim_step_data(slim_ctx* c, const int32_t* ids, int n_ids, const void* b_block,
+                           slim_step_info* info) {
+  if (!c) return fail(SLIM_EINVAL, "ctx is NULL");
+  if (n_ids != c->g) return fail(SLIM_EINVAL, "n_ids must equal angles_per_block");
+  if (!b_block) return fail(SLIM_EINVAL, "b_block is NULL");
+  slim_status s = check_ids(c, ids, n_ids, false);
+  if (s != SLIM_OK) return s;
+  if (!c->bound || !c->streaming)
+    return fail(SLIM_ESTATE, "no streaming data bound (slim_set_data with b = NULL)");
+  const AngleList l = make_list(ids, c->g);
+  if (on_device(b_block)) {  // placed directly, in the context stream's order
+    HIP_TRY(launch_scatter_rows(b_block, c->bf16() ? 1 : 0, c->n_angles, c->R, c->B, l,
+                                c->d_bstream, c->st));
+    return do_step(c, ids, info);
+  }
+  const int k = c->stage_next;
+  c->stage_next ^= 1;
+  const size_t bytes = (size_t)(c->bf16() ? 2 : 4) * c->B * c->g * c->R;
+  // the staging buffer is free once the step that used it two calls ago
+  // has placed its rows
+  if (c->used_pending[k]) HIP_TRY(hipStreamWaitEvent(c->copy_st, c->ev_used[k], 0));
+  HIP_TRY(hipMemcpyAsync(c->d_stage[k], b_block, bytes, hipMemcpyHostToDevice, c->copy_st));
+  HIP_TRY(hipEventRecord(c->ev_copied[k], c->copy_st));
+  HIP_TRY(hipStreamWaitEvent(c->st, c->ev_copied[k], 0));
+  HIP_TRY(launch_scatter_rows(c->d_stage[k], c->bf16() ? 1 : 0, c->n_angles, c->R, c->B, l,
+                              c->d_bstream, c->st));
+  HIP_TRY(hipEventRecord(c->ev_used[k], c->st));
+  c->used_pending[k] = true;
   return do_step(c, ids, info);
 }
 
@@ -637,6 +732,7 @@ slim_status slim_solve(slim_ctx* c, const void* b, void* x, const float* x_true,
   if (!c) return fail(SLIM_EINVAL, "ctx is NULL");
   if (max_epochs < 1) return fail(SLIM_EINVAL, "max_epochs must be >= 1");
   if (!std::isfinite(tol)) return fail(SLIM_EINVAL, "tol must be finite");
+  if (!b) return fail(SLIM_EINVAL, "b must be non-NULL");
   slim_status s = slim_set_data(c, b, x, x_true);
   if (s != SLIM_OK) return s;
   const int M = c->n_angles / c->g;

@@ -233,6 +233,11 @@ hipError_t launch_tik_rhs(const double* mx, size_t mx_stride, const double* res,
                           size_t res_stride, int p, int nres, double c, double* rhs,
                           size_t rhs_stride, int B, hipStream_t st);
 
+// b[s][ids[i]][t] = in[s][i][t] for B slices (float32, or bf16 bits when
+// bf16): a delivered block's rows placed into a [B][n_angles][R] sinogram.
+hipError_t launch_scatter_rows(const void* in, int bf16, int n_angles, int R, int B,
+                               const AngleList& ids, void* b, hipStream_t st);
+
 // Record msg as the library's last error message and return s.
 slim_status set_error(slim_status s, const std::string& msg);
 

@@ -92,6 +92,7 @@ def load() -> ctypes.CDLL:
         "slim_set_data": (I, [P, P, P, P]),
         "slim_step": (I, [P, i32p, I, ctypes.POINTER(StepInfo)]),
         "slim_set_lambda": (I, [P, D]),
+        "slim_step_data": (I, [P, i32p, I, P, ctypes.POINTER(StepInfo)]),
         "slim_solve": (I, [P, P, P, P, D, I, ctypes.POINTER(SolveInfo)]),
         "slim_project": (I, [P, i32p, I, P, P]),
         "slim_backproject": (I, [P, i32p, I, P, P]),
@@ -209,6 +210,7 @@ class Slim:
         return torch.bfloat16 if self.precision == "bf16" else torch.float32
 
     def set_data(self, b, x, x_true=None):
+        """Bind b (None: streaming data, see step_data), x and x_true."""
         nb, nx = self.B * self.n_angles * self.R, self.B * self.N * self.N
         for t, n, name in ((b, nb, "b"), (x, nx, "x"), (x_true, nx, "x_true")):
             if t is not None and isinstance(t, torch.Tensor) and t.numel() != n:
@@ -224,6 +226,27 @@ class Slim:
         _check(load().slim_step(self._h, p, n, ctypes.byref(info) if read else None))
         if not read:
             return None
+        return {f: getattr(info, f) for f, _ in StepInfo._fields_}
+
+    def step_data(self, angle_ids, b_block, read: bool = True) -> dict | None:
+        """One step with the block's data [n_slices][len(ids)][R] (a contiguous
+        tensor on the GPU or in host memory, pinned for an asynchronous copy)."""
+        a, p, n = _ids(angle_ids)
+        if not isinstance(b_block, torch.Tensor) or not b_block.is_contiguous():
+            raise ValueError("b_block must be a contiguous torch tensor")
+        if b_block.dtype != self._b_dtype():
+            raise TypeError(f"b_block must be {self._b_dtype()}")
+        if b_block.numel() != self.B * n * self.R:
+            raise ValueError(f"b_block has {b_block.numel()} elements, expected {self.B * n * self.R}")
+        # the copy may still be pending after an unread step: hold every block
+        # until a step is read back (which synchronises the stream)
+        self._blocks = getattr(self, "_blocks", []) + [b_block]
+        info = StepInfo()
+        _check(load().slim_step_data(self._h, p, n, ctypes.c_void_p(b_block.data_ptr()),
+                                     ctypes.byref(info) if read else None))
+        if not read:
+            return None
+        self._blocks = []
         return {f: getattr(info, f) for f, _ in StepInfo._fields_}
 
     def set_lambda(self, lam: float):
