@@ -287,9 +287,10 @@ typedef struct {
  * that size.  n_ids = 0 tunes the
  * CG workload -- a window of (r+1) blocks of angles_per_block angles spread
  * over [0, pi) -- and also makes its shape the default for every other size;
- * n_ids > 0 (at most min(256, n_angles)) tunes n_ids angles spread over
- * [0, pi), e.g. angles_per_block for the residual and single-block
- * projections.  Results are cached per (N, n_slices, n_rays, list size) for
+ * n_ids > 0 (at most min(256, n_angles)) tunes a block of n_ids adjacent
+ * angles (e.g. angles_per_block, for the residual and single-block
+ * projections), scored by the sum of its times from angle 0 (row-stepping)
+ * and from angle n_angles/2 (column-stepping) when 2 n_ids <= n_angles.  Results are cached per (N, n_slices, n_rays, list size) for
  * the process; force != 0 measures again.  Uses temporary device memory of
  * about 2 images and the list's rays per slice.  info may be NULL.
  * Errors: SLIM_EINVAL, SLIM_ENOMEM, SLIM_EDEVICE. */

@@ -1024,8 +1024,10 @@ slim_status slim_autotune(slim_ctx* c, int n_ids, int force, slim_tune_info* inf
   if (!c) return fail(SLIM_EINVAL, "ctx is NULL");
   if (n_ids < 0 || n_ids > std::min(kMaxList, c->n_angles))
     return fail(SLIM_EINVAL, "n_ids must be in [0, min(256, n_angles)]");
-  AngleList win;
-  win.n = 0;
+  AngleList lists[2];
+  int nlists = 1;
+  lists[0].n = lists[1].n = 0;
+  AngleList& win = lists[0];
   const bool window = n_ids == 0;
   if (window) {  // the CG window: r+1 blocks spread over [0, pi)
     const int M = c->n_angles / c->g;
@@ -1034,10 +1036,13 @@ slim_status slim_autotune(slim_ctx* c, int n_ids, int force, slim_tune_info* inf
       const int beta = (int)((int64_t)j * M / nblk);
       for (int a = 0; a < c->g; ++a) win.id[win.n++] = beta * c->g + a;
     }
-  } else {       // n_ids angles spread over [0, pi)
-    for (int j = 0; j < n_ids; ++j) win.id[win.n++] = (int)((int64_t)j * c->n_angles / n_ids);
+  } else {       // a block of n_ids adjacent angles from 0 and from pi/2
+    nlists = 2 * n_ids <= c->n_angles ? 2 : 1;
+    for (int L = 0; L < nlists; ++L)
+      for (int j = 0; j < n_ids; ++j) lists[L].id[lists[L].n++] = L * (c->n_angles / 2) + j;
   }
-  for (int i = win.n; i < kMaxList; ++i) win.id[i] = 0;
+  for (int L = 0; L < 2; ++L)
+    for (int i = lists[L].n; i < kMaxList; ++i) lists[L].id[i] = 0;
   auto keep = [&](const ProjTune& t) {
     c->tune_by_n[win.n] = t;
     if (window) c->tune = t;
@@ -1076,8 +1081,9 @@ slim_status slim_autotune(slim_ctx* c, int n_ids, int force, slim_tune_info* inf
     }
   }
   size_t part = 0;
-  for (const ProjTune& t : fwd_c)
-    part = std::max(part, forward_partial_floats(c->h_geom.data(), c->N, c->R, win, c->B, t));
+  for (int L = 0; L < nlists; ++L)
+    for (const ProjTune& t : fwd_c)
+      part = std::max(part, forward_partial_floats(c->h_geom.data(), c->N, c->R, lists[L], c->B, t));
 
   // workspace: an image and its transpose (zeros), the window's rays, partials
   const size_t nimg = c->img_elems() * c->B;
@@ -1131,40 +1137,48 @@ slim_status slim_autotune(slim_ctx* c, int n_ids, int force, slim_tune_info* inf
   std::vector<double> tf(fwd_c.size(), 1e300), tb(back_c.size(), 1e300);
   for (int round = 0; round < kRounds && e == hipSuccess; ++round) {
     for (size_t k = 0; k < fwd_c.size() && e == hipSuccess; ++k) {
-      FwdArgs fa;
-      fa.tune = fwd_c[k];
-      fa.geom = c->d_geom;
-      fa.h_geom = c->h_geom.data();
-      fa.N = c->N;
-      fa.R = c->R;
-      fa.B = c->B;
-      fa.ids = &win;
-      fa.img = img;
-      fa.imgT = imgT;
-      fa.img_stride = c->img_elems();
-      fa.out32 = rays;
-      fa.out_stride = (size_t)win.n * c->R;
-      fa.partial = fpart;
-      double us = 0.0;
-      e = timed([&]() { return launch_forward(fa, c->st); }, &us);
-      tf[k] = std::min(tf[k], us);
+      double sum = 0.0;
+      for (int L = 0; L < nlists && e == hipSuccess; ++L) {
+        FwdArgs fa;
+        fa.tune = fwd_c[k];
+        fa.geom = c->d_geom;
+        fa.h_geom = c->h_geom.data();
+        fa.N = c->N;
+        fa.R = c->R;
+        fa.B = c->B;
+        fa.ids = &lists[L];
+        fa.img = img;
+        fa.imgT = imgT;
+        fa.img_stride = c->img_elems();
+        fa.out32 = rays;
+        fa.out_stride = (size_t)win.n * c->R;
+        fa.partial = fpart;
+        double us = 0.0;
+        e = timed([&]() { return launch_forward(fa, c->st); }, &us);
+        sum += us;
+      }
+      tf[k] = std::min(tf[k], sum);
     }
     for (size_t k = 0; k < back_c.size() && e == hipSuccess; ++k) {
-      BackArgs ba;
-      ba.tune = back_c[k];
-      ba.geom = c->d_geom;
-      ba.N = c->N;
-      ba.R = c->R;
-      ba.B = c->B;
-      ba.ids = &win;
-      ba.v32 = rays;
-      ba.v_stride = (size_t)win.n * c->R;
-      ba.out = img;
-      ba.img_stride = c->img_elems();
-      ba.mode = 0;
-      double us = 0.0;
-      e = timed([&]() { return launch_back(ba, c->st); }, &us);
-      tb[k] = std::min(tb[k], us);
+      double sum = 0.0;
+      for (int L = 0; L < nlists && e == hipSuccess; ++L) {
+        BackArgs ba;
+        ba.tune = back_c[k];
+        ba.geom = c->d_geom;
+        ba.N = c->N;
+        ba.R = c->R;
+        ba.B = c->B;
+        ba.ids = &lists[L];
+        ba.v32 = rays;
+        ba.v_stride = (size_t)win.n * c->R;
+        ba.out = img;
+        ba.img_stride = c->img_elems();
+        ba.mode = 0;
+        double us = 0.0;
+        e = timed([&]() { return launch_back(ba, c->st); }, &us);
+        sum += us;
+      }
+      tb[k] = std::min(tb[k], sum);
     }
   }
   double best_f = 1e300, best_b = 1e300;
