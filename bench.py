@@ -458,6 +458,51 @@ def warm_bench(dev, n_test, n_timed):
 
 
 
+def stream_bench(s_res, cfg, x_true, b, sched, warmup, steps, stream, resident_ms):
+    """The same 1024^2 steps with each block's rows handed over from pinned host
+    memory (slim_step_data) instead of a resident sinogram: the PCIe-inclusive
+    rate, read back every step, and read back only at the end (the copy of the
+    next block then overlaps the current step)."""
+    import numpy as np
+    import torch
+    from paper_1912_07962_amd import Slim
+
+    N, na, g, r, lam = cfg["N"], cfg["n_angles"], cfg["g"], cfg["r"], cfg["lam"]
+    dev = torch.device("cuda:0")
+    t = s_res.get_tune()
+    out = {"block_bytes": None}
+    for mode in ("read_every_step", "read_at_end"):
+        ss = Slim(N, na, r=r, lam=lam, angles_per_block=g, gram_mode="pcg", pcg_tol=1e-6,
+                  stream=stream)
+        ss.set_tune(fwd_bt=t["fwd_bt"], fwd_items=t["fwd_items"], fwd_slots=t["fwd_slots"],
+                    back_bt=t["back_bt"])
+        x = torch.zeros((N, N), dtype=torch.float32, device=dev)
+        ss.set_data(None, x, torch.as_tensor(x_true, dtype=torch.float32, device=dev))
+        bb = np.asarray(b, np.float32).reshape(na, -1)
+        blocks = []
+        for k in range(warmup + steps):
+            beta = int(sched[k])
+            ids = list(range(beta * g, beta * g + g))
+            blocks.append((ids, torch.from_numpy(np.ascontiguousarray(bb[ids])).pin_memory()))
+        out["block_bytes"] = blocks[0][1].numel() * 4
+        for ids, blk in blocks[:warmup]:
+            ss.step_data(ids, blk)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k, (ids, blk) in enumerate(blocks[warmup:]):
+            ss.step_data(ids, blk, read=(mode == "read_every_step" or k == steps - 1))
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        out[mode] = {"ms_per_step": wall / steps * 1e3,
+                     "rays_per_s": g * ss.R * steps / wall}
+        ss.close()
+    out["resident_ms_per_step"] = resident_ms
+    print(f"bench: streamed blocks {out['read_every_step']['ms_per_step']:.2f} / "
+          f"{out['read_at_end']['ms_per_step']:.2f} ms/step (resident {resident_ms:.2f})",
+          file=sys.stderr, flush=True)
+    return out
+
+
 def mixed_bench(dev, steps, autotune=True):
     """Mixed batch: 64 slices of 256^2, 32 of 512^2 and 8 of 1024^2 (one
     ellipsoid volume sampled at three resolutions), 360 angles, 4 angles per
@@ -541,6 +586,8 @@ def main():
     ap.add_argument("--calibration-copy", action="store_true",
                     help="copy 256 MiB once before timing (a kernel of known traffic for "
                          "scaling hardware byte counters)")
+    ap.add_argument("--stream-steps", type=int, default=20,
+                    help="timed steps with blocks handed over from host memory (0: skip)")
     ap.add_argument("--mixed-steps", type=int, default=3,
                     help="timed steps of the mixed batch (0 skips it)")
     ap.add_argument("--gram-steps", type=int, default=20,
@@ -675,6 +722,12 @@ def main():
                  "back_rays_per_s": 8 * R / t_b, "fwd_back_rays_per_s": 8 * R / (t_f + t_b),
                  "fwd_us": t_f * 1e6, "back_us": t_b * 1e6}
 
+    streaming = None
+    if args.stream_steps > 0:
+        streaming = stream_bench(s, cfg, x_true, b, sched, args.warmup,
+                                 min(args.stream_steps, len(sched) - args.warmup), main_stream,
+                                 wall / args.steps * 1e3)
+
     ttr = None
     if not args.no_ttr:
         t = plain_ttr(s, bd, x, xt, sched, g, r, M, float(np.linalg.norm(x_true)))
@@ -736,6 +789,7 @@ def main():
         "projector": projector,
         "time_to_target": ttr,
         "batched": batched,
+        "streaming": streaming,
         "volume": volume,
         "mixed": mixed,
         "gram_solve": gram,
