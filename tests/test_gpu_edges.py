@@ -1,6 +1,7 @@
 """Edge sizes through the C ABI against the FP64 oracle: the smallest grids
 (N = 2, a single ray, one angle, one block holding every angle) and the
-largest detector the library accepts (R = 4096) on a 4096^2 image, where
+largest detector the library accepts (R = 4096) on 4096^2 and 8192^2 (the
+largest) images, where
 the oracle evaluates sampled rays one by one from the closed-form weight and
 the adjoint identity covers every ray and pixel."""
 import math
@@ -81,9 +82,10 @@ def test_tiny_grids_step_like_the_oracle(N, na, R, g, r):
 
 @gpu
 @pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")
-def test_largest_detector_sampled_rays_and_adjoint():
+@pytest.mark.parametrize("N", [4096, 8192])    # 8192: the largest image, one-row bands
+def test_largest_detector_sampled_rays_and_adjoint(N):
     from paper_1912_07962_amd import Slim
-    N, na, R = 4096, 8, 4096
+    na, R = 8, 4096
     ids = list(range(na))                 # row- and column-stepping angles
     rng = np.random.default_rng(7)
     img = rng.uniform(0.0, 1.0, (N, N)).astype(np.float32)
