@@ -503,6 +503,41 @@ def stream_bench(s_res, cfg, x_true, b, sched, warmup, steps, stream, resident_m
     return out
 
 
+def tik_bench(s_res, cfg, bd, xt, sched, warmup, steps, stream, resident_ms, resident_iters, tik):
+    """The same 1024^2 steps as slimTik with L = I (one more forward projection
+    of the window per step; the Tikhonov shift also changes the CG's
+    conditioning): ms per step and CG iterations against plain slimLS."""
+    import torch
+    from paper_1912_07962_amd import Slim
+
+    N, na, g, r, lam = cfg["N"], cfg["n_angles"], cfg["g"], cfg["r"], cfg["lam"]
+    t = s_res.get_tune()
+    st = Slim(N, na, r=r, lam=lam, angles_per_block=g, gram_mode="pcg", pcg_tol=1e-6,
+              stream=stream, tikhonov=tik)
+    st.set_tune(fwd_bt=t["fwd_bt"], fwd_items=t["fwd_items"], fwd_slots=t["fwd_slots"],
+                back_bt=t["back_bt"])
+    x = torch.zeros((N, N), dtype=torch.float32, device=bd.device)
+    st.set_data(bd, x, xt)
+    for k in range(warmup):
+        beta = int(sched[k])
+        st.step(list(range(beta * g, beta * g + g)))
+    torch.cuda.synchronize()
+    iters = []
+    t0 = time.perf_counter()
+    for k in range(warmup, warmup + steps):
+        beta = int(sched[k])
+        iters.append(st.step(list(range(beta * g, beta * g + g)))["pcg_iters"])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    st.close()
+    out = {"tikhonov": tik, "ms_per_step": wall / steps * 1e3,
+           "cg_iters_per_step": sum(iters) / steps, "plain_ms_per_step": resident_ms,
+           "plain_cg_iters_per_step": resident_iters}
+    print(f"bench: slimTik {out['ms_per_step']:.2f} ms/step, {out['cg_iters_per_step']:.1f} CG "
+          f"iterations (plain {resident_ms:.2f}, {resident_iters:.1f})", file=sys.stderr, flush=True)
+    return out
+
+
 def mixed_bench(dev, steps, autotune=True):
     """Mixed batch: 64 slices of 256^2, 32 of 512^2 and 8 of 1024^2 (one
     ellipsoid volume sampled at three resolutions), 360 angles, 4 angles per
@@ -588,6 +623,10 @@ def main():
                          "scaling hardware byte counters)")
     ap.add_argument("--stream-steps", type=int, default=20,
                     help="timed steps with blocks handed over from host memory (0: skip)")
+    ap.add_argument("--tik-steps", type=int, default=20,
+                    help="timed slimTik steps (L = I) of the same workload (0: skip)")
+    ap.add_argument("--tikhonov", type=float, default=0.1,
+                    help="Tikhonov parameter of the slimTik leg")
     ap.add_argument("--mixed-steps", type=int, default=3,
                     help="timed steps of the mixed batch (0 skips it)")
     ap.add_argument("--gram-steps", type=int, default=20,
@@ -728,6 +767,12 @@ def main():
                                  min(args.stream_steps, len(sched) - args.warmup), main_stream,
                                  wall / args.steps * 1e3)
 
+    tik = None
+    if args.tik_steps > 0:
+        tik = tik_bench(s, cfg, bd, xt, sched, args.warmup,
+                        min(args.tik_steps, len(sched) - args.warmup), main_stream,
+                        wall / args.steps * 1e3, sum(iters) / len(iters), args.tikhonov)
+
     ttr = None
     if not args.no_ttr:
         t = plain_ttr(s, bd, x, xt, sched, g, r, M, float(np.linalg.norm(x_true)))
@@ -790,6 +835,7 @@ def main():
         "time_to_target": ttr,
         "batched": batched,
         "streaming": streaming,
+        "slimtik": tik,
         "volume": volume,
         "mixed": mixed,
         "gram_solve": gram,
