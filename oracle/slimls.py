@@ -312,6 +312,6 @@ class Tomo:
             rec = self.step(int(beta))
             if rec.k % epoch_len == 0:
                 snaps.append(self.x.copy())
-            if tol is not None and rec.k >= self.it.r + 1 and rec.step_norm <= tol * rec.x_norm:
+            if tol is not None and stop_index([rec], self.it.r, tol) is not None:
                 return self.x.copy(), snaps, rec.k
         return self.x.copy(), snaps, None

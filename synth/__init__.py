@@ -18,6 +18,7 @@ from .phantom import (  # noqa: F401
     add_noise,
     make_slice_problem,
     make_volume_problem,
+    volume_slice,
     schedule,
     scan_geometry,
     n_rays_for,

@@ -159,24 +159,34 @@ def make_slice_problem(N: int, n_angles: int, n_ellipses: int, noise: float,
     return x_true, add_noise(clean, noise, noise_seed), clean
 
 
+def volume_slice(N: int, n_slices: int, k: int, n_angles: int, n_ellipsoids: int,
+                 noise: float, phantom_seed: int, noise_seed: int, ells=None):
+    """Slice k of the volume of ``make_volume_problem``: (x_true[N, N],
+    b[n_angles, R]) float64.  The slice sits at z_k = (k - (B-1)/2) * 2/B and
+    gets noise seed ``noise_seed + k``; an empty slice has b = 0."""
+    theta, s, _ = scan_geometry(N, n_angles)
+    if ells is None:
+        ells = random_ellipsoids(n_ellipsoids, phantom_seed)
+    z = (k - (n_slices - 1) / 2.0) * (2.0 / n_slices)
+    sl = ellipsoid_slice(ells, z)
+    clean = analytic_sinogram(sl, theta, s)
+    b = add_noise(clean, noise, noise_seed + k) if np.any(clean) else clean
+    return rasterize(sl, N), b
+
+
 def make_volume_problem(N: int, n_slices: int, n_angles: int, n_ellipsoids: int,
                         noise: float, phantom_seed: int, noise_seed: int):
     """Independent z-slices of one random ellipsoid volume.
 
-    Returns (x_true[B, N, N], b[B, n_angles, R]) float64; slice k sits at
-    z_k = (k - (B-1)/2) * 2/B and gets noise seed ``noise_seed + k``."""
-    theta, s, _ = scan_geometry(N, n_angles)
+    Returns (x_true[B, N, N], b[B, n_angles, R]) float64; slice k is
+    ``volume_slice(..., k, ...)``."""
     ells = random_ellipsoids(n_ellipsoids, phantom_seed)
-    R = s.size
+    R = n_rays_for(N)
     xs = np.zeros((n_slices, N, N), dtype=np.float64)
     bs = np.zeros((n_slices, n_angles, R), dtype=np.float64)
     for k in range(n_slices):
-        z = (k - (n_slices - 1) / 2.0) * (2.0 / n_slices)
-        sl = ellipsoid_slice(ells, z)
-        xs[k] = rasterize(sl, N)
-        clean = analytic_sinogram(sl, theta, s)
-        if np.any(clean):
-            bs[k] = add_noise(clean, noise, noise_seed + k)
+        xs[k], bs[k] = volume_slice(N, n_slices, k, n_angles, n_ellipsoids, noise,
+                                    phantom_seed, noise_seed, ells)
     return xs, bs
 
 

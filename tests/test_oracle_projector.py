@@ -119,3 +119,54 @@ def test_symmetry_of_opposite_angles():
         # rotating the image by -90 deg maps angle theta to theta + pi/2
         q = P.angle(a + na // 2) @ np.rot90(x, k=-1).reshape(-1)
         np.testing.assert_allclose(q, p, rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("N,na,ids", [
+    (16, 12, [0, 3, 6, 9]),
+    (21, 30, [29, 0, 7, 7, 15, 22]),          # any order, a repeated angle
+    (64, 90, list(range(0, 90, 11))),
+    (33, 7, [6, 2, 4]),
+])
+def test_back_is_adjoint_of_forward(N, na, ids):
+    # <A_ids x, y> = <x, A_ids^T y> for random x, y: pins the layout of the
+    # rays ([len(ids)][R], angle-major) in Projector.back against the forward
+    # projector, which the Radon pins above fix.
+    P = system.Projector(N, na)
+    rng = np.random.default_rng(N * 1000 + na)
+    x = rng.standard_normal(N * N)
+    y = rng.standard_normal(len(ids) * P.R)
+    lhs = float(P.forward(ids, x) @ y)
+    rhs = float(x @ P.back(ids, y))
+    assert abs(lhs - rhs) <= 1e-13 * np.linalg.norm(P.forward(ids, x)) * np.linalg.norm(y)
+
+
+def test_back_equals_bruteforce_transpose():
+    # A^T y with every (ray, pixel) weight evaluated directly
+    N, na = 12, 10
+    P = system.Projector(N, na)
+    ids = [9, 1, 4]
+    dense = system.dense_bruteforce(N, P.R, P.theta[ids])
+    y = np.random.default_rng(1).standard_normal(len(ids) * P.R)
+    np.testing.assert_allclose(P.back(ids, y), dense.T @ y, rtol=0, atol=1e-13)
+
+
+def test_back_of_ones_at_zero_and_right_angle_is_h():
+    # theta = 0 (rays x = s) and pi/2 (rays y = s): d = 1 and the rays are one
+    # pixel apart, so the hat weights of a pixel sum to 1 (linear
+    # interpolation is a partition of unity) and every pixel whose centre lies
+    # between two rays of the detector gets exactly h from a row of ones.
+    N = 24
+    P = system.Projector(N, 2)          # angles 0 and pi/2
+    h = 2.0 / N
+    for a in (0, 1):
+        out = P.back([a], np.ones(P.R)).reshape(N, N)
+        np.testing.assert_allclose(out, h, rtol=0, atol=1e-15)
+    # one ray on: its weights are the hat function of the distance to it
+    v = np.zeros(P.R)
+    t = (P.R - 1) // 2 + 3
+    v[t] = 1.0
+    out = P.back([0], v).reshape(N, N)
+    xc = geo.pixel_centres(N)
+    s_t = geo.ray_offsets(N, P.R)[t]
+    ref = h * np.maximum(0.0, 1.0 - np.abs(s_t - xc) / h)
+    np.testing.assert_allclose(out, np.tile(ref, (N, 1)), rtol=0, atol=1e-15)

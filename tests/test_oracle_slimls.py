@@ -269,6 +269,27 @@ def test_stop_rule():
     assert slimls.stop_index(H, r=2, tol=1e-2) == 4     # k=2 is inside the first r+1 steps
 
 
+def test_tomo_run_stops_where_stop_index_says():
+    # Tomo.run's early termination (sec. 4.3) is the first k >= r+1 with
+    # ||s_k|| <= tol ||x_k||: the same step as stop_index over the full history
+    N, na, g, r, lam = 24, 30, 1, 3, 1e-2
+    P = system.Projector(N, na)
+    _, b, _ = synth.make_slice_problem(N, na, 5, 0.01, 61, 62)
+    sched = sampler.schedule(na // g, 3, 8)
+    full = slimls.Tomo(P, b, g, r, lam)
+    full.run(sched)
+    for tol in (0.3, 5e-2, 1e-2):
+        k_ref = slimls.stop_index(full.it.history, r, tol)
+        assert k_ref is not None and k_ref >= r + 1
+        T = slimls.Tomo(P, b, g, r, lam)
+        x, _, k = T.run(sched, tol=tol)
+        assert k == k_ref and len(T.it.history) == k
+        np.testing.assert_array_equal(x, T.x)
+    # a tolerance never met runs the whole schedule
+    T = slimls.Tomo(P, b, g, r, lam)
+    assert T.run(sched, tol=1e-12)[2] is None and len(T.it.history) == len(sched)
+
+
 def test_sparse_block_matches_dense_block():
     N, na = 9, 6
     P = system.Projector(N, na)
