@@ -211,6 +211,28 @@ slim_status slim_solve(slim_ctx* ctx, const void* b, void* x, const float* x_tru
 slim_status slim_project(slim_ctx* ctx, const int32_t* angle_ids, int n_ids, const float* x,
                          float* out);
 
+/* slim_project for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same projection, launches and results, but the projector's partial
+ * sums live in a fixed scratch array of 16 MiB (4,194,304 floats) that the
+ * library's code object holds on each device it runs on until the process
+ * ends, instead of the context's workspace (which slim_project grows with
+ * hipMalloc).  This call allocates nothing and frees nothing; the scratch's
+ * device address is taken once per device by slim_init.
+ *  angle_ids, x, out as in slim_project (caller-owned).
+ * The scratch needed is what slim_project's workspace needs for the same
+ * call: n_slices * G * n_ids * n_rays floats, G the number of groups of image
+ * bands the launch splits the image into (G = 8 for 88 angles of one 1024^2
+ * image, 1.02 M floats); a call that needs more returns SLIM_EINVAL and
+ * launches nothing (slim_project has no such limit).
+ * Every call on one device shares that device's scratch and leaves its
+ * contents behind (each call overwrites every entry it reads), so calls that
+ * overlap on one device -- from different streams or threads -- race; calls
+ * ordered on one stream do not.
+ * Errors: SLIM_EINVAL (bad arguments, scratch too small), SLIM_EDEVICE. */
+slim_status slim_project_noalloc(slim_ctx* ctx, const int32_t* angle_ids, int n_ids,
+                                 const float* x, float* out);
+
 /* Back-projection, the exact adjoint of slim_project with the same weights.
  *  v    device [n_slices][n_ids][n_rays] float32
  *  out  device [n_slices][N][N] float32, out = A_ids^T v (overwritten)

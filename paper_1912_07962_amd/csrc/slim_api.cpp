@@ -85,6 +85,7 @@ struct slim_ctx {
   double lam = 0.0;
   slim_opts o{};
   hipStream_t st = nullptr;
+  int dev = 0;  // device current at slim_init
   int mode = SLIM_GRAM_CHOL;
   int64_t ell = 0, pmax = 0;
 
@@ -585,6 +586,9 @@ slim_status slim_init(slim_ctx** out, const slim_grid* grid, int n_angles, const
     return fail(SLIM_EDEVICE, std::string("allocation: ") + hipGetErrorString(e));
   };
   hipError_t e;
+  if ((e = hipGetDevice(&c->dev)) != hipSuccess) return oom(e);
+  // the allocation-free projection's scratch: its address on this device
+  if ((e = forward_scratch_setup()) != hipSuccess) return oom(e);
   const size_t nimg = c->img_elems() * c->B;
   if ((e = dalloc(&c->d_geom, n_angles)) != hipSuccess) return oom(e);
   if ((e = dalloc(&c->d_res64, (size_t)c->B * ell)) != hipSuccess) return oom(e);
@@ -776,6 +780,32 @@ slim_status slim_project(slim_ctx* c, const int32_t* ids, int n_ids, const float
   if (s != SLIM_OK) return s;
   // column-stepping angles stage bands of columns of x (no transposed copy)
   FwdArgs fa = base_fwd(c, &l);
+  fa.img = x;
+  fa.imgT = nullptr;
+  fa.out32 = out;
+  fa.out_stride = (size_t)n_ids * c->R;
+  HIP_TRY(launch_forward(fa, c->st));
+  return SLIM_OK;
+}
+
+slim_status slim_project_noalloc(slim_ctx* c, const int32_t* ids, int n_ids, const float* x,
+                                 float* out) {
+  if (!c) return fail(SLIM_EINVAL, "ctx is NULL");
+  slim_status s = check_ids(c, ids, n_ids, true);
+  if (s != SLIM_OK) return s;
+  if (!x || !out) return fail(SLIM_EINVAL, "x and out must be non-NULL");
+  const AngleList l = make_list(ids, n_ids);
+  const size_t need = forward_partial_floats(c->h_geom.data(), c->N, c->R, l, c->B, c->tune_for(l.n));
+  if (need > forward_scratch_floats())
+    return fail(SLIM_EINVAL, "projection needs " + std::to_string(need) +
+                                 " floats of scratch; the fixed scratch holds " +
+                                 std::to_string(forward_scratch_floats()) + " (use slim_project)");
+  float* scratch = forward_scratch(c->dev);
+  if (!scratch) return fail(SLIM_EDEVICE, "fixed scratch not set up on this device");
+  // the same launches as slim_project; every partial sum the reduction reads
+  // is written first by the band kernel, so nothing is cleared
+  FwdArgs fa = base_fwd(c, &l);
+  fa.partial = scratch;
   fa.img = x;
   fa.imgT = nullptr;
   fa.out32 = out;

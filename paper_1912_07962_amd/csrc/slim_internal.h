@@ -238,6 +238,14 @@ hipError_t launch_tik_rhs(const double* mx, size_t mx_stride, const double* res,
 hipError_t launch_scatter_rows(const void* in, int bf16, int n_angles, int R, int B,
                                const AngleList& ids, void* b, hipStream_t st);
 
+// Fixed forward scratch of the allocation-free projection: its capacity in
+// floats, its set-up on the current device (hipGetSymbolAddress, once per
+// device; slim_init calls it), and its device address on device dev (NULL
+// before the set-up).  Concurrent users of one device share the array.
+size_t forward_scratch_floats();
+hipError_t forward_scratch_setup();
+float* forward_scratch(int dev);
+
 // Record msg as the library's last error message and return s.
 slim_status set_error(slim_status s, const std::string& msg);
 

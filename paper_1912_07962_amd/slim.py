@@ -95,6 +95,7 @@ def load() -> ctypes.CDLL:
         "slim_step_data": (I, [P, i32p, I, P, ctypes.POINTER(StepInfo)]),
         "slim_solve": (I, [P, P, P, P, D, I, ctypes.POINTER(SolveInfo)]),
         "slim_project": (I, [P, i32p, I, P, P]),
+        "slim_project_noalloc": (I, [P, i32p, I, P, P]),
         "slim_backproject": (I, [P, i32p, I, P, P]),
         "slim_gram": (I, [P, i32p, I, i32p, I, P]),
         "slim_get_state": (I, [P, P, ctypes.POINTER(ctypes.c_int64)]),
@@ -319,6 +320,14 @@ class Slim:
                               dtype=torch.float32, device=x.device)
         _check(load().slim_project(self._h, p, n, _ptr(x, torch.float32, "x"),
                                    _ptr(out, torch.float32, "out")))
+        return out
+
+    def project_noalloc(self, angle_ids, x, out):
+        """slim_project into a caller-given ``out`` through the library's fixed
+        scratch (no device allocation in the call)."""
+        a, p, n = _ids(angle_ids)
+        _check(load().slim_project_noalloc(self._h, p, n, _ptr(x, torch.float32, "x"),
+                                           _ptr(out, torch.float32, "out")))
         return out
 
     def backproject(self, angle_ids, v, out=None):

@@ -50,6 +50,7 @@ def test_null_handles_are_rejected():
     assert lib.slim_step_data(None, None, 0, None, None) == slim.SLIM_EINVAL
     assert lib.slim_solve(None, None, None, None, 1e-2, 1, None) == slim.SLIM_EINVAL
     assert lib.slim_project(None, None, 0, None, None) == slim.SLIM_EINVAL
+    assert lib.slim_project_noalloc(None, None, 0, None, None) == slim.SLIM_EINVAL
     assert lib.slim_slice_norms(None, None, 0) == slim.SLIM_EINVAL
     assert lib.slim_autotune(None, 0, 0, None) == slim.SLIM_EINVAL
     assert lib.slim_group_create(None, None, 0) == slim.SLIM_EINVAL
