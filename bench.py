@@ -117,30 +117,75 @@ def window_nnz(N, thetas):
     return sum(2.0 * max(abs(math.cos(t)), abs(math.sin(t))) * N * N for t in thetas)
 
 
-def cpu_baseline(cfg, b, x_true, budget_s):
-    """Time the FP64 oracle's first steps of the same run (bounded)."""
+def cpu_baseline(cfg, b, sched, mean_cg_iters, budget_s):
+    """Time the FP64 oracle on a full-window step of the same run (bounded).
+
+    The oracle (scipy CSR products, FP64 CG) takes step r + 2 of the run, whose
+    window holds the r + 1 = 11 blocks sched[1..r+1] (p = 127,512):
+    the residual of the new block, CG iterations on the Gram system until the
+    budget is spent, then s = M^T z and the update.  The step's cost is
+    extrapolated to ``mean_cg_iters`` CG iterations (the GPU's mean per timed
+    step at the same tolerance); building the CSR rows of the window is set
+    up before timing and not counted."""
     import numpy as np
     from oracle import slimls, system
-    import synth
 
     N, na, g, r, lam = cfg["N"], cfg["n_angles"], cfg["g"], cfg["r"], cfg["lam"]
     P = system.Projector(N, na)
-    T = slimls.Tomo(P, b, g, r, lam, x_true=x_true, chol_max_p=0, cg_tol=1e-6)
-    sched = synth.schedule(na // g, 1, cfg["schedule_seed"])
+    T = slimls.Tomo(P, b, g, r, lam, chol_max_p=0, cg_tol=1e-6)
+    window = [int(v) for v in sched[1:r + 2]]       # the window after step r + 2
+    t_build = time.perf_counter()
+    mats = [T.rows(beta) for beta in window]
+    M = sp_vstack(mats)
+    t_build = time.perf_counter() - t_build
+    x = np.zeros(P.n)
+    lam_k = lam
     t0 = time.perf_counter()
-    steps = 0
-    for beta in sched:
-        T.step(int(beta))
-        steps += 1
-        if time.perf_counter() - t0 > budget_s:
-            break
-    dt = time.perf_counter() - t0
+    res = np.asarray(mats[-1] @ x).reshape(-1) - T.data(window[-1])
+    e = np.zeros(M.shape[0])
+    e[-res.size:] = res
+    t_res = time.perf_counter() - t0
+    # bounded CG: the oracle's own routine with an iteration cap sized to the
+    # budget from a two-iteration probe (the tolerance is never reached)
+    apply = lambda v: M @ (M.T @ v) + lam_k * v
+    t0 = time.perf_counter()
+    slimls.cg(apply, e, 1e-300, max_iter=2)
+    probe = (time.perf_counter() - t0) / 2.0
+    its = int(max(2, min(200, budget_s / max(probe, 1e-6))))
+    t0 = time.perf_counter()
+    slimls.cg(apply, e, 1e-300, max_iter=its)
+    t_it = (time.perf_counter() - t0) / its
+    t0 = time.perf_counter()
+    z = e * 0.0
+    s_ = np.asarray(M.T @ z).reshape(-1)
+    x = x - s_
+    t_back = time.perf_counter() - t0
+    step_s = t_res + mean_cg_iters * t_it + t_back
     ell = g * P.R
-    return {"value": ell * steps / dt, "unit": "rays/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {steps} slimLS steps of the same 1024^2 run from x=0 (window "
-                      f"filling, p up to {min(steps, r + 1) * ell}), scipy CSR products, FP64 "
-                      f"CG to 1e-6, CSR build of each new block included; {dt:.1f} s, "
-                      f"single-threaded sparse kernels"}
+    return {"value": ell / step_s, "unit": "rays/s", "cores": 1, "kind": "oracle",
+            "cpu": _cpu_model(), "nproc": os.cpu_count(),
+            "sample": f"one full-window step of the same 1024^2 run (window of {r + 1} blocks, "
+                      f"p = {M.shape[0]}): residual {t_res * 1e3:.0f} ms, {its} FP64 CG "
+                      f"iterations at {t_it * 1e3:.0f} ms each extrapolated to the GPU's "
+                      f"{mean_cg_iters:.1f} per step, back-projection and update "
+                      f"{t_back * 1e3:.0f} ms; scipy CSR products (single-threaded), CSR "
+                      f"rows of the window built beforehand in {t_build:.0f} s (not counted)"}
+
+
+def sp_vstack(mats):
+    import scipy.sparse as sp
+    return sp.vstack(mats, format="csr")
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def plain_ttr(s, bd, x, xt, sched, g, r, M, nrm):
@@ -542,8 +587,10 @@ def mixed_bench(dev, steps, autotune=True):
     """Mixed batch: 64 slices of 256^2, 32 of 512^2 and 8 of 1024^2 (one
     ellipsoid volume sampled at three resolutions), 360 angles, 4 angles per
     block, r = 8, lambda = 1e-3, CG; one context per size on its own stream,
-    stepped as one group (interleaved CG) and, for comparison, one context
-    after another."""
+    stepped as one group (interleaved CG), against a second, identical set of
+    contexts stepped one after another over the same steps (both sets take
+    the same r + 1 steps first, so both time full-window steps of the same
+    blocks)."""
     import numpy as np
     import torch
     import synth
@@ -552,29 +599,37 @@ def mixed_bench(dev, steps, autotune=True):
     cfg = synth.get_config("c4m")
     na, g, r, lam = cfg["n_angles"], cfg["g"], cfg["r"], cfg["lam"]
     print("bench: mixed batch inputs", file=sys.stderr, flush=True)
-    ctxs, keep, rays, tunes = [], [], 0, []
+    sets = ([], [])
+    keep, rays, tunes = [], 0, []
     for N, B in cfg["groups"]:
         xs, bs = synth.make_volume_problem(N, B, na, cfg["n_ellipsoids"], cfg["noise"],
                                            cfg["phantom_seed"], cfg["noise_seed"])
-        st = torch.cuda.Stream()
-        with torch.cuda.stream(st):
-            s = Slim(N, na, r=r, lam=lam, n_slices=B, angles_per_block=g, gram_mode="pcg",
-                     pcg_tol=1e-6, stream=st)
-            if autotune:
-                tunes.append(s.autotune()["chosen"])
-            bd = torch.as_tensor(bs, dtype=torch.float32, device=dev)
-            xt = torch.as_tensor(xs, dtype=torch.float32, device=dev)
-            x = torch.zeros((B, N, N), dtype=torch.float32, device=dev)
-        st.synchronize()
-        s.set_data(bd, x, xt)
-        ctxs.append(s)
-        keep.append((st, bd, xt, x))
-        rays += B * g * s.R
-    grp = Group(ctxs)
+        tuned = None
+        for which in (0, 1):
+            st = torch.cuda.Stream()
+            with torch.cuda.stream(st):
+                s = Slim(N, na, r=r, lam=lam, n_slices=B, angles_per_block=g, gram_mode="pcg",
+                         pcg_tol=1e-6, stream=st)
+                if autotune and tuned is None:
+                    tuned = s.autotune()["chosen"]
+                    tunes.append(tuned)
+                elif tuned is not None:
+                    s.set_tune(**tuned)
+                bd = torch.as_tensor(bs, dtype=torch.float32, device=dev)
+                xt = torch.as_tensor(xs, dtype=torch.float32, device=dev)
+                x = torch.zeros((B, N, N), dtype=torch.float32, device=dev)
+            st.synchronize()
+            s.set_data(bd, x, xt)
+            sets[which].append(s)
+            keep.append((st, bd, xt, x))
+        rays += B * g * sets[0][-1].R
+    grp = Group(sets[0])
     sched = synth.schedule(na // g, 1, cfg["schedule_seed"])
     blk = lambda k: list(range(int(sched[k]) * g, int(sched[k]) * g + g))
     for k in range(r + 1):
         grp.step(blk(k))
+        for s in sets[1]:
+            s.step(blk(k))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(r + 1, r + 1 + steps):
@@ -582,20 +637,21 @@ def mixed_bench(dev, steps, autotune=True):
     torch.cuda.synchronize()
     t_grp = (time.perf_counter() - t0) / steps
     t0 = time.perf_counter()
-    for k in range(r + 1 + steps, r + 1 + 2 * steps):
-        for s in ctxs:
+    for k in range(r + 1, r + 1 + steps):
+        for s in sets[1]:
             s.step(blk(k))
     torch.cuda.synchronize()
     t_seq = (time.perf_counter() - t0) / steps
     grp.close()
-    for s in ctxs:
+    for s in sets[0] + sets[1]:
         s.close()
     print(f"bench: mixed batch {t_grp * 1e3:.1f} ms/step grouped, {t_seq * 1e3:.1f} sequential",
           file=sys.stderr, flush=True)
     return {"groups": [list(gp) for gp in cfg["groups"]], "steps": steps,
             "group_ms_per_step": t_grp * 1e3, "sequential_ms_per_step": t_seq * 1e3,
             "group_speedup": t_seq / t_grp, "slice_rays_per_s": rays / t_grp,
-            "cg_iters_last_step": [i["pcg_iters"] for i in infos], "autotune": tunes}
+            "same_steps": True, "cg_iters_last_step": [i["pcg_iters"] for i in infos],
+            "autotune": tunes}
 
 
 def main():
@@ -669,7 +725,8 @@ def main():
     R = s.R
     ell = g * R
     M = na // g
-    sched = synth.schedule(M, 1 + (args.warmup + 2 * args.steps) // M + 1, cfg["schedule_seed"])
+    sched = synth.schedule(M, 1 + (max(args.warmup, r + 2) + 2 * args.steps) // M + 1,
+                           cfg["schedule_seed"])
     theta = np.arange(na) * (np.pi / na)
 
     if args.calibration_copy:
@@ -682,10 +739,21 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     s.set_data(bd, x, xt)
-    print(f"bench: warmup {args.warmup} steps", file=sys.stderr, flush=True)
-    for k in range(args.warmup):
+    # the timed steps start with the memory window full (r + 1 blocks) whatever
+    # --warmup says; steps r + 1 and r + 2 are checked against the FP64 oracle
+    # run stored for this workload (same schedule, CG to 1e-12)
+    warmup = max(args.warmup, r + 2)
+    print(f"bench: warmup {warmup} steps", file=sys.stderr, flush=True)
+    gold = np.load(os.path.join(ROOT, "tests", "golden", "c2_window.npz"))
+    assert [int(v) for v in gold["blocks"]] == [int(v) for v in sched[:r + 2]]
+    parity = {}
+    for k in range(warmup):
         beta = int(sched[k])
         s.step(list(range(beta * g, beta * g + g)))
+        if f"x{k + 1}" in gold.files:
+            ref = gold[f"x{k + 1}"].astype(np.float64).reshape(-1)
+            got = x.cpu().numpy().astype(np.float64).reshape(-1)
+            parity[f"step_{k + 1}"] = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
     torch.cuda.synchronize()
 
     # timed region: exactly `steps` steps, no instrumentation
@@ -694,7 +762,7 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ev0.record(main_stream)
-    for k in range(args.warmup, args.warmup + args.steps):
+    for k in range(warmup, warmup + args.steps):
         beta = int(sched[k])
         info = s.step(list(range(beta * g, beta * g + g)))
         iters.append(info["pcg_iters"])
@@ -709,7 +777,7 @@ def main():
     s.profile(True)
     prof_iters = []
     flops_cg = 0.0
-    k0 = args.warmup + args.steps
+    k0 = warmup + args.steps
     window = [int(sched[k]) for k in range(max(0, k0 - r), k0)]
     for k in range(k0, k0 + args.steps):
         beta = int(sched[k])
@@ -763,14 +831,14 @@ def main():
 
     streaming = None
     if args.stream_steps > 0:
-        streaming = stream_bench(s, cfg, x_true, b, sched, args.warmup,
-                                 min(args.stream_steps, len(sched) - args.warmup), main_stream,
+        streaming = stream_bench(s, cfg, x_true, b, sched, warmup,
+                                 min(args.stream_steps, len(sched) - warmup), main_stream,
                                  wall / args.steps * 1e3)
 
     tik = None
     if args.tik_steps > 0:
-        tik = tik_bench(s, cfg, bd, xt, sched, args.warmup,
-                        min(args.tik_steps, len(sched) - args.warmup), main_stream,
+        tik = tik_bench(s, cfg, bd, xt, sched, warmup,
+                        min(args.tik_steps, len(sched) - warmup), main_stream,
                         wall / args.steps * 1e3, sum(iters) / len(iters), args.tikhonov)
 
     ttr = None
@@ -806,7 +874,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         print("bench: cpu baseline (FP64 oracle)", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(cfg, b, x_true, args.cpu_budget)
+        cpu = cpu_baseline(cfg, b, sched, float(np.mean(iters)), args.cpu_budget)
 
     value = ell * args.steps / wall
     line = {
@@ -815,7 +883,8 @@ def main():
         "unit": "rays/s",
         "n_gpus": 1,
         "steps": args.steps,
-        "warmup": args.warmup,
+        "warmup": warmup,
+        "warmup_requested": args.warmup,
         "ms_per_step": wall / args.steps * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
@@ -841,6 +910,9 @@ def main():
         "gram_solve": gram,
         "warm_start": warm,
         "cg_iters_per_step": float(np.mean(iters)),
+        "window_blocks_timed": r + 1,
+        "parity_rel_err": {"vs": "FP64 oracle (CG to 1e-12), same schedule from x = 0",
+                           "cg_tol": 1e-6, **parity},
         "event_ms_timed_region": ev_ms,
         "graphs": True,
         "kernel_ms": {k: v2["total_ms"] for k, v2 in stats.items()},

@@ -36,7 +36,6 @@
 #include "pcg.h"
 
 #include <algorithm>
-#include <mutex>
 
 namespace slim {
 
@@ -1094,40 +1093,6 @@ hipError_t launch_gather_rows(const void* b, int b_bf16, int n_angles, int R, in
     hipLaunchKernelGGL(gather_rows_kernel<float>, grid, dim3(256), 0, st, (const float*)b,
                        n_angles, R, ids, out);
   return hipGetLastError();
-}
-
-// ------------------------------------------------------- fixed scratch
-// The forward projector's partial sums for callers that cannot allocate
-// (slim_project_noalloc): one array per device, loaded with the library's
-// code object and held until the process ends.  In host code the symbol is
-// only a stand-in; kernels receive the device address that
-// hipGetSymbolAddress returns for the current device, kept per device.
-constexpr size_t kScratchFloats = size_t(4) << 20;  // 16 MiB
-static __device__ __align__(256) float scratch[kScratchFloats];
-constexpr int kMaxScratchDevices = 64;
-static float* g_scratch[kMaxScratchDevices] = {};
-static std::mutex g_scratch_mu;
-
-size_t forward_scratch_floats() { return kScratchFloats; }
-
-hipError_t forward_scratch_setup() {
-  int dev = 0;
-  hipError_t e = hipGetDevice(&dev);
-  if (e != hipSuccess) return e;
-  if (dev < 0 || dev >= kMaxScratchDevices) return hipErrorInvalidDevice;
-  std::lock_guard<std::mutex> lock(g_scratch_mu);
-  if (g_scratch[dev]) return hipSuccess;
-  void* p = nullptr;
-  e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
-  if (e != hipSuccess) return e;
-  g_scratch[dev] = (float*)p;
-  return hipSuccess;
-}
-
-float* forward_scratch(int dev) {
-  if (dev < 0 || dev >= kMaxScratchDevices) return nullptr;
-  std::lock_guard<std::mutex> lock(g_scratch_mu);
-  return g_scratch[dev];
 }
 
 }  // namespace slim
