@@ -23,4 +23,13 @@ from .phantom import (  # noqa: F401
     scan_geometry,
     n_rays_for,
 )
+from .phantom3d import (  # noqa: F401
+    Ellipsoid3,
+    random_directions,
+    detector_basis,
+    random_ellipsoids3,
+    rasterize3,
+    line_integrals,
+    make_problem3,
+)
 from .configs import CONFIGS, get_config, warmstart_sample  # noqa: F401
