@@ -132,7 +132,7 @@ def single_ray(N: int, n_det: int, w, q: int, t: int, x: np.ndarray) -> float:
     m, a, b = major_axis(w)
     c = _centres(N)
     o = (t - (n_det - 1) / 2.0) * h * eu + (q - (n_det - 1) / 2.0) * h * ev
-    x = np.asarray(x, np.float64).reshape(N, N, N)     # [z][y][x]
+    x = np.asarray(x).reshape(N, N, N)                 # [z][y][x], read entry by entry
     total = 0.0
     for km in range(N):
         tau = (c[km] - o[m]) / w[m]
@@ -148,7 +148,7 @@ def single_ray(N: int, n_det: int, w, q: int, t: int, x: np.ndarray) -> float:
                     continue
                 idx = [0, 0, 0]
                 idx[m], idx[a], idx[b] = km, ia, ib
-                total += wgt * x[idx[2], idx[1], idx[0]]
+                total += wgt * float(x[idx[2], idx[1], idx[0]])
     return total
 
 

@@ -5,4 +5,6 @@ PCG of the Gram system and the fused update -- lives in the HIP library
 ``_lib/libslim.so`` behind the C ABI of ``include/slim.h``; ``slim`` is its
 ctypes binding.
 """
-from .slim import Cnn, Group, Slim, SlimError, cnn_layout, load, header_symbols  # noqa: F401
+from .slim import (  # noqa: F401
+    Cnn, Group, Slim, Slim3D, SlimError, cnn_layout, header_symbols, load,
+)

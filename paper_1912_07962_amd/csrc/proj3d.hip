@@ -1,0 +1,395 @@
+// Matrix-free 3D parallel-beam projectors (Joseph's method along the major
+// axis) and the float64 CG kernels of the 3D slimLS path, for gfx950.
+//
+// Forward (ray-driven): a workgroup owns a 16 x 16 tile of detector pixels
+// of one direction; each lane walks its ray through the planes x_m = const
+// that it crosses inside the volume, its crossing point in 32.32 fixed point
+// (one 64-bit add per plane and axis), and interpolates bilinearly between
+// the four voxel centres around it (zero outside the volume).  Ray sums run
+// in float32 over 32 planes at a time and accumulate in float64.
+//
+// Back (voxel-driven gather, the exact adjoint): a workgroup owns a tile of
+// 8 x 8 x 4 voxels; per direction it stages the detector window its tile
+// projects onto (at most 17 x 17 of the 24 x 24 LDS pixels, scaled by
+// h/|w_m|) and every lane evaluates the closed-form weights of the 4 x 4
+// candidate rays around its voxel's own ray: the crossing-point displacement
+// is linear in the detector offset (DirGeom), and a weight is the product of
+// two tents.
+#include "slim3d_internal.h"
+
+namespace slim {
+namespace {
+
+constexpr int kRT = 16;                   // forward ray tile (t and q)
+constexpr int kVX = 8, kVY = 8, kVZ = 4;  // back-projector voxel tile
+constexpr int kFP = 24;                   // staged detector window side
+constexpr int kFlush = 32;                // planes per float32 partial sum
+constexpr double kTwo32 = 4294967296.0;
+constexpr float kInv32 = 2.3283064365386963e-10f;  // 2^-32
+
+// Planes k with -1 < f0 + k s < N (the crossing index f along one axis),
+// intersected into [lo, hi] (real bounds; callers round outwards).
+__device__ __forceinline__ void plane_range(double f0, double s, int N, double& lo, double& hi) {
+  if (s > 0.0) {
+    lo = fmax(lo, (-1.0 - f0) / s);
+    hi = fmin(hi, ((double)N - f0) / s);
+  } else if (s < 0.0) {
+    lo = fmax(lo, ((double)N - f0) / s);
+    hi = fmin(hi, (-1.0 - f0) / s);
+  } else if (!(f0 > -1.0 && f0 < (double)N)) {
+    hi = -2.0;
+  }
+}
+
+__device__ __forceinline__ float unit_clamp(float v) { return __builtin_amdgcn_fmed3f(v, 0.f, 1.f); }
+
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  const double s = sh[0] + sh[1] + sh[2] + sh[3];
+  __syncthreads();
+  return s;
+}
+
+__global__ __launch_bounds__(256) void fwd3_kernel(
+    const DirGeom* __restrict__ geom, DirList ids, int N, int n, const float* __restrict__ x,
+    const float* __restrict__ sub, float* __restrict__ out32, double* __restrict__ out64,
+    const double* __restrict__ pd, double lam, double* __restrict__ dots,
+    const int* __restrict__ ctl) {
+  if (ctl && ctl[kCtlDone]) return;
+  __shared__ double sh[4];
+  const int slot = blockIdx.z;
+  const DirGeom G = geom[ids.id[slot]];
+  const int t = blockIdx.x * kRT + (threadIdx.x & (kRT - 1));
+  const int q = blockIdx.y * kRT + (threadIdx.x / kRT);
+  const bool ok = t < n && q < n;
+  double sum = 0.0;
+  if (ok) {
+    const double hN = 0.5 * (N - 1), hn = 0.5 * (n - 1);
+    const double tt = t - hn, qq = q - hn;
+    const double fa0 = hN + tt * G.La[0] + qq * G.La[1] - hN * G.sa;
+    const double fb0 = hN + tt * G.Lb[0] + qq * G.Lb[1] - hN * G.sb;
+    double lo = 0.0, hi = (double)(N - 1);
+    plane_range(fa0, G.sa, N, lo, hi);
+    plane_range(fb0, G.sb, N, lo, hi);
+    const int k0 = (int)fmin((double)N, fmax(0.0, floor(lo)));
+    const int k1 = (int)fmax(-1.0, fmin((double)(N - 1), ceil(hi)));
+    if (k0 <= k1) {
+      const int st[3] = {1, N, N * N};
+      const int sm = st[G.m], sa = st[G.a], sb = st[G.b];
+      int64_t Fa = llrint((fa0 + k0 * G.sa) * kTwo32), Fb = llrint((fb0 + k0 * G.sb) * kTwo32);
+      const int64_t Sa = llrint(G.sa * kTwo32), Sb = llrint(G.sb * kTwo32);
+      const unsigned uN = (unsigned)N;
+      float part = 0.f;
+      int cnt = 0;
+      for (int k = k0; k <= k1; ++k) {
+        const int ia = (int)(Fa >> 32), ib = (int)(Fb >> 32);
+        const float fa = (float)(uint32_t)Fa * kInv32, fb = (float)(uint32_t)Fb * kInv32;
+        const bool a0 = (unsigned)ia < uN, a1 = (unsigned)(ia + 1) < uN;
+        const bool b0 = (unsigned)ib < uN, b1 = (unsigned)(ib + 1) < uN;
+        const float* p = x + (k * sm + ia * sa + ib * sb);
+        const float v00 = (a0 && b0) ? p[0] : 0.f;
+        const float v10 = (a1 && b0) ? p[sa] : 0.f;
+        const float v01 = (a0 && b1) ? p[sb] : 0.f;
+        const float v11 = (a1 && b1) ? p[sa + sb] : 0.f;
+        const float lo_b = fmaf(fa, v10 - v00, v00);
+        const float hi_b = fmaf(fa, v11 - v01, v01);
+        part += fmaf(fb, hi_b - lo_b, lo_b);
+        Fa += Sa;
+        Fb += Sb;
+        if (++cnt == kFlush) {
+          sum += (double)part;
+          part = 0.f;
+          cnt = 0;
+        }
+      }
+      sum += (double)part;
+    }
+    sum *= G.scale;
+  }
+  const size_t o = ((size_t)slot * n + (ok ? q : 0)) * n + (ok ? t : 0);
+  double d = 0.0;
+  if (ok) {
+    double v = sum;
+    if (sub) v -= (double)sub[((size_t)ids.id[slot] * n + q) * n + t];
+    if (pd) {
+      const double pv = pd[o];
+      v = fma(lam, pv, v);
+      d = pv * v;
+    }
+    if (out64) out64[o] = v;
+    if (out32) out32[o] = (float)v;
+  }
+  if (dots) {
+    const double s = block_sum(d, sh);
+    if (threadIdx.x == 0)
+      dots[((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = s;
+  }
+}
+
+template <typename VT>
+__global__ __launch_bounds__(256) void back3_kernel(
+    const DirGeom* __restrict__ geom, DirList ids, int N, int n, const VT* __restrict__ v,
+    float* __restrict__ out, float* __restrict__ x, const float* __restrict__ x_true,
+    double* __restrict__ partials, int mode, const int* __restrict__ ctl) {
+  if (ctl && ctl[kCtlDone]) return;
+  __shared__ float sv[kFP * kFP];
+  __shared__ double sh[4];
+  const int tid = threadIdx.x;
+  const int j = blockIdx.x * kVX + (tid & (kVX - 1));
+  const int i = blockIdx.y * kVY + ((tid / kVX) & (kVY - 1));
+  const int k = blockIdx.z * kVZ + tid / (kVX * kVY);
+  const bool ok = i < N && j < N && k < N;
+  const double hN = 0.5 * (N - 1), hn = 0.5 * (n - 1);
+  const double cx = j - hN, cy = i - hN, cz = k - hN;                 // centre / h
+  const double tx0 = blockIdx.x * kVX - hN, ty0 = blockIdx.y * kVY - hN, tz0 = blockIdx.z * kVZ - hN;
+  float acc = 0.f;
+  for (int s = 0; s < ids.n; ++s) {
+    const DirGeom G = geom[ids.id[s]];
+    // detector window of the tile: its voxels' projections, floor - 1 .. floor + 2,
+    // with one more pixel on the low side for rounding between fu and umin
+    const double ub = tx0 * G.eu[0] + ty0 * G.eu[1] + tz0 * G.eu[2] + hn;
+    const double vb = tx0 * G.ev[0] + ty0 * G.ev[1] + tz0 * G.ev[2] + hn;
+    const double umin = ub + fmin(0.0, (kVX - 1) * G.eu[0]) + fmin(0.0, (kVY - 1) * G.eu[1]) +
+                        fmin(0.0, (kVZ - 1) * G.eu[2]);
+    const double vmin = vb + fmin(0.0, (kVX - 1) * G.ev[0]) + fmin(0.0, (kVY - 1) * G.ev[1]) +
+                        fmin(0.0, (kVZ - 1) * G.ev[2]);
+    const int t0 = (int)floor(umin) - 2, q0 = (int)floor(vmin) - 2;
+    const float sc = (float)G.scale;
+    const VT* vs = v + (size_t)s * n * n;
+    __syncthreads();  // the previous direction's reads are done
+    for (int e = tid; e < kFP * kFP; e += 256) {
+      const int tq = q0 + e / kFP, tt = t0 + e % kFP;
+      float val = 0.f;
+      if ((unsigned)tq < (unsigned)n && (unsigned)tt < (unsigned)n)
+        val = (float)vs[(size_t)tq * n + tt] * sc;
+      sv[e] = val;
+    }
+    __syncthreads();
+    if (ok) {
+      const double fu = cx * G.eu[0] + cy * G.eu[1] + cz * G.eu[2] + hn;
+      const double fv = cx * G.ev[0] + cy * G.ev[1] + cz * G.ev[2] + hn;
+      const double flu = floor(fu), flv = floor(fv);
+      const float du0 = (float)(flu - fu), dv0 = (float)(flv - fv);
+      // 1 .. 14 for every voxel of the tile; clamped so that no read leaves the window
+      const int lt = min(max((int)flu - 1 - t0, 0), kFP - 4);
+      const int lq = min(max((int)flv - 1 - q0, 0), kFP - 4);
+      const float la0 = (float)G.La[0], la1 = (float)G.La[1];
+      const float lb0 = (float)G.Lb[0], lb1 = (float)G.Lb[1];
+      float du[4];
+#pragma unroll
+      for (int o = 0; o < 4; ++o) du[o] = du0 + (float)(o - 1);
+#pragma unroll
+      for (int oq = 0; oq < 4; ++oq) {
+        const float dv = dv0 + (float)(oq - 1);
+        const float ra = la1 * dv, rb = lb1 * dv;
+        const float* row = sv + (lq + oq) * kFP + lt;
+#pragma unroll
+        for (int ot = 0; ot < 4; ++ot) {
+          const float wa = unit_clamp(1.f - fabsf(fmaf(la0, du[ot], ra)));
+          const float wb = unit_clamp(1.f - fabsf(fmaf(lb0, du[ot], rb)));
+          acc = fmaf(wa * wb, row[ot], acc);
+        }
+      }
+    }
+  }
+  const size_t idx = ((size_t)(ok ? k : 0) * N + (ok ? i : 0)) * N + (ok ? j : 0);
+  if (mode == 0) {
+    if (ok) out[idx] = acc;
+    return;
+  }
+  double n0 = 0.0, n1 = 0.0, n2 = 0.0;
+  if (ok) {
+    const float xn = x[idx] - acc;
+    x[idx] = xn;
+    n0 = (double)acc * acc;
+    n1 = (double)xn * xn;
+    if (x_true) {
+      const double e = (double)xn - (double)x_true[idx];
+      n2 = e * e;
+    }
+  }
+  n0 = block_sum(n0, sh);
+  n1 = block_sum(n1, sh);
+  n2 = block_sum(n2, sh);
+  if (tid == 0) {
+    const size_t wg = ((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+    partials[wg * 3 + 0] = n0;
+    partials[wg * 3 + 1] = n1;
+    partials[wg * 3 + 2] = n2;
+  }
+}
+
+// ---------------------------------------------------------------- CG
+enum { SC_RR = 0, SC_RR0, SC_ALPHA, SC_TOL2, SC_PQ, SC_BETA, SC_COUNT };
+
+__device__ double fixed_sum(const double* __restrict__ a, int n, double* sh) {
+  double v = 0.0;
+  for (int k = threadIdx.x; k < n; k += 256) v += a[k];
+  return block_sum(v, sh);
+}
+
+__global__ __launch_bounds__(256) void cg3_init_kernel(const double* __restrict__ e,
+                                                       double* __restrict__ r,
+                                                       double* __restrict__ pd,
+                                                       double* __restrict__ z, int p,
+                                                       double* __restrict__ parts) {
+  __shared__ double sh[4];
+  const int o = blockIdx.x * 256 + threadIdx.x;
+  double d = 0.0;
+  if (o < p) {
+    const double v = e[o];
+    r[o] = v;
+    pd[o] = v;
+    z[o] = 0.0;
+    d = v * v;
+  }
+  d = block_sum(d, sh);
+  if (threadIdx.x == 0) parts[blockIdx.x] = d;
+}
+
+__global__ __launch_bounds__(256) void cg3_start_kernel(const double* __restrict__ parts, int np,
+                                                        double* __restrict__ sc,
+                                                        int* __restrict__ ctl, double tol2) {
+  __shared__ double sh[4];
+  const double rr = fixed_sum(parts, np, sh);
+  if (threadIdx.x == 0) {
+    sc[SC_RR] = rr;
+    sc[SC_RR0] = rr;
+    sc[SC_TOL2] = tol2;
+    ctl[kCtlDone] = rr > 0.0 ? 0 : 1;
+    ctl[kCtlIters] = 0;
+    ctl[2] = 0;
+  }
+}
+
+__global__ __launch_bounds__(256) void cg3_alpha_kernel(const double* __restrict__ dots, int nd,
+                                                        double* __restrict__ sc,
+                                                        int* __restrict__ ctl) {
+  if (ctl[kCtlDone]) return;
+  __shared__ double sh[4];
+  const double pq = fixed_sum(dots, nd, sh);
+  if (threadIdx.x == 0) {
+    sc[SC_PQ] = pq;
+    if (pq > 0.0 && isfinite(pq)) {
+      sc[SC_ALPHA] = sc[SC_RR] / pq;
+    } else {  // breakdown: stop with the current z
+      ctl[kCtlDone] = 1;
+      ctl[2] = 1;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void cg3_update_kernel(double* __restrict__ z,
+                                                         double* __restrict__ r,
+                                                         const double* __restrict__ pd,
+                                                         const double* __restrict__ q, int p,
+                                                         double* __restrict__ parts,
+                                                         const double* __restrict__ sc,
+                                                         const int* __restrict__ ctl) {
+  if (ctl[kCtlDone]) return;
+  __shared__ double sh[4];
+  const double alpha = sc[SC_ALPHA];
+  const int o = blockIdx.x * 256 + threadIdx.x;
+  double d = 0.0;
+  if (o < p) {
+    z[o] = fma(alpha, pd[o], z[o]);
+    const double rn = fma(-alpha, q[o], r[o]);
+    r[o] = rn;
+    d = rn * rn;
+  }
+  d = block_sum(d, sh);
+  if (threadIdx.x == 0) parts[blockIdx.x] = d;
+}
+
+__global__ __launch_bounds__(256) void cg3_rr_kernel(const double* __restrict__ parts, int np,
+                                                     double* __restrict__ sc,
+                                                     int* __restrict__ ctl) {
+  if (ctl[kCtlDone]) return;
+  __shared__ double sh[4];
+  const double rr = fixed_sum(parts, np, sh);
+  if (threadIdx.x == 0) {
+    ctl[kCtlIters] += 1;
+    if (rr <= sc[SC_TOL2] * sc[SC_RR0] || !isfinite(rr)) {
+      ctl[kCtlDone] = 1;
+      if (!isfinite(rr)) ctl[2] = 1;
+    } else {
+      sc[SC_BETA] = rr / sc[SC_RR];
+    }
+    sc[SC_RR] = rr;
+  }
+}
+
+__global__ __launch_bounds__(256) void cg3_pd_kernel(const double* __restrict__ r,
+                                                     double* __restrict__ pd, int p,
+                                                     const double* __restrict__ sc,
+                                                     const int* __restrict__ ctl) {
+  if (ctl[kCtlDone]) return;
+  const double beta = sc[SC_BETA];
+  const int o = blockIdx.x * 256 + threadIdx.x;
+  if (o < p) pd[o] = fma(beta, pd[o], r[o]);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- launchers
+int fwd3_num_workgroups(int n, int n_ids) {
+  const int g = (n + kRT - 1) / kRT;
+  return g * g * n_ids;
+}
+
+hipError_t launch_fwd3(const Fwd3Args& a, hipStream_t st) {
+  if (a.ids.n <= 0) return hipSuccess;
+  const int g = (a.n + kRT - 1) / kRT;
+  hipLaunchKernelGGL(fwd3_kernel, dim3(g, g, a.ids.n), dim3(256), 0, st, a.geom, a.ids, a.N, a.n,
+                     a.x, a.sub, a.out32, a.out64, a.pd, a.lam, a.dots, a.ctl);
+  return hipGetLastError();
+}
+
+int64_t back3_num_workgroups(int N) {
+  return (int64_t)((N + kVX - 1) / kVX) * ((N + kVY - 1) / kVY) * ((N + kVZ - 1) / kVZ);
+}
+
+hipError_t launch_back3(const Back3Args& a, hipStream_t st) {
+  const dim3 grid((a.N + kVX - 1) / kVX, (a.N + kVY - 1) / kVY, (a.N + kVZ - 1) / kVZ);
+  if (a.v64)
+    hipLaunchKernelGGL(back3_kernel<double>, grid, dim3(256), 0, st, a.geom, a.ids, a.N, a.n, a.v64,
+                       a.out, a.x, a.x_true, a.partials, a.mode, a.ctl);
+  else
+    hipLaunchKernelGGL(back3_kernel<float>, grid, dim3(256), 0, st, a.geom, a.ids, a.N, a.n, a.v32,
+                       a.out, a.x, a.x_true, a.partials, a.mode, a.ctl);
+  return hipGetLastError();
+}
+
+int cg3_num_parts(int p) { return (p + 255) / 256; }
+
+hipError_t launch_cg3_init(const double* e, double* r, double* pd, double* z, int p, double* parts,
+                           int nparts_cap, double* sc, int* ctl, double tol2, hipStream_t st) {
+  const int np = cg3_num_parts(p);
+  if (np > nparts_cap) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(cg3_init_kernel, dim3(np), dim3(256), 0, st, e, r, pd, z, p, parts);
+  hipLaunchKernelGGL(cg3_start_kernel, dim3(1), dim3(256), 0, st, parts, np, sc, ctl, tol2);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg3_alpha(const double* dots, int nd, double* sc, int* ctl, hipStream_t st) {
+  hipLaunchKernelGGL(cg3_alpha_kernel, dim3(1), dim3(256), 0, st, dots, nd, sc, ctl);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg3_update(double* z, double* r, const double* pd, const double* q, int p,
+                             double* parts, double* sc, int* ctl, hipStream_t st) {
+  hipLaunchKernelGGL(cg3_update_kernel, dim3(cg3_num_parts(p)), dim3(256), 0, st, z, r, pd, q, p,
+                     parts, sc, ctl);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg3_beta(double* r, double* pd, int p, const double* parts, double* sc, int* ctl,
+                           hipStream_t st) {
+  hipLaunchKernelGGL(cg3_rr_kernel, dim3(1), dim3(256), 0, st, parts, cg3_num_parts(p), sc, ctl);
+  hipLaunchKernelGGL(cg3_pd_kernel, dim3(cg3_num_parts(p)), dim3(256), 0, st, r, pd, p, sc, ctl);
+  return hipGetLastError();
+}
+
+}  // namespace slim

@@ -1,0 +1,97 @@
+// Internal declarations of the 3D parallel-beam path: the per-direction
+// geometry table and the launchers of its projectors and CG kernels.
+#pragma once
+
+#include "slim_internal.h"
+
+namespace slim {
+
+// Per-direction geometry.  Voxel (k, i, j) has centre ((j, i, k) - hN) h with
+// hN = (N-1)/2; a ray (q, t) of the n_det x n_det detector is
+// {(t - hn) h e_u + (q - hn) h e_v + tau w} with hn = (n_det-1)/2.  With m the
+// major axis of w and a, b the other two, the ray crosses the plane of voxel
+// index k along m at index coordinates (in voxels, along a and b)
+//     f_a(k) = hN + (t - hn) La[0] + (q - hn) La[1] + (k - hN) sa,
+// (f_b likewise), La = (e_u[a] - e_u[m] sa, e_v[a] - e_v[m] sa), sa = w_a/w_m.
+// For a voxel c the displacement from its own ray's crossing point, in
+// voxels, is (P - c)_a = La[0] du + La[1] dv with (du, dv) the detector
+// offset (in pixels) of the ray from the voxel's projection
+// (c.e_u / h + hn, c.e_v / h + hn); only |du| < |e_u[a]| + |e_u[b]| <= sqrt 2
+// (dv likewise) can give a non-zero weight.
+struct DirGeom {
+  double eu[3], ev[3];   // detector basis
+  double La[2], Lb[2];   // crossing-point displacement per detector pixel
+  double sa, sb;         // crossing-point change per plane along m
+  double scale;          // h / |w_m|
+  int m, a, b;           // major axis, the other two (x = 0, y = 1, z = 2)
+  int pad;
+};
+
+// Directions of one launch (a window of r+1 blocks of g directions).
+struct DirList {
+  int n;
+  int id[kMaxList];
+};
+
+// Forward projection over the directions of ids (slot s = ids.id[s]):
+//   v[s][q][t] = sum A[(ids[s],q,t), voxel] x[voxel]   (float64 ray sums)
+// minus sub[ids[s]][q][t] when sub is given (the data, [n_dirs][n][n]),
+// written to out64 / out32 [s][q][t].  CG tail when pd is given:
+// out64 = v + lam pd, per-workgroup partial sums of pd . out64 into dots
+// (fwd3_num_workgroups values, fixed order).  Returns at entry when
+// ctl[kCtlDone] is set.
+struct Fwd3Args {
+  const DirGeom* geom = nullptr;
+  DirList ids;
+  int N = 0, n = 0;
+  const float* x = nullptr;
+  const float* sub = nullptr;
+  float* out32 = nullptr;
+  double* out64 = nullptr;
+  const double* pd = nullptr;
+  double lam = 0.0;
+  double* dots = nullptr;
+  const int* ctl = nullptr;
+};
+hipError_t launch_fwd3(const Fwd3Args& a, hipStream_t st);
+int fwd3_num_workgroups(int n, int n_ids);
+
+// Back-projection over the directions of ids, the exact adjoint of the
+// forward: s[voxel] = sum_s sum_(q,t) A[(ids[s],q,t), voxel] v[s][q][t] with v
+// float32 (v32) or float64 (v64), [s][q][t].  mode 0: out = s.  mode 1:
+// x -= s in place and per-workgroup float64 partial norms (||s||^2,
+// ||x_new||^2, ||x_new - x_true||^2) into partials[wg * 3 + k]
+// (back3_num_workgroups values).  Returns at entry when ctl[kCtlDone] is set.
+struct Back3Args {
+  const DirGeom* geom = nullptr;
+  DirList ids;
+  int N = 0, n = 0;
+  const float* v32 = nullptr;
+  const double* v64 = nullptr;
+  float* out = nullptr;
+  float* x = nullptr;
+  const float* x_true = nullptr;
+  double* partials = nullptr;
+  int mode = 0;
+  const int* ctl = nullptr;
+};
+hipError_t launch_back3(const Back3Args& a, hipStream_t st);
+int64_t back3_num_workgroups(int N);
+
+// CG on (lam I + M M^T) z = e in float64 (e: p entries), matrix-free:
+//   init:  r = e, pd = e, z = 0, rr = rr0 = e.e (ctl done if e = 0)
+//   iteration: u = M^T pd (back), q = M u + lam pd with partial dots
+//   (forward tail), alpha = rr / pd.q, z += alpha pd, r -= alpha q,
+//   rr' = r.r, stop when rr' <= tol^2 rr0, else pd = r + (rr'/rr) pd.
+// sc holds the scalars [rr, rr0, alpha, tol^2, pq]; ctl [done, iterations].
+hipError_t launch_cg3_init(const double* e, double* r, double* pd, double* z, int p,
+                           double* parts, int nparts_cap, double* sc, int* ctl, double tol2,
+                           hipStream_t st);
+hipError_t launch_cg3_alpha(const double* dots, int nd, double* sc, int* ctl, hipStream_t st);
+hipError_t launch_cg3_update(double* z, double* r, const double* pd, const double* q, int p,
+                             double* parts, double* sc, int* ctl, hipStream_t st);
+hipError_t launch_cg3_beta(double* r, double* pd, int p, const double* parts, double* sc,
+                           int* ctl, hipStream_t st);
+int cg3_num_parts(int p);
+
+}  // namespace slim

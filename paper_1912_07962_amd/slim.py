@@ -17,7 +17,8 @@ import torch  # loads the HIP runtime first, so libslim binds to the same one
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "_lib", "libslim.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "slim.h")
-HEADERS = [HEADER, os.path.join(os.path.dirname(_HERE), "include", "slim_cnn.h")]
+HEADERS = [HEADER, os.path.join(os.path.dirname(_HERE), "include", "slim_cnn.h"),
+           os.path.join(os.path.dirname(_HERE), "include", "slim3d.h")]
 
 SLIM_OK, SLIM_EINVAL, SLIM_ENOMEM, SLIM_EDEVICE, SLIM_ENUMERIC, SLIM_ENOTCONV, SLIM_ESTATE = range(7)
 PREC = {"fp32": 0, "bf16": 1}
@@ -121,6 +122,15 @@ def load() -> ctypes.CDLL:
         "slim_cnn_forward_flops": (D, [P]),
         "slim_cnn_destroy": (None, [P]),
         "slim_destroy": (None, [P]),
+        "slim3d_init": (I, [ctypes.POINTER(P), I, I, ctypes.POINTER(D), I, I, D,
+                            ctypes.POINTER(Opts)]),
+        "slim3d_set_data": (I, [P, P, P, P]),
+        "slim3d_step": (I, [P, i32p, I, ctypes.POINTER(StepInfo)]),
+        "slim3d_project": (I, [P, i32p, I, P, P]),
+        "slim3d_backproject": (I, [P, i32p, I, P, P]),
+        "slim3d_profile": (I, [P, I]),
+        "slim3d_kernel_stats": (I, [P, I, ctypes.POINTER(D), ctypes.POINTER(ctypes.c_int64)]),
+        "slim3d_destroy": (None, [P]),
         "slim_strerror": (ctypes.c_char_p, [I]),
         "slim_last_error": (ctypes.c_char_p, []),
     }
@@ -133,9 +143,10 @@ def load() -> ctypes.CDLL:
 
 
 def header_symbols() -> list[str]:
-    """Names of the functions declared in include/slim.h and slim_cnn.h."""
+    """Names of the functions declared in include/slim.h, slim_cnn.h and
+    slim3d.h."""
     txt = "".join(open(h).read() for h in HEADERS)
-    return sorted(set(re.findall(r"\b(slim_[a-z_]+)\s*\(", txt)))
+    return sorted(set(re.findall(r"\b(slim(?:3d)?_[a-z_]+)\s*\(", txt)))
 
 
 def _check(st: int):
@@ -410,6 +421,93 @@ def init_error(**kw) -> int:
     if st == SLIM_OK:
         lib.slim_destroy(h)
     return st
+
+
+class Slim3D:
+    """A 3D parallel-beam slimLS context (projection images from arbitrary
+    directions) bound to the current device and torch stream."""
+
+    KINDS = {"cg_forward": 0, "cg_back": 1, "cg_vector": 4, "residual": 5, "update": 6}
+
+    def __init__(self, N: int, dirs, n_det: int | None = None, r: int = 0, lam: float = 1e-2,
+                 dirs_per_block: int = 1, pcg_max_iter: int = 1000, pcg_tol: float = 1e-6,
+                 stream=None):
+        lib = load()
+        self._dirs = np.ascontiguousarray(np.asarray(dirs, dtype=np.float64).reshape(-1, 3))
+        self.N, self.n_dirs = int(N), int(self._dirs.shape[0])
+        self.n_det = int(N if n_det is None else n_det)
+        self.r, self.lam, self.g = int(r), float(lam), int(dirs_per_block)
+        o = Opts()
+        lib.slim_default_opts(ctypes.byref(o))
+        o.angles_per_block = self.g
+        o.pcg_max_iter = int(pcg_max_iter)
+        o.pcg_tol = float(pcg_tol)
+        if stream is None and torch.cuda.is_available():
+            stream = torch.cuda.current_stream()
+        o.stream = ctypes.c_void_p(stream.cuda_stream if stream is not None else 0)
+        self.stream = stream
+        h = ctypes.c_void_p()
+        _check(lib.slim3d_init(ctypes.byref(h), self.N, self.n_dirs,
+                               self._dirs.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                               self.n_det, self.r, self.lam, ctypes.byref(o)))
+        self._h = h
+        self._keep = []
+
+    def set_data(self, b, x, x_true=None):
+        nb, nx = self.n_dirs * self.n_det * self.n_det, self.N ** 3
+        for t, n, name in ((b, nb, "b"), (x, nx, "x"), (x_true, nx, "x_true")):
+            if t is not None and t.numel() != n:
+                raise ValueError(f"{name} has {t.numel()} elements, expected {n}")
+        self._keep = [b, x, x_true]
+        _check(load().slim3d_set_data(self._h, _ptr(b, torch.float32, "b"),
+                                      _ptr(x, torch.float32, "x"),
+                                      _ptr(x_true, torch.float32, "x_true")))
+
+    def step(self, dir_ids, read: bool = True) -> dict | None:
+        a, p, n = _ids(dir_ids)
+        info = StepInfo()
+        _check(load().slim3d_step(self._h, p, n, ctypes.byref(info) if read else None))
+        if not read:
+            return None
+        return {f: getattr(info, f) for f, _ in StepInfo._fields_}
+
+    def project(self, dir_ids, x, out=None):
+        a, p, n = _ids(dir_ids)
+        if out is None:
+            out = torch.empty((n, self.n_det, self.n_det), dtype=torch.float32, device=x.device)
+        _check(load().slim3d_project(self._h, p, n, _ptr(x, torch.float32, "x"),
+                                     _ptr(out, torch.float32, "out")))
+        return out
+
+    def backproject(self, dir_ids, v, out=None):
+        a, p, n = _ids(dir_ids)
+        if out is None:
+            out = torch.empty((self.N, self.N, self.N), dtype=torch.float32, device=v.device)
+        _check(load().slim3d_backproject(self._h, p, n, _ptr(v, torch.float32, "v"),
+                                         _ptr(out, torch.float32, "out")))
+        return out
+
+    def profile(self, on: bool = True):
+        _check(load().slim3d_profile(self._h, int(bool(on))))
+
+    def kernel_stats(self) -> dict:
+        out = {}
+        for name, k in self.KINDS.items():
+            ms, n = ctypes.c_double(), ctypes.c_int64()
+            _check(load().slim3d_kernel_stats(self._h, k, ctypes.byref(ms), ctypes.byref(n)))
+            out[name] = {"total_ms": ms.value, "launches": n.value}
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().slim3d_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Group:

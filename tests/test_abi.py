@@ -95,3 +95,46 @@ def test_cnn_layout_counts():
     assert names[-3:] == ["head.w", "head.b", "head.cu"]
     assert len(names) == 2 * 17 + 3
     assert sum(int(np.prod(s)) for _, s in lay) == 2140066
+
+
+def _init3d(N=16, n_dirs=4, dirs="unit", n_det=16, r=0, lam=1e-2, **opt):
+    lib = slim.load()
+    o = slim.Opts()
+    lib.slim_default_opts(ctypes.byref(o))
+    for k, v in opt.items():
+        setattr(o, k, v)
+    if isinstance(dirs, str):
+        d = np.zeros((max(n_dirs, 1), 3))
+        d[:, 2] = 1.0 if dirs == "unit" else 1.5
+        if dirs == "nan":
+            d[0, 0] = float("nan")
+        dp = d.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    else:
+        d, dp = None, None
+    h = ctypes.c_void_p()
+    st = lib.slim3d_init(ctypes.byref(h), N, n_dirs, dp, n_det, r, lam, ctypes.byref(o))
+    assert st != slim.SLIM_OK or h.value is not None
+    if st == slim.SLIM_OK:
+        lib.slim3d_destroy(h)
+    return st
+
+
+@pytest.mark.parametrize("kw", [
+    dict(N=1), dict(N=2000), dict(n_dirs=0), dict(dirs=None), dict(dirs="long"), dict(dirs="nan"),
+    dict(n_det=0), dict(n_det=5000), dict(r=-1), dict(lam=0.0), dict(lam=float("inf")),
+    dict(angles_per_block=3), dict(precision=1), dict(gram_mode=1), dict(tikhonov=0.1),
+    dict(pcg_max_iter=0), dict(r=300),
+])
+def test_init3d_rejects_bad_arguments(kw):
+    assert _init3d(**kw) == slim.SLIM_EINVAL
+    assert slim.load().slim_last_error() != b""
+
+
+def test_null_3d_handles_are_rejected():
+    lib = slim.load()
+    assert lib.slim3d_set_data(None, None, None, None) == slim.SLIM_EINVAL
+    assert lib.slim3d_step(None, None, 0, None) == slim.SLIM_EINVAL
+    assert lib.slim3d_project(None, None, 0, None, None) == slim.SLIM_EINVAL
+    assert lib.slim3d_backproject(None, None, 0, None, None) == slim.SLIM_EINVAL
+    assert lib.slim3d_profile(None, 1) == slim.SLIM_EINVAL
+    lib.slim3d_destroy(None)
