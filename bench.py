@@ -379,6 +379,120 @@ def volume_bench(dev, B, steps, autotune=True):
 
 
 
+def crossings3(N, n_det, w):
+    """Ray-plane crossings inside the volume of one direction (each carries
+    up to four non-zero bilinear weights): the walk of the 3D forward
+    projector, counted on the host."""
+    import numpy as np
+    import synth
+    w = np.asarray(w, np.float64)
+    eu, ev = synth.detector_basis(w)
+    m = int(np.argmax(np.abs(w)))
+    a, b = [k for k in range(3) if k != m]
+    hN, hn = (N - 1) / 2.0, (n_det - 1) / 2.0
+    t = np.arange(n_det) - hn
+    T, Q = np.meshgrid(t, t)
+    lo = np.zeros_like(T)
+    hi = np.full_like(T, N - 1.0)
+    for ax in (a, b):
+        s = w[ax] / w[m]
+        f0 = hN + T * (eu[ax] - eu[m] * s) + Q * (ev[ax] - ev[m] * s) - hN * s
+        if s != 0.0:
+            e1, e2 = (-1.0 - f0) / s, (N - f0) / s
+            lo = np.maximum(lo, np.minimum(e1, e2))
+            hi = np.minimum(hi, np.maximum(e1, e2))
+        else:
+            hi = np.where((f0 > -1.0) & (f0 < N), hi, -1.0)
+    return float(np.clip(np.floor(hi) - np.ceil(lo) + 1, 0, None).sum())
+
+
+def proj3d_bench(dev, steps):
+    """The paper's 3D experiment: a 511^3 volume, projection images of
+    511 x 511 pixels from 1000 directions uniform on the sphere, one image per
+    block, r = 0, alpha = 1 in unit-voxel scaling (lambda = h^2), 0.1% noise,
+    CG to 1e-6: one-direction projector rays/s, then whole slimLS steps."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_1912_07962_amd import Slim3D
+
+    cfg = synth.get_config("c3d")
+    N, n, nd, r, lam = cfg["N"], cfg["n_det"], cfg["n_dirs"], cfg["r"], cfg["lam"]
+    sched = synth.schedule(nd, 1, cfg["schedule_seed"])
+    visit = [int(v) for v in sched[:steps + 1]]
+    print(f"bench: 3D {N}^3 inputs ({len(visit)} directions)", file=sys.stderr, flush=True)
+    x_true, b, dirs = synth.make_problem3(N, nd, n, cfg["n_ellipsoids"], cfg["noise"],
+                                          cfg["phantom_seed"], cfg["dir_seed"], cfg["noise_seed"],
+                                          dir_ids=visit)
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        xt = torch.as_tensor(x_true, dtype=torch.float32, device=dev)
+        bd = torch.as_tensor(b, dtype=torch.float32, device=dev)
+        x = torch.zeros((N, N, N), dtype=torch.float32, device=dev)
+        v = torch.randn((1, n, n), device=dev)
+        out_f = torch.empty((1, n, n), device=dev)
+        out_b = torch.empty((N, N, N), device=dev)
+    st.synchronize()
+    del x_true, b
+    s = Slim3D(N, dirs, n_det=n, r=r, lam=lam, pcg_tol=1e-6, stream=st)
+
+    def _time(fn, reps=10):
+        fn()
+        st.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(reps):
+            fn()
+        e1.record(st)
+        st.synchronize()
+        return e0.elapsed_time(e1) / reps * 1e-3
+
+    proj = []
+    for d in visit[:2]:
+        t_f = _time(lambda: s.project([d], xt, out_f))
+        t_b = _time(lambda: s.backproject([d], v, out_b))
+        cross = crossings3(N, n, dirs[d])
+        proj.append({"dir": d, "fwd_us": t_f * 1e6, "back_us": t_b * 1e6,
+                     "fwd_rays_per_s": n * n / t_f, "back_rays_per_s": n * n / t_b,
+                     "fwd_back_rays_per_s": n * n / (t_f + t_b),
+                     # algorithmic traffic: the volume once and the image once each way
+                     "fwd_hbm_frac": (4.0 * N ** 3 + 4.0 * n * n) / t_f / 1e9 / PEAK_HBM_GBS,
+                     "back_hbm_frac": (4.0 * N ** 3 + 4.0 * n * n) / t_b / 1e9 / PEAK_HBM_GBS,
+                     "crossings": cross,
+                     "fwd_alu_tflops": 2 * 4.0 * cross / t_f / 1e12,
+                     "back_alu_tflops": 2 * 4.0 * cross / t_b / 1e12})
+    del out_f, out_b, v
+    s.set_data(bd, x, xt)
+    s.step([visit[0]])                          # first step: untimed
+    st.synchronize()
+    t0 = time.perf_counter()
+    infos = []
+    for d in visit[1:]:
+        infos.append(s.step([d]))
+    st.synchronize()
+    wall = time.perf_counter() - t0
+    # the same steps' kernels timed one by one on a second pass over fresh data
+    s.set_data(bd, x.zero_(), xt)
+    s.profile(True)
+    for d in visit:
+        s.step([d])
+    stats = s.kernel_stats()
+    s.profile(False)
+    it = sum(i["pcg_iters"] for i in infos)
+    cg_f = stats["cg_forward"]["total_ms"] / max(stats["cg_forward"]["launches"], 1)
+    cg_b = stats["cg_back"]["total_ms"] / max(stats["cg_back"]["launches"], 1)
+    s.close()
+    rel = [i["err_norm"] / float(np.linalg.norm(xt.cpu().numpy().astype(np.float64)))
+           for i in infos[-1:]]
+    print(f"bench: 3D step {wall / len(infos) * 1e3:.1f} ms, {it / len(infos):.1f} CG iterations",
+          file=sys.stderr, flush=True)
+    return {"N": N, "n_det": n, "n_dirs": nd, "r": r, "lambda": lam, "steps": len(infos),
+            "ms_per_step": wall / len(infos) * 1e3, "rays_per_s": n * n * len(infos) / wall,
+            "cg_iters_per_step": it / len(infos), "rel_err_last": rel[0],
+            "cg_forward_us": cg_f * 1e3, "cg_back_us": cg_b * 1e3,
+            "kernel_ms": {k: v2["total_ms"] for k, v2 in stats.items()}, "projector": proj}
+
+
 def gram_bench(dev, steps):
     """Explicit Gram mode on the 256^2 workload (180 angles x 363 rays, 1
     angle/block, r = 5, lambda = 1e-2, p = 6 x 363 = 2178): per-step times of
@@ -685,6 +799,8 @@ def main():
                     help="Tikhonov parameter of the slimTik leg")
     ap.add_argument("--mixed-steps", type=int, default=3,
                     help="timed steps of the mixed batch (0 skips it)")
+    ap.add_argument("--proj3d-steps", type=int, default=3,
+                    help="timed steps of the 3D random-direction workload (0 skips it)")
     ap.add_argument("--gram-steps", type=int, default=20,
                     help="timed steps of the explicit-Gram (FP64 Cholesky) 256^2 run (0 skips it)")
     ap.add_argument("--warm-test", type=int, default=256,
@@ -871,6 +987,10 @@ def main():
     if args.volume_slices > 0:
         volume = volume_bench(dev, args.volume_slices, args.volume_steps, not args.no_autotune)
 
+    p3d = None
+    if args.proj3d_steps > 0:
+        p3d = proj3d_bench(dev, args.proj3d_steps)
+
     cpu = None
     if not args.no_cpu_baseline:
         print("bench: cpu baseline (FP64 oracle)", file=sys.stderr, flush=True)
@@ -908,6 +1028,7 @@ def main():
         "volume": volume,
         "mixed": mixed,
         "gram_solve": gram,
+        "proj3d": p3d,
         "warm_start": warm,
         "cg_iters_per_step": float(np.mean(iters)),
         "window_blocks_timed": r + 1,

@@ -94,13 +94,20 @@ def rasterize3(ells: list[Ellipsoid3], N: int, k0: int = 0, k1: int | None = Non
     h = 2.0 / N
     c = (np.arange(N, dtype=np.float64) - (N - 1) / 2.0) * h
     out = np.zeros((k1 - k0, N, N))
-    Y, X = np.meshgrid(c, c, indexing="ij")
-    for kk in range(k0, k1):
-        P = np.stack([X, Y, np.full_like(X, c[kk])], axis=-1)
-        for e in ells:
-            cen, F = _frame(e)
-            yv = (P - cen) @ F.T
-            out[kk - k0] += e.rho * (np.einsum("...i,...i->...", yv, yv) <= 1.0)
+    for e in ells:
+        cen, F = _frame(e)
+        # only voxels within the ellipsoid's bounding ball can be inside it
+        rad = max(e.axes)
+        lo = np.searchsorted(c, cen - rad, side="left")
+        hi = np.searchsorted(c, cen + rad, side="right")
+        kl, kh = max(lo[2], k0), min(hi[2], k1)
+        if kl >= kh or lo[0] >= hi[0] or lo[1] >= hi[1]:
+            continue
+        Z, Y, X = np.meshgrid(c[kl:kh], c[lo[1]:hi[1]], c[lo[0]:hi[0]], indexing="ij")
+        P = np.stack([X, Y, Z], axis=-1) - cen
+        yv = P @ F.T
+        out[kl - k0:kh - k0, lo[1]:hi[1], lo[0]:hi[0]] += \
+            e.rho * (np.einsum("...i,...i->...", yv, yv) <= 1.0)
     return out
 
 
