@@ -151,8 +151,11 @@ slim_status slim_set_data(slim_ctx* ctx, const void* b, void* x, const float* x_
  * [0, n_angles), no duplicates).  The block enters the memory window; the
  * oldest block leaves once the window holds r+1 blocks.  info may be NULL
  * (then nothing is read back and the stream is not synchronised).
- * Errors: SLIM_EINVAL (bad ids), SLIM_ESTATE (no data), SLIM_ENUMERIC,
- * SLIM_ENOTCONV (CG cap reached; the step is still applied), SLIM_EDEVICE. */
+ * Errors: SLIM_EINVAL (bad ids), SLIM_ESTATE (no data), SLIM_ENOMEM (the
+ * projector's workspace for this window does not fit; the step is not taken
+ * and the context is unchanged), SLIM_ENUMERIC, SLIM_ENOTCONV (CG cap
+ * reached; the step is still applied), SLIM_EDEVICE (the context is left
+ * unbound: rebind with slim_set_data before the next step). */
 slim_status slim_step(slim_ctx* ctx, const int32_t* angle_ids, int n_ids, slim_step_info* info);
 
 /* slim_step for streaming data (data bound with b = NULL).  The method needs
@@ -277,8 +280,11 @@ slim_status slim_group_create(slim_group** out, slim_ctx* const* ctxs, int n);
 
 /* One step of every context of the group (eq. (ram) with the same block).
  *  infos  host [n] or NULL (then nothing is read back).
- * Errors: as slim_step; after an error the contexts must be rebound with
- * slim_set_data. */
+ * Errors: as slim_step, and SLIM_ESTATE for a context bound to streaming
+ * data (b = NULL; step those with slim_step_data).  A step refused before any
+ * device work (bad ids, no data, streaming data, a workspace that does not
+ * fit) leaves every context as it was; after a device error every context
+ * of the group is left unbound and must be rebound with slim_set_data. */
 slim_status slim_group_step(slim_group* g, const int32_t* angle_ids, int n_ids,
                             slim_step_info* infos);
 void slim_group_destroy(slim_group* g);

@@ -84,8 +84,9 @@ slim_status slim3d_set_data(slim3d_ctx* ctx, const float* b, float* x, const flo
  * float64 norms.  info may be NULL (then nothing is read back; the CG's
  * host loop still synchronises the stream between chunks of iterations).
  * Errors: SLIM_EINVAL (bad ids), SLIM_ESTATE (no data), SLIM_ENUMERIC
- * (non-finite norm), SLIM_ENOTCONV (CG cap reached; the step is applied),
- * SLIM_EDEVICE. */
+ * (non-finite data, iterate or norm), SLIM_ENOTCONV (CG cap reached; the
+ * step is applied), SLIM_EDEVICE (the context is left unbound: rebind with
+ * slim3d_set_data). */
 slim_status slim3d_step(slim3d_ctx* ctx, const int32_t* dir_ids, int n_ids, slim_step_info* info);
 
 /* Forward projection out = A_ids x (ids host int32 [n_ids], repeats allowed,

@@ -448,15 +448,18 @@ void pcg_report(PcgRun& run, int* iters, double* relres) {
   const volatile int* ctl = w.h_ctl;   // final once the stream is synchronised
   int it_max = 0;
   double rel_max = 0.0;
+  bool finite = true;
   for (int b = 0; b < B; ++b) {
     const int it = ctl[b * kCtlCount + kCtlIters];
     const double* s0 = w.h_sc + (size_t)b * S_COUNT;   // set 0: <e, e> and the latest gamma
     it_max = std::max(it_max, it);
+    // a non-finite right-hand side (data or iterate) stops the CG at once
+    finite = finite && std::isfinite(s0[S_BB]) && std::isfinite(s0[S_LAST]);
     if (s0[S_BB] > 0.0) rel_max = std::max(rel_max, std::sqrt(s0[S_LAST] / s0[S_BB]));
   }
   w.last_iters = it_max;
   *iters = it_max;
-  *relres = rel_max;
+  *relres = finite ? rel_max : NAN;
 }
 
 hipError_t pcg_solve(PcgWork& w, const AngleGeom* geom, const AngleGeom* h_geom, float* partial,

@@ -260,7 +260,7 @@ __global__ __launch_bounds__(256) void cg3_start_kernel(const double* __restrict
     sc[SC_TOL2] = tol2;
     ctl[kCtlDone] = rr > 0.0 ? 0 : 1;
     ctl[kCtlIters] = 0;
-    ctl[2] = 0;
+    ctl[2] = isfinite(rr) ? 0 : 1;   // non-finite data or iterate
   }
 }
 

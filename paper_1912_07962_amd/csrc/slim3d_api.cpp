@@ -284,7 +284,8 @@ slim_status do_step3(slim3d_ctx* c, const int32_t* ids, slim_step_info* info) {
   }
   for (int q = 0; q < 3; ++q)
     if (!std::isfinite(c->h_out[q])) return set_error(SLIM_ENUMERIC, "non-finite norm");
-  if (c->h_ctl[2] != 0) return set_error(SLIM_ENUMERIC, "CG breakdown (non-positive curvature)");
+  if (c->h_ctl[2] != 0)
+    return set_error(SLIM_ENUMERIC, "non-finite CG right-hand side or breakdown (non-positive curvature)");
   if (relres > tol) return set_error(SLIM_ENOTCONV, "CG reached its iteration cap");
   return SLIM_OK;
 }
@@ -400,7 +401,9 @@ slim_status slim3d_step(slim3d_ctx* c, const int32_t* ids, int n_ids, slim_step_
   slim_status s = check_dir_ids(c, ids, n_ids, false);
   if (s != SLIM_OK) return s;
   if (!c->bound) return set_error(SLIM_ESTATE, "no data bound (slim3d_set_data)");
-  return do_step3(c, ids, info);
+  s = do_step3(c, ids, info);
+  if (s == SLIM_EDEVICE) c->bound = false;   // rebind before the next step
+  return s;
 }
 
 slim_status slim3d_project(slim3d_ctx* c, const int32_t* ids, int n_ids, const float* x,

@@ -224,15 +224,6 @@ AngleList make_list(const int32_t* ids, int n) {
   return l;
 }
 
-AngleList window_list(const slim_ctx* c) {
-  AngleList l;
-  l.n = 0;
-  for (int s : c->window)
-    for (int a : c->slot_ids[s]) l.id[l.n++] = a;
-  for (int i = l.n; i < kMaxList; ++i) l.id[i] = 0;
-  return l;
-}
-
 // Refresh the copies of x that the forward projector reads: x^T (float32),
 // or the bf16 shadows of x and x^T in the bf16-storage variant.
 slim_status transpose_slices(slim_ctx* c) {
@@ -326,25 +317,52 @@ struct StepState {
   PcgRun run;
 };
 
-slim_status step_begin(slim_ctx* c, const int32_t* ids, StepState& ss) {
+// The window after a step with block ids (slot k mod (r+1); the oldest
+// block leaves once r+1 are held), and the angle lists of the new block and
+// of that window, without changing the context.
+void plan_window(const slim_ctx* c, const int32_t* ids, StepState& ss, std::deque<int>& win) {
   const int S = c->r + 1;
   ss.slot = c->k % S;
-  ss.lam = lam_at(c, c->k + 1);
-  if ((int)c->window.size() == S) c->window.pop_front();
-  c->slot_ids[ss.slot].assign(ids, ids + c->g);
-  c->window.push_back(ss.slot);
+  win = c->window;
+  if ((int)win.size() == S) win.pop_front();
+  win.push_back(ss.slot);
   ss.blk = make_list(ids, c->g);
-  ss.win = window_list(c);
-  const int64_t ell = c->ell;
+  ss.win.n = 0;
+  for (int sl : win) {
+    if (sl == ss.slot)
+      for (int a = 0; a < c->g; ++a) ss.win.id[ss.win.n++] = ids[a];
+    else
+      for (int a : c->slot_ids[sl]) ss.win.id[ss.win.n++] = a;
+  }
+  for (int i = ss.win.n; i < kMaxList; ++i) ss.win.id[i] = 0;
+}
 
+// Host work of a step that can fail without touching the iteration state:
+// the forward projector's workspace for the new block and the window.
+slim_status step_prepare(slim_ctx* c, const StepState& ss) {
+  slim_status s = ensure_fpart(c, ss.blk);
+  if (s == SLIM_OK && (c->mode == SLIM_GRAM_PCG || c->o.tikhonov > 0.0)) s = ensure_fpart(c, ss.win);
+  return s;
+}
+
+// Everything up to the Gram solve.  The window is committed only after
+// step_prepare succeeded, so a refused step (workspace that does not fit)
+// leaves the context as it was; a failing device call (SLIM_EDEVICE) leaves
+// the context unbound (the caller rebinds with slim_set_data).
+slim_status step_begin(slim_ctx* c, const int32_t* ids, StepState& ss) {
+  std::deque<int> win;
+  plan_window(c, ids, ss, win);
+  ss.lam = lam_at(c, c->k + 1);
+  const int64_t ell = c->ell;
+  {
+    slim_status s = step_prepare(c, ss);
+    if (s != SLIM_OK) return s;
+  }
+  c->window = win;
+  c->slot_ids[ss.slot].assign(ids, ids + c->g);
   if (c->prof.on && c->prof.used > 4096) {
     HIP_TRY(hipStreamSynchronize(c->st));
     HIP_TRY(c->prof.harvest());
-  }
-  {
-    slim_status s = ensure_fpart(c, ss.blk);
-    if (s == SLIM_OK && (c->mode == SLIM_GRAM_PCG || c->o.tikhonov > 0.0)) s = ensure_fpart(c, ss.win);
-    if (s != SLIM_OK) return s;
   }
   // 1. residual of the new block, all slices in one launch
   if (c->prof.on) HIP_TRY(c->prof.begin(K_RESID, c->st));
@@ -461,12 +479,14 @@ slim_status step_end(slim_ctx* c, StepState& ss, slim_step_info* info) {
       if (!std::isfinite(c->h_norms[3 * sl + q])) return fail(SLIM_ENUMERIC, "non-finite norm");
   if (c->mode == SLIM_GRAM_CHOL && *c->h_info != 0)
     return fail(SLIM_ENUMERIC, "Cholesky pivot " + std::to_string(*c->h_info - 1) + " not positive");
+  if (c->mode == SLIM_GRAM_PCG && !std::isfinite(pcg_rel))
+    return fail(SLIM_ENUMERIC, "non-finite CG right-hand side (data or iterate not finite)");
   if (c->mode == SLIM_GRAM_PCG && pcg_rel > c->o.pcg_tol)
     return fail(SLIM_ENOTCONV, "CG reached its iteration cap");
   return SLIM_OK;
 }
 
-slim_status do_step(slim_ctx* c, const int32_t* ids, slim_step_info* info) {
+slim_status do_step_inner(slim_ctx* c, const int32_t* ids, slim_step_info* info) {
   StepState ss;
   slim_status s = step_begin(c, ids, ss);
   if (s != SLIM_OK) return s;
@@ -476,6 +496,14 @@ slim_status do_step(slim_ctx* c, const int32_t* ids, slim_step_info* info) {
     if (e != hipSuccess) return fail(SLIM_EDEVICE, std::string("pcg: ") + hipGetErrorString(e));
   }
   return step_end(c, ss, info);
+}
+
+// A device failure inside a step leaves the window and the device state out
+// of step with each other: the context must be rebound before the next step.
+slim_status do_step(slim_ctx* c, const int32_t* ids, slim_step_info* info) {
+  const slim_status s = do_step_inner(c, ids, info);
+  if (s == SLIM_EDEVICE) c->bound = false;
+  return s;
 }
 
 }  // namespace
@@ -1304,29 +1332,52 @@ slim_status slim_group_step(slim_group* g, const int32_t* ids, int n_ids, slim_s
     slim_status s = check_ids(c, ids, n_ids, false);
     if (s != SLIM_OK) return s;
     if (!c->bound) return fail(SLIM_ESTATE, "no data bound (slim_set_data)");
+    if (c->streaming)
+      return fail(SLIM_ESTATE, "streaming context: step it with slim_step_data, not in a group");
   }
   std::unique_ptr<StepState[]> ss(new StepState[n]);  // fixed addresses (CG runs)
+  // every context's fallible host work first, so that a refused step leaves
+  // all of them as they were
+  for (int i = 0; i < n; ++i) {
+    std::deque<int> win;
+    plan_window(g->ctx[i], ids, ss[i], win);
+    slim_status s = step_prepare(g->ctx[i], ss[i]);
+    if (s != SLIM_OK) return s;
+  }
+  auto unbind_all = [&]() {
+    for (slim_ctx* c : g->ctx) c->bound = false;
+  };
   for (int i = 0; i < n; ++i) {
     slim_status s = step_begin(g->ctx[i], ids, ss[i]);
-    if (s != SLIM_OK) return s;
+    if (s != SLIM_OK) {
+      unbind_all();
+      return s;
+    }
   }
   for (bool all = false; !all;) {
     all = true;
     for (int i = 0; i < n; ++i)
       if (ss[i].pcg && !ss[i].run.done) {
         hipError_t e = pcg_enqueue(ss[i].run, g->ctx[i]->graphs());
-        if (e != hipSuccess) return fail(SLIM_EDEVICE, std::string("pcg: ") + hipGetErrorString(e));
+        if (e != hipSuccess) {
+          unbind_all();
+          return fail(SLIM_EDEVICE, std::string("pcg: ") + hipGetErrorString(e));
+        }
       }
     for (int i = 0; i < n; ++i)
       if (ss[i].pcg && !ss[i].run.done) {
         hipError_t e = pcg_poll(ss[i].run);
-        if (e != hipSuccess) return fail(SLIM_EDEVICE, std::string("pcg: ") + hipGetErrorString(e));
+        if (e != hipSuccess) {
+          unbind_all();
+          return fail(SLIM_EDEVICE, std::string("pcg: ") + hipGetErrorString(e));
+        }
         all = all && ss[i].run.done;
       }
   }
   slim_status first = SLIM_OK;
   for (int i = 0; i < n; ++i) {
     slim_status s = step_end(g->ctx[i], ss[i], infos ? infos + i : nullptr);
+    if (s == SLIM_EDEVICE) g->ctx[i]->bound = false;
     if (s != SLIM_OK && first == SLIM_OK) first = s;
   }
   return first;

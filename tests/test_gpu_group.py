@@ -87,3 +87,34 @@ def test_group_argument_errors():
     g = Group([a])
     with pytest.raises(SlimError):
         g.step([0, 1])                # no data bound
+    # a context bound to streaming data is refused before any context moves
+    x1 = torch.zeros((32, 32), device="cuda")
+    a.set_data(torch.zeros((NA, a.R), device="cuda"), x1)
+    c = Slim(32, NA, r=1, lam=1e-2, angles_per_block=G)
+    c.set_data(None, torch.zeros((32, 32), device="cuda"))
+    g2 = Group([a, c])
+    with pytest.raises(SlimError) as e:
+        g2.step([0, 1])
+    assert e.value.status == 6
+    assert a.step([0, 1])["k"] == 1   # a's iteration did not advance
+    g2.close()
+
+
+def test_non_finite_data_is_reported():
+    """NaN or Inf in b (or in x0) reaches the step norms: SLIM_ENUMERIC."""
+    from paper_1912_07962_amd import Slim, SlimError
+    N = 32
+    for mode in ("chol", "pcg"):
+        for where in ("b", "x"):
+            s = Slim(N, NA, r=1, lam=1e-2, angles_per_block=G, gram_mode=mode)
+            b = torch.zeros((NA, s.R), device="cuda")
+            x = torch.zeros((N, N), device="cuda")
+            if where == "b":
+                b[0, s.R // 2] = float("nan")
+            else:
+                x[N // 2, N // 2] = float("inf")
+            s.set_data(b, x)
+            with pytest.raises(SlimError) as e:
+                s.step([0, 1])
+            assert e.value.status == 4, (mode, where)
+            s.close()

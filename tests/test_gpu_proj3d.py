@@ -170,3 +170,21 @@ def test_full_size_step_optimality(full):
     assert err <= 1e-4, err
     assert abs(float(s_true.norm()) - info["step_norm"]) <= 1e-5 * info["step_norm"]
     s.close()
+
+
+def test_non_finite_data_is_reported():
+    from paper_1912_07962_amd import Slim3D, SlimError
+    dirs = synth.random_directions(4, 2)
+    for where in ("b", "x"):
+        s = Slim3D(12, dirs, r=1)
+        b = torch.zeros((4, 12, 12), device="cuda")
+        x = torch.zeros((12, 12, 12), device="cuda")
+        if where == "b":
+            b[1, 6, 6] = float("nan")
+        else:
+            x[6, 6, 6] = float("inf")
+        s.set_data(b, x)
+        with pytest.raises(SlimError) as e:
+            s.step([1])
+        assert e.value.status == 4, where
+        s.close()
