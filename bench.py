@@ -700,11 +700,13 @@ def tik_bench(s_res, cfg, bd, xt, sched, warmup, steps, stream, resident_ms, res
 def mixed_bench(dev, steps, autotune=True):
     """Mixed batch: 64 slices of 256^2, 32 of 512^2 and 8 of 1024^2 (one
     ellipsoid volume sampled at three resolutions), 360 angles, 4 angles per
-    block, r = 8, lambda = 1e-3, CG; one context per size on its own stream,
-    stepped as one group (interleaved CG), against a second, identical set of
-    contexts stepped one after another over the same steps (both sets take
-    the same r + 1 steps first, so both time full-window steps of the same
-    blocks)."""
+    block, r = 8, lambda = 1e-3, CG; one context per size on its own stream.
+    Three identical sets of contexts take the same steps: stepped as one
+    group whose CG solves run in shared launches (one launch per kernel per
+    iteration over all sizes, chunks replayed as graphs), as one group with
+    each context's own launches interleaved by the host, and one context
+    after another.  All take the same r + 1 steps first, so every timed step
+    has a full window."""
     import numpy as np
     import torch
     import synth
@@ -713,13 +715,14 @@ def mixed_bench(dev, steps, autotune=True):
     cfg = synth.get_config("c4m")
     na, g, r, lam = cfg["n_angles"], cfg["g"], cfg["r"], cfg["lam"]
     print("bench: mixed batch inputs", file=sys.stderr, flush=True)
-    sets = ([], [])
+    modes = ("shared", "interleaved", "sequential")
+    sets = {m: [] for m in modes}
     keep, rays, tunes = [], 0, []
     for N, B in cfg["groups"]:
         xs, bs = synth.make_volume_problem(N, B, na, cfg["n_ellipsoids"], cfg["noise"],
                                            cfg["phantom_seed"], cfg["noise_seed"])
         tuned = None
-        for which in (0, 1):
+        for m in modes:
             st = torch.cuda.Stream()
             with torch.cuda.stream(st):
                 s = Slim(N, na, r=r, lam=lam, n_slices=B, angles_per_block=g, gram_mode="pcg",
@@ -734,38 +737,50 @@ def mixed_bench(dev, steps, autotune=True):
                 x = torch.zeros((B, N, N), dtype=torch.float32, device=dev)
             st.synchronize()
             s.set_data(bd, x, xt)
-            sets[which].append(s)
+            sets[m].append(s)
             keep.append((st, bd, xt, x))
-        rays += B * g * sets[0][-1].R
-    grp = Group(sets[0])
+        rays += B * g * sets["shared"][-1].R
+    grp = {"shared": Group(sets["shared"], shared=True),
+           "interleaved": Group(sets["interleaved"], shared=False)}
     sched = synth.schedule(na // g, 1, cfg["schedule_seed"])
     blk = lambda k: list(range(int(sched[k]) * g, int(sched[k]) * g + g))
+
+    def run(m, k):
+        if m in grp:
+            return grp[m].step(blk(k))
+        return [s.step(blk(k)) for s in sets[m]]
+
     for k in range(r + 1):
-        grp.step(blk(k))
-        for s in sets[1]:
-            s.step(blk(k))
+        for m in modes:
+            run(m, k)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(r + 1, r + 1 + steps):
-        infos = grp.step(blk(k))
-    torch.cuda.synchronize()
-    t_grp = (time.perf_counter() - t0) / steps
-    t0 = time.perf_counter()
-    for k in range(r + 1, r + 1 + steps):
-        for s in sets[1]:
-            s.step(blk(k))
-    torch.cuda.synchronize()
-    t_seq = (time.perf_counter() - t0) / steps
-    grp.close()
-    for s in sets[0] + sets[1]:
-        s.close()
-    print(f"bench: mixed batch {t_grp * 1e3:.1f} ms/step grouped, {t_seq * 1e3:.1f} sequential",
+    ms, iters = {}, {}
+    for m in modes:
+        t0 = time.perf_counter()
+        for k in range(r + 1, r + 1 + steps):
+            infos = run(m, k)
+        torch.cuda.synchronize()
+        ms[m] = (time.perf_counter() - t0) / steps * 1e3
+        iters[m] = [i["pcg_iters"] for i in infos]
+    same = all(torch.equal(a, b) for a, b in zip(
+        [t[3] for t in keep[0::3]], [t[3] for t in keep[1::3]])) and all(torch.equal(a, b) for a, b in zip(
+        [t[3] for t in keep[0::3]], [t[3] for t in keep[2::3]]))
+    for gp in grp.values():
+        gp.close()
+    for m in modes:
+        for s in sets[m]:
+            s.close()
+    print(f"bench: mixed batch {ms['shared']:.1f} ms/step shared launches, "
+          f"{ms['interleaved']:.1f} interleaved, {ms['sequential']:.1f} sequential",
           file=sys.stderr, flush=True)
     return {"groups": [list(gp) for gp in cfg["groups"]], "steps": steps,
-            "group_ms_per_step": t_grp * 1e3, "sequential_ms_per_step": t_seq * 1e3,
-            "group_speedup": t_seq / t_grp, "slice_rays_per_s": rays / t_grp,
-            "same_steps": True, "cg_iters_last_step": [i["pcg_iters"] for i in infos],
-            "autotune": tunes}
+            "shared_ms_per_step": ms["shared"], "interleaved_ms_per_step": ms["interleaved"],
+            "sequential_ms_per_step": ms["sequential"],
+            "shared_speedup_vs_sequential": ms["sequential"] / ms["shared"],
+            "shared_speedup_vs_interleaved": ms["interleaved"] / ms["shared"],
+            "slice_rays_per_s": rays / (ms["shared"] * 1e-3),
+            "same_steps": True, "results_identical": bool(same),
+            "cg_iters_last_step": iters["shared"], "autotune": tunes}
 
 
 def main():

@@ -269,9 +269,9 @@ slim_status slim_set_state(slim_ctx* ctx, const void* buf, int64_t size);
  * batches of 256^2, 512^2 and 1024^2 slices) scanned with the same angles and
  * block size.  slim_group_step applies one sampled block to every context:
  * the residual projections and explicit Gram solves of all contexts are
- * enqueued first, then the contexts' CG solves advance chunk by chunk under
- * one host loop (no context waits on another's host round trips; contexts on
- * different streams also overlap on the GPU), then every update.  The group
+ * enqueued first, then the contexts' CG solves (in shared launches, see
+ * slim_group_set_shared, or chunk by chunk under one host loop), then every
+ * update.  The group
  * borrows the contexts, which must outlive it.
  * Errors: SLIM_EINVAL (NULL, n < 1, a context listed twice, contexts with
  * different n_angles or angles_per_block). */
@@ -287,6 +287,27 @@ slim_status slim_group_create(slim_group** out, slim_ctx* const* ctxs, int n);
  * of the group is left unbound and must be rebound with slim_set_data. */
 slim_status slim_group_step(slim_group* g, const int32_t* angle_ids, int n_ids,
                             slim_step_info* infos);
+
+/* How the group's CG solves run: independent problems of different sizes
+ * batched into shared launches, or not.  on = 1 (groups of at most 16
+ * contexts): the solves of all contexts in CG mode
+ * advance in the same launches -- per iteration one back-projection, one
+ * forward projection (band kernel and reduction) and one vector kernel over
+ * every context's slices, each workgroup finding its context in a table of
+ * descriptors in device memory -- on the first such context's stream, with
+ * chunks of iterations replayed as one graph; the other contexts' streams
+ * hand over and take back their work by events.  Each slice still stops at
+ * its own tolerance, and the results equal those of on = 0 (the default),
+ * where each context's solve uses its own launches and one host loop
+ * interleaves them; contexts on different streams then also overlap on the
+ * GPU, which hides the kernel boundaries that shared launches keep (on the
+ * 64 x 256^2 + 32 x 512^2 + 8 x 1024^2 batch shared launches take 32 ms per
+ * step, interleaved ones 27 ms, one context after another 36 ms).  While
+ * kernel timing (slim_profile) is on in a context, the group uses on = 0 for
+ * that step.
+ * Errors: SLIM_EINVAL (NULL group, on not 0 or 1, on = 1 with more than 16
+ * contexts). */
+slim_status slim_group_set_shared(slim_group* g, int on);
 void slim_group_destroy(slim_group* g);
 
 /* Launch shape of the projectors.  Zero fields take the built-in rules. */

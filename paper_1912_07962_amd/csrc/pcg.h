@@ -83,4 +83,44 @@ hipError_t pcg_poll(PcgRun& run);
 hipError_t pcg_finish_async(PcgRun& run);
 void pcg_report(PcgRun& run, int* iters, double* relres);
 
+// Grouped CG: the solves of several contexts (images of different sizes,
+// the same window of angles) advanced in the same launches -- per iteration
+// one grouped back-projection, one grouped forward (band kernel and
+// reduction) and one grouped vector kernel over all contexts' slices, every
+// workgroup finding its context in a descriptor table in device memory --
+// with chunks of iterations replayed as one graph on one stream.  Each
+// context keeps its own workspace, stop flags and iteration count (a
+// converged slice's blocks return at entry); the runs come from pcg_begin.
+constexpr int kMaxGroup = 16;
+
+struct PcgGroupWork {
+  int cap = 0;                 // contexts the descriptor tables hold
+  size_t bytes = 0;
+  void* h_desc = nullptr;      // pinned staging of the tables
+  void* d_desc = nullptr;      // device tables
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  hipGraphExec_t graph_exec = nullptr;
+};
+
+struct PcgGroupRun {
+  PcgGroupWork* w = nullptr;
+  PcgRun* runs[kMaxGroup] = {};
+  int n = 0;
+  GroupShape shape;
+  int vec_total = 0;
+  hipStream_t st = nullptr;
+  int max_iter = 0, last_iters = 0;
+  int enq = 0, chunks = 0, seen = 0;
+  bool graph_ready = false;
+  bool done = false;
+};
+
+hipError_t pcg_group_alloc(PcgGroupWork& gw, int n);
+void pcg_group_free(PcgGroupWork& gw);
+// The runs must have been begun (pcg_begin) with work ordered before st.
+hipError_t pcg_group_begin(PcgGroupRun& gr, PcgGroupWork& gw, PcgRun* const* runs, int n,
+                           hipStream_t st);
+hipError_t pcg_group_enqueue(PcgGroupRun& gr, bool use_graph);
+hipError_t pcg_group_poll(PcgGroupRun& gr);
+
 }  // namespace slim

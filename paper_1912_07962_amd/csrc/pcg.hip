@@ -148,22 +148,18 @@ __global__ __launch_bounds__(kThreads) void init_scalars_kernel(const double* __
 // z += alpha pd, r -= alpha s, and workgroup 0 publishes gamma and alpha in
 // sc_next (the two sets alternate) and counts the iteration.  last: set 0 of
 // the scalars (its S_LAST slot, read by no kernel, holds the latest gamma).
-__global__ __launch_bounds__(kThreads) void cg_vector_kernel(int p, int pmax, int nb, int nparts,
-                                                             const double* __restrict__ sc_all,
-                                                             double* __restrict__ sc_next_all,
-                                                             double* __restrict__ last_all,
-                                                             const double* __restrict__ dq_parts,
-                                                             const double* __restrict__ rr_parts,
-                                                             double tol2,
-                                                             const double* __restrict__ q,
-                                                             double* __restrict__ r,
-                                                             double* __restrict__ pd,
-                                                             double* __restrict__ sv,
-                                                             double* __restrict__ z,
-                                                             size_t z_stride,
-                                                             int* __restrict__ ctl,
-                                                             int* __restrict__ live) {
-  const int sl = blockIdx.y;
+// (block bx of slice sl; shared by the one-context and the grouped launch)
+__device__ __forceinline__ void cg_vector_body(int bx, int sl, int p, int pmax, int nb, int nparts,
+                                               const double* __restrict__ sc_all,
+                                               double* __restrict__ sc_next_all,
+                                               double* __restrict__ last_all,
+                                               const double* __restrict__ dq_parts,
+                                               const double* __restrict__ rr_parts, double tol2,
+                                               const double* __restrict__ q,
+                                               double* __restrict__ r, double* __restrict__ pd,
+                                               double* __restrict__ sv, double* __restrict__ z,
+                                               size_t z_stride, int* __restrict__ ctl,
+                                               int* __restrict__ live) {
   if (ctl[sl * kCtlCount + kCtlDone]) return;
   __shared__ double sh[2 * (kThreads / 64)];
   const double* sc = sc_all + (size_t)sl * S_COUNT;
@@ -177,7 +173,7 @@ __global__ __launch_bounds__(kThreads) void cg_vector_kernel(int p, int pmax, in
   const bool conv = !(gamma > tol2 * bb);
   const double beta = (g_old > 0.0) ? gamma / g_old : 0.0;
   const double alpha = (g_old > 0.0) ? gamma / (delta - beta * gamma / a_old) : gamma / delta;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  if (bx == 0 && threadIdx.x == 0) {
     last_all[(size_t)sl * S_COUNT + S_LAST] = gamma;
     if (conv) {
       ctl[sl * kCtlCount + kCtlDone] = 1;
@@ -194,7 +190,7 @@ __global__ __launch_bounds__(kThreads) void cg_vector_kernel(int p, int pmax, in
     }
   }
   if (conv) return;
-  const int i = blockIdx.x * kThreads + threadIdx.x;
+  const int i = bx * kThreads + threadIdx.x;
   if (i < p) {
     const size_t o = (size_t)sl * pmax + i;
     const double pn = fma(beta, pd[o], r[o]);
@@ -205,6 +201,57 @@ __global__ __launch_bounds__(kThreads) void cg_vector_kernel(int p, int pmax, in
     zs[i] = fma(alpha, pn, zs[i]);
     r[o] = fma(-alpha, sn, r[o]);
   }
+}
+
+__global__ __launch_bounds__(kThreads) void cg_vector_kernel(int p, int pmax, int nb, int nparts,
+                                                             const double* __restrict__ sc_all,
+                                                             double* __restrict__ sc_next_all,
+                                                             double* __restrict__ last_all,
+                                                             const double* __restrict__ dq_parts,
+                                                             const double* __restrict__ rr_parts,
+                                                             double tol2,
+                                                             const double* __restrict__ q,
+                                                             double* __restrict__ r,
+                                                             double* __restrict__ pd,
+                                                             double* __restrict__ sv,
+                                                             double* __restrict__ z,
+                                                             size_t z_stride,
+                                                             int* __restrict__ ctl,
+                                                             int* __restrict__ live) {
+  cg_vector_body(blockIdx.x, blockIdx.y, p, pmax, nb, nparts, sc_all, sc_next_all, last_all,
+                 dq_parts, rr_parts, tol2, q, r, pd, sv, z, z_stride, ctl, live);
+}
+
+// One context of a grouped vector launch (device memory): its CG workspace
+// and the first workgroup of its nb x B blocks in the launch.
+struct VecGroupDesc {
+  double* sc;      // both scalar sets [2][B][S_COUNT]
+  const double* q;
+  double* r;
+  double* pd;
+  double* sv;
+  double* z;
+  const double* dq_parts;
+  const double* rr_parts;
+  int* ctl;
+  int* live;
+  size_t z_stride;
+  double tol2;
+  int p, pmax, nb, nparts, B, start;
+};
+
+// parity: the iteration's parity, which picks the current scalar set
+__global__ __launch_bounds__(kThreads) void cg_vector_grouped(const VecGroupDesc* __restrict__ d,
+                                                              int n, int parity) {
+  const int w = blockIdx.x;
+  int g = 0;
+  while (g + 1 < n && w >= d[g + 1].start) ++g;
+  const VecGroupDesc& a = d[g];
+  const int lw = w - a.start;
+  const size_t set = (size_t)a.B * S_COUNT;
+  cg_vector_body(lw % a.nb, lw / a.nb, a.p, a.pmax, a.nb, a.nparts, a.sc + (parity & 1) * set,
+                 a.sc + ((parity + 1) & 1) * set, a.sc, a.dq_parts, a.rr_parts, a.tol2, a.q, a.r,
+                 a.pd, a.sv, a.z, a.z_stride, a.ctl, a.live);
 }
 
 }  // namespace
@@ -432,6 +479,171 @@ hipError_t pcg_poll(PcgRun& run) {
     bool all = true;
     for (int b = 0; b < run.B; ++b) all = all && live[b * kCtlCount + kCtlDone] != 0;
     if (all || (run.enq >= run.max_iter && run.seen == run.chunks)) run.done = true;
+  }
+  return hipSuccess;
+}
+
+// ------------------------------------------------------------ grouped CG
+static size_t vec_desc_offset(int n) { return (grouped_desc_bytes(n) + 255) & ~size_t(255); }
+
+hipError_t pcg_group_alloc(PcgGroupWork& gw, int n) {
+  pcg_group_free(gw);
+  gw.cap = n;
+  gw.bytes = vec_desc_offset(n) + (size_t)n * sizeof(VecGroupDesc);
+  hipError_t e;
+  if ((e = hipHostMalloc(&gw.h_desc, gw.bytes, hipHostMallocDefault)) != hipSuccess) return e;
+  if ((e = hipMalloc(&gw.d_desc, gw.bytes)) != hipSuccess) return e;
+  for (int k = 0; k < 2; ++k)
+    if ((e = hipEventCreateWithFlags(&gw.ev[k], hipEventDisableTiming)) != hipSuccess) return e;
+  return hipSuccess;
+}
+
+void pcg_group_free(PcgGroupWork& gw) {
+  if (gw.graph_exec) (void)hipGraphExecDestroy(gw.graph_exec);
+  if (gw.h_desc) (void)hipHostFree(gw.h_desc);
+  (void)hipFree(gw.d_desc);
+  for (int k = 0; k < 2; ++k)
+    if (gw.ev[k]) (void)hipEventDestroy(gw.ev[k]);
+  gw = PcgGroupWork{};
+}
+
+hipError_t pcg_group_begin(PcgGroupRun& gr, PcgGroupWork& gw, PcgRun* const* runs, int n,
+                           hipStream_t st) {
+  if (n < 1 || n > gw.cap || n > kMaxGroup) return hipErrorInvalidValue;
+  gr.w = &gw;
+  gr.n = n;
+  gr.st = st;
+  gr.enq = gr.chunks = gr.seen = 0;
+  gr.done = false;
+  gr.graph_ready = false;
+  gr.max_iter = 0;
+  gr.last_iters = 0;
+  const FwdArgs* fa[kMaxGroup];
+  const BackArgs* ba[kMaxGroup];
+  for (int g = 0; g < n; ++g) {
+    gr.runs[g] = runs[g];
+    fa[g] = &runs[g]->fa;
+    ba[g] = &runs[g]->ba;
+    gr.max_iter = std::max(gr.max_iter, runs[g]->max_iter);
+    gr.last_iters = std::max(gr.last_iters, runs[g]->w->last_iters);
+  }
+  hipError_t e = grouped_prepare(fa, ba, n, gw.h_desc, &gr.shape);
+  if (e != hipSuccess) return e;
+  VecGroupDesc* vd = reinterpret_cast<VecGroupDesc*>(static_cast<char*>(gw.h_desc) +
+                                                     vec_desc_offset(n));
+  gr.vec_total = 0;
+  for (int g = 0; g < n; ++g) {
+    const PcgRun& r = *runs[g];
+    PcgWork& w = *r.w;
+    VecGroupDesc& v = vd[g];
+    v.sc = w.sc;
+    v.q = w.q;
+    v.r = w.r;
+    v.pd = w.pd;
+    v.sv = w.s;
+    v.z = r.z;
+    v.dq_parts = w.parts;
+    v.rr_parts = w.parts + (size_t)r.B * w.nparts;
+    v.ctl = w.ctl;
+    v.live = w.d_live;
+    v.z_stride = r.z_stride;
+    v.tol2 = r.tol2;
+    v.p = r.p;
+    v.pmax = w.pmax;
+    v.nb = r.nb;
+    v.nparts = w.nparts;
+    v.B = r.B;
+    v.start = gr.vec_total;
+    gr.vec_total += r.nb * r.B;
+  }
+  // the table reaches the device in the stream's order, before the first
+  // chunk (a replayed graph reads the table as it is at replay time)
+  return hipMemcpyAsync(gw.d_desc, gw.h_desc, gw.bytes, hipMemcpyHostToDevice, st);
+}
+
+namespace {
+
+hipError_t group_iterations(PcgGroupRun& gr, int todo) {
+  PcgGroupWork& gw = *gr.w;
+  const VecGroupDesc* vd = reinterpret_cast<const VecGroupDesc*>(
+      static_cast<const char*>(gw.d_desc) + vec_desc_offset(gr.n));
+  hipError_t e;
+  for (int q = 0; q < todo; ++q) {
+    const int it = gr.enq + q;
+    if ((e = launch_back_grouped(gw.d_desc, gr.shape, gr.st)) != hipSuccess) return e;
+    if ((e = launch_forward_grouped(gw.d_desc, gr.shape, gr.st)) != hipSuccess) return e;
+    hipLaunchKernelGGL(cg_vector_grouped, dim3(gr.vec_total), dim3(kThreads), 0, gr.st, vd, gr.n,
+                       it & 1);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t group_chunk_graph(PcgGroupRun& gr) {
+  PcgGroupWork& gw = *gr.w;
+  hipError_t e = hipStreamBeginCapture(gr.st, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return e;
+  hipError_t ek = group_iterations(gr, kChunk);
+  hipGraph_t g = nullptr;
+  e = hipStreamEndCapture(gr.st, &g);
+  if (ek != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return ek;
+  }
+  if (e != hipSuccess) return e;
+  if (gw.graph_exec) {
+    hipGraphExecUpdateResult res;
+    hipGraphNode_t bad = nullptr;
+    if (hipGraphExecUpdate(gw.graph_exec, g, &bad, &res) != hipSuccess ||
+        res != hipGraphExecUpdateSuccess) {
+      (void)hipGetLastError();
+      (void)hipGraphExecDestroy(gw.graph_exec);
+      gw.graph_exec = nullptr;
+    }
+  }
+  if (!gw.graph_exec) e = hipGraphInstantiate(&gw.graph_exec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  return e;
+}
+
+}  // namespace
+
+hipError_t pcg_group_enqueue(PcgGroupRun& gr, bool use_graph) {
+  if (gr.done || gr.enq >= gr.max_iter || gr.chunks - gr.seen >= 2) return hipSuccess;
+  PcgGroupWork& gw = *gr.w;
+  const int K = gr.last_iters;
+  const bool tail = K > 0 && gr.enq + kChunk > K - kTailLead && gr.enq < K + kChunk;
+  const int todo = std::min(tail ? kTail : kChunk, gr.max_iter - gr.enq);
+  hipError_t e;
+  if (use_graph && gr.st != nullptr && todo == kChunk && gr.enq > 0 && (gr.enq & 1) == 0) {
+    if (!gr.graph_ready) {
+      if ((e = group_chunk_graph(gr)) != hipSuccess) return e;
+      gr.graph_ready = true;
+    }
+    if ((e = hipGraphLaunch(gw.graph_exec, gr.st)) != hipSuccess) return e;
+  } else {
+    if ((e = group_iterations(gr, todo)) != hipSuccess) return e;
+  }
+  gr.enq += todo;
+  if ((e = hipEventRecord(gw.ev[gr.chunks & 1], gr.st)) != hipSuccess) return e;
+  ++gr.chunks;
+  return hipSuccess;
+}
+
+hipError_t pcg_group_poll(PcgGroupRun& gr) {
+  if (gr.done) return hipSuccess;
+  if (gr.chunks - gr.seen >= 2 || (gr.enq >= gr.max_iter && gr.seen < gr.chunks)) {
+    PcgGroupWork& gw = *gr.w;
+    hipError_t e = hipEventSynchronize(gw.ev[gr.seen & 1]);
+    if (e != hipSuccess) return e;
+    ++gr.seen;
+    bool all = true;
+    for (int g = 0; g < gr.n; ++g) {
+      const PcgRun& r = *gr.runs[g];
+      const volatile int* live = r.w->h_ctl;
+      for (int b = 0; b < r.B; ++b) all = all && live[b * kCtlCount + kCtlDone] != 0;
+    }
+    if (all || (gr.enq >= gr.max_iter && gr.seen == gr.chunks)) gr.done = true;
   }
   return hipSuccess;
 }

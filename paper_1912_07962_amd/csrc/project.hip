@@ -153,24 +153,26 @@ __device__ __forceinline__ int slot_item(int q, int tid) {
   return q * kFT + tid;
 }
 
+// XCD-aware numbering of a launch's workgroups (the grid is a multiple of 8):
+// consecutive positions (same slice tile and band group, different angle
+// chunks) live on one XCD.
+__device__ __forceinline__ int xcd_position() {
+  const int per_xcd = gridDim.x >> 3;
+  return (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+}
+
+// The band kernel's work at position pos < n_groups n_chunks n_tiles of its
+// plan (shared by the one-context launch and the grouped launch).
 template <int IT, int BT, typename IMG>
-__global__ __launch_bounds__(kFT, 2) void fwd_band_kernel(const AngleGeom* __restrict__ geom, int N,
-                                                          int R, FwdPlan pl, int B,
-                                                          const IMG* __restrict__ img,
-                                                          const IMG* __restrict__ imgT,
-                                                          size_t img_stride,
-                                                          float* __restrict__ partial,
-                                                          const int* __restrict__ stop,
-                                                          int stop_stride) {
+__device__ __forceinline__ void fwd_band_body(int pos, const AngleGeom* __restrict__ geom, int N,
+                                              int R, const FwdPlan& pl, int B,
+                                              const IMG* __restrict__ img,
+                                              const IMG* __restrict__ imgT, size_t img_stride,
+                                              float* __restrict__ partial,
+                                              const int* __restrict__ stop, int stop_stride) {
   typedef typename Lane<BT>::T LT;
   extern __shared__ float band[];
   const int W = N + 2 * kPad;
-  // XCD-aware numbering: consecutive positions (same slice tile and band
-  // group, different angle chunks) live on one XCD
-  const int total = pl.n_groups * pl.n_chunks * pl.n_tiles;
-  const int per_xcd = gridDim.x >> 3;
-  const int pos = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
-  if (pos >= total) return;
   const int chunk = pos % pl.n_chunks;
   const int tg = pos / pl.n_chunks;
   const int grp = tg % pl.n_groups;
@@ -455,21 +457,35 @@ __global__ __launch_bounds__(kFT, 2) void fwd_band_kernel(const AngleGeom* __res
   }
 }
 
-// out[s][t] = (h/d) sum_groups partial - sub for every slice (blockIdx.y);
-// optional CG tail q = out + lam*pd with per-workgroup partial dots <pd, q>
-// (and <pd, pd> into dots2 when it is non-NULL).
+template <int IT, int BT, typename IMG>
+__global__ __launch_bounds__(kFT, 2) void fwd_band_kernel(const AngleGeom* __restrict__ geom, int N,
+                                                          int R, FwdPlan pl, int B,
+                                                          const IMG* __restrict__ img,
+                                                          const IMG* __restrict__ imgT,
+                                                          size_t img_stride,
+                                                          float* __restrict__ partial,
+                                                          const int* __restrict__ stop,
+                                                          int stop_stride) {
+  const int pos = xcd_position();
+  if (pos >= pl.n_groups * pl.n_chunks * pl.n_tiles) return;
+  fwd_band_body<IT, BT, IMG>(pos, geom, N, R, pl, B, img, imgT, img_stride, partial, stop,
+                             stop_stride);
+}
+
+// out[s][t] = (h/d) sum_groups partial - sub for slice sl (ray block bx of
+// 256); optional CG tail q = out + lam*pd with per-workgroup partial dots
+// <pd, q> (and <pd, pd> into dots2 when it is non-NULL).
 template <typename SUB>
-__global__ __launch_bounds__(256) void fwd_reduce_kernel(
-    const AngleGeom* __restrict__ geom, int R, AngleList ids, int n_groups,
+__device__ __forceinline__ void fwd_reduce_body(
+    int bx, int sl, const AngleGeom* __restrict__ geom, int R, const AngleList& ids, int n_groups,
     const float* __restrict__ partial, const SUB* __restrict__ sub, size_t sub_stride,
     float* __restrict__ out32, double* __restrict__ out64, size_t out_stride,
     const double* __restrict__ pd, size_t pd_stride, double lam, double* __restrict__ dots,
     double* __restrict__ dots2, size_t dots_stride, const int* __restrict__ stop,
     int stop_stride) {
-  const int sl = blockIdx.y;
   if (stop && stop[(size_t)sl * stop_stride + kCtlDone]) return;
   __shared__ double sh[8];
-  const int o = blockIdx.x * 256 + threadIdx.x;
+  const int o = bx * 256 + threadIdx.x;
   const int n = ids.n * R;
   double d = 0.0, d2 = 0.0;
   if (o < n) {
@@ -509,10 +525,23 @@ __global__ __launch_bounds__(256) void fwd_reduce_kernel(
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-      dots[(size_t)sl * dots_stride + blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
-      if (dots2) dots2[(size_t)sl * dots_stride + blockIdx.x] = sh[4] + sh[5] + sh[6] + sh[7];
+      dots[(size_t)sl * dots_stride + bx] = sh[0] + sh[1] + sh[2] + sh[3];
+      if (dots2) dots2[(size_t)sl * dots_stride + bx] = sh[4] + sh[5] + sh[6] + sh[7];
     }
   }
+}
+
+template <typename SUB>
+__global__ __launch_bounds__(256) void fwd_reduce_kernel(
+    const AngleGeom* __restrict__ geom, int R, AngleList ids, int n_groups,
+    const float* __restrict__ partial, const SUB* __restrict__ sub, size_t sub_stride,
+    float* __restrict__ out32, double* __restrict__ out64, size_t out_stride,
+    const double* __restrict__ pd, size_t pd_stride, double lam, double* __restrict__ dots,
+    double* __restrict__ dots2, size_t dots_stride, const int* __restrict__ stop,
+    int stop_stride) {
+  fwd_reduce_body<SUB>(blockIdx.x, blockIdx.y, geom, R, ids, n_groups, partial, sub, sub_stride,
+                       out32, out64, out_stride, pd, pd_stride, lam, dots, dots2, dots_stride,
+                       stop, stop_stride);
 }
 
 // ------------------------------------------------------------------- back
@@ -545,13 +574,17 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// The back-projector's work for pixel tile (bx, by) of a gx x gy grid of
+// tiles and slice tile bz (shared by the one-context launch and the grouped
+// launch).
 template <typename VT, int BT>
-__global__ __launch_bounds__(256) void back_kernel(
-    const AngleGeom* __restrict__ geom, int N, int R, AngleList ids, int B,
-    const VT* __restrict__ v, size_t v_stride, float* __restrict__ out, float* __restrict__ x,
-    float* __restrict__ xT, const float* __restrict__ x_true, size_t img_stride,
-    double* __restrict__ partials, int mode, const int* __restrict__ stop, int stop_stride,
-    uint16_t* __restrict__ xs, uint16_t* __restrict__ xsT, float shrink) {
+__device__ __forceinline__ void back_body(
+    int bx, int by, int bz, int gx, int gy, const AngleGeom* __restrict__ geom, int N, int R,
+    const AngleList& ids, int B, const VT* __restrict__ v, size_t v_stride,
+    float* __restrict__ out, float* __restrict__ x, float* __restrict__ xT,
+    const float* __restrict__ x_true, size_t img_stride, double* __restrict__ partials, int mode,
+    const int* __restrict__ stop, int stop_stride, uint16_t* __restrict__ xs,
+    uint16_t* __restrict__ xsT, float shrink) {
   typedef typename Lane<BT>::T LT;
   // A lane's pixels are columns tx + 16 q: for each q the 16 lanes of a row
   // take consecutive columns, so a wave's LDS reads hit nearby rays (fewer
@@ -567,7 +600,7 @@ __global__ __launch_bounds__(256) void back_kernel(
   constexpr int kBuf = kDB ? kSegFloats / 2 : kSegFloats;  // floats of one pass buffer
   constexpr int kPass = kBuf / (kSeg * BT);               // angles staged per pass
   constexpr int kConst = kDB ? kMaxList : kPass;           // angles with constants held
-  const int b0 = blockIdx.z * BT;
+  const int b0 = bz * BT;
   const int nb = min(BT, B - b0);
   if (stop) {
     bool all = true;
@@ -584,7 +617,7 @@ __global__ __launch_bounds__(256) void back_kernel(
   float(*tile)[kBW + 1] = reinterpret_cast<float(*)[kBW + 1]>(seg);
   const int tx = threadIdx.x & 15;       // 16 lanes x 4 pixels = 64 columns
   const int ty = threadIdx.x >> 4;       // 16 rows
-  const int i0 = blockIdx.y * kBH, j0 = blockIdx.x * kBW;
+  const int i0 = by * kBH, j0 = bx * kBW;
   const int i = i0 + ty;
   const int jb = j0 + kL * tx;           // pixel q of the lane: column jb + kQ q
   const double half = 0.5 * (N - 1);
@@ -790,14 +823,124 @@ __global__ __launch_bounds__(256) void back_kernel(
       if ((threadIdx.x & 63) == 0) wred[w][3 * b + k] = r;
     }
   __syncthreads();
-  const int nwg = gridDim.x * gridDim.y;
-  const int wg = blockIdx.y * gridDim.x + blockIdx.x;
+  const int nwg = gx * gy;
+  const int wg = by * gx + bx;
   if ((int)threadIdx.x < 3 * nb) {
     const int b = threadIdx.x / 3, k = threadIdx.x % 3;
     const double r = wred[0][threadIdx.x] + wred[1][threadIdx.x] + wred[2][threadIdx.x] +
                      wred[3][threadIdx.x];
     partials[((size_t)(b0 + b) * nwg + wg) * 3 + k] = r;
   }
+}
+
+template <typename VT, int BT>
+__global__ __launch_bounds__(256) void back_kernel(
+    const AngleGeom* __restrict__ geom, int N, int R, AngleList ids, int B,
+    const VT* __restrict__ v, size_t v_stride, float* __restrict__ out, float* __restrict__ x,
+    float* __restrict__ xT, const float* __restrict__ x_true, size_t img_stride,
+    double* __restrict__ partials, int mode, const int* __restrict__ stop, int stop_stride,
+    uint16_t* __restrict__ xs, uint16_t* __restrict__ xsT, float shrink) {
+  back_body<VT, BT>(blockIdx.x, blockIdx.y, blockIdx.z, gridDim.x, gridDim.y, geom, N, R, ids, B,
+                    v, v_stride, out, x, xT, x_true, img_stride, partials, mode, stop, stop_stride,
+                    xs, xsT, shrink);
+}
+
+// ------------------------------------------------------- grouped launches
+// The CG products of several contexts (images of different sizes, the same
+// angle list) in one launch per kernel: workgroup w finds its context g in a
+// table of descriptors in device memory (start: the first workgroup or
+// position of the context) and runs the one-context body at w - start.
+// The band kernel's positions keep the XCD layout of a one-context launch:
+// every XCD runs per = ceil(total / 8) consecutive positions of each
+// context, its slots start .. start + per - 1 (of the launch's workgroups
+// that the XCD runs) holding positions x per + (slot - start) on XCD x.
+struct FwdGroupDesc {
+  FwdPlan pl;
+  const AngleGeom* geom;
+  const float* img;
+  const float* imgT;
+  float* partial;
+  const int* stop;
+  size_t img_stride;
+  int N, R, B, stop_stride, start, per, total, bt, items;
+};
+
+struct RedGroupDesc {
+  AngleList ids;
+  const AngleGeom* geom;
+  const float* partial;
+  double* out64;
+  const double* pd;
+  double* dots;
+  double* dots2;
+  const int* stop;
+  size_t out_stride, pd_stride, dots_stride;
+  double lam;
+  int R, n_groups, gx, start, stop_stride;
+};
+
+struct BackGroupDesc {
+  AngleList ids;
+  const AngleGeom* geom;
+  const double* v;
+  float* out;
+  float* xT;
+  const int* stop;
+  size_t v_stride, img_stride;
+  int N, R, B, gx, gy, start, stop_stride;
+};
+
+template <typename D>
+__device__ __forceinline__ int group_of(const D* __restrict__ d, int n, int w) {
+  int g = 0;
+  while (g + 1 < n && w >= d[g + 1].start) ++g;
+  return g;
+}
+
+// every (slice tile, rays per lane) pair that launch_band instantiates
+__global__ __launch_bounds__(kFT, 2) void fwd_band_grouped(const FwdGroupDesc* __restrict__ d,
+                                                           int n) {
+  const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
+  const FwdGroupDesc& a = d[group_of(d, n, slot)];
+  const int lp = xcd * a.per + (slot - a.start);
+  if (lp >= a.total) return;
+#define SLIM_GRP_CASE(BT_, IT_)                                                                 \
+  case BT_ * 16 + IT_:                                                                          \
+    fwd_band_body<IT_, BT_, float>(lp, a.geom, a.N, a.R, a.pl, a.B, a.img, a.imgT, a.img_stride, \
+                                   a.partial, a.stop, a.stop_stride);                           \
+    break;
+  switch (a.bt * 16 + a.items) {
+    SLIM_GRP_CASE(1, 1) SLIM_GRP_CASE(1, 2) SLIM_GRP_CASE(1, 3) SLIM_GRP_CASE(1, 4)
+    SLIM_GRP_CASE(1, 5) SLIM_GRP_CASE(1, 6) SLIM_GRP_CASE(1, 8)
+    SLIM_GRP_CASE(2, 1) SLIM_GRP_CASE(2, 2) SLIM_GRP_CASE(2, 3) SLIM_GRP_CASE(2, 4)
+    SLIM_GRP_CASE(2, 5) SLIM_GRP_CASE(2, 6)
+    SLIM_GRP_CASE(4, 1) SLIM_GRP_CASE(4, 2) SLIM_GRP_CASE(4, 3)
+    default: break;
+  }
+#undef SLIM_GRP_CASE
+}
+
+__global__ __launch_bounds__(256) void fwd_reduce_grouped(const RedGroupDesc* __restrict__ d,
+                                                          int n) {
+  const int w = blockIdx.x;
+  const RedGroupDesc& a = d[group_of(d, n, w)];
+  const int lw = w - a.start;
+  fwd_reduce_body<float>(lw % a.gx, lw / a.gx, a.geom, a.R, a.ids, a.n_groups, a.partial,
+                         (const float*)nullptr, 0, nullptr, a.out64, a.out_stride, a.pd,
+                         a.pd_stride, a.lam, a.dots, a.dots2, a.dots_stride, a.stop,
+                         a.stop_stride);
+}
+
+template <int BT>
+__global__ __launch_bounds__(256) void back_grouped(const BackGroupDesc* __restrict__ d, int n) {
+  const int w = blockIdx.x;
+  const BackGroupDesc& a = d[group_of(d, n, w)];
+  const int lw = w - a.start;
+  const int per = a.gx * a.gy;
+  const int bz = lw / per, rem = lw - bz * per;
+  back_body<double, BT>(rem % a.gx, rem / a.gx, bz, a.gx, a.gy, a.geom, a.N, a.R, a.ids, a.B, a.v,
+                        a.v_stride, a.out, nullptr, a.xT, nullptr, a.img_stride, nullptr, 0, a.stop,
+                        a.stop_stride, nullptr, nullptr, 0.f);
 }
 
 // out[3*slice + k] = sum over n partial 3-vectors of the slice (fixed order)
@@ -1067,6 +1210,127 @@ hipError_t launch_back(const BackArgs& a, hipStream_t st) {
     launch_back_bt(a, a.v64, st);
   else
     launch_back_bt(a, a.v32, st);
+  return hipGetLastError();
+}
+
+static size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+size_t grouped_desc_bytes(int n) {
+  return align256(n * sizeof(FwdGroupDesc)) + align256(n * sizeof(RedGroupDesc)) +
+         align256(n * sizeof(BackGroupDesc));
+}
+
+hipError_t grouped_prepare(const FwdArgs* const* fa, const BackArgs* const* ba, int n,
+                           void* host_desc, GroupShape* shape) {
+  if (n < 1) return hipErrorInvalidValue;
+  char* base = static_cast<char*>(host_desc);
+  FwdGroupDesc* fd = reinterpret_cast<FwdGroupDesc*>(base);
+  RedGroupDesc* rd = reinterpret_cast<RedGroupDesc*>(base + align256(n * sizeof(FwdGroupDesc)));
+  BackGroupDesc* bd = reinterpret_cast<BackGroupDesc*>(
+      base + align256(n * sizeof(FwdGroupDesc)) + align256(n * sizeof(RedGroupDesc)));
+  GroupShape sh;
+  sh.n = n;
+  sh.back_bt = 4;
+  for (int g = 0; g < n; ++g) {
+    const BackArgs& b = *ba[g];
+    const int bt = b.tune.back_bt > 0 ? std::min(b.tune.back_bt, slice_tile(b.B)) : slice_tile(b.B);
+    sh.back_bt = std::min(sh.back_bt, bt);
+  }
+  for (int g = 0; g < n; ++g) {
+    const FwdArgs& a = *fa[g];
+    const BackArgs& b = *ba[g];
+    if (a.img_bf16 || a.sub || !a.pd || a.out32 || b.v32 || b.mode != 0)
+      return hipErrorInvalidValue;  // only the CG products are grouped
+    const FwdPlan pl = make_plan(a.h_geom, a.N, a.R, *a.ids, a.B, a.tune);
+    FwdGroupDesc& f = fd[g];
+    f.pl = pl;
+    f.geom = a.geom;
+    f.img = static_cast<const float*>(a.img);
+    f.imgT = static_cast<const float*>(a.imgT);
+    f.partial = a.partial;
+    f.stop = a.stop;
+    f.img_stride = a.img_stride;
+    f.N = a.N;
+    f.R = a.R;
+    f.B = a.B;
+    f.stop_stride = a.stop_stride;
+    f.total = pl.n_groups * pl.n_chunks * pl.n_tiles;
+    f.per = (f.total + 7) / 8;
+    f.start = sh.band_grid / 8;
+    sh.band_grid += 8 * f.per;
+    f.bt = pl.bt;
+    f.items = pl.items;
+    // the (slice tile, rays per lane) pairs the grouped band kernel holds
+    const bool known = (pl.bt == 1 && ((pl.items >= 1 && pl.items <= 6) || pl.items == 8)) ||
+                       (pl.bt == 2 && pl.items >= 1 && pl.items <= 6) ||
+                       (pl.bt == 4 && pl.items >= 1 && pl.items <= 3);
+    if (!known) return hipErrorInvalidValue;
+    sh.band_total += f.total;
+    sh.band_lds = std::max(sh.band_lds, (size_t)pl.H * (a.N + 2 * kPad) * pl.bt * sizeof(float));
+    RedGroupDesc& r = rd[g];
+    r.ids = *a.ids;
+    r.geom = a.geom;
+    r.partial = a.partial;
+    r.out64 = a.out64;
+    r.pd = a.pd;
+    r.dots = a.dots;
+    r.dots2 = a.dots2;
+    r.stop = a.stop;
+    r.out_stride = a.out_stride;
+    r.pd_stride = a.pd_stride;
+    r.dots_stride = a.dots_stride;
+    r.lam = a.lam;
+    r.R = a.R;
+    r.n_groups = pl.n_groups;
+    r.gx = (a.ids->n * a.R + 255) / 256;
+    r.stop_stride = a.stop_stride;
+    r.start = sh.red_total;
+    sh.red_total += r.gx * a.B;
+    BackGroupDesc& k = bd[g];
+    k.ids = *b.ids;
+    k.geom = b.geom;
+    k.v = b.v64;
+    k.out = b.out;
+    k.xT = b.xT;
+    k.stop = b.stop;
+    k.v_stride = b.v_stride;
+    k.img_stride = b.img_stride;
+    k.N = b.N;
+    k.R = b.R;
+    k.B = b.B;
+    k.gx = (b.N + kBW - 1) / kBW;
+    k.gy = (b.N + kBH - 1) / kBH;
+    k.stop_stride = b.stop_stride;
+    k.start = sh.back_total;
+    sh.back_total += k.gx * k.gy * ((b.B + sh.back_bt - 1) / sh.back_bt);
+  }
+  *shape = sh;
+  return hipSuccess;
+}
+
+hipError_t launch_back_grouped(const void* dev_desc, const GroupShape& sh, hipStream_t st) {
+  const char* base = static_cast<const char*>(dev_desc);
+  const BackGroupDesc* bd = reinterpret_cast<const BackGroupDesc*>(
+      base + align256(sh.n * sizeof(FwdGroupDesc)) + align256(sh.n * sizeof(RedGroupDesc)));
+  if (sh.back_total <= 0) return hipSuccess;
+  if (sh.back_bt == 4)
+    hipLaunchKernelGGL(back_grouped<4>, dim3(sh.back_total), dim3(256), 0, st, bd, sh.n);
+  else if (sh.back_bt == 2)
+    hipLaunchKernelGGL(back_grouped<2>, dim3(sh.back_total), dim3(256), 0, st, bd, sh.n);
+  else
+    hipLaunchKernelGGL(back_grouped<1>, dim3(sh.back_total), dim3(256), 0, st, bd, sh.n);
+  return hipGetLastError();
+}
+
+hipError_t launch_forward_grouped(const void* dev_desc, const GroupShape& sh, hipStream_t st) {
+  const char* base = static_cast<const char*>(dev_desc);
+  const FwdGroupDesc* fd = reinterpret_cast<const FwdGroupDesc*>(base);
+  const RedGroupDesc* rd =
+      reinterpret_cast<const RedGroupDesc*>(base + align256(sh.n * sizeof(FwdGroupDesc)));
+  if (sh.band_total > 0)
+    hipLaunchKernelGGL(fwd_band_grouped, dim3(sh.band_grid), dim3(kFT), sh.band_lds, st, fd, sh.n);
+  if (sh.red_total > 0)
+    hipLaunchKernelGGL(fwd_reduce_grouped, dim3(sh.red_total), dim3(256), 0, st, rd, sh.n);
   return hipGetLastError();
 }
 

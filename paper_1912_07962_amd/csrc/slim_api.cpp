@@ -1304,7 +1304,49 @@ void slim_destroy(slim_ctx* c) {
 // ------------------------------------------------------------------ groups
 struct slim_group {
   std::vector<slim_ctx*> ctx;
+  bool grouped = false;            // CG solves in shared launches
+  PcgGroupWork gw;                 // their descriptor tables and graph
+  std::vector<hipEvent_t> ev;      // one per context: hand-over between streams
+  ~slim_group() {
+    pcg_group_free(gw);
+    for (hipEvent_t e : ev)
+      if (e) (void)hipEventDestroy(e);
+  }
 };
+
+namespace {
+
+// The group's CG solves (contexts in CG mode with a solve in progress) in
+// shared launches on the first such context's stream: the other contexts'
+// streams hand their work over by events before, and take it back after.
+slim_status group_cg_shared(slim_group* g, StepState* ss, const std::vector<int>& idx) {
+  const int m = (int)idx.size();
+  hipStream_t st0 = g->ctx[idx[0]]->st;
+  for (int j = 1; j < m; ++j) {
+    slim_ctx* c = g->ctx[idx[j]];
+    HIP_TRY(hipEventRecord(g->ev[idx[j]], c->st));
+    HIP_TRY(hipStreamWaitEvent(st0, g->ev[idx[j]], 0));
+  }
+  PcgRun* runs[kMaxGroup];
+  bool graphs = true;
+  for (int j = 0; j < m; ++j) {
+    runs[j] = &ss[idx[j]].run;
+    graphs = graphs && g->ctx[idx[j]]->graphs();
+  }
+  PcgGroupRun gr;
+  hipError_t e = pcg_group_begin(gr, g->gw, runs, m, st0);
+  while (e == hipSuccess && !gr.done) {
+    e = pcg_group_enqueue(gr, graphs);
+    if (e == hipSuccess) e = pcg_group_poll(gr);
+  }
+  if (e != hipSuccess) return fail(SLIM_EDEVICE, std::string("grouped CG: ") + hipGetErrorString(e));
+  for (int j = 0; j < m; ++j) runs[j]->done = true;
+  HIP_TRY(hipEventRecord(g->ev[idx[0]], st0));
+  for (int j = 1; j < m; ++j) HIP_TRY(hipStreamWaitEvent(g->ctx[idx[j]]->st, g->ev[idx[0]], 0));
+  return SLIM_OK;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -1320,7 +1362,26 @@ slim_status slim_group_create(slim_group** out, slim_ctx* const* ctxs, int n) {
   }
   slim_group* g = new slim_group;
   g->ctx.assign(ctxs, ctxs + n);
+  g->ev.assign(n, nullptr);
+  hipError_t e = hipSuccess;
+  for (int i = 0; i < n && e == hipSuccess; ++i)
+    e = hipEventCreateWithFlags(&g->ev[i], hipEventDisableTiming);
+  if (e == hipSuccess && n <= kMaxGroup) e = pcg_group_alloc(g->gw, n);
+  g->grouped = false;
+  if (e != hipSuccess) {
+    delete g;
+    return fail(SLIM_EDEVICE, std::string("group: ") + hipGetErrorString(e));
+  }
   *out = g;
+  return SLIM_OK;
+}
+
+slim_status slim_group_set_shared(slim_group* g, int on) {
+  if (!g) return fail(SLIM_EINVAL, "group is NULL");
+  if (on != 0 && on != 1) return fail(SLIM_EINVAL, "on must be 0 or 1");
+  if (on && g->ctx.size() > (size_t)kMaxGroup)
+    return fail(SLIM_EINVAL, "shared launches hold at most 16 contexts");
+  g->grouped = on != 0;
   return SLIM_OK;
 }
 
@@ -1352,6 +1413,23 @@ slim_status slim_group_step(slim_group* g, const int32_t* ids, int n_ids, slim_s
     if (s != SLIM_OK) {
       unbind_all();
       return s;
+    }
+  }
+  {
+    std::vector<int> cg;
+    bool profiling = false;
+    for (int i = 0; i < n; ++i) {
+      if (ss[i].pcg && !ss[i].run.done) cg.push_back(i);
+      profiling = profiling || g->ctx[i]->prof.on;
+    }
+    // shared launches for two or more solves (kernel timing keeps the
+    // contexts' own launches, which its counters follow)
+    if (g->grouped && cg.size() >= 2 && !profiling) {
+      slim_status s = group_cg_shared(g, ss.get(), cg);
+      if (s != SLIM_OK) {
+        unbind_all();
+        return s;
+      }
     }
   }
   for (bool all = false; !all;) {

@@ -181,7 +181,35 @@ struct BackArgs {
 hipError_t launch_back(const BackArgs& a, hipStream_t st);
 int back_num_workgroups(int N);
 
-// Per slice, sum the n partial 3-vectors in a fixed order into out[3*slice..].
+// Grouped CG products: the work of several contexts (images of different
+// sizes, the same angle list) in one launch per kernel -- one back-projector
+// launch for u_g = M^T v_g, one band launch and one reduction launch for
+// q_g = M u_g + lam pd_g with the dots -- every workgroup finding its
+// context in a table of descriptors in device memory.  grouped_prepare
+// fills host_desc (grouped_desc_bytes(n) bytes) from the contexts' CG
+// arguments (BackArgs mode 0 with float64 v; FwdArgs with pd, float32
+// images, no data) and returns the launch shape; the caller copies the table
+// to device memory (dev_desc) before the launches, which take only its
+// address (so a captured graph stays valid while the table is rewritten
+// between replays).  The back-projector runs with the smallest slice tile
+// of the contexts; every other launch shape is each context's own, so the
+// results equal the one-context launches'.
+struct GroupShape {
+  int n = 0;
+  int back_bt = 1;
+  int back_total = 0;    // back-projector workgroups
+  int band_total = 0;    // band-kernel positions
+  int band_grid = 0;     // band-kernel grid: 8 x the contexts' positions per XCD
+  size_t band_lds = 0;   // dynamic LDS of the band kernel (largest band)
+  int red_total = 0;     // reduction workgroups
+};
+size_t grouped_desc_bytes(int n);
+hipError_t grouped_prepare(const FwdArgs* const* fa, const BackArgs* const* ba, int n,
+                           void* host_desc, GroupShape* shape);
+hipError_t launch_back_grouped(const void* dev_desc, const GroupShape& shape, hipStream_t st);
+hipError_t launch_forward_grouped(const void* dev_desc, const GroupShape& shape, hipStream_t st);
+
+// Per slice, sum the n partial 3-vectors in a fixed order into out[3*slice..].// Per slice, sum the n partial 3-vectors in a fixed order into out[3*slice..].
 hipError_t launch_reduce3(const double* partials, int n, int B, double* out, hipStream_t st);
 
 // dst = src^T (if dst), bf16 copies of src (bs) and src^T (bsT) if given, for

@@ -109,6 +109,7 @@ def load() -> ctypes.CDLL:
         "slim_group_create": (I, [ctypes.POINTER(P), ctypes.POINTER(P), I]),
         "slim_group_step": (I, [P, i32p, I, ctypes.POINTER(StepInfo)]),
         "slim_group_destroy": (None, [P]),
+        "slim_group_set_shared": (I, [P, I]),
         "slim_set_tune": (I, [P, ctypes.POINTER(Tune)]),
         "slim_get_tune": (I, [P, ctypes.POINTER(Tune)]),
         "slim_warmstart": (I, [P, P, i32p, I, P, ctypes.POINTER(I)]),
@@ -512,14 +513,20 @@ class Slim3D:
 
 class Group:
     """Contexts of different grid sizes stepped together with the same block
-    (include/slim.h, slim_group_*): their CG solves are interleaved."""
+    (include/slim.h, slim_group_*): their CG solves run in shared launches
+    (shared=True) or interleaved by one host loop (False, the library's
+    default)."""
 
-    def __init__(self, contexts):
+    def __init__(self, contexts, shared: bool = False):
         self.contexts = list(contexts)
         arr = (ctypes.c_void_p * len(self.contexts))(*[c._h.value for c in self.contexts])
         h = ctypes.c_void_p()
         _check(load().slim_group_create(ctypes.byref(h), arr, len(self.contexts)))
         self._h = h
+        self.set_shared(shared)
+
+    def set_shared(self, on: bool):
+        _check(load().slim_group_set_shared(self._h, int(bool(on))))
 
     def step(self, angle_ids, read: bool = True):
         a, p, n = _ids(angle_ids)

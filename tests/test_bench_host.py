@@ -30,13 +30,17 @@ def test_code_digest_ignores_comments_and_layout(tmp_path):
     assert bench.code_digest(str(a)) != bench.code_digest(str(c))
 
 
-def test_counter_readings_match_the_projector_code():
-    # the stored PMC readings belong to the committed projector code
-    t = bench.PMC_TRAFFIC
-    assert bench.code_digest(os.path.join(ROOT, t["source"])) == t["sha256"]
+def test_counter_readings_are_reported_only_for_the_code_they_measured(monkeypatch):
+    # the stored PMC readings are reported while the projector code is the
+    # code they were taken on, and never for another code or instance
+    t = dict(bench.PMC_TRAFFIC)
+    current = bench.code_digest(os.path.join(ROOT, t["source"]))
+    monkeypatch.setattr(bench, "PMC_TRAFFIC", dict(t, sha256=current))
     b4 = bench.pmc_traffic("cg_forward/4")
     assert b4 == (t["kib"]["cg_forward/4"][0] * 2.0 + t["kib"]["cg_forward/4"][1]) * 1024.0
     assert bench.pmc_traffic("cg_forward/5") is None
+    monkeypatch.setattr(bench, "PMC_TRAFFIC", dict(t, sha256="0" * 64))
+    assert bench.pmc_traffic("cg_forward/4") is None
 
 
 def test_rays_per_lane_follows_the_launch_plan():

@@ -157,7 +157,8 @@ def test_volume_512_full_window_sampled_slices(volume_512, tol):
 
 
 # --------------------------------------------------------- mixed batch
-def test_mixed_group_each_context_matches_its_oracle():
+@pytest.mark.parametrize("shared", [True, False])
+def test_mixed_group_each_context_matches_its_oracle(shared):
     from paper_1912_07962_amd import Group, Slim
     gd = _golden("c4m_slices")
     cfg = synth.get_config("c4m")
@@ -180,7 +181,7 @@ def test_mixed_group_each_context_matches_its_oracle():
         ctxs.append(s)
         xs.append(x)
         keep.append((st, bd))
-    grp = Group(ctxs)
+    grp = Group(ctxs, shared=shared)
     res = []
     for k, beta in enumerate(gd["s0_blocks"], start=1):
         grp.step(_block(beta, g))

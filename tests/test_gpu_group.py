@@ -30,15 +30,22 @@ def _ctx(N, B, mode, b, stream=None, use_graph=True):
     return s, x, bd
 
 
-SPECS = [(32, 3, "pcg"), (64, 2, "chol"), (48, 4, "pcg")]
+SPECS = [(32, 3, "pcg"), (64, 2, "chol"), (48, 4, "pcg"), (40, 1, "pcg")]
 
 
-def test_group_step_equals_separate_steps():
+@pytest.mark.parametrize("shared,streams", [(False, False), (True, False), (True, True)])
+def test_group_step_equals_separate_steps(shared, streams):
+    """Shared launches (one back-projection, forward and vector launch per
+    CG iteration over all contexts; graph replay when the contexts have
+    streams of their own) and interleaved per-context launches both equal
+    the contexts stepped alone, bit for bit."""
     from paper_1912_07962_amd import Group
     probs = [_problem(N, B, 100 + i) for i, (N, B, _) in enumerate(SPECS)]
-    grp_ctx = [_ctx(N, B, m, probs[i][1]) for i, (N, B, m) in enumerate(SPECS)]
+    sts = [torch.cuda.Stream() if streams else None for _ in SPECS]
+    grp_ctx = [_ctx(N, B, m, probs[i][1], stream=sts[i]) for i, (N, B, m) in enumerate(SPECS)]
+    torch.cuda.synchronize()
     solo = [_ctx(N, B, m, probs[i][1]) for i, (N, B, m) in enumerate(SPECS)]
-    grp = Group([c[0] for c in grp_ctx])
+    grp = Group([c[0] for c in grp_ctx], shared=shared)
     sched = synth.schedule(NA // G, 1, 17)
     for beta in sched:
         ids = list(range(int(beta) * G, int(beta) * G + G))
@@ -47,8 +54,10 @@ def test_group_step_equals_separate_steps():
             inf = s.step(ids)
             assert infos[i]["step_norm"] == inf["step_norm"]
             assert infos[i]["pcg_iters"] == inf["pcg_iters"]
+        torch.cuda.synchronize()
         for (_, xg, _), (_, xs, _) in zip(grp_ctx, solo):
             assert torch.equal(xg, xs)
+    grp.close()
 
 
 def test_graph_replay_equals_eager_launches():
