@@ -493,6 +493,88 @@ def proj3d_bench(dev, steps):
             "kernel_ms": {k: v2["total_ms"] for k, v2 in stats.items()}, "projector": proj}
 
 
+def precision_bench(dev, s_fp32_ms, steps=10):
+    """The precision variant: the 64^2 workload's 20 epochs in FP32 and with
+    bf16 storage (image shadow and sinogram), each epoch's error against the
+    stored FP64 oracle run (tests/golden/c1_epochs.npz, written by the oracle
+    alone) and against the oracle under the bf16 storage model; then the
+    1024^2 workload's full-window steps with bf16 storage, timed against the
+    FP32 steps of the headline."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_1912_07962_amd import Slim
+
+    gd = np.load(os.path.join(ROOT, "tests", "golden", "c1_epochs.npz"))
+    cfg = synth.get_config("c3")
+    N, na, r, lam, E = cfg["N"], cfg["n_angles"], cfg["r"], cfg["lam"], cfg["epochs"]
+    x_true, b, _ = synth.make_slice_problem(N, na, cfg["n_ellipses"], cfg["noise"],
+                                            cfg["phantom_seed"], cfg["noise_seed"])
+    sched = gd["schedule"]   # the schedule the stored oracle run followed
+    def rel(a, c):
+        a = np.asarray(a, np.float64).reshape(-1)
+        c = np.asarray(c, np.float64).reshape(-1)
+        return float(np.linalg.norm(a - c) / np.linalg.norm(c))
+    out = {"workload": "64^2, 90 angles x 91 rays, 1 angle/block, r = 5, lambda = 1e-2, 20 epochs"}
+    for prec in ("fp32", "bf16"):
+        st = torch.cuda.Stream()
+        s = Slim(N, na, r=r, lam=lam, precision=prec, stream=st)
+        with torch.cuda.stream(st):
+            bd = torch.as_tensor(b, dtype=torch.float32, device=dev)
+            if prec == "bf16":
+                bd = bd.to(torch.bfloat16)
+            x = torch.zeros((N, N), dtype=torch.float32, device=dev)
+        st.synchronize()
+        s.set_data(bd, x)
+        e64, emod = [], []
+        t0 = time.perf_counter()
+        for k, beta in enumerate(sched, 1):
+            s.step([int(beta)], read=False)
+            if k % na == 0:
+                st.synchronize()          # the steps run on the context's stream
+                xe = x.cpu().numpy()
+                e64.append(rel(xe, gd["x_fp64"][k // na - 1]))
+                emod.append(rel(xe, gd["x_bf16"][k // na - 1]))
+        wall = time.perf_counter() - t0
+        out[prec] = {"rel_err_vs_fp64_per_epoch": e64, "rel_err_vs_bf16_model_per_epoch": emod,
+                     "ms_per_step_incl_epoch_readback": wall / len(sched) * 1e3}
+        s.close()
+    out["rel_err_vs_x_true_fp64_oracle"] = [float(v) for v in gd["err_fp64"]]
+    # 1024^2 full-window steps with bf16 storage
+    cfg2 = synth.get_config("c2")
+    N2, na2, g2, r2, lam2 = cfg2["N"], cfg2["n_angles"], cfg2["g"], cfg2["r"], cfg2["lam"]
+    xt2, b2, _ = synth.make_slice_problem(N2, na2, cfg2["n_ellipses"], cfg2["noise"],
+                                          cfg2["phantom_seed"], cfg2["noise_seed"])
+    st = torch.cuda.Stream()
+    s = Slim(N2, na2, r=r2, lam=lam2, angles_per_block=g2, gram_mode="pcg", pcg_tol=1e-6,
+             precision="bf16", stream=st)
+    s.autotune()
+    with torch.cuda.stream(st):
+        bd = torch.as_tensor(b2, dtype=torch.float32, device=dev).to(torch.bfloat16)
+        x = torch.zeros((N2, N2), dtype=torch.float32, device=dev)
+        xt = torch.as_tensor(xt2, dtype=torch.float32, device=dev)
+    st.synchronize()
+    s.set_data(bd, x, xt)
+    sched2 = synth.schedule(na2 // g2, 1, cfg2["schedule_seed"])
+    for k in range(r2 + 2):
+        s.step(list(range(int(sched2[k]) * g2, int(sched2[k]) * g2 + g2)))
+    st.synchronize()
+    t0 = time.perf_counter()
+    its = []
+    for k in range(r2 + 2, r2 + 2 + steps):
+        its.append(s.step(list(range(int(sched2[k]) * g2, int(sched2[k]) * g2 + g2)))["pcg_iters"])
+    st.synchronize()
+    wall = time.perf_counter() - t0
+    s.close()
+    out["bf16_1024"] = {"ms_per_step": wall / steps * 1e3, "fp32_ms_per_step": s_fp32_ms,
+                        "cg_iters_per_step": float(np.mean(its)), "steps": steps}
+    print(f"bench: precision variant: bf16 error vs FP64 {out['bf16']['rel_err_vs_fp64_per_epoch'][0]:.2e} "
+          f"(epoch 1) .. {out['bf16']['rel_err_vs_fp64_per_epoch'][-1]:.2e} (epoch {E}); fp32 "
+          f"{max(out['fp32']['rel_err_vs_fp64_per_epoch']):.2e} at most; 1024^2 bf16 "
+          f"{out['bf16_1024']['ms_per_step']:.2f} ms/step", file=sys.stderr, flush=True)
+    return out
+
+
 def gram_bench(dev, steps):
     """Explicit Gram mode on the 256^2 workload (180 angles x 363 rays, 1
     angle/block, r = 5, lambda = 1e-2, p = 6 x 363 = 2178): per-step times of
@@ -558,6 +640,26 @@ def warm_bench(dev, n_test, n_timed):
     xte, bte = ws.make_samples(seeds, workers=min(16, os.cpu_count() or 1), cfg=cfg)
     plain = ws.plain_data(bte, xte, cfg)
     ev = ws.evaluate(net, bte, xte, plain, cfg)
+
+    # error floor set by the null space of A: the part of x0 - x_true that no
+    # update can remove (updates lie in R(A^T)), for the network's x0 and x0 = 0
+    n_fl = min(32, n_test)
+    x0_fl = ws.warm_start(net, plain["u"][:n_fl].contiguous(), net.max_batch)
+    floors = []
+    for lam_f in (1e-3, 1e-4):
+        fl = ws.null_space_floor(x0_fl, xte[:n_fl], cfg, lam=lam_f, tol=1e-4, max_iter=4000)
+        floors.append({"lambda": lam_f,
+                       "net_x0_rel_mean": float(np.mean(fl["x0"]["rel_floor"])),
+                       "net_x0_rel_max": float(np.max(fl["x0"]["rel_floor"])),
+                       "zero_x0_rel_mean": float(np.mean(fl["zero"]["rel_floor"])),
+                       "cg_iters": [fl["x0"]["cg_iters"], fl["zero"]["cg_iters"]],
+                       "cg_relres": [fl["x0"]["cg_relres"], fl["zero"]["cg_relres"]]})
+    ev["null_space_floor"] = {"samples": n_fl, "upper_bounds": floors,
+                              "e_star_mean_same_samples": float(np.mean(plain["e_star"][:n_fl]))}
+    print(f"bench: null-space floor <= {floors[-1]['net_x0_rel_mean']:.2e} (network x0), "
+          f"{floors[-1]['zero_x0_rel_mean']:.2e} (x0 = 0) of ||x_true||; e* "
+          f"{ev['null_space_floor']['e_star_mean_same_samples']:.3f}", file=sys.stderr, flush=True)
+    del x0_fl
 
     # CNN inference throughput (batch 16)
     u16 = plain["u"][:16].contiguous()
@@ -814,6 +916,8 @@ def main():
                     help="Tikhonov parameter of the slimTik leg")
     ap.add_argument("--mixed-steps", type=int, default=3,
                     help="timed steps of the mixed batch (0 skips it)")
+    ap.add_argument("--no-precision", action="store_true",
+                    help="skip the precision-variant leg (bf16 storage)")
     ap.add_argument("--proj3d-steps", type=int, default=3,
                     help="timed steps of the 3D random-direction workload (0 skips it)")
     ap.add_argument("--gram-steps", type=int, default=20,
@@ -1002,6 +1106,10 @@ def main():
     if args.volume_slices > 0:
         volume = volume_bench(dev, args.volume_slices, args.volume_steps, not args.no_autotune)
 
+    precision = None
+    if not args.no_precision:
+        precision = precision_bench(dev, wall / args.steps * 1e3)
+
     p3d = None
     if args.proj3d_steps > 0:
         p3d = proj3d_bench(dev, args.proj3d_steps)
@@ -1044,6 +1152,7 @@ def main():
         "mixed": mixed,
         "gram_solve": gram,
         "proj3d": p3d,
+        "precision": precision,
         "warm_start": warm,
         "cg_iters_per_step": float(np.mean(iters)),
         "window_blocks_timed": r + 1,

@@ -36,7 +36,7 @@ import torch
 
 import synth
 
-from .slim import Cnn, Slim
+from .slim import Cnn, Slim, SlimError
 
 CHANNELS = (32, 64, 128, 256)
 N_FIRST = 4          # blocks whose back-projection feeds the network
@@ -305,6 +305,45 @@ def init_params(channels=CHANNELS, seed: int = 0) -> np.ndarray:
             v = np.zeros(shape)
         parts.append(v.reshape(-1))
     return np.concatenate(parts).astype(np.float32)
+
+
+def null_space_floor(x0, x_true, cfg, lam: float = 1e-6, tol: float = 1e-6,
+                     max_iter: int = 3000):
+    """Error floor of a start x0: slimLS updates lie in R(A^T) (sec. 1), so
+    the component of x0 - x_true in the null space of A (all angles) is never
+    removed.  One step of the library with every angle in one block, b = 0
+    and damping lam turns d = x0 - x_true into
+        d - A^T (A A^T + lam I)^{-1} A d = lam (A^T A + lam I)^{-1} d,
+    which is the null-space component of d plus what remains of its range
+    component after the factors lam / (sigma^2 + lam); its norm bounds the
+    floor from above and reaches it as lam -> 0 (CG to tol, at most max_iter
+    iterations, the reached residual reported).  Returns per sample
+    ||.|| / ||x_true|| for x0 (a tensor [n, N, N] on the GPU or None) and
+    for x0 = 0, with the CG's iterations and residual."""
+    N, na = cfg["N"], cfg["n_angles"]
+    xt = torch.as_tensor(x_true, dtype=torch.float32, device="cuda").reshape(-1, N, N)
+    n = xt.shape[0]
+    s = Slim(N, na, r=0, lam=lam, n_slices=n, angles_per_block=na, gram_mode="pcg",
+             pcg_tol=tol, pcg_max_iter=max_iter)
+    b0 = torch.zeros((n, na, s.R), dtype=torch.float32, device="cuda")
+    nrm = torch.linalg.vector_norm(xt.reshape(n, -1), dim=1).double().cpu().numpy()
+    out = {"lambda": lam}
+    for name, d in (("x0", None if x0 is None else x0 - xt), ("zero", -xt)):
+        if d is None:
+            continue
+        x = d.contiguous().clone()
+        s.set_data(b0, x)
+        try:
+            info = s.step(list(range(na)))
+        except SlimError as e:          # the cap reached: still an upper bound
+            if e.status != 5:
+                raise
+            info = {"pcg_iters": max_iter, "pcg_relres": float("nan")}
+        rem = torch.linalg.vector_norm(x.reshape(n, -1), dim=1).double().cpu().numpy()
+        out[name] = {"rel_floor": (rem / nrm).tolist(), "cg_iters": info["pcg_iters"],
+                     "cg_relres": info["pcg_relres"]}
+    s.close()
+    return out
 
 
 def evaluate(net: Cnn, b, x_true, plain, cfg, chunk=512):

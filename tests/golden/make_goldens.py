@@ -43,7 +43,16 @@ numpy archives next to this script.
               gradient of every tensor of at most 20,000 entries, and for the
               larger ones 4,096 entries at seeded positions plus the norm.
 
-usage: python tests/golden/make_goldens.py [c2_window] [c4_slices] [c4m_slices] [chol_cap] [cnn_256]
+  c1_epochs   the 64^2 workload (90 angles x 91 rays, one angle per block,
+              r = 5, lambda = 1e-2) over its 20 epochs of the random-cyclic
+              schedule (oracle.sampler.schedule(90, 20, 3001)) from x = 0,
+              twice: in float64, and with the bf16 storage model of the
+              precision variant (b and the image read by the residual rounded
+              to bf16, nearest even).  Stores the schedule, x after every
+              epoch (float32) and the errors vs x_true.
+
+usage: python tests/golden/make_goldens.py [c2_window] [c4_slices] [c4m_slices] [chol_cap]
+                                          [cnn_256] [c1_epochs]
 """
 from __future__ import annotations
 
@@ -59,6 +68,7 @@ sys.path.insert(0, ROOT)
 
 import synth  # noqa: E402
 from oracle import cnn as ocnn  # noqa: E402
+from oracle import sampler  # noqa: E402
 from oracle import slimls, system  # noqa: E402
 
 CG_TOL = 1e-12
@@ -224,8 +234,36 @@ def cnn_256():
                         param_seed=CNN_PARAM_SEED, x0=x0.astype(np.float64), loss=loss, **store)
 
 
+def c1_epochs():
+    cfg = synth.get_config("c1")
+    N, na, r, lam, E = cfg["N"], cfg["n_angles"], cfg["r"], cfg["lam"], cfg["epochs"]
+    x_true, b, _ = synth.make_slice_problem(N, na, cfg["n_ellipses"], cfg["noise"],
+                                            cfg["phantom_seed"], cfg["noise_seed"])
+    sched = sampler.schedule(na, E, cfg["schedule_seed"])
+    P = system.Projector(N, na)
+    runs = {"fp64": slimls.Tomo(P, b, 1, r, lam, x_true=x_true),
+            "bf16": slimls.Tomo(P, slimls.round_bf16(b), 1, r, lam, x_true=x_true,
+                                x_store=slimls.round_bf16)}
+    store = {}
+    t0 = time.time()
+    for name, T in runs.items():
+        xs, errs = [], []
+        for k, beta in enumerate(sched, 1):
+            rec = T.step(int(beta))
+            if k % na == 0:
+                xs.append(T.x.astype(np.float32))
+                errs.append(rec.err_norm / np.linalg.norm(x_true))
+        store[f"x_{name}"] = np.stack(xs)
+        store[f"err_{name}"] = np.asarray(errs)
+        print(f"c1_epochs[{name}]: {len(xs)} epochs, {time.time() - t0:.0f} s", flush=True)
+    np.savez_compressed(os.path.join(HERE, "c1_epochs.npz"), N=N, n_angles=na, r=r, lam=lam,
+                        epochs=E, schedule_seed=cfg["schedule_seed"],
+                        schedule=np.asarray(sched, np.int32), **store)
+
+
 if __name__ == "__main__":
-    which = sys.argv[1:] or ["c4_slices", "c2_window", "c4m_slices", "chol_cap", "cnn_256"]
+    which = sys.argv[1:] or ["c4_slices", "c2_window", "c4m_slices", "chol_cap", "cnn_256",
+                             "c1_epochs"]
     for w in which:
         {"c2_window": c2_window, "c4_slices": c4_slices, "c4m_slices": c4m_slices,
-         "chol_cap": chol_cap, "cnn_256": cnn_256}[w]()
+         "chol_cap": chol_cap, "cnn_256": cnn_256, "c1_epochs": c1_epochs}[w]()
