@@ -511,7 +511,11 @@ slim_status do_step(slim_ctx* c, const int32_t* ids, slim_step_info* info) {
 extern "C" {
 
 const char* slim_strerror(slim_status s) {
-  switch (s) {
+  // a C caller may pass any int: read the representation, not an enum value
+  // that C++ need not be able to hold
+  int v = 0;
+  std::memcpy(&v, &s, sizeof v);
+  switch (v) {
     case SLIM_OK: return "ok";
     case SLIM_EINVAL: return "invalid argument";
     case SLIM_ENOMEM: return "out of device memory";
