@@ -60,10 +60,12 @@ typedef struct slim3d_ctx slim3d_ctx;
  *            pcg_max_iter, stream.  Other fields must hold their defaults'
  *            meaning for this path: precision FP32, gram_mode AUTO or PCG
  *            (the Gram system is always solved by CG), tikhonov 0.
- * Allocates the direction table and the step workspace: one image of N^3
- * floats (the CG's M^T p), five float64 vectors of (r+1) g n_det^2 entries
- * (right-hand side, residual, direction, product, solution) and small
- * reduction buffers.
+ * Allocates the direction table and the step workspace: three volumes of N^3
+ * floats (the CG's M^T p, and copies stored with x or y slowest that the
+ * forward projector reads for directions of that major axis), five float64
+ * vectors of (r+1) g n_det^2 entries (right-hand side, residual, direction,
+ * product, solution), the forward projector's per-segment ray sums (eight
+ * float64 values per ray of (r+1) g images) and small reduction buffers.
  * Errors: SLIM_EINVAL, SLIM_ENOMEM, SLIM_EDEVICE. */
 slim_status slim3d_init(slim3d_ctx** out, int N, int n_dirs, const double* dirs, int n_det, int r,
                         double lambda, const slim_opts* opts);

@@ -1,20 +1,25 @@
 // Matrix-free 3D parallel-beam projectors (Joseph's method along the major
 // axis) and the float64 CG kernels of the 3D slimLS path, for gfx950.
 //
-// Forward (ray-driven): a workgroup owns a 16 x 16 tile of detector pixels
-// of one direction; each lane walks its ray through the planes x_m = const
-// that it crosses inside the volume, its crossing point in 32.32 fixed point
-// (one 64-bit add per plane and axis), and interpolates bilinearly between
-// the four voxel centres around it (zero outside the volume).  Ray sums run
-// in float32 over 32 planes at a time and accumulate in float64.
+// Forward (ray-driven): the volume is read stored with the direction's major
+// axis m slowest, so every plane x_m = const a ray crosses is a contiguous
+// N x N block whose rows run along the axis a.  A workgroup owns a 16 x 16
+// tile of detector pixels of one direction and one of kSeg segments of the
+// planes; each lane walks its ray through the segment's planes it crosses
+// inside the volume, its crossing point in 32.32 fixed point (one 64-bit add
+// per plane and axis), and interpolates bilinearly between the four voxel
+// centres around it (masked loads: zero outside the volume).  Ray sums run
+// in float32 over 32 planes and accumulate in float64; a second kernel adds
+// the segments' sums in a fixed order and applies h/|w_m|, the data and the
+// CG tail.
 //
 // Back (voxel-driven gather, the exact adjoint): a workgroup owns a tile of
 // 8 x 8 x 4 voxels; per direction it stages the detector window its tile
 // projects onto (at most 17 x 17 of the 24 x 24 LDS pixels, scaled by
-// h/|w_m|) and every lane evaluates the closed-form weights of the 4 x 4
-// candidate rays around its voxel's own ray: the crossing-point displacement
-// is linear in the detector offset (DirGeom), and a weight is the product of
-// two tents.
+// h/|w_m|) and every lane evaluates the closed-form weights of the candidate
+// rays around its voxel's own ray (2 or 3 detector columns times 2 or 3
+// rows, by the direction): the crossing-point displacement is linear in the
+// detector offset (DirGeom), and a weight is the product of two tents.
 #include "slim3d_internal.h"
 
 namespace slim {
@@ -52,67 +57,98 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   return s;
 }
 
+// Index of voxel (z k, y i, x j) in the volume stored with axis m slowest:
+// plane k_m, then axis b, then axis a fastest (a < b the other two axes), so
+// a plane crossed by the rays of a direction with major axis m is one
+// contiguous N x N block.  m = 2 is the standard [z][y][x] layout.
+__device__ __forceinline__ size_t lay_index(int m, int N, int k, int i, int j) {
+  if (m == 2) return ((size_t)k * N + i) * N + j;
+  if (m == 1) return ((size_t)i * N + k) * N + j;
+  return ((size_t)j * N + k) * N + i;
+}
+
+// Forward: the planes along m are cut into kSeg segments, one workgroup per
+// (ray tile, direction, segment), each writing its rays' partial sums; a
+// second kernel adds the segments in a fixed order.
+constexpr int kSeg = 8;
+
 __global__ __launch_bounds__(256) void fwd3_kernel(
-    const DirGeom* __restrict__ geom, DirList ids, int N, int n, const float* __restrict__ x,
-    const float* __restrict__ sub, float* __restrict__ out32, double* __restrict__ out64,
-    const double* __restrict__ pd, double lam, double* __restrict__ dots,
-    const int* __restrict__ ctl) {
+    const DirGeom* __restrict__ geom, DirList ids, int N, int n, const float* __restrict__ vol0,
+    const float* __restrict__ vol1, const float* __restrict__ vol2, double* __restrict__ part,
+    size_t part_stride, const int* __restrict__ ctl) {
   if (ctl && ctl[kCtlDone]) return;
-  __shared__ double sh[4];
-  const int slot = blockIdx.z;
+  const int slot = blockIdx.z / kSeg, seg = blockIdx.z - slot * kSeg;
   const DirGeom G = geom[ids.id[slot]];
+  const float* __restrict__ vol = G.m == 0 ? vol0 : (G.m == 1 ? vol1 : vol2);
   const int t = blockIdx.x * kRT + (threadIdx.x & (kRT - 1));
   const int q = blockIdx.y * kRT + (threadIdx.x / kRT);
-  const bool ok = t < n && q < n;
+  if (t >= n || q >= n) return;
+  const double hN = 0.5 * (N - 1), hn = 0.5 * (n - 1);
+  const double fa0 = hN + (t - hn) * G.La[0] + (q - hn) * G.La[1] - hN * G.sa;
+  const double fb0 = hN + (t - hn) * G.Lb[0] + (q - hn) * G.Lb[1] - hN * G.sb;
+  // the ray's planes (-1 < f < N on both axes) within this segment
+  double lo = (double)(seg * N / kSeg), hi = (double)((seg + 1) * N / kSeg - 1);
+  plane_range(fa0, G.sa, N, lo, hi);
+  plane_range(fb0, G.sb, N, lo, hi);
+  const int k0 = (int)fmin((double)N, fmax((double)(seg * N / kSeg), floor(lo)));
+  const int k1 = (int)fmax(-1.0, fmin((double)((seg + 1) * N / kSeg - 1), ceil(hi)));
   double sum = 0.0;
-  if (ok) {
-    const double hN = 0.5 * (N - 1), hn = 0.5 * (n - 1);
-    const double tt = t - hn, qq = q - hn;
-    const double fa0 = hN + tt * G.La[0] + qq * G.La[1] - hN * G.sa;
-    const double fb0 = hN + tt * G.Lb[0] + qq * G.Lb[1] - hN * G.sb;
-    double lo = 0.0, hi = (double)(N - 1);
-    plane_range(fa0, G.sa, N, lo, hi);
-    plane_range(fb0, G.sb, N, lo, hi);
-    const int k0 = (int)fmin((double)N, fmax(0.0, floor(lo)));
-    const int k1 = (int)fmax(-1.0, fmin((double)(N - 1), ceil(hi)));
-    if (k0 <= k1) {
-      const int st[3] = {1, N, N * N};
-      const int sm = st[G.m], sa = st[G.a], sb = st[G.b];
-      int64_t Fa = llrint((fa0 + k0 * G.sa) * kTwo32), Fb = llrint((fb0 + k0 * G.sb) * kTwo32);
-      const int64_t Sa = llrint(G.sa * kTwo32), Sb = llrint(G.sb * kTwo32);
-      const unsigned uN = (unsigned)N;
-      float part = 0.f;
-      int cnt = 0;
-      for (int k = k0; k <= k1; ++k) {
-        const int ia = (int)(Fa >> 32), ib = (int)(Fb >> 32);
-        const float fa = (float)(uint32_t)Fa * kInv32, fb = (float)(uint32_t)Fb * kInv32;
-        const bool a0 = (unsigned)ia < uN, a1 = (unsigned)(ia + 1) < uN;
-        const bool b0 = (unsigned)ib < uN, b1 = (unsigned)(ib + 1) < uN;
-        const float* p = x + (k * sm + ia * sa + ib * sb);
-        const float v00 = (a0 && b0) ? p[0] : 0.f;
-        const float v10 = (a1 && b0) ? p[sa] : 0.f;
-        const float v01 = (a0 && b1) ? p[sb] : 0.f;
-        const float v11 = (a1 && b1) ? p[sa + sb] : 0.f;
-        const float lo_b = fmaf(fa, v10 - v00, v00);
-        const float hi_b = fmaf(fa, v11 - v01, v01);
-        part += fmaf(fb, hi_b - lo_b, lo_b);
-        Fa += Sa;
-        Fb += Sb;
-        if (++cnt == kFlush) {
-          sum += (double)part;
-          part = 0.f;
-          cnt = 0;
-        }
+  if (k0 <= k1) {
+    // within a plane of the m-major layout, axis a is contiguous, b has
+    // stride N; the planes have stride N^2
+    const size_t sm = (size_t)N * N;
+    int64_t Fa = llrint((fa0 + k0 * G.sa) * kTwo32), Fb = llrint((fb0 + k0 * G.sb) * kTwo32);
+    const int64_t Sa = llrint(G.sa * kTwo32), Sb = llrint(G.sb * kTwo32);
+    const unsigned uN = (unsigned)N;
+    float acc = 0.f;
+    int cnt = 0;
+#pragma unroll 2
+    for (int k = k0; k <= k1; ++k) {
+      const int ia = (int)(Fa >> 32), ib = (int)(Fb >> 32);
+      const float fa = (float)(uint32_t)Fa * kInv32, fb = (float)(uint32_t)Fb * kInv32;
+      const bool a0 = (unsigned)ia < uN, a1 = (unsigned)(ia + 1) < uN;
+      const bool b0 = (unsigned)ib < uN, b1 = (unsigned)(ib + 1) < uN;
+      const float* p = vol + (k * sm + (size_t)ib * N + ia);
+      const float v00 = (a0 && b0) ? p[0] : 0.f;
+      const float v10 = (a1 && b0) ? p[1] : 0.f;
+      const float v01 = (a0 && b1) ? p[N] : 0.f;
+      const float v11 = (a1 && b1) ? p[N + 1] : 0.f;
+      const float lo_b = fmaf(fa, v10 - v00, v00);
+      const float hi_b = fmaf(fa, v11 - v01, v01);
+      acc += fmaf(fb, hi_b - lo_b, lo_b);
+      Fa += Sa;
+      Fb += Sb;
+      if (++cnt == kFlush) {
+        sum += (double)acc;
+        acc = 0.f;
+        cnt = 0;
       }
-      sum += (double)part;
     }
-    sum *= G.scale;
+    sum += (double)acc;
   }
-  const size_t o = ((size_t)slot * n + (ok ? q : 0)) * n + (ok ? t : 0);
+  part[seg * part_stride + ((size_t)slot * n + q) * n + t] = sum;
+}
+
+// out[s][q][t] = (h/|w_m|) sum_segments part - sub for every ray (fixed
+// order); optional CG tail q = out + lam pd with per-workgroup partial dots.
+__global__ __launch_bounds__(256) void fwd3_reduce_kernel(
+    const DirGeom* __restrict__ geom, DirList ids, int n, const double* __restrict__ part,
+    size_t part_stride, const float* __restrict__ sub, float* __restrict__ out32,
+    double* __restrict__ out64, const double* __restrict__ pd, double lam,
+    double* __restrict__ dots, const int* __restrict__ ctl) {
+  if (ctl && ctl[kCtlDone]) return;
+  __shared__ double sh[4];
+  const size_t nn = (size_t)n * n;
+  const size_t o = (size_t)blockIdx.x * 256 + threadIdx.x;
+  const size_t tot = nn * ids.n;
   double d = 0.0;
-  if (ok) {
-    double v = sum;
-    if (sub) v -= (double)sub[((size_t)ids.id[slot] * n + q) * n + t];
+  if (o < tot) {
+    const int slot = (int)(o / nn);
+    double v = 0.0;
+#pragma unroll
+    for (int sg = 0; sg < kSeg; ++sg) v += part[sg * part_stride + o];
+    v *= geom[ids.id[slot]].scale;
+    if (sub) v -= (double)sub[(size_t)ids.id[slot] * nn + (o - slot * nn)];
     if (pd) {
       const double pv = pd[o];
       v = fma(lam, pv, v);
@@ -123,16 +159,26 @@ __global__ __launch_bounds__(256) void fwd3_kernel(
   }
   if (dots) {
     const double s = block_sum(d, sh);
-    if (threadIdx.x == 0)
-      dots[((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = s;
+    if (threadIdx.x == 0) dots[blockIdx.x] = s;
   }
+}
+
+// dst = the standard-layout volume src stored with axis m slowest
+// (lay_index); tiles of 8 x 8 x 4 voxels, so both sides move 32-byte runs.
+__global__ __launch_bounds__(256) void relayout3_kernel(const float* __restrict__ src,
+                                                        float* __restrict__ dst, int N, int m) {
+  const int j = blockIdx.x * kVX + (threadIdx.x & (kVX - 1));
+  const int i = blockIdx.y * kVY + ((threadIdx.x / kVX) & (kVY - 1));
+  const int k = blockIdx.z * kVZ + threadIdx.x / (kVX * kVY);
+  if (i < N && j < N && k < N) dst[lay_index(m, N, k, i, j)] = src[((size_t)k * N + i) * N + j];
 }
 
 template <typename VT>
 __global__ __launch_bounds__(256) void back3_kernel(
     const DirGeom* __restrict__ geom, DirList ids, int N, int n, const VT* __restrict__ v,
-    float* __restrict__ out, float* __restrict__ x, const float* __restrict__ x_true,
-    double* __restrict__ partials, int mode, const int* __restrict__ ctl) {
+    float* __restrict__ out0, float* __restrict__ out1, float* __restrict__ out2,
+    float* __restrict__ x, const float* __restrict__ x_true, double* __restrict__ partials,
+    int mode, const int* __restrict__ ctl) {
   if (ctl && ctl[kCtlDone]) return;
   __shared__ float sv[kFP * kFP];
   __shared__ double sh[4];
@@ -168,35 +214,48 @@ __global__ __launch_bounds__(256) void back3_kernel(
     }
     __syncthreads();
     if (ok) {
+      // candidate rays: |du| < wu = |e_u[a]| + |e_u[b]| (dv likewise), i.e.
+      // the integers of the open interval (fu - wu, fu + wu), at most
+      // ceil(2 wu) <= 3 of them (2 x 2 for a direction along an axis)
+      const double wu = G.wu, wv = G.wv;
+      const int nt = (int)ceil(2.0 * wu), nq = (int)ceil(2.0 * wv);
       const double fu = cx * G.eu[0] + cy * G.eu[1] + cz * G.eu[2] + hn;
       const double fv = cx * G.ev[0] + cy * G.ev[1] + cz * G.ev[2] + hn;
-      const double flu = floor(fu), flv = floor(fv);
-      const float du0 = (float)(flu - fu), dv0 = (float)(flv - fv);
+      const double tsu = floor(fu - wu) + 1.0, tsv = floor(fv - wv) + 1.0;
+      const float du0 = (float)(tsu - fu), dv0 = (float)(tsv - fv);
       // 1 .. 14 for every voxel of the tile; clamped so that no read leaves the window
-      const int lt = min(max((int)flu - 1 - t0, 0), kFP - 4);
-      const int lq = min(max((int)flv - 1 - q0, 0), kFP - 4);
+      const int lt = min(max((int)tsu - t0, 0), kFP - 3);
+      const int lq = min(max((int)tsv - q0, 0), kFP - 3);
       const float la0 = (float)G.La[0], la1 = (float)G.La[1];
       const float lb0 = (float)G.Lb[0], lb1 = (float)G.Lb[1];
-      float du[4];
+      float du[3];
 #pragma unroll
-      for (int o = 0; o < 4; ++o) du[o] = du0 + (float)(o - 1);
+      for (int o = 0; o < 3; ++o) du[o] = du0 + (float)o;
 #pragma unroll
-      for (int oq = 0; oq < 4; ++oq) {
-        const float dv = dv0 + (float)(oq - 1);
-        const float ra = la1 * dv, rb = lb1 * dv;
-        const float* row = sv + (lq + oq) * kFP + lt;
+      for (int oq = 0; oq < 3; ++oq) {
+        if (oq < nq) {   // uniform over the workgroup (one direction)
+          const float dv = dv0 + (float)oq;
+          const float ra = la1 * dv, rb = lb1 * dv;
+          const float* row = sv + (lq + oq) * kFP + lt;
 #pragma unroll
-        for (int ot = 0; ot < 4; ++ot) {
-          const float wa = unit_clamp(1.f - fabsf(fmaf(la0, du[ot], ra)));
-          const float wb = unit_clamp(1.f - fabsf(fmaf(lb0, du[ot], rb)));
-          acc = fmaf(wa * wb, row[ot], acc);
+          for (int ot = 0; ot < 3; ++ot) {
+            if (ot < nt) {
+              const float wa = unit_clamp(1.f - fabsf(fmaf(la0, du[ot], ra)));
+              const float wb = unit_clamp(1.f - fabsf(fmaf(lb0, du[ot], rb)));
+              acc = fmaf(wa * wb, row[ot], acc);
+            }
+          }
         }
       }
     }
   }
   const size_t idx = ((size_t)(ok ? k : 0) * N + (ok ? i : 0)) * N + (ok ? j : 0);
   if (mode == 0) {
-    if (ok) out[idx] = acc;
+    if (ok) {
+      if (out0) out0[lay_index(0, N, k, i, j)] = acc;
+      if (out1) out1[lay_index(1, N, k, i, j)] = acc;
+      if (out2) out2[idx] = acc;
+    }
     return;
   }
   double n0 = 0.0, n1 = 0.0, n2 = 0.0;
@@ -335,15 +394,26 @@ __global__ __launch_bounds__(256) void cg3_pd_kernel(const double* __restrict__ 
 
 // ---------------------------------------------------------------- launchers
 int fwd3_num_workgroups(int n, int n_ids) {
-  const int g = (n + kRT - 1) / kRT;
-  return g * g * n_ids;
+  return (int)(((size_t)n * n * n_ids + 255) / 256);
 }
+
+size_t fwd3_part_doubles(int n, int n_ids) { return (size_t)kSeg * n * n * n_ids; }
 
 hipError_t launch_fwd3(const Fwd3Args& a, hipStream_t st) {
   if (a.ids.n <= 0) return hipSuccess;
   const int g = (a.n + kRT - 1) / kRT;
-  hipLaunchKernelGGL(fwd3_kernel, dim3(g, g, a.ids.n), dim3(256), 0, st, a.geom, a.ids, a.N, a.n,
-                     a.x, a.sub, a.out32, a.out64, a.pd, a.lam, a.dots, a.ctl);
+  const size_t stride = (size_t)a.n * a.n * a.ids.n;
+  hipLaunchKernelGGL(fwd3_kernel, dim3(g, g, a.ids.n * kSeg), dim3(256), 0, st, a.geom, a.ids, a.N,
+                     a.n, a.vol[0], a.vol[1], a.vol[2], a.part, stride, a.ctl);
+  hipLaunchKernelGGL(fwd3_reduce_kernel, dim3(fwd3_num_workgroups(a.n, a.ids.n)), dim3(256), 0, st,
+                     a.geom, a.ids, a.n, a.part, stride, a.sub, a.out32, a.out64, a.pd, a.lam,
+                     a.dots, a.ctl);
+  return hipGetLastError();
+}
+
+hipError_t launch_relayout3(const float* src, float* dst, int N, int m, hipStream_t st) {
+  const dim3 grid((N + kVX - 1) / kVX, (N + kVY - 1) / kVY, (N + kVZ - 1) / kVZ);
+  hipLaunchKernelGGL(relayout3_kernel, grid, dim3(256), 0, st, src, dst, N, m);
   return hipGetLastError();
 }
 
@@ -355,10 +425,10 @@ hipError_t launch_back3(const Back3Args& a, hipStream_t st) {
   const dim3 grid((a.N + kVX - 1) / kVX, (a.N + kVY - 1) / kVY, (a.N + kVZ - 1) / kVZ);
   if (a.v64)
     hipLaunchKernelGGL(back3_kernel<double>, grid, dim3(256), 0, st, a.geom, a.ids, a.N, a.n, a.v64,
-                       a.out, a.x, a.x_true, a.partials, a.mode, a.ctl);
+                       a.out[0], a.out[1], a.out[2], a.x, a.x_true, a.partials, a.mode, a.ctl);
   else
     hipLaunchKernelGGL(back3_kernel<float>, grid, dim3(256), 0, st, a.geom, a.ids, a.N, a.n, a.v32,
-                       a.out, a.x, a.x_true, a.partials, a.mode, a.ctl);
+                       a.out[0], a.out[1], a.out[2], a.x, a.x_true, a.partials, a.mode, a.ctl);
   return hipGetLastError();
 }
 

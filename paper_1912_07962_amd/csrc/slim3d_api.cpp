@@ -59,7 +59,13 @@ struct slim3d_ctx {
   double* d_q = nullptr;      // (M M^T + lam I) pd   [pmax]
   double* d_z = nullptr;      // solution             [pmax]
   float* d_u = nullptr;       // M^T pd               [N^3]
+  // volumes stored with x (0) or y (1) slowest, read by the forward projector
+  // for directions of that major axis: copies of x for the residual, of u in
+  // the CG, of the caller's image in slim3d_project
+  float* d_lay[2] = {nullptr, nullptr};
   double* d_dots = nullptr;   // forward partial dots
+  double* d_part = nullptr;   // forward per-segment ray sums, for up to wmax directions
+  int wmax = 0;               // directions of the largest window, (r+1) g
   double* d_parts = nullptr;  // vector-kernel partial sums
   int nparts = 0;
   double* d_sc = nullptr;     // CG scalars
@@ -80,7 +86,10 @@ struct slim3d_ctx {
     (void)hipFree(d_q);
     (void)hipFree(d_z);
     (void)hipFree(d_u);
+    (void)hipFree(d_lay[0]);
+    (void)hipFree(d_lay[1]);
     (void)hipFree(d_dots);
+    (void)hipFree(d_part);
     (void)hipFree(d_parts);
     (void)hipFree(d_sc);
     (void)hipFree(d_ctl);
@@ -105,6 +114,21 @@ slim_status check_dir_ids(const slim3d_ctx* c, const int32_t* ids, int n, bool a
       for (int j = 0; j < i; ++j)
         if (ids[j] == ids[i]) return set_error(SLIM_EINVAL, "duplicate direction id in a block");
   }
+  return SLIM_OK;
+}
+
+// Bit m set when a direction of the list has major axis m.
+int majors_of(const slim3d_ctx* c, const DirList& l) {
+  int mask = 0;
+  for (int i = 0; i < l.n; ++i) mask |= 1 << c->h_geom[l.id[i]].m;
+  return mask;
+}
+
+// The copies of a standard-layout volume x that the forward projector reads
+// for the majors in mask (x itself serves major z).
+slim_status relayout_for(slim3d_ctx* c, const float* x, int mask) {
+  for (int m = 0; m < 2; ++m)
+    if (mask & (1 << m)) HIP3_TRY(launch_relayout3(x, c->d_lay[m], c->N, m, c->st));
   return SLIM_OK;
 }
 
@@ -149,6 +173,8 @@ DirGeom make_geom(const double* w, int N) {
   G.Lb[0] = G.eu[b] - G.eu[m] * G.sb;
   G.Lb[1] = G.ev[b] - G.ev[m] * G.sb;
   G.scale = (2.0 / N) / std::fabs(w[m]);
+  G.wu = std::fabs(G.eu[a]) + std::fabs(G.eu[b]);
+  G.wv = std::fabs(G.ev[a]) + std::fabs(G.ev[b]);
   return G;
 }
 
@@ -184,9 +210,14 @@ slim_status do_step3(slim3d_ctx* c, const int32_t* ids, slim_step_info* info) {
     fa.ids = make_dir_list(ids, c->g);
     fa.N = c->N;
     fa.n = c->n;
-    fa.x = c->x;
+    slim_status s = relayout_for(c, c->x, majors_of(c, fa.ids));
+    if (s != SLIM_OK) return s;
+    fa.vol[0] = c->d_lay[0];
+    fa.vol[1] = c->d_lay[1];
+    fa.vol[2] = c->x;
     fa.sub = c->b;
     fa.out64 = c->d_e + (p - c->ell);
+    fa.part = c->d_part;
     HIP3_TRY(launch_fwd3(fa, c->st));
   }
   if (p > c->ell) HIP3_TRY(hipMemsetAsync(c->d_e, 0, sizeof(double) * (p - c->ell), c->st));
@@ -204,7 +235,12 @@ slim_status do_step3(slim3d_ctx* c, const int32_t* ids, slim_step_info* info) {
   bu.N = c->N;
   bu.n = c->n;
   bu.v64 = c->d_pd;
-  bu.out = c->d_u;
+  {  // u = M^T pd written in the layouts of the window's majors
+    const int mask = majors_of(c, wl);
+    bu.out[0] = (mask & 1) ? c->d_lay[0] : nullptr;
+    bu.out[1] = (mask & 2) ? c->d_lay[1] : nullptr;
+    bu.out[2] = (mask & 4) ? c->d_u : nullptr;
+  }
   bu.mode = 0;
   bu.ctl = c->d_ctl;
   Fwd3Args fq;
@@ -212,12 +248,15 @@ slim_status do_step3(slim3d_ctx* c, const int32_t* ids, slim_step_info* info) {
   fq.ids = wl;
   fq.N = c->N;
   fq.n = c->n;
-  fq.x = c->d_u;
+  fq.vol[0] = c->d_lay[0];
+  fq.vol[1] = c->d_lay[1];
+  fq.vol[2] = c->d_u;
   fq.out64 = c->d_q;
   fq.pd = c->d_pd;
   fq.lam = c->lam;
   fq.dots = c->d_dots;
   fq.ctl = c->d_ctl;
+  fq.part = c->d_part;
   const int nd = fwd3_num_workgroups(c->n, wl.n);
   int enq = 0;
   bool done = false;
@@ -363,7 +402,11 @@ slim_status slim3d_init(slim3d_ctx** out, int N, int n_dirs, const double* dirs,
   if ((e = dalloc(&c->d_q, pmax)) != hipSuccess) return oom(e);
   if ((e = dalloc(&c->d_z, pmax)) != hipSuccess) return oom(e);
   if ((e = dalloc(&c->d_u, (size_t)c->nvox)) != hipSuccess) return oom(e);
-  if ((e = dalloc(&c->d_dots, (size_t)fwd3_num_workgroups(n_det, (r + 1) * g))) != hipSuccess) return oom(e);
+  if ((e = dalloc(&c->d_lay[0], (size_t)c->nvox)) != hipSuccess) return oom(e);
+  if ((e = dalloc(&c->d_lay[1], (size_t)c->nvox)) != hipSuccess) return oom(e);
+  c->wmax = (r + 1) * g;
+  if ((e = dalloc(&c->d_dots, (size_t)fwd3_num_workgroups(n_det, c->wmax))) != hipSuccess) return oom(e);
+  if ((e = dalloc(&c->d_part, fwd3_part_doubles(n_det, c->wmax))) != hipSuccess) return oom(e);
   if ((e = dalloc(&c->d_parts, (size_t)c->nparts)) != hipSuccess) return oom(e);
   if ((e = dalloc(&c->d_sc, SC_COUNT)) != hipSuccess) return oom(e);
   if ((e = dalloc(&c->d_ctl, kCtlWords)) != hipSuccess) return oom(e);
@@ -417,9 +460,20 @@ slim_status slim3d_project(slim3d_ctx* c, const int32_t* ids, int n_ids, const f
   fa.ids = make_dir_list(ids, n_ids);
   fa.N = c->N;
   fa.n = c->n;
-  fa.x = x;
-  fa.out32 = out;
-  HIP3_TRY(launch_fwd3(fa, c->st));
+  s = relayout_for(c, x, majors_of(c, fa.ids));
+  if (s != SLIM_OK) return s;
+  fa.vol[0] = c->d_lay[0];
+  fa.vol[1] = c->d_lay[1];
+  fa.vol[2] = x;
+  fa.part = c->d_part;
+  // the partial-sum workspace holds wmax directions: launch in chunks
+  const size_t img = (size_t)c->n * c->n;
+  for (int i0 = 0; i0 < n_ids; i0 += c->wmax) {
+    const int cnt = std::min(c->wmax, n_ids - i0);
+    fa.ids = make_dir_list(ids + i0, cnt);
+    fa.out32 = out + i0 * img;
+    HIP3_TRY(launch_fwd3(fa, c->st));
+  }
   return SLIM_OK;
 }
 
@@ -435,7 +489,7 @@ slim_status slim3d_backproject(slim3d_ctx* c, const int32_t* ids, int n_ids, con
   ba.N = c->N;
   ba.n = c->n;
   ba.v32 = v;
-  ba.out = out;
+  ba.out[2] = out;
   ba.mode = 0;
   HIP3_TRY(launch_back3(ba, c->st));
   return SLIM_OK;

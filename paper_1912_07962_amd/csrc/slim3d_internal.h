@@ -23,6 +23,7 @@ struct DirGeom {
   double La[2], Lb[2];   // crossing-point displacement per detector pixel
   double sa, sb;         // crossing-point change per plane along m
   double scale;          // h / |w_m|
+  double wu, wv;         // |e_u[a]| + |e_u[b]|, |e_v[a]| + |e_v[b]|: candidate half-widths
   int m, a, b;           // major axis, the other two (x = 0, y = 1, z = 2)
   int pad;
 };
@@ -38,13 +39,17 @@ struct DirList {
 // minus sub[ids[s]][q][t] when sub is given (the data, [n_dirs][n][n]),
 // written to out64 / out32 [s][q][t].  CG tail when pd is given:
 // out64 = v + lam pd, per-workgroup partial sums of pd . out64 into dots
-// (fwd3_num_workgroups values, fixed order).  Returns at entry when
-// ctl[kCtlDone] is set.
+// (fwd3_num_workgroups values, one per 256 outputs, fixed order).  Returns
+// at entry when ctl[kCtlDone] is set.
+// The volume is read in the layout of each direction's major axis m:
+// vol[m] holds it stored with axis m slowest (plane, then axis b, then axis
+// a; vol[2] is the standard [z][y][x] layout); only the layouts of the
+// list's directions are read.
 struct Fwd3Args {
   const DirGeom* geom = nullptr;
   DirList ids;
   int N = 0, n = 0;
-  const float* x = nullptr;
+  const float* vol[3] = {nullptr, nullptr, nullptr};
   const float* sub = nullptr;
   float* out32 = nullptr;
   double* out64 = nullptr;
@@ -52,13 +57,19 @@ struct Fwd3Args {
   double lam = 0.0;
   double* dots = nullptr;
   const int* ctl = nullptr;
+  double* part = nullptr;   // workspace: fwd3_part_doubles(n, ids.n) doubles
 };
 hipError_t launch_fwd3(const Fwd3Args& a, hipStream_t st);
+// Workgroups of the reduction (= the dot partials it writes) and the
+// partial-sum workspace of a forward over n_ids directions.
 int fwd3_num_workgroups(int n, int n_ids);
+size_t fwd3_part_doubles(int n, int n_ids);
 
 // Back-projection over the directions of ids, the exact adjoint of the
 // forward: s[voxel] = sum_s sum_(q,t) A[(ids[s],q,t), voxel] v[s][q][t] with v
-// float32 (v32) or float64 (v64), [s][q][t].  mode 0: out = s.  mode 1:
+// float32 (v32) or float64 (v64), [s][q][t].  mode 0: out[m] = s stored
+// with axis m slowest, for every m whose out[m] is given (out[2]: the
+// standard layout).  mode 1:
 // x -= s in place and per-workgroup float64 partial norms (||s||^2,
 // ||x_new||^2, ||x_new - x_true||^2) into partials[wg * 3 + k]
 // (back3_num_workgroups values).  Returns at entry when ctl[kCtlDone] is set.
@@ -68,7 +79,7 @@ struct Back3Args {
   int N = 0, n = 0;
   const float* v32 = nullptr;
   const double* v64 = nullptr;
-  float* out = nullptr;
+  float* out[3] = {nullptr, nullptr, nullptr};
   float* x = nullptr;
   const float* x_true = nullptr;
   double* partials = nullptr;
@@ -76,6 +87,8 @@ struct Back3Args {
   const int* ctl = nullptr;
 };
 hipError_t launch_back3(const Back3Args& a, hipStream_t st);
+// dst = src (standard layout) stored with axis m slowest (m = 0 or 1).
+hipError_t launch_relayout3(const float* src, float* dst, int N, int m, hipStream_t st);
 int64_t back3_num_workgroups(int N);
 
 // CG on (lam I + M M^T) z = e in float64 (e: p entries), matrix-free:
