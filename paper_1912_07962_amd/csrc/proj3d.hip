@@ -14,20 +14,21 @@
 // CG tail.
 //
 // Back (voxel-driven gather, the exact adjoint): a workgroup owns a tile of
-// 8 x 8 x 4 voxels; per direction it stages the detector window its tile
-// projects onto (at most 17 x 17 of the 24 x 24 LDS pixels, scaled by
-// h/|w_m|) and every lane evaluates the closed-form weights of the candidate
-// rays around its voxel's own ray (2 or 3 detector columns times 2 or 3
-// rows, by the direction): the crossing-point displacement is linear in the
-// detector offset (DirGeom), and a weight is the product of two tents.
+// 16 x 16 x 8 voxels, a lane a column of 8 along z; per direction it stages
+// the detector window its tile projects onto (at most 27 x 28 of the
+// 32 x 32 LDS pixels, scaled by h/|w_m|) and every voxel evaluates the
+// closed-form weights of the candidate rays around its own ray (2 or 3
+// detector columns times 2 or 3 rows, by the direction): the crossing-point
+// displacement is linear in the detector offset (DirGeom), and a weight is
+// the product of two tents.
 #include "slim3d_internal.h"
 
 namespace slim {
 namespace {
 
 constexpr int kRT = 16;                   // forward ray tile (t and q)
-constexpr int kVX = 8, kVY = 8, kVZ = 4;  // back-projector voxel tile
-constexpr int kFP = 24;                   // staged detector window side
+constexpr int kVX = 16, kVY = 16, kVZ = 8;  // back-projector voxel tile (a lane: kVZ along z)
+constexpr int kFP = 32;                     // staged detector window side
 constexpr int kFlush = 32;                // planes per float32 partial sum
 constexpr double kTwo32 = 4294967296.0;
 constexpr float kInv32 = 2.3283064365386963e-10f;  // 2^-32
@@ -165,14 +166,37 @@ __global__ __launch_bounds__(256) void fwd3_reduce_kernel(
 
 // dst = the standard-layout volume src stored with axis m slowest
 // (lay_index); tiles of 8 x 8 x 4 voxels, so both sides move 32-byte runs.
-__global__ __launch_bounds__(256) void relayout3_kernel(const float* __restrict__ src,
-                                                        float* __restrict__ dst, int N, int m) {
-  const int j = blockIdx.x * kVX + (threadIdx.x & (kVX - 1));
-  const int i = blockIdx.y * kVY + ((threadIdx.x / kVX) & (kVY - 1));
-  const int k = blockIdx.z * kVZ + threadIdx.x / (kVX * kVY);
-  if (i < N && j < N && k < N) dst[lay_index(m, N, k, i, j)] = src[((size_t)k * N + i) * N + j];
+// dst = src stored with y slowest ([y][z][x]): rows along x move whole.
+__global__ __launch_bounds__(256) void relayout3_y_kernel(const float* __restrict__ src,
+                                                          float* __restrict__ dst, int N) {
+  const int j = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int i = blockIdx.y;
+  const int k = blockIdx.z * 4 + threadIdx.x / 64;
+  if (j < N && k < N) dst[((size_t)i * N + k) * N + j] = src[((size_t)k * N + i) * N + j];
 }
 
+// dst = src stored with x slowest ([x][z][y]): every z plane is transposed
+// through a padded 64 x 64 LDS tile, both sides in 256-byte rows.
+__global__ __launch_bounds__(256) void relayout3_x_kernel(const float* __restrict__ src,
+                                                          float* __restrict__ dst, int N) {
+  __shared__ float tile[64 * 65];
+  const int j0 = blockIdx.x * 64, i0 = blockIdx.y * 64, k = blockIdx.z;
+  const int l = threadIdx.x & 63, w = threadIdx.x / 64;
+  for (int r = w; r < 64; r += 4) {
+    const int i = i0 + r, j = j0 + l;
+    if (i < N && j < N) tile[r * 65 + l] = src[((size_t)k * N + i) * N + j];
+  }
+  __syncthreads();
+  for (int r = w; r < 64; r += 4) {
+    const int j = j0 + r, i = i0 + l;
+    if (i < N && j < N) dst[((size_t)j * N + k) * N + i] = tile[l * 65 + r];
+  }
+}
+
+// Back-projection: a workgroup owns kVX x kVY voxels (x, y) of kVZ
+// consecutive z planes, a lane one (x, y) column of kVZ voxels.  Per
+// direction the detector window of the whole tile is staged in LDS (scaled
+// by h/|w_m|); every voxel then visits its candidate rays (see above).
 template <typename VT>
 __global__ __launch_bounds__(256) void back3_kernel(
     const DirGeom* __restrict__ geom, DirList ids, int N, int n, const VT* __restrict__ v,
@@ -181,22 +205,26 @@ __global__ __launch_bounds__(256) void back3_kernel(
     int mode, const int* __restrict__ ctl) {
   if (ctl && ctl[kCtlDone]) return;
   __shared__ float sv[kFP * kFP];
+  __shared__ float tr[kVZ * kVY * (kVX + 1)];   // the tile, for the x-slowest layout
   __shared__ double sh[4];
   const int tid = threadIdx.x;
-  const int j = blockIdx.x * kVX + (tid & (kVX - 1));
-  const int i = blockIdx.y * kVY + ((tid / kVX) & (kVY - 1));
-  const int k = blockIdx.z * kVZ + tid / (kVX * kVY);
-  const bool ok = i < N && j < N && k < N;
+  const int jl = tid & (kVX - 1), il = tid / kVX;
+  const int j = blockIdx.x * kVX + jl, i = blockIdx.y * kVY + il, kb = blockIdx.z * kVZ;
+  const int nk = min(kVZ, N - kb);
+  const bool ok = i < N && j < N;
   const double hN = 0.5 * (N - 1), hn = 0.5 * (n - 1);
-  const double cx = j - hN, cy = i - hN, cz = k - hN;                 // centre / h
-  const double tx0 = blockIdx.x * kVX - hN, ty0 = blockIdx.y * kVY - hN, tz0 = blockIdx.z * kVZ - hN;
-  float acc = 0.f;
+  const double cx = j - hN, cy = i - hN, cz = kb - hN;                // centre / h
+  const double tx0 = blockIdx.x * kVX - hN, ty0 = blockIdx.y * kVY - hN;
+  float acc[kVZ];
+#pragma unroll
+  for (int c = 0; c < kVZ; ++c) acc[c] = 0.f;
   for (int s = 0; s < ids.n; ++s) {
     const DirGeom G = geom[ids.id[s]];
     // detector window of the tile: its voxels' projections, floor - 1 .. floor + 2,
     // with one more pixel on the low side for rounding between fu and umin
-    const double ub = tx0 * G.eu[0] + ty0 * G.eu[1] + tz0 * G.eu[2] + hn;
-    const double vb = tx0 * G.ev[0] + ty0 * G.ev[1] + tz0 * G.ev[2] + hn;
+    // (at most 15 sqrt 2 + 5 < 27 pixels along u, sqrt(15^2 + 15^2 + 7^2) + 5 < 28 along v)
+    const double ub = tx0 * G.eu[0] + ty0 * G.eu[1] + cz * G.eu[2] + hn;
+    const double vb = tx0 * G.ev[0] + ty0 * G.ev[1] + cz * G.ev[2] + hn;
     const double umin = ub + fmin(0.0, (kVX - 1) * G.eu[0]) + fmin(0.0, (kVY - 1) * G.eu[1]) +
                         fmin(0.0, (kVZ - 1) * G.eu[2]);
     const double vmin = vb + fmin(0.0, (kVX - 1) * G.ev[0]) + fmin(0.0, (kVY - 1) * G.ev[1]) +
@@ -219,54 +247,78 @@ __global__ __launch_bounds__(256) void back3_kernel(
       // ceil(2 wu) <= 3 of them (2 x 2 for a direction along an axis)
       const double wu = G.wu, wv = G.wv;
       const int nt = (int)ceil(2.0 * wu), nq = (int)ceil(2.0 * wv);
-      const double fu = cx * G.eu[0] + cy * G.eu[1] + cz * G.eu[2] + hn;
-      const double fv = cx * G.ev[0] + cy * G.ev[1] + cz * G.ev[2] + hn;
-      const double tsu = floor(fu - wu) + 1.0, tsv = floor(fv - wv) + 1.0;
-      const float du0 = (float)(tsu - fu), dv0 = (float)(tsv - fv);
-      // 1 .. 14 for every voxel of the tile; clamped so that no read leaves the window
-      const int lt = min(max((int)tsu - t0, 0), kFP - 3);
-      const int lq = min(max((int)tsv - q0, 0), kFP - 3);
+      const double fu_xy = cx * G.eu[0] + cy * G.eu[1] + hn;
+      const double fv_xy = cx * G.ev[0] + cy * G.ev[1] + hn;
       const float la0 = (float)G.La[0], la1 = (float)G.La[1];
       const float lb0 = (float)G.Lb[0], lb1 = (float)G.Lb[1];
-      float du[3];
 #pragma unroll
-      for (int o = 0; o < 3; ++o) du[o] = du0 + (float)o;
+      for (int c = 0; c < kVZ; ++c) {
+        const double fu = fma(cz + c, G.eu[2], fu_xy), fv = fma(cz + c, G.ev[2], fv_xy);
+        const double tsu = floor(fu - wu) + 1.0, tsv = floor(fv - wv) + 1.0;
+        const float du0 = (float)(tsu - fu), dv0 = (float)(tsv - fv);
+        // clamped so that no read leaves the window (never active for a voxel of the tile)
+        const int lt = min(max((int)tsu - t0, 0), kFP - 3);
+        const int lq = min(max((int)tsv - q0, 0), kFP - 3);
+        float a = acc[c];
 #pragma unroll
-      for (int oq = 0; oq < 3; ++oq) {
-        if (oq < nq) {   // uniform over the workgroup (one direction)
-          const float dv = dv0 + (float)oq;
-          const float ra = la1 * dv, rb = lb1 * dv;
-          const float* row = sv + (lq + oq) * kFP + lt;
+        for (int oq = 0; oq < 3; ++oq) {
+          if (oq < nq) {   // uniform over the workgroup (one direction)
+            const float dv = dv0 + (float)oq;
+            const float ra = la1 * dv, rb = lb1 * dv;
+            const float* row = sv + (lq + oq) * kFP + lt;
 #pragma unroll
-          for (int ot = 0; ot < 3; ++ot) {
-            if (ot < nt) {
-              const float wa = unit_clamp(1.f - fabsf(fmaf(la0, du[ot], ra)));
-              const float wb = unit_clamp(1.f - fabsf(fmaf(lb0, du[ot], rb)));
-              acc = fmaf(wa * wb, row[ot], acc);
+            for (int ot = 0; ot < 3; ++ot) {
+              if (ot < nt) {
+                const float du = du0 + (float)ot;
+                const float wa = unit_clamp(1.f - fabsf(fmaf(la0, du, ra)));
+                const float wb = unit_clamp(1.f - fabsf(fmaf(lb0, du, rb)));
+                a = fmaf(wa * wb, row[ot], a);
+              }
             }
           }
         }
+        acc[c] = a;
       }
     }
   }
-  const size_t idx = ((size_t)(ok ? k : 0) * N + (ok ? i : 0)) * N + (ok ? j : 0);
   if (mode == 0) {
     if (ok) {
-      if (out0) out0[lay_index(0, N, k, i, j)] = acc;
-      if (out1) out1[lay_index(1, N, k, i, j)] = acc;
-      if (out2) out2[idx] = acc;
+#pragma unroll
+      for (int c = 0; c < kVZ; ++c) {
+        if (c < nk) {
+          if (out2) out2[((size_t)(kb + c) * N + i) * N + j] = acc[c];
+          if (out1) out1[lay_index(1, N, kb + c, i, j)] = acc[c];
+        }
+      }
+    }
+    if (out0) {  // rows along y: through LDS, so that a wave writes 64-byte runs
+#pragma unroll
+      for (int c = 0; c < kVZ; ++c) tr[(c * kVY + il) * (kVX + 1) + jl] = acc[c];
+      __syncthreads();
+      for (int e = tid; e < kVZ * kVY * kVX; e += 256) {
+        const int il2 = e % kVY, c = (e / kVY) % kVZ, jl2 = e / (kVY * kVZ);
+        const int i2 = blockIdx.y * kVY + il2, j2 = blockIdx.x * kVX + jl2;
+        if (i2 < N && j2 < N && c < nk)
+          out0[lay_index(0, N, kb + c, i2, j2)] = tr[(c * kVY + il2) * (kVX + 1) + jl2];
+      }
     }
     return;
   }
   double n0 = 0.0, n1 = 0.0, n2 = 0.0;
   if (ok) {
-    const float xn = x[idx] - acc;
-    x[idx] = xn;
-    n0 = (double)acc * acc;
-    n1 = (double)xn * xn;
-    if (x_true) {
-      const double e = (double)xn - (double)x_true[idx];
-      n2 = e * e;
+#pragma unroll
+    for (int c = 0; c < kVZ; ++c) {
+      if (c < nk) {
+        const size_t idx = ((size_t)(kb + c) * N + i) * N + j;
+        const float xn = x[idx] - acc[c];
+        x[idx] = xn;
+        n0 += (double)acc[c] * acc[c];
+        n1 += (double)xn * xn;
+        if (x_true) {
+          const double e = (double)xn - (double)x_true[idx];
+          n2 += e * e;
+        }
+      }
     }
   }
   n0 = block_sum(n0, sh);
@@ -412,8 +464,12 @@ hipError_t launch_fwd3(const Fwd3Args& a, hipStream_t st) {
 }
 
 hipError_t launch_relayout3(const float* src, float* dst, int N, int m, hipStream_t st) {
-  const dim3 grid((N + kVX - 1) / kVX, (N + kVY - 1) / kVY, (N + kVZ - 1) / kVZ);
-  hipLaunchKernelGGL(relayout3_kernel, grid, dim3(256), 0, st, src, dst, N, m);
+  if (m == 1)
+    hipLaunchKernelGGL(relayout3_y_kernel, dim3((N + 63) / 64, N, (N + 3) / 4), dim3(256), 0, st,
+                       src, dst, N);
+  else
+    hipLaunchKernelGGL(relayout3_x_kernel, dim3((N + 63) / 64, (N + 63) / 64, N), dim3(256), 0, st,
+                       src, dst, N);
   return hipGetLastError();
 }
 
