@@ -452,7 +452,9 @@ def proj3d_bench(dev, steps):
         t_f = _time(lambda: s.project([d], xt, out_f))
         t_b = _time(lambda: s.backproject([d], v, out_b))
         cross = crossings3(N, n, dirs[d])
-        proj.append({"dir": d, "fwd_us": t_f * 1e6, "back_us": t_b * 1e6,
+        w = np.abs(dirs[d])
+        proj.append({"dir": d, "major_axis": "xyz"[int(np.argmax(w))],
+                     "fwd_us": t_f * 1e6, "back_us": t_b * 1e6,
                      "fwd_rays_per_s": n * n / t_f, "back_rays_per_s": n * n / t_b,
                      "fwd_back_rays_per_s": n * n / (t_f + t_b),
                      # algorithmic traffic: the volume once and the image once each way

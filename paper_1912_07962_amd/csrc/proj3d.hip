@@ -1,17 +1,20 @@
 // Matrix-free 3D parallel-beam projectors (Joseph's method along the major
 // axis) and the float64 CG kernels of the 3D slimLS path, for gfx950.
 //
-// Forward (ray-driven): the volume is read stored with the direction's major
-// axis m slowest, so every plane x_m = const a ray crosses is a contiguous
-// N x N block whose rows run along the axis a.  A workgroup owns a 16 x 16
-// tile of detector pixels of one direction and one of kSeg segments of the
-// planes; each lane walks its ray through the segment's planes it crosses
-// inside the volume, its crossing point in 32.32 fixed point (one 64-bit add
-// per plane and axis), and interpolates bilinearly between the four voxel
-// centres around it (masked loads: zero outside the volume).  Ray sums run
-// in float32 over 32 planes and accumulate in float64; a second kernel adds
-// the segments' sums in a fixed order and applies h/|w_m|, the data and the
-// CG tail.
+// Forward (ray-driven): the volume is read in a padded layout stored with
+// the direction's major axis m slowest, so every plane x_m = const a ray
+// crosses is a contiguous block of rows along the axis a, each starting on a
+// 16-byte boundary.  A workgroup owns a 16 x 16 tile of detector pixels of
+// one direction and one of kSeg segments of the planes, and walks the planes
+// its rays cross four at a time: the box of voxels around the tile's
+// crossing points in each plane (at most 32 x 32: a detector step moves the
+// crossing point by at most 2 voxels along a and along b) is staged in LDS
+// with 16-byte loads, zeros outside the volume; every lane then advances its
+// crossing point in 32.32 fixed point (one 64-bit add per plane and axis) and
+// interpolates bilinearly between the four voxel centres around it.  Ray sums
+// run in float32 over 32 planes and accumulate in float64; a second kernel
+// adds the segments' sums in a fixed order and applies h/|w_m|, the data and
+// the CG tail.
 //
 // Back (voxel-driven gather, the exact adjoint): a workgroup owns a tile of
 // 16 x 16 x 8 voxels, a lane a column of 8 along z; per direction it stages
@@ -58,76 +61,138 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   return s;
 }
 
-// Index of voxel (z k, y i, x j) in the volume stored with axis m slowest:
-// plane k_m, then axis b, then axis a fastest (a < b the other two axes), so
-// a plane crossed by the rays of a direction with major axis m is one
-// contiguous N x N block.  m = 2 is the standard [z][y][x] layout.
-__device__ __forceinline__ size_t lay_index(int m, int N, int k, int i, int j) {
-  if (m == 2) return ((size_t)k * N + i) * N + j;
-  if (m == 1) return ((size_t)i * N + k) * N + j;
-  return ((size_t)j * N + k) * N + i;
+// Index of voxel (z k, y i, x j) in the padded volume stored with axis m
+// slowest: plane k_m, then axis b, then axis a fastest (a < b the other two
+// axes), each row of N voxels preceded by kPad zeros and padded with zeros to
+// the pitch lay_pitch(N), a multiple of four; a plane crossed by the rays of
+// a direction with major axis m is one contiguous block of N rows.
+__device__ __forceinline__ size_t lay_index(int m, int N, int P, int k, int i, int j) {
+  if (m == 2) return ((size_t)k * N + i) * P + j + kPad;
+  if (m == 1) return ((size_t)i * N + k) * P + j + kPad;
+  return ((size_t)j * N + k) * P + i + kPad;
 }
 
 // Forward: the planes along m are cut into kSeg segments, one workgroup per
 // (ray tile, direction, segment), each writing its rays' partial sums; a
 // second kernel adds the segments in a fixed order.
 constexpr int kSeg = 8;
+constexpr int kSlab = 4;            // planes staged per pass
+constexpr int kBA = 40, kBB = 34;   // staged box per plane: voxels along a, rows along b
 
 __global__ __launch_bounds__(256) void fwd3_kernel(
-    const DirGeom* __restrict__ geom, DirList ids, int N, int n, const float* __restrict__ vol0,
-    const float* __restrict__ vol1, const float* __restrict__ vol2, double* __restrict__ part,
+    const DirGeom* __restrict__ geom, DirList ids, int N, int n, const float* __restrict__ lay0,
+    const float* __restrict__ lay1, const float* __restrict__ lay2, double* __restrict__ part,
     size_t part_stride, const int* __restrict__ ctl) {
   if (ctl && ctl[kCtlDone]) return;
+  __shared__ __align__(16) float box[kSlab * kBB * kBA];
+  __shared__ int kr[8];
   const int slot = blockIdx.z / kSeg, seg = blockIdx.z - slot * kSeg;
   const DirGeom G = geom[ids.id[slot]];
-  const float* __restrict__ vol = G.m == 0 ? vol0 : (G.m == 1 ? vol1 : vol2);
-  const int t = blockIdx.x * kRT + (threadIdx.x & (kRT - 1));
-  const int q = blockIdx.y * kRT + (threadIdx.x / kRT);
-  if (t >= n || q >= n) return;
+  const float* __restrict__ vol = G.m == 0 ? lay0 : (G.m == 1 ? lay1 : lay2);
+  const int P = lay_pitch(N);
+  const int tid = threadIdx.x;
+  const int t = blockIdx.x * kRT + (tid & (kRT - 1));
+  const int q = blockIdx.y * kRT + (tid / kRT);
+  const bool live = t < n && q < n;
   const double hN = 0.5 * (N - 1), hn = 0.5 * (n - 1);
   const double fa0 = hN + (t - hn) * G.La[0] + (q - hn) * G.La[1] - hN * G.sa;
   const double fb0 = hN + (t - hn) * G.Lb[0] + (q - hn) * G.Lb[1] - hN * G.sb;
+  // the crossing points of the tile's rays (live or not) in plane k lie in
+  // [amin0 + k sa, amin0 + k sa + aspan] along a (b likewise): the tile's
+  // corners bound them, the crossing point being linear in (t, q)
+  const double tc = blockIdx.x * kRT - hn, qc = blockIdx.y * kRT - hn;
+  const double amin0 = hN + tc * G.La[0] + qc * G.La[1] - hN * G.sa +
+                       fmin(0.0, (kRT - 1) * G.La[0]) + fmin(0.0, (kRT - 1) * G.La[1]);
+  const double bmin0 = hN + tc * G.Lb[0] + qc * G.Lb[1] - hN * G.sb +
+                       fmin(0.0, (kRT - 1) * G.Lb[0]) + fmin(0.0, (kRT - 1) * G.Lb[1]);
+  const double aspan = (kRT - 1) * (fabs(G.La[0]) + fabs(G.La[1]));   // <= 30
+  const double bspan = (kRT - 1) * (fabs(G.Lb[0]) + fabs(G.Lb[1]));
+  // staged per plane: rows floor(bmin) - 1 .. floor(bmin) + ceil(bspan) + 2
+  // and voxels from floor(amin) - 1 rounded down to a multiple of four to
+  // floor(amin) + ceil(aspan) + 2, one voxel of slack on either side for
+  // rounding between the lanes' fixed point and bmin/amin
+  const int nrow = min(kBB, (int)ceil(bspan) + 4);
+  const int nvec = min(kBA / 4, ((int)ceil(aspan) + 7 + 3) / 4);
   // the ray's planes (-1 < f < N on both axes) within this segment
-  double lo = (double)(seg * N / kSeg), hi = (double)((seg + 1) * N / kSeg - 1);
+  const int s0 = seg * N / kSeg, s1 = (seg + 1) * N / kSeg - 1;
+  double lo = (double)s0, hi = (double)s1;
   plane_range(fa0, G.sa, N, lo, hi);
   plane_range(fb0, G.sb, N, lo, hi);
-  const int k0 = (int)fmin((double)N, fmax((double)(seg * N / kSeg), floor(lo)));
-  const int k1 = (int)fmax(-1.0, fmin((double)((seg + 1) * N / kSeg - 1), ceil(hi)));
+  int k0 = live ? (int)fmin((double)N, fmax((double)s0, floor(lo))) : N;
+  int k1 = live ? (int)fmax(-1.0, fmin((double)s1, ceil(hi))) : -1;
+  if (k0 > k1) {
+    k0 = N;
+    k1 = -1;
+  }
+  // the workgroup walks the union of its rays' plane ranges (a lane outside
+  // its own range finds its crossing point outside the volume: zeros)
+  for (int o = 32; o > 0; o >>= 1) {
+    k0 = min(k0, __shfl_xor(k0, o, 64));
+    k1 = max(k1, __shfl_xor(k1, o, 64));
+  }
+  if ((tid & 63) == 0) {
+    kr[tid >> 6] = k0;
+    kr[4 + (tid >> 6)] = k1;
+  }
+  __syncthreads();
+  const int K0 = min(min(kr[0], kr[1]), min(kr[2], kr[3]));
+  const int K1 = max(max(kr[4], kr[5]), max(kr[6], kr[7]));
   double sum = 0.0;
-  if (k0 <= k1) {
-    // within a plane of the m-major layout, axis a is contiguous, b has
-    // stride N; the planes have stride N^2
-    const size_t sm = (size_t)N * N;
-    int64_t Fa = llrint((fa0 + k0 * G.sa) * kTwo32), Fb = llrint((fb0 + k0 * G.sb) * kTwo32);
+  if (K0 <= K1) {
+    const size_t sm = (size_t)N * P;
+    int64_t Fa = llrint((fa0 + K0 * G.sa) * kTwo32), Fb = llrint((fb0 + K0 * G.sb) * kTwo32);
     const int64_t Sa = llrint(G.sa * kTwo32), Sb = llrint(G.sb * kTwo32);
-    const unsigned uN = (unsigned)N;
+    const int per = nrow * nvec;
+    const float inv_per = 1.0f / (float)per, inv_nvec = 1.0f / (float)nvec;
     float acc = 0.f;
     int cnt = 0;
-#pragma unroll 2
-    for (int k = k0; k <= k1; ++k) {
-      const int ia = (int)(Fa >> 32), ib = (int)(Fb >> 32);
-      const float fa = (float)(uint32_t)Fa * kInv32, fb = (float)(uint32_t)Fb * kInv32;
-      const bool a0 = (unsigned)ia < uN, a1 = (unsigned)(ia + 1) < uN;
-      const bool b0 = (unsigned)ib < uN, b1 = (unsigned)(ib + 1) < uN;
-      const float* p = vol + (k * sm + (size_t)ib * N + ia);
-      const float v00 = (a0 && b0) ? p[0] : 0.f;
-      const float v10 = (a1 && b0) ? p[1] : 0.f;
-      const float v01 = (a0 && b1) ? p[N] : 0.f;
-      const float v11 = (a1 && b1) ? p[N + 1] : 0.f;
-      const float lo_b = fmaf(fa, v10 - v00, v00);
-      const float hi_b = fmaf(fa, v11 - v01, v01);
-      acc += fmaf(fb, hi_b - lo_b, lo_b);
-      Fa += Sa;
-      Fb += Sb;
-      if (++cnt == kFlush) {
-        sum += (double)acc;
-        acc = 0.f;
-        cnt = 0;
+    for (int k = K0; k <= K1; k += kSlab) {
+      const int np = min(kSlab, K1 - k + 1);
+      __syncthreads();  // the previous slab's reads are done
+      // stage rows of 16-byte vectors (zeros outside the volume: the padded
+      // layout's pads, rows outside 0 .. N-1 and vectors outside the pitch)
+      for (int e = tid; e < np * per; e += 256) {
+        // exact: the quotients' fractional parts stay >= 0.5 / per from integers
+        const int pl = (int)(((float)e + 0.5f) * inv_per);
+        const int r = e - pl * per;
+        const int row = (int)(((float)r + 0.5f) * inv_nvec);
+        const int c = r - row * nvec;
+        const int A0 = ((int)floor(fma((double)(k + pl), G.sa, amin0)) - 1) & ~3;
+        const int b = (int)floor(fma((double)(k + pl), G.sb, bmin0)) - 1 + row;
+        const int as = A0 + 4 * c + kPad;
+        float4 val = make_float4(0.f, 0.f, 0.f, 0.f);
+        if ((unsigned)b < (unsigned)N && as >= 0 && as + 4 <= P)
+          val = *reinterpret_cast<const float4*>(vol + ((size_t)(k + pl) * sm + (size_t)b * P + as));
+        *reinterpret_cast<float4*>(box + (pl * kBB + row) * kBA + 4 * c) = val;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int pl = 0; pl < kSlab; ++pl) {
+        if (pl < np) {
+          const int A0 = ((int)floor(fma((double)(k + pl), G.sa, amin0)) - 1) & ~3;
+          const int B0 = (int)floor(fma((double)(k + pl), G.sb, bmin0)) - 1;
+          const int ia = (int)(Fa >> 32), ib = (int)(Fb >> 32);
+          const float fa = (float)(uint32_t)Fa * kInv32, fb = (float)(uint32_t)Fb * kInv32;
+          // never clamped for a ray of the tile (see the box bounds above)
+          const int la = min(max(ia - A0, 0), kBA - 2), lb = min(max(ib - B0, 0), kBB - 2);
+          const float* bx = box + (pl * kBB + lb) * kBA + la;
+          const float v00 = bx[0], v10 = bx[1], v01 = bx[kBA], v11 = bx[kBA + 1];
+          const float lo_b = fmaf(fa, v10 - v00, v00);
+          const float hi_b = fmaf(fa, v11 - v01, v01);
+          acc += fmaf(fb, hi_b - lo_b, lo_b);
+          Fa += Sa;
+          Fb += Sb;
+          if (++cnt == kFlush) {
+            sum += (double)acc;
+            acc = 0.f;
+            cnt = 0;
+          }
+        }
       }
     }
     sum += (double)acc;
   }
-  part[seg * part_stride + ((size_t)slot * n + q) * n + t] = sum;
+  if (live) part[seg * part_stride + ((size_t)slot * n + q) * n + t] = sum;
 }
 
 // out[s][q][t] = (h/|w_m|) sum_segments part - sub for every ray (fixed
@@ -164,22 +229,26 @@ __global__ __launch_bounds__(256) void fwd3_reduce_kernel(
   }
 }
 
-// dst = the standard-layout volume src stored with axis m slowest
-// (lay_index); tiles of 8 x 8 x 4 voxels, so both sides move 32-byte runs.
-// dst = src stored with y slowest ([y][z][x]): rows along x move whole.
-__global__ __launch_bounds__(256) void relayout3_y_kernel(const float* __restrict__ src,
-                                                          float* __restrict__ dst, int N) {
-  const int j = blockIdx.x * 64 + (threadIdx.x & 63);
-  const int i = blockIdx.y;
-  const int k = blockIdx.z * 4 + threadIdx.x / 64;
-  if (j < N && k < N) dst[((size_t)i * N + k) * N + j] = src[((size_t)k * N + i) * N + j];
+// dst = the standard-layout volume src in the padded layout of major axis m
+// (lay_index; the pads are never written).  m = 1, 2: rows along x move
+// whole, a wave per row.
+__global__ __launch_bounds__(256) void relayout3_rows_kernel(const float* __restrict__ src,
+                                                             float* __restrict__ dst, int N, int m) {
+  const int P = lay_pitch(N);
+  const int i = blockIdx.x;
+  const int k = blockIdx.y * 4 + threadIdx.x / 64;
+  if (k >= N) return;
+  const float* __restrict__ s = src + ((size_t)k * N + i) * N;
+  float* __restrict__ d = dst + lay_index(m, N, P, k, i, 0);
+  for (int j = threadIdx.x & 63; j < N; j += 64) d[j] = s[j];
 }
 
-// dst = src stored with x slowest ([x][z][y]): every z plane is transposed
-// through a padded 64 x 64 LDS tile, both sides in 256-byte rows.
+// m = 0 ([x][z][y]): every z plane is transposed through a padded 64 x 64
+// LDS tile, both sides in 256-byte rows.
 __global__ __launch_bounds__(256) void relayout3_x_kernel(const float* __restrict__ src,
                                                           float* __restrict__ dst, int N) {
   __shared__ float tile[64 * 65];
+  const int P = lay_pitch(N);
   const int j0 = blockIdx.x * 64, i0 = blockIdx.y * 64, k = blockIdx.z;
   const int l = threadIdx.x & 63, w = threadIdx.x / 64;
   for (int r = w; r < 64; r += 4) {
@@ -189,7 +258,7 @@ __global__ __launch_bounds__(256) void relayout3_x_kernel(const float* __restric
   __syncthreads();
   for (int r = w; r < 64; r += 4) {
     const int j = j0 + r, i = i0 + l;
-    if (i < N && j < N) dst[((size_t)j * N + k) * N + i] = tile[l * 65 + r];
+    if (i < N && j < N) dst[lay_index(0, N, P, k, i, j)] = tile[l * 65 + r];
   }
 }
 
@@ -200,9 +269,9 @@ __global__ __launch_bounds__(256) void relayout3_x_kernel(const float* __restric
 template <typename VT>
 __global__ __launch_bounds__(256) void back3_kernel(
     const DirGeom* __restrict__ geom, DirList ids, int N, int n, const VT* __restrict__ v,
-    float* __restrict__ out0, float* __restrict__ out1, float* __restrict__ out2,
-    float* __restrict__ x, const float* __restrict__ x_true, double* __restrict__ partials,
-    int mode, const int* __restrict__ ctl) {
+    float* __restrict__ out, float* __restrict__ out0, float* __restrict__ out1,
+    float* __restrict__ out2, float* __restrict__ x, const float* __restrict__ x_true,
+    double* __restrict__ partials, int mode, const int* __restrict__ ctl) {
   if (ctl && ctl[kCtlDone]) return;
   __shared__ float sv[kFP * kFP];
   __shared__ float tr[kVZ * kVY * (kVX + 1)];   // the tile, for the x-slowest layout
@@ -282,12 +351,14 @@ __global__ __launch_bounds__(256) void back3_kernel(
     }
   }
   if (mode == 0) {
+    const int P = lay_pitch(N);
     if (ok) {
 #pragma unroll
       for (int c = 0; c < kVZ; ++c) {
         if (c < nk) {
-          if (out2) out2[((size_t)(kb + c) * N + i) * N + j] = acc[c];
-          if (out1) out1[lay_index(1, N, kb + c, i, j)] = acc[c];
+          if (out) out[((size_t)(kb + c) * N + i) * N + j] = acc[c];
+          if (out2) out2[lay_index(2, N, P, kb + c, i, j)] = acc[c];
+          if (out1) out1[lay_index(1, N, P, kb + c, i, j)] = acc[c];
         }
       }
     }
@@ -299,7 +370,7 @@ __global__ __launch_bounds__(256) void back3_kernel(
         const int il2 = e % kVY, c = (e / kVY) % kVZ, jl2 = e / (kVY * kVZ);
         const int i2 = blockIdx.y * kVY + il2, j2 = blockIdx.x * kVX + jl2;
         if (i2 < N && j2 < N && c < nk)
-          out0[lay_index(0, N, kb + c, i2, j2)] = tr[(c * kVY + il2) * (kVX + 1) + jl2];
+          out0[lay_index(0, N, P, kb + c, i2, j2)] = tr[(c * kVY + il2) * (kVX + 1) + jl2];
       }
     }
     return;
@@ -456,7 +527,7 @@ hipError_t launch_fwd3(const Fwd3Args& a, hipStream_t st) {
   const int g = (a.n + kRT - 1) / kRT;
   const size_t stride = (size_t)a.n * a.n * a.ids.n;
   hipLaunchKernelGGL(fwd3_kernel, dim3(g, g, a.ids.n * kSeg), dim3(256), 0, st, a.geom, a.ids, a.N,
-                     a.n, a.vol[0], a.vol[1], a.vol[2], a.part, stride, a.ctl);
+                     a.n, a.lay[0], a.lay[1], a.lay[2], a.part, stride, a.ctl);
   hipLaunchKernelGGL(fwd3_reduce_kernel, dim3(fwd3_num_workgroups(a.n, a.ids.n)), dim3(256), 0, st,
                      a.geom, a.ids, a.n, a.part, stride, a.sub, a.out32, a.out64, a.pd, a.lam,
                      a.dots, a.ctl);
@@ -464,12 +535,12 @@ hipError_t launch_fwd3(const Fwd3Args& a, hipStream_t st) {
 }
 
 hipError_t launch_relayout3(const float* src, float* dst, int N, int m, hipStream_t st) {
-  if (m == 1)
-    hipLaunchKernelGGL(relayout3_y_kernel, dim3((N + 63) / 64, N, (N + 3) / 4), dim3(256), 0, st,
-                       src, dst, N);
-  else
+  if (m == 0)
     hipLaunchKernelGGL(relayout3_x_kernel, dim3((N + 63) / 64, (N + 63) / 64, N), dim3(256), 0, st,
                        src, dst, N);
+  else
+    hipLaunchKernelGGL(relayout3_rows_kernel, dim3(N, (N + 3) / 4), dim3(256), 0, st, src, dst, N,
+                       m);
   return hipGetLastError();
 }
 
@@ -481,10 +552,12 @@ hipError_t launch_back3(const Back3Args& a, hipStream_t st) {
   const dim3 grid((a.N + kVX - 1) / kVX, (a.N + kVY - 1) / kVY, (a.N + kVZ - 1) / kVZ);
   if (a.v64)
     hipLaunchKernelGGL(back3_kernel<double>, grid, dim3(256), 0, st, a.geom, a.ids, a.N, a.n, a.v64,
-                       a.out[0], a.out[1], a.out[2], a.x, a.x_true, a.partials, a.mode, a.ctl);
+                       a.out, a.lay[0], a.lay[1], a.lay[2], a.x, a.x_true, a.partials, a.mode,
+                       a.ctl);
   else
     hipLaunchKernelGGL(back3_kernel<float>, grid, dim3(256), 0, st, a.geom, a.ids, a.N, a.n, a.v32,
-                       a.out[0], a.out[1], a.out[2], a.x, a.x_true, a.partials, a.mode, a.ctl);
+                       a.out, a.lay[0], a.lay[1], a.lay[2], a.x, a.x_true, a.partials, a.mode,
+                       a.ctl);
   return hipGetLastError();
 }
 

@@ -58,11 +58,11 @@ struct slim3d_ctx {
   double* d_pd = nullptr;     // CG direction         [pmax]
   double* d_q = nullptr;      // (M M^T + lam I) pd   [pmax]
   double* d_z = nullptr;      // solution             [pmax]
-  float* d_u = nullptr;       // M^T pd               [N^3]
-  // volumes stored with x (0) or y (1) slowest, read by the forward projector
-  // for directions of that major axis: copies of x for the residual, of u in
-  // the CG, of the caller's image in slim3d_project
-  float* d_lay[2] = {nullptr, nullptr};
+  // padded volume layouts of the three major axes (lay_floats(N) floats
+  // each), read by the forward projector for directions of that major axis:
+  // copies of x for the residual, M^T pd in the CG, copies of the caller's
+  // volume in slim3d_project
+  float* d_lay[3] = {nullptr, nullptr, nullptr};
   double* d_dots = nullptr;   // forward partial dots
   double* d_part = nullptr;   // forward per-segment ray sums, for up to wmax directions
   int wmax = 0;               // directions of the largest window, (r+1) g
@@ -85,9 +85,7 @@ struct slim3d_ctx {
     (void)hipFree(d_pd);
     (void)hipFree(d_q);
     (void)hipFree(d_z);
-    (void)hipFree(d_u);
-    (void)hipFree(d_lay[0]);
-    (void)hipFree(d_lay[1]);
+    for (float* l : d_lay) (void)hipFree(l);
     (void)hipFree(d_dots);
     (void)hipFree(d_part);
     (void)hipFree(d_parts);
@@ -124,10 +122,10 @@ int majors_of(const slim3d_ctx* c, const DirList& l) {
   return mask;
 }
 
-// The copies of a standard-layout volume x that the forward projector reads
-// for the majors in mask (x itself serves major z).
+// The padded copies of a standard-layout volume x that the forward
+// projector reads for the majors in mask.
 slim_status relayout_for(slim3d_ctx* c, const float* x, int mask) {
-  for (int m = 0; m < 2; ++m)
+  for (int m = 0; m < 3; ++m)
     if (mask & (1 << m)) HIP3_TRY(launch_relayout3(x, c->d_lay[m], c->N, m, c->st));
   return SLIM_OK;
 }
@@ -212,9 +210,7 @@ slim_status do_step3(slim3d_ctx* c, const int32_t* ids, slim_step_info* info) {
     fa.n = c->n;
     slim_status s = relayout_for(c, c->x, majors_of(c, fa.ids));
     if (s != SLIM_OK) return s;
-    fa.vol[0] = c->d_lay[0];
-    fa.vol[1] = c->d_lay[1];
-    fa.vol[2] = c->x;
+    for (int m = 0; m < 3; ++m) fa.lay[m] = c->d_lay[m];
     fa.sub = c->b;
     fa.out64 = c->d_e + (p - c->ell);
     fa.part = c->d_part;
@@ -237,9 +233,7 @@ slim_status do_step3(slim3d_ctx* c, const int32_t* ids, slim_step_info* info) {
   bu.v64 = c->d_pd;
   {  // u = M^T pd written in the layouts of the window's majors
     const int mask = majors_of(c, wl);
-    bu.out[0] = (mask & 1) ? c->d_lay[0] : nullptr;
-    bu.out[1] = (mask & 2) ? c->d_lay[1] : nullptr;
-    bu.out[2] = (mask & 4) ? c->d_u : nullptr;
+    for (int m = 0; m < 3; ++m) bu.lay[m] = (mask & (1 << m)) ? c->d_lay[m] : nullptr;
   }
   bu.mode = 0;
   bu.ctl = c->d_ctl;
@@ -248,9 +242,7 @@ slim_status do_step3(slim3d_ctx* c, const int32_t* ids, slim_step_info* info) {
   fq.ids = wl;
   fq.N = c->N;
   fq.n = c->n;
-  fq.vol[0] = c->d_lay[0];
-  fq.vol[1] = c->d_lay[1];
-  fq.vol[2] = c->d_u;
+  for (int m = 0; m < 3; ++m) fq.lay[m] = c->d_lay[m];
   fq.out64 = c->d_q;
   fq.pd = c->d_pd;
   fq.lam = c->lam;
@@ -401,9 +393,8 @@ slim_status slim3d_init(slim3d_ctx** out, int N, int n_dirs, const double* dirs,
   if ((e = dalloc(&c->d_pd, pmax)) != hipSuccess) return oom(e);
   if ((e = dalloc(&c->d_q, pmax)) != hipSuccess) return oom(e);
   if ((e = dalloc(&c->d_z, pmax)) != hipSuccess) return oom(e);
-  if ((e = dalloc(&c->d_u, (size_t)c->nvox)) != hipSuccess) return oom(e);
-  if ((e = dalloc(&c->d_lay[0], (size_t)c->nvox)) != hipSuccess) return oom(e);
-  if ((e = dalloc(&c->d_lay[1], (size_t)c->nvox)) != hipSuccess) return oom(e);
+  for (float*& l : c->d_lay)
+    if ((e = dalloc(&l, lay_floats(N))) != hipSuccess) return oom(e);
   c->wmax = (r + 1) * g;
   if ((e = dalloc(&c->d_dots, (size_t)fwd3_num_workgroups(n_det, c->wmax))) != hipSuccess) return oom(e);
   if ((e = dalloc(&c->d_part, fwd3_part_doubles(n_det, c->wmax))) != hipSuccess) return oom(e);
@@ -417,7 +408,10 @@ slim_status slim3d_init(slim3d_ctx** out, int N, int n_dirs, const double* dirs,
   if ((e = hipHostMalloc((void**)&c->h_out, sizeof(double) * 8, hipHostMallocDefault)) != hipSuccess) return oom(e);
   if ((e = hipMemcpyAsync(c->d_geom, c->h_geom.data(), sizeof(DirGeom) * n_dirs,
                           hipMemcpyHostToDevice, c->st)) != hipSuccess) return oom(e);
-  // the padding of the last norm group is never written by a kernel
+  // the layouts' pads and the padding of the last norm group are never
+  // written by a kernel
+  for (float* l : c->d_lay)
+    if ((e = hipMemsetAsync(l, 0, sizeof(float) * lay_floats(N), c->st)) != hipSuccess) return oom(e);
   if ((e = hipMemsetAsync(c->d_bparts, 0, sizeof(double) * c->nbgroups * kNormGroup * 3, c->st)) != hipSuccess) return oom(e);
   if ((e = hipMemsetAsync(c->d_ctl, 0, sizeof(int) * kCtlWords, c->st)) != hipSuccess) return oom(e);
   if ((e = hipStreamSynchronize(c->st)) != hipSuccess) return oom(e);
@@ -462,9 +456,7 @@ slim_status slim3d_project(slim3d_ctx* c, const int32_t* ids, int n_ids, const f
   fa.n = c->n;
   s = relayout_for(c, x, majors_of(c, fa.ids));
   if (s != SLIM_OK) return s;
-  fa.vol[0] = c->d_lay[0];
-  fa.vol[1] = c->d_lay[1];
-  fa.vol[2] = x;
+  for (int m = 0; m < 3; ++m) fa.lay[m] = c->d_lay[m];
   fa.part = c->d_part;
   // the partial-sum workspace holds wmax directions: launch in chunks
   const size_t img = (size_t)c->n * c->n;
@@ -489,7 +481,7 @@ slim_status slim3d_backproject(slim3d_ctx* c, const int32_t* ids, int n_ids, con
   ba.N = c->N;
   ba.n = c->n;
   ba.v32 = v;
-  ba.out[2] = out;
+  ba.out = out;
   ba.mode = 0;
   HIP3_TRY(launch_back3(ba, c->st));
   return SLIM_OK;

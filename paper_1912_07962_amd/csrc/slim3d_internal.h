@@ -28,6 +28,15 @@ struct DirGeom {
   int pad;
 };
 
+// Padded volume layouts read by the forward projector and written by the
+// back-projector: stored with axis m slowest (plane along m, then the higher
+// of the other two axes, then the lower), each row of N voxels preceded by
+// kPad zeros and followed by zeros up to the pitch lay_pitch(N), a multiple
+// of four (16-byte rows).  The pads are zeroed once and never written.
+constexpr int kPad = 4;
+__host__ __device__ inline int lay_pitch(int N) { return (N + 2 * kPad + 3) / 4 * 4; }
+inline size_t lay_floats(int N) { return (size_t)N * N * lay_pitch(N); }
+
 // Directions of one launch (a window of r+1 blocks of g directions).
 struct DirList {
   int n;
@@ -41,15 +50,13 @@ struct DirList {
 // out64 = v + lam pd, per-workgroup partial sums of pd . out64 into dots
 // (fwd3_num_workgroups values, one per 256 outputs, fixed order).  Returns
 // at entry when ctl[kCtlDone] is set.
-// The volume is read in the layout of each direction's major axis m:
-// vol[m] holds it stored with axis m slowest (plane, then axis b, then axis
-// a; vol[2] is the standard [z][y][x] layout); only the layouts of the
-// list's directions are read.
+// The volume is read in the padded layout of each direction's major axis
+// m, lay[m]; only the layouts of the list's directions are read.
 struct Fwd3Args {
   const DirGeom* geom = nullptr;
   DirList ids;
   int N = 0, n = 0;
-  const float* vol[3] = {nullptr, nullptr, nullptr};
+  const float* lay[3] = {nullptr, nullptr, nullptr};
   const float* sub = nullptr;
   float* out32 = nullptr;
   double* out64 = nullptr;
@@ -67,9 +74,9 @@ size_t fwd3_part_doubles(int n, int n_ids);
 
 // Back-projection over the directions of ids, the exact adjoint of the
 // forward: s[voxel] = sum_s sum_(q,t) A[(ids[s],q,t), voxel] v[s][q][t] with v
-// float32 (v32) or float64 (v64), [s][q][t].  mode 0: out[m] = s stored
-// with axis m slowest, for every m whose out[m] is given (out[2]: the
-// standard layout).  mode 1:
+// float32 (v32) or float64 (v64), [s][q][t].  mode 0: out = s in the
+// standard [z][y][x] layout when out is given, and lay[m] = s in the padded
+// layout of major axis m for every m whose lay[m] is given.  mode 1:
 // x -= s in place and per-workgroup float64 partial norms (||s||^2,
 // ||x_new||^2, ||x_new - x_true||^2) into partials[wg * 3 + k]
 // (back3_num_workgroups values).  Returns at entry when ctl[kCtlDone] is set.
@@ -79,7 +86,8 @@ struct Back3Args {
   int N = 0, n = 0;
   const float* v32 = nullptr;
   const double* v64 = nullptr;
-  float* out[3] = {nullptr, nullptr, nullptr};
+  float* out = nullptr;
+  float* lay[3] = {nullptr, nullptr, nullptr};
   float* x = nullptr;
   const float* x_true = nullptr;
   double* partials = nullptr;
@@ -87,7 +95,7 @@ struct Back3Args {
   const int* ctl = nullptr;
 };
 hipError_t launch_back3(const Back3Args& a, hipStream_t st);
-// dst = src (standard layout) stored with axis m slowest (m = 0 or 1).
+// dst = src (standard layout) in the padded layout of major axis m.
 hipError_t launch_relayout3(const float* src, float* dst, int N, int m, hipStream_t st);
 int64_t back3_num_workgroups(int N);
 
