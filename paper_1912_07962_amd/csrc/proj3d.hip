@@ -79,6 +79,8 @@ constexpr int kSeg = 8;
 constexpr int kSlab = 4;            // planes staged per pass
 constexpr int kBA = 40, kBB = 34;   // staged box per plane: voxels along a, rows along b
 
+constexpr int kStage = (kSlab * kBB * kBA / 4 + 255) / 256;   // 16-byte loads per lane per slab
+
 __global__ __launch_bounds__(256) void fwd3_kernel(
     const DirGeom* __restrict__ geom, DirList ids, int N, int n, const float* __restrict__ lay0,
     const float* __restrict__ lay1, const float* __restrict__ lay2, double* __restrict__ part,
@@ -86,13 +88,20 @@ __global__ __launch_bounds__(256) void fwd3_kernel(
   if (ctl && ctl[kCtlDone]) return;
   __shared__ __align__(16) float box[kSlab * kBB * kBA];
   __shared__ int kr[8];
-  const int slot = blockIdx.z / kSeg, seg = blockIdx.z - slot * kSeg;
+  // XCD-aware numbering: consecutive positions (neighbouring tiles, whose
+  // boxes overlap) run on one XCD and share its L2
+  const int gt = (n + kRT - 1) / kRT;
+  const int per_xcd = gridDim.x >> 3;
+  const int pos = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+  if (pos >= gt * gt * kSeg * ids.n) return;
+  const int tt = pos % gt, tq = (pos / gt) % gt, ss = pos / (gt * gt);
+  const int slot = ss / kSeg, seg = ss - slot * kSeg;
   const DirGeom G = geom[ids.id[slot]];
   const float* __restrict__ vol = G.m == 0 ? lay0 : (G.m == 1 ? lay1 : lay2);
   const int P = lay_pitch(N);
   const int tid = threadIdx.x;
-  const int t = blockIdx.x * kRT + (tid & (kRT - 1));
-  const int q = blockIdx.y * kRT + (tid / kRT);
+  const int t = tt * kRT + (tid & (kRT - 1));
+  const int q = tq * kRT + (tid / kRT);
   const bool live = t < n && q < n;
   const double hN = 0.5 * (N - 1), hn = 0.5 * (n - 1);
   const double fa0 = hN + (t - hn) * G.La[0] + (q - hn) * G.La[1] - hN * G.sa;
@@ -100,7 +109,7 @@ __global__ __launch_bounds__(256) void fwd3_kernel(
   // the crossing points of the tile's rays (live or not) in plane k lie in
   // [amin0 + k sa, amin0 + k sa + aspan] along a (b likewise): the tile's
   // corners bound them, the crossing point being linear in (t, q)
-  const double tc = blockIdx.x * kRT - hn, qc = blockIdx.y * kRT - hn;
+  const double tc = tt * kRT - hn, qc = tq * kRT - hn;
   const double amin0 = hN + tc * G.La[0] + qc * G.La[1] - hN * G.sa +
                        fmin(0.0, (kRT - 1) * G.La[0]) + fmin(0.0, (kRT - 1) * G.La[1]);
   const double bmin0 = hN + tc * G.Lb[0] + qc * G.Lb[1] - hN * G.sb +
@@ -110,7 +119,7 @@ __global__ __launch_bounds__(256) void fwd3_kernel(
   // staged per plane: rows floor(bmin) - 1 .. floor(bmin) + ceil(bspan) + 2
   // and voxels from floor(amin) - 1 rounded down to a multiple of four to
   // floor(amin) + ceil(aspan) + 2, one voxel of slack on either side for
-  // rounding between the lanes' fixed point and bmin/amin
+  // rounding between the lanes' crossing points and the box's
   const int nrow = min(kBB, (int)ceil(bspan) + 4);
   const int nvec = min(kBA / 4, ((int)ceil(aspan) + 7 + 3) / 4);
   // the ray's planes (-1 < f < N on both axes) within this segment
@@ -140,37 +149,57 @@ __global__ __launch_bounds__(256) void fwd3_kernel(
   double sum = 0.0;
   if (K0 <= K1) {
     const size_t sm = (size_t)N * P;
-    int64_t Fa = llrint((fa0 + K0 * G.sa) * kTwo32), Fb = llrint((fb0 + K0 * G.sb) * kTwo32);
+    // crossing points (lanes) and box corners in 32.32 fixed point from K0,
+    // all advanced by the same per-plane steps
     const int64_t Sa = llrint(G.sa * kTwo32), Sb = llrint(G.sb * kTwo32);
+    int64_t Fa = llrint((fa0 + K0 * G.sa) * kTwo32), Fb = llrint((fb0 + K0 * G.sb) * kTwo32);
+    const int64_t Ma = llrint((amin0 + K0 * G.sa) * kTwo32), Mb = llrint((bmin0 + K0 * G.sb) * kTwo32);
     const int per = nrow * nvec;
     const float inv_per = 1.0f / (float)per, inv_nvec = 1.0f / (float)nvec;
+    // slab staging in two halves: the loads of slab k + kSlab are in flight
+    // while slab k is interpolated from LDS
+    float4 pre[kStage];
+    int off[kStage];
+    auto load_slab = [&](int k) {
+      const int np = min(kSlab, K1 - k + 1);
+#pragma unroll
+      for (int u = 0; u < kStage; ++u) {
+        const int e = tid + 256 * u;
+        pre[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+        off[u] = -1;
+        if (e < np * per) {
+          // exact: the quotients' fractional parts stay >= 0.5 / per from integers
+          const int pl = (int)(((float)e + 0.5f) * inv_per);
+          const int r = e - pl * per;
+          const int row = (int)(((float)r + 0.5f) * inv_nvec);
+          const int c = r - row * nvec;
+          const int64_t dk = k + pl - K0;
+          const int A0 = ((int)((Ma + dk * Sa) >> 32) - 1) & ~3;
+          const int b = (int)((Mb + dk * Sb) >> 32) - 1 + row;
+          const int as = A0 + 4 * c + kPad;
+          off[u] = (pl * kBB + row) * kBA + 4 * c;
+          if ((unsigned)b < (unsigned)N && as >= 0 && as + 4 <= P)
+            pre[u] = *reinterpret_cast<const float4*>(vol + ((size_t)(k + pl) * sm + (size_t)b * P + as));
+        }
+      }
+    };
+    load_slab(K0);
     float acc = 0.f;
     int cnt = 0;
     for (int k = K0; k <= K1; k += kSlab) {
       const int np = min(kSlab, K1 - k + 1);
       __syncthreads();  // the previous slab's reads are done
-      // stage rows of 16-byte vectors (zeros outside the volume: the padded
-      // layout's pads, rows outside 0 .. N-1 and vectors outside the pitch)
-      for (int e = tid; e < np * per; e += 256) {
-        // exact: the quotients' fractional parts stay >= 0.5 / per from integers
-        const int pl = (int)(((float)e + 0.5f) * inv_per);
-        const int r = e - pl * per;
-        const int row = (int)(((float)r + 0.5f) * inv_nvec);
-        const int c = r - row * nvec;
-        const int A0 = ((int)floor(fma((double)(k + pl), G.sa, amin0)) - 1) & ~3;
-        const int b = (int)floor(fma((double)(k + pl), G.sb, bmin0)) - 1 + row;
-        const int as = A0 + 4 * c + kPad;
-        float4 val = make_float4(0.f, 0.f, 0.f, 0.f);
-        if ((unsigned)b < (unsigned)N && as >= 0 && as + 4 <= P)
-          val = *reinterpret_cast<const float4*>(vol + ((size_t)(k + pl) * sm + (size_t)b * P + as));
-        *reinterpret_cast<float4*>(box + (pl * kBB + row) * kBA + 4 * c) = val;
-      }
+#pragma unroll
+      for (int u = 0; u < kStage; ++u)
+        if (off[u] >= 0) *reinterpret_cast<float4*>(box + off[u]) = pre[u];
       __syncthreads();
+      if (k + kSlab <= K1) load_slab(k + kSlab);
 #pragma unroll
       for (int pl = 0; pl < kSlab; ++pl) {
         if (pl < np) {
-          const int A0 = ((int)floor(fma((double)(k + pl), G.sa, amin0)) - 1) & ~3;
-          const int B0 = (int)floor(fma((double)(k + pl), G.sb, bmin0)) - 1;
+          const int64_t dk = k + pl - K0;
+          const int A0 = ((int)((Ma + dk * Sa) >> 32) - 1) & ~3;
+          const int B0 = (int)((Mb + dk * Sb) >> 32) - 1;
           const int ia = (int)(Fa >> 32), ib = (int)(Fb >> 32);
           const float fa = (float)(uint32_t)Fa * kInv32, fb = (float)(uint32_t)Fb * kInv32;
           // never clamped for a ray of the tile (see the box bounds above)
@@ -526,7 +555,8 @@ hipError_t launch_fwd3(const Fwd3Args& a, hipStream_t st) {
   if (a.ids.n <= 0) return hipSuccess;
   const int g = (a.n + kRT - 1) / kRT;
   const size_t stride = (size_t)a.n * a.n * a.ids.n;
-  hipLaunchKernelGGL(fwd3_kernel, dim3(g, g, a.ids.n * kSeg), dim3(256), 0, st, a.geom, a.ids, a.N,
+  const int wgs = (g * g * kSeg * a.ids.n + 7) / 8 * 8;   // a multiple of the 8 XCDs
+  hipLaunchKernelGGL(fwd3_kernel, dim3(wgs), dim3(256), 0, st, a.geom, a.ids, a.N,
                      a.n, a.lay[0], a.lay[1], a.lay[2], a.part, stride, a.ctl);
   hipLaunchKernelGGL(fwd3_reduce_kernel, dim3(fwd3_num_workgroups(a.n, a.ids.n)), dim3(256), 0, st,
                      a.geom, a.ids, a.n, a.part, stride, a.sub, a.out32, a.out64, a.pd, a.lam,
