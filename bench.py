@@ -410,7 +410,8 @@ def proj3d_bench(dev, steps):
     """The paper's 3D experiment: a 511^3 volume, projection images of
     511 x 511 pixels from 1000 directions uniform on the sphere, one image per
     block, r = 0, alpha = 1 in unit-voxel scaling (lambda = h^2), 0.1% noise,
-    CG to 1e-6: one-direction projector rays/s, then whole slimLS steps."""
+    CG to 1e-6: one-direction projector rays/s, then whole slimLS steps with
+    the Jacobi-preconditioned CG (the library's default) and with plain CG."""
     import numpy as np
     import torch
     import synth
@@ -484,6 +485,19 @@ def proj3d_bench(dev, steps):
     cg_f = stats["cg_forward"]["total_ms"] / max(stats["cg_forward"]["launches"], 1)
     cg_b = stats["cg_back"]["total_ms"] / max(stats["cg_back"]["launches"], 1)
     s.close()
+    # the same steps with plain (unpreconditioned) CG, for comparison
+    s = Slim3D(N, dirs, n_det=n, r=r, lam=lam, pcg_tol=1e-6, stream=st, gram_mode="pcg")
+    s.set_data(bd, x.zero_(), xt)
+    s.step([visit[0]])
+    st.synchronize()
+    t0 = time.perf_counter()
+    plain = [s.step([d]) for d in visit[1:]]
+    st.synchronize()
+    wall_plain = time.perf_counter() - t0
+    s.close()
+    it_plain = sum(i["pcg_iters"] for i in plain)
+    print(f"bench: 3D step with plain CG {wall_plain / len(plain) * 1e3:.1f} ms, "
+          f"{it_plain / len(plain):.1f} CG iterations", file=sys.stderr, flush=True)
     rel = [i["err_norm"] / float(np.linalg.norm(xt.cpu().numpy().astype(np.float64)))
            for i in infos[-1:]]
     print(f"bench: 3D step {wall / len(infos) * 1e3:.1f} ms, {it / len(infos):.1f} CG iterations",
@@ -492,6 +506,9 @@ def proj3d_bench(dev, steps):
             "ms_per_step": wall / len(infos) * 1e3, "rays_per_s": n * n * len(infos) / wall,
             "cg_iters_per_step": it / len(infos), "rel_err_last": rel[0],
             "cg_forward_us": cg_f * 1e3, "cg_back_us": cg_b * 1e3,
+            "preconditioner": "jacobi",
+            "plain_cg": {"ms_per_step": wall_plain / len(plain) * 1e3,
+                         "cg_iters_per_step": it_plain / len(plain)},
             "kernel_ms": {k: v2["total_ms"] for k, v2 in stats.items()}, "projector": proj}
 
 

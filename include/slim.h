@@ -61,14 +61,17 @@ typedef struct {
 } slim_grid;
 
 enum { SLIM_PREC_FP32 = 0, SLIM_PREC_BF16 = 1 };
-enum { SLIM_GRAM_AUTO = 0, SLIM_GRAM_CHOL = 1, SLIM_GRAM_PCG = 2 };
+/* Gram solve: AUTO (2D: Cholesky while p <= chol_max_p, else CG; 3D:
+ * Jacobi-preconditioned CG), CHOL (2D only), PCG (plain CG), JACOBI (3D
+ * only: CG preconditioned by the inverse of the Gram diagonal). */
+enum { SLIM_GRAM_AUTO = 0, SLIM_GRAM_CHOL = 1, SLIM_GRAM_PCG = 2, SLIM_GRAM_JACOBI = 3 };
 
 typedef struct {
   int angles_per_block; /* g: angles in one sampled block; divides n_angles */
   int precision;        /* SLIM_PREC_FP32 or SLIM_PREC_BF16 (bf16 sinogram
                            input and bf16 image shadow read by the forward
                            projector; fp32 master image and accumulation)  */
-  int gram_mode;        /* SLIM_GRAM_AUTO / CHOL / PCG                      */
+  int gram_mode;        /* SLIM_GRAM_AUTO / CHOL / PCG / JACOBI             */
   int chol_max_p;       /* AUTO uses Cholesky while p <= chol_max_p         */
   int pcg_max_iter;     /* CG iteration cap per step                        */
   double pcg_tol;       /* CG stop: ||res|| <= pcg_tol * ||rhs||            */

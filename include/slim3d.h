@@ -13,7 +13,9 @@
  * computed here in the Gram form s = M^T z, (M M^T + lambda I) z =
  * [0; ...; 0; A_k x - b_k], the Gram system solved by conjugate gradients
  * with matrix-free projectors (a block has n_det^2 rows, so the Gram matrix
- * is never formed).
+ * is never formed), by default preconditioned by the inverse of the Gram
+ * diagonal: a ray's squared weights vary with its chord through the cube,
+ * and scaling them out cuts the iterations several-fold for one image.
  *
  * Geometry: the volume covers [-1, 1]^3 with N^3 voxels of side h = 2/N,
  * stored [k][i][j] = (z, y, x) row-major, voxel centre ((j, i, k) - (N-1)/2) h.
@@ -57,14 +59,19 @@ typedef struct slim3d_ctx slim3d_ctx;
  *  lambda    damping 1/alpha > 0, finite
  *  opts      host or NULL; used fields: angles_per_block (directions per
  *            block, g, must divide n_dirs; (r+1) g <= 256), pcg_tol,
- *            pcg_max_iter, stream.  Other fields must hold their defaults'
- *            meaning for this path: precision FP32, gram_mode AUTO or PCG
- *            (the Gram system is always solved by CG), tikhonov 0.
- * Allocates the direction table and the step workspace: three volumes of N^3
- * floats (the CG's M^T p, and copies stored with x or y slowest that the
- * forward projector reads for directions of that major axis), five float64
- * vectors of (r+1) g n_det^2 entries (right-hand side, residual, direction,
- * product, solution), the forward projector's per-segment ray sums (eight
+ *            pcg_max_iter, gram_mode, stream.  gram_mode AUTO or JACOBI:
+ *            CG preconditioned by the inverse Gram diagonal; PCG: plain CG
+ *            (the stop test is ||res|| <= pcg_tol ||rhs|| on the true
+ *            residual either way); CHOL is refused.  Other fields must hold
+ *            their defaults' meaning for this path: precision FP32,
+ *            tikhonov 0.
+ * Allocates the direction table and the step workspace: three padded
+ * volumes of N^2 (N + 11) floats at most (the volume stored with x, y or z
+ * slowest, rows on 16-byte boundaries, which the forward projector reads
+ * for directions of that major axis: copies of x and the CG's M^T p), five
+ * float64 vectors of (r+1) g n_det^2 entries (right-hand side, residual,
+ * direction, product, solution) and one more with JACOBI (the
+ * preconditioner), the forward projector's per-segment ray sums (eight
  * float64 values per ray of (r+1) g images) and small reduction buffers.
  * Errors: SLIM_EINVAL, SLIM_ENOMEM, SLIM_EDEVICE. */
 slim_status slim3d_init(slim3d_ctx** out, int N, int n_dirs, const double* dirs, int n_det, int r,

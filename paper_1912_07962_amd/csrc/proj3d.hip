@@ -433,31 +433,87 @@ __global__ __launch_bounds__(256) void back3_kernel(
 }
 
 // ---------------------------------------------------------------- CG
-enum { SC_RR = 0, SC_RR0, SC_ALPHA, SC_TOL2, SC_PQ, SC_BETA, SC_COUNT };
-
 __device__ double fixed_sum(const double* __restrict__ a, int n, double* sh) {
   double v = 0.0;
   for (int k = threadIdx.x; k < n; k += 256) v += a[k];
   return block_sum(v, sh);
 }
 
+// Jacobi preconditioner of the Gram system: minv[s][q][t] = 1 / (lam +
+// (A A^T) diagonal), the diagonal being the ray's squared weights summed
+// over the planes it crosses; per plane the four voxels' weights are the
+// products of the two axes' tents, so the squares factor into
+// ((1-fa)^2 [ia inside] + fa^2 [ia+1 inside]) times the same along b.
+__global__ __launch_bounds__(256) void diag3_kernel(const DirGeom* __restrict__ geom, DirList ids,
+                                                    int N, int n, double lam,
+                                                    double* __restrict__ minv) {
+  const int slot = blockIdx.z;
+  const DirGeom G = geom[ids.id[slot]];
+  const int t = blockIdx.x * kRT + (threadIdx.x & (kRT - 1));
+  const int q = blockIdx.y * kRT + (threadIdx.x / kRT);
+  if (t >= n || q >= n) return;
+  const double hN = 0.5 * (N - 1), hn = 0.5 * (n - 1);
+  const double fa0 = hN + (t - hn) * G.La[0] + (q - hn) * G.La[1] - hN * G.sa;
+  const double fb0 = hN + (t - hn) * G.Lb[0] + (q - hn) * G.Lb[1] - hN * G.sb;
+  double lo = 0.0, hi = N - 1.0;
+  plane_range(fa0, G.sa, N, lo, hi);
+  plane_range(fb0, G.sb, N, lo, hi);
+  const int k0 = (int)fmin((double)N, fmax(0.0, floor(lo)));
+  const int k1 = (int)fmax(-1.0, fmin(N - 1.0, ceil(hi)));
+  double sum = 0.0;
+  if (k0 <= k1) {
+    int64_t Fa = llrint((fa0 + k0 * G.sa) * kTwo32), Fb = llrint((fb0 + k0 * G.sb) * kTwo32);
+    const int64_t Sa = llrint(G.sa * kTwo32), Sb = llrint(G.sb * kTwo32);
+    const unsigned uN = (unsigned)N;
+    float acc = 0.f;
+    int cnt = 0;
+    for (int k = k0; k <= k1; ++k) {
+      const int ia = (int)(Fa >> 32), ib = (int)(Fb >> 32);
+      const float fa = (float)(uint32_t)Fa * kInv32, fb = (float)(uint32_t)Fb * kInv32;
+      const float ga = ((unsigned)ia < uN ? (1.f - fa) * (1.f - fa) : 0.f) +
+                       ((unsigned)(ia + 1) < uN ? fa * fa : 0.f);
+      const float gb = ((unsigned)ib < uN ? (1.f - fb) * (1.f - fb) : 0.f) +
+                       ((unsigned)(ib + 1) < uN ? fb * fb : 0.f);
+      acc = fmaf(ga, gb, acc);
+      Fa += Sa;
+      Fb += Sb;
+      if (++cnt == kFlush) {
+        sum += (double)acc;
+        acc = 0.f;
+        cnt = 0;
+      }
+    }
+    sum += (double)acc;
+  }
+  minv[((size_t)slot * n + q) * n + t] = 1.0 / fma(G.scale * G.scale, sum, lam);
+}
+
+// CG init: r = e, pd = y = minv r (y = r without minv), z = 0; per-workgroup
+// partial sums of r.r into parts and of r.y into parts + np.
 __global__ __launch_bounds__(256) void cg3_init_kernel(const double* __restrict__ e,
+                                                       const double* __restrict__ minv,
                                                        double* __restrict__ r,
                                                        double* __restrict__ pd,
                                                        double* __restrict__ z, int p,
                                                        double* __restrict__ parts) {
   __shared__ double sh[4];
   const int o = blockIdx.x * 256 + threadIdx.x;
-  double d = 0.0;
+  double d = 0.0, dy = 0.0;
   if (o < p) {
     const double v = e[o];
+    const double y = minv ? minv[o] * v : v;
     r[o] = v;
-    pd[o] = v;
+    pd[o] = y;
     z[o] = 0.0;
     d = v * v;
+    dy = v * y;
   }
   d = block_sum(d, sh);
-  if (threadIdx.x == 0) parts[blockIdx.x] = d;
+  dy = block_sum(dy, sh);
+  if (threadIdx.x == 0) {
+    parts[blockIdx.x] = d;
+    parts[gridDim.x + blockIdx.x] = dy;
+  }
 }
 
 __global__ __launch_bounds__(256) void cg3_start_kernel(const double* __restrict__ parts, int np,
@@ -465,13 +521,15 @@ __global__ __launch_bounds__(256) void cg3_start_kernel(const double* __restrict
                                                         int* __restrict__ ctl, double tol2) {
   __shared__ double sh[4];
   const double rr = fixed_sum(parts, np, sh);
+  const double ry = fixed_sum(parts + np, np, sh);
   if (threadIdx.x == 0) {
-    sc[SC_RR] = rr;
-    sc[SC_RR0] = rr;
-    sc[SC_TOL2] = tol2;
+    sc[SC3_RR] = rr;
+    sc[SC3_RR0] = rr;
+    sc[SC3_RY] = ry;
+    sc[SC3_TOL2] = tol2;
     ctl[kCtlDone] = rr > 0.0 ? 0 : 1;
     ctl[kCtlIters] = 0;
-    ctl[2] = isfinite(rr) ? 0 : 1;   // non-finite data or iterate
+    ctl[2] = isfinite(rr) && isfinite(ry) ? 0 : 1;   // non-finite data or iterate
   }
 }
 
@@ -482,9 +540,9 @@ __global__ __launch_bounds__(256) void cg3_alpha_kernel(const double* __restrict
   __shared__ double sh[4];
   const double pq = fixed_sum(dots, nd, sh);
   if (threadIdx.x == 0) {
-    sc[SC_PQ] = pq;
+    sc[SC3_PQ] = pq;
     if (pq > 0.0 && isfinite(pq)) {
-      sc[SC_ALPHA] = sc[SC_RR] / pq;
+      sc[SC3_ALPHA] = sc[SC3_RY] / pq;
     } else {  // breakdown: stop with the current z
       ctl[kCtlDone] = 1;
       ctl[2] = 1;
@@ -492,54 +550,66 @@ __global__ __launch_bounds__(256) void cg3_alpha_kernel(const double* __restrict
   }
 }
 
+// z += alpha pd, r -= alpha q; partial sums of r.r and r.(minv r).
 __global__ __launch_bounds__(256) void cg3_update_kernel(double* __restrict__ z,
                                                          double* __restrict__ r,
                                                          const double* __restrict__ pd,
-                                                         const double* __restrict__ q, int p,
+                                                         const double* __restrict__ q,
+                                                         const double* __restrict__ minv, int p,
                                                          double* __restrict__ parts,
                                                          const double* __restrict__ sc,
                                                          const int* __restrict__ ctl) {
   if (ctl[kCtlDone]) return;
   __shared__ double sh[4];
-  const double alpha = sc[SC_ALPHA];
+  const double alpha = sc[SC3_ALPHA];
   const int o = blockIdx.x * 256 + threadIdx.x;
-  double d = 0.0;
+  double d = 0.0, dy = 0.0;
   if (o < p) {
     z[o] = fma(alpha, pd[o], z[o]);
     const double rn = fma(-alpha, q[o], r[o]);
     r[o] = rn;
     d = rn * rn;
+    dy = minv ? rn * (minv[o] * rn) : d;
   }
   d = block_sum(d, sh);
-  if (threadIdx.x == 0) parts[blockIdx.x] = d;
+  dy = block_sum(dy, sh);
+  if (threadIdx.x == 0) {
+    parts[blockIdx.x] = d;
+    parts[gridDim.x + blockIdx.x] = dy;
+  }
 }
 
+// Stop once r.r <= tol^2 e.e (the true residual, preconditioned or not);
+// else beta = r.y / (r.y)_old.
 __global__ __launch_bounds__(256) void cg3_rr_kernel(const double* __restrict__ parts, int np,
                                                      double* __restrict__ sc,
                                                      int* __restrict__ ctl) {
   if (ctl[kCtlDone]) return;
   __shared__ double sh[4];
   const double rr = fixed_sum(parts, np, sh);
+  const double ry = fixed_sum(parts + np, np, sh);
   if (threadIdx.x == 0) {
     ctl[kCtlIters] += 1;
-    if (rr <= sc[SC_TOL2] * sc[SC_RR0] || !isfinite(rr)) {
+    if (rr <= sc[SC3_TOL2] * sc[SC3_RR0] || !isfinite(rr) || !isfinite(ry)) {
       ctl[kCtlDone] = 1;
-      if (!isfinite(rr)) ctl[2] = 1;
+      if (!isfinite(rr) || !isfinite(ry)) ctl[2] = 1;
     } else {
-      sc[SC_BETA] = rr / sc[SC_RR];
+      sc[SC3_BETA] = ry / sc[SC3_RY];
     }
-    sc[SC_RR] = rr;
+    sc[SC3_RR] = rr;
+    sc[SC3_RY] = ry;
   }
 }
 
 __global__ __launch_bounds__(256) void cg3_pd_kernel(const double* __restrict__ r,
+                                                     const double* __restrict__ minv,
                                                      double* __restrict__ pd, int p,
                                                      const double* __restrict__ sc,
                                                      const int* __restrict__ ctl) {
   if (ctl[kCtlDone]) return;
-  const double beta = sc[SC_BETA];
+  const double beta = sc[SC3_BETA];
   const int o = blockIdx.x * 256 + threadIdx.x;
-  if (o < p) pd[o] = fma(beta, pd[o], r[o]);
+  if (o < p) pd[o] = fma(beta, pd[o], minv ? minv[o] * r[o] : r[o]);
 }
 
 }  // namespace
@@ -593,11 +663,20 @@ hipError_t launch_back3(const Back3Args& a, hipStream_t st) {
 
 int cg3_num_parts(int p) { return (p + 255) / 256; }
 
-hipError_t launch_cg3_init(const double* e, double* r, double* pd, double* z, int p, double* parts,
-                           int nparts_cap, double* sc, int* ctl, double tol2, hipStream_t st) {
+hipError_t launch_diag3(const DirGeom* geom, const DirList& ids, int N, int n, double lam,
+                        double* minv, hipStream_t st) {
+  if (ids.n <= 0) return hipSuccess;
+  const int g = (n + kRT - 1) / kRT;
+  hipLaunchKernelGGL(diag3_kernel, dim3(g, g, ids.n), dim3(256), 0, st, geom, ids, N, n, lam, minv);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg3_init(const double* e, const double* minv, double* r, double* pd, double* z,
+                           int p, double* parts, int nparts_cap, double* sc, int* ctl, double tol2,
+                           hipStream_t st) {
   const int np = cg3_num_parts(p);
-  if (np > nparts_cap) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(cg3_init_kernel, dim3(np), dim3(256), 0, st, e, r, pd, z, p, parts);
+  if (2 * np > nparts_cap) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(cg3_init_kernel, dim3(np), dim3(256), 0, st, e, minv, r, pd, z, p, parts);
   hipLaunchKernelGGL(cg3_start_kernel, dim3(1), dim3(256), 0, st, parts, np, sc, ctl, tol2);
   return hipGetLastError();
 }
@@ -607,17 +686,19 @@ hipError_t launch_cg3_alpha(const double* dots, int nd, double* sc, int* ctl, hi
   return hipGetLastError();
 }
 
-hipError_t launch_cg3_update(double* z, double* r, const double* pd, const double* q, int p,
-                             double* parts, double* sc, int* ctl, hipStream_t st) {
-  hipLaunchKernelGGL(cg3_update_kernel, dim3(cg3_num_parts(p)), dim3(256), 0, st, z, r, pd, q, p,
-                     parts, sc, ctl);
+hipError_t launch_cg3_update(double* z, double* r, const double* pd, const double* q,
+                             const double* minv, int p, double* parts, double* sc, int* ctl,
+                             hipStream_t st) {
+  hipLaunchKernelGGL(cg3_update_kernel, dim3(cg3_num_parts(p)), dim3(256), 0, st, z, r, pd, q, minv,
+                     p, parts, sc, ctl);
   return hipGetLastError();
 }
 
-hipError_t launch_cg3_beta(double* r, double* pd, int p, const double* parts, double* sc, int* ctl,
-                           hipStream_t st) {
+hipError_t launch_cg3_beta(double* r, const double* minv, double* pd, int p, const double* parts,
+                           double* sc, int* ctl, hipStream_t st) {
   hipLaunchKernelGGL(cg3_rr_kernel, dim3(1), dim3(256), 0, st, parts, cg3_num_parts(p), sc, ctl);
-  hipLaunchKernelGGL(cg3_pd_kernel, dim3(cg3_num_parts(p)), dim3(256), 0, st, r, pd, p, sc, ctl);
+  hipLaunchKernelGGL(cg3_pd_kernel, dim3(cg3_num_parts(p)), dim3(256), 0, st, r, minv, pd, p, sc,
+                     ctl);
   return hipGetLastError();
 }
 

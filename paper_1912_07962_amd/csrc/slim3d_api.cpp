@@ -12,8 +12,6 @@ using namespace slim;
 
 namespace {
 
-// float64 scalars of the CG (their order is fixed by the kernels)
-enum { SC_RR = 0, SC_RR0 = 1, SC_COUNT = 6 };
 constexpr int kCtlWords = 4;     // done, iterations, breakdown, pad
 constexpr int kNormGroup = 512;  // back-projector norm partials summed per group
 constexpr int kChunk = 4;        // CG iterations enqueued between reads of the stop flag
@@ -66,8 +64,10 @@ struct slim3d_ctx {
   double* d_dots = nullptr;   // forward partial dots
   double* d_part = nullptr;   // forward per-segment ray sums, for up to wmax directions
   int wmax = 0;               // directions of the largest window, (r+1) g
-  double* d_parts = nullptr;  // vector-kernel partial sums
+  double* d_parts = nullptr;  // vector-kernel partial sums (two sets)
   int nparts = 0;
+  bool jacobi = true;         // CG preconditioned by the Gram diagonal's inverse
+  double* d_minv = nullptr;   // that inverse for the window's rays [pmax]
   double* d_sc = nullptr;     // CG scalars
   int* d_ctl = nullptr;       // CG stop flag, iterations, breakdown
   double* d_bparts = nullptr; // back-projector norm partials, padded to groups of 512
@@ -89,6 +89,7 @@ struct slim3d_ctx {
     (void)hipFree(d_dots);
     (void)hipFree(d_part);
     (void)hipFree(d_parts);
+    (void)hipFree(d_minv);
     (void)hipFree(d_sc);
     (void)hipFree(d_ctl);
     (void)hipFree(d_bparts);
@@ -222,7 +223,9 @@ slim_status do_step3(slim3d_ctx* c, const int32_t* ids, slim_step_info* info) {
   // 2. CG on (M M^T + lam I) z = e
   const double tol = c->o.pcg_tol;
   if (c->prof.on) HIP3_TRY(c->prof.begin(K_VEC, c->st));
-  HIP3_TRY(launch_cg3_init(c->d_e, c->d_r, c->d_pd, c->d_z, (int)p, c->d_parts, c->nparts,
+  if (c->jacobi) HIP3_TRY(launch_diag3(c->d_geom, wl, c->N, c->n, c->lam, c->d_minv, c->st));
+  const double* minv = c->jacobi ? c->d_minv : nullptr;
+  HIP3_TRY(launch_cg3_init(c->d_e, minv, c->d_r, c->d_pd, c->d_z, (int)p, c->d_parts, c->nparts,
                            c->d_sc, c->d_ctl, tol * tol, c->st));
   if (c->prof.on) HIP3_TRY(c->prof.end(c->st));
   Back3Args bu;
@@ -263,9 +266,10 @@ slim_status do_step3(slim3d_ctx* c, const int32_t* ids, slim_step_info* info) {
       if (c->prof.on) HIP3_TRY(c->prof.end(c->st));
       if (c->prof.on) HIP3_TRY(c->prof.begin(K_VEC, c->st));
       HIP3_TRY(launch_cg3_alpha(c->d_dots, nd, c->d_sc, c->d_ctl, c->st));
-      HIP3_TRY(launch_cg3_update(c->d_z, c->d_r, c->d_pd, c->d_q, (int)p, c->d_parts, c->d_sc,
-                                 c->d_ctl, c->st));
-      HIP3_TRY(launch_cg3_beta(c->d_r, c->d_pd, (int)p, c->d_parts, c->d_sc, c->d_ctl, c->st));
+      HIP3_TRY(launch_cg3_update(c->d_z, c->d_r, c->d_pd, c->d_q, minv, (int)p, c->d_parts,
+                                 c->d_sc, c->d_ctl, c->st));
+      HIP3_TRY(launch_cg3_beta(c->d_r, minv, c->d_pd, (int)p, c->d_parts, c->d_sc, c->d_ctl,
+                               c->st));
       if (c->prof.on) HIP3_TRY(c->prof.end(c->st));
     }
     enq += chunk;
@@ -303,7 +307,7 @@ slim_status do_step3(slim3d_ctx* c, const int32_t* ids, slim_step_info* info) {
   HIP3_TRY(hipStreamSynchronize(c->st));
   if (c->prof.on) HIP3_TRY(c->prof.harvest());
   const int iters = c->h_ctl[kCtlIters];
-  const double rr = c->h_out[3 + SC_RR], rr0 = c->h_out[3 + SC_RR0];
+  const double rr = c->h_out[3 + SC3_RR], rr0 = c->h_out[3 + SC3_RR0];
   const double relres = rr0 > 0.0 ? std::sqrt(rr / rr0) : 0.0;
   if (info) {
     info->step_norm = std::sqrt(c->h_out[0]);
@@ -346,7 +350,7 @@ slim_status slim3d_init(slim3d_ctx** out, int N, int n_dirs, const double* dirs,
   if (o.precision != SLIM_PREC_FP32) return set_error(SLIM_EINVAL, "3D path needs FP32 precision");
   if (o.gram_mode == SLIM_GRAM_CHOL)
     return set_error(SLIM_EINVAL, "3D path solves the Gram system by CG only");
-  if (o.gram_mode < SLIM_GRAM_AUTO || o.gram_mode > SLIM_GRAM_PCG)
+  if (o.gram_mode < SLIM_GRAM_AUTO || o.gram_mode > SLIM_GRAM_JACOBI)
     return set_error(SLIM_EINVAL, "unknown gram_mode");
   if (o.tikhonov != 0.0) return set_error(SLIM_EINVAL, "3D path has no Tikhonov term");
   if (o.pcg_max_iter < 1 || !(o.pcg_tol > 0.0)) return set_error(SLIM_EINVAL, "bad CG settings");
@@ -384,7 +388,8 @@ slim_status slim3d_init(slim3d_ctx** out, int N, int n_dirs, const double* dirs,
     return set_error(SLIM_EDEVICE, std::string("allocation: ") + hipGetErrorString(e));
   };
   hipError_t e;
-  c->nparts = cg3_num_parts((int)pmax);
+  c->nparts = 2 * cg3_num_parts((int)pmax);
+  c->jacobi = o.gram_mode != SLIM_GRAM_PCG;
   const int64_t nbw = back3_num_workgroups(N);
   c->nbgroups = (nbw + kNormGroup - 1) / kNormGroup;
   if ((e = dalloc(&c->d_geom, n_dirs)) != hipSuccess) return oom(e);
@@ -399,7 +404,8 @@ slim_status slim3d_init(slim3d_ctx** out, int N, int n_dirs, const double* dirs,
   if ((e = dalloc(&c->d_dots, (size_t)fwd3_num_workgroups(n_det, c->wmax))) != hipSuccess) return oom(e);
   if ((e = dalloc(&c->d_part, fwd3_part_doubles(n_det, c->wmax))) != hipSuccess) return oom(e);
   if ((e = dalloc(&c->d_parts, (size_t)c->nparts)) != hipSuccess) return oom(e);
-  if ((e = dalloc(&c->d_sc, SC_COUNT)) != hipSuccess) return oom(e);
+  if (c->jacobi && (e = dalloc(&c->d_minv, pmax)) != hipSuccess) return oom(e);
+  if ((e = dalloc(&c->d_sc, SC3_COUNT)) != hipSuccess) return oom(e);
   if ((e = dalloc(&c->d_ctl, kCtlWords)) != hipSuccess) return oom(e);
   if ((e = dalloc(&c->d_bparts, (size_t)c->nbgroups * kNormGroup * 3)) != hipSuccess) return oom(e);
   if ((e = dalloc(&c->d_btmp, (size_t)c->nbgroups * 3)) != hipSuccess) return oom(e);

@@ -99,20 +99,31 @@ hipError_t launch_back3(const Back3Args& a, hipStream_t st);
 hipError_t launch_relayout3(const float* src, float* dst, int N, int m, hipStream_t st);
 int64_t back3_num_workgroups(int N);
 
-// CG on (lam I + M M^T) z = e in float64 (e: p entries), matrix-free:
-//   init:  r = e, pd = e, z = 0, rr = rr0 = e.e (ctl done if e = 0)
+// float64 scalars of the CG, in its device buffer sc.
+enum { SC3_RR = 0, SC3_RR0, SC3_ALPHA, SC3_TOL2, SC3_PQ, SC3_BETA, SC3_RY, SC3_COUNT };
+
+// CG on (lam I + M M^T) z = e in float64 (e: p entries), matrix-free,
+// preconditioned by minv (the inverse of the Gram diagonal, diag3) when minv
+// is non-NULL, plain otherwise (y = r below):
+//   init:  r = e, y = minv r, pd = y, z = 0, rr = rr0 = e.e, ry = r.y
+//          (ctl done if e = 0)
 //   iteration: u = M^T pd (back), q = M u + lam pd with partial dots
-//   (forward tail), alpha = rr / pd.q, z += alpha pd, r -= alpha q,
-//   rr' = r.r, stop when rr' <= tol^2 rr0, else pd = r + (rr'/rr) pd.
-// sc holds the scalars [rr, rr0, alpha, tol^2, pq]; ctl [done, iterations].
-hipError_t launch_cg3_init(const double* e, double* r, double* pd, double* z, int p,
-                           double* parts, int nparts_cap, double* sc, int* ctl, double tol2,
+//   (forward tail), alpha = ry / pd.q, z += alpha pd, r -= alpha q,
+//   rr' = r.r, ry' = r.(minv r), stop when rr' <= tol^2 rr0, else
+//   pd = minv r + (ry'/ry) pd.
+// sc holds the scalars; ctl [done, iterations, non-finite].  parts holds
+// 2 cg3_num_parts(p) doubles.
+hipError_t launch_diag3(const DirGeom* geom, const DirList& ids, int N, int n, double lam,
+                        double* minv, hipStream_t st);
+hipError_t launch_cg3_init(const double* e, const double* minv, double* r, double* pd, double* z,
+                           int p, double* parts, int nparts_cap, double* sc, int* ctl, double tol2,
                            hipStream_t st);
 hipError_t launch_cg3_alpha(const double* dots, int nd, double* sc, int* ctl, hipStream_t st);
-hipError_t launch_cg3_update(double* z, double* r, const double* pd, const double* q, int p,
-                             double* parts, double* sc, int* ctl, hipStream_t st);
-hipError_t launch_cg3_beta(double* r, double* pd, int p, const double* parts, double* sc,
-                           int* ctl, hipStream_t st);
+hipError_t launch_cg3_update(double* z, double* r, const double* pd, const double* q,
+                             const double* minv, int p, double* parts, double* sc, int* ctl,
+                             hipStream_t st);
+hipError_t launch_cg3_beta(double* r, const double* minv, double* pd, int p, const double* parts,
+                           double* sc, int* ctl, hipStream_t st);
 int cg3_num_parts(int p);
 
 }  // namespace slim

@@ -566,6 +566,7 @@ slim_status slim_init(slim_ctx** out, const slim_grid* grid, int n_angles, const
   if ((int64_t)(r + 1) * g > kMaxList) return fail(SLIM_EINVAL, "(r+1)*angles_per_block exceeds 256");
   if (o.precision != SLIM_PREC_FP32 && o.precision != SLIM_PREC_BF16)
     return fail(SLIM_EINVAL, "unknown precision");
+  if (o.gram_mode == SLIM_GRAM_JACOBI) return fail(SLIM_EINVAL, "Jacobi preconditioning is a 3D option");
   if (o.gram_mode < SLIM_GRAM_AUTO || o.gram_mode > SLIM_GRAM_PCG) return fail(SLIM_EINVAL, "unknown gram_mode");
   if (o.check_every < 1) return fail(SLIM_EINVAL, "check_every must be >= 1");
   if (o.damping_ramp != 0 && o.damping_ramp != 1) return fail(SLIM_EINVAL, "damping_ramp must be 0 or 1");

@@ -22,7 +22,7 @@ HEADERS = [HEADER, os.path.join(os.path.dirname(_HERE), "include", "slim_cnn.h")
 
 SLIM_OK, SLIM_EINVAL, SLIM_ENOMEM, SLIM_EDEVICE, SLIM_ENUMERIC, SLIM_ENOTCONV, SLIM_ESTATE = range(7)
 PREC = {"fp32": 0, "bf16": 1}
-GRAM = {"auto": 0, "chol": 1, "pcg": 2}
+GRAM = {"auto": 0, "chol": 1, "pcg": 2, "jacobi": 3}
 
 
 class SlimError(RuntimeError):
@@ -432,7 +432,9 @@ class Slim3D:
 
     def __init__(self, N: int, dirs, n_det: int | None = None, r: int = 0, lam: float = 1e-2,
                  dirs_per_block: int = 1, pcg_max_iter: int = 1000, pcg_tol: float = 1e-6,
-                 stream=None):
+                 stream=None, gram_mode: str = "auto"):
+        """gram_mode "auto" / "jacobi": CG preconditioned by the inverse Gram
+        diagonal; "pcg": plain CG."""
         lib = load()
         self._dirs = np.ascontiguousarray(np.asarray(dirs, dtype=np.float64).reshape(-1, 3))
         self.N, self.n_dirs = int(N), int(self._dirs.shape[0])
@@ -443,6 +445,7 @@ class Slim3D:
         o.angles_per_block = self.g
         o.pcg_max_iter = int(pcg_max_iter)
         o.pcg_tol = float(pcg_tol)
+        o.gram_mode = GRAM[gram_mode]
         if stream is None and torch.cuda.is_available():
             stream = torch.cuda.current_stream()
         o.stream = ctypes.c_void_p(stream.cuda_stream if stream is not None else 0)

@@ -34,7 +34,7 @@ def test_strerror_and_default_opts():
     dict(angles_per_block=7), dict(angles_per_block=0), dict(precision=5), dict(gram_mode=9),
     dict(check_every=0), dict(r=200, angles_per_block=2), dict(damping_ramp=2),
     dict(damping_ramp=-1), dict(tikhonov=-1.0), dict(tikhonov=float("nan")),
-    dict(tikhonov=float("inf")), dict(tikhonov=0.5, precision=1),
+    dict(tikhonov=float("inf")), dict(tikhonov=0.5, precision=1), dict(gram_mode=3),
     dict(N=512, n_rays=725, n_angles=360, angles_per_block=4, r=8, gram_mode=1),  # p > 8192
 ])
 def test_init_rejects_bad_arguments(kw):
@@ -122,7 +122,8 @@ def _init3d(N=16, n_dirs=4, dirs="unit", n_det=16, r=0, lam=1e-2, **opt):
 @pytest.mark.parametrize("kw", [
     dict(N=1), dict(N=2000), dict(n_dirs=0), dict(dirs=None), dict(dirs="long"), dict(dirs="nan"),
     dict(n_det=0), dict(n_det=5000), dict(r=-1), dict(lam=0.0), dict(lam=float("inf")),
-    dict(angles_per_block=3), dict(precision=1), dict(gram_mode=1), dict(tikhonov=0.1),
+    dict(angles_per_block=3), dict(precision=1), dict(gram_mode=1), dict(gram_mode=4),
+    dict(gram_mode=-1), dict(tikhonov=0.1),
     dict(pcg_max_iter=0), dict(r=300),
 ])
 def test_init3d_rejects_bad_arguments(kw):
