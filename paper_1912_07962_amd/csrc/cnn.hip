@@ -8,6 +8,9 @@
 // A holds row r, k = 8q..8q+7; B holds column r, k = 8q..8q+7; accumulator
 // e of lane l is D[4q + e][r].
 //
+// On grids of at least 32 x 32 the operands are staged in LDS instead
+// (conv3x3_lds_kernel below).
+//
 // Weight gradients contract over pixels, the strided dimension of NHWC, so
 // their workgroups stage 64-pixel chunks of dz and of the shifted input
 // through LDS transposed (pixel-contiguous rows) and write split-K partials
@@ -122,6 +125,106 @@ __global__ __launch_bounds__(64 * kCW) void conv3x3_kernel(ConvArgs a, int64_t n
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int64_t P = pt * 64 + 16 * i + 4 * q + e;
+        float v = acc[i][j][e] + bias;
+        if (a.relu) v = fmaxf(v, 0.f);
+        if (a.mask.p && !(bf2f(a.mask.p[P * a.mask.cs + a.mask.co + co]) > 0.f)) v = 0.f;
+        a.out.p[P * a.out.cs + a.out.co + co] = f2bf(v);
+      }
+    }
+  }
+}
+
+// LDS-tiled variant for grids of at least 32 x 32: a workgroup owns an
+// output tile of TR rows x 32 columns x CO channels (TR = 2 NPT, CO = 16 NCT)
+// and walks the input channels in chunks of 32.  Per chunk it stages the
+// (TR + 2) x 34 input patch (all nine taps' pixels, zeros outside the grid,
+// the nearest-neighbour upsampling applied on the way in) and the CO x 9 x 32
+// weights in LDS with 16-byte loads; each wavefront then takes NPT/2 rows of
+// the tile (NPT MFMA tiles of 16 pixels) x CO channels, reading its A and B
+// operands from LDS: 16 consecutive pixels' 32 channels are one contiguous
+// kilobyte (conflict-free), and the weight rows are padded so that 16 output
+// channels' reads fall into distinct banks.
+constexpr int kWS = 9 * 32 + 8;   // LDS row stride (bf16) of one output channel's weights
+
+__device__ __forceinline__ bf16x8 lds8(const uint16_t* p) {
+  return __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(p));
+}
+
+template <int NPT, int NCT>
+__global__ __launch_bounds__(256, 2) void conv3x3_lds_kernel(ConvArgs a, int n_blocks) {
+  constexpr int TR = 2 * NPT, TC = 32, CO = 16 * NCT;
+  constexpr int PR = TR + 2, PC = TC + 2;
+  __shared__ __align__(16) uint16_t patch[PR * PC * 32];
+  __shared__ __align__(16) uint16_t wts[CO * kWS];
+  const int64_t blk = xcd_block();
+  if (blk >= n_blocks) return;
+  const int H = a.H, Hin = a.up ? (H >> 1) : H;
+  const int nco = a.Cout / CO, ntx = H / TC, nty = H / TR;
+  // output-channel tiles fastest: consecutive blocks share the input patch
+  const int cot = (int)(blk % nco);
+  int64_t t = blk / nco;
+  const int tx = (int)(t % ntx);
+  t /= ntx;
+  const int ty = (int)(t % nty);
+  const int64_t n = t / nty;
+  const int y0 = ty * TR, x0 = tx * TC;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int r = lane & 15, q = lane >> 4;
+  const int64_t img = n * Hin * Hin;
+
+  f32x4 acc[NPT][NCT];
+#pragma unroll
+  for (int i = 0; i < NPT; ++i)
+#pragma unroll
+    for (int j = 0; j < NCT; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  for (int c0 = 0; c0 < a.Cin; c0 += 32) {
+    __syncthreads();  // the previous chunk's reads are done
+    for (int e = tid; e < PR * PC * 4; e += 256) {
+      const int pix = e >> 2, g = e & 3;
+      const int py = pix / PC, px = pix - py * PC;
+      const int yy = y0 - 1 + py, xx = x0 - 1 + px;
+      bf16x8 v = zero8();
+      if ((unsigned)yy < (unsigned)H && (unsigned)xx < (unsigned)H) {
+        const int ys = a.up ? yy >> 1 : yy, xs = a.up ? xx >> 1 : xx;
+        v = ld8(a.in.p + ((img + (int64_t)ys * Hin + xs) * a.in.cs + a.in.co + c0 + 8 * g));
+      }
+      *reinterpret_cast<bf16x8*>(patch + pix * 32 + 8 * g) = v;
+    }
+    for (int e = tid; e < CO * 36; e += 256) {
+      const int co = e / 36, rem = e - co * 36, tap = rem >> 2, g = rem & 3;
+      *reinterpret_cast<bf16x8*>(wts + co * kWS + tap * 32 + 8 * g) =
+          ld8(a.w + ((size_t)(cot * CO + co) * 9 + tap) * a.Cin + c0 + 8 * g);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap) {
+      const int dy = tap / 3, dx = tap % 3;   // patch offsets (the tap's -1 .. 1 plus the halo)
+      bf16x8 Bv[NCT];
+#pragma unroll
+      for (int j = 0; j < NCT; ++j) Bv[j] = lds8(wts + (16 * j + r) * kWS + tap * 32 + 8 * q);
+#pragma unroll
+      for (int i = 0; i < NPT; ++i) {
+        const int prow = wave * (NPT / 2) + (i >> 1) + dy, pcol = 16 * (i & 1) + r + dx;
+        const bf16x8 A = lds8(patch + (prow * PC + pcol) * 32 + 8 * q);
+#pragma unroll
+        for (int j = 0; j < NCT; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, Bv[j], acc[i][j], 0, 0, 0);
+      }
+    }
+  }
+
+#pragma unroll
+  for (int j = 0; j < NCT; ++j) {
+    const int co = cot * CO + 16 * j + r;
+    const float bias = a.bias ? a.bias[co] : 0.f;
+#pragma unroll
+    for (int i = 0; i < NPT; ++i) {
+      const int y = y0 + wave * (NPT / 2) + (i >> 1);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int x = x0 + 16 * (i & 1) + 4 * q + e;
+        const int64_t P = (n * H + y) * H + x;
         float v = acc[i][j][e] + bias;
         if (a.relu) v = fmaxf(v, 0.f);
         if (a.mask.p && !(bf2f(a.mask.p[P * a.mask.cs + a.mask.co + co]) > 0.f)) v = 0.f;
@@ -489,6 +592,20 @@ unsigned blocks256(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 // ----------------------------------------------------------------- launchers
 hipError_t launch_conv3x3(const ConvArgs& a, hipStream_t st) {
+  if (a.H >= 32 && a.H % 32 == 0 && a.Cin % 32 == 0) {
+    if (a.Cout == 32) {   // 16 x 32 pixels x 32 channels per workgroup
+      const int64_t blocks = (int64_t)a.B * (a.H / 16) * (a.H / 32);
+      hipLaunchKernelGGL((conv3x3_lds_kernel<8, 2>), dim3(grid8(blocks)), dim3(256), 0, st, a,
+                         (int)blocks);
+      return hipGetLastError();
+    }
+    if (a.Cout % 64 == 0) {   // 8 x 32 pixels x 64 channels per workgroup
+      const int64_t blocks = (int64_t)a.B * (a.H / 8) * (a.H / 32) * (a.Cout / 64);
+      hipLaunchKernelGGL((conv3x3_lds_kernel<4, 4>), dim3(grid8(blocks)), dim3(256), 0, st, a,
+                         (int)blocks);
+      return hipGetLastError();
+    }
+  }
   const int64_t npx = (int64_t)a.B * a.H * a.H;
   const int64_t tiles = (npx / 64) * (a.Cout / 32);
   const int64_t blocks = (tiles + kCW - 1) / kCW;
