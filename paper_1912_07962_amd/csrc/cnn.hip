@@ -358,25 +358,48 @@ WgradPlan wgrad_plan(int Cout, int Cin, int B, int H) {
 }
 
 // ------------------------------------------------------------ first layer
-__global__ void conv_in_kernel(const float* u, float in_scale, const uint16_t* w,
-                               const float* bias, Tensor out, int Cout, int B, int H) {
-  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const int64_t total = (int64_t)B * H * H * Cout;
-  if (idx >= total) return;
-  const int co = (int)(idx % Cout);
-  const int64_t P = idx / Cout;
+// First layer (one input channel): a lane per pixel computes all Cout
+// channels (weights and biases in LDS as float) and stores them eight at a
+// time (16 bytes); each channel's sum runs over the taps in order, as the
+// definition writes it (taps outside the grid add zero).
+__global__ __launch_bounds__(256) void conv_in_kernel(const float* u, float in_scale,
+                                                      const uint16_t* w, const float* bias,
+                                                      Tensor out, int Cout, int B, int H) {
+  extern __shared__ float wsh[];   // [Cout][9] weights, then [Cout] biases
+  for (int e = threadIdx.x; e < Cout * 10; e += 256)
+    wsh[e] = e < Cout * 9 ? bf2f(w[e]) : bias[e - Cout * 9];
+  __syncthreads();
+  const int64_t P = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (P >= (int64_t)B * H * H) return;
   const int64_t n = P / (H * H);
   const int rem = (int)(P - n * H * H);
-  const int y = rem / H, x = rem % H;
+  const int y = rem / H, x = rem - (rem / H) * H;
   const float* un = u + n * H * H;
-  float z = 0.f;
+  float uv[9];
+#pragma unroll
   for (int tap = 0; tap < 9; ++tap) {
     const int yy = y + tap / 3 - 1, xx = x + tap % 3 - 1;
-    if ((unsigned)yy < (unsigned)H && (unsigned)xx < (unsigned)H)
-      z += bf2f(w[co * 9 + tap]) * (in_scale * un[yy * H + xx]);
+    uv[tap] = ((unsigned)yy < (unsigned)H && (unsigned)xx < (unsigned)H)
+                  ? in_scale * un[yy * H + xx] : 0.f;
   }
-  z = fmaxf(z + bias[co], 0.f);
-  out.p[P * out.cs + out.co + co] = f2bf(z);
+  uint16_t* dst = out.p + P * out.cs + out.co;
+  for (int c0 = 0; c0 < Cout; c0 += 8) {
+    u32x4 pk;
+#pragma unroll
+    for (int k = 0; k < 8; k += 2) {
+      float z[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const float* wc = wsh + (c0 + k + h) * 9;
+        float acc = 0.f;
+#pragma unroll
+        for (int tap = 0; tap < 9; ++tap) acc += wc[tap] * uv[tap];
+        z[h] = fmaxf(acc + wsh[Cout * 9 + c0 + k + h], 0.f);
+      }
+      pk[k >> 1] = (uint32_t)f2bf(z[0]) | ((uint32_t)f2bf(z[1]) << 16);
+    }
+    *reinterpret_cast<u32x4*>(dst + c0) = pk;
+  }
 }
 
 // entry t = k * Cout + co: tap k < 9 (weight) or k = 9 (bias) of channel co,
@@ -430,51 +453,89 @@ __global__ void wgrad_in_reduce_kernel(const float* part, int nsplit, int Cout, 
 }
 
 // ------------------------------------------------------- pool / up / head
+// The pooling and upsampling kernels take a lane per (pixel, group of 8
+// channels): 16-byte loads and stores of NHWC rows (C a multiple of 8).
+__device__ __forceinline__ float lane8(const u32x4& v, int k) {
+  return bf2f((uint16_t)(v[k >> 1] >> (16 * (k & 1))));
+}
+__device__ __forceinline__ u32x4 ld16(const uint16_t* p) { return *reinterpret_cast<const u32x4*>(p); }
+
 __global__ void pool_kernel(Tensor in, Tensor out, int C, int B, int H) {
-  const int Ho = H >> 1;
+  const int Ho = H >> 1, G = C >> 3;
   const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (idx >= (int64_t)B * Ho * Ho * C) return;
-  const int c = (int)(idx % C);
-  const int64_t Q = idx / C;
+  if (idx >= (int64_t)B * Ho * Ho * G) return;
+  const int64_t Q = idx / G;
+  const int c = 8 * (int)(idx - Q * G);
   const int64_t n = Q / (Ho * Ho);
   const int rem = (int)(Q - n * Ho * Ho);
   const int y = 2 * (rem / Ho), x = 2 * (rem % Ho);
   const int64_t P = (n * H + y) * H + x;
   const uint16_t* s = in.p + in.co + c;
-  const float v = bf2f(s[P * in.cs]) + bf2f(s[(P + 1) * in.cs]) + bf2f(s[(P + H) * in.cs]) +
-                  bf2f(s[(P + H + 1) * in.cs]);
-  out.p[Q * out.cs + out.co + c] = f2bf(0.25f * v);
+  const u32x4 a = ld16(s + P * in.cs), b = ld16(s + (P + 1) * in.cs);
+  const u32x4 d = ld16(s + (P + H) * in.cs), e = ld16(s + (P + H + 1) * in.cs);
+  u32x4 o;
+#pragma unroll
+  for (int k = 0; k < 8; k += 2) {
+    const float v0 = lane8(a, k) + lane8(b, k) + lane8(d, k) + lane8(e, k);
+    const float v1 = lane8(a, k + 1) + lane8(b, k + 1) + lane8(d, k + 1) + lane8(e, k + 1);
+    o[k >> 1] = (uint32_t)f2bf(0.25f * v0) | ((uint32_t)f2bf(0.25f * v1) << 16);
+  }
+  *reinterpret_cast<u32x4*>(out.p + Q * out.cs + out.co + c) = o;
 }
 
 __global__ void pool_back_add_kernel(Tensor dp, Tensor e, Tensor de, int C, int B, int H) {
+  const int G = C >> 3;
   const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (idx >= (int64_t)B * H * H * C) return;
-  const int c = (int)(idx % C);
-  const int64_t P = idx / C;
+  if (idx >= (int64_t)B * H * H * G) return;
+  const int64_t P = idx / G;
+  const int c = 8 * (int)(idx - P * G);
   const int64_t n = P / (H * H);
   const int rem = (int)(P - n * H * H);
   const int Ho = H >> 1;
   const int64_t Q = (n * Ho + (rem / H) / 2) * Ho + (rem % H) / 2;
   uint16_t* d = de.p + P * de.cs + de.co + c;
-  float v = bf2f(*d) + 0.25f * bf2f(dp.p[Q * dp.cs + dp.co + c]);
-  if (!(bf2f(e.p[P * e.cs + e.co + c]) > 0.f)) v = 0.f;
-  *d = f2bf(v);
+  const u32x4 dv = ld16(d), pv = ld16(dp.p + Q * dp.cs + dp.co + c);
+  const u32x4 ev = ld16(e.p + P * e.cs + e.co + c);
+  u32x4 o;
+#pragma unroll
+  for (int k = 0; k < 8; k += 2) {
+    float v[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      v[h] = lane8(dv, k + h) + 0.25f * lane8(pv, k + h);
+      if (!(lane8(ev, k + h) > 0.f)) v[h] = 0.f;
+    }
+    o[k >> 1] = (uint32_t)f2bf(v[0]) | ((uint32_t)f2bf(v[1]) << 16);
+  }
+  *reinterpret_cast<u32x4*>(d) = o;
 }
 
 __global__ void up_back_kernel(Tensor du, Tensor d, Tensor dd, int C, int B, int H) {
+  const int G = C >> 3;
   const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (idx >= (int64_t)B * H * H * C) return;
-  const int c = (int)(idx % C);
-  const int64_t Q = idx / C;
+  if (idx >= (int64_t)B * H * H * G) return;
+  const int64_t Q = idx / G;
+  const int c = 8 * (int)(idx - Q * G);
   const int64_t n = Q / (H * H);
   const int rem = (int)(Q - n * H * H);
   const int H2 = 2 * H;
   const int64_t P = (n * H2 + 2 * (rem / H)) * H2 + 2 * (rem % H);
   const uint16_t* s = du.p + du.co + c;
-  float v = bf2f(s[P * du.cs]) + bf2f(s[(P + 1) * du.cs]) + bf2f(s[(P + H2) * du.cs]) +
-            bf2f(s[(P + H2 + 1) * du.cs]);
-  if (!(bf2f(d.p[Q * d.cs + d.co + c]) > 0.f)) v = 0.f;
-  dd.p[Q * dd.cs + dd.co + c] = f2bf(v);
+  const u32x4 a = ld16(s + P * du.cs), b = ld16(s + (P + 1) * du.cs);
+  const u32x4 e = ld16(s + (P + H2) * du.cs), f = ld16(s + (P + H2 + 1) * du.cs);
+  const u32x4 m = ld16(d.p + Q * d.cs + d.co + c);
+  u32x4 o;
+#pragma unroll
+  for (int k = 0; k < 8; k += 2) {
+    float v[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      v[h] = lane8(a, k + h) + lane8(b, k + h) + lane8(e, k + h) + lane8(f, k + h);
+      if (!(lane8(m, k + h) > 0.f)) v[h] = 0.f;
+    }
+    o[k >> 1] = (uint32_t)f2bf(v[0]) | ((uint32_t)f2bf(v[1]) << 16);
+  }
+  *reinterpret_cast<u32x4*>(dd.p + Q * dd.cs + dd.co + c) = o;
 }
 
 __global__ void head_kernel(Tensor d, int C, const float* head, const float* u, float in_scale,
@@ -483,7 +544,11 @@ __global__ void head_kernel(Tensor d, int C, const float* head, const float* u, 
   if (P >= npx) return;
   const uint16_t* dp = d.p + P * d.cs + d.co;
   float s = 0.f;
-  for (int c = 0; c < C; ++c) s += head[c] * bf2f(dp[c]);
+  for (int c = 0; c < C; c += 8) {   // 16-byte loads, channels summed in order
+    const u32x4 v = ld16(dp + c);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) s += head[c + k] * lane8(v, k);
+  }
   x0[P] = s + head[C] + head[C + 1] * (in_scale * u[P]);
 }
 
@@ -643,9 +708,9 @@ hipError_t launch_wgrad(const WgradArgs& a, hipStream_t st) {
 
 hipError_t launch_conv_in(const float* u, double in_scale, const uint16_t* w, const float* bias,
                           Tensor out, int Cout, int B, int H, hipStream_t st) {
-  const int64_t n = (int64_t)B * H * H * Cout;
-  hipLaunchKernelGGL(conv_in_kernel, dim3(blocks256(n)), dim3(256), 0, st, u, (float)in_scale, w,
-                     bias, out, Cout, B, H);
+  const int64_t n = (int64_t)B * H * H;
+  hipLaunchKernelGGL(conv_in_kernel, dim3(blocks256(n)), dim3(256), sizeof(float) * 10 * Cout, st,
+                     u, (float)in_scale, w, bias, out, Cout, B, H);
   return hipGetLastError();
 }
 
@@ -673,21 +738,21 @@ hipError_t launch_wgrad_in(const uint16_t* dz, int Cout, const float* u, double 
 }
 
 hipError_t launch_pool(Tensor in, Tensor out, int C, int B, int H, hipStream_t st) {
-  const int64_t n = (int64_t)B * (H / 2) * (H / 2) * C;
+  const int64_t n = (int64_t)B * (H / 2) * (H / 2) * (C / 8);
   hipLaunchKernelGGL(pool_kernel, dim3(blocks256(n)), dim3(256), 0, st, in, out, C, B, H);
   return hipGetLastError();
 }
 
 hipError_t launch_pool_back_add(Tensor dp, Tensor e, Tensor de, int C, int B, int H,
                                 hipStream_t st) {
-  const int64_t n = (int64_t)B * H * H * C;
+  const int64_t n = (int64_t)B * H * H * (C / 8);
   hipLaunchKernelGGL(pool_back_add_kernel, dim3(blocks256(n)), dim3(256), 0, st, dp, e, de, C, B,
                      H);
   return hipGetLastError();
 }
 
 hipError_t launch_up_back(Tensor du, Tensor d, Tensor dd, int C, int B, int H, hipStream_t st) {
-  const int64_t n = (int64_t)B * H * H * C;
+  const int64_t n = (int64_t)B * H * H * (C / 8);
   hipLaunchKernelGGL(up_back_kernel, dim3(blocks256(n)), dim3(256), 0, st, du, d, dd, C, B, H);
   return hipGetLastError();
 }
