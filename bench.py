@@ -67,13 +67,13 @@ PEAK_FP64_TFLOPS = 78.6
 # line reports traffic as null.
 PMC_TRAFFIC = {
     "source": "paper_1912_07962_amd/csrc/project.hip",
-    "sha256": "e681cb313f5c9ed48a8def7615ad46ae97c08e5bc76fa1265af95ae19b21578d",
+    "sha256": "6daf19dd8671fa1b5042fdfa67d48cca49a083ddcb52ad6723a7f79cbb71ea19",
     "fetch_scale": 2.0,
     "write_scale": 1.0,
     # instance -> (FETCH_SIZE, WRITE_SIZE) KiB per dispatch
-    "kib": {"cg_forward/2": (6232.2, 1992.8), "cg_forward/3": (6247.1, 2989.1),
-            "cg_forward/4": (4217.5, 3984.8), "cg_forward/6": (5399.0, 5479.7),
-            "cg_forward/8": (4281.5, 7969.5), "cg_back/1": (3097.1, 8192.8)},
+    "kib": {"cg_forward/2": (6221.3, 1992.8), "cg_forward/3": (6251.6, 2989.1),
+            "cg_forward/4": (4219.0, 3984.8), "cg_forward/6": (5403.0, 5479.6),
+            "cg_forward/8": (4276.0, 7969.5), "cg_back/1": (3094.1, 8192.8)},
 }
 
 
