@@ -345,17 +345,28 @@ __global__ __launch_bounds__(256) void back3_kernel(
       // ceil(2 wu) <= 3 of them (2 x 2 for a direction along an axis)
       const double wu = G.wu, wv = G.wv;
       const int nt = (int)ceil(2.0 * wu), nq = (int)ceil(2.0 * wv);
-      const double fu_xy = cx * G.eu[0] + cy * G.eu[1] + hn;
+      // e_u has no z component, so a column's voxels share fu: its detector
+      // columns, their offsets du and the du terms of both tents are the
+      // column's (fu is evaluated as cx e_u[0] + cy e_u[1] + hn)
+      const double fu = cx * G.eu[0] + cy * G.eu[1] + hn;
       const double fv_xy = cx * G.ev[0] + cy * G.ev[1] + hn;
+      const double tsu = floor(fu - wu) + 1.0;
+      const float du0 = (float)(tsu - fu);
+      // clamped so that no read leaves the window (never active for a voxel of the tile)
+      const int lt = min(max((int)tsu - t0, 0), kFP - 3);
       const float la0 = (float)G.La[0], la1 = (float)G.La[1];
       const float lb0 = (float)G.Lb[0], lb1 = (float)G.Lb[1];
+      float ta[3], tb[3];
+#pragma unroll
+      for (int ot = 0; ot < 3; ++ot) {
+        ta[ot] = la0 * (du0 + (float)ot);
+        tb[ot] = lb0 * (du0 + (float)ot);
+      }
 #pragma unroll
       for (int c = 0; c < kVZ; ++c) {
-        const double fu = fma(cz + c, G.eu[2], fu_xy), fv = fma(cz + c, G.ev[2], fv_xy);
-        const double tsu = floor(fu - wu) + 1.0, tsv = floor(fv - wv) + 1.0;
-        const float du0 = (float)(tsu - fu), dv0 = (float)(tsv - fv);
-        // clamped so that no read leaves the window (never active for a voxel of the tile)
-        const int lt = min(max((int)tsu - t0, 0), kFP - 3);
+        const double fv = fma(cz + c, G.ev[2], fv_xy);
+        const double tsv = floor(fv - wv) + 1.0;
+        const float dv0 = (float)(tsv - fv);
         const int lq = min(max((int)tsv - q0, 0), kFP - 3);
         float a = acc[c];
 #pragma unroll
@@ -367,9 +378,8 @@ __global__ __launch_bounds__(256) void back3_kernel(
 #pragma unroll
             for (int ot = 0; ot < 3; ++ot) {
               if (ot < nt) {
-                const float du = du0 + (float)ot;
-                const float wa = unit_clamp(1.f - fabsf(fmaf(la0, du, ra)));
-                const float wb = unit_clamp(1.f - fabsf(fmaf(lb0, du, rb)));
+                const float wa = fmaxf(1.f - fabsf(ta[ot] + ra), 0.f);
+                const float wb = fmaxf(1.f - fabsf(tb[ot] + rb), 0.f);
                 a = fmaf(wa * wb, row[ot], a);
               }
             }
