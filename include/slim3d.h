@@ -61,8 +61,9 @@ typedef struct slim3d_ctx slim3d_ctx;
  *            block, g, must divide n_dirs; (r+1) g <= 256), pcg_tol,
  *            pcg_max_iter, gram_mode, stream.  gram_mode AUTO or JACOBI:
  *            CG preconditioned by the inverse Gram diagonal; PCG: plain CG
- *            (the stop test is ||res|| <= pcg_tol ||rhs|| on the true
- *            residual either way); CHOL is refused.  Other fields must hold
+ *            (either way the stop test is ||res|| <= pcg_tol ||rhs|| on
+ *            the Gram system's residual, not the preconditioned one); CHOL
+ *            is refused.  Other fields must hold
  *            their defaults' meaning for this path: precision FP32,
  *            tikhonov 0.
  * Allocates the direction table and the step workspace: three padded

@@ -589,8 +589,8 @@ __global__ __launch_bounds__(256) void cg3_update_kernel(double* __restrict__ z,
   }
 }
 
-// Stop once r.r <= tol^2 e.e (the true residual, preconditioned or not);
-// else beta = r.y / (r.y)_old.
+// Stop once r.r <= tol^2 e.e (r the Gram system's own residual, kept by the
+// recurrence, not the preconditioned one); else beta = r.y / (r.y)_old.
 __global__ __launch_bounds__(256) void cg3_rr_kernel(const double* __restrict__ parts, int np,
                                                      double* __restrict__ sc,
                                                      int* __restrict__ ctl) {
