@@ -694,6 +694,25 @@ def warm_bench(dev, n_test, n_timed):
     t_inf = e0.elapsed_time(e1) / 10 * 1e-3
     inf_tflops = net.forward_flops() * 16 / t_inf / 1e12
 
+    # CNN training steps at batch 16 (loss, gradients, Adam) on a copy of the
+    # network, targets the plain method's iterates; the convolution work of a
+    # step is ~3x the forward's (forward, data and weight gradients)
+    net_t = Cnn(cfg["N"], ws.CHANNELS, max_batch=16, in_scale=ws.in_scale(cfg))
+    net_t.set_params(np.load(path))
+    t16 = plain["target"][:16].contiguous()
+    for _ in range(2):
+        net_t.loss_grad(u16, t16)
+        net_t.adam(1e-5)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(10):
+        net_t.loss_grad(u16, t16)
+        net_t.adam(1e-5)
+    torch.cuda.synchronize()
+    t_train = (time.perf_counter() - t0) / 10
+    net_t.close()
+    train_tflops = 3.0 * net.forward_flops() * 16 / t_train / 1e12
+
     # single-slice wall clock
     N, g, r = cfg["N"], cfg["g"], cfg["r"]
     sched = ws.schedule(cfg)
@@ -730,7 +749,8 @@ def warm_bench(dev, n_test, n_timed):
                "timed_warm_steps_mean": float(np.mean(st_warm)),
                "speedup_vs_plain": float(np.mean(t_plain) / np.mean(t_warm)),
                "cnn_inference_ms_batch16": t_inf * 1e3, "cnn_inference_tflops": inf_tflops,
-               "cnn_inference_mfma_frac": inf_tflops / PEAK_BF16_TFLOPS})
+               "cnn_inference_mfma_frac": inf_tflops / PEAK_BF16_TFLOPS,
+               "cnn_train_step_ms_batch16": t_train * 1e3, "cnn_train_tflops_3x_forward": train_tflops})
     net.close()
     print(f"bench: warm {ev['warm_s_mean']:.3f} s vs plain {ev['plain_s_mean']:.3f} s per slice",
           file=sys.stderr, flush=True)

@@ -403,39 +403,68 @@ __global__ __launch_bounds__(256) void conv_in_kernel(const float* u, float in_s
 }
 
 // entry t = k * Cout + co: tap k < 9 (weight) or k = 9 (bias) of channel co,
-// summed over this workgroup's pixel range
+// summed over this workgroup's pixels [p0, p1).  Per chunk of 32 channels a
+// lane takes one group of 8 channels (tid & 3) of every 64th pixel (pixel
+// lane tid >> 2), with 16-byte loads of dz, and sums its 80 products in
+// order; the 64 pixel lanes are then added by a butterfly within each
+// wavefront and the four wavefronts in order (fixed order throughout).
 __global__ __launch_bounds__(256) void wgrad_in_kernel(const uint16_t* dz, int Cout,
                                                        const float* u, float in_scale, int B,
                                                        int H, int64_t cps, float* part) {
+  __shared__ float red[4][4][80];
   const int64_t npx = (int64_t)B * H * H;
   const int64_t p0 = (int64_t)blockIdx.x * cps, p1 = min(npx, p0 + cps);
-  const int64_t n0 = p0 / (H * H);
-  const int rem0 = (int)(p0 - n0 * H * H);
-  for (int t = threadIdx.x; t < 10 * Cout; t += blockDim.x) {
-    const int co = t % Cout, k = t / Cout;
-    const int dy = k / 3 - 1, dx = k % 3 - 1;
-    float acc = 0.f;
-    // pixel coordinates stepped along the range (no division per pixel)
-    int y = rem0 / H, x = rem0 % H;
-    const float* un = u + n0 * H * H;
-    for (int64_t P = p0; P < p1; ++P) {
-      const float g = bf2f(dz[P * Cout + co]);
-      if (k == 9) {
-        acc += g;
-      } else {
-        const int yy = y + dy, xx = x + dx;
-        if ((unsigned)yy < (unsigned)H && (unsigned)xx < (unsigned)H)
-          acc += g * (in_scale * un[yy * H + xx]);
+  const int tid = threadIdx.x, cg = tid & 3, pl = tid >> 2, w = tid >> 6;
+  const int HH = H * H;
+  for (int c0 = 0; c0 < Cout; c0 += 32) {
+    float acc[10][8];
+#pragma unroll
+    for (int k = 0; k < 10; ++k)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) acc[k][j] = 0.f;
+    for (int64_t P = p0 + pl; P < p1; P += 64) {
+      const int64_t n = P / HH;
+      const int rem = (int)(P - n * HH);
+      const int y = rem / H, x = rem - (rem / H) * H;
+      const float* un = u + n * HH;
+      const u32x4 gv = *reinterpret_cast<const u32x4*>(dz + P * Cout + c0 + 8 * cg);
+      float g[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) g[j] = bf2f((uint16_t)(gv[j >> 1] >> (16 * (j & 1))));
+#pragma unroll
+      for (int k = 0; k < 9; ++k) {
+        const int yy = y + k / 3 - 1, xx = x + k % 3 - 1;
+        const float uv = ((unsigned)yy < (unsigned)H && (unsigned)xx < (unsigned)H)
+                             ? in_scale * un[yy * H + xx] : 0.f;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) acc[k][j] = fmaf(g[j], uv, acc[k][j]);
       }
-      if (++x == H) {
-        x = 0;
-        if (++y == H) {
-          y = 0;
-          un += H * H;
-        }
-      }
+#pragma unroll
+      for (int j = 0; j < 8; ++j) acc[9][j] += g[j];
     }
-    part[(size_t)blockIdx.x * 10 * Cout + t] = acc;
+    // the 16 pixel lanes of a wavefront with the same channel group: lanes
+    // 4 apart, added by a butterfly over lane bits 2..5
+#pragma unroll
+    for (int k = 0; k < 10; ++k)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        float v = acc[k][j];
+        for (int o = 4; o < 64; o <<= 1) v += __shfl_xor(v, o, 64);
+        acc[k][j] = v;
+      }
+    if ((tid & 63) < 4) {
+#pragma unroll
+      for (int k = 0; k < 10; ++k)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) red[w][cg][k * 8 + j] = acc[k][j];
+    }
+    __syncthreads();
+    for (int e = tid; e < 320; e += 256) {
+      const int g4 = e / 80, kj = e % 80, k = kj / 8, j = kj % 8;
+      const float v = (red[0][g4][kj] + red[1][g4][kj]) + (red[2][g4][kj] + red[3][g4][kj]);
+      part[(size_t)blockIdx.x * 10 * Cout + k * Cout + c0 + 8 * g4 + j] = v;
+    }
+    __syncthreads();
   }
 }
 
@@ -564,34 +593,54 @@ __global__ __launch_bounds__(256) void head_back_kernel(Tensor d, int C, const f
                                                         const float* u, float in_scale,
                                                         const float* x0, const float* target,
                                                         int64_t npx, Tensor dz, double* part) {
+  // Per lane: every (gridDim.x * 256)-th pixel from its own, each quantity
+  // summed over them in order; then across the wavefront by shuffles and
+  // across the four wavefronts in order.  Channels go eight at a time
+  // (16-byte loads of D and stores of dz).
   extern __shared__ double red[];  // [4][C + 3]
-  const int64_t P = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const bool in = P < npx;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  float diff = 0.f, g = 0.f, uh = 0.f;
-  if (in) {
-    diff = x0[P] - target[P];
-    g = 2.f * diff / (float)npx;
-    uh = in_scale * u[P];
-  }
-  const uint16_t* dp = d.p + (in ? P : 0) * d.cs + d.co;
-  for (int k = 0; k < C + 3; ++k) {
-    double v = 0.0;
-    if (in) {
-      if (k < C) {
-        const float dv = bf2f(dp[k]);
-        v = (double)g * dv;
-        dz.p[P * dz.cs + dz.co + k] = f2bf(dv > 0.f ? g * head[k] : 0.f);
-      } else if (k == C) {
-        v = g;
-      } else if (k == C + 1) {
-        v = (double)g * uh;
-      } else {
-        v = (double)diff * diff;
+  const int64_t P0 = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t step = (int64_t)gridDim.x * 256;
+  const float inv = 2.f / (float)npx;
+  for (int c0 = 0; c0 < C; c0 += 8) {
+    double acc[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) acc[j] = 0.0;
+    for (int64_t P = P0; P < npx; P += step) {
+      const float g = inv * (x0[P] - target[P]);
+      const u32x4 dv = *reinterpret_cast<const u32x4*>(d.p + P * d.cs + d.co + c0);
+      u32x4 o;
+#pragma unroll
+      for (int j = 0; j < 8; j += 2) {
+        const float a = lane8(dv, j), b = lane8(dv, j + 1);
+        acc[j] += (double)g * a;
+        acc[j + 1] += (double)g * b;
+        o[j >> 1] = (uint32_t)f2bf(a > 0.f ? g * head[c0 + j] : 0.f) |
+                    ((uint32_t)f2bf(b > 0.f ? g * head[c0 + j + 1] : 0.f) << 16);
       }
+      *reinterpret_cast<u32x4*>(dz.p + P * dz.cs + dz.co + c0) = o;
     }
-    v = wave_sum64(v);
-    if (lane == 0) red[w * (C + 3) + k] = v;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const double v = wave_sum64(acc[j]);
+      if (lane == 0) red[w * (C + 3) + c0 + j] = v;
+    }
+  }
+  double a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  for (int64_t P = P0; P < npx; P += step) {
+    const float diff = x0[P] - target[P];
+    const float g = inv * diff;
+    a1 += g;
+    a2 += (double)g * (in_scale * u[P]);
+    a3 += (double)diff * diff;
+  }
+  a1 = wave_sum64(a1);
+  a2 = wave_sum64(a2);
+  a3 = wave_sum64(a3);
+  if (lane == 0) {
+    red[w * (C + 3) + C] = a1;
+    red[w * (C + 3) + C + 1] = a2;
+    red[w * (C + 3) + C + 2] = a3;
   }
   __syncthreads();
   for (int k = threadIdx.x; k < C + 3; k += 256)
@@ -716,7 +765,7 @@ hipError_t launch_conv_in(const float* u, double in_scale, const uint16_t* w, co
 
 static int wgrad_in_splits(int B, int H) {
   const int64_t npx = (int64_t)B * H * H;
-  return (int)std::min<int64_t>(1024, std::max<int64_t>(1, npx / 256));
+  return (int)std::min<int64_t>(512, std::max<int64_t>(1, npx / 1024));
 }
 
 size_t wgrad_in_part_floats(int Cout, int B, int H) {
@@ -764,12 +813,16 @@ hipError_t launch_head(Tensor d, int C, const float* head, const float* u, doubl
   return hipGetLastError();
 }
 
-size_t head_part_doubles(int C, int64_t npx) { return (size_t)blocks256(npx) * (C + 3); }
+// workgroups of the head's backward: at most 1024, each lane then covers
+// every (1024 * 256)-th pixel
+static unsigned head_blocks(int64_t npx) { return (unsigned)std::min<int64_t>(1024, blocks256(npx)); }
+
+size_t head_part_doubles(int C, int64_t npx) { return (size_t)head_blocks(npx) * (C + 3); }
 
 hipError_t launch_head_back(Tensor d, int C, const float* head, const float* u, double in_scale,
                             const float* x0, const float* target, int64_t npx, Tensor dz,
                             double* part, double* loss, float* dhead, hipStream_t st) {
-  const unsigned nblk = blocks256(npx);
+  const unsigned nblk = head_blocks(npx);
   hipLaunchKernelGGL(head_back_kernel, dim3(nblk), dim3(256), (size_t)4 * (C + 3) * sizeof(double),
                      st, d, C, head, u, (float)in_scale, x0, target, npx, dz, part);
   hipError_t e = hipGetLastError();
