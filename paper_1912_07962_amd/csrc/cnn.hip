@@ -321,26 +321,180 @@ __global__ __launch_bounds__(64 * (TCO / 32) * (TCI / 32)) void wgrad_kernel(Wgr
     a.part[(size_t)gridDim.x * nw + (size_t)split * a.Cout + cot * TCO + tid] = bsum;
 }
 
-// dw[i] = sum_s part[s][i], db[c] = sum_s bpart[s][c], splits in order
-__global__ void wgrad_reduce_kernel(const float* part, int nsplit, int64_t nw, int Cout,
-                                    float* dw, float* db) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+// Weight gradient on grids of at least 64 columns (a multiple of 64): the
+// pixels are walked in 64-pixel row segments and a workgroup forms all nine
+// taps of its TCO x TCI tile, so each segment's dz (TCO channels x 64
+// pixels) and the three input rows the taps reach (TCI channels x 66 pixels,
+// zeros outside the grid) are staged once, transposed to pixel-contiguous
+// rows.  A tap's row offset selects the staged row and its column offset is
+// applied when the B operand is read (an aligned 16-byte read, the next four
+// bytes and a byte alignment).  The (TCO/32) x (TCI/32) blocks of 32 x 32
+// go to the wavefronts, a block's nine taps dealt out among its wavefronts.
+constexpr int kLX = 80;   // LDS row stride (bf16) of the staged input rows (66 pixels + pad)
+
+__device__ __forceinline__ bf16x8 lds8_at(const uint16_t* row, int s, int d) {
+  // row[s .. s+7] with s = 8 m + d, d in {0, 1, 2}
+  const u32x4 lo = *reinterpret_cast<const u32x4*>(row + (s - d));
+  if (d == 0) return __builtin_bit_cast(bf16x8, lo);
+  const uint32_t hi = *reinterpret_cast<const uint32_t*>(row + (s - d) + 8);
+  u32x4 o;
+  if (d == 2) {
+    o[0] = lo[1];
+    o[1] = lo[2];
+    o[2] = lo[3];
+    o[3] = hi;
+  } else {
+    o[0] = __builtin_amdgcn_alignbyte(lo[1], lo[0], 2);
+    o[1] = __builtin_amdgcn_alignbyte(lo[2], lo[1], 2);
+    o[2] = __builtin_amdgcn_alignbyte(lo[3], lo[2], 2);
+    o[3] = __builtin_amdgcn_alignbyte(hi, lo[3], 2);
+  }
+  return __builtin_bit_cast(bf16x8, o);
+}
+
+template <int TCO, int TCI>
+__global__ __launch_bounds__(256) void wgrad_row_kernel(WgradArgs a, int n_chunks, int cps,
+                                                        int nci_t) {
+  constexpr int NB = (TCO / 32) * (TCI / 32);   // 32 x 32 blocks of the tile
+  constexpr int WPB = 4 / NB;                   // wavefronts per block
+  constexpr int NTW = (9 + WPB - 1) / WPB;      // taps per wavefront, at most
+  __shared__ __attribute__((aligned(16))) uint16_t sz[TCO * kLD];
+  __shared__ __attribute__((aligned(16))) uint16_t sx[3 * TCI * kLX];
+  const int split = blockIdx.x;
+  const int cot = blockIdx.z / nci_t, cit = blockIdx.z % nci_t;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int blk = w / WPB, wib = w % WPB;
+  const int wco = (blk / (TCI / 32)) * 32, wci = (blk % (TCI / 32)) * 32;
+  const int r = lane & 15, q = lane >> 4;
+  const int H = a.H, Hin = a.up ? (H >> 1) : H;
+  const int spr = H / 64;   // segments per row
+  const bool do_bias = cit == 0;
+
+  f32x4 acc[NTW][2][2];
+#pragma unroll
+  for (int it = 0; it < NTW; ++it)
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) acc[it][i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  float bsum = 0.f;
+
+  const int c_begin = split * cps, c_end = min(n_chunks, c_begin + cps);
+  for (int ch = c_begin; ch < c_end; ++ch) {
+    const int64_t grow = ch / spr;                 // n H + y
+    const int x0 = (int)(ch - grow * spr) * 64;
+    const int64_t n = grow / H;
+    const int y = (int)(grow - n * H);
+    const int64_t P0 = grow * H + x0;
+    for (int e = tid; e < 64 * (TCO / 8); e += 256) {
+      const int p = e / (TCO / 8), cg = e % (TCO / 8);
+      const u32x4 v = *reinterpret_cast<const u32x4*>(a.dz.p + (P0 + p) * a.dz.cs + a.dz.co +
+                                                      cot * TCO + cg * 8);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) sz[(cg * 8 + j) * kLD + p] = (uint16_t)(v[j >> 1] >> (16 * (j & 1)));
+    }
+    for (int e = tid; e < 3 * 66 * (TCI / 8); e += 256) {
+      const int cg = e % (TCI / 8), rest = e / (TCI / 8);
+      const int j = rest % 66, dy = rest / 66;
+      const int yy = y + dy - 1, xx = x0 + j - 1;
+      u32x4 v = {0u, 0u, 0u, 0u};
+      if ((unsigned)yy < (unsigned)H && (unsigned)xx < (unsigned)H) {
+        const int ys = a.up ? yy >> 1 : yy, xs = a.up ? xx >> 1 : xx;
+        v = *reinterpret_cast<const u32x4*>(a.in.p + ((n * Hin + ys) * Hin + xs) * a.in.cs +
+                                            a.in.co + cit * TCI + cg * 8);
+      }
+#pragma unroll
+      for (int jj = 0; jj < 8; ++jj)
+        sx[(dy * TCI + cg * 8 + jj) * kLX + j] = (uint16_t)(v[jj >> 1] >> (16 * (jj & 1)));
+    }
+    __syncthreads();
+    if (do_bias && tid < TCO)
+      for (int p = 0; p < 64; ++p) bsum += bf2f(sz[tid * kLD + p]);
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks) {
+      bf16x8 A[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) A[i] = ld8(sz + (wco + 16 * i + r) * kLD + 32 * ks + 8 * q);
+#pragma unroll
+      for (int it = 0; it < NTW; ++it) {
+        const int t = wib + it * WPB;
+        if (t < 9) {   // uniform over the wavefront
+          const int dy = t / 3, dx = t % 3;
+          bf16x8 Bv[2];
+#pragma unroll
+          for (int j = 0; j < 2; ++j)
+            Bv[j] = lds8_at(sx + (dy * TCI + wci + 16 * j + r) * kLX, 32 * ks + 8 * q + dx, dx);
+#pragma unroll
+          for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+              acc[it][i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[i], Bv[j], acc[it][i][j], 0, 0, 0);
+        }
+      }
+    }
+    __syncthreads();
+  }
+
+  const size_t nw = (size_t)a.Cout * 9 * a.Cin;
+  float* wp = a.part + (size_t)split * nw;
+#pragma unroll
+  for (int it = 0; it < NTW; ++it) {
+    const int t = wib + it * WPB;
+    if (t < 9) {
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int co = cot * TCO + wco + 16 * i + 4 * q + e;
+            const int ci = cit * TCI + wci + 16 * j + r;
+            wp[((size_t)co * 9 + t) * a.Cin + ci] = acc[it][i][j][e];
+          }
+    }
+  }
+  if (do_bias && tid < TCO)
+    a.part[(size_t)gridDim.x * nw + (size_t)split * a.Cout + cot * TCO + tid] = bsum;
+}
+
+// dw[i] = sum_s part[s][i], db[c] = sum_s bpart[s][c]: a workgroup takes 64
+// entries, its four wavefronts the splits s = 4 m + w (each summed in
+// order), combined in the order w = 0 .. 3 (a fixed order throughout).
+__global__ __launch_bounds__(256) void wgrad_reduce_kernel(const float* part, int nsplit,
+                                                           int64_t nw, int Cout, float* dw,
+                                                           float* db) {
+  __shared__ float red[4][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t i = (int64_t)blockIdx.x * 64 + lane;
+  float s = 0.f;
   if (i < nw) {
-    float s = 0.f;
-    for (int k = 0; k < nsplit; ++k) s += part[(size_t)k * nw + i];
-    dw[i] = s;
+#pragma unroll 4
+    for (int k = w; k < nsplit; k += 4) s += part[(size_t)k * nw + i];
   } else if (i < nw + Cout) {
-    const int c = (int)(i - nw);
     const float* bp = part + (size_t)nsplit * nw;
-    float s = 0.f;
-    for (int k = 0; k < nsplit; ++k) s += bp[(size_t)k * Cout + c];
-    db[c] = s;
+    const int c = (int)(i - nw);
+#pragma unroll 4
+    for (int k = w; k < nsplit; k += 4) s += bp[(size_t)k * Cout + c];
+  }
+  red[w][lane] = s;
+  __syncthreads();
+  if (w == 0) {
+    const float t = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
+    if (i < nw)
+      dw[i] = t;
+    else if (i < nw + Cout)
+      db[i - nw] = t;
   }
 }
 
 struct WgradPlan {
   int tco, tci, nco_t, nci_t, n_chunks, cps, nsplit;
 };
+
+// rows: the row-segment kernel (grids of 64 columns or more, all nine taps
+// per workgroup, about 512 workgroups), else the per-tap kernel (about 2048)
+static bool wgrad_rows(int H) { return H >= 64 && H % 64 == 0; }
 
 WgradPlan wgrad_plan(int Cout, int Cin, int B, int H) {
   WgradPlan p;
@@ -349,8 +503,9 @@ WgradPlan wgrad_plan(int Cout, int Cin, int B, int H) {
   p.nco_t = Cout / p.tco;
   p.nci_t = Cin / p.tci;
   p.n_chunks = (int)((int64_t)B * H * H / 64);
-  const int base = 9 * p.nco_t * p.nci_t;
-  int want = (2048 + base - 1) / base;
+  const int base = (wgrad_rows(H) ? 1 : 9) * p.nco_t * p.nci_t;
+  const int target = wgrad_rows(H) ? 512 : 2048;
+  int want = (target + base - 1) / base;
   want = std::max(1, std::min(want, p.n_chunks));
   p.cps = (p.n_chunks + want - 1) / want;
   p.nsplit = (p.n_chunks + p.cps - 1) / p.cps;
@@ -468,17 +623,30 @@ __global__ __launch_bounds__(256) void wgrad_in_kernel(const uint16_t* dz, int C
   }
 }
 
-__global__ void wgrad_in_reduce_kernel(const float* part, int nsplit, int Cout, float* dw,
-                                       float* db) {
-  const int t = blockIdx.x * 256 + threadIdx.x;
-  if (t >= 10 * Cout) return;
+// dw, db of the first layer: a workgroup takes 16 entries t, its lanes
+// (t, g) the splits g, g + 16, ... (each in order), combined over g in order.
+__global__ __launch_bounds__(256) void wgrad_in_reduce_kernel(const float* part, int nsplit,
+                                                              int Cout, float* dw, float* db) {
+  __shared__ float red[16][17];
+  const int e = threadIdx.x & 15, g = threadIdx.x >> 4;
+  const int t = blockIdx.x * 16 + e;
   float s = 0.f;
-  for (int k = 0; k < nsplit; ++k) s += part[(size_t)k * 10 * Cout + t];
-  const int co = t % Cout, k = t / Cout;
-  if (k < 9)
-    dw[co * 9 + k] = s;
-  else
-    db[co] = s;
+  if (t < 10 * Cout) {
+#pragma unroll 4
+    for (int k = g; k < nsplit; k += 16) s += part[(size_t)k * 10 * Cout + t];
+  }
+  red[g][e] = s;
+  __syncthreads();
+  if (g == 0 && t < 10 * Cout) {
+    float v = 0.f;
+#pragma unroll
+    for (int h = 0; h < 16; ++h) v += red[h][e];
+    const int co = t % Cout, k = t / Cout;
+    if (k < 9)
+      dw[co * 9 + k] = v;
+    else
+      db[co] = v;
+  }
 }
 
 // ------------------------------------------------------- pool / up / head
@@ -731,13 +899,25 @@ hipError_t launch_conv3x3(const ConvArgs& a, hipStream_t st) {
 // than min(ceil(2048 / base), n_chunks), and that bound grows with B.
 size_t wgrad_part_floats(int Cout, int Cin, int B, int H) {
   const WgradPlan p = wgrad_plan(Cout, Cin, B, H);
-  const int base = 9 * p.nco_t * p.nci_t;
-  const int bound = std::max(1, std::min((2048 + base - 1) / base, p.n_chunks));
+  const int base = (wgrad_rows(H) ? 1 : 9) * p.nco_t * p.nci_t;
+  const int target = wgrad_rows(H) ? 512 : 2048;
+  const int bound = std::max(1, std::min((target + base - 1) / base, p.n_chunks));
   return (size_t)bound * ((size_t)Cout * 9 * Cin + Cout);
 }
 
 hipError_t launch_wgrad(const WgradArgs& a, hipStream_t st) {
   const WgradPlan p = wgrad_plan(a.Cout, a.Cin, a.B, a.H);
+  if (wgrad_rows(a.H)) {
+    const dim3 grid(p.nsplit, 1, p.nco_t * p.nci_t);
+    if (p.tco == 64 && p.tci == 64)
+      hipLaunchKernelGGL((wgrad_row_kernel<64, 64>), grid, dim3(256), 0, st, a, p.n_chunks, p.cps, p.nci_t);
+    else if (p.tco == 64)
+      hipLaunchKernelGGL((wgrad_row_kernel<64, 32>), grid, dim3(256), 0, st, a, p.n_chunks, p.cps, p.nci_t);
+    else if (p.tci == 64)
+      hipLaunchKernelGGL((wgrad_row_kernel<32, 64>), grid, dim3(256), 0, st, a, p.n_chunks, p.cps, p.nci_t);
+    else
+      hipLaunchKernelGGL((wgrad_row_kernel<32, 32>), grid, dim3(256), 0, st, a, p.n_chunks, p.cps, p.nci_t);
+  } else {
   const dim3 grid(p.nsplit, 9, p.nco_t * p.nci_t);
   if (p.tco == 64 && p.tci == 64)
     hipLaunchKernelGGL((wgrad_kernel<64, 64>), grid, dim3(256), 0, st, a, p.n_chunks, p.cps, p.nci_t);
@@ -747,11 +927,12 @@ hipError_t launch_wgrad(const WgradArgs& a, hipStream_t st) {
     hipLaunchKernelGGL((wgrad_kernel<32, 64>), grid, dim3(128), 0, st, a, p.n_chunks, p.cps, p.nci_t);
   else
     hipLaunchKernelGGL((wgrad_kernel<32, 32>), grid, dim3(64), 0, st, a, p.n_chunks, p.cps, p.nci_t);
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t nw = (int64_t)a.Cout * 9 * a.Cin;
-  hipLaunchKernelGGL(wgrad_reduce_kernel, dim3(blocks256(nw + a.Cout)), dim3(256), 0, st,
-                     (const float*)a.part, p.nsplit, nw, a.Cout, a.dw, a.db);
+  hipLaunchKernelGGL(wgrad_reduce_kernel, dim3((unsigned)((nw + a.Cout + 63) / 64)), dim3(256), 0,
+                     st, (const float*)a.part, p.nsplit, nw, a.Cout, a.dw, a.db);
   return hipGetLastError();
 }
 
@@ -781,8 +962,8 @@ hipError_t launch_wgrad_in(const uint16_t* dz, int Cout, const float* u, double 
                      B, H, cps, part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(wgrad_in_reduce_kernel, dim3(blocks256(10 * Cout)), dim3(256), 0, st,
-                     (const float*)part, ns, Cout, dw, db);
+  hipLaunchKernelGGL(wgrad_in_reduce_kernel, dim3((unsigned)((10 * Cout + 15) / 16)), dim3(256), 0,
+                     st, (const float*)part, ns, Cout, dw, db);
   return hipGetLastError();
 }
 
