@@ -875,9 +875,9 @@ unsigned blocks256(int64_t n) { return (unsigned)((n + 255) / 256); }
 // ----------------------------------------------------------------- launchers
 hipError_t launch_conv3x3(const ConvArgs& a, hipStream_t st) {
   if (a.H >= 32 && a.H % 32 == 0 && a.Cin % 32 == 0) {
-    if (a.Cout == 32) {   // 16 x 32 pixels x 32 channels per workgroup
-      const int64_t blocks = (int64_t)a.B * (a.H / 16) * (a.H / 32);
-      hipLaunchKernelGGL((conv3x3_lds_kernel<8, 2>), dim3(grid8(blocks)), dim3(256), 0, st, a,
+    if (a.Cout == 32) {   // 8 x 32 pixels x 32 channels per workgroup
+      const int64_t blocks = (int64_t)a.B * (a.H / 8) * (a.H / 32);
+      hipLaunchKernelGGL((conv3x3_lds_kernel<4, 2>), dim3(grid8(blocks)), dim3(256), 0, st, a,
                          (int)blocks);
       return hipGetLastError();
     }
