@@ -32,6 +32,7 @@ namespace {
 constexpr int kRT = 16;                   // forward ray tile (t and q)
 constexpr int kVX = 16, kVY = 16, kVZ = 8;  // back-projector voxel tile (a lane: kVZ along z)
 constexpr int kFP = 32;                     // staged detector window side
+constexpr int kFS = kFP + 1;                // its LDS row stride (odd: rows fall in distinct banks)
 constexpr int kFlush = 32;                // planes per float32 partial sum
 constexpr double kTwo32 = 4294967296.0;
 constexpr float kInv32 = 2.3283064365386963e-10f;  // 2^-32
@@ -302,7 +303,7 @@ __global__ __launch_bounds__(256) void back3_kernel(
     float* __restrict__ out2, float* __restrict__ x, const float* __restrict__ x_true,
     double* __restrict__ partials, int mode, const int* __restrict__ ctl) {
   if (ctl && ctl[kCtlDone]) return;
-  __shared__ float sv[kFP * kFP];
+  __shared__ float sv[kFP * kFS];
   __shared__ float tr[kVZ * kVY * (kVX + 1)];   // the tile, for the x-slowest layout
   __shared__ double sh[4];
   const int tid = threadIdx.x;
@@ -336,7 +337,7 @@ __global__ __launch_bounds__(256) void back3_kernel(
       float val = 0.f;
       if ((unsigned)tq < (unsigned)n && (unsigned)tt < (unsigned)n)
         val = (float)vs[(size_t)tq * n + tt] * sc;
-      sv[e] = val;
+      sv[(e / kFP) * kFS + e % kFP] = val;
     }
     __syncthreads();
     if (ok) {
@@ -374,7 +375,7 @@ __global__ __launch_bounds__(256) void back3_kernel(
           if (oq < nq) {   // uniform over the workgroup (one direction)
             const float dv = dv0 + (float)oq;
             const float ra = la1 * dv, rb = lb1 * dv;
-            const float* row = sv + (lq + oq) * kFP + lt;
+            const float* row = sv + (lq + oq) * kFS + lt;
 #pragma unroll
             for (int ot = 0; ot < 3; ++ot) {
               if (ot < nt) {
