@@ -36,6 +36,8 @@
 #include "pcg.h"
 
 #include <algorithm>
+#include <cstring>
+#include <mutex>
 
 namespace slim {
 
@@ -96,6 +98,8 @@ inline int item_count(int BT, int want) {
 constexpr int kPad = 4;       // zero columns on each side of a band row (keeps rows 16B-aligned)
 constexpr int kPF = 8;        // float4 prefetch registers per lane: H*N*BT/4 <= 8 * kFT
 
+constexpr int kMaxOrd = 1024;   // largest grid whose chunk order is balanced
+
 struct FwdPlan {
   int n;          // entries (= output rows)
   int n_row;      // entries 0..n_row-1 are row-stepping angles
@@ -107,6 +111,10 @@ struct FwdPlan {
   int items;      // rays per lane (template argument of the band kernel)
   int bt;         // slice tile (template argument of the band kernel)
   int il_lg;      // log2 of the number of angles whose rays interleave (ray_of)
+  double inv_full;     // 1 / (2^il_lg R)
+  double inv_tail[2];  // 1 / (angles left over after the interleaved groups), per orientation
+  int n_ord;           // positions with a chunk in corder (0: chunk = position mod n_chunks)
+  unsigned char corder[kMaxOrd];   // chunk of each position (a permutation within each tile-group)
   short id[kMaxList];
   short slot[kMaxList];
 };
@@ -131,16 +139,24 @@ __device__ __forceinline__ void chunk_range(const FwdPlan& pl, int R, int c, int
 // the list (within a block of the window: row ranges that differ little,
 // and the bins' spread shrinks by il); the last ng mod il angles interleave
 // likewise among themselves.
-__device__ __forceinline__ void ray_of(int j, int ng, int R, int lg, int& e, int& t) {
+// floor(j / D) for 0 <= j < 2^24 and 1 <= D < 2^20 from inv = 1 / D rounded
+// to double: j inv is within 2^-28 of j / D, whose fraction is 0 or at most
+// 1 - 1/D < 1 - 2^-20, so adding 2^-21 before truncation gives the quotient.
+__device__ __forceinline__ int div_by(int j, double inv) {
+  return (int)fma((double)j, inv, 0x1p-21);
+}
+
+__device__ __forceinline__ void ray_of(int j, int ng, int R, int lg, double inv_full,
+                                       double inv_tail, int& e, int& t) {
   const int il = 1 << lg, full = (ng >> lg) << lg;
   if (j < full * R) {
-    const int m = j / (il * R), rem = j - m * il * R;
+    const int m = div_by(j, inv_full), rem = j - m * il * R;
     e = il * m + (rem & (il - 1));
     t = rem >> lg;
   } else {
     const int j2 = j - full * R, k = ng - full;
-    e = full + j2 % k;
-    t = j2 / k;
+    t = div_by(j2, inv_tail);
+    e = full + j2 - t * k;
   }
 }
 
@@ -173,7 +189,7 @@ __device__ __forceinline__ void fwd_band_body(int pos, const AngleGeom* __restri
   typedef typename Lane<BT>::T LT;
   extern __shared__ float band[];
   const int W = N + 2 * kPad;
-  const int chunk = pos % pl.n_chunks;
+  const int chunk = pl.n_ord ? (int)pl.corder[pos] : pos % pl.n_chunks;
   const int tg = pos / pl.n_chunks;
   const int grp = tg % pl.n_groups;
   const int tile = tg / pl.n_groups;
@@ -197,8 +213,6 @@ __device__ __forceinline__ void fwd_band_body(int pos, const AngleGeom* __restri
 #pragma unroll
   for (int b = 0; b < BT; ++b)
     src[b] = (colm && !cband ? imgT : img) + (size_t)(b0 + min(b, nb - 1)) * img_stride;
-  const double half = 0.5 * (N - 1);
-  const double off = 0.5 * (R - 1);
   const int kg = grp * pl.G * pl.H;
 
   // Ray position along the minor axis in 32.32 fixed point: P = pos * 2^32
@@ -213,48 +227,57 @@ __device__ __forceinline__ void fwd_band_body(int pos, const AngleGeom* __restri
   int64_t P0[IT], S[IT];
   double acc[IT][BT];
   int wlo[IT], whi[IT];
+  int oi[IT];   // the slot's output offset slot(e) R + t, -1 for no ray
+  {
+    // every slot first finds its ray (an empty slot takes the chunk's last
+    // ray and is switched off below), so the table reads of all slots are
+    // in flight together
+    int e_[IT], t_[IT], id_[IT];
 #pragma unroll
-  for (int q = 0; q < IT; ++q) {
-    const int item = slot_item<IT>(q, threadIdx.x);
+    for (int q = 0; q < IT; ++q) {
+      const int item = min(slot_item<IT>(q, threadIdx.x), nitems - 1);
+      ray_of(i0 + item, ng, R, pl.il_lg, pl.inv_full, pl.inv_tail[colm ? 1 : 0], e_[q], t_[q]);
+      e_[q] += eg;
+      id_[q] = pl.id[e_[q]];
+    }
+    const double lo_p = kPad - 1.5, hi_p = N + kPad + 0.5;
 #pragma unroll
-    for (int b = 0; b < BT; ++b) acc[q][b] = 0.0;
-    P0[q] = 0;  // index 0: pad column
-    S[q] = 0;
-    int klo = N, khi = -1;
-    if (item < nitems) {
-      int e, t;
-      ray_of(i0 + item, ng, R, pl.il_lg, e, t);
-      e += eg;
-      const AngleGeom g = geom[pl.id[e]];
-      const double cm = colm ? g.c : g.s;   // coefficient of the major coordinate
-      const double cn = colm ? g.s : g.c;   // of the minor one, |cn| = d
-      const double inv = 1.0 / cn;
-      const double n1 = -cm * inv;          // pos(k) = p0 + k * n1
-      const double p0 = ((double)t - off) * inv + half + kPad - half * n1;
+    for (int q = 0; q < IT; ++q) {
+      const AngleGeom* g = geom + id_[q];
+      const double inv = g->f_inv, c0 = g->f_c0, n1 = g->f_n1;
+      const double qa = g->f_qa, qb = g->f_qb, qs = g->f_qs;
+      const int64_t Sq = g->f_S;
+      const bool live = slot_item<IT>(q, threadIdx.x) < nitems;
+#pragma unroll
+      for (int b = 0; b < BT; ++b) acc[q][b] = 0.0;
+      const double tt = (double)t_[q];
+      const double p0 = fma(tt, inv, c0);
       // rows with pos - kPad in [-1.5, N + 0.5] hold every contributing row
-      const double lo_p = kPad - 1.5, hi_p = N + kPad + 0.5;
       double lo = 0.0, hi = N - 1;
       if (n1 != 0.0) {
-        const double ma = (lo_p - p0) / n1, mb = (hi_p - p0) / n1;
+        const double ma = fma(tt, qs, qa), mb = fma(tt, qs, qb);
         lo = fmax(lo, ceil(fmin(ma, mb)));
         hi = fmin(hi, floor(fmax(ma, mb)));
       } else if (p0 < lo_p || p0 > hi_p) {
         lo = 1.0;
         hi = 0.0;
       }
-      if (lo <= hi) {
+      int klo = N, khi = -1;
+      if (live && lo <= hi) {
         klo = (int)lo;
         khi = (int)hi;
       }
-      P0[q] = __double2ll_rn(p0 * 4294967296.0);
-      S[q] = __double2ll_rn(n1 * 4294967296.0);
+      // index 0 (a pad column) and no step for an empty slot
+      P0[q] = live ? __double2ll_rn(p0 * 4294967296.0) : 0;
+      S[q] = live ? Sq : 0;
+      oi[q] = live ? pl.slot[e_[q]] * R + t_[q] : -1;
+      for (int o = 32; o > 0; o >>= 1) {
+        klo = min(klo, __shfl_xor(klo, o, 64));
+        khi = max(khi, __shfl_xor(khi, o, 64));
+      }
+      wlo[q] = __builtin_amdgcn_readfirstlane(klo);
+      whi[q] = __builtin_amdgcn_readfirstlane(khi);
     }
-    for (int o = 32; o > 0; o >>= 1) {
-      klo = min(klo, __shfl_xor(klo, o, 64));
-      khi = max(khi, __shfl_xor(khi, o, 64));
-    }
-    wlo[q] = __builtin_amdgcn_readfirstlane(klo);
-    whi[q] = __builtin_amdgcn_readfirstlane(khi);
   }
 
   // the zero pads are written once; band loads never touch them
@@ -443,16 +466,11 @@ __device__ __forceinline__ void fwd_band_body(int pos, const AngleGeom* __restri
   }
 #pragma unroll
   for (int q = 0; q < IT; ++q) {
-    const int item = slot_item<IT>(q, threadIdx.x);
-    if (item < nitems) {
-      int e, t;
-      ray_of(i0 + item, ng, R, pl.il_lg, e, t);
-      e += eg;
+    if (oi[q] >= 0) {
 #pragma unroll
       for (int b = 0; b < BT; ++b)
         if (b < nb)
-          partial[(((size_t)(b0 + b) * pl.n_groups + grp) * pl.n + pl.slot[e]) * R + t] =
-              (float)acc[q][b];
+          partial[((size_t)(b0 + b) * pl.n_groups + grp) * pl.n * R + oi[q]] = (float)acc[q][b];
     }
   }
 }
@@ -1040,6 +1058,27 @@ static int fwd_slice_tile(int B, int N) {
 // into groups, with chunks * tiles * groups <= 2 * (number of
 // CUs) where possible, so that a launch is one round of resident workgroups
 // (two per CU, bounded by LDS).
+void fwd_angle_consts(AngleGeom& g, int N, int R) {
+  const bool colm = g.colmajor != 0;
+  const double cm = colm ? g.c : g.s;   // coefficient of the major coordinate
+  const double cn = colm ? g.s : g.c;   // of the minor one, |cn| = d
+  const double half = 0.5 * (N - 1), off = 0.5 * (R - 1);
+  const double inv = 1.0 / cn;
+  const double n1 = -cm * inv;
+  g.f_inv = inv;
+  g.f_n1 = n1;
+  g.f_c0 = half + kPad - half * n1 - off * inv;
+  g.f_S = llrint(n1 * 4294967296.0);
+  const double lo_p = kPad - 1.5, hi_p = N + kPad + 0.5;
+  if (n1 != 0.0) {
+    g.f_qa = (lo_p - g.f_c0) / n1;
+    g.f_qb = (hi_p - g.f_c0) / n1;
+    g.f_qs = -inv / n1;
+  } else {
+    g.f_qa = g.f_qb = g.f_qs = 0.0;
+  }
+}
+
 static FwdPlan make_plan(const AngleGeom* h_geom, int N, int R, const AngleList& ids, int B,
                          const ProjTune& tune) {
   FwdPlan pl;
@@ -1068,6 +1107,12 @@ static FwdPlan make_plan(const AngleGeom* h_geom, int N, int R, const AngleList&
   // spreads its LDS reads over more clusters: four angles paid off for
   // detectors of 725 bins (512^2 volume window), two for 1449 (1024^2)
   pl.il_lg = R >= 1024 ? 1 : 2;
+  pl.inv_full = 1.0 / (double)((1 << pl.il_lg) * R);
+  for (int o = 0; o < 2; ++o) {
+    const int ng = o ? ids.n - pl.n_row : pl.n_row;
+    const int k = ng - ((ng >> pl.il_lg) << pl.il_lg);
+    pl.inv_tail[o] = 1.0 / (double)(k > 0 ? k : 1);
+  }
   pl.H = std::max(1, std::min(N, 16384 / ((N + 2 * kPad) * BT)));
   // bands of columns load four columns per 16-byte read: H a multiple of 4
   // (rounded up while the band stays within 68 KB and the lanes' prefetch
@@ -1086,7 +1131,153 @@ static FwdPlan make_plan(const AngleGeom* h_geom, int N, int R, const AngleList&
   int want = std::max(1, std::min(slots / (pl.n_chunks * pl.n_tiles), nbands));
   pl.G = (nbands + want - 1) / want;
   pl.n_groups = (nbands + pl.G - 1) / pl.G;
+  pl.n_ord = 0;
   return pl;
+}
+
+// Rows a ray crosses inside the padded image (the band kernel's per-ray row
+// range, as a count).
+static double ray_rows(const AngleGeom& g, int N, int t) {
+  const double lo_p = kPad - 1.5, hi_p = N + kPad + 0.5;
+  if (g.f_n1 == 0.0) {
+    const double p0 = t * g.f_inv + g.f_c0;
+    return (p0 < lo_p || p0 > hi_p) ? 0.0 : (double)N;
+  }
+  const double ma = g.f_qa + t * g.f_qs, mb = g.f_qb + t * g.f_qs;
+  const double lo = std::max(0.0, std::ceil(std::min(ma, mb)));
+  const double hi = std::min((double)(N - 1), std::floor(std::max(ma, mb)));
+  return hi >= lo ? hi - lo + 1.0 : 0.0;
+}
+
+// Workgroup order that evens out the CUs' work.  A launch's workgroups are
+// spread over the eight XCDs by position (xcd_position); within an XCD the
+// first round of positions takes one CU each and the second round the
+// second slot of the same CUs, in the same order.  Each chunk's work (rows
+// summed over its rays, estimated from 32 sampled rays) is the same for
+// every band group, so the first round takes the heaviest chunks of each
+// position's tile-group and the second round gives the lightest remaining
+// chunk to the position whose CU partner is heaviest; later rounds take the
+// heaviest first.  Every tile-group still holds each chunk once, so only the
+// schedule changes, never a result.
+static void order_chunks_compute(FwdPlan& pl, const AngleGeom* h_geom, int N, int R) {
+  const int total = pl.n_groups * pl.n_chunks * pl.n_tiles;
+  const int ncu = num_cu();
+  if (total > kMaxOrd || pl.n_chunks > 255 || ncu % 8 != 0 || total <= ncu / 8) return;
+  std::vector<double> work(pl.n_chunks);
+  const int nrc = (pl.n_row * R + pl.per - 1) / pl.per;
+  for (int c = 0; c < pl.n_chunks; ++c) {
+    const bool colm = c >= nrc;
+    const int eg = colm ? pl.n_row : 0, ng = colm ? pl.n - pl.n_row : pl.n_row;
+    const int i0 = (colm ? c - nrc : c) * pl.per;
+    const int i1 = std::min(ng * R, i0 + pl.per);
+    const int il = 1 << pl.il_lg, full = (ng >> pl.il_lg) << pl.il_lg;
+    double sum = 0.0;
+    constexpr int S = 32;
+    for (int k = 0; k < S; ++k) {
+      const int j = i0 + (int)((k + 0.5) * (i1 - i0) / S);
+      int e, t;
+      if (j < full * R) {
+        const int m = j / (il * R), rem = j - m * il * R;
+        e = il * m + (rem & (il - 1));
+        t = rem >> pl.il_lg;
+      } else {
+        const int j2 = j - full * R, kk = ng - full;
+        e = full + j2 % kk;
+        t = j2 / kk;
+      }
+      sum += ray_rows(h_geom[pl.id[eg + e]], N, t);
+    }
+    work[c] = sum * (i1 - i0) / S;
+  }
+  std::vector<int> byw(pl.n_chunks);
+  for (int c = 0; c < pl.n_chunks; ++c) byw[c] = c;
+  std::stable_sort(byw.begin(), byw.end(), [&](int a, int b) { return work[a] > work[b]; });
+  const int n_tg = pl.n_groups * pl.n_tiles;
+  std::vector<int> head(n_tg, 0), tail(n_tg, pl.n_chunks);   // unused part of byw per tile-group
+  const int cux = ncu / 8;
+  const int per_xcd = (total + 7) / 8;
+  std::vector<int> cu_work(cux);
+  std::vector<int> round1;
+  for (int x = 0; x < 8; ++x) {
+    const int base = x * per_xcd;
+    for (int p = 0; p < per_xcd; ++p) {
+      const int pos = base + p;
+      if (pos >= total) break;
+      const int tg = pos / pl.n_chunks;
+      if (p < cux) {
+        const int c = byw[head[tg]++];
+        pl.corder[pos] = (unsigned char)c;
+        cu_work[p] = (int)work[c];
+      } else if (p < 2 * cux) {
+        round1.push_back(p);
+      } else {
+        pl.corder[pos] = (unsigned char)byw[head[tg]++];
+      }
+      if (p + 1 == std::min(per_xcd, 2 * cux) || pos + 1 == total) {
+        // second round: heaviest partners first, each takes its tile-group's lightest chunk
+        std::stable_sort(round1.begin(), round1.end(),
+                         [&](int a, int b) { return cu_work[a - cux] > cu_work[b - cux]; });
+        for (int q : round1) {
+          const int tq = (base + q) / pl.n_chunks;
+          pl.corder[base + q] = (unsigned char)byw[--tail[tq]];
+        }
+        round1.clear();
+      }
+    }
+  }
+  // each tile-group must hold every chunk exactly once; else keep the plain order
+  std::vector<unsigned char> seen((size_t)n_tg * pl.n_chunks, 0);
+  for (int pos = 0; pos < total; ++pos) {
+    const int c = pl.corder[pos];
+    if (c >= pl.n_chunks || seen[(size_t)(pos / pl.n_chunks) * pl.n_chunks + c]++) return;
+  }
+  pl.n_ord = total;
+}
+
+// The order of the last few plans, so a CG solve (one plan per window,
+// launched every iteration) computes it once.  An entry matches on the
+// plan's shape and angle order and on the geometry table's address; the
+// order it returns is a permutation of this shape's chunks in any case.
+struct OrderEntry {
+  const AngleGeom* geom = nullptr;
+  int N = 0, R = 0, n = 0, n_row = 0, per = 0, il_lg = 0, n_chunks = 0, total = 0;
+  short id[kMaxList];
+  int n_ord = 0;
+  unsigned char corder[kMaxOrd];
+};
+static std::mutex g_ord_mu;
+static OrderEntry g_ord[8];
+static int g_ord_next = 0;
+
+static void order_chunks(FwdPlan& pl, const AngleGeom* h_geom, int N, int R) {
+  const int total = pl.n_groups * pl.n_chunks * pl.n_tiles;
+  auto same = [&](const OrderEntry& o) {
+    return o.geom == h_geom && o.N == N && o.R == R && o.n == pl.n && o.n_row == pl.n_row &&
+           o.per == pl.per && o.il_lg == pl.il_lg && o.n_chunks == pl.n_chunks &&
+           o.total == total && std::memcmp(o.id, pl.id, sizeof(short) * pl.n) == 0;
+  };
+  std::lock_guard<std::mutex> lock(g_ord_mu);
+  for (const OrderEntry& o : g_ord)
+    if (same(o)) {
+      pl.n_ord = o.n_ord;
+      std::memcpy(pl.corder, o.corder, (size_t)o.n_ord);
+      return;
+    }
+  order_chunks_compute(pl, h_geom, N, R);
+  OrderEntry& o = g_ord[g_ord_next];
+  g_ord_next = (g_ord_next + 1) % 8;
+  o.geom = h_geom;
+  o.N = N;
+  o.R = R;
+  o.n = pl.n;
+  o.n_row = pl.n_row;
+  o.per = pl.per;
+  o.il_lg = pl.il_lg;
+  o.n_chunks = pl.n_chunks;
+  o.total = total;
+  std::memcpy(o.id, pl.id, sizeof(short) * pl.n);
+  o.n_ord = pl.n_ord;
+  std::memcpy(o.corder, pl.corder, (size_t)pl.n_ord);
 }
 
 int forward_max_items(int bt) { return max_items(bt); }
@@ -1149,7 +1340,8 @@ static void launch_band_bt(int BT, int items, dim3 grid, size_t lds, hipStream_t
 
 hipError_t launch_forward(const FwdArgs& a, hipStream_t st) {
   if (a.ids->n <= 0) return hipSuccess;
-  const FwdPlan pl = make_plan(a.h_geom, a.N, a.R, *a.ids, a.B, a.tune);
+  FwdPlan pl = make_plan(a.h_geom, a.N, a.R, *a.ids, a.B, a.tune);
+  order_chunks(pl, a.h_geom, a.N, a.R);
   const int BT = pl.bt;
   const bool timed = a.prof && a.prof->on;
   hipError_t e;

@@ -611,6 +611,7 @@ slim_status slim_init(slim_ctx** out, const slim_grid* grid, int n_angles, const
     G.invd = (float)(1.0 / d);
     G.colmajor = std::fabs(sn) > std::fabs(cs) ? 1 : 0;
     G.pad = 0;
+    fwd_angle_consts(G, c->N, c->R);
   }
   auto oom = [&](hipError_t e) -> slim_status {
     delete c;

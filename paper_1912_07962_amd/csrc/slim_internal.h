@@ -31,7 +31,17 @@ struct AngleGeom {
   float invd;       // 1 / d
   int colmajor;     // 1 if |s| > |c|
   int pad;
+  // Forward-projector constants of the angle's own orientation (filled by
+  // fwd_angle_consts for the image size N and detector size R): ray t is at
+  // position p(k) = fma(t, f_inv, f_c0) + k f_n1 in the row (column) k it
+  // crosses, in pixels counted from the start of the projector's padded band
+  // row; f_S is f_n1 in 32.32 fixed point; for f_n1 != 0 the rows whose
+  // position lies within half a pixel beyond the image's border pixels are
+  // those between fma(t, f_qs, f_qa) and fma(t, f_qs, f_qb).
+  double f_inv, f_c0, f_n1, f_qa, f_qb, f_qs;
+  long long f_S;
 };
+void fwd_angle_consts(AngleGeom& g, int N, int R);
 
 // Canonical detector coordinate of a pixel.  The Gram kernel evaluates
 // exactly this expression; the back-projector evaluates it at each tile's
