@@ -160,16 +160,25 @@ __device__ __forceinline__ void cg_vector_body(int bx, int sl, int p, int pmax, 
                                                double* __restrict__ sv, double* __restrict__ z,
                                                size_t z_stride, int* __restrict__ ctl,
                                                int* __restrict__ live) {
-  if (ctl[sl * kCtlCount + kCtlDone]) return;
   __shared__ double sh[2 * (kThreads / 64)];
+  // every load of the workgroup (stop flag, scalars, partial dots, the
+  // lane's vector entries) is issued before the first wait; a stopped
+  // slice's workgroups read and leave without writing
+  const bool stopped = ctl[sl * kCtlCount + kCtlDone] != 0;
   const double* sc = sc_all + (size_t)sl * S_COUNT;
+  const double bb = sc[S_BB], g_old = sc[S_RR], a_old = sc[S_ALPHA];
+  const int i = bx * kThreads + threadIdx.x;
+  const size_t o = (size_t)sl * pmax + min(i, p - 1);
+  double* zs = z + (size_t)sl * z_stride;
+  const double pd_o = pd[o], r_o = r[o], sv_o = sv[o], q_o = q[o];
+  const double z_o = zs[min(i, p - 1)];
   double delta = 0.0, gamma = 0.0;
   for (int k = threadIdx.x; k < nb; k += kThreads) {
     delta += dq_parts[(size_t)sl * nparts + k];
     gamma += rr_parts[(size_t)sl * nparts + k];
   }
+  if (stopped) return;   // the same for the whole workgroup
   block_sum2(delta, gamma, sh);
-  const double bb = sc[S_BB], g_old = sc[S_RR], a_old = sc[S_ALPHA];
   const bool conv = !(gamma > tol2 * bb);
   const double beta = (g_old > 0.0) ? gamma / g_old : 0.0;
   const double alpha = (g_old > 0.0) ? gamma / (delta - beta * gamma / a_old) : gamma / delta;
@@ -190,16 +199,13 @@ __device__ __forceinline__ void cg_vector_body(int bx, int sl, int p, int pmax, 
     }
   }
   if (conv) return;
-  const int i = bx * kThreads + threadIdx.x;
   if (i < p) {
-    const size_t o = (size_t)sl * pmax + i;
-    const double pn = fma(beta, pd[o], r[o]);
-    const double sn = fma(beta, sv[o], q[o]);
+    const double pn = fma(beta, pd_o, r_o);
+    const double sn = fma(beta, sv_o, q_o);
     pd[o] = pn;
     sv[o] = sn;
-    double* zs = z + (size_t)sl * z_stride;
-    zs[i] = fma(alpha, pn, zs[i]);
-    r[o] = fma(-alpha, sn, r[o]);
+    zs[i] = fma(alpha, pn, z_o);
+    r[o] = fma(-alpha, sn, r_o);
   }
 }
 

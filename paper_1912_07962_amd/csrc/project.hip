@@ -501,7 +501,9 @@ __device__ __forceinline__ void fwd_reduce_body(
     const double* __restrict__ pd, size_t pd_stride, double lam, double* __restrict__ dots,
     double* __restrict__ dots2, size_t dots_stride, const int* __restrict__ stop,
     int stop_stride) {
-  if (stop && stop[(size_t)sl * stop_stride + kCtlDone]) return;
+  // the stop flag is read with everything else; a stopped slice's
+  // workgroups leave before writing
+  const bool stopped = stop && stop[(size_t)sl * stop_stride + kCtlDone];
   __shared__ double sh[8];
   const int o = bx * 256 + threadIdx.x;
   const int n = ids.n * R;
@@ -511,16 +513,18 @@ __device__ __forceinline__ void fwd_reduce_body(
     const int ang = ids.id[s];
     const size_t gs = (size_t)ids.n * R;
     const float* pp = partial + (size_t)sl * n_groups * gs + (size_t)s * R + t;
+    // band groups summed in order, loaded 16 at a time without branches
+    // (past the last group: the last one is read again and +0 added)
+    constexpr int kLd = 16;
     double v = 0.0;
-    int g = 0;
-    for (; g + 4 <= n_groups; g += 4) {
-      const float a = pp[g * gs], b = pp[(g + 1) * gs], c = pp[(g + 2) * gs], e = pp[(g + 3) * gs];
-      v += (double)a;
-      v += (double)b;
-      v += (double)c;
-      v += (double)e;
+    for (int g = 0; g < n_groups; g += kLd) {
+      float a[kLd];
+#pragma unroll
+      for (int u = 0; u < kLd; ++u) a[u] = pp[(size_t)min(g + u, n_groups - 1) * gs];
+#pragma unroll
+      for (int u = 0; u < kLd; ++u) v += g + u < n_groups ? (double)a[u] : 0.0;
     }
-    for (; g < n_groups; ++g) v += (double)pp[g * gs];
+    if (stopped) return;   // the same for the whole workgroup
     v *= (double)geom[ang].hd;
     if (sub) v -= (double)tof(sub[(size_t)sl * sub_stride + (size_t)ang * R + t]);
     if (pd) {
@@ -531,6 +535,8 @@ __device__ __forceinline__ void fwd_reduce_body(
     }
     if (out32) out32[(size_t)sl * out_stride + o] = (float)v;
     if (out64) out64[(size_t)sl * out_stride + o] = v;
+  } else if (stopped) {
+    return;
   }
   if (dots) {
     for (int w = 32; w > 0; w >>= 1) {
