@@ -67,13 +67,13 @@ PEAK_FP64_TFLOPS = 78.6
 # line reports traffic as null.
 PMC_TRAFFIC = {
     "source": "paper_1912_07962_amd/csrc/project.hip",
-    "sha256": "6daf19dd8671fa1b5042fdfa67d48cca49a083ddcb52ad6723a7f79cbb71ea19",
+    "sha256": "20066c4e6ac0ebd9b290e224d37832a0b31ef2ef2c5d5b6aa66afb82b63c3def",
     "fetch_scale": 2.0,
     "write_scale": 1.0,
     # instance -> (FETCH_SIZE, WRITE_SIZE) KiB per dispatch
-    "kib": {"cg_forward/2": (6221.3, 1992.8), "cg_forward/3": (6251.6, 2989.1),
-            "cg_forward/4": (4219.0, 3984.8), "cg_forward/6": (5403.0, 5479.6),
-            "cg_forward/8": (4276.0, 7969.5), "cg_back/1": (3094.1, 8192.8)},
+    "kib": {"cg_forward/2": (8289.1, 2008.5), "cg_forward/3": (8298.5, 3002.0),
+            "cg_forward/4": (4207.9, 3984.8), "cg_forward/6": (6727.8, 5483.7),
+            "cg_forward/8": (4247.9, 7969.5), "cg_back/1": (3116.6, 8192.8)},
 }
 
 
