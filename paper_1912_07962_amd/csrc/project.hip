@@ -530,8 +530,10 @@ __device__ __forceinline__ void fwd_reduce_body(
     if (pd) {
       const double pv = pd[(size_t)sl * pd_stride + o];
       v = fma(lam, pv, v);
-      d = pv * v;
-      d2 = pv * pv;
+      // rounded products (never fused into the sums below), so every
+      // launch that runs this body forms the same dot products
+      d = __dmul_rn(pv, v);
+      d2 = __dmul_rn(pv, pv);
     }
     if (out32) out32[(size_t)sl * out_stride + o] = (float)v;
     if (out64) out64[(size_t)sl * out_stride + o] = v;
@@ -569,9 +571,12 @@ __global__ __launch_bounds__(256) void fwd_reduce_kernel(
 }
 
 // ------------------------------------------------------------------- back
-constexpr int kBH = 16, kBW = 64;   // tile rows, columns
-constexpr int kBPX = 4;             // pixels per lane
-constexpr int kSeg = 72;                // rays of one angle's segment
+constexpr int kBH = 16, kBW = 64;   // tile rows, columns (per row block of 16)
+constexpr int kBPX = 4;             // pixels per lane and row block
+// rays of one angle's segment: the detector span of a 32 x 64 tile (two row
+// blocks) is at most sqrt(31^2 + 63^2) < 71 ray spacings between its corner
+// pixels, plus the floor, the next ray and the segment's first-ray margin
+constexpr int kSeg = 80;
 constexpr int kSegFloats = 64 * kSeg;   // LDS floats of staged segments
 constexpr int kPre = kSegFloats / 512;  // staged values per lane per pass (two buffers)
 
@@ -585,6 +590,7 @@ struct BackAngle {
   uint64_t T0;
   int64_t Ts, Tc;
   int64_t step;
+  int64_t rstep;   // 16 Ts: the lane's next row block
   float invd32, c1;
 };
 
@@ -600,8 +606,9 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 // The back-projector's work for pixel tile (bx, by) of a gx x gy grid of
 // tiles and slice tile bz (shared by the one-context launch and the grouped
-// launch).
-template <typename VT, int BT>
+// launch).  A tile is 16 RB rows by 64 columns: a lane's pixels are rows
+// ty + 16 r (r < RB) of columns tx + 16 q (q < 4).
+template <typename VT, int BT, int RB>
 __device__ __forceinline__ void back_body(
     int bx, int by, int bz, int gx, int gy, const AngleGeom* __restrict__ geom, int N, int R,
     const AngleList& ids, int B, const VT* __restrict__ v, size_t v_stride,
@@ -637,12 +644,13 @@ __device__ __forceinline__ void back_body(
   __shared__ BackAngle ang[kConst];
   __shared__ double wred[4][3 * BT];
   // the transposed-copy tile reuses the segment buffers once every pass is done
-  static_assert(kSegFloats >= kBH * (kBW + 1), "tile does not fit the segment buffers");
+  constexpr int kTH = kBH * RB;           // tile rows
+  static_assert(kSegFloats >= kTH * (kBW + 1), "tile does not fit the segment buffers");
   float(*tile)[kBW + 1] = reinterpret_cast<float(*)[kBW + 1]>(seg);
   const int tx = threadIdx.x & 15;       // 16 lanes x 4 pixels = 64 columns
-  const int ty = threadIdx.x >> 4;       // 16 rows
-  const int i0 = by * kBH, j0 = bx * kBW;
-  const int i = i0 + ty;
+  const int ty = threadIdx.x >> 4;       // 16 rows per row block
+  const int i0 = by * kTH, j0 = bx * kBW;
+  const int i = i0 + ty;                 // the lane's row in row block r: i + 16 r
   const int jb = j0 + kL * tx;           // pixel q of the lane: column jb + kQ q
   const double half = 0.5 * (N - 1);
   // detector coordinates are shifted by kTOff (>= every |jj c + ii s|), so
@@ -650,7 +658,7 @@ __device__ __forceinline__ void back_body(
   const int kTOff = 2 * N + 8;
   const double off = 0.5 * (R - 1) + kTOff;
   // nominal tile corners (pixel centres) bound every pixel the lanes evaluate
-  const double ci0 = (double)i0 - half, ci1 = (double)(i0 + kBH - 1) - half;
+  const double ci0 = (double)i0 - half, ci1 = (double)(i0 + kTH - 1) - half;
   const double cj0 = (double)j0 - half, cj1 = (double)(j0 + kBW - 1) - half;
   // constants of list angle a in slot c: the first ray of its segment (tmin)
   // and the position constants (base relative to its place in the pass)
@@ -663,43 +671,56 @@ __device__ __forceinline__ void back_body(
     hdA[c] = g.hd;
     BackAngle A;
     {
-      const double t = det_coord(g, ci0, cj0, off) + (double)((a % kPass) * kSeg - tm);
-      const int t0 = (int)t;                      // t >= 1: floor
-      A.T0 = ((uint64_t)(uint32_t)t0 << 32) | (uint32_t)((t - (double)t0) * 4294967296.0);
+      // integer and fraction of the corner's coordinate taken before the
+      // (integer) move onto the segment, so the fraction does not depend on
+      // the pass layout (slice tile) and no rounding of the moved sum enters
+      const double t = det_coord(g, ci0, cj0, off);
+      const double fl = floor(t);
+      const int t0 = (int)fl + (a % kPass) * kSeg - tm;   // >= 1
+      A.T0 = ((uint64_t)(uint32_t)t0 << 32) | (uint32_t)((t - fl) * 4294967296.0);
     }
     A.Ts = __double2ll_rn(g.s * 4294967296.0);
     A.Tc = __double2ll_rn(g.c * 4294967296.0);
     A.step = kQ * A.Tc;
+    A.rstep = kBH * A.Ts;
     A.invd32 = g.invd * 2.3283064365386963e-10f;
     A.c1 = 1.f - g.invd;
     ang[c] = A;
   };
-  float s[kBPX][BT];
+  float s[RB * kBPX][BT];   // pixel (r, q) at index r kBPX + q
 #pragma unroll
-  for (int q = 0; q < kBPX; ++q)
+  for (int q = 0; q < RB * kBPX; ++q)
 #pragma unroll
     for (int b = 0; b < BT; ++b) s[q][b] = 0.f;
   // na angles of a pass from LDS segments segp, constants from slot c0
+  // (rows past the image are evaluated too when RB > 1: their positions lie
+  // within the tile's nominal corners, so inside the segments)
   auto accumulate = [&](const float* segp, int c0, int na) {
-    if (i >= N) return;
+    if (RB == 1 && i >= N) return;
     const LT* segv = reinterpret_cast<const LT*>(segp);
     for (int a = 0; a < na; ++a) {
       const BackAngle A = ang[c0 + a];
       // the lane's first pixel (row ty, column tx of the tile); with the
-      // steps to its other pixels every position is within 40 2^-32
-      // (< 1e-8 pixel) of the canonical coordinate
-      uint64_t T = A.T0 + (uint64_t)((int64_t)ty * A.Ts) + (uint64_t)((int64_t)tx * A.Tc);
+      // steps to its other pixels every position is within 56 2^-32
+      // (< 2e-8 pixel) of the canonical coordinate
+      uint64_t Tr = A.T0 + (uint64_t)((int64_t)ty * A.Ts) + (uint64_t)((int64_t)tx * A.Tc);
 #pragma unroll
-      for (int q = 0; q < kBPX; ++q) {
-        if (q) T += (uint64_t)A.step;             // kQ columns on: t + kQ c
-        const uint32_t k = (uint32_t)(T >> 32);
-        const float f = (float)(uint32_t)T;       // 2^32 x distance to ray k
-        const float w0 = unit_clamp(fmaf(-f, A.invd32, 1.f));   // 1 - f/d
-        const float w1 = unit_clamp(fmaf(f, A.invd32, A.c1));   // 1 - (1-f)/d
-        const LT v0 = segv[k], v1 = segv[k + 1];
+      for (int r = 0; r < RB; ++r) {
+        if (r) Tr += (uint64_t)A.rstep;           // 16 rows on: t + 16 s
+        uint64_t T = Tr;
 #pragma unroll
-        for (int b = 0; b < BT; ++b)
-          s[q][b] = fmaf(w0, Lane<BT>::get(v0, b), fmaf(w1, Lane<BT>::get(v1, b), s[q][b]));
+        for (int q = 0; q < kBPX; ++q) {
+          if (q) T += (uint64_t)A.step;           // kQ columns on: t + kQ c
+          const uint32_t k = (uint32_t)(T >> 32);
+          const float f = (float)(uint32_t)T;     // 2^32 x distance to ray k
+          const float w0 = unit_clamp(fmaf(-f, A.invd32, 1.f));   // 1 - f/d
+          const float w1 = unit_clamp(fmaf(f, A.invd32, A.c1));   // 1 - (1-f)/d
+          const LT v0 = segv[k], v1 = segv[k + 1];
+#pragma unroll
+          for (int b = 0; b < BT; ++b)
+            s[r * kBPX + q][b] =
+                fmaf(w0, Lane<BT>::get(v0, b), fmaf(w1, Lane<BT>::get(v1, b), s[r * kBPX + q][b]));
+        }
       }
     }
   };
@@ -770,26 +791,30 @@ __device__ __forceinline__ void back_body(
     }
     __syncthreads();   // the segments are reused as the transposed-copy tile
   }
-  const size_t prow = (size_t)i * N + jb;
-
   if (mode == 0) {
 #pragma unroll
     for (int b = 0; b < BT; ++b) {
       if (b >= nb) break;
       float* ob = out + (size_t)(b0 + b) * img_stride;
-      if (i < N) {
 #pragma unroll
-        for (int q = 0; q < kBPX; ++q)
-          if (jb + kQ * q < N) ob[prow + kQ * q] = s[q][b];
+      for (int r = 0; r < RB; ++r) {
+        const int ir = i + kBH * r;
+        if (ir < N) {
+#pragma unroll
+          for (int q = 0; q < kBPX; ++q)
+            if (jb + kQ * q < N) ob[(size_t)ir * N + jb + kQ * q] = s[r * kBPX + q][b];
+        }
       }
       if (xT) {  // transposed copy of out through LDS
         __syncthreads();
 #pragma unroll
-        for (int q = 0; q < kBPX; ++q) tile[ty][kL * tx + kQ * q] = s[q][b];
+        for (int r = 0; r < RB; ++r)
+#pragma unroll
+          for (int q = 0; q < kBPX; ++q) tile[ty + kBH * r][kL * tx + kQ * q] = s[r * kBPX + q][b];
         __syncthreads();
         float* tb = xT + (size_t)(b0 + b) * img_stride;
-        for (int e = threadIdx.x; e < kBH * kBW; e += 256) {
-          const int jl = e / kBH, il = e % kBH;
+        for (int e = threadIdx.x; e < kTH * kBW; e += 256) {
+          const int jl = e / kTH, il = e % kTH;
           if (j0 + jl < N && i0 + il < N) tb[(size_t)(j0 + jl) * N + i0 + il] = tile[il][jl];
         }
       }
@@ -800,23 +825,29 @@ __device__ __forceinline__ void back_body(
 #pragma unroll
   for (int b = 0; b < BT; ++b) {
     nrm[b][0] = nrm[b][1] = nrm[b][2] = 0.0;
-    float xn[kBPX] = {0.f, 0.f, 0.f, 0.f};
+    float xn[RB * kBPX];
+#pragma unroll
+    for (int q = 0; q < RB * kBPX; ++q) xn[q] = 0.f;
     if (b < nb) {
       const size_t so = (size_t)(b0 + b) * img_stride;
-      if (i < N) {
+#pragma unroll
+      for (int r = 0; r < RB; ++r) {
+        const int ir = i + kBH * r;
+        if (ir >= N) continue;
 #pragma unroll
         for (int q = 0; q < kBPX; ++q) {
           if (jb + kQ * q < N) {
-            const size_t p = so + prow + kQ * q;
+            const int pq = r * kBPX + q;
+            const size_t p = so + (size_t)ir * N + jb + kQ * q;
             const float xo = x[p];
-            const float sq = fmaf(shrink, xo, s[q][b]);
-            xn[q] = xo - sq;
-            x[p] = xn[q];
-            if (xs) xs[p] = f2bf(xn[q]);
+            const float sq = fmaf(shrink, xo, s[pq][b]);
+            xn[pq] = xo - sq;
+            x[p] = xn[pq];
+            if (xs) xs[p] = f2bf(xn[pq]);
             nrm[b][0] += (double)sq * (double)sq;
-            nrm[b][1] += (double)xn[q] * (double)xn[q];
+            nrm[b][1] += (double)xn[pq] * (double)xn[pq];
             if (x_true) {
-              const double e = (double)xn[q] - (double)x_true[p];
+              const double e = (double)xn[pq] - (double)x_true[p];
               nrm[b][2] += e * e;
             }
           }
@@ -825,10 +856,12 @@ __device__ __forceinline__ void back_body(
       if (xT || xsT) {
         __syncthreads();
 #pragma unroll
-        for (int q = 0; q < kBPX; ++q) tile[ty][kL * tx + kQ * q] = xn[q];
+        for (int r = 0; r < RB; ++r)
+#pragma unroll
+          for (int q = 0; q < kBPX; ++q) tile[ty + kBH * r][kL * tx + kQ * q] = xn[r * kBPX + q];
         __syncthreads();
-        for (int e = threadIdx.x; e < kBH * kBW; e += 256) {
-          const int jl = e / kBH, il = e % kBH;
+        for (int e = threadIdx.x; e < kTH * kBW; e += 256) {
+          const int jl = e / kTH, il = e % kTH;
           if (j0 + jl < N && i0 + il < N) {
             const size_t o = so + (size_t)(j0 + jl) * N + i0 + il;
             if (xT) xT[o] = tile[il][jl];
@@ -857,14 +890,14 @@ __device__ __forceinline__ void back_body(
   }
 }
 
-template <typename VT, int BT>
+template <typename VT, int BT, int RB>
 __global__ __launch_bounds__(256) void back_kernel(
     const AngleGeom* __restrict__ geom, int N, int R, AngleList ids, int B,
     const VT* __restrict__ v, size_t v_stride, float* __restrict__ out, float* __restrict__ x,
     float* __restrict__ xT, const float* __restrict__ x_true, size_t img_stride,
     double* __restrict__ partials, int mode, const int* __restrict__ stop, int stop_stride,
     uint16_t* __restrict__ xs, uint16_t* __restrict__ xsT, float shrink) {
-  back_body<VT, BT>(blockIdx.x, blockIdx.y, blockIdx.z, gridDim.x, gridDim.y, geom, N, R, ids, B,
+  back_body<VT, BT, RB>(blockIdx.x, blockIdx.y, blockIdx.z, gridDim.x, gridDim.y, geom, N, R, ids, B,
                     v, v_stride, out, x, xT, x_true, img_stride, partials, mode, stop, stop_stride,
                     xs, xsT, shrink);
 }
@@ -962,7 +995,7 @@ __global__ __launch_bounds__(256) void back_grouped(const BackGroupDesc* __restr
   const int lw = w - a.start;
   const int per = a.gx * a.gy;
   const int bz = lw / per, rem = lw - bz * per;
-  back_body<double, BT>(rem % a.gx, rem / a.gx, bz, a.gx, a.gy, a.geom, a.N, a.R, a.ids, a.B, a.v,
+  back_body<double, BT, 2>(rem % a.gx, rem / a.gx, bz, a.gx, a.gy, a.geom, a.N, a.R, a.ids, a.B, a.v,
                         a.v_stride, a.out, nullptr, a.xT, nullptr, a.img_stride, nullptr, 0, a.stop,
                         a.stop_stride, nullptr, nullptr, 0.f);
 }
@@ -1384,9 +1417,9 @@ hipError_t launch_forward(const FwdArgs& a, hipStream_t st) {
 
 int back_num_workgroups(int N) { return ((N + kBW - 1) / kBW) * ((N + kBH - 1) / kBH); }
 
-template <typename VT, int BT>
+template <typename VT, int BT, int RB>
 static void launch_back_t(const BackArgs& a, const VT* v, dim3 grid, hipStream_t st) {
-  hipLaunchKernelGGL((back_kernel<VT, BT>), grid, dim3(256), 0, st, a.geom, a.N, a.R, *a.ids, a.B, v,
+  hipLaunchKernelGGL((back_kernel<VT, BT, RB>), grid, dim3(256), 0, st, a.geom, a.N, a.R, *a.ids, a.B, v,
                      a.v_stride, a.out, a.x, a.xT, a.x_true, a.img_stride, a.partials, a.mode,
                      a.stop, a.stop_stride, a.xs, a.xsT, a.shrink);
 }
@@ -1394,13 +1427,28 @@ static void launch_back_t(const BackArgs& a, const VT* v, dim3 grid, hipStream_t
 template <typename VT>
 static void launch_back_bt(const BackArgs& a, const VT* v, hipStream_t st) {
   const int BT = a.tune.back_bt > 0 ? std::min(a.tune.back_bt, slice_tile(a.B)) : slice_tile(a.B);
-  dim3 grid((a.N + kBW - 1) / kBW, (a.N + kBH - 1) / kBH, (a.B + BT - 1) / BT);
-  if (BT == 4)
-    launch_back_t<VT, 4>(a, v, grid, st);
-  else if (BT == 2)
-    launch_back_t<VT, 2>(a, v, grid, st);
-  else
-    launch_back_t<VT, 1>(a, v, grid, st);
+  // Without the update (mode 0): tiles of two row blocks (32 x 64), so each
+  // lane's per-angle set-up serves 8 pixels and each workgroup's staged
+  // segments twice the pixels.  Every mode-0 launch (any slice tile, and the
+  // grouped one) uses them, so a slice's result does not depend on the
+  // launch it is in.
+  const int RB = a.mode == 0 ? 2 : 1;
+  dim3 grid((a.N + kBW - 1) / kBW, (a.N + RB * kBH - 1) / (RB * kBH), (a.B + BT - 1) / BT);
+  if (RB == 2) {
+    if (BT == 4)
+      launch_back_t<VT, 4, 2>(a, v, grid, st);
+    else if (BT == 2)
+      launch_back_t<VT, 2, 2>(a, v, grid, st);
+    else
+      launch_back_t<VT, 1, 2>(a, v, grid, st);
+  } else {
+    if (BT == 4)
+      launch_back_t<VT, 4, 1>(a, v, grid, st);
+    else if (BT == 2)
+      launch_back_t<VT, 2, 1>(a, v, grid, st);
+    else
+      launch_back_t<VT, 1, 1>(a, v, grid, st);
+  }
 }
 
 hipError_t launch_back(const BackArgs& a, hipStream_t st) {
@@ -1497,7 +1545,7 @@ hipError_t grouped_prepare(const FwdArgs* const* fa, const BackArgs* const* ba, 
     k.R = b.R;
     k.B = b.B;
     k.gx = (b.N + kBW - 1) / kBW;
-    k.gy = (b.N + kBH - 1) / kBH;
+    k.gy = (b.N + 2 * kBH - 1) / (2 * kBH);   // mode 0: tiles of two row blocks
     k.stop_stride = b.stop_stride;
     k.start = sh.back_total;
     sh.back_total += k.gx * k.gy * ((b.B + sh.back_bt - 1) / sh.back_bt);
