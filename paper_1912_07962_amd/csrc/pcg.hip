@@ -161,10 +161,15 @@ __device__ __forceinline__ void cg_vector_body(int bx, int sl, int p, int pmax, 
                                                size_t z_stride, int* __restrict__ ctl,
                                                int* __restrict__ live) {
   __shared__ double sh[2 * (kThreads / 64)];
+  __shared__ int stop_sh;
   // every load of the workgroup (stop flag, scalars, partial dots, the
   // lane's vector entries) is issued before the first wait; a stopped
-  // slice's workgroups read and leave without writing
-  const bool stopped = ctl[sl * kCtlCount + kCtlDone] != 0;
+  // slice's workgroups read and leave without writing.  The stop flag is
+  // read once per workgroup and shared through LDS: the slice's first
+  // workgroup may set it during this launch, and waves reading it apart
+  // could disagree (a wave leaving early would leave its slot of the block
+  // sum unwritten for the waves that stay).
+  if (threadIdx.x == 0) stop_sh = ctl[sl * kCtlCount + kCtlDone];
   const double* sc = sc_all + (size_t)sl * S_COUNT;
   const double bb = sc[S_BB], g_old = sc[S_RR], a_old = sc[S_ALPHA];
   const int i = bx * kThreads + threadIdx.x;
@@ -177,8 +182,8 @@ __device__ __forceinline__ void cg_vector_body(int bx, int sl, int p, int pmax, 
     delta += dq_parts[(size_t)sl * nparts + k];
     gamma += rr_parts[(size_t)sl * nparts + k];
   }
-  if (stopped) return;   // the same for the whole workgroup
-  block_sum2(delta, gamma, sh);
+  block_sum2(delta, gamma, sh);   // its barriers publish stop_sh
+  if (stop_sh) return;
   const bool conv = !(gamma > tol2 * bb);
   const double beta = (g_old > 0.0) ? gamma / g_old : 0.0;
   const double alpha = (g_old > 0.0) ? gamma / (delta - beta * gamma / a_old) : gamma / delta;

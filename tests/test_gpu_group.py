@@ -127,3 +127,52 @@ def test_non_finite_data_is_reported():
                 s.step([0, 1])
             assert e.value.status == 4, (mode, where)
             s.close()
+
+
+def test_shared_launches_repeatable_at_scale():
+    """Two identical groups of the mixed-batch sizes (64 slices of 256^2, 32
+    of 512^2, 8 of 1024^2; 360 angles, 4 per block, r = 8) in shared launches
+    give the same iterates bit for bit, step after step, and equal the
+    contexts stepped alone.  At these sizes the CG vector launch holds
+    thousands of workgroups, so a slice's stop flag is set while other
+    workgroups of the same slice are starting: their stop decision must be
+    the same for all of a workgroup's waves."""
+    from paper_1912_07962_amd import Group, Slim
+    cfg = synth.get_config("c4m")
+    na, g, r, lam = cfg["n_angles"], cfg["g"], cfg["r"], cfg["lam"]
+    sets = {"A": [], "B": [], "solo": []}
+    for N, B in cfg["groups"]:
+        xs, bs = synth.make_volume_problem(N, B, na, cfg["n_ellipsoids"], cfg["noise"],
+                                           cfg["phantom_seed"], cfg["noise_seed"])
+        for key in sets:
+            st = torch.cuda.Stream()
+            with torch.cuda.stream(st):
+                s = Slim(N, na, r=r, lam=lam, n_slices=B, angles_per_block=g, gram_mode="pcg",
+                         pcg_tol=1e-6, stream=st)
+                bd = torch.as_tensor(bs, dtype=torch.float32, device="cuda")
+                x = torch.zeros((B, N, N), dtype=torch.float32, device="cuda")
+            st.synchronize()
+            s.set_data(bd, x)
+            sets[key].append((s, x, bd))
+    grp = {k: Group([c[0] for c in sets[k]], shared=True) for k in ("A", "B")}
+    sched = synth.schedule(na // g, 1, cfg["schedule_seed"])
+    for k in range(r + 4):
+        ids = list(range(int(sched[k]) * g, int(sched[k]) * g + g))
+        ia = grp["A"].step(ids)
+        ib = grp["B"].step(ids)
+        assert [i["pcg_iters"] for i in ia] == [i["pcg_iters"] for i in ib]
+        torch.cuda.synchronize()
+        for (_, xa, _), (_, xb, _) in zip(sets["A"], sets["B"]):
+            assert torch.equal(xa, xb), f"step {k + 1}"
+    for k in range(r + 4):
+        ids = list(range(int(sched[k]) * g, int(sched[k]) * g + g))
+        for s, _, _ in sets["solo"]:
+            s.step(ids)
+    torch.cuda.synchronize()
+    for (_, xa, _), (_, xs, _) in zip(sets["A"], sets["solo"]):
+        assert torch.equal(xa, xs)
+    for gp in grp.values():
+        gp.close()
+    for v in sets.values():
+        for s, _, _ in v:
+            s.close()
