@@ -324,7 +324,8 @@ def volume_bench(dev, B, steps, autotune=True):
     out_b = torch.empty((B, N, N), device=dev)
     torch.cuda.synchronize()
     # a block of row-stepping angles (theta near 0) and one of column-stepping
-    # angles (theta near pi/2; the public forward transposes x for those)
+    # angles (theta near pi/2; the public forward stages bands of columns of x
+    # for those, transposed on their way into LDS)
     for blk in (list(range(0, g)), list(range(na // 2, na // 2 + g))):
         t_f = _time(lambda: s.project(blk, xt, out_f))
         t_b = _time(lambda: s.backproject(blk, v, out_b))
