@@ -76,6 +76,30 @@ PMC_TRAFFIC = {
             "cg_forward/8": (4236.4, 7969.5), "cg_back/1": (3051.0, 8192.0)},
 }
 
+# VALU wave instructions per launch of the same kernel instances, from
+# rocprofv3 --pmc SQ_INSTS_VALU (median over the window launches of the same
+# runs' kind; same source digest rule).  MI355X issues at most one wave64 VALU
+# instruction per CU and cycle (four 16-lane SIMDs, four cycles per wave64
+# instruction): 256 CUs x 2.4 GHz = 614.4 G instructions/s.
+PMC_VALU = {
+    "sha256": PMC_TRAFFIC["sha256"],
+    "insts": {"cg_forward/8": 14363638, "cg_back/1": 13305856},
+}
+PEAK_VALU_GINST = 256 * 2.4
+
+
+def pmc_valu(kind, avg_launch_s):
+    """VALU issue of a kernel instance against the chip's VALU issue rate, or
+    None when no counters were taken on this code and instance."""
+    if kind not in PMC_VALU["insts"]:
+        return None
+    if code_digest(os.path.join(ROOT, PMC_TRAFFIC["source"])) != PMC_VALU["sha256"]:
+        return None
+    n = PMC_VALU["insts"][kind]
+    rate = n / avg_launch_s / 1e9
+    return {"insts_per_launch": n, "achieved_ginst_s": rate, "peak_ginst_s": PEAK_VALU_GINST,
+            "frac": rate / PEAK_VALU_GINST}
+
 
 def fwd_rays_per_lane(fwd_items, rays_in_group):
     """Rays per lane (the band kernel's IT) the library's launch plan uses for
@@ -1182,7 +1206,8 @@ def main():
         "roofline": {"bound": "alu", "kernel": f"{dom}: {kernel_name} (88-angle window)",
                      "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": pmc_traffic(inst),
-                     "avg_launch_us": avg_ms * 1e3, "flops_per_launch": flops_per_launch},
+                     "avg_launch_us": avg_ms * 1e3, "flops_per_launch": flops_per_launch,
+                     "valu_issue": pmc_valu(inst, avg_ms * 1e-3)},
         "cpu_baseline": cpu,
         "autotune": tune,
         "projector": projector,
