@@ -25,10 +25,11 @@
 // pairs, and the grid is sized to one round of resident workgroups (two per
 // CU by default).
 //
-// Back (pixel-driven gather): a workgroup owns a 16 x 64 pixel tile of a
-// slice tile and stages, for every angle of the list, the segment of ray
-// values its tile touches (scaled by h/d) in LDS; each lane gathers two rays
-// per angle for four pixels of a row, 16 columns apart.  No atomics; the optional
+// Back (pixel-driven gather): a workgroup owns a 16 x 64 pixel tile (32 x 64
+// without the update) of a slice tile and stages, for every angle of the list,
+// the segment of ray values its tile touches (scaled by h/d) in LDS; each lane
+// gathers two rays per angle for four pixels of a row, 16 columns apart, in
+// each of its row blocks.  No atomics; the optional
 // fused update writes x -= s, the transposed image, bf16 shadows and
 // per-workgroup float64 partial norms.  Both projectors evaluate the same
 // closed-form weights and agree to float32 rounding of the weights.
