@@ -78,14 +78,14 @@ PMC_TRAFFIC = {
 
 # VALU wave instructions per launch of the same kernel instances, from
 # rocprofv3 --pmc SQ_INSTS_VALU (median over the window launches of the same
-# runs' kind; same source digest rule).  MI355X issues at most one wave64 VALU
-# instruction per CU and cycle (four 16-lane SIMDs, four cycles per wave64
-# instruction): 256 CUs x 2.4 GHz = 614.4 G instructions/s.
+# runs' kind; same source digest rule).  The FP32 vector peak (157.3 TFLOP/s
+# = 256 CUs x 2.4 GHz x 128 FMA lanes) is two wave64 FP32 VALU instructions
+# per CU and cycle: 1228.8 G instructions/s, the issue ceiling used here.
 PMC_VALU = {
     "sha256": PMC_TRAFFIC["sha256"],
     "insts": {"cg_forward/8": 14363638, "cg_back/1": 13305856},
 }
-PEAK_VALU_GINST = 256 * 2.4
+PEAK_VALU_GINST = 256 * 2.4 * 2
 
 
 def pmc_valu(kind, avg_launch_s):

@@ -43,13 +43,13 @@ def test_counter_readings_are_reported_only_for_the_code_they_measured(monkeypat
     assert bench.pmc_traffic("cg_forward/4") is None
 
     # the VALU instruction counts follow the same rule, and their issue
-    # fraction is the count over the launch time against 614.4 G/s
+    # fraction is the count over the launch time against 1228.8 G/s
     monkeypatch.setattr(bench, "PMC_TRAFFIC", dict(t, sha256=current))
     monkeypatch.setattr(bench, "PMC_VALU", dict(bench.PMC_VALU, sha256=current))
     n = bench.PMC_VALU["insts"]["cg_forward/8"]
     v = bench.pmc_valu("cg_forward/8", 40e-6)
     assert v["insts_per_launch"] == n
-    assert abs(v["frac"] - n / 40e-6 / 614.4e9) < 1e-12
+    assert abs(v["frac"] - n / 40e-6 / 1228.8e9) < 1e-12
     assert bench.pmc_valu("cg_forward/6", 40e-6) is None
     monkeypatch.setattr(bench, "PMC_VALU", dict(bench.PMC_VALU, sha256="0" * 64))
     assert bench.pmc_valu("cg_forward/8", 40e-6) is None
